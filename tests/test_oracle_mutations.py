@@ -1,0 +1,95 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case plants one mistake in a copy of the oracle source (a dropped factor,
+a flipped sign, an index off by one), builds it with gcc into a temporary
+directory, and checks that at least one pin fails on it.  Runs on the CPU only.
+"""
+import importlib.util
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from tests import test_oracle_dense as TD
+from tests import test_oracle_dispersion as TP
+from tests import test_oracle_invariants as TI
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(os.path.dirname(HERE), "oracle", "tete_oracle.c")
+PY = os.path.join(os.path.dirname(HERE), "oracle", "oracle.py")
+
+MUTANTS = {
+    # S3 with alpha instead of 2 alpha
+    "ez_half_weight": ("upd_ez(g, m, f, 2.0 * a, jz);", "upd_ez(g, m, f, a, jz);",
+                       [lambda o: TD.test_ten_updates_equal_dense_scheme(o, 0)]),
+    # S4/S5 left out (TM group half-updated)
+    "no_second_h_half": ("    upd_hx(g, m, f, a);                /* S4", "    (void)0;                /* S4",
+                         [lambda o: TD.test_ten_updates_equal_dense_scheme(o, 0),
+                          lambda o: TI.test_energy_conserved_without_current(o, False)]),
+    # wrong sign of P_z e_y in S1/S4
+    "hx_pz_sign": ("f[HX][idx(g, i, j, k)] += a * m[HX][idx(g, i, j, k)] * (pz_ey - py_ez);",
+                   "f[HX][idx(g, i, j, k)] += a * m[HX][idx(g, i, j, k)] * (-pz_ey - py_ez);",
+                   [lambda o: TP.test_one_step_eigenvalues_follow_27(o)]),
+    # transposed difference taken forward instead of backward in S6/S9
+    "ex_pyt_index": ("double pyt_hz = at(g, f, HZ, i, j - 1, k) - at(g, f, HZ, i, j, k);",
+                     "double pyt_hz = at(g, f, HZ, i, j, k) - at(g, f, HZ, i, j + 1, k);",
+                     [lambda o: TD.test_ten_updates_equal_dense_scheme(o, 0)]),
+    # cross term of W^{n,e} with the wrong sign
+    "energy_cross_sign": ("return 0.5 * sq - 0.5 * a * a * (r0 + r1) + a * lc;",
+                          "return 0.5 * sq - 0.5 * a * a * (r0 + r1) - a * lc;",
+                          [lambda o: TD.test_energy_is_half_yQy(o, 0)]),
+    # energy R-term with + alpha^2 (the sign the paper prints)
+    "energy_r_sign": ("return 0.5 * sq - 0.5 * a * a * (r0 + r1) + a * lc;",
+                      "return 0.5 * sq + 0.5 * a * a * (r0 + r1) + a * lc;",
+                      [lambda o: TD.test_energy_is_half_yQy(o, 0)]),
+    # charge with (I + alpha^2 r_0)
+    "charge_r_sign": ("return e0 / kap - a * a * r;", "return e0 / kap + a * a * r;",
+                      [lambda o: TI.test_gauss_law_moving_bunch(o)]),
+    # current with the sign printed in the scaled forms
+    "current_sign": ("(pyt_hx - pxt_hy - src);", "(pyt_hx - pxt_hy + src);",
+                     [lambda o: TI.test_gauss_law_moving_bunch(o)]),
+    # bunch one cell late
+    "bunch_late": ("int mm = k - n + b->M;", "int mm = k - n + 1 + b->M;",
+                   [lambda o: TI.test_gauss_law_moving_bunch(o)]),
+    # wake sample taken one step early
+    "wake_index": ("int jj = n - k - b->M;", "int jj = n - k - b->M + 1;",
+                   [lambda o: TI.test_wake_energy_identity(o)]),
+    # staircase rule misses one adjacent cell
+    "pec_rule": ("cell_is_pec(g, cell_pec, i, j - 1, k) || cell_is_pec(g, cell_pec, i, j, k);\n        m[EX]",
+                 "cell_is_pec(g, cell_pec, i, j, k);\n        m[EX]",
+                 [lambda o: TI.test_staircase_pec_edges_are_cell_edges(o)]),
+}
+
+
+def _load_mutant(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, name
+    src = src.replace(old, new)
+    c = tmp_path / (name + ".c")
+    c.write_text(src)
+    so = tmp_path / (name + ".so")
+    subprocess.check_call(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                           "-o", str(so), str(c), "-lm"])
+    spec = importlib.util.spec_from_file_location("oracle_mutant_" + name, PY)
+    mod = importlib.util.module_from_spec(spec)
+    sys.modules[spec.name] = mod
+    spec.loader.exec_module(mod)
+    mod.LIB = str(so)
+    mod._lib = None
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(tmp_path, name):
+    old, new, pins = MUTANTS[name]
+    mod = _load_mutant(tmp_path, name, old, new)
+    caught = 0
+    for pin in pins:
+        try:
+            with np.errstate(all="ignore"):
+                pin(mod)
+        except (AssertionError, FloatingPointError, ValueError, np.linalg.LinAlgError):
+            caught += 1
+    assert caught >= 1, "no pin caught mutant %s" % name
