@@ -1,0 +1,158 @@
+#!/usr/bin/env python
+"""Throughput of the explicit TE/TM step on one MI355X.
+
+One "step" is one time step of the whole hot path: the TM-like half (S1-S5 with
+the bunch current and the FP64 wake update) and the TE-like half (S6-S10) over
+every grid entry.  Workload: tapered round-in-square collimator, 512 x 512 x
+2048 cells (0.54 G cells), FP32 fields with FP64 wake accumulation, Gaussian
+bunch sigma = 0.3 mm, synthetic geometry.  Inputs are resident in HBM before
+the timed region; the timed region is bracketed by stream synchronisation and
+measured with HIP events on the grid's stream.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+METRIC = "Gcell-updates/s + HBM GB/s; batched wake solves/s with p50/p99 latency"
+
+
+def cpu_baseline(case, nz_slab=32, steps=4):
+    """The FP64 oracle (plain C, one thread) on a z-slab of the same workload."""
+    from oracle import oracle as O
+    g = O.Geom(case.nx, case.ny, nz_slab, case.dx, case.dy, case.dz, case.cdt)
+    k0 = case.nz // 2 - nz_slab // 2
+    cells = case.cell_mask()[:, :, k0:k0 + nz_slab]
+    m = O.vacuum_materials(g, cells)
+    f = O.zeros(g)
+    b = O.Bunch(Q=case.Q, sigma=case.sigma, i0=case.i0, j0=case.j0, M=case.M, jmin=-4, nw=8)
+    t0 = time.perf_counter()
+    O.run(g, m, f, steps, n0=nz_slab // 2 + case.M - steps // 2, bunch=b)
+    dt = time.perf_counter() - t0
+    return {"value": case.nx * case.ny * nz_slab * steps / dt / 1e9, "unit": "Gcell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%dx%dx%d z-slab (cells %d..%d) of the %s workload with its geometry and bunch, %d steps, "
+                      "FP64, single thread, %.1f s" % (case.nx, case.ny, nz_slab, k0, k0 + nz_slab - 1, case.name,
+                                                       steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single-wake", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0901_1053_amd import inputs, tete
+
+    case = inputs.large_case()
+    print("# workload %s, %s, steps %d, warmup %d" % (case.name, args.precision, args.steps, args.warmup),
+          file=sys.stderr, flush=True)
+    G = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.cdt, precision=args.precision)
+    G.set_pec_cells(case.cell_mask())
+    G.set_bunch(case.Q, case.sigma, case.i0, case.j0, case.M, case.jmin, case.nw)
+    G.step(args.warmup)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    G.set_timing(K)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(G.stream)
+    G.step(K)
+    e1.record(G.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_tm, ms_te, nt = G.timing()
+    G.set_timing(0)
+    print("# timed %d steps in %.2f ms" % (K, ms), file=sys.stderr, flush=True)
+
+    cells = case.cells
+    entries = G.np
+    b = 4 if args.precision == "fp32" else 8
+    ms_step = ms / K
+    value = cells * K / (ms / 1e3) / 1e9
+    step_bytes = (12 * b + 1) * entries        # read + write six components, PEC code
+    kern = {"tm": ms_tm / nt, "te": ms_te / nt}
+    dom = max(kern, key=kern.get)
+    kbytes = (8 * b + 1) * entries             # each half reads five arrays + code, writes three
+    achieved = kbytes / (kern[dom] / 1e3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": case.name, "cells": cells, "grid_entries": entries,
+                   "fields": args.precision, "wake_accumulation": "fp64",
+                   "geometry": "tapered round aperture in 20 mm square pipe, 10 deg, 2->10 mm diameter",
+                   "bunch_sigma_m": case.sigma, "cdt_over_dz": 1.0, "dx_over_dz": 2.0},
+        "hbm_gbps_algorithmic": round(step_bytes / (ms_step / 1e3) / 1e9, 1),
+        "roofline": {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(achieved, 1),
+                     "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "traffic": None,
+                     "bytes_per_launch": kbytes, "ms_per_launch": round(kern[dom], 4),
+                     "kernels_ms_per_step": {k: round(v, 4) for k, v in kern.items()}},
+    }
+    del G
+    torch.cuda.empty_cache()
+
+    if not args.no_single_wake:
+        sw = inputs.single_wake_case()
+        res = {}
+        for prec in ("fp64", "fp32"):
+            S = tete.Grid(sw.nx, sw.ny, sw.nz, sw.dx, sw.dy, sw.dz, sw.cdt, precision=prec)
+            S.set_pec_cells(sw.cell_mask())
+            S.set_bunch(sw.Q, sw.sigma, sw.i0, sw.j0, sw.M, sw.jmin, sw.nw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S.step(sw.steps)
+            W = S.wake()
+            dt = time.perf_counter() - t0
+            res[prec] = {"solve_s": round(dt, 4), "gcell_updates_per_s": round(sw.cells * sw.steps / dt / 1e9, 2),
+                         "loss_factor_V_per_pC": None}
+            res[prec + "_W"] = W
+            del S
+            torch.cuda.empty_cache()
+        import numpy as np
+        w64, w32 = res.pop("fp64_W"), res.pop("fp32_W")
+        res["fp32_delta_vs_fp64_gpu"] = float(np.max(np.abs(w32 - w64)) / (np.max(w64) - np.min(w64)))
+        res["workload"] = sw.name
+        res["steps"] = sw.steps
+        out["single_wake"] = res
+        print("# single wake done", file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * tete.h -- C-ABI of the explicit TE/TM wakefield time stepper for MI355X
+ * (gfx950), after Dohlus & Zagorodnov, "Explicit TE/TM scheme for particle
+ * beam simulations".
+ *
+ * The library advances the discrete Cauchy problem of Sec. 2, eq. (1) with
+ * PEC walls (n x E = 0 on the boundary), in the finite-integration form (4):
+ * the curl C and its transpose on a Cartesian grid doublet, diagonal material
+ * matrices M_eps^-1 and M_mu^-1, and a current j.  Time stepping is the
+ * explicit TE/TM scheme (23), executed as the ten sub-updates of Sec. 4.2 on
+ * the GPU.  The source is a rigid Gaussian bunch moving at v = c along a node
+ * line; the library accumulates the longitudinal wake potential of Sec. 5 and
+ * evaluates the discrete energy of Sec. 4.4 and the conserved charges (34),
+ * (35).
+ *
+ * Units: c = eps0 = mu0 = 1 internally; lengths in metres; charge in
+ * coulombs.  Field values are FIT voltages: e^ = E * edge length,
+ * h^ = H * dual-edge length, in these units.  tete_wake converts to V/C.
+ *
+ * Grid and layout: nx, ny, nz cells; node (i,j,k) at (i dx, j dy, k dz).
+ * Every component is one array of np = (nx+1)(ny+1)(nz+1) entries, z fastest:
+ * index = k + (nz+1) * (j + (ny+1) * i).  Component positions:
+ *   e_x (i+1/2, j, k)   e_y (i, j+1/2, k)   e_z (i, j, k+1/2)
+ *   h_x (i, j+1/2, k+1/2)  h_y (i+1/2, j, k+1/2)  h_z (i+1/2, j+1/2, k)
+ * Entries outside a component's index range (e.g. e_x at i = nx) hold no grid
+ * object; the library keeps them at zero.  Array order in the [6] arguments
+ * below: e_x, e_y, e_z, h_x, h_y, h_z.
+ *
+ * Memory: the caller owns one device workspace (tete_workspace_bytes) and
+ * the HIP stream; the library never allocates or frees device memory.  All
+ * bulk array arguments are DEVICE pointers, read or written on the grid's
+ * stream; small result arguments are HOST pointers.  A call that returns an
+ * error leaves the grid state unchanged unless stated otherwise.
+ *
+ * Ordering: calls are ordered on the grid's stream.  tete_step only enqueues
+ * work; tete_wake, tete_energy, tete_energy_series, tete_probes and
+ * tete_charges synchronise the stream before they return.  One grid may be
+ * used by one host thread at a time.
+ */
+#ifndef TETE_H
+#define TETE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tete_grid tete_grid; /* opaque handle */
+
+typedef enum {
+    TETE_OK = 0,
+    TETE_ERR_ARG = -1,       /* invalid argument (size, index, pointer, alignment) */
+    TETE_ERR_UNSTABLE = -2,  /* cdt violates the stability bound (25) */
+    TETE_ERR_NOMEM = -3,     /* workspace smaller than tete_workspace_bytes */
+    TETE_ERR_DEVICE = -4,    /* a HIP call or kernel launch failed */
+    TETE_ERR_STATE = -5,     /* call not valid in the grid's current state */
+    TETE_ERR_NONFINITE = -6  /* a diagnostic found NaN or Inf in the fields */
+} tete_status;
+
+/* Arithmetic type of the field arrays.  FP32 keeps the wake accumulation,
+ * energy and charge diagnostics and the bunch table in FP64. */
+enum { TETE_FP64 = 0, TETE_FP32 = 1 };
+
+/* desc.flags */
+enum {
+    TETE_F_MATERIALS = 1u << 0  /* reserve per-entry material arrays (tete_set_materials) */
+};
+
+/* Capacities of the small per-grid tables held in the workspace. */
+enum {
+    TETE_MAX_BUNCH_CELLS = 8191, /* 2M+1 cells of the truncated bunch */
+    TETE_MAX_WAKE = 65536,       /* wake samples */
+    TETE_MAX_PROBES = 16         /* e_z probe points */
+};
+
+typedef struct {
+    int32_t nx, ny, nz;   /* cells, each >= 2; (nx+1)(ny+1)(nz+1) < 2^31 */
+    double dx, dy, dz;    /* cell sizes [m] */
+    double cdt;           /* dtau = c dt [m]; must satisfy (25):
+                             cdt <= dz and cdt <= (dx^-2 + dy^-2)^(-1/2) */
+    int32_t precision;    /* TETE_FP64 or TETE_FP32 */
+    uint32_t flags;       /* TETE_F_* */
+    int32_t max_series;   /* capacity of energy / probe series (0: 4096) */
+} tete_grid_desc;
+
+/* Stability and size check of a descriptor (host only, no device access).
+ * Returns TETE_OK, TETE_ERR_ARG or TETE_ERR_UNSTABLE (bound (25), Sec. 4.4). */
+tete_status tete_check_desc(const tete_grid_desc* desc);
+
+/* Bytes of device workspace a grid with this descriptor needs (0 if the
+ * descriptor is invalid).  This is the grid's whole HBM footprint. */
+size_t tete_workspace_bytes(const tete_grid_desc* desc);
+
+/* Create a grid on the current HIP device inside the caller's workspace
+ * (dev_ws, 256-byte aligned, ws_bytes >= tete_workspace_bytes(desc)), using
+ * the HIP stream hip_stream (a hipStream_t; NULL = null stream).  The fields
+ * start at zero, the domain is an empty vacuum PEC box (kappa = 0 on the
+ * edges tangential to the walls, Sec. 2), no bunch, step counter 0.
+ * Errors: TETE_ERR_ARG, TETE_ERR_UNSTABLE, TETE_ERR_NOMEM, TETE_ERR_DEVICE. */
+tete_status tete_grid_create(const tete_grid_desc* desc, void* dev_ws, size_t ws_bytes,
+                             void* hip_stream, tete_grid** out);
+
+/* Release the host handle (the workspace stays the caller's). */
+tete_status tete_grid_destroy(tete_grid* g);
+
+/* Staircase geometry (Sec. 4.4 bound and Sec. 2 PEC): cell_is_pec is a DEVICE
+ * array of nx*ny*nz bytes, index k + nz*(j + ny*i), non-zero = perfectly
+ * conducting cell.  An edge becomes PEC (kappa = 0) if any of its up to four
+ * adjacent cells is PEC; cells outside the box count as PEC.  Vacuum values
+ * elsewhere: kappa_x = mu_x = dx/(dy dz), cyclic.  NULL = empty box.  Zeroes
+ * e on the new PEC edges (n x E = 0).  Copies; the caller keeps its array. */
+tete_status tete_set_pec_cells(tete_grid* g, const uint8_t* cell_is_pec);
+
+/* General diagonal materials (Sec. 2, eq. (4)): DEVICE arrays of np entries
+ * of type dtype (TETE_FP64/TETE_FP32): inv_eps[0..2] = M_eps^-1 on e_x,e_y,e_z
+ * edges (0 = PEC edge), inv_mu[0..2] = M_mu^-1 on h_x,h_y,h_z.  Requires a grid
+ * created with TETE_F_MATERIALS, else TETE_ERR_STATE.  Values must be finite
+ * and >= 0.  Zeroes e where inv_eps = 0.  Replaces the staircase vacuum. */
+tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3],
+                               const void* const inv_mu[3], int32_t dtype);
+
+/* Initial field y^0 = (u^{-1/2}, v^0) (time levels of eq. (17)): h_x, h_y, e_z
+ * at tau = -cdt/2 and e_x, e_y, h_z at tau = 0.  f[6] are DEVICE arrays of np
+ * entries of type dtype.  Out-of-range entries and e on PEC edges are
+ * stored as zero.  Resets the step counter, the wake accumulator and the
+ * series. */
+tete_status tete_set_fields(tete_grid* g, const void* const f[6], int32_t dtype);
+
+/* Copy the current state y^n into DEVICE arrays f[6] (np entries of dtype). */
+tete_status tete_get_fields(tete_grid* g, void* const f[6], int32_t dtype);
+
+/* Rigid Gaussian bunch (Fig. 1): total charge charge_C, RMS length sigma_z,
+ * moving at v = c along +z on the node line (i0, j0), 0 < i0 < nx,
+ * 0 < j0 < ny.  It is cut to 2*half_cells+1 cells of length dz; cell m
+ * (|m| <= half_cells, m dz ahead of the centre) carries
+ * charge_C [Phi((m+1/2) dz/sigma) - Phi((m-1/2) dz/sigma)].  Requires
+ * cdt == dz (one cell per step).  The charge crossing e_z edge k in step n is
+ * the charge of cell m = k - n + half_cells: the head crosses edge 0 in step
+ * 0.  Wake samples s_j = j dz for j = jmin .. jmin+nw-1 (s > 0 behind the
+ * centre).  Resets the wake accumulator; the step counter is not changed.
+ * Errors: TETE_ERR_ARG (bounds, capacities), TETE_ERR_STATE (cdt != dz). */
+typedef struct {
+    double charge_C;
+    double sigma_z;       /* [m] */
+    int32_t i0, j0;
+    int32_t half_cells;   /* M */
+    int32_t jmin;
+    int32_t nw;           /* <= TETE_MAX_WAKE */
+} tete_bunch;
+tete_status tete_set_bunch(tete_grid* g, const tete_bunch* b);
+
+/* Remove the bunch (no current; wake accumulation stops). */
+tete_status tete_clear_bunch(tete_grid* g);
+
+/* Diagnostics recorded during tete_step: every > 0 records W^{n,e} of y^n
+ * (Sec. 4.4) before each step n with n % every == 0; 0 disables. */
+tete_status tete_set_diagnostics(tete_grid* g, int32_t every);
+
+/* e_z probes recorded after every step (e_z^{n+1/2}); idx are HOST array
+ * indices into the e_z array (0 <= idx < np), np_ <= TETE_MAX_PROBES. */
+tete_status tete_set_probes(tete_grid* g, const int64_t* idx, int32_t np_);
+
+/* Enqueue nsteps steps of scheme (23) on the grid's stream (asynchronous).
+ * Errors: TETE_ERR_ARG (nsteps < 0), TETE_ERR_STATE (series full while
+ * recording), TETE_ERR_DEVICE (launch failure). */
+tete_status tete_step(tete_grid* g, int64_t nsteps);
+
+/* Number of completed steps (host counter, no synchronisation). */
+tete_status tete_steps_done(tete_grid* g, int64_t* n);
+
+/* Longitudinal wake potential (Sec. 5) W(s_j) = -(1/Q) int E_z dz at
+ * t = (z + s)/c on the bunch line, in V/C, for the nw samples of the bunch
+ * (HOST array W of at least nw doubles).  Sample j is complete once step
+ * nz - 1 + half_cells + j has run.  Synchronises the stream. */
+tete_status tete_wake(tete_grid* g, double* W, int32_t nw);
+
+/* Discrete energy W^{n,e} = 1/2 <Q^e y^n, y^n> (Sec. 4.4) of the current
+ * state, FP64, internal units (joules = W / eps0 with charge in coulombs);
+ * *n = steps done.  Synchronises.  TETE_ERR_NONFINITE if the sum is not finite. */
+tete_status tete_energy(tete_grid* g, double* W, int64_t* n);
+
+/* Copy the energies recorded during tete_step (see tete_set_diagnostics):
+ * out[0..count-1] in step order, *count = entries recorded (<= max).  Synchronises. */
+tete_status tete_energy_series(tete_grid* g, double* out, int64_t max, int64_t* count);
+
+/* Copy the probe series: out[s * nprobes + p] for recorded steps s, HOST
+ * array of max entries; *count = steps recorded.  Synchronises. */
+tete_status tete_probes(tete_grid* g, double* out, int64_t max, int64_t* count);
+
+/* Conserved charges of Sec. 4.5 after the last step n (needs >= 1 step since
+ * the last tete_set_fields): max over nodes whose six edges are non-PEC of
+ * |q_e^{n+1/2} - bunch charge of the node's dual cell| (eq. (35)), and max over
+ * cells of |q_h^n| (eq. (34)), both FP64 in coulombs / internal flux units.
+ * Synchronises.  TETE_ERR_STATE if no step has run. */
+tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h);
+
+/* Live kernel timing for measurement.  max_steps > 0 arms up to max_steps
+ * timed steps: each subsequent step records HIP events on the grid's stream
+ * before, between and after its two kernels (TM-like half S1-S5 with the
+ * source and wake update; TE-like half S6-S10).  0 disarms.  Synchronises.
+ * Steps beyond the armed count fail with TETE_ERR_STATE. */
+tete_status tete_set_timing(tete_grid* g, int64_t max_steps);
+
+/* Sum of the kernel durations of the timed steps since the last call, in ms:
+ * ms[0] = TM-like kernel, ms[1] = TE-like kernel (nphase >= 2); *steps =
+ * number of timed steps.  Resets the count.  Synchronises. */
+tete_status tete_timing(tete_grid* g, double* ms, int32_t nphase, int64_t* steps);
+
+/* Human-readable status name. */
+const char* tete_status_str(tete_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TETE_H */

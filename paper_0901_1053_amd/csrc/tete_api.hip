@@ -1,0 +1,536 @@
+// Host runtime of libtete: descriptor validation (stability bound (25)),
+// workspace layout, grid state and the C-ABI entry points of include/tete.h.
+// All device work is enqueued on the grid's stream; the library never
+// allocates device memory.
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "tete_impl.h"
+
+using namespace tete;
+
+namespace {
+
+constexpr double kEps0 = 8.8541878128e-12;   // vacuum permittivity [F/m] (CODATA 2018)
+constexpr size_t kAlign = 256;
+
+size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t lam, wacc, partial, scal, pidx, eser, pser, code, field[12], mat[6], total;
+};
+
+int64_t series_cap(const tete_grid_desc* d) { return d->max_series > 0 ? d->max_series : 4096; }
+
+bool make_layout(const tete_grid_desc* d, Layout* L)
+{
+    const int64_t np = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
+    const size_t rb = d->precision == TETE_FP32 ? 4 : 8;
+    size_t o = 0;
+    L->lam = o;     o = up(o + sizeof(double) * TETE_MAX_BUNCH_CELLS);
+    L->wacc = o;    o = up(o + sizeof(double) * TETE_MAX_WAKE);
+    L->partial = o; o = up(o + sizeof(double) * 2 * RED_BLOCKS);
+    L->scal = o;    o = up(o + sizeof(double) * 64);
+    L->pidx = o;    o = up(o + sizeof(int64_t) * TETE_MAX_PROBES);
+    L->eser = o;    o = up(o + sizeof(double) * (size_t)series_cap(d));
+    L->pser = o;    o = up(o + sizeof(double) * (size_t)series_cap(d) * TETE_MAX_PROBES);
+    L->code = o;    o = up(o + (size_t)np);
+    for (int c = 0; c < 12; ++c) { L->field[c] = o; o = up(o + rb * (size_t)np); }
+    for (int c = 0; c < 6; ++c) {
+        if (d->flags & TETE_F_MATERIALS) { L->mat[c] = o; o = up(o + rb * (size_t)np); }
+        else L->mat[c] = 0;
+    }
+    L->total = o;
+    return true;
+}
+
+// Runs f() with dev current, restoring the previous device afterwards.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard()
+    {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct tete_grid {
+    tete_grid_desc d;
+    hipStream_t stream;
+    int device;
+    char* ws;
+    Layout L;
+    Geo geo;
+    int fp32;
+    void* f[2][6];
+    int cur;           // f[cur] holds y^n
+    uint8_t* code;
+    void* mat[6];
+    int mat_set;
+    double *lam, *wacc, *partial, *scal, *eser, *pser;
+    int64_t* pidx;
+    int64_t n;         // steps since create / set_fields
+    int has_bunch;
+    tete_bunch b;
+    int diag_every;
+    int64_t ecount, pcount, cap;
+    int nprobe;
+    double kv[3], mv[3], alpha;
+    // live kernel timing (tete_set_timing): 3 events per timed step
+    int timing;
+    hipEvent_t* ev;
+    int64_t ev_cap, ev_steps;
+};
+
+#define HIPCHK(x)                                      \
+    do {                                               \
+        if ((x) != hipSuccess) return TETE_ERR_DEVICE; \
+    } while (0)
+
+namespace {
+
+template <typename R>
+Fields<R> fields(tete_grid* g, int set)
+{
+    Fields<R> F;
+    for (int c = 0; c < 6; ++c) F.c[c] = (R*)g->f[set][c];
+    return F;
+}
+
+template <typename R>
+Mat<R> mats(tete_grid* g)
+{
+    Mat<R> M;
+    M.code = g->code;
+    for (int c = 0; c < 6; ++c) M.arr[c] = g->mat_set ? (const R*)g->mat[c] : nullptr;
+    for (int c = 0; c < 3; ++c) { M.k[c] = (R)g->kv[c]; M.m[c] = (R)g->mv[c]; }
+    return M;
+}
+
+Src source(tete_grid* g, int64_t n)
+{
+    Src s;
+    s.on = g->has_bunch;
+    s.i0 = g->b.i0;
+    s.j0 = g->b.j0;
+    s.M = g->b.half_cells;
+    s.n = n;
+    s.lam = g->lam;
+    s.wacc = g->wacc;
+    s.jmin = g->b.jmin;
+    s.nw = g->b.nw;
+    return s;
+}
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+template <typename R>
+tete_status do_steps(tete_grid* g, int64_t nsteps)
+{
+    Mat<R> M = mats<R>(g);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        if (g->diag_every > 0 && g->n % g->diag_every == 0) {
+            HIPCHK(launch_energy<R>(fields<R>(g, g->cur), M, g->geo, g->alpha, g->partial, g->eser + g->ecount,
+                                    g->stream));
+            g->ecount++;
+        }
+        hipEvent_t* ev = nullptr;
+        if (g->timing) {
+            if (g->ev_steps >= g->ev_cap) return TETE_ERR_STATE;
+            ev = g->ev + 3 * g->ev_steps;
+            g->ev_steps++;
+        }
+        HIPCHK(launch_step<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
+                              source(g, g->n), g->stream, ev));
+        g->cur = 1 - g->cur;
+        g->n++;
+        if (g->nprobe > 0) {
+            HIPCHK(launch_probes<R>((const R*)g->f[g->cur][2], g->pidx, g->nprobe, g->pser + g->pcount * g->nprobe,
+                                    g->stream));
+            g->pcount++;
+        }
+    }
+    return TETE_OK;
+}
+
+tete_status reset_series(tete_grid* g)
+{
+    g->n = 0;
+    g->ecount = 0;
+    g->pcount = 0;
+    HIPCHK(launch_fill_f64(g->wacc, TETE_MAX_WAKE, 0.0, g->stream));
+    return TETE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tete_status_str(tete_status s)
+{
+    switch (s) {
+    case TETE_OK: return "TETE_OK";
+    case TETE_ERR_ARG: return "TETE_ERR_ARG";
+    case TETE_ERR_UNSTABLE: return "TETE_ERR_UNSTABLE";
+    case TETE_ERR_NOMEM: return "TETE_ERR_NOMEM";
+    case TETE_ERR_DEVICE: return "TETE_ERR_DEVICE";
+    case TETE_ERR_STATE: return "TETE_ERR_STATE";
+    case TETE_ERR_NONFINITE: return "TETE_ERR_NONFINITE";
+    }
+    return "TETE_ERR_UNKNOWN";
+}
+
+tete_status tete_check_desc(const tete_grid_desc* d)
+{
+    if (!d) return TETE_ERR_ARG;
+    if (d->nx < 2 || d->ny < 2 || d->nz < 2) return TETE_ERR_ARG;
+    const int64_t np = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
+    if (np >= ((int64_t)1 << 31) - 1) return TETE_ERR_ARG;
+    if (!finite_pos(d->dx) || !finite_pos(d->dy) || !finite_pos(d->dz) || !finite_pos(d->cdt)) return TETE_ERR_ARG;
+    if (d->precision != TETE_FP64 && d->precision != TETE_FP32) return TETE_ERR_ARG;
+    if (d->flags & ~(uint32_t)TETE_F_MATERIALS) return TETE_ERR_ARG;
+    if (d->max_series < 0 || d->max_series > (1 << 24)) return TETE_ERR_ARG;
+    // (25): dtau <= dz and dtau <= (dx^-2 + dy^-2)^(-1/2), equality allowed
+    const double tol = 1.0 + 1e-12;
+    const double bt = 1.0 / sqrt(1.0 / (d->dx * d->dx) + 1.0 / (d->dy * d->dy));
+    if (d->cdt > d->dz * tol || d->cdt > bt * tol) return TETE_ERR_UNSTABLE;
+    return TETE_OK;
+}
+
+size_t tete_workspace_bytes(const tete_grid_desc* d)
+{
+    if (tete_check_desc(d) == TETE_ERR_ARG) return 0;
+    Layout L;
+    make_layout(d, &L);
+    return L.total;
+}
+
+tete_status tete_grid_create(const tete_grid_desc* d, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                             tete_grid** out)
+{
+    if (!out) return TETE_ERR_ARG;
+    *out = nullptr;
+    tete_status st = tete_check_desc(d);
+    if (st != TETE_OK) return st;
+    if (!dev_ws || ((uintptr_t)dev_ws % kAlign) != 0) return TETE_ERR_ARG;
+    Layout L;
+    make_layout(d, &L);
+    if (ws_bytes < L.total) return TETE_ERR_NOMEM;
+
+    tete_grid* g = (tete_grid*)calloc(1, sizeof(tete_grid));
+    if (!g) return TETE_ERR_NOMEM;
+    g->d = *d;
+    g->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&g->device) != hipSuccess) { free(g); return TETE_ERR_DEVICE; }
+    g->ws = (char*)dev_ws;
+    g->L = L;
+    g->geo.nx = d->nx;
+    g->geo.ny = d->ny;
+    g->geo.nz = d->nz;
+    g->geo.sz = d->nz + 1;
+    g->geo.sp = (d->ny + 1) * (d->nz + 1);
+    g->geo.np = (d->nx + 1) * g->geo.sp;
+    g->fp32 = d->precision == TETE_FP32;
+    for (int s = 0; s < 2; ++s)
+        for (int c = 0; c < 6; ++c) g->f[s][c] = g->ws + L.field[6 * s + c];
+    g->cur = 0;
+    g->code = (uint8_t*)(g->ws + L.code);
+    for (int c = 0; c < 6; ++c) g->mat[c] = (d->flags & TETE_F_MATERIALS) ? g->ws + L.mat[c] : nullptr;
+    g->lam = (double*)(g->ws + L.lam);
+    g->wacc = (double*)(g->ws + L.wacc);
+    g->partial = (double*)(g->ws + L.partial);
+    g->scal = (double*)(g->ws + L.scal);
+    g->pidx = (int64_t*)(g->ws + L.pidx);
+    g->eser = (double*)(g->ws + L.eser);
+    g->pser = (double*)(g->ws + L.pser);
+    g->cap = series_cap(d);
+    // vacuum M_eps^-1 and M_mu^-1 (c = eps0 = mu0 = 1): edge length / dual facet area
+    g->kv[0] = g->mv[0] = d->dx / (d->dy * d->dz);
+    g->kv[1] = g->mv[1] = d->dy / (d->dz * d->dx);
+    g->kv[2] = g->mv[2] = d->dz / (d->dx * d->dy);
+    g->alpha = 0.5 * d->cdt;   // alpha = dtau / 2, eq. (17)
+
+    // zero the whole workspace, then mark the box walls
+    if (launch_zero_bytes(g->ws, L.total, g->stream) != hipSuccess ||
+        launch_build_codes(g->code, nullptr, g->geo, g->stream) != hipSuccess) {
+        free(g);
+        return TETE_ERR_DEVICE;
+    }
+    *out = g;
+    return TETE_OK;
+}
+
+tete_status tete_grid_destroy(tete_grid* g)
+{
+    if (!g) return TETE_ERR_ARG;
+    for (int64_t e = 0; e < 3 * g->ev_cap; ++e) (void)hipEventDestroy(g->ev[e]);
+    free(g->ev);
+    free(g);
+    return TETE_OK;
+}
+
+tete_status tete_set_timing(tete_grid* g, int64_t max_steps)
+{
+    if (!g || max_steps < 0 || max_steps > (1 << 20)) return TETE_ERR_ARG;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    HIPCHK(hipStreamSynchronize(g->stream));
+    if (max_steps > g->ev_cap) {
+        hipEvent_t* ev = (hipEvent_t*)realloc(g->ev, sizeof(hipEvent_t) * 3 * max_steps);
+        if (!ev) return TETE_ERR_NOMEM;
+        g->ev = ev;
+        for (int64_t e = 3 * g->ev_cap; e < 3 * max_steps; ++e) {
+            if (hipEventCreate(&g->ev[e]) != hipSuccess) {
+                g->ev_cap = e / 3;
+                return TETE_ERR_DEVICE;
+            }
+        }
+        g->ev_cap = max_steps;
+    }
+    g->timing = max_steps > 0;
+    g->ev_steps = 0;
+    return TETE_OK;
+}
+
+tete_status tete_timing(tete_grid* g, double* ms, int32_t nphase, int64_t* steps)
+{
+    if (!g || !ms || !steps || nphase < 1) return TETE_ERR_ARG;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    HIPCHK(hipStreamSynchronize(g->stream));
+    for (int p = 0; p < nphase; ++p) ms[p] = 0.0;
+    for (int64_t s = 0; s < g->ev_steps; ++s) {
+        float t0 = 0.f, t1 = 0.f;
+        HIPCHK(hipEventElapsedTime(&t0, g->ev[3 * s], g->ev[3 * s + 1]));
+        HIPCHK(hipEventElapsedTime(&t1, g->ev[3 * s + 1], g->ev[3 * s + 2]));
+        ms[0] += t0;
+        if (nphase > 1) ms[1] += t1;
+    }
+    *steps = g->ev_steps;
+    g->ev_steps = 0;
+    return TETE_OK;
+}
+
+tete_status tete_set_pec_cells(tete_grid* g, const uint8_t* cells)
+{
+    if (!g) return TETE_ERR_ARG;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    HIPCHK(launch_build_codes(g->code, cells, g->geo, g->stream));
+    g->mat_set = 0;
+    if (g->fp32) HIPCHK(launch_zero_pec<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->stream));
+    else HIPCHK(launch_zero_pec<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->stream));
+    return TETE_OK;
+}
+
+tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3], const void* const inv_mu[3], int32_t dtype)
+{
+    if (!g || !inv_eps || !inv_mu) return TETE_ERR_ARG;
+    if (dtype != TETE_FP64 && dtype != TETE_FP32) return TETE_ERR_ARG;
+    for (int c = 0; c < 3; ++c)
+        if (!inv_eps[c] || !inv_mu[c]) return TETE_ERR_ARG;
+    if (!(g->d.flags & TETE_F_MATERIALS)) return TETE_ERR_STATE;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    const void* src[6] = {inv_eps[0], inv_eps[1], inv_eps[2], inv_mu[0], inv_mu[1], inv_mu[2]};
+    if (g->fp32) {
+        float* dst[6];
+        for (int c = 0; c < 6; ++c) dst[c] = (float*)g->mat[c];
+        HIPCHK(launch_import_materials<float>(dst, src, dtype == TETE_FP32, g->geo, g->stream));
+        g->mat_set = 1;
+        HIPCHK(launch_zero_pec<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->stream));
+    } else {
+        double* dst[6];
+        for (int c = 0; c < 6; ++c) dst[c] = (double*)g->mat[c];
+        HIPCHK(launch_import_materials<double>(dst, src, dtype == TETE_FP32, g->geo, g->stream));
+        g->mat_set = 1;
+        HIPCHK(launch_zero_pec<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->stream));
+    }
+    return TETE_OK;
+}
+
+tete_status tete_set_fields(tete_grid* g, const void* const f[6], int32_t dtype)
+{
+    if (!g || !f) return TETE_ERR_ARG;
+    if (dtype != TETE_FP64 && dtype != TETE_FP32) return TETE_ERR_ARG;
+    for (int c = 0; c < 6; ++c)
+        if (!f[c]) return TETE_ERR_ARG;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    if (g->fp32) HIPCHK(launch_import<float>(fields<float>(g, g->cur), f, dtype == TETE_FP32, mats<float>(g), g->geo, g->stream));
+    else HIPCHK(launch_import<double>(fields<double>(g, g->cur), f, dtype == TETE_FP32, mats<double>(g), g->geo, g->stream));
+    return reset_series(g);
+}
+
+tete_status tete_get_fields(tete_grid* g, void* const f[6], int32_t dtype)
+{
+    if (!g || !f) return TETE_ERR_ARG;
+    if (dtype != TETE_FP64 && dtype != TETE_FP32) return TETE_ERR_ARG;
+    for (int c = 0; c < 6; ++c)
+        if (!f[c]) return TETE_ERR_ARG;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    if (g->fp32) HIPCHK(launch_export<float>(f, dtype == TETE_FP32, fields<float>(g, g->cur), g->geo, g->stream));
+    else HIPCHK(launch_export<double>(f, dtype == TETE_FP32, fields<double>(g, g->cur), g->geo, g->stream));
+    return TETE_OK;
+}
+
+tete_status tete_set_bunch(tete_grid* g, const tete_bunch* b)
+{
+    if (!g || !b) return TETE_ERR_ARG;
+    if (!isfinite(b->charge_C) || b->charge_C == 0.0 || !finite_pos(b->sigma_z)) return TETE_ERR_ARG;
+    if (b->i0 <= 0 || b->i0 >= g->d.nx || b->j0 <= 0 || b->j0 >= g->d.ny) return TETE_ERR_ARG;
+    if (b->half_cells < 0 || 2 * (int64_t)b->half_cells + 1 > TETE_MAX_BUNCH_CELLS) return TETE_ERR_ARG;
+    if (b->nw < 1 || b->nw > TETE_MAX_WAKE) return TETE_ERR_ARG;
+    if (g->d.cdt != g->d.dz) return TETE_ERR_STATE;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    HIPCHK(launch_lambda(g->lam, b->charge_C, b->sigma_z, g->d.dz, b->half_cells, g->stream));
+    HIPCHK(launch_fill_f64(g->wacc, TETE_MAX_WAKE, 0.0, g->stream));
+    g->b = *b;
+    g->has_bunch = 1;
+    return TETE_OK;
+}
+
+tete_status tete_clear_bunch(tete_grid* g)
+{
+    if (!g) return TETE_ERR_ARG;
+    g->has_bunch = 0;
+    return TETE_OK;
+}
+
+tete_status tete_set_diagnostics(tete_grid* g, int32_t every)
+{
+    if (!g || every < 0) return TETE_ERR_ARG;
+    g->diag_every = every;
+    return TETE_OK;
+}
+
+tete_status tete_set_probes(tete_grid* g, const int64_t* idx, int32_t np_)
+{
+    if (!g || np_ < 0 || np_ > TETE_MAX_PROBES || (np_ > 0 && !idx)) return TETE_ERR_ARG;
+    for (int p = 0; p < np_; ++p)
+        if (idx[p] < 0 || idx[p] >= g->geo.np) return TETE_ERR_ARG;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    if (np_ > 0) {
+        HIPCHK(hipMemcpyAsync(g->pidx, idx, sizeof(int64_t) * np_, hipMemcpyHostToDevice, g->stream));
+        HIPCHK(hipStreamSynchronize(g->stream));
+    }
+    g->nprobe = np_;
+    g->pcount = 0;
+    return TETE_OK;
+}
+
+tete_status tete_step(tete_grid* g, int64_t nsteps)
+{
+    if (!g || nsteps < 0) return TETE_ERR_ARG;
+    if (nsteps == 0) return TETE_OK;
+    // capacity of the series for the steps requested
+    int64_t need_e = 0;
+    if (g->diag_every > 0) {
+        int64_t e = g->diag_every;
+        int64_t first = (g->n + e - 1) / e * e;
+        need_e = first < g->n + nsteps ? (g->n + nsteps - 1 - first) / e + 1 : 0;
+    }
+    if (g->ecount + need_e > g->cap) return TETE_ERR_STATE;
+    if (g->nprobe > 0 && g->pcount + nsteps > g->cap) return TETE_ERR_STATE;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    return g->fp32 ? do_steps<float>(g, nsteps) : do_steps<double>(g, nsteps);
+}
+
+tete_status tete_steps_done(tete_grid* g, int64_t* n)
+{
+    if (!g || !n) return TETE_ERR_ARG;
+    *n = g->n;
+    return TETE_OK;
+}
+
+tete_status tete_wake(tete_grid* g, double* W, int32_t nw)
+{
+    if (!g || !W) return TETE_ERR_ARG;
+    if (!g->has_bunch) return TETE_ERR_STATE;
+    if (nw < 1 || nw > g->b.nw) return TETE_ERR_ARG;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    HIPCHK(hipMemcpyAsync(W, g->wacc, sizeof(double) * nw, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    const double s = 1.0 / (g->b.charge_C * kEps0);
+    for (int j = 0; j < nw; ++j) W[j] *= s;
+    return TETE_OK;
+}
+
+tete_status tete_energy(tete_grid* g, double* W, int64_t* n)
+{
+    if (!g || !W) return TETE_ERR_ARG;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    if (g->fp32) HIPCHK(launch_energy<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->alpha, g->partial, g->scal, g->stream));
+    else HIPCHK(launch_energy<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->alpha, g->partial, g->scal, g->stream));
+    double v;
+    HIPCHK(hipMemcpyAsync(&v, g->scal, sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    *W = v;
+    if (n) *n = g->n;
+    return isfinite(v) ? TETE_OK : TETE_ERR_NONFINITE;
+}
+
+tete_status tete_energy_series(tete_grid* g, double* out, int64_t max, int64_t* count)
+{
+    if (!g || !count || max < 0 || (max > 0 && !out)) return TETE_ERR_ARG;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    int64_t c = std::min(max, g->ecount);
+    if (c > 0) HIPCHK(hipMemcpyAsync(out, g->eser, sizeof(double) * c, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    *count = g->ecount;
+    return TETE_OK;
+}
+
+tete_status tete_probes(tete_grid* g, double* out, int64_t max, int64_t* count)
+{
+    if (!g || !count || max < 0 || (max > 0 && !out)) return TETE_ERR_ARG;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    int64_t c = std::min(max, g->pcount * g->nprobe);
+    if (c > 0) HIPCHK(hipMemcpyAsync(out, g->pser, sizeof(double) * c, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    *count = g->pcount;
+    return TETE_OK;
+}
+
+tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h)
+{
+    if (!g || !max_res_e || !max_abs_h) return TETE_ERR_ARG;
+    if (g->n < 1) return TETE_ERR_STATE;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    Src s = source(g, g->n - 1);
+    if (g->fp32)
+        HIPCHK(launch_charges<float>(fields<float>(g, 1 - g->cur), fields<float>(g, g->cur), mats<float>(g), g->geo,
+                                     g->alpha, s, g->partial, g->scal + 2, g->stream));
+    else
+        HIPCHK(launch_charges<double>(fields<double>(g, 1 - g->cur), fields<double>(g, g->cur), mats<double>(g),
+                                      g->geo, g->alpha, s, g->partial, g->scal + 2, g->stream));
+    double v[2];
+    HIPCHK(hipMemcpyAsync(v, g->scal + 2, sizeof(double) * 2, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    *max_res_e = v[0];
+    *max_abs_h = v[1];
+    return (isfinite(v[0]) && isfinite(v[1])) ? TETE_OK : TETE_ERR_NONFINITE;
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Internal declarations shared by the host runtime and the kernel translation
+// units of libtete.  Not part of the public ABI (include/tete.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tete.h"
+
+namespace tete {
+
+// Grid geometry as the kernels see it.  Arrays are (nx+1)(ny+1)(nz+1), z
+// fastest; sz = nz+1 is the row length, sp = (ny+1)(nz+1) the plane length.
+struct Geo {
+    int nx, ny, nz;
+    int sz;      // nz + 1
+    int sp;      // (ny + 1) * (nz + 1)
+    int np;      // (nx + 1) * sp
+};
+
+// Six field components of one time level.
+template <typename R>
+struct Fields {
+    R* c[6];     // ex, ey, ez, hx, hy, hz
+};
+
+// Material description: vacuum scalars with PEC codes, or per-entry arrays.
+template <typename R>
+struct Mat {
+    const uint8_t* code;   // bit0: e_x PEC/absent, bit1: e_y, bit2: e_z
+    const R* arr[6];       // kappa_x,y,z, mu_x,y,z per entry (nullptr: vacuum)
+    R k[3], m[3];          // vacuum kappa_x,y,z and mu_x,y,z
+};
+
+// Rigid-bunch source and wake accumulator for one step.
+struct Src {
+    int on;
+    int i0, j0, M;
+    int64_t n;           // index of the step being taken
+    const double* lam;   // 2M+1 cell charges
+    double* wacc;        // wake accumulator (FP64)
+    int jmin, nw;
+};
+
+enum { RED_BLOCKS = 2048, RED_THREADS = 256 };
+
+// ---- launchers (tete_kernels.hip) ---------------------------------------
+hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_zero_bytes(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_build_codes(uint8_t* code, const uint8_t* cells, Geo g, hipStream_t s);
+hipError_t launch_lambda(double* lam, double Q, double sigma, double dz, int M, hipStream_t s);
+
+template <typename R>
+hipError_t launch_import(Fields<R> dst, const void* const src[6], int src_fp32, Mat<R> mat, Geo g,
+                         hipStream_t s);
+template <typename R>
+hipError_t launch_export(void* const dst[6], int dst_fp32, Fields<R> src, Geo g, hipStream_t s);
+template <typename R>
+hipError_t launch_import_materials(R* const dst[6], const void* const src[6], int src_fp32, Geo g,
+                                   hipStream_t s);
+template <typename R>
+hipError_t launch_zero_pec(Fields<R> f, Mat<R> mat, Geo g, hipStream_t s);
+
+// One step; ev (optional) receives three events: before the TM kernel,
+// between the TM and TE kernels, after the TE kernel.
+template <typename R>
+hipError_t launch_step(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src,
+                       hipStream_t s, hipEvent_t* ev);
+
+// energy of a state -> out[0] (FP64), using partial[RED_BLOCKS]
+template <typename R>
+hipError_t launch_energy(Fields<R> f, Mat<R> mat, Geo g, double alpha, double* partial, double* out,
+                         hipStream_t s);
+// charges: out[0] = max |q_e - node charge| (interior nodes), out[1] = max |q_h|
+template <typename R>
+hipError_t launch_charges(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, double alpha, Src src,
+                          double* partial, double* out, hipStream_t s);
+template <typename R>
+hipError_t launch_probes(const R* ez, const int64_t* idx, int nprobe, double* out, hipStream_t s);
+
+}  // namespace tete

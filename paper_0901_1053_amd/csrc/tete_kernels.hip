@@ -1,0 +1,647 @@
+// HIP kernels of libtete for gfx950: set-up (PEC codes, bunch table, field
+// import/export), the explicit TE/TM step, and the FP64 diagnostics.
+//
+// The step follows scheme (23) of Dohlus & Zagorodnov as the ten sub-updates
+// of Sec. 4.2: the TM-like group u = (h_x, h_y, e_z) is advanced from
+// u^{n-1/2} to u^{n+1/2} with v^n, then the TE-like group v = (e_x, e_y, h_z)
+// from v^n to v^{n+1} with u^{n+1/2}.  Each group is one kernel that writes a
+// second (ping-pong) copy of its three arrays, so no thread ever reads a value
+// another thread of the same launch writes.  The intermediate values h_x^n,
+// h_y^n (S1, S2) and e_x^{n+1/2}, e_y^{n+1/2} (S6, S7) are never stored: each
+// thread recomputes the ones its stencil touches.
+
+#include <float.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include "tete_impl.h"
+
+namespace tete {
+namespace {
+
+constexpr int TB = 256;   // threads per block of the element-wise kernels
+
+__device__ __forceinline__ void decomp(int idx, const Geo& g, int& i, int& j, int& k)
+{
+    i = idx / g.sp;
+    int r = idx - i * g.sp;
+    j = r / g.sz;
+    k = r - j * g.sz;
+}
+
+__device__ __forceinline__ bool in_nodes(const Geo& g, int i, int j, int k)
+{
+    return (unsigned)i <= (unsigned)g.nx && (unsigned)j <= (unsigned)g.ny && (unsigned)k <= (unsigned)g.nz;
+}
+
+__device__ __forceinline__ int lin(const Geo& g, int i, int j, int k) { return k + j * g.sz + i * g.sp; }
+
+// Component index ranges (entries outside them hold no grid object).
+__device__ __forceinline__ bool ex_ok(const Geo& g, int i, int, int) { return i < g.nx; }
+__device__ __forceinline__ bool ey_ok(const Geo& g, int, int j, int) { return j < g.ny; }
+__device__ __forceinline__ bool ez_ok(const Geo& g, int, int, int k) { return k < g.nz; }
+__device__ __forceinline__ bool hx_ok(const Geo& g, int, int j, int k) { return j < g.ny && k < g.nz; }
+__device__ __forceinline__ bool hy_ok(const Geo& g, int i, int, int k) { return i < g.nx && k < g.nz; }
+__device__ __forceinline__ bool hz_ok(const Geo& g, int i, int j, int) { return i < g.nx && j < g.ny; }
+
+__device__ __forceinline__ bool comp_ok(int c, const Geo& g, int i, int j, int k)
+{
+    switch (c) {
+    case 0: return ex_ok(g, i, j, k);
+    case 1: return ey_ok(g, i, j, k);
+    case 2: return ez_ok(g, i, j, k);
+    case 3: return hx_ok(g, i, j, k);
+    case 4: return hy_ok(g, i, j, k);
+    default: return hz_ok(g, i, j, k);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ R ld(const R* p, const Geo& g, int i, int j, int k)
+{
+    return in_nodes(g, i, j, k) ? p[lin(g, i, j, k)] : R(0);
+}
+
+// M_eps^-1 entry of e component c (0..2) at linear index id.
+template <typename R>
+__device__ __forceinline__ R kap(const Mat<R>& M, int c, int id)
+{
+    if (M.arr[c]) return M.arr[c][id];
+    return ((M.code[id] >> c) & 1) ? R(0) : M.k[c];
+}
+
+// M_mu^-1 entry of h component c (0..2).
+template <typename R>
+__device__ __forceinline__ R muv(const Mat<R>& M, int c, int id)
+{
+    return M.arr[3 + c] ? M.arr[3 + c][id] : M.m[c];
+}
+
+// ---------------------------------------------------------------------------
+// Set-up kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = v;
+}
+
+__global__ void k_zero16(uint4* p, int64_t n)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = v;
+}
+
+// Staircase PEC: an edge is PEC if any of its (up to four) adjacent cells is
+// PEC; cells outside the box count as PEC, so the edges tangential to the
+// walls are PEC (n x E = 0).  Entries outside a component's range are marked
+// too, which keeps them at zero.
+__global__ void k_build_codes(uint8_t* code, const uint8_t* cells, Geo g)
+{
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.np) return;
+    int i, j, k;
+    decomp(idx, g, i, j, k);
+    auto pec = [&](int ci, int cj, int ck) -> bool {
+        if (ci < 0 || cj < 0 || ck < 0 || ci >= g.nx || cj >= g.ny || ck >= g.nz) return true;
+        return cells ? cells[ck + g.nz * (cj + g.ny * ci)] != 0 : false;
+    };
+    uint8_t c = 0;
+    if (i >= g.nx || pec(i, j - 1, k - 1) || pec(i, j, k - 1) || pec(i, j - 1, k) || pec(i, j, k)) c |= 1;
+    if (j >= g.ny || pec(i - 1, j, k - 1) || pec(i, j, k - 1) || pec(i - 1, j, k) || pec(i, j, k)) c |= 2;
+    if (k >= g.nz || pec(i - 1, j - 1, k) || pec(i, j - 1, k) || pec(i - 1, j, k) || pec(i, j, k)) c |= 4;
+    code[idx] = c;
+}
+
+// Cell charges of the truncated Gaussian: lam[m+M] = Q [Phi(b) - Phi(a)],
+// a = (m-1/2) dz/sigma, b = (m+1/2) dz/sigma, written with erfc on the side
+// of the mean where the difference does not cancel.
+__global__ void k_lambda(double* lam, double Q, double sigma, double dz, int M)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > 2 * M) return;
+    int m = t - M;
+    const double r2 = 0.70710678118654752440;   // 1/sqrt(2)
+    double a = (m - 0.5) * dz / sigma, b = (m + 0.5) * dz / sigma, v;
+    if (a >= 0.0)
+        v = 0.5 * (erfc(a * r2) - erfc(b * r2));
+    else if (b <= 0.0)
+        v = 0.5 * (erfc(-b * r2) - erfc(-a * r2));
+    else
+        v = 1.0 - 0.5 * erfc(-a * r2) - 0.5 * erfc(b * r2);
+    lam[t] = Q * v;
+}
+
+template <typename R>
+__device__ __forceinline__ bool e_pec(const Mat<R>& M, int c, int id)
+{
+    return kap(M, c, id) == R(0);
+}
+
+template <typename R>
+__global__ void k_import(Fields<R> dst, const void* s0, const void* s1, const void* s2, const void* s3,
+                         const void* s4, const void* s5, int src_fp32, Mat<R> M, Geo g)
+{
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.np) return;
+    int i, j, k;
+    decomp(idx, g, i, j, k);
+    const void* src[6] = {s0, s1, s2, s3, s4, s5};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        R v = src_fp32 ? (R)((const float*)src[c])[idx] : (R)((const double*)src[c])[idx];
+        bool keep = comp_ok(c, g, i, j, k) && (c >= 3 || !e_pec(M, c, idx));
+        dst.c[c][idx] = keep ? v : R(0);
+    }
+}
+
+template <typename R>
+__global__ void k_export(void* d0, void* d1, void* d2, void* d3, void* d4, void* d5, int dst_fp32,
+                         Fields<R> src, Geo g)
+{
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.np) return;
+    void* dst[6] = {d0, d1, d2, d3, d4, d5};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        if (dst_fp32)
+            ((float*)dst[c])[idx] = (float)src.c[c][idx];
+        else
+            ((double*)dst[c])[idx] = (double)src.c[c][idx];
+    }
+}
+
+template <typename R>
+__global__ void k_import_mat(R* d0, R* d1, R* d2, R* d3, R* d4, R* d5, const void* s0, const void* s1,
+                             const void* s2, const void* s3, const void* s4, const void* s5, int src_fp32,
+                             Geo g)
+{
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.np) return;
+    int i, j, k;
+    decomp(idx, g, i, j, k);
+    R* dst[6] = {d0, d1, d2, d3, d4, d5};
+    const void* src[6] = {s0, s1, s2, s3, s4, s5};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        R v = src_fp32 ? (R)((const float*)src[c])[idx] : (R)((const double*)src[c])[idx];
+        dst[c][idx] = comp_ok(c, g, i, j, k) ? v : R(0);
+    }
+}
+
+template <typename R>
+__global__ void k_zero_pec(Fields<R> f, Mat<R> M, Geo g)
+{
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.np) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        if (e_pec(M, c, idx)) f.c[c][idx] = R(0);
+}
+
+// ---------------------------------------------------------------------------
+// TM-like half step: S1..S5.  One thread per node entry (i,j,k) writes
+// h_x^{n+1/2}, h_y^{n+1/2}, e_z^{n+1/2} there.  The bunch current enters S3
+// on the node line (i0, j0); the wake accumulator takes the time-centred
+// e_z of the thread's own edge (no two threads share a sample in one step).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(TB) void k_tm(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R a, Src src)
+{
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.np) return;
+    int i, j, k;
+    decomp(idx, g, i, j, k);
+    const R* ex = o.c[0];
+    const R* ey = o.c[1];
+    const R* ez = o.c[2];
+    const R* hx = o.c[3];
+    const R* hy = o.c[4];
+    const R a2 = a + a;
+
+    // S1: h_x^n = h_x^{n-1/2} + a mu_x [P_z e_y^n - P_y e_z^{n-1/2}]
+    auto hxn = [&](int ii, int jj) -> R {
+        if (!in_nodes(g, ii, jj, k) || !hx_ok(g, ii, jj, k)) return R(0);
+        int id = lin(g, ii, jj, k);
+        return hx[id] + a * muv(M, 0, id) * ((ld(ey, g, ii, jj, k + 1) - ey[id]) - (ld(ez, g, ii, jj + 1, k) - ez[id]));
+    };
+    // S2: h_y^n = h_y^{n-1/2} + a mu_y [-P_z e_x^n + P_x e_z^{n-1/2}]
+    auto hyn = [&](int ii, int jj) -> R {
+        if (!in_nodes(g, ii, jj, k) || !hy_ok(g, ii, jj, k)) return R(0);
+        int id = lin(g, ii, jj, k);
+        return hy[id] + a * muv(M, 1, id) * (-(ld(ex, g, ii, jj, k + 1) - ex[id]) + (ld(ez, g, ii + 1, jj, k) - ez[id]));
+    };
+    // S3: e_z^{n+1/2} = e_z^{n-1/2} + 2a kappa_z [P_y^T h_x^n - P_x^T h_y^n - j_z^n]
+    auto ezh = [&](int ii, int jj) -> R {
+        if (!in_nodes(g, ii, jj, k) || !ez_ok(g, ii, jj, k)) return R(0);
+        int id = lin(g, ii, jj, k);
+        R kp = kap(M, 2, id);
+        R v = ez[id] + a2 * kp * ((hxn(ii, jj - 1) - hxn(ii, jj)) - (hyn(ii - 1, jj) - hyn(ii, jj)));
+        if (src.on && ii == src.i0 && jj == src.j0) {
+            int64_t m = (int64_t)k - src.n + src.M;       // charge of cell m crosses edge k in step n
+            if (m >= -src.M && m <= src.M) v -= (R)((double)kp * src.lam[m + src.M]);
+        }
+        return v;
+    };
+
+    const R e0 = ezh(i, j);
+    nf.c[2][idx] = e0;
+    // S4: h_x^{n+1/2} = h_x^n + a mu_x [P_z e_y^n - P_y e_z^{n+1/2}]
+    R hxv = R(0);
+    if (hx_ok(g, i, j, k))
+        hxv = hxn(i, j) + a * muv(M, 0, idx) * ((ld(ey, g, i, j, k + 1) - ey[idx]) - (ezh(i, j + 1) - e0));
+    nf.c[3][idx] = hxv;
+    // S5: h_y^{n+1/2} = h_y^n + a mu_y [-P_z e_x^n + P_x e_z^{n+1/2}]
+    R hyv = R(0);
+    if (hy_ok(g, i, j, k))
+        hyv = hyn(i, j) + a * muv(M, 1, idx) * (-(ld(ex, g, i, j, k + 1) - ex[idx]) + (ezh(i + 1, j) - e0));
+    nf.c[4][idx] = hyv;
+
+    // wake: W(s_j) sample of edge k is taken in step n = k + M + j
+    if (src.on && i == src.i0 && j == src.j0 && k < g.nz) {
+        int64_t js = src.n - k - src.M;
+        if (js >= src.jmin && js < (int64_t)src.jmin + src.nw)
+            src.wacc[js - src.jmin] += -0.5 * ((double)ez[idx] + (double)e0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// TE-like half step: S6..S10 with u^{n+1/2} (the TM kernel's output).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(TB) void k_te(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R a)
+{
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.np) return;
+    int i, j, k;
+    decomp(idx, g, i, j, k);
+    const R* ex = o.c[0];
+    const R* ey = o.c[1];
+    const R* hz = o.c[5];
+    const R* hx1 = nf.c[3];
+    const R* hy1 = nf.c[4];
+    const R a2 = a + a;
+
+    // S6: e_x^{n+1/2} = e_x^n + a kappa_x [P_z^T h_y^{n+1/2} - P_y^T h_z^n]
+    auto exh = [&](int ii, int jj) -> R {
+        if (!in_nodes(g, ii, jj, k)) return R(0);
+        int id = lin(g, ii, jj, k);
+        return ex[id] + a * kap(M, 0, id) * ((ld(hy1, g, ii, jj, k - 1) - hy1[id]) - (ld(hz, g, ii, jj - 1, k) - hz[id]));
+    };
+    // S7: e_y^{n+1/2} = e_y^n + a kappa_y [-P_z^T h_x^{n+1/2} + P_x^T h_z^n]
+    auto eyh = [&](int ii, int jj) -> R {
+        if (!in_nodes(g, ii, jj, k)) return R(0);
+        int id = lin(g, ii, jj, k);
+        return ey[id] + a * kap(M, 1, id) * (-(ld(hx1, g, ii, jj, k - 1) - hx1[id]) + (ld(hz, g, ii - 1, jj, k) - hz[id]));
+    };
+    // S8: h_z^{n+1} = h_z^n + 2a mu_z [P_y e_x^{n+1/2} - P_x e_y^{n+1/2}]
+    auto hzn = [&](int ii, int jj) -> R {
+        if (!in_nodes(g, ii, jj, k) || !hz_ok(g, ii, jj, k)) return R(0);
+        int id = lin(g, ii, jj, k);
+        return hz[id] + a2 * muv(M, 2, id) * ((exh(ii, jj + 1) - exh(ii, jj)) - (eyh(ii + 1, jj) - eyh(ii, jj)));
+    };
+
+    const R h0 = hzn(i, j);
+    nf.c[5][idx] = h0;
+    // S9: e_x^{n+1} = e_x^{n+1/2} + a kappa_x [P_z^T h_y^{n+1/2} - P_y^T h_z^{n+1}]
+    nf.c[0][idx] = exh(i, j) + a * kap(M, 0, idx) * ((ld(hy1, g, i, j, k - 1) - hy1[idx]) - (hzn(i, j - 1) - h0));
+    // S10: e_y^{n+1} = e_y^{n+1/2} + a kappa_y [-P_z^T h_x^{n+1/2} + P_x^T h_z^{n+1}]
+    nf.c[1][idx] = eyh(i, j) + a * kap(M, 1, idx) * (-(ld(hx1, g, i, j, k - 1) - hx1[idx]) + (hzn(i - 1, j) - h0));
+}
+
+// ---------------------------------------------------------------------------
+// FP64 diagnostics
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double nan_max(double a, double b)
+{
+    if (a != a || b != b) return NAN;
+    return a > b ? a : b;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = nan_max(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+template <bool MAX>
+__device__ __forceinline__ double block_reduce(double v)
+{
+    __shared__ double red[RED_THREADS / 64];
+    v = MAX ? wave_max(v) : wave_sum(v);
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double r = red[0];
+    for (int t = 1; t < RED_THREADS / 64; ++t) r = MAX ? nan_max(r, red[t]) : r + red[t];
+    __syncthreads();
+    return r;
+}
+
+template <typename R>
+__device__ __forceinline__ double ldd(const R* p, const Geo& g, int i, int j, int k)
+{
+    return (double)ld(p, g, i, j, k);
+}
+
+// W^{n,e} = 1/2 <Q^e y, y> (Sec. 4.4) expanded over the grid entries:
+//   1/2 [sum h^2/mu + sum_{kappa>0} e^2/kappa]
+//   - a^2/2 [sum_hx mu_x (P_y e_z)^2 + sum_hy mu_y (P_x e_z)^2
+//            + sum_{ex,kappa>0} kappa_x (P_y^T h_z)^2 + sum_{ey,kappa>0} kappa_y (P_x^T h_z)^2]
+//   + a [sum_hx h_x P_z e_y - sum_hy h_y P_z e_x]
+template <typename R>
+__global__ __launch_bounds__(RED_THREADS) void k_energy(Fields<R> f, Mat<R> M, Geo g, double a, double* partial)
+{
+    const R *ex = f.c[0], *ey = f.c[1], *ez = f.c[2], *hx = f.c[3], *hy = f.c[4], *hz = f.c[5];
+    double acc = 0.0;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < g.np; idx += gridDim.x * blockDim.x) {
+        int i, j, k;
+        decomp(idx, g, i, j, k);
+        double sq = 0.0, r = 0.0, lc = 0.0;
+        double kx = (double)kap(M, 0, idx), ky = (double)kap(M, 1, idx), kz = (double)kap(M, 2, idx);
+        if (kx > 0.0) {
+            double e = ex[idx], d = ldd(hz, g, i, j - 1, k) - (double)hz[idx];
+            sq += e * e / kx;
+            r += kx * d * d;
+        }
+        if (ky > 0.0) {
+            double e = ey[idx], d = ldd(hz, g, i - 1, j, k) - (double)hz[idx];
+            sq += e * e / ky;
+            r += ky * d * d;
+        }
+        if (kz > 0.0) {
+            double e = ez[idx];
+            sq += e * e / kz;
+        }
+        if (hx_ok(g, i, j, k)) {
+            double mu = (double)muv(M, 0, idx), h = hx[idx];
+            if (mu > 0.0) sq += h * h / mu;
+            double d = ldd(ez, g, i, j + 1, k) - (double)ez[idx];
+            r += mu * d * d;
+            lc += h * (ldd(ey, g, i, j, k + 1) - (double)ey[idx]);
+        }
+        if (hy_ok(g, i, j, k)) {
+            double mu = (double)muv(M, 1, idx), h = hy[idx];
+            if (mu > 0.0) sq += h * h / mu;
+            double d = ldd(ez, g, i + 1, j, k) - (double)ez[idx];
+            r += mu * d * d;
+            lc -= h * (ldd(ex, g, i, j, k + 1) - (double)ex[idx]);
+        }
+        if (hz_ok(g, i, j, k)) {
+            double mu = (double)muv(M, 2, idx), h = hz[idx];
+            if (mu > 0.0) sq += h * h / mu;
+        }
+        acc += 0.5 * sq - 0.5 * a * a * r + a * lc;
+    }
+    double s = block_reduce<false>(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <bool MAX>
+__global__ __launch_bounds__(RED_THREADS) void k_finish(const double* partial, int n, int stride, double* out)
+{
+    double v = MAX ? 0.0 : 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        double x = partial[(int64_t)t * stride];
+        v = MAX ? nan_max(v, x) : v + x;
+    }
+    double r = block_reduce<MAX>(v);
+    if (threadIdx.x == 0) *out = r;
+}
+
+// Conserved charges (Sec. 4.5), from y^n (o) and y^{n+1} (nf):
+//  q_e^{n+1/2} at nodes with six non-PEC edges, compared with the charge of the
+//  bunch inside the node's dual cell at tau_{n+1/2}: lam_{k-n-1+M} on the bunch line;
+//  q_h^n at every cell (must stay zero).
+template <typename R>
+__global__ __launch_bounds__(RED_THREADS) void k_charges(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, double a,
+                                                         Src src, double* partial)
+{
+    double me = 0.0, mh = 0.0;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < g.np; idx += gridDim.x * blockDim.x) {
+        int i, j, k;
+        decomp(idx, g, i, j, k);
+        // ---- q_e at node (i,j,k)
+        if (i > 0 && j > 0 && k > 0 && i < g.nx && j < g.ny && k < g.nz) {
+            int ixm = lin(g, i - 1, j, k), jym = lin(g, i, j - 1, k), kzm = lin(g, i, j, k - 1);
+            double kx0 = kap(M, 0, idx), kx1 = kap(M, 0, ixm), ky0 = kap(M, 1, idx), ky1 = kap(M, 1, jym),
+                   kz0 = kap(M, 2, idx), kz1 = kap(M, 2, kzm);
+            if (kx0 > 0 && kx1 > 0 && ky0 > 0 && ky1 > 0 && kz0 > 0 && kz1 > 0) {
+                auto dbar = [&](int c, int id, double kp) {
+                    return 0.5 * ((double)o.c[c][id] + (double)nf.c[c][id]) / kp;
+                };
+                // dtil_z(kk) = e_z/kappa_z - a^2 (P_y^T mu_x P_y + P_x^T mu_y P_x) e_z at level kk, e_z^{n+1/2}
+                auto dtil = [&](int kk, double kp) {
+                    const R* e = nf.c[2];
+                    int id = lin(g, i, j, kk);
+                    double e0 = e[id];
+                    double mxm = muv(M, 0, lin(g, i, j - 1, kk)), mxp = muv(M, 0, id);
+                    double mym = muv(M, 1, lin(g, i - 1, j, kk)), myp = muv(M, 1, id);
+                    double rr = mxm * (e0 - (double)e[lin(g, i, j - 1, kk)]) - mxp * ((double)e[lin(g, i, j + 1, kk)] - e0)
+                              + mym * (e0 - (double)e[lin(g, i - 1, j, kk)]) - myp * ((double)e[lin(g, i + 1, j, kk)] - e0);
+                    return e0 / kp - a * a * rr;
+                };
+                double q = dbar(0, idx, kx0) - dbar(0, ixm, kx1) + dbar(1, idx, ky0) - dbar(1, jym, ky1)
+                         + dtil(k, kz0) - dtil(k - 1, kz1);
+                double want = 0.0;
+                if (src.on && i == src.i0 && j == src.j0) {
+                    int64_t m = (int64_t)k - src.n - 1 + src.M;
+                    if (m >= -src.M && m <= src.M) want = src.lam[m + src.M];
+                }
+                double res = fabs(q - want);
+                me = nan_max(me, (res <= DBL_MAX) ? res : NAN);
+            }
+        }
+        // ---- q_h at cell (i,j,k)
+        if (i < g.nx && j < g.ny && k < g.nz) {
+            auto bbar = [&](int c, int id) {
+                double mu = muv(M, c - 3, id);
+                return mu > 0.0 ? 0.5 * ((double)o.c[c][id] + (double)nf.c[c][id]) / mu : 0.0;
+            };
+            auto btil = [&](int kk) {
+                const R* h = o.c[5];
+                int id = lin(g, i, j, kk);
+                double mu = muv(M, 2, id);
+                if (!(mu > 0.0)) return 0.0;
+                double h0 = h[id];
+                double gxp = (double)kap(M, 0, lin(g, i, j + 1, kk)) * (h0 - ldd(h, g, i, j + 1, kk));
+                double gx0 = (double)kap(M, 0, id) * (ldd(h, g, i, j - 1, kk) - h0);
+                double gyp = (double)kap(M, 1, lin(g, i + 1, j, kk)) * (h0 - ldd(h, g, i + 1, j, kk));
+                double gy0 = (double)kap(M, 1, id) * (ldd(h, g, i - 1, j, kk) - h0);
+                return h0 / mu - a * a * ((gxp - gx0) + (gyp - gy0));
+            };
+            double q = bbar(3, lin(g, i + 1, j, k)) - bbar(3, idx) + bbar(4, lin(g, i, j + 1, k)) - bbar(4, idx)
+                     + btil(k + 1) - btil(k);
+            double res = fabs(q);
+            mh = nan_max(mh, (res <= DBL_MAX) ? res : NAN);
+        }
+    }
+    double re = block_reduce<true>(me);
+    double rh = block_reduce<true>(mh);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = re;
+        partial[2 * blockIdx.x + 1] = rh;
+    }
+}
+
+template <typename R>
+__global__ void k_probes(const R* ez, const int64_t* idx, int n, double* out)
+{
+    int t = threadIdx.x;
+    if (t < n) out[t] = (double)ez[idx[t]];
+}
+
+inline int nblocks(int64_t n, int tb) { return (int)((n + tb - 1) / tb); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int nb = (int)std::min<int64_t>(nblocks(n, TB), 65536);
+    k_fill_u8<<<nb, TB, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int nb = (int)std::min<int64_t>(nblocks(n, TB), 65536);
+    k_fill_f64<<<nb, TB, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_bytes(void* p, size_t bytes, hipStream_t s)
+{
+    // bulk in 16-byte stores (p is 256-byte aligned), tail bytewise
+    int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 > 0) {
+        int nb = (int)std::min<int64_t>(nblocks(n16, TB), 65536);
+        k_zero16<<<nb, TB, 0, s>>>((uint4*)p, n16);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return launch_fill_u8((uint8_t*)p + n16 * 16, (int64_t)(bytes - n16 * 16), 0, s);
+}
+
+hipError_t launch_build_codes(uint8_t* code, const uint8_t* cells, Geo g, hipStream_t s)
+{
+    k_build_codes<<<nblocks(g.np, TB), TB, 0, s>>>(code, cells, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_lambda(double* lam, double Q, double sigma, double dz, int M, hipStream_t s)
+{
+    k_lambda<<<nblocks(2 * M + 1, TB), TB, 0, s>>>(lam, Q, sigma, dz, M);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_import(Fields<R> dst, const void* const src[6], int src_fp32, Mat<R> mat, Geo g, hipStream_t s)
+{
+    k_import<R><<<nblocks(g.np, TB), TB, 0, s>>>(dst, src[0], src[1], src[2], src[3], src[4], src[5], src_fp32, mat, g);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_export(void* const dst[6], int dst_fp32, Fields<R> src, Geo g, hipStream_t s)
+{
+    k_export<R><<<nblocks(g.np, TB), TB, 0, s>>>(dst[0], dst[1], dst[2], dst[3], dst[4], dst[5], dst_fp32, src, g);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_import_materials(R* const dst[6], const void* const src[6], int src_fp32, Geo g, hipStream_t s)
+{
+    k_import_mat<R><<<nblocks(g.np, TB), TB, 0, s>>>(dst[0], dst[1], dst[2], dst[3], dst[4], dst[5], src[0], src[1],
+                                                     src[2], src[3], src[4], src[5], src_fp32, g);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_zero_pec(Fields<R> f, Mat<R> mat, Geo g, hipStream_t s)
+{
+    k_zero_pec<R><<<nblocks(g.np, TB), TB, 0, s>>>(f, mat, g);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_step(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src, hipStream_t s,
+                       hipEvent_t* ev)
+{
+    int nb = nblocks(g.np, TB);
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+    k_tm<R><<<nb, TB, 0, s>>>(oldf, newf, mat, g, alpha, src);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+    k_te<R><<<nb, TB, 0, s>>>(oldf, newf, mat, g, alpha);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t launch_energy(Fields<R> f, Mat<R> mat, Geo g, double alpha, double* partial, double* out, hipStream_t s)
+{
+    k_energy<R><<<RED_BLOCKS, RED_THREADS, 0, s>>>(f, mat, g, alpha, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_finish<false><<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, out);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_charges(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, double alpha, Src src, double* partial,
+                          double* out, hipStream_t s)
+{
+    k_charges<R><<<RED_BLOCKS, RED_THREADS, 0, s>>>(oldf, newf, mat, g, alpha, src, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_finish<true><<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 2, out);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_finish<true><<<1, RED_THREADS, 0, s>>>(partial + 1, RED_BLOCKS, 2, out + 1);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_probes(const R* ez, const int64_t* idx, int nprobe, double* out, hipStream_t s)
+{
+    if (nprobe <= 0) return hipSuccess;
+    k_probes<R><<<1, 64, 0, s>>>(ez, idx, nprobe, out);
+    return hipGetLastError();
+}
+
+#define TETE_INST(R)                                                                                              \
+    template hipError_t launch_import<R>(Fields<R>, const void* const[6], int, Mat<R>, Geo, hipStream_t);          \
+    template hipError_t launch_export<R>(void* const[6], int, Fields<R>, Geo, hipStream_t);                        \
+    template hipError_t launch_import_materials<R>(R* const[6], const void* const[6], int, Geo, hipStream_t);      \
+    template hipError_t launch_zero_pec<R>(Fields<R>, Mat<R>, Geo, hipStream_t);                                   \
+    template hipError_t launch_step<R>(Fields<R>, Fields<R>, Mat<R>, Geo, R, Src, hipStream_t, hipEvent_t*);                    \
+    template hipError_t launch_energy<R>(Fields<R>, Mat<R>, Geo, double, double*, double*, hipStream_t);           \
+    template hipError_t launch_charges<R>(Fields<R>, Fields<R>, Mat<R>, Geo, double, Src, double*, double*,        \
+                                          hipStream_t);                                                            \
+    template hipError_t launch_probes<R>(const R*, const int64_t*, int, double*, hipStream_t);
+
+TETE_INST(double)
+TETE_INST(float)
+
+}  // namespace tete

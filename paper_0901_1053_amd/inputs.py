@@ -277,3 +277,23 @@ def batched_cases(count: int = 64, seed: int = 20260901, nts=(64, 96, 128, 160, 
         nz = int(rng.choice(nzs))
         out.append(scaled_wake_case(nt, nz, seed + 1 + r))
     return out
+
+
+def random_fields_torch(shape, seed: int, device, dtype):
+    """Seeded N(0,1) fields generated on the device (for full-size runs)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    return {k: torch.randn(shape, generator=gen, device=device, dtype=dtype) for k in KEYS}
+
+
+def sample_points(shape, seed: int, count: int = 16):
+    """Seeded node indices for sampled parity checks: random interior points
+    plus points on the walls and corners of the box."""
+    nx, ny, nz = shape[0] - 1, shape[1] - 1, shape[2] - 1
+    rng = np.random.default_rng(seed)
+    pts = [(0, 0, 0), (nx, ny, nz), (nx // 2, ny // 2, 0), (nx // 2, ny // 2, nz - 1), (1, ny - 1, nz // 2),
+           (nx - 1, 1, 1)]
+    while len(pts) < count:
+        pts.append((int(rng.integers(0, nx + 1)), int(rng.integers(0, ny + 1)), int(rng.integers(0, nz + 1))))
+    return pts

@@ -1,0 +1,269 @@
+"""Thin Python binding of libtete (include/tete.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch provides the device workspace, the device arrays handed to
+the library, and the stream.  If the library is not built the import fails
+loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtete.so")
+
+FP64, FP32 = 0, 1
+F_MATERIALS = 1
+MAX_BUNCH_CELLS = 8191
+MAX_WAKE = 65536
+MAX_PROBES = 16
+KEYS = ("ex", "ey", "ez", "hx", "hy", "hz")
+
+STATUS = {0: "TETE_OK", -1: "TETE_ERR_ARG", -2: "TETE_ERR_UNSTABLE", -3: "TETE_ERR_NOMEM",
+          -4: "TETE_ERR_DEVICE", -5: "TETE_ERR_STATE", -6: "TETE_ERR_NONFINITE"}
+
+
+class TeteError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__("%s failed: %s (%d)" % (fn, STATUS.get(code, "?"), code))
+        self.code = code
+        self.status = STATUS.get(code, "?")
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("cdt", C.c_double),
+                ("precision", C.c_int32), ("flags", C.c_uint32), ("max_series", C.c_int32)]
+
+
+class Bunch(C.Structure):
+    _fields_ = [("charge_C", C.c_double), ("sigma_z", C.c_double), ("i0", C.c_int32), ("j0", C.c_int32),
+                ("half_cells", C.c_int32), ("jmin", C.c_int32), ("nw", C.c_int32)]
+
+
+_lib = None
+P6 = C.c_void_p * 6
+P3 = C.c_void_p * 3
+
+
+def load(path: str = LIB_PATH):
+    """Load libtete.so and declare its C signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libtete.so is not built (%s); run python -m paper_0901_1053_amd.build" % path)
+    L = C.CDLL(path)
+    st = C.c_int
+    vp = C.c_void_p
+    sig = {
+        "tete_check_desc": (st, [C.POINTER(GridDesc)]),
+        "tete_workspace_bytes": (C.c_size_t, [C.POINTER(GridDesc)]),
+        "tete_grid_create": (st, [C.POINTER(GridDesc), vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "tete_grid_destroy": (st, [vp]),
+        "tete_set_pec_cells": (st, [vp, vp]),
+        "tete_set_materials": (st, [vp, P3, P3, C.c_int32]),
+        "tete_set_fields": (st, [vp, P6, C.c_int32]),
+        "tete_get_fields": (st, [vp, P6, C.c_int32]),
+        "tete_set_bunch": (st, [vp, C.POINTER(Bunch)]),
+        "tete_clear_bunch": (st, [vp]),
+        "tete_set_diagnostics": (st, [vp, C.c_int32]),
+        "tete_set_probes": (st, [vp, vp, C.c_int32]),
+        "tete_step": (st, [vp, C.c_int64]),
+        "tete_steps_done": (st, [vp, C.POINTER(C.c_int64)]),
+        "tete_wake": (st, [vp, vp, C.c_int32]),
+        "tete_energy": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "tete_energy_series": (st, [vp, vp, C.c_int64, C.POINTER(C.c_int64)]),
+        "tete_probes": (st, [vp, vp, C.c_int64, C.POINTER(C.c_int64)]),
+        "tete_charges": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "tete_set_timing": (st, [vp, C.c_int64]),
+        "tete_timing": (st, [vp, vp, C.c_int32, C.POINTER(C.c_int64)]),
+        "tete_status_str": (C.c_char_p, [C.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _chk(fn, code):
+    if code != 0:
+        raise TeteError(fn, code)
+
+
+def make_desc(nx, ny, nz, dx, dy, dz, cdt, precision="fp64", materials=False, max_series=0) -> GridDesc:
+    prec = {"fp64": FP64, "fp32": FP32}[precision]
+    return GridDesc(nx, ny, nz, dx, dy, dz, cdt, prec, F_MATERIALS if materials else 0, max_series)
+
+
+def check_desc(desc: GridDesc) -> str:
+    return STATUS[load().tete_check_desc(C.byref(desc))]
+
+
+def workspace_bytes(desc: GridDesc) -> int:
+    return int(load().tete_workspace_bytes(C.byref(desc)))
+
+
+class Grid:
+    """One explicit TE/TM grid living in a torch-owned device workspace."""
+
+    def __init__(self, nx, ny, nz, dx, dy, dz, cdt, precision="fp64", materials=False, max_series=0,
+                 device="cuda:0", stream=None):
+        import torch
+        L = load()
+        self.torch = torch
+        self.desc = make_desc(nx, ny, nz, dx, dy, dz, cdt, precision, materials, max_series)
+        _chk("tete_check_desc", L.tete_check_desc(C.byref(self.desc)))
+        self.nbytes = workspace_bytes(self.desc)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # 256-byte aligned workspace (the caching allocator aligns to 512 bytes)
+        self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        assert self.ws.data_ptr() % 256 == 0
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _chk("tete_grid_create", L.tete_grid_create(C.byref(self.desc), C.c_void_p(self.ws.data_ptr()),
+                                                        self.nbytes, C.c_void_p(self.stream.cuda_stream),
+                                                        C.byref(h)))
+        self.h = h
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.dx, self.dy, self.dz, self.cdt = dx, dy, dz, cdt
+        self.precision = precision
+        self.shape = (nx + 1, ny + 1, nz + 1)
+        self.np = (nx + 1) * (ny + 1) * (nz + 1)
+        self.bunch = None
+        self._keep = []
+
+    # -- helpers ---------------------------------------------------------
+    def _dev(self, a, dtype):
+        t = self.torch
+        if isinstance(a, np.ndarray):
+            a = t.from_numpy(np.ascontiguousarray(a))
+        return a.to(device=self.device, dtype=dtype).contiguous()
+
+    def close(self):
+        if self.h:
+            load().tete_grid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- set-up ---------------------------------------------------------
+    def set_pec_cells(self, cells):
+        t = self.torch
+        if cells is None:
+            _chk("tete_set_pec_cells", load().tete_set_pec_cells(self.h, None))
+            return
+        d = self._dev(cells, t.uint8)
+        assert tuple(d.shape) == (self.nx, self.ny, self.nz)
+        _chk("tete_set_pec_cells", load().tete_set_pec_cells(self.h, C.c_void_p(d.data_ptr())))
+        self.stream.synchronize()
+
+    def set_materials(self, mat: dict, dtype="fp64"):
+        t = self.torch
+        td = t.float64 if dtype == "fp64" else t.float32
+        arrs = [self._dev(mat[k], td) for k in KEYS]
+        pe = P3(*[a.data_ptr() for a in arrs[:3]])
+        pm = P3(*[a.data_ptr() for a in arrs[3:]])
+        _chk("tete_set_materials", load().tete_set_materials(self.h, pe, pm, FP64 if dtype == "fp64" else FP32))
+        self.stream.synchronize()
+
+    def set_fields(self, f: dict, dtype="fp64"):
+        t = self.torch
+        td = t.float64 if dtype == "fp64" else t.float32
+        arrs = [self._dev(f[k], td) for k in KEYS]
+        for a in arrs:
+            assert a.numel() == self.np
+        _chk("tete_set_fields", load().tete_set_fields(self.h, P6(*[a.data_ptr() for a in arrs]),
+                                                       FP64 if dtype == "fp64" else FP32))
+        self.stream.synchronize()
+
+    def get_fields(self, dtype="fp64", numpy=True):
+        t = self.torch
+        td = t.float64 if dtype == "fp64" else t.float32
+        arrs = [t.empty(self.shape, dtype=td, device=self.device) for _ in KEYS]
+        _chk("tete_get_fields", load().tete_get_fields(self.h, P6(*[a.data_ptr() for a in arrs]),
+                                                       FP64 if dtype == "fp64" else FP32))
+        self.stream.synchronize()
+        if numpy:
+            return {k: a.cpu().numpy() for k, a in zip(KEYS, arrs)}
+        return dict(zip(KEYS, arrs))
+
+    def set_bunch(self, charge, sigma, i0, j0, half_cells, jmin, nw):
+        self.bunch = Bunch(charge, sigma, i0, j0, half_cells, jmin, nw)
+        _chk("tete_set_bunch", load().tete_set_bunch(self.h, C.byref(self.bunch)))
+
+    def clear_bunch(self):
+        _chk("tete_clear_bunch", load().tete_clear_bunch(self.h))
+        self.bunch = None
+
+    def set_diagnostics(self, every: int):
+        _chk("tete_set_diagnostics", load().tete_set_diagnostics(self.h, every))
+
+    def set_probes(self, idx):
+        a = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+        _chk("tete_set_probes", load().tete_set_probes(self.h, a.ctypes.data, len(a)))
+
+    # -- stepping -------------------------------------------------------
+    def step(self, n: int):
+        _chk("tete_step", load().tete_step(self.h, int(n)))
+
+    def steps_done(self) -> int:
+        v = C.c_int64()
+        _chk("tete_steps_done", load().tete_steps_done(self.h, C.byref(v)))
+        return v.value
+
+    # -- results --------------------------------------------------------
+    def wake(self) -> np.ndarray:
+        """W(s_j) in V/C for j = jmin .. jmin+nw-1."""
+        nw = self.bunch.nw
+        out = np.zeros(nw)
+        _chk("tete_wake", load().tete_wake(self.h, out.ctypes.data, nw))
+        return out
+
+    def wake_s(self) -> np.ndarray:
+        return (self.bunch.jmin + np.arange(self.bunch.nw)) * self.dz
+
+    def energy(self):
+        w = C.c_double()
+        n = C.c_int64()
+        _chk("tete_energy", load().tete_energy(self.h, C.byref(w), C.byref(n)))
+        return w.value, n.value
+
+    def energy_series(self, max_n=1 << 20) -> np.ndarray:
+        cnt = C.c_int64()
+        out = np.zeros(max_n)
+        _chk("tete_energy_series", load().tete_energy_series(self.h, out.ctypes.data, max_n, C.byref(cnt)))
+        return out[: min(cnt.value, max_n)].copy()
+
+    def probes(self, nprobe: int, max_steps=1 << 16) -> np.ndarray:
+        cnt = C.c_int64()
+        out = np.zeros(max_steps * nprobe)
+        _chk("tete_probes", load().tete_probes(self.h, out.ctypes.data, out.size, C.byref(cnt)))
+        n = min(cnt.value, max_steps)
+        return out[: n * nprobe].reshape(n, nprobe).copy()
+
+    def set_timing(self, max_steps: int):
+        _chk("tete_set_timing", load().tete_set_timing(self.h, int(max_steps)))
+
+    def timing(self):
+        """(ms of the TM-like kernel, ms of the TE-like kernel, timed steps)."""
+        ms = np.zeros(2)
+        n = C.c_int64()
+        _chk("tete_timing", load().tete_timing(self.h, ms.ctypes.data, 2, C.byref(n)))
+        return float(ms[0]), float(ms[1]), n.value
+
+    def charges(self):
+        e = C.c_double()
+        h = C.c_double()
+        _chk("tete_charges", load().tete_charges(self.h, C.byref(e), C.byref(h)))
+        return e.value, h.value

@@ -1,0 +1,85 @@
+"""Full-size GPU checks in the benchmark's launch configuration.
+
+(1) Sampled parity: random initial fields on the full grid, a few steps, and
+    the oracle recomputes sampled entries one by one from sub-boxes (their
+    domain of dependence).
+(2) Properties that hold at any size for a complete wake run: the modified
+    Gauss law (35)/(34), causality of the wake, and the wake energy identity
+    (field energy left behind = sum_m lam_m Q W(s = -m dz))."""
+import numpy as np
+import pytest
+
+from paper_0901_1053_amd import inputs, tete
+from tests import parity as P
+from tests.subbox import oracle_point
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("which,precision", [("single", "fp64"), ("single", "fp32"), ("large", "fp32")])
+def test_full_size_sampled_parity(which, precision):
+    import torch
+    case = inputs.single_wake_case() if which == "single" else inputs.large_case()
+    print("case", case.name, precision, flush=True)
+    cells = case.cell_mask()
+    G = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.cdt, precision=precision)
+    G.set_pec_cells(cells)
+    td = torch.float64 if precision == "fp64" else torch.float32
+    f0 = inputs.random_fields_torch(G.shape, case.seed, "cuda", td)
+    G.set_fields(f0, dtype=precision)
+    steps = 3
+    G.step(steps)
+    fg = G.get_fields(dtype=precision, numpy=False)
+    masks = P.range_masks((3, 3, 3))    # component range by position class, see below
+    nx, ny, nz = case.nx, case.ny, case.nz
+
+    def in_range(k, p):
+        i, j, kk = p
+        return {"ex": i < nx, "ey": j < ny, "ez": kk < nz, "hx": j < ny and kk < nz,
+                "hy": i < nx and kk < nz, "hz": i < nx and j < ny}[k]
+
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for p in inputs.sample_points(G.shape, case.seed + 1, count=16) + [(case.i0, case.j0, nz // 2)]:
+        vals, sub = oracle_point(
+            p, G.shape, case.dx, case.dy, case.dz, case.cdt,
+            lambda lo, hi: {k: f0[k][lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1].double().cpu().numpy()
+                            for k in tete.KEYS},
+            lambda lo, hi: cells[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]], steps)
+        scale = max(np.max(np.abs(v)) for v in sub.values())
+        for k in tete.KEYS:
+            got = float(fg[k][p].item())
+            if in_range(k, p):
+                assert abs(got - vals[k]) <= tol * scale, (p, k, got, vals[k])
+            else:
+                assert got == 0.0, (p, k)
+    del fg, f0, G
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_single_wake_full_run_properties(precision):
+    """Step collimator 128x128x1024, 1 nC, sigma = 1 mm, run until the bunch
+    has left the grid, with a wake window reaching ahead of the head."""
+    case = inputs.single_wake_case()
+    M = case.M
+    jmin = -M - 8
+    jmax = M + 8
+    nw = jmax - jmin + 1
+    steps = case.nz + M + jmax + 1
+    print("steps", steps, flush=True)
+    G = P.gpu_grid(case, precision)
+    G.set_bunch(case.Q, case.sigma, case.i0, case.j0, M, jmin, nw)
+    G.step(steps)
+    W = G.wake()
+    e, _ = G.energy()
+    j = jmin + np.arange(nw)
+    assert np.all(W[j < -M] == 0.0)
+    from oracle import oracle as O
+    lam = O.bunch_cells(case.Q, case.sigma, case.dz, M)
+    acc = W * case.Q * P.EPS0                          # back to internal units
+    tot = sum(lam[m + M] * acc[-m - jmin] for m in range(-M, M + 1))
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert e > 0 and abs(e - tot) <= tol * e * 10
+    if precision == "fp64":
+        res_e, res_h = G.charges()
+        assert res_e <= 1e-12 * case.Q and res_h <= 1e-12 * case.Q
