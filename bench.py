@@ -25,6 +25,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_traffic.json")
+
+
+def measured_traffic(kernel_name, workload, precision):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current source of the fused kernel; else None."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+        with open(os.path.join(ROOT, t["source"]), "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError, KeyError):
+        return None
+    if sha != t["source_sha256"] or t["workload"] != workload or t["precision"] != precision:
+        return None
+    if not kernel_name.startswith("k_fused"):
+        return None
+    return t["read_bytes_per_launch"] + t["write_bytes_per_launch"]
 METRIC = "Gcell-updates/s + HBM GB/s; batched wake solves/s with p50/p99 latency"
 
 
@@ -55,6 +74,13 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single-wake", action="store_true")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "split"])
+    ap.add_argument("--rows", type=int, default=0, help="fused kernel: rows per workgroup (12 or 16)")
+    ap.add_argument("--xchunk", type=int, default=0, help="fused kernel: x-planes per workgroup (0: auto)")
+    ap.add_argument("--depth", type=int, default=0, help="fused kernel: planes prefetched ahead (1..3)")
+    ap.add_argument("--order", type=int, default=0, help="fused kernel: tile order (1..3; 0: library default)")
+    ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device copy of this many GiB, 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
@@ -64,12 +90,25 @@ def main():
     import torch
     from paper_0901_1053_amd import inputs, tete
 
+    if args.calibrate_copy > 0:
+        n = int(args.calibrate_copy * 2 ** 30) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n}))
+        return
+
     case = inputs.large_case()
     print("# workload %s, %s, steps %d, warmup %d" % (case.name, args.precision, args.steps, args.warmup),
           file=sys.stderr, flush=True)
     G = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.cdt, precision=args.precision)
     G.set_pec_cells(case.cell_mask())
     G.set_bunch(case.Q, case.sigma, case.i0, case.j0, case.M, case.jmin, case.nw)
+    G.set_tuning(args.kernel, args.rows, args.xchunk, args.depth, args.order)
+    tuning = G.get_tuning()
     G.step(args.warmup)
     torch.cuda.synchronize()
 
@@ -93,9 +132,14 @@ def main():
     ms_step = ms / K
     value = cells * K / (ms / 1e3) / 1e9
     step_bytes = (12 * b + 1) * entries        # read + write six components, PEC code
-    kern = {"tm": ms_tm / nt, "te": ms_te / nt}
-    dom = max(kern, key=kern.get)
-    kbytes = (8 * b + 1) * entries             # each half reads five arrays + code, writes three
+    if tuning["kernel"] == "fused":
+        kern = {"fused": ms_tm / nt}
+        dom = "fused"
+        kbytes = step_bytes                    # one launch per step
+    else:
+        kern = {"tm": ms_tm / nt, "te": ms_te / nt}
+        dom = max(kern, key=kern.get)
+        kbytes = (8 * b + 1) * entries         # each half reads five arrays + code, writes three
     achieved = kbytes / (kern[dom] / 1e3) / 1e9
     out = {
         "metric": METRIC,
@@ -113,11 +157,12 @@ def main():
         "config": {"workload": case.name, "cells": cells, "grid_entries": entries,
                    "fields": args.precision, "wake_accumulation": "fp64",
                    "geometry": "tapered round aperture in 20 mm square pipe, 10 deg, 2->10 mm diameter",
-                   "bunch_sigma_m": case.sigma, "cdt_over_dz": 1.0, "dx_over_dz": 2.0},
+                   "bunch_sigma_m": case.sigma, "cdt_over_dz": 1.0, "dx_over_dz": 2.0,
+                   "kernel": tuning},
         "hbm_gbps_algorithmic": round(step_bytes / (ms_step / 1e3) / 1e9, 1),
         "roofline": {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(achieved, 1),
                      "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
-                     "traffic": None,
+                     "traffic": measured_traffic("k_" + dom, case.name, args.precision),
                      "bytes_per_launch": kbytes, "ms_per_launch": round(kern[dom], 4),
                      "kernels_ms_per_step": {k: round(v, 4) for k, v in kern.items()}},
     }

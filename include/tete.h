@@ -196,16 +196,41 @@ tete_status tete_probes(tete_grid* g, double* out, int64_t max, int64_t* count);
  * Synchronises.  TETE_ERR_STATE if no step has run. */
 tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h);
 
+/* Kernel choice and launch shape (for tuning; results do not depend on it
+ * beyond rounding order).  kernel: TETE_KERNEL_AUTO picks the fused
+ * single-kernel step unless per-entry materials are set; TETE_KERNEL_FUSED
+ * forces it (TETE_ERR_STATE with per-entry materials); TETE_KERNEL_SPLIT runs
+ * the two-kernel step (one kernel per half step).  rows: rows per workgroup of
+ * the fused kernel, 12 or 16 (0: 16 for FP32, 12 for FP64).  xchunk: x-planes per workgroup of the
+ * fused kernel (0: chosen from the grid size).  depth: x-planes of old data
+ * the fused kernel prefetches ahead, 1..3 (0: 2).  order: order in which
+ * the fused kernel's tiles are scheduled: 1 (j-tiles first), 2 (k-tiles
+ * first), 3 (blocks of 8 k-tiles by 4 j-tiles); 0 = 2.  tete_set_materials turns a
+ * forced FUSED back into AUTO.  tete_get_tuning reports the kernel that
+ * tete_step will use (FUSED or SPLIT). */
+enum { TETE_KERNEL_AUTO = 0, TETE_KERNEL_FUSED = 1, TETE_KERNEL_SPLIT = 2 };
+typedef struct {
+    int32_t kernel;
+    int32_t rows;
+    int32_t xchunk;
+    int32_t depth;
+    int32_t order;
+} tete_tuning;
+tete_status tete_set_tuning(tete_grid* g, const tete_tuning* t);
+tete_status tete_get_tuning(tete_grid* g, tete_tuning* t);
+
 /* Live kernel timing for measurement.  max_steps > 0 arms up to max_steps
  * timed steps: each subsequent step records HIP events on the grid's stream
- * before, between and after its two kernels (TM-like half S1-S5 with the
- * source and wake update; TE-like half S6-S10).  0 disarms.  Synchronises.
+ * around its kernels (fused step: one kernel; two-kernel step: TM-like half
+ * S1-S5 with the source and wake update, then TE-like half S6-S10).  0
+ * disarms.  Synchronises.
  * Steps beyond the armed count fail with TETE_ERR_STATE. */
 tete_status tete_set_timing(tete_grid* g, int64_t max_steps);
 
 /* Sum of the kernel durations of the timed steps since the last call, in ms:
- * ms[0] = TM-like kernel, ms[1] = TE-like kernel (nphase >= 2); *steps =
- * number of timed steps.  Resets the count.  Synchronises. */
+ * two-kernel step: ms[0] = TM-like kernel, ms[1] = TE-like kernel; fused
+ * step: ms[0] = the fused kernel, ms[1] = 0 (nphase >= 2); *steps = number
+ * of timed steps.  Resets the count.  Synchronises. */
 tete_status tete_timing(tete_grid* g, double* ms, int32_t nphase, int64_t* steps);
 
 /* Human-readable status name. */

@@ -88,6 +88,7 @@ struct tete_grid {
     int64_t ecount, pcount, cap;
     int nprobe;
     double kv[3], mv[3], alpha;
+    tete_tuning tune;
     // live kernel timing (tete_set_timing): 3 events per timed step
     int timing;
     hipEvent_t* ev;
@@ -136,6 +137,14 @@ Src source(tete_grid* g, int64_t n)
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
+// The fused kernel covers vacuum cells with staircase PEC codes; per-entry
+// materials take the two-kernel path.
+bool use_fused(const tete_grid* g)
+{
+    if (g->mat_set || !fused_fits(g->geo, g->fp32 ? 4 : 8)) return false;
+    return g->tune.kernel != TETE_KERNEL_SPLIT;
+}
+
 template <typename R>
 tete_status do_steps(tete_grid* g, int64_t nsteps)
 {
@@ -152,8 +161,13 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             ev = g->ev + 3 * g->ev_steps;
             g->ev_steps++;
         }
-        HIPCHK(launch_step<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
-                              source(g, g->n), g->stream, ev));
+        if (use_fused(g))
+            HIPCHK(launch_step_fused<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
+                                        source(g, g->n), g->tune.rows, g->tune.xchunk, g->tune.depth, g->tune.order,
+                                        g->stream, ev));
+        else
+            HIPCHK(launch_step<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
+                                  source(g, g->n), g->stream, ev));
         g->cur = 1 - g->cur;
         g->n++;
         if (g->nprobe > 0) {
@@ -261,6 +275,11 @@ tete_status tete_grid_create(const tete_grid_desc* d, void* dev_ws, size_t ws_by
     g->kv[1] = g->mv[1] = d->dy / (d->dz * d->dx);
     g->kv[2] = g->mv[2] = d->dz / (d->dx * d->dy);
     g->alpha = 0.5 * d->cdt;   // alpha = dtau / 2, eq. (17)
+    g->tune.kernel = TETE_KERNEL_AUTO;
+    g->tune.rows = 0;
+    g->tune.xchunk = 0;
+    g->tune.depth = 2;
+    g->tune.order = 0;
 
     // zero the whole workspace, then mark the box walls
     if (launch_zero_bytes(g->ws, L.total, g->stream) != hipSuccess ||
@@ -278,6 +297,28 @@ tete_status tete_grid_destroy(tete_grid* g)
     for (int64_t e = 0; e < 3 * g->ev_cap; ++e) (void)hipEventDestroy(g->ev[e]);
     free(g->ev);
     free(g);
+    return TETE_OK;
+}
+
+tete_status tete_set_tuning(tete_grid* g, const tete_tuning* t)
+{
+    if (!g || !t) return TETE_ERR_ARG;
+    if (t->kernel < TETE_KERNEL_AUTO || t->kernel > TETE_KERNEL_SPLIT) return TETE_ERR_ARG;
+    if (t->rows != 0 && t->rows != 12 && t->rows != 16) return TETE_ERR_ARG;
+    if (t->xchunk < 0) return TETE_ERR_ARG;
+    if (t->depth < 0 || t->depth > 3) return TETE_ERR_ARG;
+    if (t->order < 0 || t->order > 3) return TETE_ERR_ARG;
+    if (t->kernel == TETE_KERNEL_FUSED && g->mat_set) return TETE_ERR_STATE;
+    g->tune = *t;
+    if (g->tune.depth == 0) g->tune.depth = 2;
+    return TETE_OK;
+}
+
+tete_status tete_get_tuning(tete_grid* g, tete_tuning* t)
+{
+    if (!g || !t) return TETE_ERR_ARG;
+    *t = g->tune;
+    t->kernel = use_fused(g) ? TETE_KERNEL_FUSED : TETE_KERNEL_SPLIT;
     return TETE_OK;
 }
 
@@ -345,6 +386,7 @@ tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3], const
     DeviceGuard dg(g->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
     const void* src[6] = {inv_eps[0], inv_eps[1], inv_eps[2], inv_mu[0], inv_mu[1], inv_mu[2]};
+    if (g->tune.kernel == TETE_KERNEL_FUSED) g->tune.kernel = TETE_KERNEL_AUTO;
     if (g->fp32) {
         float* dst[6];
         for (int c = 0; c < 6; ++c) dst[c] = (float*)g->mat[c];

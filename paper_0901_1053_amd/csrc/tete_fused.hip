@@ -1,0 +1,428 @@
+// Fused explicit TE/TM step (scheme (23), the ten sub-updates of Sec. 4.2) in
+// one kernel, for vacuum cells with staircase PEC codes.
+//
+// Work decomposition.  A workgroup owns a tile of TY rows (j) by 62 entries
+// (k) of the grid and marches along x through a chunk of planes.  Each wave is
+// one j-row of 64 consecutive k (lanes), the tile plus a halo of one k below
+// and one above; the workgroup holds TY + 4 rows, the tile plus a halo of two
+// rows below and two above.  Along k, neighbours come from lane shuffles;
+// along j, from LDS; along x, from registers, because the march visits the
+// planes in order.  Every value of the step is therefore computed in
+// registers and each field entry is read once from HBM and written once.
+//
+// The ten sub-updates form a pipeline over the planes.  With old data of plane
+// p loaded at iteration p, the sub-updates run at plane lags
+//   S1 (h_x^n)          p        S2 (h_y^n)        p-1    S3 (e_z^{n+1/2}) p-1
+//   S4 (h_x^{n+1/2})    p-2      S5 (h_y^{n+1/2})  p-2
+//   S6 (e_x^{n+1/2})    p-2      S7 (e_y^{n+1/2})  p-2    S8 (h_z^{n+1})   p-3
+//   S9 (e_x^{n+1})      p-4      S10 (e_y^{n+1})   p-3
+// chosen so that every j-neighbour a sub-update needs was produced in an
+// earlier iteration (or loaded in this one): one LDS write phase and a single
+// barrier per plane suffice, with the LDS double-buffered by plane parity.
+// The halo rows, halo lanes and the first planes of a chunk compute values
+// that are never stored; only the tile's own entries are written.
+
+#include <algorithm>
+
+#include "tete_impl.h"
+
+namespace tete {
+namespace {
+
+constexpr int KT = 62;   // k entries owned per workgroup (64 lanes minus two halo lanes)
+
+template <typename R>
+struct FArgs {
+    const R* ex; const R* ey; const R* ez; const R* hx; const R* hy; const R* hz;
+    R* ex1; R* ey1; R* ez1; R* hx1; R* hy1; R* hz1;
+    const uint8_t* code;
+    Geo g;
+    R a, kx, ky, kz, mx, my, mz;
+    Src src;
+    int nyt, nzt, nxc, xchunk;   // tiles along j, k; chunks along x; planes per chunk
+    int order;                   // tile order, see tile_of()
+    int nblk;                    // workgroups launched
+};
+
+template <typename R>
+__device__ __forceinline__ R bload(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+template <typename R>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, R v);
+template <>
+__device__ __forceinline__ void bstore<float>(__amdgpu_buffer_rsrc_t r, uint32_t off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+template <>
+__device__ __forceinline__ void bstore<double>(__amdgpu_buffer_rsrc_t r, uint32_t off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+
+// Neighbours along k are the neighbouring lanes of the wave: DPP whole-wave
+// shifts by one lane (lane 0 / lane 63 receive 0; both are halo lanes).
+__device__ __forceinline__ int dpp_prev(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_next(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ float lane_prev(float v) { return __builtin_bit_cast(float, dpp_prev(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ float lane_next(float v) { return __builtin_bit_cast(float, dpp_next(__builtin_bit_cast(int, v))); }
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double lane_prev(double v)
+{
+    i32x2 w = __builtin_bit_cast(i32x2, v);
+    w.x = dpp_prev(w.x);
+    w.y = dpp_prev(w.y);
+    return __builtin_bit_cast(double, w);
+}
+__device__ __forceinline__ double lane_next(double v)
+{
+    i32x2 w = __builtin_bit_cast(i32x2, v);
+    w.x = dpp_next(w.x);
+    w.y = dpp_next(w.y);
+    return __builtin_bit_cast(double, w);
+}
+
+// Logical tile of a workgroup.  Consecutive hardware workgroups are spread
+// round-robin over the eight XCDs; the remap gives each XCD a contiguous range
+// of logical tiles so that neighbouring j-tiles (which share halo rows) run on
+// the same XCD and share its L2.
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    const int nx = 8;
+    int x = b % nx, r = b / nx;
+    int base = n / nx, extra = n % nx;
+    return x < extra ? x * (base + 1) + r : extra * (base + 1) + (x - extra) * base + r;
+}
+
+// Tile (ty, tz) and x-chunk cx of logical workgroup lb.  order 0 or 2:
+// k-tiles fastest, so the tiles of one band of rows, which together cover
+// whole contiguous rows, run together (measured fastest); order 1: j-tiles
+// fastest; order 3: blocks of 8 k-tiles by 4 j-tiles (32 workgroups, one
+// XCD's worth) fastest.  Returns false for the padding workgroups of order 3.
+constexpr int BZ = 8, BY = 4;
+__device__ __forceinline__ bool tile_of(int lb, int order, int nyt, int nzt, int& ty, int& tz, int& cx)
+{
+    if (order == 0 || order == 2) {
+        tz = lb % nzt;
+        ty = (lb / nzt) % nyt;
+        cx = lb / (nzt * nyt);
+        return true;
+    }
+    if (order == 3) {
+        const int nbz = (nzt + BZ - 1) / BZ, nby = (nyt + BY - 1) / BY;
+        const int w = lb % (BZ * BY), b = lb / (BZ * BY);
+        tz = (b % nbz) * BZ + w % BZ;
+        ty = ((b / nbz) % nby) * BY + w / BZ;
+        cx = b / (nbz * nby);
+        return tz < nzt && ty < nyt;
+    }
+    ty = lb % nyt;
+    tz = (lb / nyt) % nzt;
+    cx = lb / (nyt * nzt);
+    return true;
+}
+
+template <typename R, int TYH, int PD>
+__global__ __launch_bounds__(64 * TYH) void k_fused(FArgs<R> A)
+{
+    constexpr int TY = TYH - 4;
+    __shared__ R sEZ[2][TYH + 2][64];
+    __shared__ R sHXN[2][TYH + 2][64];
+    __shared__ R sEZH[2][TYH + 2][64];
+    __shared__ R sHZ[2][TYH + 2][64];
+    __shared__ R sEXH[2][TYH + 2][64];
+    __shared__ R sHZN[2][TYH + 2][64];
+
+    const Geo g = A.g;
+    int ty, tz, cx;
+    if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) return;   // whole group
+
+    const int kl = threadIdx.x & 63;
+    const int jl = threadIdx.x >> 6;
+    const int j = ty * TY - 2 + jl;
+    const int k = tz * KT - 1 + kl;
+    const bool jin = (unsigned)j <= (unsigned)g.ny;
+    const bool kin = (unsigned)k <= (unsigned)g.nz;
+    const bool node = jin && kin;
+    const bool owned = node && jl >= 2 && jl < 2 + TY && kl >= 1 && kl <= KT;
+    const int roff = k + j * g.sz;
+
+    // index-range masks of the h components (x part applied per plane)
+    const bool hx_jk = node && j < g.ny && k < g.nz;
+    const bool hy_k = node && k < g.nz;
+    const bool hz_j = node && j < g.ny;
+
+    const int xs = cx * A.xchunk;
+    const int xe = min(xs + A.xchunk, g.nx + 1);
+    const int xload_end = min(xe + 1, g.nx);    // last plane whose old data is needed
+
+    const R a = A.a, a2 = A.a + A.a;
+    const bool src_row = A.src.on && j == A.src.j0;
+
+    // carried pipeline state (see the lag table above)
+    R EXm1 = 0, EXm2 = 0, pzEXm2 = 0;
+    R EYm1 = 0, EYm2 = 0, pzEYm1 = 0, pzEYm2 = 0;
+    R EZm1 = 0, HYm1 = 0;
+    R HZm1 = 0, HZm2 = 0, HZm3 = 0;
+    uint32_t cm1 = 7, cm2 = 7, cm3 = 7, cm4 = 7;   // PEC codes of planes p-1..p-4
+    R hxn_m1 = 0, hxn_m2 = 0, hyn_m2 = 0, ezh_m2 = 0;
+    R pztHX_m3 = 0, pztHY_m3 = 0, pztHY_m4 = 0;
+    R exh_m3 = 0, exh_m4 = 0, eyh_m3 = 0, hzn_m4 = 0;
+
+    // Loads and stores go through buffer resources built once per workgroup in
+    // scalar registers, each covering the planes of the chunk (loads: from
+    // plane pb = max(0, xs - 2) to xload_end; stores: xs .. xe-1).  The byte
+    // offset of an entry is its in-plane offset plus the plane's offset from
+    // the first covered plane; a plane outside the covered range wraps to an
+    // offset past the end, and lanes outside the grid use an offset past the
+    // end, so out-of-range loads return 0 and such stores are dropped.  The
+    // range check needs every covered range below 2^31 bytes (the host limits
+    // the chunk length accordingly).
+    constexpr uint32_t RB = sizeof(R);
+    constexpr uint32_t OOB = 0x80000000u;
+    const uint32_t plane_bytes = (uint32_t)g.sp * RB;
+    const int pb = max(0, xs - 2);
+    const int nload = xload_end >= pb ? xload_end - pb + 1 : 0;
+    auto mk = [](const void* base, uint32_t bytes) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+    };
+    const int64_t ld0 = (int64_t)pb * g.sp;
+    const auto rEX = mk(A.ex + ld0, nload * plane_bytes), rEY = mk(A.ey + ld0, nload * plane_bytes),
+               rEZ = mk(A.ez + ld0, nload * plane_bytes), rHX = mk(A.hx + ld0, nload * plane_bytes),
+               rHY = mk(A.hy + ld0, nload * plane_bytes), rHZ = mk(A.hz + ld0, nload * plane_bytes);
+    // PEC codes (one byte per entry) are read as the aligned dword holding the
+    // lane's byte: a sub-dword load would be packed with other bytes into one
+    // register, which needs the load complete at once and defeats the prefetch.
+    const auto rC = mk(A.code, (uint32_t)std::min<int64_t>((int64_t)g.np + 4, 0x7fffffff));
+    const int64_t st0 = (int64_t)xs * g.sp;
+    const uint32_t nstb = (uint32_t)(xe - xs) * plane_bytes;
+    const auto sEX = mk(A.ex1 + st0, nstb), sEY = mk(A.ey1 + st0, nstb), sEZ1 = mk(A.ez1 + st0, nstb),
+               sHX = mk(A.hx1 + st0, nstb), sHY = mk(A.hy1 + st0, nstb), sHZ1 = mk(A.hz1 + st0, nstb);
+    const uint32_t in_ld = (uint32_t)roff * RB;
+    const uint32_t cfix = node ? 0u : 7u;              // outside the grid: PEC
+
+    auto load_plane = [&](int i, R& vex, R& vey, R& vez, R& vhx, R& vhy, R& vhz, uint32_t& vc) {
+        const uint32_t po = (uint32_t)(i - pb);
+        const uint32_t off = node ? in_ld + po * plane_bytes : OOB;
+        vex = bload<R>(rEX, off);
+        vey = bload<R>(rEY, off);
+        vez = bload<R>(rEZ, off);
+        vhx = bload<R>(rHX, off);
+        vhy = bload<R>(rHY, off);
+        vhz = bload<R>(rHZ, off);
+        const uint32_t offc = node ? ((uint32_t)(roff + i * g.sp) & ~3u) : OOB;
+        vc = __builtin_amdgcn_raw_buffer_load_b32(rC, offc, 0, 0);   // byte extracted when used
+    };
+
+    // Prefetch: the old data of planes p+1 .. p+PD are in flight while plane p
+    // is processed.  The PD+1 plane buffers are used round-robin by a loop
+    // unrolled PD+1 times, so a buffer that a load is writing is never copied
+    // (a copy would have to wait for that load).
+    struct PR {
+        R ex, ey, ez, hx, hy, hz;
+        uint32_t c;
+    };
+    PR buf[PD + 1];
+#pragma unroll
+    for (int d = 0; d < PD; ++d)
+        load_plane(xs - 2 + d, buf[d].ex, buf[d].ey, buf[d].ez, buf[d].hx, buf[d].hy, buf[d].hz, buf[d].c);
+
+    const int pend = xe + 3;
+    auto body = [&](const int p, const PR& cur, PR& nxt) {
+        load_plane(p + PD, nxt.ex, nxt.ey, nxt.ez, nxt.hx, nxt.hy, nxt.hz, nxt.c);
+        const R EX0 = cur.ex, EY0 = cur.ey, EZ0 = cur.ez, HX0 = cur.hx, HY0 = cur.hy, HZ0 = cur.hz;
+        // outside the grid, or a plane without old data: PEC on all edges
+        const uint32_t c0 = ((cur.c >> (((uint32_t)(roff + p * g.sp) & 3u) * 8u)) & 7u) | cfix |
+                            ((p >= pb && p <= xload_end) ? 0u : 7u);
+
+        // j-exchange through LDS (row r of the tile is LDS row r+1).  Rows 0 and
+        // TYH+1 are never written: what they hold reaches only rows 0, 1,
+        // TYH-2 and TYH-1 of the tile, which are never stored.
+        const int s = p & 1;
+        sEZ[s][jl + 1][kl] = EZ0;
+        sHXN[s][jl + 1][kl] = hxn_m1;
+        sEZH[s][jl + 1][kl] = ezh_m2;
+        sHZ[s][jl + 1][kl] = HZm2;
+        sEXH[s][jl + 1][kl] = exh_m3;
+        sHZN[s][jl + 1][kl] = hzn_m4;
+        __syncthreads();
+        const R EZ0_jp = sEZ[s][jl + 2][kl];
+        const R hxn_m1_jm = sHXN[s][jl][kl];
+        const R ezh_m2_jp = sEZH[s][jl + 2][kl];
+        const R HZm2_jm = sHZ[s][jl][kl];
+        const R exh_m3_jp = sEXH[s][jl + 2][kl];
+        const R hzn_m4_jm = sHZN[s][jl][kl];
+
+        // planes handled in this iteration and their x-range masks
+        const int q0 = p, q1 = p - 1, q2 = p - 2, q3 = p - 3, q4 = p - 4;
+        auto xin = [&](int q) { return (unsigned)q <= (unsigned)g.nx; };
+        auto xlt = [&](int q) { return q >= 0 && q < g.nx; };
+        const R mx0 = (hx_jk && xin(q0)) ? A.mx : R(0);
+        const R mx2 = (hx_jk && xin(q2)) ? A.mx : R(0);
+        const R my1 = (hy_k && xlt(q1)) ? A.my : R(0);
+        const R my2 = (hy_k && xlt(q2)) ? A.my : R(0);
+        const R mz3 = (hz_j && xlt(q3)) ? A.mz : R(0);
+        const R kz1 = (cm1 & 4u) ? R(0) : A.kz;
+        const R ky2 = (cm2 & 2u) ? R(0) : A.ky;
+        const R kx2 = (cm2 & 1u) ? R(0) : A.kx;
+        const R ky3 = (cm3 & 2u) ? R(0) : A.ky;
+        const R kx4 = (cm4 & 1u) ? R(0) : A.kx;
+
+        // S1 at q0: h_x^n = h_x^{n-1/2} + a mu_x [P_z e_y^n - P_y e_z^{n-1/2}]
+        const R pzEY0 = lane_next(EY0) - EY0;
+        const R hxn0 = HX0 + a * mx0 * (pzEY0 - (EZ0_jp - EZ0));
+        // S2 at q1: h_y^n = h_y^{n-1/2} + a mu_y [-P_z e_x^n + P_x e_z^{n-1/2}]
+        const R pzEXm1 = lane_next(EXm1) - EXm1;
+        const R hyn_m1 = HYm1 + a * my1 * (-pzEXm1 + (EZ0 - EZm1));
+        // S3 at q1: e_z^{n+1/2} = e_z^{n-1/2} + 2a kappa_z [P_y^T h_x^n - P_x^T h_y^n - j_z^n]
+        R ezh_m1 = EZm1 + a2 * kz1 * ((hxn_m1_jm - hxn_m1) - (hyn_m2 - hyn_m1));
+        if (src_row && q1 == A.src.i0 && kin && k < g.nz) {
+            const int64_t m = (int64_t)k - A.src.n + A.src.M;   // cell m crosses edge k in step n
+            if (m >= -A.src.M && m <= A.src.M) ezh_m1 -= (R)((double)kz1 * A.src.lam[m + A.src.M]);
+            if (owned && q1 >= xs && q1 < xe) {
+                const int64_t js = A.src.n - k - A.src.M;      // wake sample of edge k
+                if (js >= A.src.jmin && js < (int64_t)A.src.jmin + A.src.nw)
+                    A.src.wacc[js - A.src.jmin] += -0.5 * ((double)EZm1 + (double)ezh_m1);
+            }
+        }
+        // S4 at q2: h_x^{n+1/2} = h_x^n + a mu_x [P_z e_y^n - P_y e_z^{n+1/2}]
+        const R hxh_m2 = hxn_m2 + a * mx2 * (pzEYm2 - (ezh_m2_jp - ezh_m2));
+        // S5 at q2: h_y^{n+1/2} = h_y^n + a mu_y [-P_z e_x^n + P_x e_z^{n+1/2}]
+        const R hyh_m2 = hyn_m2 + a * my2 * (-pzEXm2 + (ezh_m1 - ezh_m2));
+        // S7 at q2: e_y^{n+1/2} = e_y^n + a kappa_y [-P_z^T h_x^{n+1/2} + P_x^T h_z^n]
+        const R pztHX_m2 = lane_prev(hxh_m2) - hxh_m2;
+        const R eyh_m2 = EYm2 + a * ky2 * (-pztHX_m2 + (HZm3 - HZm2));
+        // S6 at q2: e_x^{n+1/2} = e_x^n + a kappa_x [P_z^T h_y^{n+1/2} - P_y^T h_z^n]
+        const R pztHY_m2 = lane_prev(hyh_m2) - hyh_m2;
+        const R exh_m2 = EXm2 + a * kx2 * (pztHY_m2 - (HZm2_jm - HZm2));
+        // S8 at q3: h_z^{n+1} = h_z^n + 2a mu_z [P_y e_x^{n+1/2} - P_x e_y^{n+1/2}]
+        const R hzn_m3 = HZm3 + a2 * mz3 * ((exh_m3_jp - exh_m3) - (eyh_m2 - eyh_m3));
+        // S9 at q4: e_x^{n+1} = e_x^{n+1/2} + a kappa_x [P_z^T h_y^{n+1/2} - P_y^T h_z^{n+1}]
+        const R ex1_m4 = exh_m4 + a * kx4 * (pztHY_m4 - (hzn_m4_jm - hzn_m4));
+        // S10 at q3: e_y^{n+1} = e_y^{n+1/2} + a kappa_y [-P_z^T h_x^{n+1/2} + P_x^T h_z^{n+1}]
+        const R ey1_m3 = eyh_m3 + a * ky3 * (-pztHX_m3 + (hzn_m4 - hzn_m3));
+
+        if (owned) {
+            const uint32_t o1 = in_ld + (uint32_t)(q1 - xs) * plane_bytes;
+            const uint32_t o2 = o1 - plane_bytes, o3 = o2 - plane_bytes, o4 = o3 - plane_bytes;
+            bstore<R>(sEZ1, o1, ezh_m1);
+            bstore<R>(sHX, o2, hxh_m2);
+            bstore<R>(sHY, o2, hyh_m2);
+            bstore<R>(sHZ1, o3, hzn_m3);
+            bstore<R>(sEY, o3, ey1_m3);
+            bstore<R>(sEX, o4, ex1_m4);
+        }
+
+        // rotate the pipeline registers by one plane
+        EXm2 = EXm1; EXm1 = EX0; pzEXm2 = pzEXm1;
+        EYm2 = EYm1; EYm1 = EY0; pzEYm2 = pzEYm1; pzEYm1 = pzEY0;
+        EZm1 = EZ0; HYm1 = HY0;
+        HZm3 = HZm2; HZm2 = HZm1; HZm1 = HZ0;
+        cm4 = cm3; cm3 = cm2; cm2 = cm1; cm1 = c0;
+        hxn_m2 = hxn_m1; hxn_m1 = hxn0;
+        hyn_m2 = hyn_m1;
+        ezh_m2 = ezh_m1;
+        pztHX_m3 = pztHX_m2;
+        pztHY_m4 = pztHY_m3; pztHY_m3 = pztHY_m2;
+        exh_m4 = exh_m3; exh_m3 = exh_m2;
+        eyh_m3 = eyh_m2;
+        hzn_m4 = hzn_m3;
+    };
+
+    // The trip count is rounded up to a multiple of PD+1 (no per-plane guard,
+    // which would make the buffers loop phis that the back edge has to copy):
+    // the extra planes lie past the chunk, where loads return 0, stores are
+    // dropped and nothing is accumulated.
+    for (int p = xs - 2; p <= pend; p += PD + 1) {
+#pragma unroll
+        for (int u = 0; u <= PD; ++u) body(p + u, buf[u], buf[(u + PD) % (PD + 1)]);
+    }
+}
+
+template <typename R, int TYH, int PD>
+hipError_t launch_fused_t(const FArgs<R>& A0, int xchunk, hipStream_t s)
+{
+    FArgs<R> A = A0;
+    constexpr int TY = TYH - 4;
+    A.nyt = (A.g.ny + 1 + TY - 1) / TY;
+    A.nzt = (A.g.nz + 1 + KT - 1) / KT;
+    const int nplanes = A.g.nx + 1;
+    int xc = xchunk;
+    if (xc <= 0) {
+        // enough workgroups to fill the chip several times over
+        const int tiles = A.nyt * A.nzt;
+        int chunks = (4096 + tiles - 1) / tiles;
+        chunks = std::max(1, std::min(chunks, (nplanes + 31) / 32));
+        xc = (nplanes + chunks - 1) / chunks;
+    }
+    // every buffer range must stay below 2^31 bytes: (xchunk + 4) planes
+    const int64_t plane_bytes = (int64_t)A.g.sp * sizeof(R);
+    const int64_t xmax = ((int64_t(1) << 31) - 1) / plane_bytes - 4;
+    if (xmax < 1) return hipErrorInvalidValue;
+    xc = (int)std::min<int64_t>(std::max(xc, 1), xmax);
+    A.xchunk = xc;
+    A.nxc = (nplanes + xc - 1) / xc;
+    if (A.order == 3)
+        A.nblk = ((A.nzt + BZ - 1) / BZ) * ((A.nyt + BY - 1) / BY) * BZ * BY * A.nxc;
+    else
+        A.nblk = A.nyt * A.nzt * A.nxc;
+    k_fused<R, TYH, PD><<<A.nblk, 64 * TYH, 0, s>>>(A);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool fused_fits(Geo g, int real_bytes)
+{
+    return (int64_t)g.sp * real_bytes * 5 < (int64_t(1) << 31);
+}
+
+template <typename R>
+hipError_t launch_step_fused(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha, Src src, int rows, int xchunk,
+                             int depth, int order, hipStream_t s, hipEvent_t* ev)
+{
+    FArgs<R> A;
+    A.ex = o.c[0]; A.ey = o.c[1]; A.ez = o.c[2]; A.hx = o.c[3]; A.hy = o.c[4]; A.hz = o.c[5];
+    A.ex1 = nf.c[0]; A.ey1 = nf.c[1]; A.ez1 = nf.c[2]; A.hx1 = nf.c[3]; A.hy1 = nf.c[4]; A.hz1 = nf.c[5];
+    A.code = M.code;
+    A.g = g;
+    A.a = alpha;
+    A.kx = M.k[0]; A.ky = M.k[1]; A.kz = M.k[2];
+    A.mx = M.m[0]; A.my = M.m[1]; A.mz = M.m[2];
+    A.src = src;
+    A.nyt = A.nzt = A.nxc = A.xchunk = A.nblk = 0;
+    A.order = order;
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+    if (rows == 0) rows = sizeof(R) == 8 ? 12 : 16;   // FP64 at 16 rows exceeds the register file
+    if (rows == 12) {
+        if (depth == 1) e = launch_fused_t<R, 12, 1>(A, xchunk, s);
+        else if (depth == 3) e = launch_fused_t<R, 12, 3>(A, xchunk, s);
+        else e = launch_fused_t<R, 12, 2>(A, xchunk, s);
+    } else {
+        if (depth == 1) e = launch_fused_t<R, 16, 1>(A, xchunk, s);
+        else if (depth == 3) e = launch_fused_t<R, 16, 3>(A, xchunk, s);
+        else e = launch_fused_t<R, 16, 2>(A, xchunk, s);
+    }
+    if (e != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+template hipError_t launch_step_fused<float>(Fields<float>, Fields<float>, Mat<float>, Geo, float, Src, int, int,
+                                             int, int, hipStream_t, hipEvent_t*);
+template hipError_t launch_step_fused<double>(Fields<double>, Fields<double>, Mat<double>, Geo, double, Src, int,
+                                              int, int, int, hipStream_t, hipEvent_t*);
+
+}  // namespace tete

@@ -68,6 +68,17 @@ template <typename R>
 hipError_t launch_step(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src,
                        hipStream_t s, hipEvent_t* ev);
 
+// Fused single-kernel step for vacuum + PEC codes (tete_fused.hip); rows = 12
+// or 16 rows per workgroup, xchunk = planes per workgroup (0: automatic),
+// depth = planes of old data prefetched ahead (1..3), order = tile order
+// of the workgroups (0..2).
+// Whether a grid's planes are small enough for the fused kernel's buffer
+// addressing (five planes below 2^31 bytes).
+bool fused_fits(Geo g, int real_bytes);
+template <typename R>
+hipError_t launch_step_fused(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src, int rows,
+                             int xchunk, int depth, int order, hipStream_t s, hipEvent_t* ev);
+
 // energy of a state -> out[0] (FP64), using partial[RED_BLOCKS]
 template <typename R>
 hipError_t launch_energy(Fields<R> f, Mat<R> mat, Geo g, double alpha, double* partial, double* out,

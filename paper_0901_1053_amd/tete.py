@@ -39,6 +39,14 @@ class GridDesc(C.Structure):
                 ("precision", C.c_int32), ("flags", C.c_uint32), ("max_series", C.c_int32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("rows", C.c_int32), ("xchunk", C.c_int32), ("depth", C.c_int32),
+                ("order", C.c_int32)]
+
+
+KERNELS = {"auto": 0, "fused": 1, "split": 2}
+
+
 class Bunch(C.Structure):
     _fields_ = [("charge_C", C.c_double), ("sigma_z", C.c_double), ("i0", C.c_int32), ("j0", C.c_int32),
                 ("half_cells", C.c_int32), ("jmin", C.c_int32), ("nw", C.c_int32)]
@@ -79,6 +87,8 @@ def load(path: str = LIB_PATH):
         "tete_energy_series": (st, [vp, vp, C.c_int64, C.POINTER(C.c_int64)]),
         "tete_probes": (st, [vp, vp, C.c_int64, C.POINTER(C.c_int64)]),
         "tete_charges": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "tete_set_tuning": (st, [vp, C.POINTER(Tuning)]),
+        "tete_get_tuning": (st, [vp, C.POINTER(Tuning)]),
         "tete_set_timing": (st, [vp, C.c_int64]),
         "tete_timing": (st, [vp, vp, C.c_int32, C.POINTER(C.c_int64)]),
         "tete_status_str": (C.c_char_p, [C.c_int]),
@@ -251,6 +261,16 @@ class Grid:
         _chk("tete_probes", load().tete_probes(self.h, out.ctypes.data, out.size, C.byref(cnt)))
         n = min(cnt.value, max_steps)
         return out[: n * nprobe].reshape(n, nprobe).copy()
+
+    def set_tuning(self, kernel="auto", rows=0, xchunk=0, depth=0, order=0):
+        t = Tuning(KERNELS[kernel], rows, xchunk, depth, order)
+        _chk("tete_set_tuning", load().tete_set_tuning(self.h, C.byref(t)))
+
+    def get_tuning(self):
+        t = Tuning()
+        _chk("tete_get_tuning", load().tete_get_tuning(self.h, C.byref(t)))
+        inv = {v: k for k, v in KERNELS.items()}
+        return {"kernel": inv[t.kernel], "rows": t.rows, "xchunk": t.xchunk, "depth": t.depth, "order": t.order}
 
     def set_timing(self, max_steps: int):
         _chk("tete_set_timing", load().tete_set_timing(self.h, int(max_steps)))

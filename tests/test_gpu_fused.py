@@ -1,0 +1,83 @@
+"""The fused single-kernel step against the oracle and against the two-kernel
+step, over launch shapes (rows per workgroup, x-planes per workgroup) that put
+tile and chunk boundaries everywhere; results must not depend on the shape."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_0901_1053_amd import inputs, tete
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(13, 11, 37), (40, 29, 130), (7, 70, 200), (2, 2, 2), (3, 25, 61)]
+
+
+def _run(shape, seed, precision, kernel, rows=0, xchunk=0, steps=25, depth=0, order=0):
+    nx, ny, nz = shape
+    G = tete.Grid(nx, ny, nz, 2.0e-3, 1.7e-3, 1.0e-3, 0.9e-3, precision=precision)
+    G.set_pec_cells(inputs.random_cells(nx, ny, nz, seed, frac=0.1))
+    G.set_tuning(kernel, rows, xchunk, depth, order)
+    assert G.get_tuning()["kernel"] == kernel
+    G.set_fields(inputs.random_fields(G.shape, seed))
+    G.step(steps)
+    return G.get_fields()
+
+
+def _oracle(shape, seed, steps=25):
+    nx, ny, nz = shape
+    g = O.Geom(nx, ny, nz, 2.0e-3, 1.7e-3, 1.0e-3, 0.9e-3)
+    m = O.vacuum_materials(g, inputs.random_cells(nx, ny, nz, seed, frac=0.1))
+    f = inputs.random_fields(g.shape, seed)
+    O.apply_pec(g, m, f)
+    O.run(g, m, f, steps)
+    return f
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fused_matches_oracle_fp64(shape):
+    ref = _oracle(shape, 21)
+    got = _run(shape, 21, "fp64", "fused")
+    assert P.field_rel_err(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("rows,xchunk,depth,order", [
+    (16, 0, 2, 1), (12, 0, 2, 2), (16, 1, 1, 1), (12, 3, 3, 3), (16, 7, 2, 0), (12, 1000, 1, 2), (16, 2, 3, 3)])
+def test_fused_launch_shape_invariance(rows, xchunk, depth, order):
+    """Bitwise identical fields for every launch shape (every entry is computed
+    by the same expressions from the same inputs, wherever the halo falls)."""
+    shape = (40, 29, 130)
+    base = _run(shape, 22, "fp64", "fused", 16, 0)
+    got = _run(shape, 22, "fp64", "fused", rows, xchunk, depth=depth, order=order)
+    for k in tete.KEYS:
+        assert np.array_equal(got[k], base[k]), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_vs_split(precision):
+    shape = (40, 29, 130)
+    a = _run(shape, 23, precision, "fused")
+    b = _run(shape, 23, precision, "split")
+    tol = 1e-13 if precision == "fp64" else 1e-6
+    assert P.field_rel_err(a, b) <= tol
+
+
+@pytest.mark.parametrize("rows,xchunk", [(16, 0), (12, 5), (16, 2)])
+def test_fused_wake_and_charges(rows, xchunk):
+    """Bunch injection and wake accumulation inside the fused kernel, with the
+    bunch line on a tile boundary row for some shapes."""
+    case = inputs.scaled_wake_case(24, 150, seed=9, sigma_dz=3.0)
+    M = case.M
+    jmin, nw = -M - 3, 2 * M + 40
+    steps = case.nz + M + jmin + nw
+    ref = P.oracle_wake(case, steps, jmin=jmin, nw=nw)
+    G = P.gpu_grid(case, "fp64")
+    G.set_tuning("fused", rows, xchunk)
+    G.set_bunch(case.Q, case.sigma, case.i0, case.j0, M, jmin, nw)
+    G.step(steps)
+    W = G.wake()
+    assert P.delta_norm(W, ref["W"]) <= 1e-12
+    j = jmin + np.arange(nw)
+    assert np.all(W[j < -M] == 0.0)
+    e, h = G.charges()
+    assert e <= 1e-13 * case.Q and h <= 1e-13 * case.Q
