@@ -72,7 +72,8 @@ enum {
 enum {
     TETE_MAX_BUNCH_CELLS = 8191, /* 2M+1 cells of the truncated bunch */
     TETE_MAX_WAKE = 65536,       /* wake samples */
-    TETE_MAX_PROBES = 16         /* e_z probe points */
+    TETE_MAX_PROBES = 16,        /* e_z probe points */
+    TETE_MAX_BATCH = 256         /* instances of one batch */
 };
 
 typedef struct {
@@ -232,6 +233,54 @@ tete_status tete_set_timing(tete_grid* g, int64_t max_steps);
  * step: ms[0] = the fused kernel, ms[1] = 0 (nphase >= 2); *steps = number
  * of timed steps.  Resets the count.  Synchronises. */
 tete_status tete_timing(tete_grid* g, double* ms, int32_t nphase, int64_t* steps);
+
+/* ------------------------------------------------------------------------
+ * Batches: many grids (of one precision, uneven sizes, own geometries and
+ * bunches) stepped together, one persistent launch per time step covering
+ * every member's tiles; blocks of steps are replayed from a captured HIP
+ * graph.  A batch owns a small device table (tete_batch_bytes) in caller
+ * memory; membership can change between calls (continuous batching) without
+ * re-capturing the graph.  Members use the fused kernel (no per-entry
+ * materials) with their own x-chunk and tile order (tete_set_tuning); energy
+ * series and probes are not recorded for batched steps.  A member's results
+ * are the same as stepping it alone (each entry is computed by the same
+ * expressions).  The steps run on a private stream of the batch, ordered
+ * after the work already enqueued on the batch's stream and before anything
+ * enqueued there later (HIP events), so the batch's stream may be the null
+ * stream.  All work is ordered on the batch's stream; the caller must
+ * order work on the members' streams before and after (using one stream for
+ * everything does that).  A member must not be stepped alone while a batch
+ * step is in flight.
+ * ---------------------------------------------------------------------- */
+typedef struct tete_batch tete_batch;
+
+/* Device table bytes of a batch of the given precision (0 if invalid). */
+size_t tete_batch_bytes(int32_t precision);
+
+/* Create a batch over a caller-owned device table (256-byte aligned, at least
+ * tete_batch_bytes(precision)), using hip_stream.  Empty, launch shape: rows
+ * chosen by precision, prefetch depth 1, graph blocks of 8 steps. */
+tete_status tete_batch_create(int32_t precision, void* dev_table, size_t bytes, void* hip_stream,
+                              tete_batch** out);
+tete_status tete_batch_destroy(tete_batch* b);
+
+/* Put grid g into slot (0 <= slot < TETE_MAX_BATCH), or empty the slot with
+ * g = NULL.  TETE_ERR_ARG: wrong precision or device, or g already in
+ * another slot; TETE_ERR_STATE: g has per-entry materials or planes too large
+ * for the fused kernel.  Changing a member (its fields, bunch or tuning)
+ * requires setting its slot again before the next batch step. */
+tete_status tete_batch_set(tete_batch* b, int32_t slot, tete_grid* g);
+
+/* Launch shape shared by the members: rows (0, 12 or 16), prefetch depth
+ * (0..3, 0 = 1) and steps per captured graph block (0 = no graph). */
+tete_status tete_batch_set_launch(tete_batch* b, int32_t rows, int32_t depth, int32_t graph_steps);
+
+/* Enqueue nsteps steps of every member (asynchronous).  Each member's step
+ * counter advances by nsteps, as if tete_step had been called on it. */
+tete_status tete_batch_step(tete_batch* b, int64_t nsteps);
+
+/* Number of occupied slots. */
+tete_status tete_batch_count(tete_batch* b, int32_t* active);
 
 /* Human-readable status name. */
 const char* tete_status_str(tete_status s);

@@ -576,3 +576,248 @@ tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: many grids stepped together by one persistent launch per step.
+// ---------------------------------------------------------------------------
+
+struct tete_batch {
+    int fp32;
+    hipStream_t stream;       // caller's stream
+    hipStream_t gstream;      // private stream the steps run on (graphs cannot be captured on the null stream)
+    hipEvent_t ev_in, ev_out; // order gstream after / before the caller's stream
+    int device;
+    void* table;              // device BatchTable<R>
+    void* host;               // host staging copy
+    size_t bytes;
+    tete_grid* slot[TETE_MAX_BATCH];
+    int64_t seen_n[TETE_MAX_BATCH];   // (n, cur) of each member when the table was built
+    int seen_cur[TETE_MAX_BATCH];
+    int rows, depth, graph_steps;
+    int dirty;
+    int phase;
+    int grid;                 // persistent workgroups
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int graph_ok;
+};
+
+namespace {
+
+template <typename R>
+size_t batch_table_bytes() { return up(sizeof(BatchTable<R>)); }
+
+template <typename R>
+tete_status batch_build(tete_batch* b)
+{
+    BatchTable<R>* H = (BatchTable<R>*)b->host;
+    memset(H, 0, sizeof(BatchTable<R>));
+    H->phase = b->phase;
+    int total = 0;
+    for (int s = 0; s < TETE_MAX_BATCH; ++s) {
+        tete_grid* g = b->slot[s];
+        if (!g) continue;
+        const int i = H->ninst++;
+        Mat<R> M = mats<R>(g);
+        Src src = source(g, g->n);
+        FArgs<R> fwd = fused_args<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha, src);
+        FArgs<R> bwd = fused_args<R>(fields<R>(g, 1 - g->cur), fields<R>(g, g->cur), M, g->geo, (R)g->alpha, src);
+        if (!fused_setup<R>(fwd, b->rows, g->tune.xchunk, g->tune.order) ||
+            !fused_setup<R>(bwd, b->rows, g->tune.xchunk, g->tune.order))
+            return TETE_ERR_ARG;
+        // at the current phase the grid reads its current set
+        H->item[i].a[b->phase] = fwd;
+        H->item[i].a[1 - b->phase] = bwd;
+        H->offset[i] = total;
+        H->step[i] = g->n;
+        total += fwd.nblk;
+        b->seen_n[s] = g->n;
+        b->seen_cur[s] = g->cur;
+    }
+    H->offset[H->ninst] = total;
+    H->total = total;
+    HIPCHK(hipMemcpyAsync(b->table, H, sizeof(BatchTable<R>), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->dirty = 0;
+    return TETE_OK;
+}
+
+template <typename R>
+tete_status batch_launch_block(tete_batch* b, int steps)
+{
+    for (int s = 0; s < steps; ++s)
+        HIPCHK(launch_batch_step<R>((BatchTable<R>*)b->table, b->rows, b->depth, b->grid, s, b->gstream));
+    HIPCHK(launch_batch_advance<R>((BatchTable<R>*)b->table, steps, b->gstream));
+    return TETE_OK;
+}
+
+void batch_drop_graph(tete_batch* b)
+{
+    if (b->graph_ok) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->graph_ok = 0;
+    }
+}
+
+template <typename R>
+tete_status batch_step(tete_batch* b, int64_t nsteps)
+{
+    for (int s = 0; s < TETE_MAX_BATCH; ++s)
+        if (b->slot[s] && (b->slot[s]->n != b->seen_n[s] || b->slot[s]->cur != b->seen_cur[s])) b->dirty = 1;
+    if (b->dirty) {
+        tete_status st = batch_build<R>(b);
+        if (st != TETE_OK) return st;
+    }
+    if (((BatchTable<R>*)b->host)->ninst == 0) return TETE_OK;
+    const int K = b->graph_steps;
+    const int64_t full = K > 0 ? nsteps / K : 0;
+    const int rem = (int)(nsteps - full * K);
+    HIPCHK(hipEventRecord(b->ev_in, b->stream));
+    HIPCHK(hipStreamWaitEvent(b->gstream, b->ev_in, 0));
+    if (full > 0 && !b->graph_ok) {
+        HIPCHK(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal));
+        tete_status st = batch_launch_block<R>(b, K);
+        hipGraph_t graph;
+        hipError_t e = hipStreamEndCapture(b->gstream, &graph);
+        if (st != TETE_OK || e != hipSuccess) return TETE_ERR_DEVICE;
+        if (hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return TETE_ERR_DEVICE;
+        }
+        b->graph = graph;
+        b->graph_ok = 1;
+    }
+    for (int64_t f = 0; f < full; ++f) HIPCHK(hipGraphLaunch(b->exec, b->gstream));
+    if (rem > 0) {
+        tete_status st = batch_launch_block<R>(b, rem);
+        if (st != TETE_OK) return st;
+    }
+    HIPCHK(hipEventRecord(b->ev_out, b->gstream));
+    HIPCHK(hipStreamWaitEvent(b->stream, b->ev_out, 0));
+    const int flip = (int)(nsteps & 1);
+    for (int s = 0; s < TETE_MAX_BATCH; ++s) {
+        tete_grid* g = b->slot[s];
+        if (!g) continue;
+        g->n += nsteps;
+        g->cur ^= flip;
+        b->seen_n[s] = g->n;
+        b->seen_cur[s] = g->cur;
+    }
+    b->phase ^= flip;
+    return TETE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tete_batch_bytes(int32_t precision)
+{
+    if (precision == TETE_FP32) return batch_table_bytes<float>();
+    if (precision == TETE_FP64) return batch_table_bytes<double>();
+    return 0;
+}
+
+tete_status tete_batch_create(int32_t precision, void* dev_table, size_t bytes, void* hip_stream, tete_batch** out)
+{
+    if (!out) return TETE_ERR_ARG;
+    *out = nullptr;
+    const size_t need = tete_batch_bytes(precision);
+    if (need == 0 || !dev_table || ((uintptr_t)dev_table % kAlign) != 0) return TETE_ERR_ARG;
+    if (bytes < need) return TETE_ERR_NOMEM;
+    tete_batch* b = (tete_batch*)calloc(1, sizeof(tete_batch));
+    if (!b) return TETE_ERR_NOMEM;
+    b->host = calloc(1, need);
+    if (!b->host) { free(b); return TETE_ERR_NOMEM; }
+    b->fp32 = precision == TETE_FP32;
+    b->stream = (hipStream_t)hip_stream;
+    b->table = dev_table;
+    b->bytes = bytes;
+    b->rows = 0;
+    b->depth = 1;   // the persistent kernel at depth 2 or 3 exceeds the register file
+    b->graph_steps = 8;
+    b->dirty = 1;
+    int cus = 0;
+    if (hipGetDevice(&b->device) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess) {
+        free(b->host);
+        free(b);
+        return TETE_ERR_DEVICE;
+    }
+    b->grid = cus > 0 ? cus : 256;
+    if (hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking) != hipSuccess) {
+        free(b->host);
+        free(b);
+        return TETE_ERR_DEVICE;
+    }
+    if (hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(b->gstream);
+        free(b->host);
+        free(b);
+        return TETE_ERR_DEVICE;
+    }
+    *out = b;
+    return TETE_OK;
+}
+
+tete_status tete_batch_destroy(tete_batch* b)
+{
+    if (!b) return TETE_ERR_ARG;
+    (void)hipStreamSynchronize(b->gstream);
+    batch_drop_graph(b);
+    (void)hipEventDestroy(b->ev_in);
+    (void)hipEventDestroy(b->ev_out);
+    (void)hipStreamDestroy(b->gstream);
+    free(b->host);
+    free(b);
+    return TETE_OK;
+}
+
+tete_status tete_batch_set(tete_batch* b, int32_t slot, tete_grid* g)
+{
+    if (!b || slot < 0 || slot >= TETE_MAX_BATCH) return TETE_ERR_ARG;
+    if (g) {
+        if (g->fp32 != b->fp32 || g->device != b->device) return TETE_ERR_ARG;
+        if (g->mat_set || !fused_fits(g->geo, g->fp32 ? 4 : 8)) return TETE_ERR_STATE;
+        for (int s = 0; s < TETE_MAX_BATCH; ++s)
+            if (s != slot && b->slot[s] == g) return TETE_ERR_ARG;
+    }
+    b->slot[slot] = g;
+    b->dirty = 1;
+    return TETE_OK;
+}
+
+tete_status tete_batch_set_launch(tete_batch* b, int32_t rows, int32_t depth, int32_t graph_steps)
+{
+    if (!b || (rows != 0 && rows != 12 && rows != 16) || depth < 0 || depth > 3 || graph_steps < 0 ||
+        graph_steps > 1024)
+        return TETE_ERR_ARG;
+    b->rows = rows;
+    b->depth = depth == 0 ? 1 : depth;
+    b->graph_steps = graph_steps;
+    batch_drop_graph(b);
+    b->dirty = 1;
+    return TETE_OK;
+}
+
+tete_status tete_batch_step(tete_batch* b, int64_t nsteps)
+{
+    if (!b || nsteps < 0) return TETE_ERR_ARG;
+    if (nsteps == 0) return TETE_OK;
+    DeviceGuard dg(b->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    return b->fp32 ? batch_step<float>(b, nsteps) : batch_step<double>(b, nsteps);
+}
+
+tete_status tete_batch_count(tete_batch* b, int32_t* active)
+{
+    if (!b || !active) return TETE_ERR_ARG;
+    int c = 0;
+    for (int s = 0; s < TETE_MAX_BATCH; ++s) c += b->slot[s] != nullptr;
+    *active = c;
+    return TETE_OK;
+}
+
+}  // extern "C"

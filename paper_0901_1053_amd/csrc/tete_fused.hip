@@ -32,19 +32,6 @@ namespace {
 constexpr int KT = 62;   // k entries owned per workgroup (64 lanes minus two halo lanes)
 
 template <typename R>
-struct FArgs {
-    const R* ex; const R* ey; const R* ez; const R* hx; const R* hy; const R* hz;
-    R* ex1; R* ey1; R* ez1; R* hx1; R* hy1; R* hz1;
-    const uint8_t* code;
-    Geo g;
-    R a, kx, ky, kz, mx, my, mz;
-    Src src;
-    int nyt, nzt, nxc, xchunk;   // tiles along j, k; chunks along x; planes per chunk
-    int order;                   // tile order, see tile_of()
-    int nblk;                    // workgroups launched
-};
-
-template <typename R>
 __device__ __forceinline__ R bload(__amdgpu_buffer_rsrc_t r, uint32_t off);
 template <>
 __device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off)
@@ -132,20 +119,31 @@ __device__ __forceinline__ bool tile_of(int lb, int order, int nyt, int nzt, int
     return true;
 }
 
+// LDS of one workgroup: six double-buffered j-exchange planes of TYH + 2 rows.
+template <typename R, int TYH>
+struct Lds {
+    R sEZ[2][TYH + 2][64];
+    R sHXN[2][TYH + 2][64];
+    R sEZH[2][TYH + 2][64];
+    R sHZ[2][TYH + 2][64];
+    R sEXH[2][TYH + 2][64];
+    R sHZN[2][TYH + 2][64];
+};
+
+// One tile (ty, tz) and x-chunk cx of one step of the grid described by A.
+// Every thread of the workgroup must call it (it contains barriers).
 template <typename R, int TYH, int PD>
-__global__ __launch_bounds__(64 * TYH) void k_fused(FArgs<R> A)
+__device__ __forceinline__ void fused_tile(const FArgs<R>& A, const int ty, const int tz, const int cx,
+                                           Lds<R, TYH>& L)
 {
     constexpr int TY = TYH - 4;
-    __shared__ R sEZ[2][TYH + 2][64];
-    __shared__ R sHXN[2][TYH + 2][64];
-    __shared__ R sEZH[2][TYH + 2][64];
-    __shared__ R sHZ[2][TYH + 2][64];
-    __shared__ R sEXH[2][TYH + 2][64];
-    __shared__ R sHZN[2][TYH + 2][64];
-
+    auto& sEZ = L.sEZ;
+    auto& sHXN = L.sHXN;
+    auto& sEZH = L.sEZH;
+    auto& sHZ = L.sHZ;
+    auto& sEXH = L.sEXH;
+    auto& sHZN = L.sHZN;
     const Geo g = A.g;
-    int ty, tz, cx;
-    if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) return;   // whole group
 
     const int kl = threadIdx.x & 63;
     const int jl = threadIdx.x >> 6;
@@ -349,11 +347,78 @@ __global__ __launch_bounds__(64 * TYH) void k_fused(FArgs<R> A)
     }
 }
 
+// One step of one grid: one workgroup per (tile, x-chunk).
 template <typename R, int TYH, int PD>
-hipError_t launch_fused_t(const FArgs<R>& A0, int xchunk, hipStream_t s)
+__global__ __launch_bounds__(64 * TYH) void k_fused(FArgs<R> A)
 {
-    FArgs<R> A = A0;
-    constexpr int TY = TYH - 4;
+    __shared__ Lds<R, TYH> L;
+    int ty, tz, cx;
+    if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) return;   // whole group
+    fused_tile<R, TYH, PD>(A, ty, tz, cx, L);
+}
+
+// One step of every active instance of a batch, by a persistent grid: work
+// item w (instance, tile, x-chunk) is taken by workgroup w mod gridDim.x in
+// round w / gridDim.x.  Within a round the items are remapped over the XCDs
+// like the tiles of one grid, so that neighbouring tiles share an L2.  The
+// instance's step index and the ping-pong parity come from the table, which
+// the host may rewrite between launches (a captured graph stays valid).
+template <typename R, int TYH, int PD>
+__global__ __launch_bounds__(64 * TYH) void k_fused_batch(const BatchTable<R>* T, int sub)
+{
+    __shared__ Lds<R, TYH> L;
+    const int total = T->total;
+    const int ninst = T->ninst;
+    const int parity = (T->phase + sub) & 1;
+    for (int round = 0; round * (int)gridDim.x < total; ++round) {
+        const int base = round * (int)gridDim.x;
+        const int span = min((int)gridDim.x, total - base);
+        if ((int)blockIdx.x >= span) break;
+        // work item and instance are uniform over the workgroup: keep them (and
+        // the instance's arguments) in scalar registers
+        const int w = __builtin_amdgcn_readfirstlane(base + xcd_remap(blockIdx.x, span));
+        int lo = 0, hi = ninst - 1;               // last instance whose first item is <= w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (T->offset[mid] <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const int inst = __builtin_amdgcn_readfirstlane(lo);
+        FArgs<R> A = T->item[inst].a[parity];
+        A.src.n = T->step[inst] + sub;
+        int ty, tz, cx;
+        if (tile_of(w - T->offset[inst], A.order, A.nyt, A.nzt, ty, tz, cx)) fused_tile<R, TYH, PD>(A, ty, tz, cx, L);
+        __syncthreads();   // the LDS is reused by the next item
+    }
+}
+
+// After a block of steps: advance every instance's step index and the phase.
+template <typename R>
+__global__ void k_batch_advance(BatchTable<R>* T, int steps)
+{
+    const int i = threadIdx.x + blockIdx.x * blockDim.x;
+    if (i < T->ninst) T->step[i] += steps;
+    if (i == 0) T->phase = (T->phase + steps) & 1;
+}
+
+template <typename R, int TYH, int PD>
+hipError_t launch_fused_t(const FArgs<R>& A, hipStream_t s)
+{
+    k_fused<R, TYH, PD><<<A.nblk, 64 * TYH, 0, s>>>(A);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int fused_default_rows(int real_bytes) { return real_bytes == 8 ? 12 : 16; }   // FP64 at 16 rows spills
+
+template <typename R>
+bool fused_setup(FArgs<R>& A, int rows, int xchunk, int order)
+{
+    if (rows == 0) rows = fused_default_rows(sizeof(R));
+    if (rows != 12 && rows != 16) return false;
+    const int TY = rows - 4;
+    A.order = order;
     A.nyt = (A.g.ny + 1 + TY - 1) / TY;
     A.nzt = (A.g.nz + 1 + KT - 1) / KT;
     const int nplanes = A.g.nx + 1;
@@ -368,7 +433,7 @@ hipError_t launch_fused_t(const FArgs<R>& A0, int xchunk, hipStream_t s)
     // every buffer range must stay below 2^31 bytes: (xchunk + 4) planes
     const int64_t plane_bytes = (int64_t)A.g.sp * sizeof(R);
     const int64_t xmax = ((int64_t(1) << 31) - 1) / plane_bytes - 4;
-    if (xmax < 1) return hipErrorInvalidValue;
+    if (xmax < 1) return false;
     xc = (int)std::min<int64_t>(std::max(xc, 1), xmax);
     A.xchunk = xc;
     A.nxc = (nplanes + xc - 1) / xc;
@@ -376,20 +441,11 @@ hipError_t launch_fused_t(const FArgs<R>& A0, int xchunk, hipStream_t s)
         A.nblk = ((A.nzt + BZ - 1) / BZ) * ((A.nyt + BY - 1) / BY) * BZ * BY * A.nxc;
     else
         A.nblk = A.nyt * A.nzt * A.nxc;
-    k_fused<R, TYH, PD><<<A.nblk, 64 * TYH, 0, s>>>(A);
-    return hipGetLastError();
-}
-
-}  // namespace
-
-bool fused_fits(Geo g, int real_bytes)
-{
-    return (int64_t)g.sp * real_bytes * 5 < (int64_t(1) << 31);
+    return true;
 }
 
 template <typename R>
-hipError_t launch_step_fused(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha, Src src, int rows, int xchunk,
-                             int depth, int order, hipStream_t s, hipEvent_t* ev)
+FArgs<R> fused_args(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha, Src src)
 {
     FArgs<R> A;
     A.ex = o.c[0]; A.ey = o.c[1]; A.ez = o.c[2]; A.hx = o.c[3]; A.hy = o.c[4]; A.hz = o.c[5];
@@ -400,25 +456,70 @@ hipError_t launch_step_fused(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha
     A.kx = M.k[0]; A.ky = M.k[1]; A.kz = M.k[2];
     A.mx = M.m[0]; A.my = M.m[1]; A.mz = M.m[2];
     A.src = src;
-    A.nyt = A.nzt = A.nxc = A.xchunk = A.nblk = 0;
-    A.order = order;
+    A.nyt = A.nzt = A.nxc = A.xchunk = A.nblk = A.order = 0;
+    return A;
+}
+
+template <typename R>
+hipError_t launch_batch_step(BatchTable<R>* T, int rows, int depth, int grid, int sub, hipStream_t s)
+{
+    if (rows == 0) rows = fused_default_rows(sizeof(R));
+    const int threads = 64 * rows;
+    if (rows == 12) {
+        if (depth == 1) k_fused_batch<R, 12, 1><<<grid, threads, 0, s>>>(T, sub);
+        else if (depth == 3) k_fused_batch<R, 12, 3><<<grid, threads, 0, s>>>(T, sub);
+        else k_fused_batch<R, 12, 2><<<grid, threads, 0, s>>>(T, sub);
+    } else {
+        if (depth == 1) k_fused_batch<R, 16, 1><<<grid, threads, 0, s>>>(T, sub);
+        else if (depth == 3) k_fused_batch<R, 16, 3><<<grid, threads, 0, s>>>(T, sub);
+        else k_fused_batch<R, 16, 2><<<grid, threads, 0, s>>>(T, sub);
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_batch_advance(BatchTable<R>* T, int steps, hipStream_t s)
+{
+    k_batch_advance<R><<<(TETE_MAX_BATCH + 255) / 256, 256, 0, s>>>(T, steps);
+    return hipGetLastError();
+}
+
+bool fused_fits(Geo g, int real_bytes)
+{
+    return (int64_t)g.sp * real_bytes * 5 < (int64_t(1) << 31);
+}
+
+template <typename R>
+hipError_t launch_step_fused(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha, Src src, int rows, int xchunk,
+                             int depth, int order, hipStream_t s, hipEvent_t* ev)
+{
+    FArgs<R> A = fused_args<R>(o, nf, M, g, alpha, src);
+    if (rows == 0) rows = fused_default_rows(sizeof(R));
+    if (!fused_setup<R>(A, rows, xchunk, order)) return hipErrorInvalidValue;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
-    if (rows == 0) rows = sizeof(R) == 8 ? 12 : 16;   // FP64 at 16 rows exceeds the register file
     if (rows == 12) {
-        if (depth == 1) e = launch_fused_t<R, 12, 1>(A, xchunk, s);
-        else if (depth == 3) e = launch_fused_t<R, 12, 3>(A, xchunk, s);
-        else e = launch_fused_t<R, 12, 2>(A, xchunk, s);
+        if (depth == 1) e = launch_fused_t<R, 12, 1>(A, s);
+        else if (depth == 3) e = launch_fused_t<R, 12, 3>(A, s);
+        else e = launch_fused_t<R, 12, 2>(A, s);
     } else {
-        if (depth == 1) e = launch_fused_t<R, 16, 1>(A, xchunk, s);
-        else if (depth == 3) e = launch_fused_t<R, 16, 3>(A, xchunk, s);
-        else e = launch_fused_t<R, 16, 2>(A, xchunk, s);
+        if (depth == 1) e = launch_fused_t<R, 16, 1>(A, s);
+        else if (depth == 3) e = launch_fused_t<R, 16, 3>(A, s);
+        else e = launch_fused_t<R, 16, 2>(A, s);
     }
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     return hipSuccess;
 }
+
+#define TETE_FUSED_INST(R)                                                                                     \
+    template bool fused_setup<R>(FArgs<R>&, int, int, int);                                                    \
+    template FArgs<R> fused_args<R>(Fields<R>, Fields<R>, Mat<R>, Geo, R, Src);                                 \
+    template hipError_t launch_batch_step<R>(BatchTable<R>*, int, int, int, int, hipStream_t);                 \
+    template hipError_t launch_batch_advance<R>(BatchTable<R>*, int, hipStream_t);
+TETE_FUSED_INST(float)
+TETE_FUSED_INST(double)
 
 template hipError_t launch_step_fused<float>(Fields<float>, Fields<float>, Mat<float>, Geo, float, Src, int, int,
                                              int, int, hipStream_t, hipEvent_t*);

@@ -44,6 +44,39 @@ struct Src {
 
 enum { RED_BLOCKS = 2048, RED_THREADS = 256 };
 
+// Arguments of one grid's fused step: old and new fields, PEC codes, vacuum
+// coefficients, source, and the tiling (tete_fused.hip).
+template <typename R>
+struct FArgs {
+    const R* ex; const R* ey; const R* ez; const R* hx; const R* hy; const R* hz;
+    R* ex1; R* ey1; R* ez1; R* hx1; R* hy1; R* hz1;
+    const uint8_t* code;
+    Geo g;
+    R a, kx, ky, kz, mx, my, mz;
+    Src src;
+    int nyt, nzt, nxc, xchunk;   // tiles along j, k; chunks along x; planes per chunk
+    int order;                   // tile order
+    int nblk;                    // work items (workgroups) of one step
+};
+
+// Device-resident table of a batch (tete_batch_*): the active instances, their
+// work-item offsets, step indices, and fused-step arguments for both ping-pong
+// parities (a[q] is used when (phase + sub-step) % 2 == q).
+template <typename R>
+struct BatchItem {
+    FArgs<R> a[2];
+};
+template <typename R>
+struct BatchTable {
+    int ninst;                         // active instances (compacted)
+    int total;                         // work items of one step, all instances
+    int phase;                         // parity of the steps taken so far
+    int pad;
+    int offset[TETE_MAX_BATCH + 1];    // first work item of each instance
+    int64_t step[TETE_MAX_BATCH];      // step index n of each instance
+    BatchItem<R> item[TETE_MAX_BATCH];
+};
+
 // ---- launchers (tete_kernels.hip) ---------------------------------------
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
@@ -78,6 +111,19 @@ bool fused_fits(Geo g, int real_bytes);
 template <typename R>
 hipError_t launch_step_fused(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src, int rows,
                              int xchunk, int depth, int order, hipStream_t s, hipEvent_t* ev);
+
+template <typename R>
+FArgs<R> fused_args(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src);
+// Fills the tiling of A for a launch shape; false if the shape is invalid or
+// the grid's planes are too large for the fused kernel.
+template <typename R>
+bool fused_setup(FArgs<R>& A, int rows, int xchunk, int order);
+int fused_default_rows(int real_bytes);
+// One step of every instance of a batch (persistent grid of `grid` workgroups)
+template <typename R>
+hipError_t launch_batch_step(BatchTable<R>* T, int rows, int depth, int grid, int sub, hipStream_t s);
+template <typename R>
+hipError_t launch_batch_advance(BatchTable<R>* T, int steps, hipStream_t s);
 
 // energy of a state -> out[0] (FP64), using partial[RED_BLOCKS]
 template <typename R>

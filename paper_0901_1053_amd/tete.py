@@ -91,6 +91,13 @@ def load(path: str = LIB_PATH):
         "tete_get_tuning": (st, [vp, C.POINTER(Tuning)]),
         "tete_set_timing": (st, [vp, C.c_int64]),
         "tete_timing": (st, [vp, vp, C.c_int32, C.POINTER(C.c_int64)]),
+        "tete_batch_bytes": (C.c_size_t, [C.c_int32]),
+        "tete_batch_create": (st, [C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "tete_batch_destroy": (st, [vp]),
+        "tete_batch_set": (st, [vp, C.c_int32, vp]),
+        "tete_batch_set_launch": (st, [vp, C.c_int32, C.c_int32, C.c_int32]),
+        "tete_batch_step": (st, [vp, C.c_int64]),
+        "tete_batch_count": (st, [vp, C.POINTER(C.c_int32)]),
         "tete_status_str": (C.c_char_p, [C.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -287,3 +294,52 @@ class Grid:
         h = C.c_double()
         _chk("tete_charges", load().tete_charges(self.h, C.byref(e), C.byref(h)))
         return e.value, h.value
+
+
+class Batch:
+    """Grids of one precision stepped together by the persistent batched kernel."""
+
+    def __init__(self, precision="fp32", device="cuda:0", stream=None):
+        import torch
+        L = load()
+        self.torch = torch
+        prec = {"fp64": FP64, "fp32": FP32}[precision]
+        self.nbytes = int(L.tete_batch_bytes(prec))
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.table = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _chk("tete_batch_create", L.tete_batch_create(prec, C.c_void_p(self.table.data_ptr()), self.nbytes,
+                                                          C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.members = {}
+
+    def set(self, slot: int, grid):
+        _chk("tete_batch_set", load().tete_batch_set(self.h, slot, grid.h if grid is not None else None))
+        if grid is None:
+            self.members.pop(slot, None)
+        else:
+            self.members[slot] = grid
+
+    def set_launch(self, rows=0, depth=0, graph_steps=8):
+        _chk("tete_batch_set_launch", load().tete_batch_set_launch(self.h, rows, depth, graph_steps))
+
+    def step(self, n: int):
+        _chk("tete_batch_step", load().tete_batch_step(self.h, int(n)))
+
+    def count(self) -> int:
+        v = C.c_int32()
+        _chk("tete_batch_count", load().tete_batch_count(self.h, C.byref(v)))
+        return v.value
+
+    def close(self):
+        if self.h:
+            load().tete_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

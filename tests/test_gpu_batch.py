@@ -1,0 +1,105 @@
+"""Batched execution: uneven grids stepped together by the persistent kernel,
+with graph-replayed step blocks, must give each member exactly what stepping it
+alone gives (and the oracle's result); members can join and leave between
+batch steps (continuous batching)."""
+import numpy as np
+import pytest
+
+from paper_0901_1053_amd import inputs, tete
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(16, 40), (24, 96), (20, 64), (32, 150), (12, 33)]
+
+
+def _cases():
+    return [inputs.scaled_wake_case(nt, nz, seed=31 + i, sigma_dz=2.0 + 0.5 * i) for i, (nt, nz) in enumerate(SIZES)]
+
+
+def _grid(case, precision):
+    G = P.gpu_grid(case, precision)
+    G.set_bunch(case.Q, case.sigma, case.i0, case.j0, case.M, case.jmin, case.nw)
+    return G
+
+
+def _alone(case, precision, steps):
+    G = _grid(case, precision)
+    G.step(steps)
+    return G.wake(), G.get_fields(dtype=precision)
+
+
+@pytest.mark.parametrize("precision,graph_steps,steps", [("fp32", 4, 23), ("fp64", 8, 17), ("fp32", 0, 9)])
+def test_batch_equals_alone(precision, graph_steps, steps):
+    cases = _cases()
+    ref = [_alone(c, precision, steps) for c in cases]
+    B = tete.Batch(precision)
+    B.set_launch(graph_steps=graph_steps)
+    grids = [_grid(c, precision) for c in cases]
+    for s, G in enumerate(grids):
+        B.set(3 * s + 1, G)             # sparse slots
+    assert B.count() == len(cases)
+    B.step(steps)
+    for G, (w_ref, f_ref), c in zip(grids, ref, cases):
+        assert G.steps_done() == steps
+        assert np.array_equal(G.wake(), w_ref), c.name
+        f = G.get_fields(dtype=precision)
+        for k in tete.KEYS:
+            assert np.array_equal(f[k], f_ref[k]), (c.name, k)
+
+
+def test_batch_continuous_membership():
+    """Members join and leave between batch steps; each one's wake equals its
+    solo run over the same number of its own steps."""
+    cases = _cases()
+    n1, n2, n3 = 7, 12, 10
+    grids = [_grid(c, "fp32") for c in cases]
+    B = tete.Batch("fp32")
+    B.set_launch(graph_steps=4)
+    B.set(0, grids[0])
+    B.set(1, grids[1])
+    B.step(n1)
+    B.set(2, grids[2])                  # joins after n1 steps of the others
+    B.step(n2)
+    B.set(0, None)                      # leaves
+    B.set(5, grids[3])
+    B.step(n3)
+    expect = {0: n1 + n2, 1: n1 + n2 + n3, 2: n2 + n3, 3: n3}
+    for i, n in expect.items():
+        assert grids[i].steps_done() == n
+        w_ref, _ = _alone(cases[i], "fp32", n)
+        assert np.array_equal(grids[i].wake(), w_ref), i
+
+
+def test_batch_member_matches_oracle_fp64():
+    case = inputs.scaled_wake_case(20, 80, seed=41, sigma_dz=2.5)
+    steps = case.steps
+    ref = P.oracle_wake(case, steps)
+    B = tete.Batch("fp64")
+    other = _grid(_cases()[1], "fp64")
+    G = _grid(case, "fp64")
+    B.set(0, other)
+    B.set(1, G)
+    B.step(steps)
+    assert P.delta_norm(G.wake(), ref["W"]) <= 1e-12
+
+
+def test_batch_errors():
+    B = tete.Batch("fp32")
+    G64 = _grid(_cases()[0], "fp64")
+    with pytest.raises(tete.TeteError) as e:
+        B.set(0, G64)
+    assert e.value.status == "TETE_ERR_ARG"
+    G = _grid(_cases()[0], "fp32")
+    B.set(0, G)
+    with pytest.raises(tete.TeteError) as e:
+        B.set(1, G)
+    assert e.value.status == "TETE_ERR_ARG"
+    M = tete.Grid(8, 8, 8, 2e-3, 2e-3, 1e-3, 1e-3, precision="fp32", materials=True)
+    M.set_materials({k: np.full(M.shape, 0.5) for k in tete.KEYS})
+    with pytest.raises(tete.TeteError) as e:
+        B.set(2, M)
+    assert e.value.status == "TETE_ERR_STATE"
+    with pytest.raises(tete.TeteError):
+        B.set(tete.MAX_BATCH if hasattr(tete, "MAX_BATCH") else 256, G)
+    B.step(0)
