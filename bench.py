@@ -66,6 +66,80 @@ def cpu_baseline(case, nz_slab=32, steps=4):
                                                        steps, dt)}
 
 
+def _tuned(cases, precision):
+    """Autotune the fused launch shape for each size class present (cache in /tmp)."""
+    from paper_0901_1053_amd.autotune import Tuner, size_class
+    tuner = Tuner(cache_path=os.path.join("/tmp", "tete_bench_autotune.json"), xchunks=(0, 32, 128), orders=(2,),
+                  steps=4, warmup=1)
+    shapes = {}
+    for c in cases:
+        key = size_class(c.nx, c.ny, c.nz, precision)
+        if key not in shapes:
+            sh = tuner.tune(c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, c.cdt, precision)
+            shapes[key] = {"xchunk": sh.xchunk, "order": sh.order, "ms_per_step": round(sh.ms, 4)}
+    return tuner, shapes
+
+
+def batched_section(count):
+    """All instances of the batched workload submitted at once and served by
+    continuous batching (FP32 fields, FP64 wake), against FP64 one-at-a-time
+    solves of the first eight instances."""
+    import numpy as np
+
+    from paper_0901_1053_amd import inputs, serve
+    cases = inputs.batched_cases(count)
+    tuner, shapes = _tuned(cases, "fp32")
+    reqs = [serve.Request(i, c, 0.0) for i, c in enumerate(cases)]
+    ex = serve.GpuExecutor("fp32", batch=True, graph_steps=8, tuner=tuner)
+    st = serve.Server(ex, max_slots=min(count, 256), block_steps=256).run(reqs)
+    ex.close()
+    cells_steps = sum(c.cells * c.steps for c in cases)
+    sub = [serve.Request(i, c, 0.0) for i, c in enumerate(cases[:8])]
+    ex64 = serve.GpuExecutor("fp64", batch=False)
+    st64 = serve.Server(ex64, max_slots=1, block_steps=10 ** 7).run(sub)
+    ex64.close()
+    delta = max(float(np.max(np.abs(reqs[i].wake - sub[i].wake)) / (np.max(sub[i].wake) - np.min(sub[i].wake)))
+                for i in range(len(sub)))
+    return {"workload": "%d tapered-jaw collimators, 64^2x256 .. 192^2x1024" % count, "instances": count,
+            "fp32_batched_solves_per_s": round(st.solves_per_s, 3), "makespan_s": round(st.makespan_s, 3),
+            "gcell_updates_per_s": round(cells_steps / st.makespan_s / 1e9, 2),
+            "fp64_one_at_a_time_solves_per_s": round(st64.solves_per_s, 3),
+            "fp64_sample": "first 8 instances", "speedup": round(st.solves_per_s / st64.solves_per_s, 2),
+            "max_fp32_delta_vs_fp64": delta, "max_active": st.max_active, "peak_gb": round(st.peak_bytes / 1e9, 2),
+            "autotuned_shapes": shapes}
+
+
+def serve_section(rates, count):
+    """Poisson streams of serving-workload requests: FP32 continuous batching
+    (p50/p99 latency, arrival to wake on host) and FP64 one-at-a-time."""
+    import numpy as np
+
+    from paper_0901_1053_amd import inputs, serve
+    cases = inputs.serve_cases(count)
+    tuner, _ = _tuned(cases, "fp32")
+    res = {"workload": "%d requests, 64^2x256 .. 256^2x2048" % count, "rates": {}}
+    for rate in rates:
+        reqs = serve.make_requests(cases, rate, seed=int(rate * 1000) + 7)
+        ex = serve.GpuExecutor("fp32", batch=True, graph_steps=8, tuner=tuner)
+        st = serve.Server(ex, block_steps=128).run(reqs)
+        ex.close()
+        base = serve.make_requests(cases, rate, seed=int(rate * 1000) + 7)
+        ex64 = serve.GpuExecutor("fp64", batch=False)
+        st64 = serve.Server(ex64, max_slots=1, block_steps=10 ** 7).run(base)
+        ex64.close()
+        delta = max(float(np.max(np.abs(a.wake - b.wake)) / (np.max(b.wake) - np.min(b.wake)))
+                    for a, b in zip(reqs, base))
+        res["rates"][str(rate)] = {
+            "fp32_batched": {"solves_per_s": round(st.solves_per_s, 3), "p50_s": round(st.p50_s, 4),
+                             "p99_s": round(st.p99_s, 4), "max_active": st.max_active},
+            "fp64_one_at_a_time": {"solves_per_s": round(st64.solves_per_s, 3), "p50_s": round(st64.p50_s, 4),
+                                   "p99_s": round(st64.p99_s, 4)},
+            "max_fp32_delta_vs_fp64": delta}
+        print("# serve rate %g done" % rate, file=sys.stderr, flush=True)
+    res["tolerance"] = 1e-5
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +153,11 @@ def main():
     ap.add_argument("--xchunk", type=int, default=0, help="fused kernel: x-planes per workgroup (0: auto)")
     ap.add_argument("--depth", type=int, default=0, help="fused kernel: planes prefetched ahead (1..3)")
     ap.add_argument("--order", type=int, default=0, help="fused kernel: tile order (1..3; 0: library default)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--batched-count", type=int, default=64)
+    ap.add_argument("--serve-rates", default="20", help="comma-separated request rates (req/s)")
+    ap.add_argument("--serve-requests", type=int, default=12)
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of this many GiB, 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -193,6 +272,13 @@ def main():
         res["steps"] = sw.steps
         out["single_wake"] = res
         print("# single wake done", file=sys.stderr, flush=True)
+
+    if not args.no_batched:
+        out["batched"] = batched_section(args.batched_count)
+        print("# batched done", file=sys.stderr, flush=True)
+    if not args.no_serve:
+        out["serve"] = serve_section([float(r) for r in args.serve_rates.split(",")], args.serve_requests)
+        print("# serve done", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case)

@@ -297,3 +297,9 @@ def sample_points(shape, seed: int, count: int = 16):
     while len(pts) < count:
         pts.append((int(rng.integers(0, nx + 1)), int(rng.integers(0, ny + 1)), int(rng.integers(0, nz + 1))))
     return pts
+
+
+def serve_cases(count: int = 200, seed: int = 20260905, nts=(64, 128, 192, 256), nzs=(256, 512, 1024, 2048)):
+    """Requests of the serving workload: geometry and sigma as in the batched
+    workload, grids from 64^2 x 256 to 256^2 x 2048 (seeded)."""
+    return batched_cases(count, seed, nts=nts, nzs=nzs)
