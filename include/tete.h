@@ -206,7 +206,8 @@ tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h);
  * fused kernel (0: chosen from the grid size).  depth: x-planes of old data
  * the fused kernel prefetches ahead, 1..3 (0: 2).  order: order in which
  * the fused kernel's tiles are scheduled: 1 (j-tiles first), 2 (k-tiles
- * first), 3 (blocks of 8 k-tiles by 4 j-tiles); 0 = 2.  tete_set_materials turns a
+ * first), 3 or 4 (blocks of 8 k-tiles by 4 j-tiles, or 16 by 2); 0: 4 where
+ * the grid has at least 16 k-tiles and 2 j-tiles, else 2.  tete_set_materials turns a
  * forced FUSED back into AUTO.  tete_get_tuning reports the kernel that
  * tete_step will use (FUSED or SPLIT). */
 enum { TETE_KERNEL_AUTO = 0, TETE_KERNEL_FUSED = 1, TETE_KERNEL_SPLIT = 2 };

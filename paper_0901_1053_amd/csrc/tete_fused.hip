@@ -91,21 +91,26 @@ __device__ __forceinline__ int xcd_remap(int b, int n)
     return x < extra ? x * (base + 1) + r : extra * (base + 1) + (x - extra) * base + r;
 }
 
-// Tile (ty, tz) and x-chunk cx of logical workgroup lb.  order 0 or 2:
-// k-tiles fastest, so the tiles of one band of rows, which together cover
-// whole contiguous rows, run together (measured fastest); order 1: j-tiles
-// fastest; order 3: blocks of 8 k-tiles by 4 j-tiles (32 workgroups, one
-// XCD's worth) fastest.  Returns false for the padding workgroups of order 3.
-constexpr int BZ = 8, BY = 4;
+// Tile (ty, tz) and x-chunk cx of logical workgroup lb.  order 2: k-tiles
+// fastest, so the tiles of one band of rows, which together cover whole
+// contiguous rows, run together; order 1: j-tiles fastest; orders 3 and 4:
+// blocks of 8 k-tiles by 4 j-tiles or 16 k-tiles by 2 j-tiles (32 workgroups,
+// one XCD's worth) fastest, so that neighbouring row bands, which share halo
+// rows, also run together (order 4 measured fastest on long grids).  Order 0
+// is resolved on the host before launch.  Returns false for the padding
+// workgroups of the blocked orders.
+__host__ __device__ __forceinline__ int block_z(int order) { return order == 4 ? 16 : 8; }
+__host__ __device__ __forceinline__ int block_y(int order) { return order == 4 ? 2 : 4; }
 __device__ __forceinline__ bool tile_of(int lb, int order, int nyt, int nzt, int& ty, int& tz, int& cx)
 {
-    if (order == 0 || order == 2) {
+    if (order == 2) {
         tz = lb % nzt;
         ty = (lb / nzt) % nyt;
         cx = lb / (nzt * nyt);
         return true;
     }
-    if (order == 3) {
+    if (order == 3 || order == 4) {
+        const int BZ = block_z(order), BY = block_y(order);
         const int nbz = (nzt + BZ - 1) / BZ, nby = (nyt + BY - 1) / BY;
         const int w = lb % (BZ * BY), b = lb / (BZ * BY);
         tz = (b % nbz) * BZ + w % BZ;
@@ -418,9 +423,10 @@ bool fused_setup(FArgs<R>& A, int rows, int xchunk, int order)
     if (rows == 0) rows = fused_default_rows(sizeof(R));
     if (rows != 12 && rows != 16) return false;
     const int TY = rows - 4;
-    A.order = order;
     A.nyt = (A.g.ny + 1 + TY - 1) / TY;
     A.nzt = (A.g.nz + 1 + KT - 1) / KT;
+    // default: 16 x 2 blocks where a block row is filled, else k-tiles first
+    A.order = order != 0 ? order : (A.nzt >= block_z(4) && A.nyt >= block_y(4) ? 4 : 2);
     const int nplanes = A.g.nx + 1;
     int xc = xchunk;
     if (xc <= 0) {
@@ -437,8 +443,10 @@ bool fused_setup(FArgs<R>& A, int rows, int xchunk, int order)
     xc = (int)std::min<int64_t>(std::max(xc, 1), xmax);
     A.xchunk = xc;
     A.nxc = (nplanes + xc - 1) / xc;
-    if (A.order == 3)
+    if (A.order == 3 || A.order == 4) {
+        const int BZ = block_z(A.order), BY = block_y(A.order);
         A.nblk = ((A.nzt + BZ - 1) / BZ) * ((A.nyt + BY - 1) / BY) * BZ * BY * A.nxc;
+    }
     else
         A.nblk = A.nyt * A.nzt * A.nxc;
     return true;
