@@ -25,15 +25,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_traffic.json")
+def traffic_file(kernel_name):
+    return os.path.join(ROOT, "profiles", kernel_name + "_traffic.json")
 
 
 def measured_traffic(kernel_name, workload, precision):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current source of the fused kernel; else None."""
+    were taken on the current source of the kernel; else None."""
     import hashlib
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(kernel_name)) as fh:
             t = json.load(fh)
         with open(os.path.join(ROOT, t["source"]), "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()
@@ -148,7 +149,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single-wake", action="store_true")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "split"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "fused", "fused2", "split"])
     ap.add_argument("--rows", type=int, default=0, help="fused kernel: rows per workgroup (12 or 16)")
     ap.add_argument("--xchunk", type=int, default=0, help="fused kernel: x-planes per workgroup (0: auto)")
     ap.add_argument("--depth", type=int, default=0, help="fused kernel: planes prefetched ahead (1..3)")
@@ -215,6 +216,10 @@ def main():
         kern = {"fused": ms_tm / nt}
         dom = "fused"
         kbytes = step_bytes                    # one launch per step
+    elif tuning["kernel"] == "fused2":
+        kern = {"fused2": 2 * ms_tm / nt}      # nt counts steps; one launch takes two
+        dom = "fused2"
+        kbytes = 2 * step_bytes                # two cell-updates per entry per launch
     else:
         kern = {"tm": ms_tm / nt, "te": ms_te / nt}
         dom = max(kern, key=kern.get)
@@ -243,7 +248,7 @@ def main():
                      "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
                      "traffic": measured_traffic("k_" + dom, case.name, args.precision),
                      "bytes_per_launch": kbytes, "ms_per_launch": round(kern[dom], 4),
-                     "kernels_ms_per_step": {k: round(v, 4) for k, v in kern.items()}},
+                     "kernels_ms_per_launch": {k: round(v, 4) for k, v in kern.items()}},
     }
     del G
     torch.cuda.empty_cache()

@@ -198,19 +198,31 @@ tete_status tete_probes(tete_grid* g, double* out, int64_t max, int64_t* count);
 tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h);
 
 /* Kernel choice and launch shape (for tuning; results do not depend on it
- * beyond rounding order).  kernel: TETE_KERNEL_AUTO picks the fused
- * single-kernel step unless per-entry materials are set; TETE_KERNEL_FUSED
- * forces it (TETE_ERR_STATE with per-entry materials); TETE_KERNEL_SPLIT runs
- * the two-kernel step (one kernel per half step).  rows: rows per workgroup of
- * the fused kernel, 12 or 16 (0: 16 for FP32, 12 for FP64).  xchunk: x-planes per workgroup of the
- * fused kernel (0: chosen from the grid size).  depth: x-planes of old data
- * the fused kernel prefetches ahead, 1..3 (0: 2).  order: order in which
- * the fused kernel's tiles are scheduled: 1 (j-tiles first), 2 (k-tiles
- * first), 3 or 4 (blocks of 8 k-tiles by 4 j-tiles, or 16 by 2); 0: 4 where
- * the grid has at least 16 k-tiles and 2 j-tiles, else 2.  tete_set_materials turns a
- * forced FUSED back into AUTO.  tete_get_tuning reports the kernel that
- * tete_step will use (FUSED or SPLIT). */
-enum { TETE_KERNEL_AUTO = 0, TETE_KERNEL_FUSED = 1, TETE_KERNEL_SPLIT = 2 };
+ * beyond rounding order, and the fused kernels give identical results).
+ * kernel:
+ *   TETE_KERNEL_AUTO   the two-step kernel for FP32 fields, the fused single
+ *                      step for FP64, the two-kernel step with per-entry
+ *                      materials;
+ *   TETE_KERNEL_FUSED  the fused single-kernel step (TETE_ERR_STATE with
+ *                      per-entry materials);
+ *   TETE_KERNEL_FUSED2 two steps per launch, temporally blocked (FP32 fields
+ *                      only, else TETE_ERR_ARG; TETE_ERR_STATE with per-entry
+ *                      materials).  tete_step pairs consecutive steps except
+ *                      where an energy sample or probes need the state in
+ *                      between; those steps, and an odd last one, run as
+ *                      fused single steps;
+ *   TETE_KERNEL_SPLIT  the two-kernel step (one kernel per half step).
+ * rows: rows per workgroup of the fused single step, 12 or 16 (0: 16 for
+ * FP32, 12 for FP64; the two-step kernel always uses 16).  xchunk: x-planes
+ * per workgroup of either fused kernel (0: chosen from the grid size).
+ * depth: x-planes of old data the fused single step prefetches ahead, 1..3
+ * (0: 2; the two-step kernel prefetches one).  order: order in which the
+ * fused kernels' tiles are scheduled: 1 (j-tiles first), 2 (k-tiles first),
+ * 3 or 4 (blocks of 8 k-tiles by 4 j-tiles, or 16 by 2); 0: 4 where the grid
+ * has at least 16 k-tiles and 2 j-tiles, else 2.  tete_set_materials turns a
+ * forced FUSED or FUSED2 back into AUTO.  tete_get_tuning reports the kernel
+ * that tete_step will use (FUSED2, FUSED or SPLIT). */
+enum { TETE_KERNEL_AUTO = 0, TETE_KERNEL_FUSED = 1, TETE_KERNEL_SPLIT = 2, TETE_KERNEL_FUSED2 = 3 };
 typedef struct {
     int32_t kernel;
     int32_t rows;
@@ -222,17 +234,18 @@ tete_status tete_set_tuning(tete_grid* g, const tete_tuning* t);
 tete_status tete_get_tuning(tete_grid* g, tete_tuning* t);
 
 /* Live kernel timing for measurement.  max_steps > 0 arms up to max_steps
- * timed steps: each subsequent step records HIP events on the grid's stream
- * around its kernels (fused step: one kernel; two-kernel step: TM-like half
- * S1-S5 with the source and wake update, then TE-like half S6-S10).  0
- * disarms.  Synchronises.
- * Steps beyond the armed count fail with TETE_ERR_STATE. */
+ * timed launches: each subsequent launch records HIP events on the grid's
+ * stream around its kernels (fused step: one kernel; two-step kernel: one
+ * kernel for two steps; two-kernel step: TM-like half S1-S5 with the source
+ * and wake update, then TE-like half S6-S10).  0 disarms.  Synchronises.
+ * Launches beyond the armed count fail with TETE_ERR_STATE. */
 tete_status tete_set_timing(tete_grid* g, int64_t max_steps);
 
-/* Sum of the kernel durations of the timed steps since the last call, in ms:
- * two-kernel step: ms[0] = TM-like kernel, ms[1] = TE-like kernel; fused
- * step: ms[0] = the fused kernel, ms[1] = 0 (nphase >= 2); *steps = number
- * of timed steps.  Resets the count.  Synchronises. */
+/* Sum of the kernel durations of the timed launches since the last call, in
+ * ms: two-kernel step: ms[0] = TM-like kernel, ms[1] = TE-like kernel; fused
+ * kernels: ms[0] = the kernel, ms[1] = 0 (nphase >= 2); *steps = number of
+ * time steps the timed launches took (so ms[0] / *steps is the time per
+ * step).  Resets the count.  Synchronises. */
 tete_status tete_timing(tete_grid* g, double* ms, int32_t nphase, int64_t* steps);
 
 /* ------------------------------------------------------------------------

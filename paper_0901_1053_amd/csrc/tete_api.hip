@@ -89,9 +89,11 @@ struct tete_grid {
     int nprobe;
     double kv[3], mv[3], alpha;
     tete_tuning tune;
-    // live kernel timing (tete_set_timing): 3 events per timed step
+    // live kernel timing (tete_set_timing): 3 events per timed launch and the
+    // steps each launch took (1, or 2 for the two-step kernel)
     int timing;
     hipEvent_t* ev;
+    unsigned char* ev_nst;
     int64_t ev_cap, ev_steps;
 };
 
@@ -145,21 +147,44 @@ bool use_fused(const tete_grid* g)
     return g->tune.kernel != TETE_KERNEL_SPLIT;
 }
 
+// The two-step kernel (FP32 fields only; automatic choice or asked for) when
+// the grid qualifies; do_steps still takes single steps where a diagnostic
+// needs the state in between.
+bool use_fused2(const tete_grid* g)
+{
+    const bool want = g->tune.kernel == TETE_KERNEL_FUSED2 || g->tune.kernel == TETE_KERNEL_AUTO;
+    return want && g->fp32 && use_fused(g) && fused2_fits(g->geo);
+}
+
 template <typename R>
 tete_status do_steps(tete_grid* g, int64_t nsteps)
 {
     Mat<R> M = mats<R>(g);
+    const bool two = use_fused2(g);
     for (int64_t s = 0; s < nsteps; ++s) {
         if (g->diag_every > 0 && g->n % g->diag_every == 0) {
             HIPCHK(launch_energy<R>(fields<R>(g, g->cur), M, g->geo, g->alpha, g->partial, g->eser + g->ecount,
                                     g->stream));
             g->ecount++;
         }
+        // two steps at once unless the state after the first is observed
+        const bool pair = two && s + 1 < nsteps && g->nprobe == 0 &&
+                          !(g->diag_every > 0 && (g->n + 1) % g->diag_every == 0);
         hipEvent_t* ev = nullptr;
         if (g->timing) {
             if (g->ev_steps >= g->ev_cap) return TETE_ERR_STATE;
             ev = g->ev + 3 * g->ev_steps;
+            g->ev_nst[g->ev_steps] = pair ? 2 : 1;
             g->ev_steps++;
+        }
+        if (pair) {
+            HIPCHK(launch_step_fused2(fields<float>(g, g->cur), fields<float>(g, 1 - g->cur), mats<float>(g), g->geo,
+                                      (float)g->alpha, source(g, g->n), g->tune.xchunk, g->tune.depth,
+                                      g->tune.order, g->stream, ev));
+            g->cur = 1 - g->cur;
+            g->n += 2;
+            ++s;
+            continue;
         }
         if (use_fused(g))
             HIPCHK(launch_step_fused<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
@@ -296,6 +321,7 @@ tete_status tete_grid_destroy(tete_grid* g)
     if (!g) return TETE_ERR_ARG;
     for (int64_t e = 0; e < 3 * g->ev_cap; ++e) (void)hipEventDestroy(g->ev[e]);
     free(g->ev);
+    free(g->ev_nst);
     free(g);
     return TETE_OK;
 }
@@ -303,12 +329,13 @@ tete_status tete_grid_destroy(tete_grid* g)
 tete_status tete_set_tuning(tete_grid* g, const tete_tuning* t)
 {
     if (!g || !t) return TETE_ERR_ARG;
-    if (t->kernel < TETE_KERNEL_AUTO || t->kernel > TETE_KERNEL_SPLIT) return TETE_ERR_ARG;
+    if (t->kernel < TETE_KERNEL_AUTO || t->kernel > TETE_KERNEL_FUSED2) return TETE_ERR_ARG;
+    if (t->kernel == TETE_KERNEL_FUSED2 && !g->fp32) return TETE_ERR_ARG;
     if (t->rows != 0 && t->rows != 12 && t->rows != 16) return TETE_ERR_ARG;
     if (t->xchunk < 0) return TETE_ERR_ARG;
     if (t->depth < 0 || t->depth > 3) return TETE_ERR_ARG;
     if (t->order < 0 || t->order > 4) return TETE_ERR_ARG;
-    if (t->kernel == TETE_KERNEL_FUSED && g->mat_set) return TETE_ERR_STATE;
+    if ((t->kernel == TETE_KERNEL_FUSED || t->kernel == TETE_KERNEL_FUSED2) && g->mat_set) return TETE_ERR_STATE;
     g->tune = *t;
     if (g->tune.depth == 0) g->tune.depth = 2;
     return TETE_OK;
@@ -318,7 +345,7 @@ tete_status tete_get_tuning(tete_grid* g, tete_tuning* t)
 {
     if (!g || !t) return TETE_ERR_ARG;
     *t = g->tune;
-    t->kernel = use_fused(g) ? TETE_KERNEL_FUSED : TETE_KERNEL_SPLIT;
+    t->kernel = use_fused2(g) ? TETE_KERNEL_FUSED2 : use_fused(g) ? TETE_KERNEL_FUSED : TETE_KERNEL_SPLIT;
     return TETE_OK;
 }
 
@@ -332,6 +359,9 @@ tete_status tete_set_timing(tete_grid* g, int64_t max_steps)
         hipEvent_t* ev = (hipEvent_t*)realloc(g->ev, sizeof(hipEvent_t) * 3 * max_steps);
         if (!ev) return TETE_ERR_NOMEM;
         g->ev = ev;
+        unsigned char* nst = (unsigned char*)realloc(g->ev_nst, (size_t)max_steps);
+        if (!nst) return TETE_ERR_NOMEM;
+        g->ev_nst = nst;
         for (int64_t e = 3 * g->ev_cap; e < 3 * max_steps; ++e) {
             if (hipEventCreate(&g->ev[e]) != hipSuccess) {
                 g->ev_cap = e / 3;
@@ -352,14 +382,16 @@ tete_status tete_timing(tete_grid* g, double* ms, int32_t nphase, int64_t* steps
     if (!dg.ok) return TETE_ERR_DEVICE;
     HIPCHK(hipStreamSynchronize(g->stream));
     for (int p = 0; p < nphase; ++p) ms[p] = 0.0;
+    int64_t nst = 0;
     for (int64_t s = 0; s < g->ev_steps; ++s) {
         float t0 = 0.f, t1 = 0.f;
         HIPCHK(hipEventElapsedTime(&t0, g->ev[3 * s], g->ev[3 * s + 1]));
         HIPCHK(hipEventElapsedTime(&t1, g->ev[3 * s + 1], g->ev[3 * s + 2]));
         ms[0] += t0;
         if (nphase > 1) ms[1] += t1;
+        nst += g->ev_nst[s];
     }
-    *steps = g->ev_steps;
+    *steps = nst;
     g->ev_steps = 0;
     return TETE_OK;
 }
@@ -386,7 +418,7 @@ tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3], const
     DeviceGuard dg(g->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
     const void* src[6] = {inv_eps[0], inv_eps[1], inv_eps[2], inv_mu[0], inv_mu[1], inv_mu[2]};
-    if (g->tune.kernel == TETE_KERNEL_FUSED) g->tune.kernel = TETE_KERNEL_AUTO;
+    if (g->tune.kernel == TETE_KERNEL_FUSED || g->tune.kernel == TETE_KERNEL_FUSED2) g->tune.kernel = TETE_KERNEL_AUTO;
     if (g->fp32) {
         float* dst[6];
         for (int c = 0; c < 6; ++c) dst[c] = (float*)g->mat[c];

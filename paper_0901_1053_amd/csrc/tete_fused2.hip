@@ -1,0 +1,417 @@
+// Two steps of scheme (23) in one kernel: temporal blocking of the fused step
+// (FP32 fields, vacuum cells with staircase PEC codes).
+//
+// The x-march of a workgroup runs two copies of the single-step pipeline of
+// tete_fused.hip.  Stage A takes the old fields (step n) loaded from HBM to
+// step n+1; stage B takes stage A's results to step n+2, four planes behind
+// stage A.  Stage A's results never leave the chip: per two steps the state is
+// read once and written once.  Each stage keeps the single-step lag table (its
+// ten sub-updates at plane lags 0-4 behind its input plane) and its own six
+// j-exchange planes in LDS; both stages share the one barrier per plane.
+//
+// Halos double.  One step invalidates one lane at each end of a wave and two
+// rows at each edge of the workgroup, so a workgroup of 16 rows by 64 lanes
+// owns 8 rows by 60 entries, and a chunk of planes xs .. xe-1 needs old data
+// on planes xs-4 .. xe+3.
+//
+// Stage B's input plane at iteration p is plane p-4: e_x from stage A's S9 of
+// this iteration, e_y (S10) and h_z (S8) from the previous one, h_x and h_y
+// (S4, S5) from two iterations back and e_z (S3) from three; delay lines in
+// LDS (one slot per thread) hold the older ones.
+//
+// Register budget.  Two stages of carried state fill the 128 VGPRs a
+// 1024-thread workgroup allows, so the coefficients are pre-multiplied by
+// their factor a or 2a, PEC selects are two bit operations, the delay lines
+// live in LDS and one plane is prefetched (a second one spills).
+//
+// Wake.  The update of sample s at step n+1 from edge k and the update of the
+// same sample at step n from edge k-1 coincide.  The lane of node k applies
+// both in one read-modify-write, step n's term first, so every sample is
+// written by one lane per launch and each sum is formed in the same order as
+// by two single-step launches.  Step n's term needs e_z^{n-1/2} and
+// e_z^{n+1/2} of edge k-1 on the source plane: the first is kept from stage
+// A's pass over that plane, the second is stage B's old e_z there; both come
+// over from the neighbouring lane when stage B reaches the plane.
+
+#include <algorithm>
+
+#include "tete_dev.h"
+
+namespace tete {
+namespace {
+
+constexpr int KT2 = 60;   // k entries owned per workgroup: 64 lanes minus two halo lanes at each end
+
+// Carried pipeline state of one stage, named by plane lag behind the stage's
+// input plane q (m1 = q-1, ...), as in the single-step kernel.  The z
+// differences of the old e_x and e_y are formed again when needed (a lane
+// shift and a subtraction) rather than carried, which saves registers.
+template <typename R>
+struct Stage {
+    R EXm1, EXm2;
+    R EYm1, EYm2;
+    R EZm1, HYm1;
+    R HZm1, HZm2, HZm3;
+    R hxn_m1, hxn_m2, hyn_m2, ezh_m2;
+    R pztHX_m3, pztHY_m3, pztHY_m4;
+    R exh_m3, exh_m4, eyh_m3, hzn_m4;
+};
+
+// Input plane of a stage (fields of the step it starts from).
+template <typename R>
+struct In {
+    R ex, ey, ez, hx, hy, hz;
+};
+// j-neighbours read from LDS: e_z (j+1) at q, h_x^n (j-1) at q-1, e_z^{n+1/2}
+// (j+1) at q-2, h_z^n (j-1) at q-2, e_x^{n+1/2} (j+1) at q-3, h_z^{n+1} (j-1)
+// at q-4.
+template <typename R>
+struct Nb {
+    R ez0_jp, hxn1_jm, ezh2_jp, hz2_jm, exh3_jp, hzn4_jm;
+};
+// Coefficients of the sub-updates of one iteration, each already multiplied
+// by its factor a or 2a (the product the single-step kernel forms first, so
+// the arithmetic is the same): mu masked by the index ranges of the h
+// components, kappa zero on PEC edges.
+template <typename R>
+struct Co {
+    R mx0, mx2, my1, my2, mz3, kz1, ky2, kx2, ky3, kx4;
+};
+// Results of one iteration: e_z^{n-1/2} and e_z^{n+1/2} at q-1, h_x^{n+1/2}
+// and h_y^{n+1/2} at q-2, h_z^{n+1} and e_y^{n+1} at q-3, e_x^{n+1} at q-4.
+template <typename R>
+struct Out {
+    R ezold1, ezh1, hxh2, hyh2, hzn3, ey13, ex14;
+};
+
+// One iteration of a stage: the ten sub-updates at their lags, then the
+// rotation of the carried state by one plane.  inj is the bunch current term
+// taken off e_z^{n+1/2} (zero off the source line; x - 0 is exact).
+template <typename R>
+__device__ __forceinline__ Out<R> stage_plane(Stage<R>& S, const In<R>& c, const Nb<R>& nb, const Co<R>& f,
+                                              const R inj)
+{
+    // S1 at q: h_x^n = h_x^{n-1/2} + a mu_x [P_z e_y^n - P_y e_z^{n-1/2}]
+    const R pzEY0 = lane_next(c.ey) - c.ey;
+    const R hxn0 = c.hx + f.mx0 * (pzEY0 - (nb.ez0_jp - c.ez));
+    // S2 at q-1: h_y^n = h_y^{n-1/2} + a mu_y [-P_z e_x^n + P_x e_z^{n-1/2}]
+    const R pzEXm1 = lane_next(S.EXm1) - S.EXm1;
+    const R hyn_m1 = S.HYm1 + f.my1 * (-pzEXm1 + (c.ez - S.EZm1));
+    // S3 at q-1: e_z^{n+1/2} = e_z^{n-1/2} + 2a kappa_z [P_y^T h_x^n - P_x^T h_y^n - j_z^n]
+    R ezh_m1 = S.EZm1 + f.kz1 * ((nb.hxn1_jm - S.hxn_m1) - (S.hyn_m2 - hyn_m1));
+    ezh_m1 -= inj;
+    // S4 at q-2: h_x^{n+1/2} = h_x^n + a mu_x [P_z e_y^n - P_y e_z^{n+1/2}]
+    const R pzEYm2 = lane_next(S.EYm2) - S.EYm2;
+    const R hxh_m2 = S.hxn_m2 + f.mx2 * (pzEYm2 - (nb.ezh2_jp - S.ezh_m2));
+    // S5 at q-2: h_y^{n+1/2} = h_y^n + a mu_y [-P_z e_x^n + P_x e_z^{n+1/2}]
+    const R pzEXm2 = lane_next(S.EXm2) - S.EXm2;
+    const R hyh_m2 = S.hyn_m2 + f.my2 * (-pzEXm2 + (ezh_m1 - S.ezh_m2));
+    // S7 at q-2: e_y^{n+1/2} = e_y^n + a kappa_y [-P_z^T h_x^{n+1/2} + P_x^T h_z^n]
+    const R pztHX_m2 = lane_prev(hxh_m2) - hxh_m2;
+    const R eyh_m2 = S.EYm2 + f.ky2 * (-pztHX_m2 + (S.HZm3 - S.HZm2));
+    // S6 at q-2: e_x^{n+1/2} = e_x^n + a kappa_x [P_z^T h_y^{n+1/2} - P_y^T h_z^n]
+    const R pztHY_m2 = lane_prev(hyh_m2) - hyh_m2;
+    const R exh_m2 = S.EXm2 + f.kx2 * (pztHY_m2 - (nb.hz2_jm - S.HZm2));
+    // S8 at q-3: h_z^{n+1} = h_z^n + 2a mu_z [P_y e_x^{n+1/2} - P_x e_y^{n+1/2}]
+    const R hzn_m3 = S.HZm3 + f.mz3 * ((nb.exh3_jp - S.exh_m3) - (eyh_m2 - S.eyh_m3));
+    // S9 at q-4: e_x^{n+1} = e_x^{n+1/2} + a kappa_x [P_z^T h_y^{n+1/2} - P_y^T h_z^{n+1}]
+    const R ex1_m4 = S.exh_m4 + f.kx4 * (S.pztHY_m4 - (nb.hzn4_jm - S.hzn_m4));
+    // S10 at q-3: e_y^{n+1} = e_y^{n+1/2} + a kappa_y [-P_z^T h_x^{n+1/2} + P_x^T h_z^{n+1}]
+    const R ey1_m3 = S.eyh_m3 + f.ky3 * (-S.pztHX_m3 + (S.hzn_m4 - hzn_m3));
+
+    const Out<R> o = {S.EZm1, ezh_m1, hxh_m2, hyh_m2, hzn_m3, ey1_m3, ex1_m4};
+
+    S.EXm2 = S.EXm1; S.EXm1 = c.ex;
+    S.EYm2 = S.EYm1; S.EYm1 = c.ey;
+    S.EZm1 = c.ez; S.HYm1 = c.hy;
+    S.HZm3 = S.HZm2; S.HZm2 = S.HZm1; S.HZm1 = c.hz;
+    S.hxn_m2 = S.hxn_m1; S.hxn_m1 = hxn0;
+    S.hyn_m2 = hyn_m1;
+    S.ezh_m2 = ezh_m1;
+    S.pztHX_m3 = pztHX_m2;
+    S.pztHY_m4 = S.pztHY_m3; S.pztHY_m3 = pztHY_m2;
+    S.exh_m4 = S.exh_m3; S.exh_m3 = exh_m2;
+    S.eyh_m3 = eyh_m2;
+    S.hzn_m4 = hzn_m3;
+    return o;
+}
+
+// LDS of one workgroup: per stage, six double-buffered j-exchange planes of
+// TYH + 2 rows ([quantity][plane parity][row][lane]); and stage B's delay
+// lines for e_z, h_x and h_y, two planes deep, one slot per thread
+// ([quantity][plane parity][thread]), kept here to free registers.
+template <int TYH>
+struct Lds2 {
+    float a[6][2][TYH + 2][64];
+    float b[6][2][TYH + 2][64];
+    float d[3][2][64 * TYH];
+};
+
+// Two steps of one tile (ty, tz) and x-chunk cx.  Every thread of the
+// workgroup must call it (it contains barriers).
+template <int TYH, int PD>
+__device__ __forceinline__ void fused2_tile(const FArgs<float>& A, const int ty, const int tz, const int cx,
+                                            Lds2<TYH>& L)
+{
+    using R = float;
+    constexpr int TY = TYH - 8;
+    const Geo g = A.g;
+
+    const int kl = threadIdx.x & 63;
+    const int jl = threadIdx.x >> 6;
+    const int j = ty * TY - 4 + jl;
+    const int k = tz * KT2 - 2 + kl;
+    const bool jin = (unsigned)j <= (unsigned)g.ny;
+    const bool kin = (unsigned)k <= (unsigned)g.nz;
+    const bool node = jin && kin;
+    const bool owned = node && jl >= 4 && jl < 4 + TY && kl >= 2 && kl < 2 + KT2;
+    const int roff = k + j * g.sz;
+
+    // index-range masks of the h components (x part applied per plane)
+    const bool hx_jk = node && j < g.ny && k < g.nz;
+    const bool hy_k = node && k < g.nz;
+    const bool hz_j = node && j < g.ny;
+
+    const int xs = cx * A.xchunk;
+    const int xe = min(xs + A.xchunk, g.nx + 1);
+    const int xload_end = min(xe + 3, g.nx);    // last plane whose old data is needed
+
+    const R a2 = A.a + A.a;
+    const bool src_row = A.src.on && j == A.src.j0;    // uniform over a wave (one row)
+    const bool src_k = kin && k < g.nz;                 // lane holds an e_z edge
+
+    // Buffer resources over the chunk's planes, as in the single-step kernel:
+    // loads cover planes pb = max(0, xs - 4) .. xload_end, stores xs .. xe-1;
+    // out-of-range loads return 0 and out-of-range stores are dropped.  The
+    // host keeps (xchunk + 8) planes below 2^31 bytes.
+    constexpr uint32_t RB = sizeof(R);
+    constexpr uint32_t OOB = 0x80000000u;
+    const uint32_t plane_bytes = (uint32_t)g.sp * RB;
+    const int pb = max(0, xs - 4);
+    const int nload = xload_end >= pb ? xload_end - pb + 1 : 0;
+    auto mk = [](const void* base, uint32_t bytes) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+    };
+    const int64_t ld0 = (int64_t)pb * g.sp;
+    const auto rEX = mk(A.ex + ld0, nload * plane_bytes), rEY = mk(A.ey + ld0, nload * plane_bytes),
+               rEZ = mk(A.ez + ld0, nload * plane_bytes), rHX = mk(A.hx + ld0, nload * plane_bytes),
+               rHY = mk(A.hy + ld0, nload * plane_bytes), rHZ = mk(A.hz + ld0, nload * plane_bytes);
+    const auto rC = mk(A.code, (uint32_t)std::min<int64_t>((int64_t)g.np + 4, 0x7fffffff));
+    const int64_t st0 = (int64_t)xs * g.sp;
+    const uint32_t nstb = (uint32_t)(xe - xs) * plane_bytes;
+    const auto sEX = mk(A.ex1 + st0, nstb), sEY = mk(A.ey1 + st0, nstb), sEZ1 = mk(A.ez1 + st0, nstb),
+               sHX = mk(A.hx1 + st0, nstb), sHY = mk(A.hy1 + st0, nstb), sHZ1 = mk(A.hz1 + st0, nstb);
+    const uint32_t in_ld = (uint32_t)roff * RB;
+    const uint32_t cfix = node ? 0u : 7u;              // outside the grid: PEC
+
+    struct PR {
+        R ex, ey, ez, hx, hy, hz;
+        uint32_t c;
+    };
+    auto load_plane = [&](int i, PR& d) {
+        const uint32_t po = (uint32_t)(i - pb);
+        const uint32_t off = node ? in_ld + po * plane_bytes : OOB;
+        d.ex = bload<R>(rEX, off);
+        d.ey = bload<R>(rEY, off);
+        d.ez = bload<R>(rEZ, off);
+        d.hx = bload<R>(rHX, off);
+        d.hy = bload<R>(rHY, off);
+        d.hz = bload<R>(rHZ, off);
+        const uint32_t offc = node ? ((uint32_t)(roff + i * g.sp) & ~3u) : OOB;
+        d.c = __builtin_amdgcn_raw_buffer_load_b32(rC, offc, 0, 0);   // byte extracted when used
+    };
+
+    Stage<R> SA = {}, SB = {};
+    const int tid = threadIdx.x;
+    for (int q = 0; q < 3; ++q) L.d[q][0][tid] = L.d[q][1][tid] = R(0);   // stage B's delay lines
+    R d_ey4 = 0;                 // e_y^{n+1} of plane p-4
+    uint32_t ch = 0x77777777u;   // PEC codes of planes p-1 .. p-8, four bits each
+    R ezA = 0;                   // e_z^{n-1/2} of edge k on the source plane
+
+    // coefficient factors: a mu and 2a mu zero outside the index range of the
+    // h component in j and k (x is applied per plane), a kappa and 2a kappa
+    const R amx = hx_jk ? A.a * A.mx : R(0), amy = hy_k ? A.a * A.my : R(0), a2mz = hz_j ? a2 * A.mz : R(0);
+    const R akx = A.a * A.kx, aky = A.a * A.ky, a2kz = a2 * A.kz;
+    auto xlt = [&](int q) { return q >= 0 && q < g.nx; };
+    // v, or 0 where bit b of the code history is set (a PEC edge)
+    auto sel = [](uint32_t hist, int b, R v) {
+        const uint32_t m = (uint32_t)(((int32_t)(hist << (31 - b))) >> 31);
+        return __builtin_bit_cast(R, __builtin_bit_cast(uint32_t, v) & ~m);
+    };
+    // coefficients of a stage whose input plane is q; hist holds the codes of
+    // planes q-1 .. q-4 in bits 0-15.  h_x outside the grid's planes needs no
+    // mask: it reaches only e on the same plane, which such planes hold at 0
+    // (their edges are PEC).
+    auto coef = [&](int q, uint32_t hist) {
+        Co<R> f;
+        f.mx0 = amx;
+        f.mx2 = amx;
+        f.my1 = xlt(q - 1) ? amy : R(0);
+        f.my2 = xlt(q - 2) ? amy : R(0);
+        f.mz3 = xlt(q - 3) ? a2mz : R(0);
+        f.kz1 = sel(hist, 2, a2kz);
+        f.ky2 = sel(hist, 5, aky);
+        f.kx2 = sel(hist, 4, akx);
+        f.ky3 = sel(hist, 9, aky);
+        f.kx4 = sel(hist, 12, akx);
+        return f;
+    };
+    // bunch current of step n on edge k (zero where no cell crosses it)
+    auto inject = [&](int64_t n, R kz) {
+        const int64_t m = (int64_t)k - n + A.src.M;
+        return (m >= -A.src.M && m <= A.src.M) ? (R)((double)kz * A.src.lam[m + A.src.M]) : R(0);
+    };
+
+    PR buf[PD + 1];
+#pragma unroll
+    for (int d = 0; d < PD; ++d) load_plane(xs - 4 + d, buf[d]);
+
+    const int pend = xe + 7;
+    auto body = [&](const int p, const PR& cur, PR& nxt) {
+        load_plane(p + PD, nxt);
+        // outside the grid, or a plane without old data: PEC on all edges
+        const uint32_t c0 = ((cur.c >> (((uint32_t)(roff + p * g.sp) & 3u) * 8u)) & 7u) | cfix |
+                            ((p >= pb && p <= xload_end) ? 0u : 7u);
+
+        // stage B's input plane p-4, except e_x (stage A's S9 of this
+        // iteration); the delay-line slot of this parity holds plane p-4 and
+        // is refilled with plane p-2
+        const int s = p & 1;
+        const R bEY = d_ey4, bEZ = L.d[0][s][tid], bHX = L.d[1][s][tid], bHY = L.d[2][s][tid], bHZ = SA.hzn_m4;
+        L.d[0][s][tid] = SA.ezh_m2;
+
+        // j-exchange through LDS (row r of the tile is LDS row r+1; rows 0 and
+        // TYH+1 are never written and reach only halo results)
+        L.a[0][s][jl + 1][kl] = cur.ez;
+        L.a[1][s][jl + 1][kl] = SA.hxn_m1;
+        L.a[2][s][jl + 1][kl] = SA.ezh_m2;
+        L.a[3][s][jl + 1][kl] = SA.HZm2;
+        L.a[4][s][jl + 1][kl] = SA.exh_m3;
+        L.a[5][s][jl + 1][kl] = SA.hzn_m4;
+        L.b[0][s][jl + 1][kl] = bEZ;
+        L.b[1][s][jl + 1][kl] = SB.hxn_m1;
+        L.b[2][s][jl + 1][kl] = SB.ezh_m2;
+        L.b[3][s][jl + 1][kl] = SB.HZm2;
+        L.b[4][s][jl + 1][kl] = SB.exh_m3;
+        L.b[5][s][jl + 1][kl] = SB.hzn_m4;
+        __syncthreads();
+        const Nb<R> nA = {L.a[0][s][jl + 2][kl], L.a[1][s][jl][kl], L.a[2][s][jl + 2][kl],
+                          L.a[3][s][jl][kl],     L.a[4][s][jl + 2][kl], L.a[5][s][jl][kl]};
+        const Nb<R> nB = {L.b[0][s][jl + 2][kl], L.b[1][s][jl][kl], L.b[2][s][jl + 2][kl],
+                          L.b[3][s][jl][kl],     L.b[4][s][jl + 2][kl], L.b[5][s][jl][kl]};
+
+        const Co<R> fA = coef(p, ch), fB = coef(p - 4, ch >> 16);
+        // S3 of stage A is at plane p-1 (step n), of stage B at plane p-5 (step n+1)
+        const bool srcA = src_row && p - 1 == A.src.i0;
+        const bool srcB = src_row && p - 5 == A.src.i0;
+        const R injA = (srcA && src_k) ? inject(A.src.n, sel(ch, 2, A.kz)) : R(0);
+        const R injB = (srcB && src_k) ? inject(A.src.n + 1, sel(ch, 18, A.kz)) : R(0);
+
+        const Out<R> oA = stage_plane(SA, In<R>{cur.ex, cur.ey, cur.ez, cur.hx, cur.hy, cur.hz}, nA, fA, injA);
+        const Out<R> oB = stage_plane(SB, In<R>{oA.ex14, bEY, bEZ, bHX, bHY, bHZ}, nB, fB, injB);
+
+        if (srcA) ezA = oA.ezold1;
+        if (srcB) {   // wave-uniform: every lane takes part in the lane shifts
+            const R ezA_km = lane_prev(ezA), ezB_km = lane_prev(oB.ezold1);
+            if (owned && A.src.i0 >= xs && A.src.i0 < xe) {
+                const int64_t js = A.src.n + 1 - k - A.src.M;   // edge k at step n+1, edge k-1 at step n
+                if (js >= A.src.jmin && js < (int64_t)A.src.jmin + A.src.nw) {
+                    double w = A.src.wacc[js - A.src.jmin];
+                    if (k >= 1) w += -0.5 * ((double)ezA_km + (double)ezB_km);
+                    if (src_k) w += -0.5 * ((double)oB.ezold1 + (double)oB.ezh1);
+                    A.src.wacc[js - A.src.jmin] = w;
+                }
+            }
+        }
+
+        if (owned) {
+            const uint32_t o1 = in_ld + (uint32_t)(p - 5 - xs) * plane_bytes;
+            const uint32_t o2 = o1 - plane_bytes, o3 = o2 - plane_bytes, o4 = o3 - plane_bytes;
+            bstore<R>(sEZ1, o1, oB.ezh1);
+            bstore<R>(sHX, o2, oB.hxh2);
+            bstore<R>(sHY, o2, oB.hyh2);
+            bstore<R>(sHZ1, o3, oB.hzn3);
+            bstore<R>(sEY, o3, oB.ey13);
+            bstore<R>(sEX, o4, oB.ex14);
+        }
+
+        L.d[1][s][tid] = oA.hxh2;
+        L.d[2][s][tid] = oA.hyh2;
+        d_ey4 = oA.ey13;
+        ch = (ch << 4) | c0;
+    };
+
+    // trip count rounded up to a multiple of PD+1, as in the single-step kernel
+    for (int p = xs - 4; p <= pend; p += PD + 1) {
+#pragma unroll
+        for (int u = 0; u <= PD; ++u) body(p + u, buf[u], buf[(u + PD) % (PD + 1)]);
+    }
+}
+
+template <int TYH, int PD>
+__global__ __launch_bounds__(64 * TYH) void k_fused2(FArgs<float> A)
+{
+    __shared__ Lds2<TYH> L;
+    int ty, tz, cx;
+    if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) return;   // whole group
+    fused2_tile<TYH, PD>(A, ty, tz, cx, L);
+}
+
+constexpr int ROWS2 = 16;
+
+}  // namespace
+
+bool fused2_setup(FArgs<float>& A, int xchunk, int order)
+{
+    constexpr int TY = ROWS2 - 8;
+    A.nyt = (A.g.ny + 1 + TY - 1) / TY;
+    A.nzt = (A.g.nz + 1 + KT2 - 1) / KT2;
+    A.order = order != 0 ? order : (A.nzt >= block_z(4) && A.nyt >= block_y(4) ? 4 : 2);
+    const int nplanes = A.g.nx + 1;
+    // every buffer range must stay below 2^31 bytes: (xchunk + 8) planes
+    const int64_t plane_bytes = (int64_t)A.g.sp * sizeof(float);
+    const int64_t xmax = ((int64_t(1) << 31) - 1) / plane_bytes - 8;
+    if (xmax < 1) return false;
+    int xc = xchunk;
+    if (xc <= 0) {
+        // about two workgroups per CU slot, long chunks (each chunk re-reads
+        // seven halo planes), and the chunk within the buffer limit
+        const int tiles = A.nyt * A.nzt;
+        int chunks = (2048 + tiles - 1) / tiles;
+        chunks = std::min(chunks, std::max(1, nplanes / 64));
+        chunks = std::max<int64_t>(chunks, (nplanes + xmax - 1) / xmax);
+        xc = (nplanes + chunks - 1) / chunks;
+    }
+    xc = (int)std::min<int64_t>(std::max(xc, 1), xmax);
+    A.xchunk = xc;
+    A.nxc = (nplanes + xc - 1) / xc;
+    if (A.order == 3 || A.order == 4) {
+        const int BZ = block_z(A.order), BY = block_y(A.order);
+        A.nblk = ((A.nzt + BZ - 1) / BZ) * ((A.nyt + BY - 1) / BY) * BZ * BY * A.nxc;
+    }
+    else
+        A.nblk = A.nyt * A.nzt * A.nxc;
+    return true;
+}
+
+bool fused2_fits(Geo g)
+{
+    return (int64_t)g.sp * (int64_t)sizeof(float) * 9 < (int64_t(1) << 31);
+}
+
+hipError_t launch_step_fused2(Fields<float> o, Fields<float> nf, Mat<float> M, Geo g, float alpha, Src src,
+                              int xchunk, int depth, int order, hipStream_t s, hipEvent_t* ev)
+{
+    FArgs<float> A = fused_args<float>(o, nf, M, g, alpha, src);
+    if (!fused2_setup(A, xchunk, order)) return hipErrorInvalidValue;
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+    (void)depth;   // one plane prefetched: a deeper prefetch does not fit the register budget
+    k_fused2<ROWS2, 1><<<A.nblk, 64 * ROWS2, 0, s>>>(A);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+}  // namespace tete

@@ -119,6 +119,12 @@ FArgs<R> fused_args(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, 
 template <typename R>
 bool fused_setup(FArgs<R>& A, int rows, int xchunk, int order);
 int fused_default_rows(int real_bytes);
+// Two steps in one launch (tete_fused2.hip, FP32 fields): the fused step
+// temporally blocked; xchunk, depth (1 or 2) and order as for the single step.
+bool fused2_fits(Geo g);
+bool fused2_setup(FArgs<float>& A, int xchunk, int order);
+hipError_t launch_step_fused2(Fields<float> oldf, Fields<float> newf, Mat<float> mat, Geo g, float alpha, Src src,
+                              int xchunk, int depth, int order, hipStream_t s, hipEvent_t* ev);
 // One step of every instance of a batch (persistent grid of `grid` workgroups)
 template <typename R>
 hipError_t launch_batch_step(BatchTable<R>* T, int rows, int depth, int grid, int sub, hipStream_t s);

@@ -44,7 +44,7 @@ class Tuning(C.Structure):
                 ("order", C.c_int32)]
 
 
-KERNELS = {"auto": 0, "fused": 1, "split": 2}
+KERNELS = {"auto": 0, "fused": 1, "split": 2, "fused2": 3}
 
 
 class Bunch(C.Structure):
