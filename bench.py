@@ -153,7 +153,7 @@ def main():
     ap.add_argument("--rows", type=int, default=0, help="fused kernel: rows per workgroup (12 or 16)")
     ap.add_argument("--xchunk", type=int, default=0, help="fused kernel: x-planes per workgroup (0: auto)")
     ap.add_argument("--depth", type=int, default=0, help="fused kernel: planes prefetched ahead (1..3)")
-    ap.add_argument("--order", type=int, default=0, help="fused kernel: tile order (1..4; 0: library default)")
+    ap.add_argument("--order", type=int, default=0, help="fused kernels: tile order (1..6; 0: library default)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--batched-count", type=int, default=64)

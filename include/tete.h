@@ -218,8 +218,8 @@ tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h);
  * depth: x-planes of old data the fused single step prefetches ahead, 1..3
  * (0: 2; the two-step kernel prefetches one).  order: order in which the
  * fused kernels' tiles are scheduled: 1 (j-tiles first), 2 (k-tiles first),
- * 3 or 4 (blocks of 8 k-tiles by 4 j-tiles, or 16 by 2); 0: 4 where the grid
- * has at least 16 k-tiles and 2 j-tiles, else 2.  tete_set_materials turns a
+ * 3, 4, 5 or 6 (blocks of 8 k-tiles by 4 j-tiles, 16 by 2, 4 by 8 or 2 by
+ * 16); 0: 4 where the grid has at least 16 k-tiles and 2 j-tiles, else 2.  tete_set_materials turns a
  * forced FUSED or FUSED2 back into AUTO.  tete_get_tuning reports the kernel
  * that tete_step will use (FUSED2, FUSED or SPLIT). */
 enum { TETE_KERNEL_AUTO = 0, TETE_KERNEL_FUSED = 1, TETE_KERNEL_SPLIT = 2, TETE_KERNEL_FUSED2 = 3 };

@@ -334,7 +334,7 @@ tete_status tete_set_tuning(tete_grid* g, const tete_tuning* t)
     if (t->rows != 0 && t->rows != 12 && t->rows != 16) return TETE_ERR_ARG;
     if (t->xchunk < 0) return TETE_ERR_ARG;
     if (t->depth < 0 || t->depth > 3) return TETE_ERR_ARG;
-    if (t->order < 0 || t->order > 4) return TETE_ERR_ARG;
+    if (t->order < 0 || t->order > 6) return TETE_ERR_ARG;
     if ((t->kernel == TETE_KERNEL_FUSED || t->kernel == TETE_KERNEL_FUSED2) && g->mat_set) return TETE_ERR_STATE;
     g->tune = *t;
     if (g->tune.depth == 0) g->tune.depth = 2;

@@ -74,14 +74,26 @@ __device__ __forceinline__ int xcd_remap(int b, int n)
 
 // Tile (ty, tz) and x-chunk cx of logical workgroup lb.  order 2: k-tiles
 // fastest, so the tiles of one band of rows, which together cover whole
-// contiguous rows, run together; order 1: j-tiles fastest; orders 3 and 4:
-// blocks of 8 k-tiles by 4 j-tiles or 16 k-tiles by 2 j-tiles (32 workgroups,
-// one XCD's worth) fastest, so that neighbouring row bands, which share halo
-// rows, also run together (order 4 measured fastest on long grids).  Order 0
-// is resolved on the host before launch.  Returns false for the padding
-// workgroups of the blocked orders.
-__host__ __device__ __forceinline__ int block_z(int order) { return order == 4 ? 16 : 8; }
-__host__ __device__ __forceinline__ int block_y(int order) { return order == 4 ? 2 : 4; }
+// contiguous rows, run together; order 1: j-tiles fastest; orders 3-6: blocks
+// of BZ k-tiles by BY j-tiles (8 x 4, 16 x 2, 4 x 8, 2 x 16: 32 workgroups, one
+// XCD's worth) fastest, so that neighbouring row bands, which share halo rows,
+// also run together and share the XCD's L2.  Order 0 is resolved on the host
+// before launch.  Returns false for the padding workgroups of the blocked
+// orders.
+__host__ __device__ __forceinline__ bool blocked_order(int order) { return order >= 3 && order <= 6; }
+__host__ __device__ __forceinline__ int block_z(int order)
+{
+    return order == 3 ? 8 : order == 4 ? 16 : order == 5 ? 4 : 2;
+}
+__host__ __device__ __forceinline__ int block_y(int order) { return 32 / block_z(order); }
+// Workgroups of one launch: tiles (padded to whole blocks for the blocked
+// orders) times x-chunks.
+__host__ __device__ __forceinline__ int launch_tiles(int order, int nyt, int nzt, int nxc)
+{
+    if (!blocked_order(order)) return nyt * nzt * nxc;
+    const int BZ = block_z(order), BY = block_y(order);
+    return ((nzt + BZ - 1) / BZ) * ((nyt + BY - 1) / BY) * BZ * BY * nxc;
+}
 __device__ __forceinline__ bool tile_of(int lb, int order, int nyt, int nzt, int& ty, int& tz, int& cx)
 {
     if (order == 2) {
@@ -90,7 +102,7 @@ __device__ __forceinline__ bool tile_of(int lb, int order, int nyt, int nzt, int
         cx = lb / (nzt * nyt);
         return true;
     }
-    if (order == 3 || order == 4) {
+    if (blocked_order(order)) {
         const int BZ = block_z(order), BY = block_y(order);
         const int nbz = (nzt + BZ - 1) / BZ, nby = (nyt + BY - 1) / BY;
         const int w = lb % (BZ * BY), b = lb / (BZ * BY);

@@ -350,12 +350,7 @@ bool fused_setup(FArgs<R>& A, int rows, int xchunk, int order)
     xc = (int)std::min<int64_t>(std::max(xc, 1), xmax);
     A.xchunk = xc;
     A.nxc = (nplanes + xc - 1) / xc;
-    if (A.order == 3 || A.order == 4) {
-        const int BZ = block_z(A.order), BY = block_y(A.order);
-        A.nblk = ((A.nzt + BZ - 1) / BZ) * ((A.nyt + BY - 1) / BY) * BZ * BY * A.nxc;
-    }
-    else
-        A.nblk = A.nyt * A.nzt * A.nxc;
+    A.nblk = launch_tiles(A.order, A.nyt, A.nzt, A.nxc);
     return true;
 }
 

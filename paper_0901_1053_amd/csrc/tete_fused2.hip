@@ -9,10 +9,12 @@
 // ten sub-updates at plane lags 0-4 behind its input plane) and its own six
 // j-exchange planes in LDS; both stages share the one barrier per plane.
 //
-// Halos double.  One step invalidates one lane at each end of a wave and two
-// rows at each edge of the workgroup, so a workgroup of 16 rows by 64 lanes
-// owns 8 rows by 60 entries, and a chunk of planes xs .. xe-1 needs old data
-// on planes xs-4 .. xe+3.
+// Halos.  One step invalidates one lane at each end of a wave and two rows
+// at each edge of the workgroup; two steps invalidate two lanes and three
+// rows (the sub-updates that reach two rows out in one step reach only one
+// row out in the other, so the halo does not double along j).  A workgroup
+// of 16 rows by 64 lanes thus owns 10 rows by 60 entries, and a chunk of
+// planes xs .. xe-1 needs old data on planes xs-4 .. xe+3.
 //
 // Stage B's input plane at iteration p is plane p-4: e_x from stage A's S9 of
 // this iteration, e_y (S10) and h_z (S8) from the previous one, h_x and h_y
@@ -154,17 +156,17 @@ __device__ __forceinline__ void fused2_tile(const FArgs<float>& A, const int ty,
                                             Lds2<TYH>& L)
 {
     using R = float;
-    constexpr int TY = TYH - 8;
+    constexpr int TY = TYH - 6;
     const Geo g = A.g;
 
     const int kl = threadIdx.x & 63;
     const int jl = threadIdx.x >> 6;
-    const int j = ty * TY - 4 + jl;
+    const int j = ty * TY - 3 + jl;
     const int k = tz * KT2 - 2 + kl;
     const bool jin = (unsigned)j <= (unsigned)g.ny;
     const bool kin = (unsigned)k <= (unsigned)g.nz;
     const bool node = jin && kin;
-    const bool owned = node && jl >= 4 && jl < 4 + TY && kl >= 2 && kl < 2 + KT2;
+    const bool owned = node && jl >= 3 && jl < 3 + TY && kl >= 2 && kl < 2 + KT2;
     const int roff = k + j * g.sz;
 
     // index-range masks of the h components (x part applied per plane)
@@ -363,7 +365,7 @@ constexpr int ROWS2 = 16;
 
 bool fused2_setup(FArgs<float>& A, int xchunk, int order)
 {
-    constexpr int TY = ROWS2 - 8;
+    constexpr int TY = ROWS2 - 6;
     A.nyt = (A.g.ny + 1 + TY - 1) / TY;
     A.nzt = (A.g.nz + 1 + KT2 - 1) / KT2;
     A.order = order != 0 ? order : (A.nzt >= block_z(4) && A.nyt >= block_y(4) ? 4 : 2);
@@ -385,12 +387,7 @@ bool fused2_setup(FArgs<float>& A, int xchunk, int order)
     xc = (int)std::min<int64_t>(std::max(xc, 1), xmax);
     A.xchunk = xc;
     A.nxc = (nplanes + xc - 1) / xc;
-    if (A.order == 3 || A.order == 4) {
-        const int BZ = block_z(A.order), BY = block_y(A.order);
-        A.nblk = ((A.nzt + BZ - 1) / BZ) * ((A.nyt + BY - 1) / BY) * BZ * BY * A.nxc;
-    }
-    else
-        A.nblk = A.nyt * A.nzt * A.nxc;
+    A.nblk = launch_tiles(A.order, A.nyt, A.nzt, A.nxc);
     return true;
 }
 

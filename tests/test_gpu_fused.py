@@ -43,7 +43,7 @@ def test_fused_matches_oracle_fp64(shape):
 
 @pytest.mark.parametrize("rows,xchunk,depth,order", [
     (16, 0, 2, 1), (12, 0, 2, 2), (16, 1, 1, 1), (12, 3, 3, 3), (16, 7, 2, 0), (12, 1000, 1, 2), (16, 2, 3, 3),
-    (16, 0, 2, 4), (12, 5, 1, 4)])
+    (16, 0, 2, 4), (12, 5, 1, 4), (16, 3, 2, 5), (12, 0, 3, 6)])
 def test_fused_launch_shape_invariance(rows, xchunk, depth, order):
     """Bitwise identical fields for every launch shape (every entry is computed
     by the same expressions from the same inputs, wherever the halo falls)."""

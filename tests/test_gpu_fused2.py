@@ -41,7 +41,7 @@ def test_two_steps_equal_single_steps(shape):
         _same(_fields(shape, 31, "fused2", steps), _fields(shape, 31, "fused", steps))
 
 
-@pytest.mark.parametrize("xchunk,order", [(1, 2), (2, 1), (3, 3), (5, 4), (7, 0), (1000, 2), (0, 4), (0, 1)])
+@pytest.mark.parametrize("xchunk,order", [(1, 2), (2, 1), (3, 3), (5, 4), (7, 0), (1000, 2), (0, 4), (0, 1), (4, 5), (0, 6)])
 def test_launch_shape_invariance(xchunk, order):
     shape = (40, 29, 1000)
     base = _fields(shape, 32, "fused", 12)
