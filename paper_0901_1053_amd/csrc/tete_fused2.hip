@@ -376,12 +376,13 @@ bool fused2_setup(FArgs<float>& A, int xchunk, int order)
     if (xmax < 1) return false;
     int xc = xchunk;
     if (xc <= 0) {
-        // about two workgroups per CU slot, long chunks (each chunk re-reads
-        // seven halo planes), and the chunk within the buffer limit
+        // as few chunks as possible (each re-reads seven halo planes and
+        // refills the pipeline), but enough workgroups for half of the CUs,
+        // chunks of at least 16 planes, and each within the buffer limit
         const int tiles = A.nyt * A.nzt;
-        int chunks = (2048 + tiles - 1) / tiles;
-        chunks = std::min(chunks, std::max(1, nplanes / 64));
-        chunks = std::max<int64_t>(chunks, (nplanes + xmax - 1) / xmax);
+        int chunks = (128 + tiles - 1) / tiles;
+        chunks = std::min(chunks, std::max(1, nplanes / 16));
+        chunks = (int)std::max<int64_t>(chunks, (nplanes + xmax - 1) / xmax);
         xc = (nplanes + chunks - 1) / chunks;
     }
     xc = (int)std::min<int64_t>(std::max(xc, 1), xmax);
