@@ -219,7 +219,8 @@ tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h);
  * (0: 2; the two-step kernel prefetches one).  order: order in which the
  * fused kernels' tiles are scheduled: 1 (j-tiles first), 2 (k-tiles first),
  * 3, 4, 5 or 6 (blocks of 8 k-tiles by 4 j-tiles, 16 by 2, 4 by 8 or 2 by
- * 16); 0: 4 where the grid has at least 16 k-tiles and 2 j-tiles, else 2.  tete_set_materials turns a
+ * 16); 0: 4 where the grid has at least 16 k-tiles and 2 j-tiles and the
+ * launch at least 2048 workgroups, else 2 (batches: 2).  tete_set_materials turns a
  * forced FUSED or FUSED2 back into AUTO.  tete_get_tuning reports the kernel
  * that tete_step will use (FUSED2, FUSED or SPLIT). */
 enum { TETE_KERNEL_AUTO = 0, TETE_KERNEL_FUSED = 1, TETE_KERNEL_SPLIT = 2, TETE_KERNEL_FUSED2 = 3 };
@@ -250,9 +251,9 @@ tete_status tete_timing(tete_grid* g, double* ms, int32_t nphase, int64_t* steps
 
 /* ------------------------------------------------------------------------
  * Batches: many grids (of one precision, uneven sizes, own geometries and
- * bunches) stepped together, one persistent launch per time step covering
- * every member's tiles; blocks of steps are replayed from a captured HIP
- * graph.  A batch owns a small device table (tete_batch_bytes) in caller
+ * bunches) stepped together, one persistent launch per time step (FP32: per
+ * two time steps, with the two-step kernel) covering every member's tiles;
+ * blocks of steps are replayed from a captured HIP graph.  A batch owns a small device table (tete_batch_bytes) in caller
  * memory; membership can change between calls (continuous batching) without
  * re-capturing the graph.  Members use the fused kernel (no per-entry
  * materials) with their own x-chunk and tile order (tete_set_tuning); energy
@@ -272,8 +273,9 @@ typedef struct tete_batch tete_batch;
 size_t tete_batch_bytes(int32_t precision);
 
 /* Create a batch over a caller-owned device table (256-byte aligned, at least
- * tete_batch_bytes(precision)), using hip_stream.  Empty, launch shape: rows
- * chosen by precision, prefetch depth 1, graph blocks of 8 steps. */
+ * tete_batch_bytes(precision)), using hip_stream.  Empty, launch shape:
+ * automatic kernel, rows chosen by precision, prefetch depth 1, graph blocks
+ * of 8 steps. */
 tete_status tete_batch_create(int32_t precision, void* dev_table, size_t bytes, void* hip_stream,
                               tete_batch** out);
 tete_status tete_batch_destroy(tete_batch* b);
@@ -285,9 +287,16 @@ tete_status tete_batch_destroy(tete_batch* b);
  * requires setting its slot again before the next batch step. */
 tete_status tete_batch_set(tete_batch* b, int32_t slot, tete_grid* g);
 
-/* Launch shape shared by the members: rows (0, 12 or 16), prefetch depth
- * (0..3, 0 = 1) and steps per captured graph block (0 = no graph). */
-tete_status tete_batch_set_launch(tete_batch* b, int32_t rows, int32_t depth, int32_t graph_steps);
+/* Launch shape shared by the members.  kernel: TETE_KERNEL_AUTO (two steps
+ * per launch for FP32 batches whose members all fit the two-step kernel,
+ * else single steps), TETE_KERNEL_FUSED (single steps) or TETE_KERNEL_FUSED2
+ * (as AUTO; TETE_ERR_ARG for FP64); a block of an odd number of steps ends
+ * with a single step.  rows (0, 12 or 16) and prefetch depth (0..3, 0 = 1)
+ * of the single-step kernel; steps per captured graph block (0 = no graph).
+ * With the two-step kernel a member uses its own tile order and, if its
+ * tuning asks for TETE_KERNEL_FUSED2, its own x-chunk. */
+tete_status tete_batch_set_launch(tete_batch* b, int32_t kernel, int32_t rows, int32_t depth,
+                                  int32_t graph_steps);
 
 /* Enqueue nsteps steps of every member (asynchronous).  Each member's step
  * counter advances by nsteps, as if tete_step had been called on it. */

@@ -625,6 +625,8 @@ struct tete_batch {
     tete_grid* slot[TETE_MAX_BATCH];
     int64_t seen_n[TETE_MAX_BATCH];   // (n, cur) of each member when the table was built
     int seen_cur[TETE_MAX_BATCH];
+    int kernel;               // TETE_KERNEL_AUTO, _FUSED or _FUSED2
+    int two;                  // the table holds two-step arguments and blocks use them
     int rows, depth, graph_steps;
     int dirty;
     int phase;
@@ -636,8 +638,38 @@ struct tete_batch {
 
 namespace {
 
+void batch_drop_graph(tete_batch* b)
+{
+    if (b->graph_ok) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->graph_ok = 0;
+    }
+}
+
 template <typename R>
 size_t batch_table_bytes() { return up(sizeof(BatchTable<R>)); }
+
+// Tile order of a batch member: its own, or k-tiles first (the blocked
+// orders, which match a single grid's tiles to the XCDs, do not apply when
+// the items of many grids share the persistent workgroups).
+int batch_order(const tete_grid* g) { return g->tune.order != 0 ? g->tune.order : 2; }
+
+// Two-step arguments of one member for both parities (FP32 batches only).
+bool batch_two_args(tete_grid* g, BatchItem<float>& it, int phase, int& total2)
+{
+    FArgs<float> f2 = fused_args<float>(fields<float>(g, g->cur), fields<float>(g, 1 - g->cur), mats<float>(g),
+                                        g->geo, (float)g->alpha, source(g, g->n));
+    FArgs<float> b2 = fused_args<float>(fields<float>(g, 1 - g->cur), fields<float>(g, g->cur), mats<float>(g),
+                                        g->geo, (float)g->alpha, source(g, g->n));
+    const int xc = g->tune.kernel == TETE_KERNEL_FUSED2 ? g->tune.xchunk : 0;
+    if (!fused2_setup(f2, xc, batch_order(g)) || !fused2_setup(b2, xc, batch_order(g))) return false;
+    it.a2[phase] = f2;
+    it.a2[1 - phase] = b2;
+    total2 += f2.nblk;
+    return true;
+}
+bool batch_two_args(tete_grid*, BatchItem<double>&, int, int&) { return false; }
 
 template <typename R>
 tete_status batch_build(tete_batch* b)
@@ -645,7 +677,16 @@ tete_status batch_build(tete_batch* b)
     BatchTable<R>* H = (BatchTable<R>*)b->host;
     memset(H, 0, sizeof(BatchTable<R>));
     H->phase = b->phase;
-    int total = 0;
+    // two steps per launch for FP32 unless the single step was asked for, and
+    // only if every member's planes fit the two-step kernel
+    bool two = b->fp32 && b->kernel != TETE_KERNEL_FUSED;
+    for (int s = 0; s < TETE_MAX_BATCH && two; ++s)
+        if (b->slot[s] && !fused2_fits(b->slot[s]->geo)) two = false;
+    if ((int)two != b->two) {
+        batch_drop_graph(b);   // the captured block launches the other kernel
+        b->two = two;
+    }
+    int total = 0, total2 = 0;
     for (int s = 0; s < TETE_MAX_BATCH; ++s) {
         tete_grid* g = b->slot[s];
         if (!g) continue;
@@ -654,42 +695,47 @@ tete_status batch_build(tete_batch* b)
         Src src = source(g, g->n);
         FArgs<R> fwd = fused_args<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha, src);
         FArgs<R> bwd = fused_args<R>(fields<R>(g, 1 - g->cur), fields<R>(g, g->cur), M, g->geo, (R)g->alpha, src);
-        if (!fused_setup<R>(fwd, b->rows, g->tune.xchunk, g->tune.order) ||
-            !fused_setup<R>(bwd, b->rows, g->tune.xchunk, g->tune.order))
+        if (!fused_setup<R>(fwd, b->rows, g->tune.xchunk, batch_order(g)) ||
+            !fused_setup<R>(bwd, b->rows, g->tune.xchunk, batch_order(g)))
             return TETE_ERR_ARG;
         // at the current phase the grid reads its current set
         H->item[i].a[b->phase] = fwd;
         H->item[i].a[1 - b->phase] = bwd;
         H->offset[i] = total;
+        H->offset2[i] = total2;
+        if (two && !batch_two_args(g, H->item[i], b->phase, total2)) return TETE_ERR_ARG;
         H->step[i] = g->n;
         total += fwd.nblk;
         b->seen_n[s] = g->n;
         b->seen_cur[s] = g->cur;
     }
     H->offset[H->ninst] = total;
+    H->offset2[H->ninst] = total2;
     H->total = total;
+    H->total2 = total2;
     HIPCHK(hipMemcpyAsync(b->table, H, sizeof(BatchTable<R>), hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     b->dirty = 0;
     return TETE_OK;
 }
 
+// Launches of a block of `steps` steps (two per launch where the batch uses
+// the two-step kernel, a single step for an odd last one); the number of
+// launches, each of which swaps the ping-pong sets once.
+int batch_block_launches(const tete_batch* b, int steps) { return b->two ? (steps + 1) / 2 : steps; }
+
 template <typename R>
 tete_status batch_launch_block(tete_batch* b, int steps)
 {
-    for (int s = 0; s < steps; ++s)
-        HIPCHK(launch_batch_step<R>((BatchTable<R>*)b->table, b->rows, b->depth, b->grid, s, b->gstream));
-    HIPCHK(launch_batch_advance<R>((BatchTable<R>*)b->table, steps, b->gstream));
+    BatchTable<R>* T = (BatchTable<R>*)b->table;
+    int done = 0, flips = 0;
+    if (b->two)
+        for (; done + 2 <= steps; done += 2, ++flips)
+            HIPCHK(launch_batch_step2((BatchTable<float>*)T, b->grid, flips, done, b->gstream));
+    for (; done < steps; ++done, ++flips)
+        HIPCHK(launch_batch_step<R>(T, b->rows, b->depth, b->grid, flips, done, b->gstream));
+    HIPCHK(launch_batch_advance<R>(T, steps, flips, b->gstream));
     return TETE_OK;
-}
-
-void batch_drop_graph(tete_batch* b)
-{
-    if (b->graph_ok) {
-        (void)hipGraphExecDestroy(b->exec);
-        (void)hipGraphDestroy(b->graph);
-        b->graph_ok = 0;
-    }
 }
 
 template <typename R>
@@ -727,7 +773,7 @@ tete_status batch_step(tete_batch* b, int64_t nsteps)
     }
     HIPCHK(hipEventRecord(b->ev_out, b->gstream));
     HIPCHK(hipStreamWaitEvent(b->stream, b->ev_out, 0));
-    const int flip = (int)(nsteps & 1);
+    const int flip = (int)((full * batch_block_launches(b, K) + batch_block_launches(b, rem)) & 1);
     for (int s = 0; s < TETE_MAX_BATCH; ++s) {
         tete_grid* g = b->slot[s];
         if (!g) continue;
@@ -821,11 +867,14 @@ tete_status tete_batch_set(tete_batch* b, int32_t slot, tete_grid* g)
     return TETE_OK;
 }
 
-tete_status tete_batch_set_launch(tete_batch* b, int32_t rows, int32_t depth, int32_t graph_steps)
+tete_status tete_batch_set_launch(tete_batch* b, int32_t kernel, int32_t rows, int32_t depth, int32_t graph_steps)
 {
     if (!b || (rows != 0 && rows != 12 && rows != 16) || depth < 0 || depth > 3 || graph_steps < 0 ||
         graph_steps > 1024)
         return TETE_ERR_ARG;
+    if (kernel != TETE_KERNEL_AUTO && kernel != TETE_KERNEL_FUSED && kernel != TETE_KERNEL_FUSED2) return TETE_ERR_ARG;
+    if (kernel == TETE_KERNEL_FUSED2 && !b->fp32) return TETE_ERR_ARG;
+    b->kernel = kernel;
     b->rows = rows;
     b->depth = depth == 0 ? 1 : depth;
     b->graph_steps = graph_steps;

@@ -94,6 +94,15 @@ __host__ __device__ __forceinline__ int launch_tiles(int order, int nyt, int nzt
     const int BZ = block_z(order), BY = block_y(order);
     return ((nzt + BZ - 1) / BZ) * ((nyt + BY - 1) / BY) * BZ * BY * nxc;
 }
+// Default tile order: 16 x 2 blocks (order 4) where a block row is filled
+// and the launch spans at least eight rounds of 256 workgroups, so that the
+// padding of partial blocks averages out over the rounds; otherwise k-tiles
+// first (order 2).
+inline int default_order(int nyt, int nzt, int nxc)
+{
+    const bool fill = nzt >= block_z(4) && nyt >= block_y(4);
+    return fill && (int64_t)nyt * nzt * nxc >= 8 * 256 ? 4 : 2;
+}
 __device__ __forceinline__ bool tile_of(int lb, int order, int nyt, int nzt, int& ty, int& tz, int& cx)
 {
     if (order == 2) {

@@ -274,14 +274,21 @@ __global__ __launch_bounds__(64 * TYH) void k_fused(FArgs<R> A)
 // round w / gridDim.x.  Within a round the items are remapped over the XCDs
 // like the tiles of one grid, so that neighbouring tiles share an L2.  The
 // instance's step index and the ping-pong parity come from the table, which
-// the host may rewrite between launches (a captured graph stays valid).
+// the host may rewrite between launches (a captured graph stays valid); this
+// launch follows `flips` launches and `steps` steps of the current block.
 template <typename R, int TYH, int PD>
-__global__ __launch_bounds__(64 * TYH) void k_fused_batch(const BatchTable<R>* T, int sub)
+__global__ __launch_bounds__(64 * TYH) void k_fused_batch(const BatchTable<R>* Tg, int flips, int steps)
 {
     __shared__ Lds<R, TYH> L;
+    // The table is read-only during the launch: reading it through the
+    // constant address space makes its (uniform) fields scalar loads into
+    // scalar registers instead of vector loads that would occupy VGPRs.
+    typedef const __attribute__((address_space(4))) BatchTable<R>* CTable;
+    typedef const __attribute__((address_space(4))) uint32_t* CWords;
+    const CTable T = (CTable)Tg;
     const int total = T->total;
     const int ninst = T->ninst;
-    const int parity = (T->phase + sub) & 1;
+    const int parity = (T->phase + flips) & 1;
     for (int round = 0; round * (int)gridDim.x < total; ++round) {
         const int base = round * (int)gridDim.x;
         const int span = min((int)gridDim.x, total - base);
@@ -296,21 +303,28 @@ __global__ __launch_bounds__(64 * TYH) void k_fused_batch(const BatchTable<R>* T
             else hi = mid - 1;
         }
         const int inst = __builtin_amdgcn_readfirstlane(lo);
-        FArgs<R> A = T->item[inst].a[parity];
-        A.src.n = T->step[inst] + sub;
+        FArgs<R> A;
+        {
+            const CWords src = (CWords)&T->item[inst].a[parity];
+            uint32_t* dst = (uint32_t*)&A;
+#pragma unroll
+            for (int i = 0; i < (int)(sizeof(FArgs<R>) / 4); ++i) dst[i] = src[i];
+        }
+        A.src.n = T->step[inst] + steps;
         int ty, tz, cx;
         if (tile_of(w - T->offset[inst], A.order, A.nyt, A.nzt, ty, tz, cx)) fused_tile<R, TYH, PD>(A, ty, tz, cx, L);
         __syncthreads();   // the LDS is reused by the next item
     }
 }
 
-// After a block of steps: advance every instance's step index and the phase.
+// After a block: advance every instance's step index, and the phase by the
+// number of launches (each launch swaps the ping-pong sets once).
 template <typename R>
-__global__ void k_batch_advance(BatchTable<R>* T, int steps)
+__global__ void k_batch_advance(BatchTable<R>* T, int steps, int flips)
 {
     const int i = threadIdx.x + blockIdx.x * blockDim.x;
     if (i < T->ninst) T->step[i] += steps;
-    if (i == 0) T->phase = (T->phase + steps) & 1;
+    if (i == 0) T->phase = (T->phase + flips) & 1;
 }
 
 template <typename R, int TYH, int PD>
@@ -332,8 +346,6 @@ bool fused_setup(FArgs<R>& A, int rows, int xchunk, int order)
     const int TY = rows - 4;
     A.nyt = (A.g.ny + 1 + TY - 1) / TY;
     A.nzt = (A.g.nz + 1 + KT - 1) / KT;
-    // default: 16 x 2 blocks where a block row is filled, else k-tiles first
-    A.order = order != 0 ? order : (A.nzt >= block_z(4) && A.nyt >= block_y(4) ? 4 : 2);
     const int nplanes = A.g.nx + 1;
     int xc = xchunk;
     if (xc <= 0) {
@@ -350,6 +362,7 @@ bool fused_setup(FArgs<R>& A, int rows, int xchunk, int order)
     xc = (int)std::min<int64_t>(std::max(xc, 1), xmax);
     A.xchunk = xc;
     A.nxc = (nplanes + xc - 1) / xc;
+    A.order = order != 0 ? order : default_order(A.nyt, A.nzt, A.nxc);
     A.nblk = launch_tiles(A.order, A.nyt, A.nzt, A.nxc);
     return true;
 }
@@ -371,26 +384,26 @@ FArgs<R> fused_args(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha, Src src
 }
 
 template <typename R>
-hipError_t launch_batch_step(BatchTable<R>* T, int rows, int depth, int grid, int sub, hipStream_t s)
+hipError_t launch_batch_step(BatchTable<R>* T, int rows, int depth, int grid, int flips, int steps, hipStream_t s)
 {
     if (rows == 0) rows = fused_default_rows(sizeof(R));
     const int threads = 64 * rows;
     if (rows == 12) {
-        if (depth == 1) k_fused_batch<R, 12, 1><<<grid, threads, 0, s>>>(T, sub);
-        else if (depth == 3) k_fused_batch<R, 12, 3><<<grid, threads, 0, s>>>(T, sub);
-        else k_fused_batch<R, 12, 2><<<grid, threads, 0, s>>>(T, sub);
+        if (depth == 1) k_fused_batch<R, 12, 1><<<grid, threads, 0, s>>>(T, flips, steps);
+        else if (depth == 3) k_fused_batch<R, 12, 3><<<grid, threads, 0, s>>>(T, flips, steps);
+        else k_fused_batch<R, 12, 2><<<grid, threads, 0, s>>>(T, flips, steps);
     } else {
-        if (depth == 1) k_fused_batch<R, 16, 1><<<grid, threads, 0, s>>>(T, sub);
-        else if (depth == 3) k_fused_batch<R, 16, 3><<<grid, threads, 0, s>>>(T, sub);
-        else k_fused_batch<R, 16, 2><<<grid, threads, 0, s>>>(T, sub);
+        if (depth == 1) k_fused_batch<R, 16, 1><<<grid, threads, 0, s>>>(T, flips, steps);
+        else if (depth == 3) k_fused_batch<R, 16, 3><<<grid, threads, 0, s>>>(T, flips, steps);
+        else k_fused_batch<R, 16, 2><<<grid, threads, 0, s>>>(T, flips, steps);
     }
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_batch_advance(BatchTable<R>* T, int steps, hipStream_t s)
+hipError_t launch_batch_advance(BatchTable<R>* T, int steps, int flips, hipStream_t s)
 {
-    k_batch_advance<R><<<(TETE_MAX_BATCH + 255) / 256, 256, 0, s>>>(T, steps);
+    k_batch_advance<R><<<(TETE_MAX_BATCH + 255) / 256, 256, 0, s>>>(T, steps, flips);
     return hipGetLastError();
 }
 
@@ -426,8 +439,8 @@ hipError_t launch_step_fused(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha
 #define TETE_FUSED_INST(R)                                                                                     \
     template bool fused_setup<R>(FArgs<R>&, int, int, int);                                                    \
     template FArgs<R> fused_args<R>(Fields<R>, Fields<R>, Mat<R>, Geo, R, Src);                                 \
-    template hipError_t launch_batch_step<R>(BatchTable<R>*, int, int, int, int, hipStream_t);                 \
-    template hipError_t launch_batch_advance<R>(BatchTable<R>*, int, hipStream_t);
+    template hipError_t launch_batch_step<R>(BatchTable<R>*, int, int, int, int, int, hipStream_t);            \
+    template hipError_t launch_batch_advance<R>(BatchTable<R>*, int, int, hipStream_t);
 TETE_FUSED_INST(float)
 TETE_FUSED_INST(double)
 

@@ -183,8 +183,8 @@ __device__ __forceinline__ void fused2_tile(const FArgs<float>& A, const int ty,
     const bool src_k = kin && k < g.nz;                 // lane holds an e_z edge
 
     // Buffer resources over the chunk's planes, as in the single-step kernel:
-    // loads cover planes pb = max(0, xs - 4) .. xload_end, stores xs .. xe-1;
-    // out-of-range loads return 0 and out-of-range stores are dropped.  The
+    // loads cover planes pb = max(0, xs - 4) .. xload_end and out-of-range
+    // loads return 0.  The
     // host keeps (xchunk + 8) planes below 2^31 bytes.
     constexpr uint32_t RB = sizeof(R);
     constexpr uint32_t OOB = 0x80000000u;
@@ -199,10 +199,19 @@ __device__ __forceinline__ void fused2_tile(const FArgs<float>& A, const int ty,
                rEZ = mk(A.ez + ld0, nload * plane_bytes), rHX = mk(A.hx + ld0, nload * plane_bytes),
                rHY = mk(A.hy + ld0, nload * plane_bytes), rHZ = mk(A.hz + ld0, nload * plane_bytes);
     const auto rC = mk(A.code, (uint32_t)std::min<int64_t>((int64_t)g.np + 4, 0x7fffffff));
+    // Stores are plain global stores: the chunk's first plane as a scalar base
+    // plus a 32-bit byte offset, predicated on the plane lying in the chunk
+    // (uniform) and the entry being owned; this keeps six buffer resources
+    // (24 scalar registers) free.
     const int64_t st0 = (int64_t)xs * g.sp;
-    const uint32_t nstb = (uint32_t)(xe - xs) * plane_bytes;
-    const auto sEX = mk(A.ex1 + st0, nstb), sEY = mk(A.ey1 + st0, nstb), sEZ1 = mk(A.ez1 + st0, nstb),
-               sHX = mk(A.hx1 + st0, nstb), sHY = mk(A.hy1 + st0, nstb), sHZ1 = mk(A.hz1 + st0, nstb);
+    char* const gEX = (char*)(A.ex1 + st0);
+    char* const gEY = (char*)(A.ey1 + st0);
+    char* const gEZ = (char*)(A.ez1 + st0);
+    char* const gHX = (char*)(A.hx1 + st0);
+    char* const gHY = (char*)(A.hy1 + st0);
+    char* const gHZ = (char*)(A.hz1 + st0);
+    auto gstore = [](char* base, uint32_t off, R v) { *(R*)(base + off) = v; };
+    auto xown = [&](int q) { return q >= xs && q < xe; };
     const uint32_t in_ld = (uint32_t)roff * RB;
     const uint32_t cfix = node ? 0u : 7u;              // outside the grid: PEC
 
@@ -327,14 +336,19 @@ __device__ __forceinline__ void fused2_tile(const FArgs<float>& A, const int ty,
         }
 
         if (owned) {
-            const uint32_t o1 = in_ld + (uint32_t)(p - 5 - xs) * plane_bytes;
+            const int q1 = p - 5;
+            const uint32_t o1 = in_ld + (uint32_t)(q1 - xs) * plane_bytes;
             const uint32_t o2 = o1 - plane_bytes, o3 = o2 - plane_bytes, o4 = o3 - plane_bytes;
-            bstore<R>(sEZ1, o1, oB.ezh1);
-            bstore<R>(sHX, o2, oB.hxh2);
-            bstore<R>(sHY, o2, oB.hyh2);
-            bstore<R>(sHZ1, o3, oB.hzn3);
-            bstore<R>(sEY, o3, oB.ey13);
-            bstore<R>(sEX, o4, oB.ex14);
+            if (xown(q1)) gstore(gEZ, o1, oB.ezh1);
+            if (xown(q1 - 1)) {
+                gstore(gHX, o2, oB.hxh2);
+                gstore(gHY, o2, oB.hyh2);
+            }
+            if (xown(q1 - 2)) {
+                gstore(gHZ, o3, oB.hzn3);
+                gstore(gEY, o3, oB.ey13);
+            }
+            if (xown(q1 - 3)) gstore(gEX, o4, oB.ex14);
         }
 
         L.d[1][s][tid] = oA.hxh2;
@@ -359,16 +373,65 @@ __global__ __launch_bounds__(64 * TYH) void k_fused2(FArgs<float> A)
     fused2_tile<TYH, PD>(A, ty, tz, cx, L);
 }
 
+// Two steps of every active instance of an FP32 batch, by a persistent grid,
+// as the single-step batch kernel does it: work item w (instance, tile,
+// x-chunk) is taken by workgroup w mod gridDim.x in round w / gridDim.x,
+// remapped over the XCDs within a round; the launch follows `flips` launches
+// and `steps` steps of the current block.
+template <int TYH>
+__global__ __launch_bounds__(64 * TYH) void k_fused2_batch(const BatchTable<float>* Tg, int flips, int steps)
+{
+    __shared__ Lds2<TYH> L;
+    // The table is read-only during the launch: reading it through the
+    // constant address space makes its (uniform) fields scalar loads into
+    // scalar registers instead of vector loads that would occupy VGPRs.
+    typedef const __attribute__((address_space(4))) BatchTable<float>* CTable;
+    typedef const __attribute__((address_space(4))) uint32_t* CWords;
+    const CTable T = (CTable)Tg;
+    const int total = T->total2;
+    const int ninst = T->ninst;
+    const int parity = (T->phase + flips) & 1;
+    for (int round = 0; round * (int)gridDim.x < total; ++round) {
+        const int base = round * (int)gridDim.x;
+        const int span = min((int)gridDim.x, total - base);
+        if ((int)blockIdx.x >= span) break;
+        const int w = __builtin_amdgcn_readfirstlane(base + xcd_remap(blockIdx.x, span));
+        int lo = 0, hi = ninst - 1;               // last instance whose first item is <= w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (T->offset2[mid] <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const int inst = __builtin_amdgcn_readfirstlane(lo);
+        FArgs<float> A;
+        {
+            const CWords src = (CWords)&T->item[inst].a2[parity];
+            uint32_t* dst = (uint32_t*)&A;
+#pragma unroll
+            for (int i = 0; i < (int)(sizeof(FArgs<float>) / 4); ++i) dst[i] = src[i];
+        }
+        A.src.n = T->step[inst] + steps;
+        int ty, tz, cx;
+        if (tile_of(w - T->offset2[inst], A.order, A.nyt, A.nzt, ty, tz, cx)) fused2_tile<TYH, 1>(A, ty, tz, cx, L);
+        __syncthreads();   // the LDS is reused by the next item
+    }
+}
+
 constexpr int ROWS2 = 16;
 
 }  // namespace
+
+hipError_t launch_batch_step2(BatchTable<float>* T, int grid, int flips, int steps, hipStream_t s)
+{
+    k_fused2_batch<ROWS2><<<grid, 64 * ROWS2, 0, s>>>(T, flips, steps);
+    return hipGetLastError();
+}
 
 bool fused2_setup(FArgs<float>& A, int xchunk, int order)
 {
     constexpr int TY = ROWS2 - 6;
     A.nyt = (A.g.ny + 1 + TY - 1) / TY;
     A.nzt = (A.g.nz + 1 + KT2 - 1) / KT2;
-    A.order = order != 0 ? order : (A.nzt >= block_z(4) && A.nyt >= block_y(4) ? 4 : 2);
     const int nplanes = A.g.nx + 1;
     // every buffer range must stay below 2^31 bytes: (xchunk + 8) planes
     const int64_t plane_bytes = (int64_t)A.g.sp * sizeof(float);
@@ -388,6 +451,7 @@ bool fused2_setup(FArgs<float>& A, int xchunk, int order)
     xc = (int)std::min<int64_t>(std::max(xc, 1), xmax);
     A.xchunk = xc;
     A.nxc = (nplanes + xc - 1) / xc;
+    A.order = order != 0 ? order : default_order(A.nyt, A.nzt, A.nxc);
     A.nblk = launch_tiles(A.order, A.nyt, A.nzt, A.nxc);
     return true;
 }

@@ -60,19 +60,22 @@ struct FArgs {
 };
 
 // Device-resident table of a batch (tete_batch_*): the active instances, their
-// work-item offsets, step indices, and fused-step arguments for both ping-pong
-// parities (a[q] is used when (phase + sub-step) % 2 == q).
+// work-item offsets, step indices, and kernel arguments for both ping-pong
+// parities (a[q] is used when (phase + launches so far in the block) % 2 ==
+// q): a for the single step, a2 for the two-step kernel (FP32 batches).
 template <typename R>
 struct BatchItem {
     FArgs<R> a[2];
+    FArgs<R> a2[2];
 };
 template <typename R>
 struct BatchTable {
     int ninst;                         // active instances (compacted)
-    int total;                         // work items of one step, all instances
-    int phase;                         // parity of the steps taken so far
-    int pad;
-    int offset[TETE_MAX_BATCH + 1];    // first work item of each instance
+    int total;                         // work items of one single step, all instances
+    int total2;                        // work items of one two-step launch
+    int phase;                         // parity of the launches taken so far
+    int offset[TETE_MAX_BATCH + 1];    // first work item of each instance (single step)
+    int offset2[TETE_MAX_BATCH + 1];   // first work item of each instance (two-step kernel)
     int64_t step[TETE_MAX_BATCH];      // step index n of each instance
     BatchItem<R> item[TETE_MAX_BATCH];
 };
@@ -125,11 +128,16 @@ bool fused2_fits(Geo g);
 bool fused2_setup(FArgs<float>& A, int xchunk, int order);
 hipError_t launch_step_fused2(Fields<float> oldf, Fields<float> newf, Mat<float> mat, Geo g, float alpha, Src src,
                               int xchunk, int depth, int order, hipStream_t s, hipEvent_t* ev);
-// One step of every instance of a batch (persistent grid of `grid` workgroups)
+// One step of every instance of a batch (persistent grid of `grid`
+// workgroups), the launch after `flips` earlier launches and `steps` earlier
+// steps of the current block
 template <typename R>
-hipError_t launch_batch_step(BatchTable<R>* T, int rows, int depth, int grid, int sub, hipStream_t s);
+hipError_t launch_batch_step(BatchTable<R>* T, int rows, int depth, int grid, int flips, int steps, hipStream_t s);
+// Two steps of every instance of an FP32 batch (tete_fused2.hip)
+hipError_t launch_batch_step2(BatchTable<float>* T, int grid, int flips, int steps, hipStream_t s);
+// After a block: step indices += steps, phase += flips (launches)
 template <typename R>
-hipError_t launch_batch_advance(BatchTable<R>* T, int steps, hipStream_t s);
+hipError_t launch_batch_advance(BatchTable<R>* T, int steps, int flips, hipStream_t s);
 
 // energy of a state -> out[0] (FP64), using partial[RED_BLOCKS]
 template <typename R>

@@ -95,7 +95,7 @@ def load(path: str = LIB_PATH):
         "tete_batch_create": (st, [C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]),
         "tete_batch_destroy": (st, [vp]),
         "tete_batch_set": (st, [vp, C.c_int32, vp]),
-        "tete_batch_set_launch": (st, [vp, C.c_int32, C.c_int32, C.c_int32]),
+        "tete_batch_set_launch": (st, [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
         "tete_batch_step": (st, [vp, C.c_int64]),
         "tete_batch_count": (st, [vp, C.POINTER(C.c_int32)]),
         "tete_status_str": (C.c_char_p, [C.c_int]),
@@ -322,8 +322,8 @@ class Batch:
         else:
             self.members[slot] = grid
 
-    def set_launch(self, rows=0, depth=0, graph_steps=8):
-        _chk("tete_batch_set_launch", load().tete_batch_set_launch(self.h, rows, depth, graph_steps))
+    def set_launch(self, rows=0, depth=0, graph_steps=8, kernel="auto"):
+        _chk("tete_batch_set_launch", load().tete_batch_set_launch(self.h, KERNELS[kernel], rows, depth, graph_steps))
 
     def step(self, n: int):
         _chk("tete_batch_step", load().tete_batch_step(self.h, int(n)))

@@ -29,12 +29,16 @@ def _alone(case, precision, steps):
     return G.wake(), G.get_fields(dtype=precision)
 
 
-@pytest.mark.parametrize("precision,graph_steps,steps", [("fp32", 4, 23), ("fp64", 8, 17), ("fp32", 0, 9)])
-def test_batch_equals_alone(precision, graph_steps, steps):
+@pytest.mark.parametrize("precision,graph_steps,steps,kernel", [
+    ("fp32", 4, 23, "auto"), ("fp64", 8, 17, "auto"), ("fp32", 0, 9, "auto"), ("fp32", 3, 22, "fused2"),
+    ("fp32", 5, 23, "fused")])
+def test_batch_equals_alone(precision, graph_steps, steps, kernel):
+    """Odd graph blocks end with a single step; both batch kernels give each
+    member its solo result bitwise."""
     cases = _cases()
     ref = [_alone(c, precision, steps) for c in cases]
     B = tete.Batch(precision)
-    B.set_launch(graph_steps=graph_steps)
+    B.set_launch(graph_steps=graph_steps, kernel=kernel)
     grids = [_grid(c, precision) for c in cases]
     for s, G in enumerate(grids):
         B.set(3 * s + 1, G)             # sparse slots
@@ -69,6 +73,31 @@ def test_batch_continuous_membership():
         assert grids[i].steps_done() == n
         w_ref, _ = _alone(cases[i], "fp32", n)
         assert np.array_equal(grids[i].wake(), w_ref), i
+
+
+def test_batch_kernel_switch_mid_run():
+    """Two-step blocks, then single steps, then two-step blocks again (the
+    captured graph is replaced each time), with an odd count in between."""
+    cases = _cases()[:3]
+    grids = [_grid(c, "fp32") for c in cases]
+    B = tete.Batch("fp32")
+    for s, G in enumerate(grids):
+        B.set(s, G)
+    B.set_launch(graph_steps=4)
+    B.step(9)
+    B.set_launch(graph_steps=4, kernel="fused")
+    B.step(6)
+    B.set_launch(graph_steps=6, kernel="fused2")
+    B.step(13)
+    for G, c in zip(grids, cases):
+        w_ref, f_ref = _alone(c, "fp32", 28)
+        assert np.array_equal(G.wake(), w_ref), c.name
+        f = G.get_fields(dtype="fp32")
+        for k in tete.KEYS:
+            assert np.array_equal(f[k], f_ref[k]), (c.name, k)
+    B64 = tete.Batch("fp64")
+    with pytest.raises(tete.TeteError):
+        B64.set_launch(kernel="fused2")
 
 
 def test_batch_member_matches_oracle_fp64():
