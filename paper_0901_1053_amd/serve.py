@@ -241,6 +241,44 @@ class Server:
                           max_active, peak_bytes, lat)
 
 
+def fifo_completions(arrivals, service):
+    """Completion times of requests served one at a time, first come first
+    served, by a server that is busy for service[i] seconds with request i."""
+    done = []
+    t = 0.0
+    for a, s in zip(arrivals, service):
+        t = max(t, a) + s
+        done.append(t)
+    return done
+
+
+def one_at_a_time_stats(arrivals, service) -> ServeStats:
+    """Statistics of one-at-a-time FIFO serving of a request stream, given
+    each request's measured solve time alone (the server's behaviour does not
+    depend on the arrival times otherwise, so one pass of solves serves every
+    arrival rate)."""
+    done = fifo_completions(arrivals, service)
+    lat = [d - a for d, a in zip(done, arrivals)]
+    makespan = max(done) if done else 0.0
+    return ServeStats(len(done), makespan, len(done) / makespan if makespan > 0 else math.nan,
+                      percentile(lat, 50), percentile(lat, 99), float(np.mean(lat)) if lat else math.nan,
+                      1 if done else 0, 0, lat)
+
+
+def solve_alone(executor, cases):
+    """Each case solved alone through the executor (admit, all its steps,
+    read-out, release), in order; returns (seconds per solve, wakes)."""
+    times, wakes = [], []
+    for i, c in enumerate(cases):
+        r = Request(i, c, 0.0)
+        t0 = executor.now()
+        executor.admit(0, r)
+        executor.step(c.steps)
+        wakes.append(executor.finish(0))
+        times.append(executor.now() - t0)
+    return times, wakes
+
+
 def make_requests(cases, rate, seed):
     arr = poisson_arrivals(rate, len(cases), seed)
     return [Request(i, c, float(t)) for i, (c, t) in enumerate(zip(cases, arr))]

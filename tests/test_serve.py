@@ -103,3 +103,24 @@ def test_size_classes():
     assert size_class(64, 64, 256, "fp32") == "fp32:64x64x256"
     assert size_class(96, 96, 768, "fp32") == "fp32:128x128x1024"
     assert size_class(65, 64, 256, "fp64") == "fp64:128x64x256"
+
+
+def test_fifo_completions_by_hand():
+    assert serve.fifo_completions([0.0, 0.5, 4.0], [1.0, 2.0, 1.0]) == [1.0, 3.0, 5.0]
+    assert serve.fifo_completions([], []) == []
+
+
+def test_one_at_a_time_model_equals_served_stream():
+    """The FIFO model over solve-alone times reproduces what the server does
+    with one slot, at a low and a high rate."""
+    cases = _cases(10, seed=8)
+    ex = serve.MockExecutor(rate_cells_per_s=3e8)
+    times, wakes = serve.solve_alone(ex, cases)
+    assert len(wakes) == len(cases) and all(w.shape == (c.nw,) for w, c in zip(wakes, cases))
+    for rate in (0.5, 500.0):
+        reqs = serve.make_requests(cases, rate, seed=9)
+        st = serve.Server(serve.MockExecutor(rate_cells_per_s=3e8), max_slots=1, block_steps=10 ** 9).run(reqs)
+        model = serve.one_at_a_time_stats([r.arrival for r in reqs], times)
+        assert model.completed == st.completed
+        assert model.latencies == pytest.approx(st.latencies, rel=1e-9, abs=1e-9)
+        assert model.p99_s == pytest.approx(st.p99_s, rel=1e-9)
