@@ -200,28 +200,28 @@ tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h);
 /* Kernel choice and launch shape (for tuning; results do not depend on it
  * beyond rounding order, and the fused kernels give identical results).
  * kernel:
- *   TETE_KERNEL_AUTO   the two-step kernel for FP32 fields, the fused single
- *                      step for FP64, the two-kernel step with per-entry
- *                      materials;
+ *   TETE_KERNEL_AUTO   the two-step kernel, or the two-kernel step with
+ *                      per-entry materials;
  *   TETE_KERNEL_FUSED  the fused single-kernel step (TETE_ERR_STATE with
  *                      per-entry materials);
- *   TETE_KERNEL_FUSED2 two steps per launch, temporally blocked (FP32 fields
- *                      only, else TETE_ERR_ARG; TETE_ERR_STATE with per-entry
- *                      materials).  tete_step pairs consecutive steps except
- *                      where an energy sample or probes need the state in
- *                      between; those steps, and an odd last one, run as
- *                      fused single steps;
+ *   TETE_KERNEL_FUSED2 two steps per launch, temporally blocked
+ *                      (TETE_ERR_STATE with per-entry materials).  tete_step
+ *                      pairs consecutive steps except where an energy sample
+ *                      or probes need the state in between; those steps, and
+ *                      an odd last one, run as fused single steps;
  *   TETE_KERNEL_SPLIT  the two-kernel step (one kernel per half step).
  * rows: rows per workgroup of the fused single step, 12 or 16 (0: 16 for
- * FP32, 12 for FP64; the two-step kernel always uses 16).  xchunk: x-planes
+ * FP32, 12 for FP64); of the two-step kernel, 16 (16 rows of 64 lanes for
+ * FP32, of 32 lanes for FP64, the default) or 32 (FP32: 32 rows of 32
+ * lanes); 32 leaves the single step at its default.  xchunk: x-planes
  * per workgroup of either fused kernel (0: chosen from the grid size).
  * depth: x-planes of old data the fused single step prefetches ahead, 1..3
  * (0: 2; the two-step kernel prefetches one).  order: order in which the
  * fused kernels' tiles are scheduled: 1 (j-tiles first), 2 (k-tiles first),
  * 3, 4, 5 or 6 (blocks of 8 k-tiles by 4 j-tiles, 16 by 2, 4 by 8 or 2 by
  * 16); 0: 4 where the grid has at least 16 k-tiles and 2 j-tiles and the
- * launch at least 2048 workgroups, else 2 (batches: 2).  tete_set_materials turns a
- * forced FUSED or FUSED2 back into AUTO.  tete_get_tuning reports the kernel
+ * launch at least 2048 workgroups, else 2 (batches: 2).  tete_set_materials
+ * turns a forced FUSED or FUSED2 back into AUTO.  tete_get_tuning reports the kernel
  * that tete_step will use (FUSED2, FUSED or SPLIT). */
 enum { TETE_KERNEL_AUTO = 0, TETE_KERNEL_FUSED = 1, TETE_KERNEL_SPLIT = 2, TETE_KERNEL_FUSED2 = 3 };
 typedef struct {
@@ -288,10 +288,9 @@ tete_status tete_batch_destroy(tete_batch* b);
 tete_status tete_batch_set(tete_batch* b, int32_t slot, tete_grid* g);
 
 /* Launch shape shared by the members.  kernel: TETE_KERNEL_AUTO (two steps
- * per launch for FP32 batches whose members all fit the two-step kernel,
- * else single steps), TETE_KERNEL_FUSED (single steps) or TETE_KERNEL_FUSED2
- * (as AUTO; TETE_ERR_ARG for FP64); a block of an odd number of steps ends
- * with a single step.  rows (0, 12 or 16) and prefetch depth (0..3, 0 = 1)
+ * per launch where every member fits the two-step kernel, else single
+ * steps), TETE_KERNEL_FUSED (single steps) or TETE_KERNEL_FUSED2 (as AUTO);
+ * a block of an odd number of steps ends with a single step.  rows (0, 12 or 16) and prefetch depth (0..3, 0 = 1)
  * of the single-step kernel; steps per captured graph block (0 = no graph).
  * With the two-step kernel a member uses its own tile order and, if its
  * tuning asks for TETE_KERNEL_FUSED2, its own x-chunk. */

@@ -147,13 +147,21 @@ bool use_fused(const tete_grid* g)
     return g->tune.kernel != TETE_KERNEL_SPLIT;
 }
 
-// The two-step kernel (FP32 fields only; automatic choice or asked for) when
-// the grid qualifies; do_steps still takes single steps where a diagnostic
-// needs the state in between.
+// The two-step kernel (automatic choice, or asked for) when the grid
+// qualifies; do_steps still takes single steps where a diagnostic needs the
+// state in between.
+// Rows of the two-step kernel: the tuning's rows when it asks for 16 or 32
+// (32: FP32 only), else the default.
+int fused2_rows(const tete_grid* g)
+{
+    const int r = g->tune.rows;
+    return r == 16 || (r == 32 && g->fp32) ? r : 0;
+}
+
 bool use_fused2(const tete_grid* g)
 {
     const bool want = g->tune.kernel == TETE_KERNEL_FUSED2 || g->tune.kernel == TETE_KERNEL_AUTO;
-    return want && g->fp32 && use_fused(g) && fused2_fits(g->geo);
+    return want && use_fused(g) && fused2_fits(g->geo, g->fp32 ? 4 : 8);
 }
 
 template <typename R>
@@ -178,9 +186,9 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             g->ev_steps++;
         }
         if (pair) {
-            HIPCHK(launch_step_fused2(fields<float>(g, g->cur), fields<float>(g, 1 - g->cur), mats<float>(g), g->geo,
-                                      (float)g->alpha, source(g, g->n), g->tune.xchunk, g->tune.depth,
-                                      g->tune.order, g->stream, ev));
+            HIPCHK(launch_step_fused2<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
+                                         source(g, g->n), fused2_rows(g), g->tune.xchunk, g->tune.order, g->stream,
+                                         ev));
             g->cur = 1 - g->cur;
             g->n += 2;
             ++s;
@@ -188,8 +196,8 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
         }
         if (use_fused(g))
             HIPCHK(launch_step_fused<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
-                                        source(g, g->n), g->tune.rows, g->tune.xchunk, g->tune.depth, g->tune.order,
-                                        g->stream, ev));
+                                        source(g, g->n), g->tune.rows == 32 ? 0 : g->tune.rows, g->tune.xchunk,
+                                        g->tune.depth, g->tune.order, g->stream, ev));
         else
             HIPCHK(launch_step<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                   source(g, g->n), g->stream, ev));
@@ -330,8 +338,7 @@ tete_status tete_set_tuning(tete_grid* g, const tete_tuning* t)
 {
     if (!g || !t) return TETE_ERR_ARG;
     if (t->kernel < TETE_KERNEL_AUTO || t->kernel > TETE_KERNEL_FUSED2) return TETE_ERR_ARG;
-    if (t->kernel == TETE_KERNEL_FUSED2 && !g->fp32) return TETE_ERR_ARG;
-    if (t->rows != 0 && t->rows != 12 && t->rows != 16) return TETE_ERR_ARG;
+    if (t->rows != 0 && t->rows != 12 && t->rows != 16 && t->rows != 32) return TETE_ERR_ARG;
     if (t->xchunk < 0) return TETE_ERR_ARG;
     if (t->depth < 0 || t->depth > 3) return TETE_ERR_ARG;
     if (t->order < 0 || t->order > 6) return TETE_ERR_ARG;
@@ -655,21 +662,21 @@ size_t batch_table_bytes() { return up(sizeof(BatchTable<R>)); }
 // the items of many grids share the persistent workgroups).
 int batch_order(const tete_grid* g) { return g->tune.order != 0 ? g->tune.order : 2; }
 
-// Two-step arguments of one member for both parities (FP32 batches only).
-bool batch_two_args(tete_grid* g, BatchItem<float>& it, int phase, int& total2)
+// Two-step arguments of one member for both parities.
+template <typename R>
+bool batch_two_args(tete_grid* g, BatchItem<R>& it, int phase, int& total2)
 {
-    FArgs<float> f2 = fused_args<float>(fields<float>(g, g->cur), fields<float>(g, 1 - g->cur), mats<float>(g),
-                                        g->geo, (float)g->alpha, source(g, g->n));
-    FArgs<float> b2 = fused_args<float>(fields<float>(g, 1 - g->cur), fields<float>(g, g->cur), mats<float>(g),
-                                        g->geo, (float)g->alpha, source(g, g->n));
+    FArgs<R> f2 = fused_args<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), mats<R>(g), g->geo, (R)g->alpha,
+                                source(g, g->n));
+    FArgs<R> b2 = fused_args<R>(fields<R>(g, 1 - g->cur), fields<R>(g, g->cur), mats<R>(g), g->geo, (R)g->alpha,
+                                source(g, g->n));
     const int xc = g->tune.kernel == TETE_KERNEL_FUSED2 ? g->tune.xchunk : 0;
-    if (!fused2_setup(f2, xc, batch_order(g)) || !fused2_setup(b2, xc, batch_order(g))) return false;
+    if (!fused2_setup<R>(f2, 0, xc, batch_order(g)) || !fused2_setup<R>(b2, 0, xc, batch_order(g))) return false;
     it.a2[phase] = f2;
     it.a2[1 - phase] = b2;
     total2 += f2.nblk;
     return true;
 }
-bool batch_two_args(tete_grid*, BatchItem<double>&, int, int&) { return false; }
 
 template <typename R>
 tete_status batch_build(tete_batch* b)
@@ -677,11 +684,11 @@ tete_status batch_build(tete_batch* b)
     BatchTable<R>* H = (BatchTable<R>*)b->host;
     memset(H, 0, sizeof(BatchTable<R>));
     H->phase = b->phase;
-    // two steps per launch for FP32 unless the single step was asked for, and
-    // only if every member's planes fit the two-step kernel
-    bool two = b->fp32 && b->kernel != TETE_KERNEL_FUSED;
+    // two steps per launch unless the single step was asked for, and only if
+    // every member's planes fit the two-step kernel
+    bool two = b->kernel != TETE_KERNEL_FUSED;
     for (int s = 0; s < TETE_MAX_BATCH && two; ++s)
-        if (b->slot[s] && !fused2_fits(b->slot[s]->geo)) two = false;
+        if (b->slot[s] && !fused2_fits(b->slot[s]->geo, b->fp32 ? 4 : 8)) two = false;
     if ((int)two != b->two) {
         batch_drop_graph(b);   // the captured block launches the other kernel
         b->two = two;
@@ -703,7 +710,7 @@ tete_status batch_build(tete_batch* b)
         H->item[i].a[1 - b->phase] = bwd;
         H->offset[i] = total;
         H->offset2[i] = total2;
-        if (two && !batch_two_args(g, H->item[i], b->phase, total2)) return TETE_ERR_ARG;
+        if (two && !batch_two_args<R>(g, H->item[i], b->phase, total2)) return TETE_ERR_ARG;
         H->step[i] = g->n;
         total += fwd.nblk;
         b->seen_n[s] = g->n;
@@ -731,7 +738,7 @@ tete_status batch_launch_block(tete_batch* b, int steps)
     int done = 0, flips = 0;
     if (b->two)
         for (; done + 2 <= steps; done += 2, ++flips)
-            HIPCHK(launch_batch_step2((BatchTable<float>*)T, b->grid, flips, done, b->gstream));
+            HIPCHK(launch_batch_step2<R>(T, b->grid, flips, done, b->gstream));
     for (; done < steps; ++done, ++flips)
         HIPCHK(launch_batch_step<R>(T, b->rows, b->depth, b->grid, flips, done, b->gstream));
     HIPCHK(launch_batch_advance<R>(T, steps, flips, b->gstream));
@@ -873,7 +880,6 @@ tete_status tete_batch_set_launch(tete_batch* b, int32_t kernel, int32_t rows, i
         graph_steps > 1024)
         return TETE_ERR_ARG;
     if (kernel != TETE_KERNEL_AUTO && kernel != TETE_KERNEL_FUSED && kernel != TETE_KERNEL_FUSED2) return TETE_ERR_ARG;
-    if (kernel == TETE_KERNEL_FUSED2 && !b->fp32) return TETE_ERR_ARG;
     b->kernel = kernel;
     b->rows = rows;
     b->depth = depth == 0 ? 1 : depth;

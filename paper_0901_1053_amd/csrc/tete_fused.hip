@@ -198,7 +198,12 @@ __device__ __forceinline__ void fused_tile(const FArgs<R>& A, const int ty, cons
         R ezh_m1 = EZm1 + a2 * kz1 * ((hxn_m1_jm - hxn_m1) - (hyn_m2 - hyn_m1));
         if (src_row && q1 == A.src.i0 && kin && k < g.nz) {
             const int64_t m = (int64_t)k - A.src.n + A.src.M;   // cell m crosses edge k in step n
-            if (m >= -A.src.M && m <= A.src.M) ezh_m1 -= (R)((double)kz1 * A.src.lam[m + A.src.M]);
+            if (m >= -A.src.M && m <= A.src.M) {
+                // the current term is rounded on its own (no fused multiply-add
+                // with the subtraction), as in the two-step kernel
+#pragma clang fp contract(off)
+                ezh_m1 -= (R)((double)kz1 * A.src.lam[m + A.src.M]);
+            }
             if (owned && q1 >= xs && q1 < xe) {
                 const int64_t js = A.src.n - k - A.src.M;      // wake sample of edge k
                 if (js >= A.src.jmin && js < (int64_t)A.src.jmin + A.src.nw)

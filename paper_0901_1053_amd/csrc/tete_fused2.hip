@@ -36,13 +36,13 @@
 // over from the neighbouring lane when stage B reaches the plane.
 
 #include <algorithm>
+#include <type_traits>
 
 #include "tete_dev.h"
 
 namespace tete {
 namespace {
 
-constexpr int KT2 = 60;   // k entries owned per workgroup: 64 lanes minus two halo lanes at each end
 
 // Carried pipeline state of one stage, named by plane lag behind the stage's
 // input plane q (m1 = q-1, ...), as in the single-step kernel.  The z
@@ -101,7 +101,10 @@ __device__ __forceinline__ Out<R> stage_plane(Stage<R>& S, const In<R>& c, const
     const R hyn_m1 = S.HYm1 + f.my1 * (-pzEXm1 + (c.ez - S.EZm1));
     // S3 at q-1: e_z^{n+1/2} = e_z^{n-1/2} + 2a kappa_z [P_y^T h_x^n - P_x^T h_y^n - j_z^n]
     R ezh_m1 = S.EZm1 + f.kz1 * ((nb.hxn1_jm - S.hxn_m1) - (S.hyn_m2 - hyn_m1));
-    ezh_m1 -= inj;
+    {
+#pragma clang fp contract(off)
+        ezh_m1 -= inj;
+    }
     // S4 at q-2: h_x^{n+1/2} = h_x^n + a mu_x [P_z e_y^n - P_y e_z^{n+1/2}]
     const R pzEYm2 = lane_next(S.EYm2) - S.EYm2;
     const R hxh_m2 = S.hxn_m2 + f.mx2 * (pzEYm2 - (nb.ezh2_jp - S.ezh_m2));
@@ -138,29 +141,50 @@ __device__ __forceinline__ Out<R> stage_plane(Stage<R>& S, const In<R>& c, const
     return o;
 }
 
-// LDS of one workgroup: per stage, six double-buffered j-exchange planes of
-// TYH + 2 rows ([quantity][plane parity][row][lane]); and stage B's delay
-// lines for e_z, h_x and h_y, two planes deep, one slot per thread
+// LDS of one workgroup: per stage, six j-exchange planes of TYH + 2 rows
+// ([quantity][buffer][row][lane]), double-buffered by plane parity (NB = 2)
+// or single (NB = 1, a second barrier per plane); and stage B's delay lines
+// for e_z, h_x and h_y, two planes deep, one slot per thread
 // ([quantity][plane parity][thread]), kept here to free registers.
-template <int TYH>
+template <typename R, int TYH, int NB, int LW>
 struct Lds2 {
-    float a[6][2][TYH + 2][64];
-    float b[6][2][TYH + 2][64];
-    float d[3][2][64 * TYH];
+    R a[6][NB][TYH + 2][LW];
+    R b[6][NB][TYH + 2][LW];
+    R d[3][2][LW * TYH];
 };
+
+// Launch shape of the two-step kernel per field type: rows of LW lanes
+// (entries along k; a wave holds 64 / LW rows), 16 rows owning 10, LW - 4
+// entries owned per row.  FP32: LW = 64, 1024 threads (16 waves, 128 VGPRs
+// each).  FP64: LW = 32, 512 threads (8 waves, 256 VGPRs each), since two
+// stages of doubles do not fit 128 registers; a row segment is then 256 bytes
+// as in FP32.  Both double-buffer the exchange planes (135 KB of LDS).
+template <typename R, int TYH, int LW>
+struct Shape2 {
+    static constexpr int rows = TYH, nb = 2, lw = LW, threads = TYH * LW;
+};
+// default rows and lanes per row of the two-step kernel, and the other
+// shape (FP32: 32 rows of 32 lanes, owning 26 x 28, selected by rows = 32)
+template <typename R> struct Default2;
+template <> struct Default2<float> { static constexpr int rows = 16, lw = 64; };
+template <> struct Default2<double> { static constexpr int rows = 16, lw = 32; };
+inline int lanes2(int real_bytes, int rows) { return real_bytes == 8 || rows == 32 ? 32 : 64; }
 
 // Two steps of one tile (ty, tz) and x-chunk cx.  Every thread of the
 // workgroup must call it (it contains barriers).
-template <int TYH, int PD>
-__device__ __forceinline__ void fused2_tile(const FArgs<float>& A, const int ty, const int tz, const int cx,
-                                            Lds2<TYH>& L)
+template <typename R, int TYH, int NB, int LW>
+__device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, const int tz, const int cx,
+                                            Lds2<R, TYH, NB, LW>& L)
 {
-    using R = float;
-    constexpr int TY = TYH - 6;
+    constexpr int PD = 1;         // planes prefetched: a second one does not fit the register budget
+    constexpr int TY = TYH - 6;   // rows owned
+    constexpr int KT2 = LW - 4;   // entries owned per row
+    // Lane shifts act on the whole wave; with two rows per wave (LW = 32) the
+    // shift across the row boundary only feeds halo lanes.
     const Geo g = A.g;
 
-    const int kl = threadIdx.x & 63;
-    const int jl = threadIdx.x >> 6;
+    const int kl = threadIdx.x % LW;
+    const int jl = threadIdx.x / LW;
     const int j = ty * TY - 3 + jl;
     const int k = tz * KT2 - 2 + kl;
     const bool jin = (unsigned)j <= (unsigned)g.ny;
@@ -179,7 +203,11 @@ __device__ __forceinline__ void fused2_tile(const FArgs<float>& A, const int ty,
     const int xload_end = min(xe + 3, g.nx);    // last plane whose old data is needed
 
     const R a2 = A.a + A.a;
-    const bool src_row = A.src.on && j == A.src.j0;    // uniform over a wave (one row)
+    const bool src_row = A.src.on && j == A.src.j0;
+    // the source row lies in this wave (uniform over the wave: lane shifts
+    // below run with every lane active)
+    const int wj0 = ty * TY - 3 + (int)(threadIdx.x / 64) * (64 / LW);
+    const bool src_wave = A.src.on && A.src.j0 >= wj0 && A.src.j0 < wj0 + 64 / LW;
     const bool src_k = kin && k < g.nz;                 // lane holds an e_z edge
 
     // Buffer resources over the chunk's planes, as in the single-step kernel:
@@ -247,7 +275,12 @@ __device__ __forceinline__ void fused2_tile(const FArgs<float>& A, const int ty,
     // v, or 0 where bit b of the code history is set (a PEC edge)
     auto sel = [](uint32_t hist, int b, R v) {
         const uint32_t m = (uint32_t)(((int32_t)(hist << (31 - b))) >> 31);
-        return __builtin_bit_cast(R, __builtin_bit_cast(uint32_t, v) & ~m);
+        if constexpr (sizeof(R) == 4) {
+            return __builtin_bit_cast(R, __builtin_bit_cast(uint32_t, v) & ~m);
+        } else {
+            const uint64_t m2 = ((uint64_t)m << 32) | m;
+            return __builtin_bit_cast(R, __builtin_bit_cast(uint64_t, v) & ~m2);
+        }
     };
     // coefficients of a stage whose input plane is q; hist holds the codes of
     // planes q-1 .. q-4 in bits 0-15.  h_x outside the grid's planes needs no
@@ -267,8 +300,10 @@ __device__ __forceinline__ void fused2_tile(const FArgs<float>& A, const int ty,
         f.kx4 = sel(hist, 12, akx);
         return f;
     };
-    // bunch current of step n on edge k (zero where no cell crosses it)
+    // bunch current of step n on edge k (zero where no cell crosses it),
+    // rounded on its own before it is subtracted
     auto inject = [&](int64_t n, R kz) {
+#pragma clang fp contract(off)
         const int64_t m = (int64_t)k - n + A.src.M;
         return (m >= -A.src.M && m <= A.src.M) ? (R)((double)kz * A.src.lam[m + A.src.M]) : R(0);
     };
@@ -293,28 +328,31 @@ __device__ __forceinline__ void fused2_tile(const FArgs<float>& A, const int ty,
 
         // j-exchange through LDS (row r of the tile is LDS row r+1; rows 0 and
         // TYH+1 are never written and reach only halo results)
-        L.a[0][s][jl + 1][kl] = cur.ez;
-        L.a[1][s][jl + 1][kl] = SA.hxn_m1;
-        L.a[2][s][jl + 1][kl] = SA.ezh_m2;
-        L.a[3][s][jl + 1][kl] = SA.HZm2;
-        L.a[4][s][jl + 1][kl] = SA.exh_m3;
-        L.a[5][s][jl + 1][kl] = SA.hzn_m4;
-        L.b[0][s][jl + 1][kl] = bEZ;
-        L.b[1][s][jl + 1][kl] = SB.hxn_m1;
-        L.b[2][s][jl + 1][kl] = SB.ezh_m2;
-        L.b[3][s][jl + 1][kl] = SB.HZm2;
-        L.b[4][s][jl + 1][kl] = SB.exh_m3;
-        L.b[5][s][jl + 1][kl] = SB.hzn_m4;
+        const int x = NB == 2 ? s : 0;   // exchange buffer
+        L.a[0][x][jl + 1][kl] = cur.ez;
+        L.a[1][x][jl + 1][kl] = SA.hxn_m1;
+        L.a[2][x][jl + 1][kl] = SA.ezh_m2;
+        L.a[3][x][jl + 1][kl] = SA.HZm2;
+        L.a[4][x][jl + 1][kl] = SA.exh_m3;
+        L.a[5][x][jl + 1][kl] = SA.hzn_m4;
+        L.b[0][x][jl + 1][kl] = bEZ;
+        L.b[1][x][jl + 1][kl] = SB.hxn_m1;
+        L.b[2][x][jl + 1][kl] = SB.ezh_m2;
+        L.b[3][x][jl + 1][kl] = SB.HZm2;
+        L.b[4][x][jl + 1][kl] = SB.exh_m3;
+        L.b[5][x][jl + 1][kl] = SB.hzn_m4;
         __syncthreads();
-        const Nb<R> nA = {L.a[0][s][jl + 2][kl], L.a[1][s][jl][kl], L.a[2][s][jl + 2][kl],
-                          L.a[3][s][jl][kl],     L.a[4][s][jl + 2][kl], L.a[5][s][jl][kl]};
-        const Nb<R> nB = {L.b[0][s][jl + 2][kl], L.b[1][s][jl][kl], L.b[2][s][jl + 2][kl],
-                          L.b[3][s][jl][kl],     L.b[4][s][jl + 2][kl], L.b[5][s][jl][kl]};
+        const Nb<R> nA = {L.a[0][x][jl + 2][kl], L.a[1][x][jl][kl], L.a[2][x][jl + 2][kl],
+                          L.a[3][x][jl][kl],     L.a[4][x][jl + 2][kl], L.a[5][x][jl][kl]};
+        const Nb<R> nB = {L.b[0][x][jl + 2][kl], L.b[1][x][jl][kl], L.b[2][x][jl + 2][kl],
+                          L.b[3][x][jl][kl],     L.b[4][x][jl + 2][kl], L.b[5][x][jl][kl]};
+        if (NB == 1) __syncthreads();    // all reads done before the next plane's writes
 
         const Co<R> fA = coef(p, ch), fB = coef(p - 4, ch >> 16);
         // S3 of stage A is at plane p-1 (step n), of stage B at plane p-5 (step n+1)
         const bool srcA = src_row && p - 1 == A.src.i0;
         const bool srcB = src_row && p - 5 == A.src.i0;
+        const bool srcBw = LW == 64 ? srcB : src_wave && p - 5 == A.src.i0;   // wave-uniform
         const R injA = (srcA && src_k) ? inject(A.src.n, sel(ch, 2, A.kz)) : R(0);
         const R injB = (srcB && src_k) ? inject(A.src.n + 1, sel(ch, 18, A.kz)) : R(0);
 
@@ -322,9 +360,10 @@ __device__ __forceinline__ void fused2_tile(const FArgs<float>& A, const int ty,
         const Out<R> oB = stage_plane(SB, In<R>{oA.ex14, bEY, bEZ, bHX, bHY, bHZ}, nB, fB, injB);
 
         if (srcA) ezA = oA.ezold1;
-        if (srcB) {   // wave-uniform: every lane takes part in the lane shifts
+        // wave-uniform (one row per wave: srcB itself)
+        if (srcBw) {
             const R ezA_km = lane_prev(ezA), ezB_km = lane_prev(oB.ezold1);
-            if (owned && A.src.i0 >= xs && A.src.i0 < xe) {
+            if ((LW == 64 || src_row) && owned && A.src.i0 >= xs && A.src.i0 < xe) {
                 const int64_t js = A.src.n + 1 - k - A.src.M;   // edge k at step n+1, edge k-1 at step n
                 if (js >= A.src.jmin && js < (int64_t)A.src.jmin + A.src.nw) {
                     double w = A.src.wacc[js - A.src.jmin];
@@ -364,28 +403,31 @@ __device__ __forceinline__ void fused2_tile(const FArgs<float>& A, const int ty,
     }
 }
 
-template <int TYH, int PD>
-__global__ __launch_bounds__(64 * TYH) void k_fused2(FArgs<float> A)
+template <typename R, int TYH, int LW>
+__global__ __launch_bounds__(TYH * LW) void k_fused2(FArgs<R> A)
 {
-    __shared__ Lds2<TYH> L;
+    typedef Shape2<R, TYH, LW> S;
+    __shared__ Lds2<R, S::rows, S::nb, S::lw> L;
     int ty, tz, cx;
     if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) return;   // whole group
-    fused2_tile<TYH, PD>(A, ty, tz, cx, L);
+    fused2_tile<R, S::rows, S::nb, S::lw>(A, ty, tz, cx, L);
 }
 
-// Two steps of every active instance of an FP32 batch, by a persistent grid,
-// as the single-step batch kernel does it: work item w (instance, tile,
-// x-chunk) is taken by workgroup w mod gridDim.x in round w / gridDim.x,
-// remapped over the XCDs within a round; the launch follows `flips` launches
-// and `steps` steps of the current block.
-template <int TYH>
-__global__ __launch_bounds__(64 * TYH) void k_fused2_batch(const BatchTable<float>* Tg, int flips, int steps)
+// Two steps of every active instance of a batch, by a persistent grid, as the
+// single-step batch kernel does it: work item w (instance, tile, x-chunk) is
+// taken by workgroup w mod gridDim.x in round w / gridDim.x, remapped over
+// the XCDs within a round; the launch follows `flips` launches and `steps`
+// steps of the current block.
+template <typename R>
+__global__ __launch_bounds__(Default2<R>::rows * Default2<R>::lw) void k_fused2_batch(const BatchTable<R>* Tg,
+                                                                                     int flips, int steps)
 {
-    __shared__ Lds2<TYH> L;
+    typedef Shape2<R, Default2<R>::rows, Default2<R>::lw> S;
+    __shared__ Lds2<R, S::rows, S::nb, S::lw> L;
     // The table is read-only during the launch: reading it through the
     // constant address space makes its (uniform) fields scalar loads into
     // scalar registers instead of vector loads that would occupy VGPRs.
-    typedef const __attribute__((address_space(4))) BatchTable<float>* CTable;
+    typedef const __attribute__((address_space(4))) BatchTable<R>* CTable;
     typedef const __attribute__((address_space(4))) uint32_t* CWords;
     const CTable T = (CTable)Tg;
     const int total = T->total2;
@@ -403,38 +445,41 @@ __global__ __launch_bounds__(64 * TYH) void k_fused2_batch(const BatchTable<floa
             else hi = mid - 1;
         }
         const int inst = __builtin_amdgcn_readfirstlane(lo);
-        FArgs<float> A;
+        FArgs<R> A;
         {
             const CWords src = (CWords)&T->item[inst].a2[parity];
             uint32_t* dst = (uint32_t*)&A;
 #pragma unroll
-            for (int i = 0; i < (int)(sizeof(FArgs<float>) / 4); ++i) dst[i] = src[i];
+            for (int i = 0; i < (int)(sizeof(FArgs<R>) / 4); ++i) dst[i] = src[i];
         }
         A.src.n = T->step[inst] + steps;
         int ty, tz, cx;
-        if (tile_of(w - T->offset2[inst], A.order, A.nyt, A.nzt, ty, tz, cx)) fused2_tile<TYH, 1>(A, ty, tz, cx, L);
+        if (tile_of(w - T->offset2[inst], A.order, A.nyt, A.nzt, ty, tz, cx))
+            fused2_tile<R, S::rows, S::nb, S::lw>(A, ty, tz, cx, L);
         __syncthreads();   // the LDS is reused by the next item
     }
 }
 
-constexpr int ROWS2 = 16;
-
 }  // namespace
 
-hipError_t launch_batch_step2(BatchTable<float>* T, int grid, int flips, int steps, hipStream_t s)
+template <typename R>
+hipError_t launch_batch_step2(BatchTable<R>* T, int grid, int flips, int steps, hipStream_t s)
 {
-    k_fused2_batch<ROWS2><<<grid, 64 * ROWS2, 0, s>>>(T, flips, steps);
+    k_fused2_batch<R><<<grid, Default2<R>::rows * Default2<R>::lw, 0, s>>>(T, flips, steps);
     return hipGetLastError();
 }
 
-bool fused2_setup(FArgs<float>& A, int xchunk, int order)
+template <typename R>
+bool fused2_setup(FArgs<R>& A, int rows, int xchunk, int order)
 {
-    constexpr int TY = ROWS2 - 6;
+    if (rows == 0) rows = Default2<R>::rows;
+    if (rows != 16 && !(rows == 32 && sizeof(R) == 4)) return false;
+    const int TY = rows - 6, KT2 = lanes2(sizeof(R), rows) - 4;
     A.nyt = (A.g.ny + 1 + TY - 1) / TY;
     A.nzt = (A.g.nz + 1 + KT2 - 1) / KT2;
     const int nplanes = A.g.nx + 1;
     // every buffer range must stay below 2^31 bytes: (xchunk + 8) planes
-    const int64_t plane_bytes = (int64_t)A.g.sp * sizeof(float);
+    const int64_t plane_bytes = (int64_t)A.g.sp * sizeof(R);
     const int64_t xmax = ((int64_t(1) << 31) - 1) / plane_bytes - 8;
     if (xmax < 1) return false;
     int xc = xchunk;
@@ -456,24 +501,39 @@ bool fused2_setup(FArgs<float>& A, int xchunk, int order)
     return true;
 }
 
-bool fused2_fits(Geo g)
+bool fused2_fits(Geo g, int real_bytes)
 {
-    return (int64_t)g.sp * (int64_t)sizeof(float) * 9 < (int64_t(1) << 31);
+    return (int64_t)g.sp * real_bytes * 9 < (int64_t(1) << 31);
 }
 
-hipError_t launch_step_fused2(Fields<float> o, Fields<float> nf, Mat<float> M, Geo g, float alpha, Src src,
-                              int xchunk, int depth, int order, hipStream_t s, hipEvent_t* ev)
+template <typename R>
+hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha, Src src, int rows, int xchunk,
+                              int order, hipStream_t s, hipEvent_t* ev)
 {
-    FArgs<float> A = fused_args<float>(o, nf, M, g, alpha, src);
-    if (!fused2_setup(A, xchunk, order)) return hipErrorInvalidValue;
+    FArgs<R> A = fused_args<R>(o, nf, M, g, alpha, src);
+    if (!fused2_setup<R>(A, rows, xchunk, order)) return hipErrorInvalidValue;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
-    (void)depth;   // one plane prefetched: a deeper prefetch does not fit the register budget
-    k_fused2<ROWS2, 1><<<A.nblk, 64 * ROWS2, 0, s>>>(A);
+    bool done = false;
+    if constexpr (sizeof(R) == 4) {
+        if (rows == 32) {
+            k_fused2<R, 32, 32><<<A.nblk, 32 * 32, 0, s>>>(A);
+            done = true;
+        }
+    }
+    if (!done) k_fused2<R, Default2<R>::rows, Default2<R>::lw><<<A.nblk, Default2<R>::rows * Default2<R>::lw, 0, s>>>(A);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     return hipSuccess;
 }
+
+#define TETE_FUSED2_INST(R)                                                                                    \
+    template hipError_t launch_batch_step2<R>(BatchTable<R>*, int, int, int, hipStream_t);                     \
+    template bool fused2_setup<R>(FArgs<R>&, int, int, int);                                                   \
+    template hipError_t launch_step_fused2<R>(Fields<R>, Fields<R>, Mat<R>, Geo, R, Src, int, int, int,         \
+                                              hipStream_t, hipEvent_t*);
+TETE_FUSED2_INST(float)
+TETE_FUSED2_INST(double)
 
 }  // namespace tete

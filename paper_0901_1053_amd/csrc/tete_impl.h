@@ -122,19 +122,23 @@ FArgs<R> fused_args(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, 
 template <typename R>
 bool fused_setup(FArgs<R>& A, int rows, int xchunk, int order);
 int fused_default_rows(int real_bytes);
-// Two steps in one launch (tete_fused2.hip, FP32 fields): the fused step
-// temporally blocked; xchunk, depth (1 or 2) and order as for the single step.
-bool fused2_fits(Geo g);
-bool fused2_setup(FArgs<float>& A, int xchunk, int order);
-hipError_t launch_step_fused2(Fields<float> oldf, Fields<float> newf, Mat<float> mat, Geo g, float alpha, Src src,
-                              int xchunk, int depth, int order, hipStream_t s, hipEvent_t* ev);
+// Two steps in one launch (tete_fused2.hip): the fused step temporally
+// blocked; xchunk and order as for the single step.
+bool fused2_fits(Geo g, int real_bytes);
+// rows: 0 (default), 16, or 32 (FP32 only: 32 rows of 32 lanes).
+template <typename R>
+bool fused2_setup(FArgs<R>& A, int rows, int xchunk, int order);
+template <typename R>
+hipError_t launch_step_fused2(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src, int rows,
+                              int xchunk, int order, hipStream_t s, hipEvent_t* ev);
 // One step of every instance of a batch (persistent grid of `grid`
 // workgroups), the launch after `flips` earlier launches and `steps` earlier
 // steps of the current block
 template <typename R>
 hipError_t launch_batch_step(BatchTable<R>* T, int rows, int depth, int grid, int flips, int steps, hipStream_t s);
-// Two steps of every instance of an FP32 batch (tete_fused2.hip)
-hipError_t launch_batch_step2(BatchTable<float>* T, int grid, int flips, int steps, hipStream_t s);
+// Two steps of every instance of a batch (tete_fused2.hip)
+template <typename R>
+hipError_t launch_batch_step2(BatchTable<R>* T, int grid, int flips, int steps, hipStream_t s);
 // After a block: step indices += steps, phase += flips (launches)
 template <typename R>
 hipError_t launch_batch_advance(BatchTable<R>* T, int steps, int flips, hipStream_t s);

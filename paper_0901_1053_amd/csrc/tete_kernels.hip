@@ -247,7 +247,11 @@ __global__ __launch_bounds__(TB) void k_tm(Fields<R> o, Fields<R> nf, Mat<R> M, 
         R v = ez[id] + a2 * kp * ((hxn(ii, jj - 1) - hxn(ii, jj)) - (hyn(ii - 1, jj) - hyn(ii, jj)));
         if (src.on && ii == src.i0 && jj == src.j0) {
             int64_t m = (int64_t)k - src.n + src.M;       // charge of cell m crosses edge k in step n
-            if (m >= -src.M && m <= src.M) v -= (R)((double)kp * src.lam[m + src.M]);
+            if (m >= -src.M && m <= src.M) {
+                // the current term is rounded on its own, as in the fused kernels
+#pragma clang fp contract(off)
+                v -= (R)((double)kp * src.lam[m + src.M]);
+            }
         }
         return v;
     };

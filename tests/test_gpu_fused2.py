@@ -111,13 +111,56 @@ def test_timing_counts_steps():
     assert n == 7 and ms > 0
 
 
-def test_fp64_and_materials_fall_back():
-    G = _grid((8, 8, 40), 5, "fused", precision="fp64")
-    with pytest.raises(tete.TeteError):
-        G.set_tuning("fused2")
+def test_materials_fall_back():
     G = tete.Grid(8, 8, 40, 2.0e-3, 1.7e-3, 1.0e-3, 0.9e-3, precision="fp32", materials=True)
     G.set_tuning("fused2")
     assert G.get_tuning()["kernel"] == "fused2"
     rng = np.random.default_rng(0)
     G.set_materials({k: rng.uniform(0.5, 1.0, G.shape) for k in tete.KEYS})
     assert G.get_tuning()["kernel"] == "split"
+
+
+@pytest.mark.parametrize("shape", [(13, 11, 37), (40, 29, 130), (2, 2, 2), (9, 20, 1000)])
+def test_fp64_two_steps_equal_single_steps(shape):
+    """FP64 two-step kernel (two rows per wave): bitwise the single steps."""
+    def run(kernel, steps):
+        G = _grid(shape, 41, kernel, precision="fp64")
+        G.step(steps)
+        return G.get_fields()
+    for steps in (2, 25):
+        _same(run("fused2", steps), run("fused", steps))
+
+
+@pytest.mark.parametrize("nt,nz,xchunk", [(24, 150, 0), (32, 200, 3)])
+def test_fp64_wake_identical_and_oracle(nt, nz, xchunk):
+    case = inputs.scaled_wake_case(nt, nz, seed=nt + nz + 1, sigma_dz=3.0)
+    M = case.M
+    jmin, nw = -M - 3, 2 * M + 40
+    steps = case.nz + M + jmin + nw
+    a = _wake_run(case, "fused2", steps, jmin, nw, precision="fp64", xchunk=xchunk)
+    b = _wake_run(case, "fused", steps, jmin, nw, precision="fp64")
+    assert np.array_equal(a.wake(), b.wake())
+    _same(a.get_fields(), b.get_fields())
+    ref = P.oracle_wake(case, steps, jmin=jmin, nw=nw)
+    assert P.delta_norm(a.wake(), ref["W"]) <= 1e-12
+
+
+@pytest.mark.parametrize("xchunk", [0, 3])
+def test_fp32_32_row_shape(xchunk):
+    """The 32-row, 32-lane FP32 shape gives the single-step results bitwise."""
+    shape = (20, 70, 300)
+    G = _grid(shape, 51, "fused2")
+    G.set_tuning("fused2", 32, xchunk, 0, 0)
+    G.step(13)
+    _same(G.get_fields(), _fields(shape, 51, "fused", 13))
+    case = inputs.scaled_wake_case(32, 200, seed=77, sigma_dz=3.0)
+    M = case.M
+    jmin, nw = -M - 3, 2 * M + 40
+    steps = case.nz + M + jmin + nw
+    a = P.gpu_grid(case, "fp32")
+    a.set_tuning("fused2", 32, xchunk, 0, 0)
+    a.set_bunch(case.Q, case.sigma, case.i0, case.j0, M, jmin, nw)
+    a.step(steps)
+    b = _wake_run(case, "fused", steps, jmin, nw)
+    assert np.array_equal(a.wake(), b.wake())
+    _same(a.get_fields(), b.get_fields())
