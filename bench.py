@@ -25,8 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
-def traffic_file(kernel_name):
-    return os.path.join(ROOT, "profiles", kernel_name + "_traffic.json")
+def traffic_file(kernel_name, precision):
+    return os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (kernel_name, precision))
 
 
 def measured_traffic(kernel_name, workload, precision):
@@ -34,7 +34,7 @@ def measured_traffic(kernel_name, workload, precision):
     were taken on the current source of the kernel; else None."""
     import hashlib
     try:
-        with open(traffic_file(kernel_name)) as fh:
+        with open(traffic_file(kernel_name, precision)) as fh:
             t = json.load(fh)
         with open(os.path.join(ROOT, t["source"]), "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()
