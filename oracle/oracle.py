@@ -58,6 +58,10 @@ def lib():
         L.orc_apply_pec.argtypes = [C.POINTER(_Geom), P6, P6]
         L.orc_step.argtypes = [C.POINTER(_Geom), P6, P6, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_energy.argtypes = [C.POINTER(_Geom), P6, P6]
+        L.orc_step_yee.argtypes = [C.POINTER(_Geom), P6, P6, C.c_void_p]
+        L.orc_yee_invariant.argtypes = [C.POINTER(_Geom), P6, P6, P6]
+        L.orc_yee_invariant.restype = C.c_double
+        L.orc_yee_charge.argtypes = [C.POINTER(_Geom), P6, P6, C.c_void_p]
         L.orc_energy.restype = C.c_double
         L.orc_charges.argtypes = [C.POINTER(_Geom), P6, P6, P6, C.c_void_p, C.c_void_p]
         L.orc_bunch_cells.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_void_p]
@@ -125,6 +129,26 @@ def step(g: Geom, m: dict, f: dict, jx=None, jy=None, jz=None) -> None:
         assert a.shape == g.shape and a.dtype == np.float64 and a.flags.c_contiguous
         return a.ctypes.data
     lib().orc_step(C.byref(g._c()), _p6(m), _p6(f), p(jx), p(jy), p(jz))
+
+
+def step_yee(g: Geom, m: dict, f: dict, jz=None) -> None:
+    """One step of Yee's scheme (7) in place: state (e^{n-1/2}, h^n)."""
+    if jz is not None:
+        assert jz.shape == g.shape and jz.dtype == np.float64 and jz.flags.c_contiguous
+    lib().orc_step_yee(C.byref(g._c()), _p6(m), _p6(f), None if jz is None else jz.ctypes.data)
+
+
+def yee_invariant(g: Geom, m: dict, f_old: dict, f_new: dict) -> float:
+    """Half the leapfrog invariant <e^{n+1/2}, e^{n-1/2}> + |h^n|^2 of Yee's
+    scheme, from the state before (f_old) and after (f_new) one step."""
+    return lib().orc_yee_invariant(C.byref(g._c()), _p6(m), _p6(f_old), _p6(f_new))
+
+
+def yee_charge(g: Geom, m: dict, f: dict) -> np.ndarray:
+    """Node charges (dual divergence of e / kappa) of a Yee state."""
+    q = np.zeros(g.shape)
+    lib().orc_yee_charge(C.byref(g._c()), _p6(m), _p6(f), q.ctypes.data)
+    return q
 
 
 def energy(g: Geom, m: dict, f: dict) -> float:

@@ -20,7 +20,9 @@
  *   - a rigid Gaussian bunch moving at v = c on a node line, with its current
  *     injected so that the charge moves one cell per step at dtau = dz (Fig. 1);
  *   - the longitudinal wake potential W_par(s) of Sec. 5 by the grid quadrature
- *     of the time-staggered e_z on the bunch line.
+ *     of the time-staggered e_z on the bunch line;
+ *   - for comparison, one step of Yee's E/M scheme (7) of Sec. 3, its leapfrog
+ *     invariant and its node charges (dual divergence).
  *
  * Readings of the paper used here (the text is ambiguous or garbled at these
  * places; each reading is pinned by a CPU test):
@@ -466,4 +468,85 @@ int orc_run(const orc_geom* g, double* const m[6], double* f[6], int n0, int nst
     free(jz);
     free(ezo);
     return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Yee's E/M scheme (7), the baseline the paper compares against (Sec. 3):
+ *   e^{n+1/2} = e^{n-1/2} + dtau C_0^* h^n - dtau j^n,
+ *   h^{n+1}   = h^n - dtau C_0 e^{n+1/2},
+ * in FIT variables: every e component is updated from h^n first, then every h
+ * component from e^{n+1/2}; stable in vacuum for dtau up to (8).  The state
+ * holds (e^{n-1/2}, h^n).  jz (or NULL) is j_z^n per e_z edge as current
+ * through the dual facet, as for orc_step.
+ * ------------------------------------------------------------------------- */
+void orc_step_yee(const orc_geom* g, double* const m[6], double* f[6], const double* jz)
+{
+    const double dt = g->cdt;
+    upd_ex(g, m, f, dt, NULL);          /* e_x^{n+1/2} */
+    upd_ey(g, m, f, dt, NULL);          /* e_y^{n+1/2} */
+    upd_ez(g, m, f, dt, jz);            /* e_z^{n+1/2} */
+    /* h^{n+1} = h^n - dtau mu C e^{n+1/2}: the h sub-updates with factor dtau */
+    upd_hx(g, m, f, dt);
+    upd_hy(g, m, f, dt);
+    upd_hz(g, m, f, dt);
+}
+
+/*
+ * Leapfrog invariant of Yee's scheme with j = 0 (exactly conserved: the change
+ * from n to n+1 is dtau (<e, C_0^* H> - <C_0 e, H>) = 0 with H = h^n + h^{n+1}):
+ *   I^n = <e^{n+1/2}, e^{n-1/2}> + |h^n|^2  (scaled variables), i.e. in FIT
+ *   variables sum_{kappa>0} e^{n+1/2} e^{n-1/2} / kappa + sum h^2 / mu.
+ * Inputs: fo = (e^{n-1/2}, h^n) and fn = the state after the step (its e part
+ * is e^{n+1/2}).  Returns I^n / 2 (an energy).
+ */
+double orc_yee_invariant(const orc_geom* g, double* const m[6], double* fo[6], double* fn[6])
+{
+    double s = 0.0;
+    for (int c = EX; c <= EZ; ++c)
+        LOOP(g, c) {
+            double kap = m[c][idx(g, i, j, k)];
+            if (kap > 0.0) s += fo[c][idx(g, i, j, k)] * fn[c][idx(g, i, j, k)] / kap;
+        }
+    for (int c = HX; c <= HZ; ++c)
+        LOOP(g, c) {
+            double mu = m[c][idx(g, i, j, k)];
+            if (mu > 0.0) s += fo[c][idx(g, i, j, k)] * fo[c][idx(g, i, j, k)] / mu;
+        }
+    return 0.5 * s;
+}
+
+/*
+ * Discrete Gauss law of Yee's scheme: with j = 0 the dual divergence of the
+ * flux d = e / kappa is constant in time, because the dual divergence of
+ * C^T h vanishes identically.  Writes, for every node (i,j,k), the value
+ *   -[P_x^T d_x + P_y^T d_y + P_z^T d_z](i,j,k)
+ *   = d_x(i,j,k) - d_x(i-1,j,k) + d_y(i,j,k) - d_y(i,j-1,k) + d_z(i,j,k) - d_z(i,j,k-1)
+ * into q (index as the field arrays); PEC edges carry no flux.
+ */
+void orc_yee_charge(const orc_geom* g, double* const m[6], double* f[6], double* q)
+{
+    memset(q, 0, sizeof(double) * (size_t)(g->nx + 1) * (g->ny + 1) * (g->nz + 1));
+    for (int i = 0; i <= g->nx; ++i)
+        for (int j = 0; j <= g->ny; ++j)
+            for (int k = 0; k <= g->nz; ++k) {
+                double s = 0.0;
+                const int di[3] = {1, 0, 0}, dj[3] = {0, 1, 0}, dk[3] = {0, 0, 1};
+                for (int c = EX; c <= EZ; ++c) {
+                    /* outgoing edge from this node, incoming edge from the previous node */
+                    int io = i, jo = j, ko = k, ii = i - di[c], ji = j - dj[c], ki = k - dk[c];
+                    if (g->periodic_xy) {
+                        ii = ((ii % g->nx) + g->nx) % g->nx;
+                        ji = ((ji % g->ny) + g->ny) % g->ny;
+                    }
+                    if (in_range(g, c, io, jo, ko)) {
+                        double kap = m[c][idx(g, io, jo, ko)];
+                        if (kap > 0.0) s += f[c][idx(g, io, jo, ko)] / kap;
+                    }
+                    if (in_range(g, c, ii, ji, ki)) {
+                        double kap = m[c][idx(g, ii, ji, ki)];
+                        if (kap > 0.0) s -= f[c][idx(g, ii, ji, ki)] / kap;
+                    }
+                }
+                q[idx(g, i, j, k)] = s;
+            }
 }

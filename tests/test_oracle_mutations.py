@@ -15,6 +15,7 @@ import pytest
 from tests import test_oracle_dense as TD
 from tests import test_oracle_dispersion as TP
 from tests import test_oracle_invariants as TI
+from tests import test_oracle_yee as TY
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(os.path.dirname(HERE), "oracle", "tete_oracle.c")
@@ -60,6 +61,25 @@ MUTANTS = {
     "pec_rule": ("cell_is_pec(g, cell_pec, i, j - 1, k) || cell_is_pec(g, cell_pec, i, j, k);\n        m[EX]",
                  "cell_is_pec(g, cell_pec, i, j, k);\n        m[EX]",
                  [lambda o: TI.test_staircase_pec_edges_are_cell_edges(o)]),
+    # Yee: half the time step in the updates
+    "yee_half_step": ("    const double dt = g->cdt;\n    upd_ex(g, m, f, dt, NULL);",
+                      "    const double dt = 0.5 * g->cdt;\n    upd_ex(g, m, f, dt, NULL);",
+                      [lambda o: TY.test_yee_eigenvalues_follow_9(o),
+                       lambda o: TY.test_yee_transversely_uniform_pulse(o)]),
+    # Yee: h updated before e (the order of (7) reversed)
+    "yee_h_first": ("    upd_ex(g, m, f, dt, NULL);          /* e_x^{n+1/2} */\n"
+                    "    upd_ey(g, m, f, dt, NULL);          /* e_y^{n+1/2} */\n"
+                    "    upd_ez(g, m, f, dt, jz);            /* e_z^{n+1/2} */\n",
+                    "    upd_hx(g, m, f, dt);\n    upd_hy(g, m, f, dt);\n    upd_hz(g, m, f, dt);\n"
+                    "    upd_ex(g, m, f, dt, NULL);          /* e_x^{n+1/2} */\n"
+                    "    upd_ey(g, m, f, dt, NULL);          /* e_y^{n+1/2} */\n"
+                    "    upd_ez(g, m, f, dt, jz);            /* e_z^{n+1/2} */\n    return;\n",
+                    [lambda o: TY.test_yee_transversely_uniform_pulse(o),
+                     lambda o: TY.test_yee_leapfrog_invariant_conserved(o)]),
+    # Yee invariant with |e^{n+1/2}|^2 instead of the cross product
+    "yee_invariant_square": ("if (kap > 0.0) s += fo[c][idx(g, i, j, k)] * fn[c][idx(g, i, j, k)] / kap;",
+                             "if (kap > 0.0) s += fn[c][idx(g, i, j, k)] * fn[c][idx(g, i, j, k)] / kap;",
+                             [lambda o: TY.test_yee_leapfrog_invariant_conserved(o)]),
 }
 
 
