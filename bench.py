@@ -110,7 +110,7 @@ def batched_section(count):
             "autotuned_shapes": shapes}
 
 
-def serve_section(rates, count):
+def serve_section(rates, count, max_cells=None):
     """Poisson streams of serving-workload requests: FP32 continuous batching
     (p50/p99 latency, arrival to wake on host) at each rate, against FP64
     one-at-a-time FIFO serving of the same stream.  The one-at-a-time server
@@ -126,14 +126,14 @@ def serve_section(rates, count):
     ex64 = serve.GpuExecutor("fp64", batch=False)
     svc64, w64 = serve.solve_alone(ex64, cases)
     ex64.close()
-    res = {"workload": "%d requests, 64^2x256 .. 256^2x2048" % count,
+    res = {"workload": "%d requests, 64^2x256 .. 256^2x2048" % count, "max_cells_in_flight": max_cells,
            "fp64_one_at_a_time": "FIFO over each request's measured FP64 solve time alone "
                                  "(%.2f s for all %d)" % (sum(svc64), count),
            "rates": {}}
     for rate in rates:
         reqs = serve.make_requests(cases, rate, seed=int(rate * 1000) + 7)
         ex = serve.GpuExecutor("fp32", batch=True, graph_steps=8, tuner=tuner)
-        st = serve.Server(ex, block_steps=128).run(reqs)
+        st = serve.Server(ex, block_steps=128, max_cells=max_cells).run(reqs)
         ex.close()
         st64 = serve.one_at_a_time_stats([r.arrival for r in reqs], svc64)
         delta = max(float(np.max(np.abs(r.wake - w64[r.rid])) / (np.max(w64[r.rid]) - np.min(w64[r.rid])))
@@ -147,6 +147,44 @@ def serve_section(rates, count):
         print("# serve rate %g done" % rate, file=sys.stderr, flush=True)
     res["tolerance"] = 1e-5
     return res
+
+
+def _ms_per_step(G, steps):
+    G.step(2)
+    G.set_timing(steps)
+    G.step(steps)
+    ms, _, n = G.timing()
+    G.set_timing(0)
+    return ms / n
+
+
+def yee_section(G, case, precision, steps=20):
+    """The paper's cost comparison, measured: kernel time per step of the
+    single-step and two-step TE/TM kernels (dtau = dz) and of Yee's scheme (7)
+    at its stability limit (8) on the same grid and geometry, and the time to
+    reach the same physical time tau (steps scale as 1 / dtau)."""
+    from paper_0901_1053_amd import tete
+    tuning = G.get_tuning()
+    G.set_tuning("fused2")
+    t2 = _ms_per_step(G, steps)
+    G.set_tuning("fused")
+    t1 = _ms_per_step(G, steps)
+    G.set_tuning(tuning["kernel"] if tuning["kernel"] != "yee" else "auto", tuning["rows"], tuning["xchunk"],
+                 tuning["depth"], tuning["order"])
+    dt_yee = (case.dx ** -2 + case.dy ** -2 + case.dz ** -2) ** -0.5
+    Y = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, dt_yee, precision=precision, yee=True)
+    Y.set_pec_cells(case.cell_mask())
+    ty = _ms_per_step(Y, steps)
+    Y.close()
+    del Y
+    r = dt_yee / case.cdt
+    return {"workload": case.name, "precision": precision,
+            "dtau_over_dz": {"te_tm": round(case.cdt / case.dz, 4), "yee_limit_8": round(dt_yee / case.dz, 4)},
+            "ms_per_step": {"te_tm_two_step": round(t2, 4), "te_tm_single_step": round(t1, 4), "yee": round(ty, 4)},
+            "time_to_same_tau_vs_yee": {"te_tm_two_step": round(t2 * r / ty, 3),
+                                        "te_tm_single_step": round(t1 * r / ty, 3)},
+            "paper": {"cost_per_step_vs_yee": round(10 / 6, 3),
+                      "run_time_vs_yee_at_dx_sqrt2_dz": round((10 / 6) / 2 ** 0.5, 3)}}
 
 
 def main():
@@ -164,9 +202,12 @@ def main():
     ap.add_argument("--order", type=int, default=0, help="fused kernels: tile order (1..6; 0: library default)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-yee", action="store_true", help="skip the comparison with Yee's scheme")
     ap.add_argument("--batched-count", type=int, default=64)
     ap.add_argument("--serve-rates", default="1,20,200", help="comma-separated request rates (req/s)")
     ap.add_argument("--serve-requests", type=int, default=12)
+    ap.add_argument("--serve-max-cells", type=float, default=2 ** 28,
+                    help="serving: grid cells in flight at most (0: no limit)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of this many GiB, 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -264,6 +305,9 @@ def main():
                           "run_time_vs_yee_at_dx_sqrt2_dz": round((10 / 6) / 2 ** 0.5, 3),
                           "hardware": "not stated in the paper", "timings": "none reported"},
     }
+    if not args.no_yee:
+        out["yee_context"] = yee_section(G, case, args.precision)
+        print("# yee comparison done", file=sys.stderr, flush=True)
     del G
     torch.cuda.empty_cache()
 
@@ -295,7 +339,8 @@ def main():
         out["batched"] = batched_section(args.batched_count)
         print("# batched done", file=sys.stderr, flush=True)
     if not args.no_serve:
-        out["serve"] = serve_section([float(r) for r in args.serve_rates.split(",")], args.serve_requests)
+        out["serve"] = serve_section([float(r) for r in args.serve_rates.split(",")], args.serve_requests,
+                                     int(args.serve_max_cells) or None)
         print("# serve done", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:

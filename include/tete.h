@@ -65,7 +65,14 @@ enum { TETE_FP64 = 0, TETE_FP32 = 1 };
 
 /* desc.flags */
 enum {
-    TETE_F_MATERIALS = 1u << 0  /* reserve per-entry material arrays (tete_set_materials) */
+    TETE_F_MATERIALS = 1u << 0, /* reserve per-entry material arrays (tete_set_materials) */
+    TETE_F_YEE = 1u << 1        /* step with Yee's E/M scheme (7) instead of (23): a
+                                 * baseline for comparison.  State (e^{n-1/2}, h^n);
+                                 * stability bound (8); vacuum with staircase PEC only
+                                 * (not with TETE_F_MATERIALS); no bunch (its current
+                                 * needs cdt = dz, which (8) excludes), no energy,
+                                 * energy series or charges (TETE_ERR_STATE); probes
+                                 * record e_z^{n+1/2}. */
 };
 
 /* Capacities of the small per-grid tables held in the workspace. */
@@ -87,7 +94,8 @@ typedef struct {
 } tete_grid_desc;
 
 /* Stability and size check of a descriptor (host only, no device access).
- * Returns TETE_OK, TETE_ERR_ARG or TETE_ERR_UNSTABLE (bound (25), Sec. 4.4). */
+ * Returns TETE_OK, TETE_ERR_ARG or TETE_ERR_UNSTABLE (bound (25), Sec. 4.4;
+ * with TETE_F_YEE bound (8), Sec. 3). */
 tete_status tete_check_desc(const tete_grid_desc* desc);
 
 /* Bytes of device workspace a grid with this descriptor needs (0 if the
@@ -223,7 +231,8 @@ tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h);
  * launch at least 2048 workgroups, else 2 (batches: 2).  tete_set_materials
  * turns a forced FUSED or FUSED2 back into AUTO.  tete_get_tuning reports the kernel
  * that tete_step will use (FUSED2, FUSED or SPLIT). */
-enum { TETE_KERNEL_AUTO = 0, TETE_KERNEL_FUSED = 1, TETE_KERNEL_SPLIT = 2, TETE_KERNEL_FUSED2 = 3 };
+enum { TETE_KERNEL_AUTO = 0, TETE_KERNEL_FUSED = 1, TETE_KERNEL_SPLIT = 2, TETE_KERNEL_FUSED2 = 3,
+       TETE_KERNEL_YEE = 4 /* reported for TETE_F_YEE grids, whose kernel ignores kernel, rows, depth */ };
 typedef struct {
     int32_t kernel;
     int32_t rows;

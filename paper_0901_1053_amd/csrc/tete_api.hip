@@ -74,6 +74,7 @@ struct tete_grid {
     Layout L;
     Geo geo;
     int fp32;
+    int yee;           // Yee's scheme (7) instead of (23)
     void* f[2][6];
     int cur;           // f[cur] holds y^n
     uint8_t* code;
@@ -143,7 +144,7 @@ bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 // materials take the two-kernel path.
 bool use_fused(const tete_grid* g)
 {
-    if (g->mat_set || !fused_fits(g->geo, g->fp32 ? 4 : 8)) return false;
+    if (g->yee || g->mat_set || !fused_fits(g->geo, g->fp32 ? 4 : 8)) return false;
     return g->tune.kernel != TETE_KERNEL_SPLIT;
 }
 
@@ -194,7 +195,10 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             ++s;
             continue;
         }
-        if (use_fused(g))
+        if (g->yee)
+            HIPCHK(launch_step_yee<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
+                                      g->tune.xchunk, g->tune.order, g->stream, ev));
+        else if (use_fused(g))
             HIPCHK(launch_step_fused<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                         source(g, g->n), g->tune.rows == 32 ? 0 : g->tune.rows, g->tune.xchunk,
                                         g->tune.depth, g->tune.order, g->stream, ev));
@@ -247,10 +251,17 @@ tete_status tete_check_desc(const tete_grid_desc* d)
     if (np >= ((int64_t)1 << 31) - 1) return TETE_ERR_ARG;
     if (!finite_pos(d->dx) || !finite_pos(d->dy) || !finite_pos(d->dz) || !finite_pos(d->cdt)) return TETE_ERR_ARG;
     if (d->precision != TETE_FP64 && d->precision != TETE_FP32) return TETE_ERR_ARG;
-    if (d->flags & ~(uint32_t)TETE_F_MATERIALS) return TETE_ERR_ARG;
+    if (d->flags & ~(uint32_t)(TETE_F_MATERIALS | TETE_F_YEE)) return TETE_ERR_ARG;
+    if ((d->flags & TETE_F_YEE) && (d->flags & TETE_F_MATERIALS)) return TETE_ERR_ARG;
     if (d->max_series < 0 || d->max_series > (1 << 24)) return TETE_ERR_ARG;
-    // (25): dtau <= dz and dtau <= (dx^-2 + dy^-2)^(-1/2), equality allowed
     const double tol = 1.0 + 1e-12;
+    if (d->flags & TETE_F_YEE) {
+        // (8): dtau <= (dx^-2 + dy^-2 + dz^-2)^(-1/2)
+        const double b8 = 1.0 / sqrt(1.0 / (d->dx * d->dx) + 1.0 / (d->dy * d->dy) + 1.0 / (d->dz * d->dz));
+        if (d->cdt > b8 * tol) return TETE_ERR_UNSTABLE;
+        return TETE_OK;
+    }
+    // (25): dtau <= dz and dtau <= (dx^-2 + dy^-2)^(-1/2), equality allowed
     const double bt = 1.0 / sqrt(1.0 / (d->dx * d->dx) + 1.0 / (d->dy * d->dy));
     if (d->cdt > d->dz * tol || d->cdt > bt * tol) return TETE_ERR_UNSTABLE;
     return TETE_OK;
@@ -290,6 +301,11 @@ tete_status tete_grid_create(const tete_grid_desc* d, void* dev_ws, size_t ws_by
     g->geo.sp = (d->ny + 1) * (d->nz + 1);
     g->geo.np = (d->nx + 1) * g->geo.sp;
     g->fp32 = d->precision == TETE_FP32;
+    g->yee = (d->flags & TETE_F_YEE) != 0;
+    if (g->yee && !yee_fits(g->geo, g->fp32 ? 4 : 8)) {   // planes too large for the Yee kernel's buffers
+        free(g);
+        return TETE_ERR_ARG;
+    }
     for (int s = 0; s < 2; ++s)
         for (int c = 0; c < 6; ++c) g->f[s][c] = g->ws + L.field[6 * s + c];
     g->cur = 0;
@@ -352,7 +368,8 @@ tete_status tete_get_tuning(tete_grid* g, tete_tuning* t)
 {
     if (!g || !t) return TETE_ERR_ARG;
     *t = g->tune;
-    t->kernel = use_fused2(g) ? TETE_KERNEL_FUSED2 : use_fused(g) ? TETE_KERNEL_FUSED : TETE_KERNEL_SPLIT;
+    t->kernel = g->yee ? TETE_KERNEL_YEE
+              : use_fused2(g) ? TETE_KERNEL_FUSED2 : use_fused(g) ? TETE_KERNEL_FUSED : TETE_KERNEL_SPLIT;
     return TETE_OK;
 }
 
@@ -495,6 +512,7 @@ tete_status tete_clear_bunch(tete_grid* g)
 tete_status tete_set_diagnostics(tete_grid* g, int32_t every)
 {
     if (!g || every < 0) return TETE_ERR_ARG;
+    if (g->yee && every > 0) return TETE_ERR_STATE;
     g->diag_every = every;
     return TETE_OK;
 }
@@ -557,6 +575,7 @@ tete_status tete_wake(tete_grid* g, double* W, int32_t nw)
 tete_status tete_energy(tete_grid* g, double* W, int64_t* n)
 {
     if (!g || !W) return TETE_ERR_ARG;
+    if (g->yee) return TETE_ERR_STATE;
     DeviceGuard dg(g->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
     if (g->fp32) HIPCHK(launch_energy<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->alpha, g->partial, g->scal, g->stream));
@@ -572,6 +591,7 @@ tete_status tete_energy(tete_grid* g, double* W, int64_t* n)
 tete_status tete_energy_series(tete_grid* g, double* out, int64_t max, int64_t* count)
 {
     if (!g || !count || max < 0 || (max > 0 && !out)) return TETE_ERR_ARG;
+    if (g->yee) return TETE_ERR_STATE;
     DeviceGuard dg(g->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
     int64_t c = std::min(max, g->ecount);
@@ -596,7 +616,7 @@ tete_status tete_probes(tete_grid* g, double* out, int64_t max, int64_t* count)
 tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h)
 {
     if (!g || !max_res_e || !max_abs_h) return TETE_ERR_ARG;
-    if (g->n < 1) return TETE_ERR_STATE;
+    if (g->n < 1 || g->yee) return TETE_ERR_STATE;
     DeviceGuard dg(g->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
     Src s = source(g, g->n - 1);
@@ -865,7 +885,7 @@ tete_status tete_batch_set(tete_batch* b, int32_t slot, tete_grid* g)
     if (!b || slot < 0 || slot >= TETE_MAX_BATCH) return TETE_ERR_ARG;
     if (g) {
         if (g->fp32 != b->fp32 || g->device != b->device) return TETE_ERR_ARG;
-        if (g->mat_set || !fused_fits(g->geo, g->fp32 ? 4 : 8)) return TETE_ERR_STATE;
+        if (g->yee || g->mat_set || !fused_fits(g->geo, g->fp32 ? 4 : 8)) return TETE_ERR_STATE;
         for (int s = 0; s < TETE_MAX_BATCH; ++s)
             if (s != slot && b->slot[s] == g) return TETE_ERR_ARG;
     }

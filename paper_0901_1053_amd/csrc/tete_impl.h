@@ -131,6 +131,12 @@ bool fused2_setup(FArgs<R>& A, int rows, int xchunk, int order);
 template <typename R>
 hipError_t launch_step_fused2(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src, int rows,
                               int xchunk, int order, hipStream_t s, hipEvent_t* ev);
+// One step of Yee's scheme (7) (tete_yee.hip): state (e^{n-1/2}, h^n),
+// dtau = 2 alpha; xchunk and order as for the fused step.
+bool yee_fits(Geo g, int real_bytes);
+template <typename R>
+hipError_t launch_step_yee(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, int xchunk, int order,
+                           hipStream_t s, hipEvent_t* ev);
 // One step of every instance of a batch (persistent grid of `grid`
 // workgroups), the launch after `flips` earlier launches and `steps` earlier
 // steps of the current block

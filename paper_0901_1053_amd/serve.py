@@ -185,11 +185,20 @@ class ServeStats:
 
 
 class Server:
-    def __init__(self, executor, budget_bytes=HBM_BYTES - 16 * 10 ** 9, max_slots=MAX_SLOTS, block_steps=64):
+    """First-come-first-served continuous batching.  A request is admitted when
+    a slot is free, its HBM footprint fits the budget, and the grid cells in
+    flight stay within max_cells (None: no limit; a request larger than the
+    limit is admitted alone).  The cell limit keeps the device saturated
+    without sharing it among more requests than needed, which would delay
+    every one of them."""
+
+    def __init__(self, executor, budget_bytes=HBM_BYTES - 16 * 10 ** 9, max_slots=MAX_SLOTS, block_steps=64,
+                 max_cells=None):
         self.ex = executor
         self.budget = budget_bytes
         self.max_slots = max_slots
         self.block = block_steps
+        self.max_cells = max_cells
 
     def run(self, requests) -> ServeStats:
         pending = deque(sorted(requests, key=lambda r: r.arrival))
@@ -200,6 +209,7 @@ class Server:
         active = {}
         free = list(range(self.max_slots))[::-1]
         used = 0
+        cells = 0
         peak_bytes = 0
         max_active = 0
         t0 = self.ex.now()
@@ -207,10 +217,12 @@ class Server:
         while pending or active:
             now = self.ex.now() - t0
             # admit, first come first served, while a slot and the memory allow
-            while pending and pending[0].arrival <= now and free and used + pending[0].footprint <= self.budget:
+            while (pending and pending[0].arrival <= now and free and used + pending[0].footprint <= self.budget
+                   and (self.max_cells is None or not active or cells + pending[0].case.cells <= self.max_cells)):
                 r = pending.popleft()
                 r.slot = free.pop()
                 used += r.footprint
+                cells += r.case.cells
                 peak_bytes = max(peak_bytes, used)
                 self.ex.admit(r.slot, r)
                 r.admitted = self.ex.now() - t0
@@ -232,6 +244,7 @@ class Server:
                 r.wake = self.ex.finish(slot)
                 r.done = self.ex.now() - t0
                 used -= r.footprint
+                cells -= r.case.cells
                 free.append(slot)
                 done.append(r)
         makespan = max(r.done for r in done) if done else 0.0

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libtete.so")
 
 FP64, FP32 = 0, 1
 F_MATERIALS = 1
+F_YEE = 2
 MAX_BUNCH_CELLS = 8191
 MAX_WAKE = 65536
 MAX_PROBES = 16
@@ -44,7 +45,7 @@ class Tuning(C.Structure):
                 ("order", C.c_int32)]
 
 
-KERNELS = {"auto": 0, "fused": 1, "split": 2, "fused2": 3}
+KERNELS = {"auto": 0, "fused": 1, "split": 2, "fused2": 3, "yee": 4}
 
 
 class Bunch(C.Structure):
@@ -113,9 +114,11 @@ def _chk(fn, code):
         raise TeteError(fn, code)
 
 
-def make_desc(nx, ny, nz, dx, dy, dz, cdt, precision="fp64", materials=False, max_series=0) -> GridDesc:
+def make_desc(nx, ny, nz, dx, dy, dz, cdt, precision="fp64", materials=False, max_series=0,
+              yee=False) -> GridDesc:
     prec = {"fp64": FP64, "fp32": FP32}[precision]
-    return GridDesc(nx, ny, nz, dx, dy, dz, cdt, prec, F_MATERIALS if materials else 0, max_series)
+    flags = (F_MATERIALS if materials else 0) | (F_YEE if yee else 0)
+    return GridDesc(nx, ny, nz, dx, dy, dz, cdt, prec, flags, max_series)
 
 
 def check_desc(desc: GridDesc) -> str:
@@ -127,14 +130,15 @@ def workspace_bytes(desc: GridDesc) -> int:
 
 
 class Grid:
-    """One explicit TE/TM grid living in a torch-owned device workspace."""
+    """One explicit TE/TM grid (or, with yee=True, a grid stepped with Yee's
+    scheme (7) for comparison) living in a torch-owned device workspace."""
 
     def __init__(self, nx, ny, nz, dx, dy, dz, cdt, precision="fp64", materials=False, max_series=0,
-                 device="cuda:0", stream=None):
+                 device="cuda:0", stream=None, yee=False):
         import torch
         L = load()
         self.torch = torch
-        self.desc = make_desc(nx, ny, nz, dx, dy, dz, cdt, precision, materials, max_series)
+        self.desc = make_desc(nx, ny, nz, dx, dy, dz, cdt, precision, materials, max_series, yee)
         _chk("tete_check_desc", L.tete_check_desc(C.byref(self.desc)))
         self.nbytes = workspace_bytes(self.desc)
         self.device = torch.device(device)

@@ -56,8 +56,22 @@ def test_descriptor_limits():
     d.precision = 7
     assert tete.check_desc(d) == "TETE_ERR_ARG"
     d = tete.make_desc(8, 8, 8, 2, 2, 1, 1)
-    d.flags = 2
+    d.flags = 4
     assert tete.check_desc(d) == "TETE_ERR_ARG"
+    d = tete.make_desc(8, 8, 8, 2, 2, 1, 0.5, materials=True, yee=True)     # Yee is vacuum + PEC only
+    assert tete.check_desc(d) == "TETE_ERR_ARG"
+
+
+@pytest.mark.parametrize("dx,dy,dz,cdt,want", [
+    (2e-3, 2e-3, 1e-3, 1e-3, "TETE_ERR_UNSTABLE"),                       # TE/TM's dtau = dz is beyond (8)
+    (2e-3, 2e-3, 1e-3, (0.25e6 + 0.25e6 + 1e6) ** -0.5, "TETE_OK"),      # exactly at (8)
+    (2e-3, 2e-3, 1e-3, 1.001 * (0.25e6 + 0.25e6 + 1e6) ** -0.5, "TETE_ERR_UNSTABLE"),
+    (1e-3, 1e-3, 1e-3, 0.999e-3 / 3 ** 0.5, "TETE_OK"),                  # cubic cells: dz / sqrt(3)
+    (1e-3, 1e-3, 1e-3, 0.999e-3 / 2 ** 0.5, "TETE_ERR_UNSTABLE"),        # allowed by (25), not by (8)
+])
+def test_yee_stability_validation(dx, dy, dz, cdt, want):
+    """Yee grids are checked against (8) instead of (25)."""
+    assert tete.check_desc(tete.make_desc(24, 24, 48, dx, dy, dz, cdt, yee=True)) == want
 
 
 def test_workspace_bytes():

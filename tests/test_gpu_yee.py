@@ -1,0 +1,83 @@
+"""Yee's scheme (7) on the GPU (TETE_F_YEE grids) against the oracle's Yee
+step, over ragged shapes with random obstacles, launch-shape invariance, the
+e_z probes, and the calls a Yee grid refuses."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_0901_1053_amd import inputs, tete
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(13, 11, 37), (40, 29, 130), (2, 2, 2), (3, 25, 61), (9, 20, 1000)]
+DX, DY, DZ, CDT = 2.0e-3, 1.7e-3, 1.0e-3, 0.75e-3      # (8) allows cdt up to 0.79 mm here
+
+
+def _gpu(shape, seed, precision, steps, xchunk=0, order=0, probes=None):
+    nx, ny, nz = shape
+    G = tete.Grid(nx, ny, nz, DX, DY, DZ, CDT, precision=precision, yee=True, max_series=steps + 4)
+    G.set_pec_cells(inputs.random_cells(nx, ny, nz, seed, frac=0.1))
+    if xchunk or order:
+        G.set_tuning("auto", 0, xchunk, 0, order)
+    assert G.get_tuning()["kernel"] == "yee"
+    G.set_fields(inputs.random_fields(G.shape, seed))
+    if probes is not None:
+        G.set_probes(probes)
+    G.step(steps)
+    return G
+
+
+def _oracle(shape, seed, steps, probes=None):
+    nx, ny, nz = shape
+    g = O.Geom(nx, ny, nz, DX, DY, DZ, CDT)
+    m = O.vacuum_materials(g, inputs.random_cells(nx, ny, nz, seed, frac=0.1))
+    f = inputs.random_fields(g.shape, seed)
+    O.apply_pec(g, m, f)
+    trace = []
+    for _ in range(steps):
+        O.step_yee(g, m, f)
+        if probes is not None:
+            trace.append([f["ez"].ravel()[p] for p in probes])
+    return f, np.array(trace)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_yee_matches_oracle(shape):
+    ref, _ = _oracle(shape, 61, 25)
+    got = _gpu(shape, 61, "fp64", 25).get_fields()
+    assert P.field_rel_err(got, ref) <= 1e-12
+    got32 = _gpu(shape, 61, "fp32", 25).get_fields()
+    assert P.field_rel_err(got32, ref) <= 2e-5
+
+
+@pytest.mark.parametrize("xchunk,order", [(1, 2), (3, 1), (1000, 3), (7, 4), (2, 0)])
+def test_yee_launch_shape_invariance(xchunk, order):
+    shape = (40, 29, 300)
+    base = _gpu(shape, 62, "fp64", 12).get_fields()
+    got = _gpu(shape, 62, "fp64", 12, xchunk, order).get_fields()
+    for k in tete.KEYS:
+        assert np.array_equal(got[k], base[k]), k
+
+
+def test_yee_probes():
+    shape = (13, 11, 37)
+    probes = np.array([5, 400, 2000, 3333], dtype=np.int64)
+    G = _gpu(shape, 63, "fp64", 30, probes=probes)
+    _, trace = _oracle(shape, 63, 30, probes=probes)
+    got = G.probes(len(probes))
+    assert got.shape == trace.shape
+    assert np.max(np.abs(got - trace)) <= 1e-12 * np.max(np.abs(trace))
+
+
+def test_yee_refuses_te_tm_only_calls():
+    G = _gpu((8, 8, 40), 64, "fp32", 2)
+    for call in (lambda: G.set_bunch(1e-9, 1e-3, 4, 4, 3, -3, 10), lambda: G.energy(), lambda: G.charges(),
+                 lambda: G.set_diagnostics(3), lambda: G.energy_series()):
+        with pytest.raises(tete.TeteError) as e:
+            call()
+        assert e.value.status == "TETE_ERR_STATE"
+    B = tete.Batch("fp32")
+    with pytest.raises(tete.TeteError) as e:
+        B.set(0, G)
+    assert e.value.status == "TETE_ERR_STATE"

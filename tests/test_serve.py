@@ -124,3 +124,26 @@ def test_one_at_a_time_model_equals_served_stream():
         assert model.completed == st.completed
         assert model.latencies == pytest.approx(st.latencies, rel=1e-9, abs=1e-9)
         assert model.p99_s == pytest.approx(st.p99_s, rel=1e-9)
+
+
+def test_cell_limit_bounds_work_in_flight():
+    """With a cell limit, the cells of the admitted requests never exceed it
+    (except a single request larger than the limit, admitted alone), every
+    request is served, and order stays first come first served."""
+    cases = _cases(16, seed=12)
+    cap = int(np.median([c.cells for c in cases]) * 2)
+    ex = serve.MockExecutor(rate_cells_per_s=2e8)
+    reqs = serve.make_requests(cases, rate=1e4, seed=13)
+    st = serve.Server(ex, max_slots=64, block_steps=32, max_cells=cap).run(reqs)
+    assert st.completed == len(cases)
+    cells = {r.rid: r.case.cells for r in reqs}
+    inflight = {}
+    for e in ex.log:
+        if e[0] == "admit":
+            inflight[e[2]] = cells[e[2]]
+            assert sum(inflight.values()) <= cap or len(inflight) == 1
+        elif e[0] == "finish":
+            inflight.pop(e[2])
+    order = [e[2] for e in ex.log if e[0] == "admit"]
+    assert order == sorted(order)
+    assert st.max_active < len(cases)
