@@ -113,3 +113,75 @@ def test_pins_catch_planted_mistake(tmp_path, name):
         except (AssertionError, FloatingPointError, ValueError, np.linalg.LinAlgError):
             caught += 1
     assert caught >= 1, "no pin caught mutant %s" % name
+
+
+# ---- the r-z oracle (Python): each mutant is a list of (old, new) first-occurrence edits
+from tests import test_oracle_rz as TZ
+
+RZ_SRC = os.path.join(os.path.dirname(HERE), "oracle", "rz_oracle.py")
+
+RZ_MUTANTS = {
+    # the implicit factors with the subscripts as printed (swapped between e_z and h_z)
+    "rz_printed_factor_order": ([('m["ez"] * m["hr"])                 # S3', 'm["hz"] * m["er"])                 # S3'),
+                                 ('m["hz"] * m["er"])                 # S8', 'm["ez"] * m["hr"])                 # S8')],
+                                [lambda z: TZ.test_rz_energy_conserved(z, 1)]),
+    # azimuthal coupling of h_r with the wrong sign
+    "rz_hr_m_sign": ([('(-pz(f["ephi"]) + M * f["ez"])', '(-pz(f["ephi"]) - M * f["ez"])')],
+                     [lambda z: TZ.test_rz_energy_conserved(z, 1),
+                      lambda z: TZ.test_rz_tm_modes_converge_second_order(z, 1)]),
+    # on-axis dual facet taken as dr^2 / 4
+    "rz_axis_area": ([("dz / (dr * dr / 8.0)", "dz / (dr * dr / 4.0)")],
+                     [lambda z: TZ.test_rz_facets_tile_the_cross_section(z)]),
+    # kappa_r at the node radius instead of r_{j+1/2}
+    "rz_kappa_r_radius": ([('m["er"] = dr / (rh * dz)', 'm["er"] = dr / (np.maximum(r, dr) * dz)')],
+                          [lambda z: TZ.test_rz_modes_with_z_variation(z, "TE", 1, 1)]),
+    # current with the sign printed in (24)
+    "rz_current_sign": ([('- M * f["hr"] - Jz)', '- M * f["hr"] + Jz)')],
+                        [lambda z: TZ.test_rz_gauss_law_ring_bunch(z, 1, 3, 1.0)]),
+    # radial difference of h_z in the energy taken forward
+    "rz_energy_r1": ([('m["ephi"] * prs(f["hz"]) ** 2', 'm["ephi"] * pr(f["hz"]) ** 2')],
+                     [lambda z: TZ.test_rz_energy_conserved(z, 1)]),
+    # charge with + alpha^2
+    "rz_charge_alpha": ([("ez * _inv(m[\"ez\"]) - a * a * rz", "ez * _inv(m[\"ez\"]) + a * a * rz")],
+                        [lambda z: TZ.test_rz_gauss_law_ring_bunch(z, 1, 3, 1.0)]),
+    # wake sample one step early
+    "rz_wake_index": ([("jj = n - k - bunch.M", "jj = n - k - bunch.M + 1")],
+                      [lambda z: TZ.test_rz_wake_energy_identity(z, 1)]),
+    # Yee with half the step
+    "rz_yee_half_step": ([("    dt = g.cdt\n    M = g.m", "    dt = 0.5 * g.cdt\n    M = g.m")],
+                         [lambda z: TZ.test_rz_stability_independent_of_m(z)]),
+    # the axis treated as a wall
+    "rz_axis_wall": ([("cell[0, :] = cell[1, :]", "cell[0, :] = True")],
+                     [lambda z: TZ.test_rz_tm_modes_converge_second_order(z, 0)]),
+    # Panofsky-Wenzel with a one-sided sum instead of the trapezoid
+    "rz_pw_rule": ([("np.cumsum(0.5 * (D[1:] + D[:-1]))", "np.cumsum(D[1:])")],
+                   [lambda z: TZ.test_rz_transverse_wake_matches_lorentz_force(z)]),
+}
+
+
+def _load_rz_mutant(tmp_path, name, edits):
+    src = open(RZ_SRC).read()
+    for old, new in edits:
+        assert src.count(old) >= 1, (name, old)
+        src = src.replace(old, new, 1)
+    p = tmp_path / (name + ".py")
+    p.write_text(src)
+    spec = importlib.util.spec_from_file_location("rz_mutant_" + name, str(p))
+    mod = importlib.util.module_from_spec(spec)
+    sys.modules[spec.name] = mod
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(RZ_MUTANTS))
+def test_rz_pins_catch_planted_mistake(tmp_path, name):
+    edits, pins = RZ_MUTANTS[name]
+    mod = _load_rz_mutant(tmp_path, name, edits)
+    caught = 0
+    for pin in pins:
+        try:
+            with np.errstate(all="ignore"):
+                pin(mod)
+        except (AssertionError, FloatingPointError, ValueError, np.linalg.LinAlgError):
+            caught += 1
+    assert caught >= 1, "no pin caught mutant %s" % name
