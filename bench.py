@@ -187,6 +187,55 @@ def yee_section(G, case, precision, steps=20):
                       "run_time_vs_yee_at_dx_sqrt2_dz": round((10 / 6) / 2 ** 0.5, 3)}}
 
 
+def rz_section(steps=100, warmup=5):
+    """The rotationally symmetric scheme (24) on the deflector-like r-z workload
+    at harmonic m = 1: kernel time per step in FP32 and FP64 (HIP events on the
+    grid's stream around each launch), Gcell-updates/s and the HBM roofline of
+    k_rz (read and write six components plus the code byte per node), and the
+    stable step against Yee's at the same m from the paper's bounds."""
+    import torch
+    from paper_0901_1053_amd import inputs, tete
+    case = inputs.tds_case(1)
+    cells = case.cells()
+    jmin, nw = case.window()
+    res = {"workload": case.name, "grid": [case.nr, case.nz], "cells": case.nr * case.nz, "mode": case.mode,
+           "dr_m": case.dr, "dz_m": case.dz, "sigma_m": case.sigma, "steps_per_solve": case.steps()}
+    for prec in ("fp32", "fp64"):
+        G = tete.RZGrid(case.nr, case.nz, case.dr, case.dz, case.cdt, case.mode, prec)
+        G.set_pec_cells(cells)
+        G.set_bunch(case.charge, case.sigma, case.j0, case.M, case.jw, jmin, nw)
+        G.step(warmup)
+        G.set_timing(steps)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(G.stream)
+        G.step(steps)
+        e1.record(G.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        kms, n = G.timing()
+        G.set_timing(0)
+        b = 4 if prec == "fp32" else 8
+        kbytes = (12 * b + 1) * G.np
+        achieved = kbytes / (kms / n / 1e3) / 1e9
+        res[prec] = {"gcell_updates_per_s": round(case.nr * case.nz * steps / (ms / 1e3) / 1e9, 2),
+                     "ms_per_step": round(ms / steps, 4),
+                     "roofline": {"bound": "hbm", "kernel": "k_rz", "achieved": round(achieved, 1),
+                                  "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                                  "frac": round(achieved / PEAK_HBM_GBPS, 4), "bytes_per_launch": kbytes,
+                                  "ms_per_launch": round(kms / n, 4)},
+                     "solve_s_estimate": round(ms / steps * case.steps() / 1e3, 2)}
+        G.close()
+        del G
+        torch.cuda.empty_cache()
+    m = case.mode
+    yee = 1.0 / ((1.2 + 0.4 * m * m) / case.dr ** 2 + 1.2 / case.dz ** 2) ** 0.5
+    res["stable_step_vs_yee"] = {"te_tm_dtau_over_dz": 1.0, "yee_bound_over_dz": round(yee / case.dz, 4),
+                                 "steps_ratio_yee_over_te_tm": round(case.dz / yee, 3)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,6 +252,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-yee", action="store_true", help="skip the comparison with Yee's scheme")
+    ap.add_argument("--no-rz", action="store_true", help="skip the rotationally symmetric workload")
     ap.add_argument("--batched-count", type=int, default=64)
     ap.add_argument("--serve-rates", default="1,20,200", help="comma-separated request rates (req/s)")
     ap.add_argument("--serve-requests", type=int, default=12)
@@ -334,6 +384,10 @@ def main():
         res["steps"] = sw.steps
         out["single_wake"] = res
         print("# single wake done", file=sys.stderr, flush=True)
+
+    if not args.no_rz:
+        out["rz"] = rz_section()
+        print("# rz done", file=sys.stderr, flush=True)
 
     if not args.no_batched:
         out["batched"] = batched_section(args.batched_count)

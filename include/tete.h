@@ -313,6 +313,125 @@ tete_status tete_batch_step(tete_batch* b, int64_t nsteps);
 /* Number of occupied slots. */
 tete_status tete_batch_count(tete_batch* b, int32_t* active);
 
+/* ---------------------------------------------------------------------------
+ * Rotationally symmetric structures: scheme (24) of Sec. 4.3 for one azimuthal
+ * harmonic m on an r-z grid.
+ *
+ * Grid: nr x nz cells, node (j, k) at (r, z) = (j dr, k dz), j = 0 on the
+ * axis, PEC walls at r = nr dr and at z = 0, nz dz.  The azimuthal derivative
+ * of harmonic m is taken exactly (P_phi -> m), so every FIT quantity is per
+ * radian: e^ = E * edge length per radian, h^ = H * dual-edge length per radian.
+ * Six arrays of (nr+1)(nz+1) entries, z fastest: index = k + (nz+1) j.  Order
+ * in the [6] arguments: e_phi, e_r, e_z, h_phi, h_r, h_z at
+ *   e_phi (j, k)   e_r (j+1/2, k)   e_z (j, k+1/2)
+ *   h_phi (j+1/2, k+1/2)   h_r (j, k+1/2)   h_z (j+1/2, k).
+ * Material matrices (vacuum, per radian): kappa = edge / dual facet, mu =
+ * dual edge / facet; the dual facet of the on-axis e_z edge is the disk of
+ * radius dr/2 (area dr^2/8 per radian) and exists for m = 0 only; e_phi has
+ * no length on the axis.  The implicit factors of (24) are taken on the
+ * e_z / h_r and h_z / e_r positions: (1 + a^2 m^2 kappa_z mu_r)^-1 on e_z and
+ * (1 + a^2 m^2 mu_z kappa_r)^-1 on h_z, a = cdt/2.
+ *
+ * Stability (Sec. 4.4): cdt <= dz and cdt <= dr for every m >= 1 (independent
+ * of m); for m = 0 the on-axis cell limits cdt to 0.9089 dr (largest
+ * eigenvalue 4.8419/dr^2 of the radial operator next to the axis).
+ *
+ * Memory, streams and errors as for tete_grid: caller-owned 256-byte aligned
+ * device workspace, caller's HIP stream, bulk arrays are DEVICE pointers,
+ * small results HOST pointers.
+ * ------------------------------------------------------------------------- */
+typedef struct tete_rz tete_rz; /* opaque handle */
+
+typedef struct {
+    int32_t nr, nz;       /* cells, each >= 2; (nr+1)(nz+1) < 2^31 */
+    double dr, dz;        /* cell sizes [m] */
+    double cdt;           /* dtau [m]: <= dz, <= dr (m >= 1) or <= 0.9089 dr (m = 0) */
+    int32_t mode;         /* azimuthal harmonic m, 0 <= m <= 4096 */
+    int32_t precision;    /* TETE_FP64 or TETE_FP32 */
+} tete_rz_desc;
+
+/* Size and stability check of a descriptor (host only).  TETE_OK,
+ * TETE_ERR_ARG or TETE_ERR_UNSTABLE (the bounds above). */
+tete_status tete_rz_check_desc(const tete_rz_desc* desc);
+
+/* Device workspace bytes of an r-z grid (0 if the descriptor is invalid). */
+size_t tete_rz_workspace_bytes(const tete_rz_desc* desc);
+
+/* Create an r-z grid on the current device inside dev_ws (256-byte aligned,
+ * ws_bytes >= tete_rz_workspace_bytes), stream hip_stream (NULL = null
+ * stream).  Fields zero, empty vacuum PEC pillbox, no bunch, counter 0.
+ * Errors: TETE_ERR_ARG, TETE_ERR_UNSTABLE, TETE_ERR_NOMEM, TETE_ERR_DEVICE. */
+tete_status tete_rz_create(const tete_rz_desc* desc, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                           tete_rz** out);
+
+/* Release the host handle (the workspace stays the caller's). */
+tete_status tete_rz_destroy(tete_rz* g);
+
+/* Staircase geometry: DEVICE array of nr*nz bytes, index k + nz*j, non-zero =
+ * PEC cell (j+1/2, k+1/2).  An edge is PEC if any adjacent cell is; cells
+ * outside r < nr dr and 0 < z < nz dz are PEC, the axis is not a wall (the
+ * cell row j = -1 mirrors j = 0).  NULL = empty pillbox.  Zeroes e on the new
+ * PEC edges.  Copies; the caller keeps its array. */
+tete_status tete_rz_set_pec_cells(tete_rz* g, const uint8_t* cell_is_pec);
+
+/* Initial state y^0 = (u^{-1/2}, v^0), u = (h_phi, h_r, e_z) at tau = -cdt/2
+ * and v = (e_phi, e_r, h_z) at tau = 0 (DEVICE arrays, dtype TETE_FP64 or
+ * TETE_FP32).  Out-of-range entries and e on PEC edges are stored as zero.
+ * Resets the step counter and the wake accumulators. */
+tete_status tete_rz_set_fields(tete_rz* g, const void* const f[6], int32_t dtype);
+
+/* Copy the current state y^n into DEVICE arrays f[6] of dtype. */
+tete_status tete_rz_get_fields(tete_rz* g, void* const f[6], int32_t dtype);
+
+/* Ring bunch of the grid's harmonic m (Sec. 5 charge model; a point charge's
+ * harmonic m carries the weight 1/(2 pi) per radian for m = 0 and 1/pi for
+ * m >= 1): total charge charge_C, RMS length sigma_z, moving at v = c along
+ * +z at radius j0 dr (0 <= j0 < nr; j0 = 0, the axis, for m = 0 only).  Cells,
+ * timing and wake samples s_j = j dz (j = jmin .. jmin+nw-1) as for
+ * tete_set_bunch.  The wake is sampled on the two e_z lines j = jw and jw+1
+ * (0 <= jw < nr - 1; jw >= 1 for m >= 1).  Requires cdt == dz.  Resets the
+ * wake accumulators.  Errors: TETE_ERR_ARG, TETE_ERR_STATE (cdt != dz). */
+typedef struct {
+    double charge_C;
+    double sigma_z;       /* [m] */
+    int32_t j0;           /* radius index of the ring */
+    int32_t half_cells;   /* M, 2M+1 <= TETE_MAX_BUNCH_CELLS */
+    int32_t jw;           /* first wake line */
+    int32_t jmin;
+    int32_t nw;           /* <= TETE_MAX_WAKE */
+} tete_rz_bunch;
+tete_status tete_rz_set_bunch(tete_rz* g, const tete_rz_bunch* b);
+
+/* Enqueue nsteps steps of (24) (asynchronous; one kernel launch per step).
+ * Errors: TETE_ERR_ARG (nsteps < 0), TETE_ERR_DEVICE. */
+tete_status tete_rz_step(tete_rz* g, int64_t nsteps);
+
+/* Number of completed steps (host counter). */
+tete_status tete_rz_steps_done(tete_rz* g, int64_t* n);
+
+/* Wakes of harmonic m (Sec. 5) in V/C, HOST arrays: W_par[0..nw-1] on line
+ * jw and W_par[nw..2nw-1] on line jw+1 (W = -(1/Q) int E_z dz at t = (z+s)/c,
+ * the 3-D quadrature), and W_perp[0..nw-1] = the radial wake at
+ * (r_{jw+1/2}, theta = 0) by the Panofsky-Wenzel relation d/ds W_perp =
+ * grad_perp W_par: the trapezoidal integral over s of the lines' difference
+ * divided by dr (W_perp may be NULL).  Synchronises. */
+tete_status tete_rz_wake(tete_rz* g, double* W_par, double* W_perp, int32_t nw);
+
+/* Discrete energy 1/2 <Q y^n, y^n> of (24) (Q = B^{e,r} - alpha A: the 3-D form
+ * of Sec. 4.4 with only the radial part of the splitting operator), FP64,
+ * internal units, per radian; *n = steps done.  Synchronises. */
+tete_status tete_rz_energy(tete_rz* g, double* W, int64_t* n);
+
+/* Launch tuning of the r-z kernel: rows per r-chunk (0 = automatic, else
+ * 8 .. 4096) and loads issued ahead (0 = automatic, else 1 .. 4). */
+tete_status tete_rz_set_tuning(tete_rz* g, int32_t chunk_rows, int32_t prefetch);
+
+/* Live kernel timing: max_launches > 0 records HIP events around each step
+ * launch (0 disables); tete_rz_timing returns the summed kernel time [ms]
+ * and the launches recorded.  Synchronises. */
+tete_status tete_rz_set_timing(tete_rz* g, int64_t max_launches);
+tete_status tete_rz_timing(tete_rz* g, double* ms, int64_t* launches);
+
 /* Human-readable status name. */
 const char* tete_status_str(tete_status s);
 

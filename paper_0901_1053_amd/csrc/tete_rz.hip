@@ -1,0 +1,845 @@
+// Rotationally symmetric structures: scheme (24) of Sec. 4.3 for one
+// azimuthal harmonic m on an r-z grid -- the step kernel, its diagnostics and
+// the tete_rz_* entry points of include/tete.h.
+//
+// Kernel design.  The step has no third direction to march along, so each
+// wave owns a strip of 64 consecutive k (one per lane; neighbours along z are
+// DPP lane shifts, lanes 0 and 63 are halo) and marches along r over a chunk
+// of rows.  The r-dependencies of the ten sub-updates fix a two-row lag: when
+// row p has been loaded, S1, S2, S3, S5 and S6 run at row p-1 and S4, S7, S8,
+// S9 and S10 at row p-2, which is then final and stored.  Everything a row
+// needs from its neighbours stays in registers, so there is no LDS and no
+// barrier; a chunk re-reads two rows on each side.  Loads run PF rows ahead
+// of the march.  Coefficients depend on r only: one table row per radius,
+// read with scalar loads.  Fields are read from one time level and written to
+// the other (chunks read each other's halo rows).
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "tete_dev.h"
+
+namespace tete {
+namespace {
+
+constexpr double kEps0 = 8.8541878128e-12;   // vacuum permittivity [F/m] (CODATA 2018)
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kLanes = 64, kOwn = 62;        // lanes per wave, owned k per wave
+constexpr int kWaves = 4;                    // waves (z-strips) per workgroup
+constexpr int kPad = 2;                      // coefficient rows below 0 and above nr
+constexpr int kRedBlocks = 1024, kRedThreads = 256;
+
+// Node code bits: e edge PEC or absent; HK = no h_phi / h_r at this k (k = nz).
+enum { C_EPHI = 1, C_ER = 2, C_EZ = 4, C_HK = 8, C_ALL = 15 };
+
+// Update coefficients of one radius: a kappa_phi, a kappa_r, 2a kappa_z f_e,
+// a mu_phi, a mu_r, 2a mu_z f_h with the implicit factors f_e = (1 + a^2 m^2
+// kappa_z mu_r)^-1 and f_h = (1 + a^2 m^2 mu_z kappa_r)^-1.
+template <typename R>
+struct Coef {
+    R cp, cr, cz, dp, dr, dz;
+};
+
+// kappa and mu of one radius (FP64, for the energy and set-up).
+struct Raw {
+    double kp, kr, kz, mp, mr, mz;
+};
+
+template <typename R>
+struct RZArgs {
+    const R* o[6];          // y^n: e_phi, e_r, e_z, h_phi, h_r, h_z
+    R* w[6];                // y^{n+1}
+    const uint8_t* code;
+    const Coef<R>* coef;    // rows -kPad .. nr+kPad, entry 0 is row -kPad
+    int nr, nz, sz;         // sz = nz + 1
+    R m;                    // harmonic m
+    int nzt, nzb, rows;     // z-strips, workgroups along z, rows per chunk
+    int src, j0, M, jw, jmin, nw;
+    int64_t n;              // step being taken
+    const double* lamw;     // 2M+1: harmonic weight * cell charge / dtau
+    double* acc;            // 2 x nw wake accumulators (lines jw, jw+1)
+};
+
+template <typename R>
+struct Row {
+    R ez, er, ep, hp, hr, hz;
+    uint32_t c;
+};
+
+template <typename R, int PF>
+__global__ __launch_bounds__(kLanes * kWaves) void k_rz(RZArgs<R> A)
+{
+    constexpr uint32_t RB = sizeof(R);
+    constexpr uint32_t OOB = 0x80000000u;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    // the wave index is uniform: taking it through a scalar register keeps the
+    // early return below a scalar branch
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes), lane = threadIdx.x % kLanes;
+    const int zt = (lb % A.nzb) * kWaves + wave;
+    const int rc = lb / A.nzb;
+    if (zt >= A.nzt) return;                          // whole wave
+    const int k = zt * kOwn - 1 + lane;
+    const bool kin = k >= 0 && k <= A.nz;
+    const bool own_k = kin && lane >= 1 && lane <= kOwn;
+    const int ra = rc * A.rows, rb = min(ra + A.rows, A.nr + 1);
+    const int L0 = max(0, ra - 2), pend = rb + 1;
+
+    const uint32_t np = (uint32_t)(A.nr + 1) * (uint32_t)A.sz;
+    auto mk = [](const void* base, uint32_t bytes) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+    };
+    const auto rEP = mk(A.o[0], np * RB), rER = mk(A.o[1], np * RB), rEZ = mk(A.o[2], np * RB),
+               rHP = mk(A.o[3], np * RB), rHR = mk(A.o[4], np * RB), rHZ = mk(A.o[5], np * RB);
+    const auto sEP = mk(A.w[0], np * RB), sER = mk(A.w[1], np * RB), sEZ = mk(A.w[2], np * RB),
+               sHP = mk(A.w[3], np * RB), sHR = mk(A.w[4], np * RB), sHZ = mk(A.w[5], np * RB);
+    const auto rC = mk(A.code, np + 4);
+
+    auto load = [&](int p) {
+        Row<R> v;
+        const bool ok = kin && p <= A.nr;
+        const uint32_t idx = (uint32_t)p * (uint32_t)A.sz + (uint32_t)k;
+        const uint32_t off = ok ? idx * RB : OOB;
+        v.ez = bload<R>(rEZ, off);
+        v.er = bload<R>(rER, off);
+        v.ep = bload<R>(rEP, off);
+        v.hp = bload<R>(rHP, off);
+        v.hr = bload<R>(rHR, off);
+        v.hz = bload<R>(rHZ, off);
+        // the code byte is read as the aligned dword that holds it
+        const uint32_t cw = __builtin_amdgcn_raw_buffer_load_b32(rC, ok ? (idx & ~3u) : OOB, 0, 0);
+        v.c = ok ? (cw >> (8 * (idx & 3u))) & 0xffu : (uint32_t)C_ALL;
+        return v;
+    };
+    auto coef = [&](int row) { return A.coef[row + kPad]; };
+
+    const R m = A.m;
+    // rows p-1 (old values), p-2 and p-3 of the pipeline
+    R EZ1 = 0, ER1 = 0, EP1 = 0, HP1 = 0, HR1 = 0, HZ1 = 0;
+    uint32_t C1 = C_ALL;
+    R HZ2 = 0, HPn2 = 0, EZh2 = 0, ER2 = 0, HRh2 = 0, EPh2 = 0;
+    uint32_t C2 = C_ALL;
+    R HZn3 = 0;
+
+    Row<R> ring[PF];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) ring[u] = load(L0 + u);
+
+    for (int p0 = L0; p0 <= pend; p0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int p = p0 + u;
+            if (p > pend) break;
+            const Row<R> cur = ring[u];
+            ring[u] = load(p + PF);
+            const Coef<R> c1 = coef(p - 1), c2 = coef(p - 2);
+            const int j1 = p - 1;
+
+            // The PEC / absence bits zero the coefficient of a masked entry
+            // (x + 0 * d == x) instead of selecting the result: a select around
+            // an update can be compiled into a branch, and a lane shift inside
+            // it would then read 0 from the lanes the branch disables.
+            const R hp1 = (C1 & C_HK) ? (R)0 : c1.dp, hr1c = (C1 & C_HK) ? (R)0 : c1.dr;
+            const R ez1c = (C1 & C_EZ) ? (R)0 : c1.cz, ep1c = (C1 & C_EPHI) ? (R)0 : c1.cp;
+            const R hp2 = (C2 & C_HK) ? (R)0 : c2.dp, er2c = (C2 & C_ER) ? (R)0 : c2.cr;
+            const R ep2c = (C2 & C_EPHI) ? (R)0 : c2.cp;
+
+            // S1 at p-1: h_phi^n = h_phi^{n-1/2} + a mu_phi [P_z e_r^n - P_r e_z^{n-1/2}]
+            const R hpn1 = HP1 + hp1 * ((lane_next(ER1) - ER1) - (cur.ez - EZ1));
+            // S2 at p-1: h_r^n = h_r^{n-1/2} + a mu_r [-P_z e_phi^n + m e_z^{n-1/2}]
+            const R pzEP1 = lane_next(EP1) - EP1;
+            const R hrn1 = HR1 + hr1c * (m * EZ1 - pzEP1);
+            // S3 at p-1: e_z^{n+1/2} = e_z^{n-1/2} + f_e 2a kappa_z [P_r^* h_phi^n - m h_r^n - j_z^n]
+            R ezh1 = EZ1 + ez1c * ((HPn2 - hpn1) - m * hrn1);
+            if (A.src && j1 == A.j0 && !(C1 & C_EZ) && k < A.nz) {
+                const int64_t mm = (int64_t)k - A.n + A.M;       // cell mm crosses edge k in step n
+                if (mm >= -A.M && mm <= A.M) {
+                    // the current term is rounded on its own, as in the 3-D kernels
+#pragma clang fp contract(off)
+                    ezh1 -= (R)((double)c1.cz * A.lamw[mm + A.M]);
+                }
+            }
+            if (A.src && (j1 == A.jw || j1 == A.jw + 1) && j1 >= ra && j1 < rb && own_k && k < A.nz) {
+                const int64_t js = A.n - k - A.M;                // wake sample of edge k
+                if (js >= A.jmin && js < (int64_t)A.jmin + A.nw)
+                    A.acc[(j1 - A.jw) * A.nw + (js - A.jmin)] += -0.5 * ((double)EZ1 + (double)ezh1);
+            }
+            // S5 at p-1: h_r^{n+1/2} = h_r^n + a mu_r [-P_z e_phi^n + m e_z^{n+1/2}]
+            const R hrh1 = hrn1 + hr1c * (m * ezh1 - pzEP1);
+            // S6 at p-1: e_phi^{n+1/2} = e_phi^n + a kappa_phi [P_z^* h_r^{n+1/2} - P_r^* h_z^n]
+            const R eph1 = EP1 + ep1c * ((lane_prev(hrh1) - hrh1) - (HZ2 - HZ1));
+            // S4 at p-2: h_phi^{n+1/2} = h_phi^n + a mu_phi [P_z e_r^n - P_r e_z^{n+1/2}]
+            const R hph2 = HPn2 + hp2 * ((lane_next(ER2) - ER2) - (ezh1 - EZh2));
+            // S7 at p-2: e_r^{n+1/2} = e_r^n + a kappa_r [-P_z^* h_phi^{n+1/2} + m h_z^n]
+            const R pzsHP2 = lane_prev(hph2) - hph2;
+            const R erh2 = ER2 + er2c * (m * HZ2 - pzsHP2);
+            // S8 at p-2: h_z^{n+1} = h_z^n + f_h 2a mu_z [P_r e_phi^{n+1/2} - m e_r^{n+1/2}]
+            const R hzn2 = HZ2 + c2.dz * ((eph1 - EPh2) - m * erh2);
+            // S9 at p-2: e_phi^{n+1} = e_phi^{n+1/2} + a kappa_phi [P_z^* h_r^{n+1/2} - P_r^* h_z^{n+1}]
+            const R ep2 = EPh2 + ep2c * ((lane_prev(HRh2) - HRh2) - (HZn3 - hzn2));
+            // S10 at p-2: e_r^{n+1} = e_r^{n+1/2} + a kappa_r [-P_z^* h_phi^{n+1/2} + m h_z^{n+1}]
+            const R er2 = erh2 + er2c * (m * hzn2 - pzsHP2);
+
+            // row p-2 is final
+            const int q = p - 2;
+            const bool st = own_k && q >= ra && q < rb;
+            const uint32_t so = st ? ((uint32_t)q * (uint32_t)A.sz + (uint32_t)k) * RB : OOB;
+            bstore<R>(sHP, so, hph2);
+            bstore<R>(sHR, so, HRh2);
+            bstore<R>(sEZ, so, EZh2);
+            bstore<R>(sEP, so, ep2);
+            bstore<R>(sER, so, er2);
+            bstore<R>(sHZ, so, hzn2);
+
+            // advance the pipeline by one row
+            HZn3 = hzn2;
+            EPh2 = eph1;
+            HRh2 = hrh1;
+            ER2 = ER1;
+            EZh2 = ezh1;
+            HPn2 = hpn1;
+            HZ2 = HZ1;
+            C2 = C1;
+            EZ1 = cur.ez;
+            ER1 = cur.er;
+            EP1 = cur.ep;
+            HP1 = cur.hp;
+            HR1 = cur.hr;
+            HZ1 = cur.hz;
+            C1 = cur.c;
+        }
+    }
+}
+
+// Node codes from a cell mask (NULL: empty pillbox).  Cells outside r < nr dr
+// and 0 < z < nz dz are PEC; row j = -1 mirrors j = 0 (the axis is no wall).
+__device__ __forceinline__ bool cell_pec(const uint8_t* cells, int nr, int nz, int j, int k)
+{
+    if (k < 0 || k >= nz || j >= nr) return true;
+    if (j < 0) j = 0;
+    return cells ? cells[(int64_t)k + (int64_t)nz * j] != 0 : false;
+}
+
+__global__ void k_rz_code(const uint8_t* cells, uint8_t* code, int nr, int nz)
+{
+    const int64_t np = (int64_t)(nr + 1) * (nz + 1);
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < np;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(idx / (nz + 1)), k = (int)(idx % (nz + 1));
+        const bool a = cell_pec(cells, nr, nz, j - 1, k - 1), b = cell_pec(cells, nr, nz, j, k - 1),
+                   c = cell_pec(cells, nr, nz, j - 1, k), d = cell_pec(cells, nr, nz, j, k);
+        uint32_t v = 0;
+        if (a || b || c || d) v |= C_EPHI;
+        if (j >= nr || b || d) v |= C_ER;
+        if (k >= nz || c || d) v |= C_EZ;
+        if (k >= nz) v |= C_HK;
+        code[idx] = (uint8_t)v;
+    }
+}
+
+// Zero every entry outside its index range and e on PEC edges (also e_phi on
+// the axis and, for m >= 1, e_z on the axis, whose kappa is zero).
+template <typename R>
+__global__ void k_rz_sanitize(R* const* f, const uint8_t* code, const Raw* raw, int nr, int nz)
+{
+    const int64_t np = (int64_t)(nr + 1) * (nz + 1);
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < np;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(idx / (nz + 1)), k = (int)(idx % (nz + 1));
+        const uint32_t c = code[idx];
+        if ((c & C_EPHI) || raw[j].kp == 0.0) f[0][idx] = 0;
+        if ((c & C_ER) || raw[j].kr == 0.0) f[1][idx] = 0;
+        if ((c & C_EZ) || raw[j].kz == 0.0) f[2][idx] = 0;
+        if (j >= nr || k >= nz) f[3][idx] = 0;
+        if (j == 0 || k >= nz) f[4][idx] = 0;
+        if (j >= nr) f[5][idx] = 0;
+    }
+}
+
+template <typename D, typename S>
+__global__ void k_rz_convert(D* dst, const S* src, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (D)src[i];
+}
+
+__device__ double block_sum(double v)
+{
+    __shared__ double s[kRedThreads];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    return s[0];
+}
+
+// Energy 1/2 <Q y, y> of (24), summed per node:
+//   1/2 [sum h^2/mu + sum_{kappa>0} e^2/kappa]
+//   - a^2/2 [sum_{h_phi} mu_phi (P_r e_z)^2 + sum_{e_phi, kappa>0} kappa_phi (P_r^T h_z)^2]
+//   + a [sum_{h_phi} h_phi P_z e_r - sum_{h_r} h_r P_z e_phi]
+template <typename R>
+__global__ __launch_bounds__(kRedThreads) void k_rz_energy(const R* const* f, const uint8_t* code, const Raw* raw,
+                                                         int nr, int nz, double a, double* partial)
+{
+    const R *ep = f[0], *er = f[1], *ez = f[2], *hp = f[3], *hr = f[4], *hz = f[5];
+    const int sz = nz + 1;
+    const int64_t np = (int64_t)(nr + 1) * sz;
+    double acc = 0.0;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < np;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(idx / sz), k = (int)(idx % sz);
+        const uint32_t c = code[idx];
+        const Raw w = raw[j];
+        double sq = 0.0, r = 0.0, lc = 0.0;
+        const double kp = (c & C_EPHI) ? 0.0 : w.kp, kr = (c & C_ER) ? 0.0 : w.kr, kz = (c & C_EZ) ? 0.0 : w.kz;
+        if (kp > 0.0) {
+            const double e = ep[idx], d = (j > 0 ? (double)hz[idx - sz] : 0.0) - (double)hz[idx];
+            sq += e * e / kp;
+            r += kp * d * d;
+        }
+        if (kr > 0.0) sq += (double)er[idx] * (double)er[idx] / kr;
+        if (kz > 0.0) sq += (double)ez[idx] * (double)ez[idx] / kz;
+        if (j < nr && k < nz && w.mp > 0.0) {
+            const double h = hp[idx], d = (double)ez[idx + sz] - (double)ez[idx];
+            sq += h * h / w.mp;
+            r += w.mp * d * d;
+            lc += h * ((double)er[idx + 1] - (double)er[idx]);
+        }
+        if (j > 0 && k < nz && w.mr > 0.0) {
+            const double h = hr[idx];
+            sq += h * h / w.mr;
+            lc -= h * ((double)ep[idx + 1] - (double)ep[idx]);
+        }
+        if (j < nr && w.mz > 0.0) sq += (double)hz[idx] * (double)hz[idx] / w.mz;
+        acc += 0.5 * sq - 0.5 * a * a * r + a * lc;
+    }
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_rz_finish(const double* partial, int n, double* out)
+{
+    double v = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) v += partial[t];
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// Wakes in V/C: W_par = acc / (Q eps0) on both lines; W_perp by the trapezoidal
+// s-integral of (line jw+1 - line jw) / dr from the first sample.
+__global__ void k_rz_wakes(const double* acc, int nw, double scale, double dr, double ds, double* wpar,
+                           double* wperp)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double prev = 0.0, run = 0.0;
+    for (int j = 0; j < nw; ++j) {
+        const double a0 = acc[j] * scale, a1 = acc[nw + j] * scale;
+        wpar[j] = a0;
+        wpar[nw + j] = a1;
+        const double d = (a1 - a0) / dr;
+        if (j > 0) run += 0.5 * (d + prev) * ds;
+        wperp[j] = run;
+        prev = d;
+    }
+}
+
+size_t up(size_t v) { return (v + 255) / 256 * 256; }
+
+struct RZLayout {
+    size_t field[12], code, coef, raw, lamw, acc, partial, scal, wout, ptrs, total;
+};
+
+bool rz_valid(const tete_rz_desc* d)
+{
+    if (!d || d->nr < 2 || d->nz < 2 || d->mode < 0 || d->mode > 4096) return false;
+    if (d->precision != TETE_FP64 && d->precision != TETE_FP32) return false;
+    if (!(d->dr > 0.0) || !(d->dz > 0.0) || !(d->cdt > 0.0) || !isfinite(d->dr) || !isfinite(d->dz) ||
+        !isfinite(d->cdt))
+        return false;
+    const int64_t np = (int64_t)(d->nr + 1) * (d->nz + 1);
+    const int64_t rb = d->precision == TETE_FP32 ? 4 : 8;
+    return np * rb < ((int64_t)1 << 31) - 256;
+}
+
+RZLayout rz_layout(const tete_rz_desc* d)
+{
+    RZLayout L;
+    const size_t np = (size_t)(d->nr + 1) * (d->nz + 1);
+    const size_t rb = d->precision == TETE_FP32 ? 4 : 8;
+    size_t o = 0;
+    for (int c = 0; c < 12; ++c) { L.field[c] = o; o = up(o + rb * np); }
+    L.code = o;    o = up(o + np + 4);
+    L.coef = o;    o = up(o + 6 * rb * (size_t)(d->nr + 1 + 2 * kPad));
+    L.raw = o;     o = up(o + sizeof(Raw) * (size_t)(d->nr + 1));
+    L.lamw = o;    o = up(o + sizeof(double) * TETE_MAX_BUNCH_CELLS);
+    L.acc = o;     o = up(o + sizeof(double) * 2 * TETE_MAX_WAKE);
+    L.partial = o; o = up(o + sizeof(double) * kRedBlocks);
+    L.scal = o;    o = up(o + sizeof(double) * 8);
+    L.wout = o;    o = up(o + sizeof(double) * 3 * TETE_MAX_WAKE);
+    L.ptrs = o;    o = up(o + sizeof(void*) * 12);
+    L.total = o;
+    return L;
+}
+
+// Largest eigenvalue of the radial operator next to the axis for m = 0, in
+// units of 1/dr^2 (dual facet dr^2/8 on the axis): limits cdt to 2/sqrt(.) dr.
+constexpr double kAxisLambda = 4.8419422636;
+
+}  // namespace
+}  // namespace tete
+
+using namespace tete;
+
+struct tete_rz {
+    tete_rz_desc d;
+    hipStream_t stream;
+    int device;
+    char* ws;
+    RZLayout L;
+    int fp32;
+    void* f[2][6];
+    void** dptr;         // device copy of the 12 field pointers (set 0 then set 1)
+    int cur;
+    uint8_t* code;
+    void* coef;
+    Raw* raw;
+    double *lamw, *acc, *partial, *scal, *wout;
+    int64_t n;
+    int has_bunch;
+    tete_rz_bunch b;
+    int chunk_rows, prefetch;
+    int timing;
+    hipEvent_t* ev;
+    int64_t ev_cap, ev_used;
+};
+
+#define RZCHK(x)                                       \
+    do {                                               \
+        if ((x) != hipSuccess) return TETE_ERR_DEVICE; \
+    } while (0)
+
+namespace {
+
+// kappa, mu per radian (vacuum) and the update coefficients of radius j.
+void rz_raw(const tete_rz_desc* d, std::vector<Raw>& raw)
+{
+    const int nr = d->nr;
+    const double dr = d->dr, dz = d->dz;
+    raw.assign(nr + 1, Raw{0, 0, 0, 0, 0, 0});
+    for (int j = 0; j <= nr; ++j) {
+        const double r = j * dr, rh = (j + 0.5) * dr;
+        Raw& w = raw[j];
+        w.kp = j > 0 && j < nr ? r / (dr * dz) : 0.0;                          // wall e_phi is PEC
+        w.kr = j < nr ? dr / (rh * dz) : 0.0;
+        w.kz = j == 0 ? (d->mode == 0 ? dz / (dr * dr / 8.0) : 0.0) : (j < nr ? dz / (r * dr) : 0.0);
+        w.mp = j < nr ? rh / (dr * dz) : 0.0;
+        w.mr = j > 0 ? dr / (r * dz) : 0.0;
+        w.mz = j < nr ? dz / (rh * dr) : 0.0;
+    }
+}
+
+template <typename R>
+void rz_coef(const tete_rz_desc* d, const std::vector<Raw>& raw, std::vector<Coef<R>>& co)
+{
+    const double a = 0.5 * d->cdt, mm = (double)d->mode * (double)d->mode;
+    co.assign(d->nr + 1 + 2 * kPad, Coef<R>{0, 0, 0, 0, 0, 0});
+    for (int j = 0; j <= d->nr; ++j) {
+        const Raw& w = raw[j];
+        const double fe = 1.0 / (1.0 + a * a * mm * w.kz * w.mr);
+        const double fh = 1.0 / (1.0 + a * a * mm * w.mz * w.kr);
+        Coef<R>& c = co[j + kPad];
+        c.cp = (R)(a * w.kp);
+        c.cr = (R)(a * w.kr);
+        c.cz = (R)(fe * 2.0 * a * w.kz);
+        c.dp = (R)(a * w.mp);
+        c.dr = (R)(a * w.mr);
+        c.dz = (R)(fh * 2.0 * a * w.mz);
+    }
+}
+
+int rz_nzt(const tete_rz_desc* d) { return (d->nz + 1 + kOwn - 1) / kOwn; }
+
+// Rows per r-chunk: enough chunks for about 16 waves per compute unit (4096
+// waves), chunks of at least 16 rows.
+int rz_rows(const tete_rz* g)
+{
+    if (g->chunk_rows > 0) return g->chunk_rows;
+    const int nzt = rz_nzt(&g->d), rows = g->d.nr + 1;
+    const int want = std::max(1, (4096 + nzt - 1) / nzt);
+    return std::max(16, (rows + want - 1) / want);
+}
+
+template <typename R>
+hipError_t rz_launch(tete_rz* g, hipStream_t s)
+{
+    RZArgs<R> A;
+    const int in = g->cur, out = 1 - g->cur;
+    for (int c = 0; c < 6; ++c) {
+        A.o[c] = (const R*)g->f[in][c];
+        A.w[c] = (R*)g->f[out][c];
+    }
+    A.code = g->code;
+    A.coef = (const Coef<R>*)g->coef;
+    A.nr = g->d.nr;
+    A.nz = g->d.nz;
+    A.sz = g->d.nz + 1;
+    A.m = (R)g->d.mode;
+    A.nzt = rz_nzt(&g->d);
+    A.nzb = (A.nzt + kWaves - 1) / kWaves;
+    A.rows = rz_rows(g);
+    A.src = g->has_bunch;
+    A.j0 = g->b.j0;
+    A.M = g->b.half_cells;
+    A.jw = g->b.jw;
+    A.jmin = g->b.jmin;
+    A.nw = g->b.nw;
+    A.n = g->n;
+    A.lamw = g->lamw;
+    A.acc = g->acc;
+    const int nrc = (g->d.nr + 1 + A.rows - 1) / A.rows;
+    const dim3 grid((unsigned)(A.nzb * nrc)), block(kLanes * kWaves);
+    switch (g->prefetch > 0 ? g->prefetch : 2) {
+        case 1: k_rz<R, 1><<<grid, block, 0, s>>>(A); break;
+        case 3: k_rz<R, 3><<<grid, block, 0, s>>>(A); break;
+        case 4: k_rz<R, 4><<<grid, block, 0, s>>>(A); break;
+        default: k_rz<R, 2><<<grid, block, 0, s>>>(A); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t rz_sanitize(tete_rz* g, int set)
+{
+    R* const* p = (R* const*)(g->dptr + 6 * set);
+    k_rz_sanitize<R><<<512, 256, 0, g->stream>>>(p, g->code, g->raw, g->d.nr, g->d.nz);
+    return hipGetLastError();
+}
+
+hipError_t rz_sanitize_any(tete_rz* g, int set)
+{
+    return g->fp32 ? rz_sanitize<float>(g, set) : rz_sanitize<double>(g, set);
+}
+
+struct Guard {
+    int prev = -1;
+    bool ok = true;
+    explicit Guard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~Guard()
+    {
+        int c;
+        if (prev >= 0 && hipGetDevice(&c) == hipSuccess && c != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+tete_status tete_rz_check_desc(const tete_rz_desc* d)
+{
+    if (!rz_valid(d)) return TETE_ERR_ARG;
+    const double tol = 1.0 + 1e-12;
+    if (d->cdt > d->dz * tol) return TETE_ERR_UNSTABLE;
+    const double rlim = d->mode == 0 ? 2.0 / sqrt(kAxisLambda) * d->dr : d->dr;
+    if (d->cdt > rlim * tol) return TETE_ERR_UNSTABLE;
+    return TETE_OK;
+}
+
+size_t tete_rz_workspace_bytes(const tete_rz_desc* d)
+{
+    if (!rz_valid(d)) return 0;
+    return rz_layout(d).total;
+}
+
+tete_status tete_rz_create(const tete_rz_desc* d, void* dev_ws, size_t ws_bytes, void* hip_stream, tete_rz** out)
+{
+    if (!out || !dev_ws || ((uintptr_t)dev_ws & 255)) return TETE_ERR_ARG;
+    *out = nullptr;
+    const tete_status st = tete_rz_check_desc(d);
+    if (st != TETE_OK) return st;
+    const RZLayout L = rz_layout(d);
+    if (ws_bytes < L.total) return TETE_ERR_NOMEM;
+    tete_rz* g = (tete_rz*)calloc(1, sizeof(tete_rz));
+    if (!g) return TETE_ERR_NOMEM;
+    g->d = *d;
+    g->stream = (hipStream_t)hip_stream;
+    g->ws = (char*)dev_ws;
+    g->L = L;
+    g->fp32 = d->precision == TETE_FP32;
+    if (hipGetDevice(&g->device) != hipSuccess) { free(g); return TETE_ERR_DEVICE; }
+    for (int s = 0; s < 2; ++s)
+        for (int c = 0; c < 6; ++c) g->f[s][c] = g->ws + L.field[6 * s + c];
+    g->dptr = (void**)(g->ws + L.ptrs);
+    g->code = (uint8_t*)(g->ws + L.code);
+    g->coef = g->ws + L.coef;
+    g->raw = (Raw*)(g->ws + L.raw);
+    g->lamw = (double*)(g->ws + L.lamw);
+    g->acc = (double*)(g->ws + L.acc);
+    g->partial = (double*)(g->ws + L.partial);
+    g->scal = (double*)(g->ws + L.scal);
+    g->wout = (double*)(g->ws + L.wout);
+    std::vector<Raw> raw;
+    rz_raw(d, raw);
+    hipError_t e = hipMemsetAsync(g->ws, 0, L.total, g->stream);
+    void* ptrs[12];
+    for (int s = 0; s < 2; ++s)
+        for (int c = 0; c < 6; ++c) ptrs[6 * s + c] = g->f[s][c];
+    if (e == hipSuccess) e = hipMemcpyAsync(g->dptr, ptrs, sizeof(ptrs), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->raw, raw.data(), sizeof(Raw) * raw.size(), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) {
+        if (g->fp32) {
+            std::vector<Coef<float>> co;
+            rz_coef<float>(d, raw, co);
+            e = hipMemcpyAsync(g->coef, co.data(), sizeof(Coef<float>) * co.size(), hipMemcpyHostToDevice, g->stream);
+        } else {
+            std::vector<Coef<double>> co;
+            rz_coef<double>(d, raw, co);
+            e = hipMemcpyAsync(g->coef, co.data(), sizeof(Coef<double>) * co.size(), hipMemcpyHostToDevice,
+                               g->stream);
+        }
+    }
+    if (e == hipSuccess) {
+        k_rz_code<<<512, 256, 0, g->stream>>>(nullptr, g->code, d->nr, d->nz);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) { free(g); return TETE_ERR_DEVICE; }
+    *out = g;
+    return TETE_OK;
+}
+
+tete_status tete_rz_destroy(tete_rz* g)
+{
+    if (!g) return TETE_ERR_ARG;
+    if (g->ev) {
+        for (int64_t i = 0; i < 2 * g->ev_cap; ++i) (void)hipEventDestroy(g->ev[i]);
+        free(g->ev);
+    }
+    free(g);
+    return TETE_OK;
+}
+
+tete_status tete_rz_set_pec_cells(tete_rz* g, const uint8_t* cells)
+{
+    if (!g) return TETE_ERR_ARG;
+    Guard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    k_rz_code<<<512, 256, 0, g->stream>>>(cells, g->code, g->d.nr, g->d.nz);
+    RZCHK(hipGetLastError());
+    RZCHK(rz_sanitize_any(g, g->cur));
+    return TETE_OK;
+}
+
+tete_status tete_rz_set_fields(tete_rz* g, const void* const f[6], int32_t dtype)
+{
+    if (!g || !f || (dtype != TETE_FP64 && dtype != TETE_FP32)) return TETE_ERR_ARG;
+    for (int c = 0; c < 6; ++c)
+        if (!f[c]) return TETE_ERR_ARG;
+    Guard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    const int64_t np = (int64_t)(g->d.nr + 1) * (g->d.nz + 1);
+    for (int c = 0; c < 6; ++c) {
+        void* dst = g->f[g->cur][c];
+        if (g->fp32 && dtype == TETE_FP32)
+            k_rz_convert<float, float><<<512, 256, 0, g->stream>>>((float*)dst, (const float*)f[c], np);
+        else if (g->fp32)
+            k_rz_convert<float, double><<<512, 256, 0, g->stream>>>((float*)dst, (const double*)f[c], np);
+        else if (dtype == TETE_FP32)
+            k_rz_convert<double, float><<<512, 256, 0, g->stream>>>((double*)dst, (const float*)f[c], np);
+        else
+            k_rz_convert<double, double><<<512, 256, 0, g->stream>>>((double*)dst, (const double*)f[c], np);
+        RZCHK(hipGetLastError());
+    }
+    RZCHK(rz_sanitize_any(g, g->cur));
+    RZCHK(hipMemsetAsync(g->acc, 0, sizeof(double) * 2 * TETE_MAX_WAKE, g->stream));
+    g->n = 0;
+    return TETE_OK;
+}
+
+tete_status tete_rz_get_fields(tete_rz* g, void* const f[6], int32_t dtype)
+{
+    if (!g || !f || (dtype != TETE_FP64 && dtype != TETE_FP32)) return TETE_ERR_ARG;
+    for (int c = 0; c < 6; ++c)
+        if (!f[c]) return TETE_ERR_ARG;
+    Guard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    const int64_t np = (int64_t)(g->d.nr + 1) * (g->d.nz + 1);
+    for (int c = 0; c < 6; ++c) {
+        const void* src = g->f[g->cur][c];
+        if (g->fp32 && dtype == TETE_FP32)
+            k_rz_convert<float, float><<<512, 256, 0, g->stream>>>((float*)f[c], (const float*)src, np);
+        else if (g->fp32)
+            k_rz_convert<double, float><<<512, 256, 0, g->stream>>>((double*)f[c], (const float*)src, np);
+        else if (dtype == TETE_FP32)
+            k_rz_convert<float, double><<<512, 256, 0, g->stream>>>((float*)f[c], (const double*)src, np);
+        else
+            k_rz_convert<double, double><<<512, 256, 0, g->stream>>>((double*)f[c], (const double*)src, np);
+        RZCHK(hipGetLastError());
+    }
+    RZCHK(hipStreamSynchronize(g->stream));
+    return TETE_OK;
+}
+
+tete_status tete_rz_set_bunch(tete_rz* g, const tete_rz_bunch* b)
+{
+    if (!g || !b) return TETE_ERR_ARG;
+    const int M = b->half_cells;
+    if (!(b->charge_C > 0.0) || !(b->sigma_z > 0.0) || !isfinite(b->charge_C) || !isfinite(b->sigma_z))
+        return TETE_ERR_ARG;
+    if (M < 0 || 2 * M + 1 > TETE_MAX_BUNCH_CELLS || b->nw < 1 || b->nw > TETE_MAX_WAKE) return TETE_ERR_ARG;
+    if (b->j0 < 0 || b->j0 >= g->d.nr || (g->d.mode > 0 && b->j0 == 0)) return TETE_ERR_ARG;
+    if (b->jw < 0 || b->jw + 1 >= g->d.nr || (g->d.mode > 0 && b->jw == 0)) return TETE_ERR_ARG;
+    if (fabs(g->d.cdt - g->d.dz) > 1e-12 * g->d.dz) return TETE_ERR_STATE;
+    Guard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    // cell charges of the truncated Gaussian (Fig. 1), times the harmonic
+    // weight, as the current through a dual facet during one step
+    const double w = g->d.mode == 0 ? 1.0 / (2.0 * kPi) : 1.0 / kPi;
+    std::vector<double> lam(2 * M + 1);
+    for (int mm = -M; mm <= M; ++mm) {
+        const double lo = (mm - 0.5) * g->d.dz / b->sigma_z, hi = (mm + 0.5) * g->d.dz / b->sigma_z;
+        double v;
+        if (lo >= 0.0) v = 0.5 * (erfc(lo / sqrt(2.0)) - erfc(hi / sqrt(2.0)));
+        else if (hi <= 0.0) v = 0.5 * (erfc(-hi / sqrt(2.0)) - erfc(-lo / sqrt(2.0)));
+        else v = 1.0 - 0.5 * erfc(-lo / sqrt(2.0)) - 0.5 * erfc(hi / sqrt(2.0));
+        lam[mm + M] = w * b->charge_C * v / g->d.cdt;
+    }
+    RZCHK(hipMemcpyAsync(g->lamw, lam.data(), sizeof(double) * lam.size(), hipMemcpyHostToDevice, g->stream));
+    RZCHK(hipMemsetAsync(g->acc, 0, sizeof(double) * 2 * TETE_MAX_WAKE, g->stream));
+    RZCHK(hipStreamSynchronize(g->stream));
+    g->b = *b;
+    g->has_bunch = 1;
+    return TETE_OK;
+}
+
+tete_status tete_rz_step(tete_rz* g, int64_t nsteps)
+{
+    if (!g || nsteps < 0) return TETE_ERR_ARG;
+    Guard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const bool rec = g->timing && g->ev_used < g->ev_cap;
+        if (rec) RZCHK(hipEventRecord(g->ev[2 * g->ev_used], g->stream));
+        RZCHK(g->fp32 ? rz_launch<float>(g, g->stream) : rz_launch<double>(g, g->stream));
+        if (rec) {
+            RZCHK(hipEventRecord(g->ev[2 * g->ev_used + 1], g->stream));
+            ++g->ev_used;
+        }
+        g->cur = 1 - g->cur;
+        ++g->n;
+    }
+    return TETE_OK;
+}
+
+tete_status tete_rz_steps_done(tete_rz* g, int64_t* n)
+{
+    if (!g || !n) return TETE_ERR_ARG;
+    *n = g->n;
+    return TETE_OK;
+}
+
+tete_status tete_rz_wake(tete_rz* g, double* W_par, double* W_perp, int32_t nw)
+{
+    if (!g || !W_par || !g->has_bunch || nw < 1 || nw > g->b.nw) return TETE_ERR_ARG;
+    Guard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    const int n = g->b.nw;
+    k_rz_wakes<<<1, 64, 0, g->stream>>>(g->acc, n, 1.0 / (g->b.charge_C * kEps0), g->d.dr, g->d.dz, g->wout,
+                                        g->wout + 2 * n);
+    RZCHK(hipGetLastError());
+    RZCHK(hipMemcpyAsync(W_par, g->wout, sizeof(double) * nw, hipMemcpyDeviceToHost, g->stream));
+    RZCHK(hipMemcpyAsync(W_par + nw, g->wout + n, sizeof(double) * nw, hipMemcpyDeviceToHost, g->stream));
+    if (W_perp)
+        RZCHK(hipMemcpyAsync(W_perp, g->wout + 2 * n, sizeof(double) * nw, hipMemcpyDeviceToHost, g->stream));
+    RZCHK(hipStreamSynchronize(g->stream));
+    return TETE_OK;
+}
+
+tete_status tete_rz_energy(tete_rz* g, double* W, int64_t* n)
+{
+    if (!g || !W) return TETE_ERR_ARG;
+    Guard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    const double a = 0.5 * g->d.cdt;
+    if (g->fp32)
+        k_rz_energy<float><<<kRedBlocks, kRedThreads, 0, g->stream>>>(
+            (const float* const*)(g->dptr + 6 * g->cur), g->code, g->raw, g->d.nr, g->d.nz, a, g->partial);
+    else
+        k_rz_energy<double><<<kRedBlocks, kRedThreads, 0, g->stream>>>(
+            (const double* const*)(g->dptr + 6 * g->cur), g->code, g->raw, g->d.nr, g->d.nz, a, g->partial);
+    RZCHK(hipGetLastError());
+    k_rz_finish<<<1, kRedThreads, 0, g->stream>>>(g->partial, kRedBlocks, g->scal);
+    RZCHK(hipGetLastError());
+    RZCHK(hipMemcpyAsync(W, g->scal, sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    RZCHK(hipStreamSynchronize(g->stream));
+    if (n) *n = g->n;
+    return isfinite(*W) ? TETE_OK : TETE_ERR_NONFINITE;
+}
+
+tete_status tete_rz_set_tuning(tete_rz* g, int32_t chunk_rows, int32_t prefetch)
+{
+    if (!g || chunk_rows < 0 || (chunk_rows > 0 && (chunk_rows < 8 || chunk_rows > 4096)) || prefetch < 0 ||
+        prefetch > 4)
+        return TETE_ERR_ARG;
+    g->chunk_rows = chunk_rows;
+    g->prefetch = prefetch;
+    return TETE_OK;
+}
+
+tete_status tete_rz_set_timing(tete_rz* g, int64_t max_launches)
+{
+    if (!g || max_launches < 0 || max_launches > (1 << 20)) return TETE_ERR_ARG;
+    Guard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    RZCHK(hipStreamSynchronize(g->stream));
+    if (g->ev) {
+        for (int64_t i = 0; i < 2 * g->ev_cap; ++i) (void)hipEventDestroy(g->ev[i]);
+        free(g->ev);
+        g->ev = nullptr;
+    }
+    g->ev_cap = g->ev_used = 0;
+    g->timing = 0;
+    if (max_launches == 0) return TETE_OK;
+    g->ev = (hipEvent_t*)calloc((size_t)(2 * max_launches), sizeof(hipEvent_t));
+    if (!g->ev) return TETE_ERR_NOMEM;
+    for (int64_t i = 0; i < 2 * max_launches; ++i) {
+        if (hipEventCreate(&g->ev[i]) != hipSuccess) {
+            for (int64_t t = 0; t < i; ++t) (void)hipEventDestroy(g->ev[t]);
+            free(g->ev);
+            g->ev = nullptr;
+            return TETE_ERR_DEVICE;
+        }
+    }
+    g->ev_cap = max_launches;
+    g->timing = 1;
+    return TETE_OK;
+}
+
+tete_status tete_rz_timing(tete_rz* g, double* ms, int64_t* launches)
+{
+    if (!g || !ms || !launches) return TETE_ERR_ARG;
+    Guard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    RZCHK(hipStreamSynchronize(g->stream));
+    double sum = 0.0;
+    for (int64_t i = 0; i < g->ev_used; ++i) {
+        float t = 0.0f;
+        RZCHK(hipEventElapsedTime(&t, g->ev[2 * i], g->ev[2 * i + 1]));
+        sum += t;
+    }
+    *ms = sum;
+    *launches = g->ev_used;
+    return TETE_OK;
+}
+
+}  // extern "C"

@@ -303,3 +303,108 @@ def serve_cases(count: int = 200, seed: int = 20260905, nts=(64, 128, 192, 256),
     """Requests of the serving workload: geometry and sigma as in the batched
     workload, grids from 64^2 x 256 to 256^2 x 2048 (seeded)."""
     return batched_cases(count, seed, nts=nts, nzs=nzs)
+
+
+# ---------------------------------------------------------------------------
+# Rotationally symmetric (r-z) inputs.  Arrays of shape (nr+1, nz+1), z
+# fastest, components e_phi, e_r, e_z, h_phi, h_r, h_z (FIT voltages per
+# radian); cell masks (nr, nz) for cells (j+1/2, k+1/2).
+# ---------------------------------------------------------------------------
+RZ_KEYS = ("ephi", "er", "ez", "hphi", "hr", "hz")
+
+
+def rz_random_fields(shape, seed: int, scale: float = 1.0) -> dict:
+    """Independent N(0, scale^2) values in every entry of every r-z component."""
+    rng = np.random.default_rng(seed)
+    return {k: scale * rng.standard_normal(shape) for k in RZ_KEYS}
+
+
+def rz_random_cells(nr: int, nz: int, seed: int, frac: float = 0.08) -> np.ndarray:
+    """Random staircase obstacles in the r-z plane."""
+    rng = np.random.default_rng(seed)
+    return (rng.random((nr, nz)) < frac).astype(np.uint8)
+
+
+def disk_loaded_cells(nr, nz, dr, dz, a_iris, period, t_iris, z0, ncell) -> np.ndarray:
+    """Disk-loaded waveguide (the outer wall is the grid's r = nr dr): irises of
+    aperture radius a_iris and thickness t_iris at the start of each of ncell
+    periods from z0, and a beam pipe of radius a_iris before and after the
+    structure.  A cell (j+1/2, k+1/2) is PEC if its centre is metal."""
+    rc = (np.arange(nr) + 0.5) * dr
+    zc = (np.arange(nz) + 0.5) * dz
+    zend = z0 + ncell * period + t_iris
+    inside = (zc >= z0) & (zc < zend)
+    ph = np.mod(zc - z0, period)
+    iris = inside & (ph < t_iris)
+    metal_z = ~inside | iris                      # pipe or iris: metal outside a_iris
+    return (metal_z[None, :] & (rc[:, None] > a_iris)).astype(np.uint8)
+
+
+@dataclass
+class RZCase:
+    """One rotationally symmetric wake solve: grid, harmonic, ring bunch and
+    wake lines (sizes in metres, charge in coulombs)."""
+    name: str
+    nr: int
+    nz: int
+    dr: float
+    dz: float
+    mode: int
+    sigma: float
+    r0: float            # ring radius (0 = the axis, m = 0)
+    a_iris: float
+    period: float
+    t_iris: float
+    z0: float
+    ncell: int
+    charge: float = 1e-9
+    s_lo: float = -5.0
+    s_hi: float = 50.0
+
+    @property
+    def cdt(self) -> float:
+        return self.dz
+
+    @property
+    def M(self) -> int:
+        return trunc_cells(self.sigma, self.dz)
+
+    @property
+    def j0(self) -> int:
+        return int(round(self.r0 / self.dr))
+
+    @property
+    def jw(self) -> int:
+        return max(self.j0, 1 if self.mode > 0 else 0)
+
+    def window(self):
+        return wake_window(self.sigma, self.dz, self.s_lo, self.s_hi)
+
+    def cells(self) -> np.ndarray:
+        return disk_loaded_cells(self.nr, self.nz, self.dr, self.dz, self.a_iris, self.period, self.t_iris,
+                                 self.z0, self.ncell)
+
+    def steps(self) -> int:
+        """Steps until the last wake sample is complete."""
+        jmin, nw = self.window()
+        return self.nz - 1 + self.M + jmin + nw
+
+
+def tds_case(mode: int = 1) -> RZCase:
+    """Transverse-deflecting-structure-like workload (the paper's first example,
+    whose geometry is not given): a 15-period disk-loaded structure of 30 mm
+    outer radius, iris aperture 11 mm, period 33.3 mm, irises 6 mm thick, with
+    20 mm pipes on both sides; sigma = 300 um at dr = dz = 30 um (sigma / dz = 10,
+    the paper's fine mesh); dipole ring at r0 = 1 mm."""
+    dz = 30e-6
+    L = 0.02 + 15 * 0.0333 + 0.006 + 0.02
+    return RZCase("tds_rz", nr=1000, nz=int(round(L / dz)), dr=dz, dz=dz, mode=mode, sigma=300e-6,
+                  r0=1e-3 if mode > 0 else 0.0, a_iris=11e-3, period=0.0333, t_iris=6e-3, z0=0.02, ncell=15)
+
+
+def small_rz_case(mode: int = 1) -> RZCase:
+    """A scaled version for parity tests: 3 periods, 24 x 260 cells."""
+    dz = 1e-3
+    dr = dz if mode > 0 else 1.25 * dz           # m = 0: the axis cell needs dtau < 0.909 dr
+    return RZCase("small_rz", nr=24, nz=260, dr=dr, dz=dz, mode=mode, sigma=3e-3,
+                  r0=3 * dr if mode > 0 else 0.0, a_iris=9 * dr, period=0.06, t_iris=0.01, z0=0.04, ncell=3)

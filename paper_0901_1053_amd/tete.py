@@ -53,6 +53,19 @@ class Bunch(C.Structure):
                 ("half_cells", C.c_int32), ("jmin", C.c_int32), ("nw", C.c_int32)]
 
 
+RZ_KEYS = ("ephi", "er", "ez", "hphi", "hr", "hz")
+
+
+class RZDesc(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("nz", C.c_int32), ("dr", C.c_double), ("dz", C.c_double),
+                ("cdt", C.c_double), ("mode", C.c_int32), ("precision", C.c_int32)]
+
+
+class RZBunch(C.Structure):
+    _fields_ = [("charge_C", C.c_double), ("sigma_z", C.c_double), ("j0", C.c_int32), ("half_cells", C.c_int32),
+                ("jw", C.c_int32), ("jmin", C.c_int32), ("nw", C.c_int32)]
+
+
 _lib = None
 P6 = C.c_void_p * 6
 P3 = C.c_void_p * 3
@@ -100,6 +113,21 @@ def load(path: str = LIB_PATH):
         "tete_batch_step": (st, [vp, C.c_int64]),
         "tete_batch_count": (st, [vp, C.POINTER(C.c_int32)]),
         "tete_status_str": (C.c_char_p, [C.c_int]),
+        "tete_rz_check_desc": (st, [C.POINTER(RZDesc)]),
+        "tete_rz_workspace_bytes": (C.c_size_t, [C.POINTER(RZDesc)]),
+        "tete_rz_create": (st, [C.POINTER(RZDesc), vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "tete_rz_destroy": (st, [vp]),
+        "tete_rz_set_pec_cells": (st, [vp, vp]),
+        "tete_rz_set_fields": (st, [vp, P6, C.c_int32]),
+        "tete_rz_get_fields": (st, [vp, P6, C.c_int32]),
+        "tete_rz_set_bunch": (st, [vp, C.POINTER(RZBunch)]),
+        "tete_rz_step": (st, [vp, C.c_int64]),
+        "tete_rz_steps_done": (st, [vp, C.POINTER(C.c_int64)]),
+        "tete_rz_wake": (st, [vp, vp, vp, C.c_int32]),
+        "tete_rz_energy": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "tete_rz_set_tuning": (st, [vp, C.c_int32, C.c_int32]),
+        "tete_rz_set_timing": (st, [vp, C.c_int64]),
+        "tete_rz_timing": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -347,3 +375,127 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def make_rz_desc(nr, nz, dr, dz, cdt, mode=0, precision="fp64") -> RZDesc:
+    return RZDesc(nr, nz, dr, dz, cdt, mode, {"fp64": FP64, "fp32": FP32}[precision])
+
+
+def rz_check_desc(desc: RZDesc) -> str:
+    return STATUS[load().tete_rz_check_desc(C.byref(desc))]
+
+
+class RZGrid:
+    """One r-z grid of the rotationally symmetric scheme (24) at azimuthal
+    harmonic `mode`, living in a torch-owned device workspace."""
+
+    def __init__(self, nr, nz, dr, dz, cdt, mode=0, precision="fp64", device="cuda:0", stream=None):
+        import torch
+        L = load()
+        self.torch = torch
+        self.desc = make_rz_desc(nr, nz, dr, dz, cdt, mode, precision)
+        _chk("tete_rz_check_desc", L.tete_rz_check_desc(C.byref(self.desc)))
+        self.nbytes = int(L.tete_rz_workspace_bytes(C.byref(self.desc)))
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        assert self.ws.data_ptr() % 256 == 0
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _chk("tete_rz_create", L.tete_rz_create(C.byref(self.desc), C.c_void_p(self.ws.data_ptr()), self.nbytes,
+                                                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.nr, self.nz, self.dr, self.dz, self.cdt, self.mode = nr, nz, dr, dz, cdt, mode
+        self.precision = precision
+        self.shape = (nr + 1, nz + 1)
+        self.np = (nr + 1) * (nz + 1)
+        self.bunch = None
+
+    def _dev(self, a, dtype):
+        t = self.torch
+        if isinstance(a, np.ndarray):
+            a = t.from_numpy(np.ascontiguousarray(a))
+        return a.to(device=self.device, dtype=dtype).contiguous()
+
+    def close(self):
+        if self.h:
+            load().tete_rz_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_pec_cells(self, cells):
+        t = self.torch
+        if cells is None:
+            _chk("tete_rz_set_pec_cells", load().tete_rz_set_pec_cells(self.h, None))
+            return
+        d = self._dev(cells, t.uint8)
+        assert tuple(d.shape) == (self.nr, self.nz)
+        _chk("tete_rz_set_pec_cells", load().tete_rz_set_pec_cells(self.h, C.c_void_p(d.data_ptr())))
+        self.stream.synchronize()
+
+    def set_fields(self, f: dict, dtype="fp64"):
+        t = self.torch
+        td = t.float64 if dtype == "fp64" else t.float32
+        arrs = [self._dev(f[k], td) for k in RZ_KEYS]
+        for a in arrs:
+            assert a.numel() == self.np
+        _chk("tete_rz_set_fields", load().tete_rz_set_fields(self.h, P6(*[a.data_ptr() for a in arrs]),
+                                                             FP64 if dtype == "fp64" else FP32))
+        self.stream.synchronize()
+
+    def get_fields(self, dtype="fp64", numpy=True):
+        t = self.torch
+        td = t.float64 if dtype == "fp64" else t.float32
+        arrs = [t.empty(self.shape, dtype=td, device=self.device) for _ in RZ_KEYS]
+        _chk("tete_rz_get_fields", load().tete_rz_get_fields(self.h, P6(*[a.data_ptr() for a in arrs]),
+                                                             FP64 if dtype == "fp64" else FP32))
+        if numpy:
+            return {k: a.cpu().numpy() for k, a in zip(RZ_KEYS, arrs)}
+        return dict(zip(RZ_KEYS, arrs))
+
+    def set_bunch(self, charge, sigma, j0, half_cells, jw, jmin, nw):
+        self.bunch = RZBunch(charge, sigma, j0, half_cells, jw, jmin, nw)
+        _chk("tete_rz_set_bunch", load().tete_rz_set_bunch(self.h, C.byref(self.bunch)))
+
+    def step(self, n: int):
+        _chk("tete_rz_step", load().tete_rz_step(self.h, int(n)))
+
+    def steps_done(self) -> int:
+        v = C.c_int64()
+        _chk("tete_rz_steps_done", load().tete_rz_steps_done(self.h, C.byref(v)))
+        return v.value
+
+    def wake(self):
+        """(W_par of shape (2, nw): lines jw and jw+1, W_perp of shape (nw,)) in V/C."""
+        nw = self.bunch.nw
+        wp = np.zeros(2 * nw)
+        wt = np.zeros(nw)
+        _chk("tete_rz_wake", load().tete_rz_wake(self.h, wp.ctypes.data, wt.ctypes.data, nw))
+        return wp.reshape(2, nw), wt
+
+    def wake_s(self) -> np.ndarray:
+        return (self.bunch.jmin + np.arange(self.bunch.nw)) * self.dz
+
+    def energy(self):
+        w = C.c_double()
+        n = C.c_int64()
+        _chk("tete_rz_energy", load().tete_rz_energy(self.h, C.byref(w), C.byref(n)))
+        return w.value, n.value
+
+    def set_tuning(self, chunk_rows=0, prefetch=0):
+        _chk("tete_rz_set_tuning", load().tete_rz_set_tuning(self.h, chunk_rows, prefetch))
+
+    def set_timing(self, max_launches: int):
+        _chk("tete_rz_set_timing", load().tete_rz_set_timing(self.h, int(max_launches)))
+
+    def timing(self):
+        """(summed kernel ms, launches timed)."""
+        ms = C.c_double()
+        n = C.c_int64()
+        _chk("tete_rz_timing", load().tete_rz_timing(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value

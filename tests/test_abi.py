@@ -84,3 +84,36 @@ def test_workspace_bytes():
     dm = tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp64", materials=True)
     assert tete.workspace_bytes(dm) >= b64 + 6 * 8 * np_
     assert tete.workspace_bytes(tete.make_desc(1, 1, 1, 2, 2, 1, 1)) == 0
+
+
+@pytest.mark.parametrize("mode,dr,dz,cdt,want", [
+    (1, 1e-3, 1e-3, 1e-3, "TETE_OK"),              # dtau = dz = dr, any m >= 1
+    (40, 1e-3, 1e-3, 1e-3, "TETE_OK"),             # independent of m
+    (1, 0.9e-3, 1e-3, 1e-3, "TETE_ERR_UNSTABLE"),  # above dr
+    (2, 1e-3, 1e-3, 1.001e-3, "TETE_ERR_UNSTABLE"),  # above dz
+    (0, 1e-3, 1e-3, 1e-3, "TETE_ERR_UNSTABLE"),    # m = 0: the on-axis cell limits dtau to 0.9089 dr
+    (0, 1.1e-3, 1e-3, 1e-3, "TETE_ERR_UNSTABLE"),  # 0.9089 * 1.1 dz < dz
+    (0, 1.2e-3, 1e-3, 1e-3, "TETE_OK"),
+    (0, 1e-3, 1e-3, 0.9085e-3, "TETE_OK"),
+    (0, 1e-3, 1e-3, 0.9095e-3, "TETE_ERR_UNSTABLE"),
+    (-1, 1e-3, 1e-3, 1e-3, "TETE_ERR_ARG"),
+    (1, 1e-3, 0.0, 1e-3, "TETE_ERR_ARG"),
+])
+def test_rz_stability_validation(mode, dr, dz, cdt, want):
+    """r-z grids: dtau <= min(dz, dr) whatever m (Sec. 4.4), and 0.9089 dr for m = 0."""
+    assert tete.rz_check_desc(tete.make_rz_desc(64, 256, dr, dz, cdt, mode)) == want
+
+
+def test_rz_descriptor_limits_and_workspace():
+    L = tete.load()
+    assert tete.rz_check_desc(tete.make_rz_desc(1, 8, 1.2, 1, 1, 0)) == "TETE_ERR_ARG"
+    assert tete.rz_check_desc(tete.make_rz_desc(2, 2, 1.2, 1, 1, 0)) == "TETE_OK"
+    # FP64 arrays must stay below 2^31 bytes (buffer addressing); FP32 may be twice as large
+    big = tete.make_rz_desc(8191, 32767, 1.2, 1, 1, 0, "fp64")
+    assert tete.rz_check_desc(big) == "TETE_ERR_ARG"
+    assert tete.rz_check_desc(tete.make_rz_desc(8191, 32767, 1.2, 1, 1, 0, "fp32")) == "TETE_OK"
+    d = tete.make_rz_desc(100, 1000, 1.2, 1, 1, 0, "fp32")
+    np_ = 101 * 1001
+    b = int(L.tete_rz_workspace_bytes(C.byref(d)))
+    assert b >= 12 * 4 * np_ + np_
+    assert int(L.tete_rz_workspace_bytes(C.byref(big))) == 0
