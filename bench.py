@@ -42,7 +42,7 @@ def measured_traffic(kernel_name, workload, precision):
         return None
     if sha != t["source_sha256"] or t["workload"] != workload or t["precision"] != precision:
         return None
-    if not kernel_name.startswith("k_fused"):
+    if not (kernel_name.startswith("k_fused") or kernel_name == "k_rz"):
         return None
     return t["read_bytes_per_launch"] + t["write_bytes_per_launch"]
 METRIC = "Gcell-updates/s + HBM GB/s; batched wake solves/s with p50/p99 latency"
@@ -214,17 +214,21 @@ def rz_section(steps=100, warmup=5):
         e1.record(G.stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
-        kms, n = G.timing()
+        kms, n, nst = G.timing()
         G.set_timing(0)
         b = 4 if prec == "fp32" else 8
-        kbytes = (12 * b + 1) * G.np
+        per = nst // n                                   # steps per launch (two-step kernel: 2)
+        kbytes = (12 * b + 1) * G.np * per               # one cell-update per entry and step
         achieved = kbytes / (kms / n / 1e3) / 1e9
+        traffic = measured_traffic("k_rz", case.name, prec)
         res[prec] = {"gcell_updates_per_s": round(case.nr * case.nz * steps / (ms / 1e3) / 1e9, 2),
                      "ms_per_step": round(ms / steps, 4),
-                     "roofline": {"bound": "hbm", "kernel": "k_rz", "achieved": round(achieved, 1),
+                     "roofline": {"bound": "hbm", "kernel": "k_rz", "steps_per_launch": per,
+                                  "achieved": round(achieved, 1),
                                   "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                                   "frac": round(achieved / PEAK_HBM_GBPS, 4), "bytes_per_launch": kbytes,
-                                  "ms_per_launch": round(kms / n, 4)},
+                                  "ms_per_launch": round(kms / n, 4), "traffic": traffic,
+                                  "traffic_gbps": round(traffic / (kms / n / 1e3) / 1e9, 1) if traffic else None},
                      "solve_s_estimate": round(ms / steps * case.steps() / 1e3, 2)}
         G.close()
         del G

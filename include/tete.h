@@ -402,7 +402,7 @@ typedef struct {
 } tete_rz_bunch;
 tete_status tete_rz_set_bunch(tete_rz* g, const tete_rz_bunch* b);
 
-/* Enqueue nsteps steps of (24) (asynchronous; one kernel launch per step).
+/* Enqueue nsteps steps of (24) (asynchronous; one or two steps per launch).
  * Errors: TETE_ERR_ARG (nsteps < 0), TETE_ERR_DEVICE. */
 tete_status tete_rz_step(tete_rz* g, int64_t nsteps);
 
@@ -422,15 +422,21 @@ tete_status tete_rz_wake(tete_rz* g, double* W_par, double* W_perp, int32_t nw);
  * internal units, per radian; *n = steps done.  Synchronises. */
 tete_status tete_rz_energy(tete_rz* g, double* W, int64_t* n);
 
-/* Launch tuning of the r-z kernel: rows per r-chunk (0 = automatic, else
- * 8 .. 4096) and loads issued ahead (0 = automatic, else 1 .. 4). */
-tete_status tete_rz_set_tuning(tete_rz* g, int32_t chunk_rows, int32_t prefetch);
+/* Launch tuning of the r-z kernel: kernel TETE_KERNEL_AUTO or
+ * TETE_KERNEL_FUSED2 (two steps per launch: a second march stage follows the
+ * first two rows behind it in the same wave, so each cell is read and written
+ * once per two steps; an odd last step runs alone) or TETE_KERNEL_FUSED (one
+ * step per launch); rows per r-chunk (0 = automatic, else 8 .. 4096), rows
+ * loaded ahead (0 = automatic, else 1 .. 4) and the workgroup order (0 =
+ * automatic, 1 = the r-chunks of a z-column consecutive, 2 = the z-strips of
+ * a chunk consecutive).  Results do not depend on it. */
+tete_status tete_rz_set_tuning(tete_rz* g, int32_t kernel, int32_t chunk_rows, int32_t prefetch, int32_t order);
 
 /* Live kernel timing: max_launches > 0 records HIP events around each step
- * launch (0 disables); tete_rz_timing returns the summed kernel time [ms]
- * and the launches recorded.  Synchronises. */
+ * launch (0 disables); tete_rz_timing returns the summed kernel time [ms],
+ * the launches recorded and the steps they took.  Synchronises. */
 tete_status tete_rz_set_timing(tete_rz* g, int64_t max_launches);
-tete_status tete_rz_timing(tete_rz* g, double* ms, int64_t* launches);
+tete_status tete_rz_timing(tete_rz* g, double* ms, int64_t* launches, int64_t* steps);
 
 /* Human-readable status name. */
 const char* tete_status_str(tete_status s);

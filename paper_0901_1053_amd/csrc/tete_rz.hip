@@ -28,9 +28,9 @@ namespace {
 
 constexpr double kEps0 = 8.8541878128e-12;   // vacuum permittivity [F/m] (CODATA 2018)
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kLanes = 64, kOwn = 62;        // lanes per wave, owned k per wave
+constexpr int kLanes = 64;                   // lanes per wave
 constexpr int kWaves = 4;                    // waves (z-strips) per workgroup
-constexpr int kPad = 2;                      // coefficient rows below 0 and above nr
+constexpr int kPad = 4;                      // coefficient rows below 0 and above nr
 constexpr int kRedBlocks = 1024, kRedThreads = 256;
 
 // Node code bits: e edge PEC or absent; HK = no h_phi / h_r at this k (k = nz).
@@ -58,35 +58,122 @@ struct RZArgs {
     int nr, nz, sz;         // sz = nz + 1
     R m;                    // harmonic m
     int nzt, nzb, rows;     // z-strips, workgroups along z, rows per chunk
+    int nrc, order;         // r-chunks, workgroup order (1: chunks fastest, 2: strips fastest)
     int src, j0, M, jw, jmin, nw;
     int64_t n;              // step being taken
     const double* lamw;     // 2M+1: harmonic weight * cell charge / dtau
-    double* acc;            // 2 x nw wake accumulators (lines jw, jw+1)
+    double* acc;            // [step parity][line jw, jw+1][nw] wake accumulators
 };
 
 template <typename R>
 struct Row {
     R ez, er, ep, hp, hr, hz;
-    uint32_t c;
+    uint32_t c;             // the dword holding the node's code byte (loaded rows)
 };
 
-template <typename R, int PF>
+// Values of one row after a step.
+template <typename R>
+struct Fin {
+    R hp, hr, ez, ep, er, hz;
+};
+
+// March state of one step along r.  With q the row it takes in: old values
+// of row q-1, the partial results of row q-2 and the new h_z of row q-3.
+// advance() runs S1, S2, S3, S5, S6 at row q-1 and S4, S7, S8, S9, S10 at row
+// q-2, which it returns final.  The PEC / absence bits zero the coefficient of
+// a masked entry (x + 0 * d == x) instead of selecting the result: a select
+// around an update can be compiled into a branch, and a lane shift inside it
+// would then read 0 from the lanes the branch disables.
+template <typename R>
+struct Stage {
+    R EZ1 = 0, ER1 = 0, EP1 = 0, HP1 = 0, HR1 = 0, HZ1 = 0;
+    uint32_t C1 = C_ALL;
+    R HZ2 = 0, HPn2 = 0, EZh2 = 0, ER2 = 0, HRh2 = 0, EPh2 = 0;
+    uint32_t C2 = C_ALL;
+    R HZn3 = 0;
+
+    // src(C1, cz1, ez_old, ez_new) adds the current to e_z of row q-1 and
+    // accumulates the wake there.
+    template <typename F>
+    __device__ __forceinline__ Fin<R> advance(const Row<R>& cur, uint32_t cq, const Coef<R>& c1,
+                                              const Coef<R>& c2, R m, F&& src)
+    {
+        const R hp1 = (C1 & C_HK) ? (R)0 : c1.dp, hr1c = (C1 & C_HK) ? (R)0 : c1.dr;
+        const R ez1c = (C1 & C_EZ) ? (R)0 : c1.cz, ep1c = (C1 & C_EPHI) ? (R)0 : c1.cp;
+        const R hp2 = (C2 & C_HK) ? (R)0 : c2.dp, er2c = (C2 & C_ER) ? (R)0 : c2.cr;
+        const R ep2c = (C2 & C_EPHI) ? (R)0 : c2.cp;
+
+        // S1 at q-1: h_phi^n = h_phi^{n-1/2} + a mu_phi [P_z e_r^n - P_r e_z^{n-1/2}]
+        const R hpn1 = HP1 + hp1 * ((lane_next(ER1) - ER1) - (cur.ez - EZ1));
+        // S2 at q-1: h_r^n = h_r^{n-1/2} + a mu_r [-P_z e_phi^n + m e_z^{n-1/2}]
+        const R pzEP1 = lane_next(EP1) - EP1;
+        const R hrn1 = HR1 + hr1c * (m * EZ1 - pzEP1);
+        // S3 at q-1: e_z^{n+1/2} = e_z^{n-1/2} + f_e 2a kappa_z [P_r^* h_phi^n - m h_r^n - j_z^n]
+        R ezh1 = EZ1 + ez1c * ((HPn2 - hpn1) - m * hrn1);
+        src(C1, c1.cz, EZ1, ezh1);
+        // S5 at q-1: h_r^{n+1/2} = h_r^n + a mu_r [-P_z e_phi^n + m e_z^{n+1/2}]
+        const R hrh1 = hrn1 + hr1c * (m * ezh1 - pzEP1);
+        // S6 at q-1: e_phi^{n+1/2} = e_phi^n + a kappa_phi [P_z^* h_r^{n+1/2} - P_r^* h_z^n]
+        const R eph1 = EP1 + ep1c * ((lane_prev(hrh1) - hrh1) - (HZ2 - HZ1));
+        // S4 at q-2: h_phi^{n+1/2} = h_phi^n + a mu_phi [P_z e_r^n - P_r e_z^{n+1/2}]
+        const R hph2 = HPn2 + hp2 * ((lane_next(ER2) - ER2) - (ezh1 - EZh2));
+        // S7 at q-2: e_r^{n+1/2} = e_r^n + a kappa_r [-P_z^* h_phi^{n+1/2} + m h_z^n]
+        const R pzsHP2 = lane_prev(hph2) - hph2;
+        const R erh2 = ER2 + er2c * (m * HZ2 - pzsHP2);
+        // S8 at q-2: h_z^{n+1} = h_z^n + f_h 2a mu_z [P_r e_phi^{n+1/2} - m e_r^{n+1/2}]
+        const R hzn2 = HZ2 + c2.dz * ((eph1 - EPh2) - m * erh2);
+        // S9 at q-2: e_phi^{n+1} = e_phi^{n+1/2} + a kappa_phi [P_z^* h_r^{n+1/2} - P_r^* h_z^{n+1}]
+        const R ep2 = EPh2 + ep2c * ((lane_prev(HRh2) - HRh2) - (HZn3 - hzn2));
+        // S10 at q-2: e_r^{n+1} = e_r^{n+1/2} + a kappa_r [-P_z^* h_phi^{n+1/2} + m h_z^{n+1}]
+        const R er2 = erh2 + er2c * (m * hzn2 - pzsHP2);
+        const Fin<R> f{hph2, HRh2, EZh2, ep2, er2, hzn2};
+
+        // advance by one row
+        HZn3 = hzn2;
+        EPh2 = eph1;
+        HRh2 = hrh1;
+        ER2 = ER1;
+        EZh2 = ezh1;
+        HPn2 = hpn1;
+        HZ2 = HZ1;
+        C2 = C1;
+        EZ1 = cur.ez;
+        ER1 = cur.er;
+        EP1 = cur.ep;
+        HP1 = cur.hp;
+        HR1 = cur.hr;
+        HZ1 = cur.hz;
+        C1 = cq;
+        return f;
+    }
+};
+
+// NS steps per launch (1 or 2).  With two, a second stage marches two rows
+// behind the first and takes its final rows (step n+1) as input, so that a
+// cell is read and written once per two steps; each step costs two rows of
+// halo on either side of a chunk and one lane on either side of the strip.
+template <typename R, int PF, int NS>
 __global__ __launch_bounds__(kLanes * kWaves) void k_rz(RZArgs<R> A)
 {
     constexpr uint32_t RB = sizeof(R);
     constexpr uint32_t OOB = 0x80000000u;
+    constexpr int OWN = kLanes - 2 * NS;             // owned lanes NS .. 63-NS
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     // the wave index is uniform: taking it through a scalar register keeps the
     // early return below a scalar branch
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes), lane = threadIdx.x % kLanes;
-    const int zt = (lb % A.nzb) * kWaves + wave;
-    const int rc = lb / A.nzb;
+    // order 1: the r-chunks of one z-column are consecutive (neighbouring
+    // chunks, which share halo rows, run together on one XCD); order 2: the
+    // z-strips of one chunk are consecutive
+    const int zg = A.order == 1 ? lb / A.nrc : lb % A.nzb;
+    const int rc = A.order == 1 ? lb % A.nrc : lb / A.nzb;
+    const int zt = zg * kWaves + wave;
     if (zt >= A.nzt) return;                          // whole wave
-    const int k = zt * kOwn - 1 + lane;
+    const int k = zt * OWN - NS + lane;
     const bool kin = k >= 0 && k <= A.nz;
-    const bool own_k = kin && lane >= 1 && lane <= kOwn;
+    const bool own_k = kin && lane >= NS && lane < kLanes - NS;
     const int ra = rc * A.rows, rb = min(ra + A.rows, A.nr + 1);
-    const int L0 = max(0, ra - 2), pend = rb + 1;
+    const int L0 = max(0, ra - 2 * NS), pend = rb + 2 * NS - 1;
 
     const uint32_t np = (uint32_t)(A.nr + 1) * (uint32_t)A.sz;
     auto mk = [](const void* base, uint32_t bytes) {
@@ -109,21 +196,68 @@ __global__ __launch_bounds__(kLanes * kWaves) void k_rz(RZArgs<R> A)
         v.hp = bload<R>(rHP, off);
         v.hr = bload<R>(rHR, off);
         v.hz = bload<R>(rHZ, off);
-        // the code byte is read as the aligned dword that holds it
-        const uint32_t cw = __builtin_amdgcn_raw_buffer_load_b32(rC, ok ? (idx & ~3u) : OOB, 0, 0);
-        v.c = ok ? (cw >> (8 * (idx & 3u))) & 0xffu : (uint32_t)C_ALL;
+        // the code byte is read as the aligned dword that holds it (out of range
+        // the load returns 0); the byte is extracted when the row is used, so
+        // that no wait for this load sits between the prefetch and the compute
+        v.c = __builtin_amdgcn_raw_buffer_load_b32(rC, ok ? (idx & ~3u) : OOB, 0, 0);
         return v;
     };
-    auto coef = [&](int row) { return A.coef[row + kPad]; };
+    auto code_of = [&](int p, uint32_t cw) {
+        const bool ok = kin && p <= A.nr;
+        const uint32_t idx = (uint32_t)p * (uint32_t)A.sz + (uint32_t)k;
+        return ((cw >> (8 * (idx & 3u))) & 0xffu) | (ok ? 0u : (uint32_t)C_ALL);
+    };
+    // The coefficient table is read through the constant address space with a
+    // uniform row index: scalar loads, outside the vector-memory counter that
+    // the row prefetch relies on (a vector load of it would wait for the
+    // prefetched rows too).
+    typedef const __attribute__((address_space(4))) R* CR;
+    const CR ctab = (CR)(const void*)A.coef;
+    auto coef = [&](int row) {
+        const int o = __builtin_amdgcn_readfirstlane(row + kPad) * 6;
+        Coef<R> c;
+        c.cp = ctab[o + 0];
+        c.cr = ctab[o + 1];
+        c.cz = ctab[o + 2];
+        c.dp = ctab[o + 3];
+        c.dr = ctab[o + 4];
+        c.dz = ctab[o + 5];
+        return c;
+    };
+    // bunch current and wake lines of the step with index n at row j1
+    auto source = [&](int j1, int64_t n) {
+        return [&, j1, n](uint32_t C1, R cz1, R ezold, R& ezh1) {
+            if (A.src && j1 == A.j0 && !(C1 & C_EZ) && k < A.nz) {
+                const int64_t mm = (int64_t)k - n + A.M;         // cell mm crosses edge k in step n
+                if (mm >= -A.M && mm <= A.M) {
+                    // the current term is rounded on its own, as in the 3-D kernels
+#pragma clang fp contract(off)
+                    ezh1 -= (R)((double)cz1 * A.lamw[mm + A.M]);
+                }
+            }
+            if (A.src && (j1 == A.jw || j1 == A.jw + 1) && j1 >= ra && j1 < rb && own_k && k < A.nz) {
+                const int64_t js = n - k - A.M;                  // wake sample of edge k
+                // even and odd steps accumulate into separate arrays: in a two-step
+                // launch lane k's step n and lane k+1's step n+1 meet at one sample
+                if (js >= A.jmin && js < (int64_t)A.jmin + A.nw)
+                    A.acc[((int)(n & 1) * 2 + (j1 - A.jw)) * A.nw + (js - A.jmin)] +=
+                        -0.5 * ((double)ezold + (double)ezh1);
+            }
+        };
+    };
+    auto store = [&](int q, const Fin<R>& f) {
+        const bool st = own_k && q >= ra && q < rb;
+        const uint32_t so = st ? ((uint32_t)q * (uint32_t)A.sz + (uint32_t)k) * RB : OOB;
+        bstore<R>(sHP, so, f.hp);
+        bstore<R>(sHR, so, f.hr);
+        bstore<R>(sEZ, so, f.ez);
+        bstore<R>(sEP, so, f.ep);
+        bstore<R>(sER, so, f.er);
+        bstore<R>(sHZ, so, f.hz);
+    };
 
     const R m = A.m;
-    // rows p-1 (old values), p-2 and p-3 of the pipeline
-    R EZ1 = 0, ER1 = 0, EP1 = 0, HP1 = 0, HR1 = 0, HZ1 = 0;
-    uint32_t C1 = C_ALL;
-    R HZ2 = 0, HPn2 = 0, EZh2 = 0, ER2 = 0, HRh2 = 0, EPh2 = 0;
-    uint32_t C2 = C_ALL;
-    R HZn3 = 0;
-
+    Stage<R> SA, SB;
     Row<R> ring[PF];
 #pragma unroll
     for (int u = 0; u < PF; ++u) ring[u] = load(L0 + u);
@@ -135,81 +269,17 @@ __global__ __launch_bounds__(kLanes * kWaves) void k_rz(RZArgs<R> A)
             if (p > pend) break;
             const Row<R> cur = ring[u];
             ring[u] = load(p + PF);
-            const Coef<R> c1 = coef(p - 1), c2 = coef(p - 2);
-            const int j1 = p - 1;
-
-            // The PEC / absence bits zero the coefficient of a masked entry
-            // (x + 0 * d == x) instead of selecting the result: a select around
-            // an update can be compiled into a branch, and a lane shift inside
-            // it would then read 0 from the lanes the branch disables.
-            const R hp1 = (C1 & C_HK) ? (R)0 : c1.dp, hr1c = (C1 & C_HK) ? (R)0 : c1.dr;
-            const R ez1c = (C1 & C_EZ) ? (R)0 : c1.cz, ep1c = (C1 & C_EPHI) ? (R)0 : c1.cp;
-            const R hp2 = (C2 & C_HK) ? (R)0 : c2.dp, er2c = (C2 & C_ER) ? (R)0 : c2.cr;
-            const R ep2c = (C2 & C_EPHI) ? (R)0 : c2.cp;
-
-            // S1 at p-1: h_phi^n = h_phi^{n-1/2} + a mu_phi [P_z e_r^n - P_r e_z^{n-1/2}]
-            const R hpn1 = HP1 + hp1 * ((lane_next(ER1) - ER1) - (cur.ez - EZ1));
-            // S2 at p-1: h_r^n = h_r^{n-1/2} + a mu_r [-P_z e_phi^n + m e_z^{n-1/2}]
-            const R pzEP1 = lane_next(EP1) - EP1;
-            const R hrn1 = HR1 + hr1c * (m * EZ1 - pzEP1);
-            // S3 at p-1: e_z^{n+1/2} = e_z^{n-1/2} + f_e 2a kappa_z [P_r^* h_phi^n - m h_r^n - j_z^n]
-            R ezh1 = EZ1 + ez1c * ((HPn2 - hpn1) - m * hrn1);
-            if (A.src && j1 == A.j0 && !(C1 & C_EZ) && k < A.nz) {
-                const int64_t mm = (int64_t)k - A.n + A.M;       // cell mm crosses edge k in step n
-                if (mm >= -A.M && mm <= A.M) {
-                    // the current term is rounded on its own, as in the 3-D kernels
-#pragma clang fp contract(off)
-                    ezh1 -= (R)((double)c1.cz * A.lamw[mm + A.M]);
-                }
+            const uint32_t c_m2 = SA.C2;                 // code of row p-2
+            const Fin<R> fa = SA.advance(cur, code_of(p, cur.c), coef(p - 1), coef(p - 2), m,
+                                         source(p - 1, A.n));
+            if constexpr (NS == 1) {
+                store(p - 2, fa);
+            } else {
+                // row p-2 after step n is the second stage's input row
+                const Row<R> rin{fa.ez, fa.er, fa.ep, fa.hp, fa.hr, fa.hz, 0u};
+                const Fin<R> fb = SB.advance(rin, c_m2, coef(p - 3), coef(p - 4), m, source(p - 3, A.n + 1));
+                store(p - 4, fb);
             }
-            if (A.src && (j1 == A.jw || j1 == A.jw + 1) && j1 >= ra && j1 < rb && own_k && k < A.nz) {
-                const int64_t js = A.n - k - A.M;                // wake sample of edge k
-                if (js >= A.jmin && js < (int64_t)A.jmin + A.nw)
-                    A.acc[(j1 - A.jw) * A.nw + (js - A.jmin)] += -0.5 * ((double)EZ1 + (double)ezh1);
-            }
-            // S5 at p-1: h_r^{n+1/2} = h_r^n + a mu_r [-P_z e_phi^n + m e_z^{n+1/2}]
-            const R hrh1 = hrn1 + hr1c * (m * ezh1 - pzEP1);
-            // S6 at p-1: e_phi^{n+1/2} = e_phi^n + a kappa_phi [P_z^* h_r^{n+1/2} - P_r^* h_z^n]
-            const R eph1 = EP1 + ep1c * ((lane_prev(hrh1) - hrh1) - (HZ2 - HZ1));
-            // S4 at p-2: h_phi^{n+1/2} = h_phi^n + a mu_phi [P_z e_r^n - P_r e_z^{n+1/2}]
-            const R hph2 = HPn2 + hp2 * ((lane_next(ER2) - ER2) - (ezh1 - EZh2));
-            // S7 at p-2: e_r^{n+1/2} = e_r^n + a kappa_r [-P_z^* h_phi^{n+1/2} + m h_z^n]
-            const R pzsHP2 = lane_prev(hph2) - hph2;
-            const R erh2 = ER2 + er2c * (m * HZ2 - pzsHP2);
-            // S8 at p-2: h_z^{n+1} = h_z^n + f_h 2a mu_z [P_r e_phi^{n+1/2} - m e_r^{n+1/2}]
-            const R hzn2 = HZ2 + c2.dz * ((eph1 - EPh2) - m * erh2);
-            // S9 at p-2: e_phi^{n+1} = e_phi^{n+1/2} + a kappa_phi [P_z^* h_r^{n+1/2} - P_r^* h_z^{n+1}]
-            const R ep2 = EPh2 + ep2c * ((lane_prev(HRh2) - HRh2) - (HZn3 - hzn2));
-            // S10 at p-2: e_r^{n+1} = e_r^{n+1/2} + a kappa_r [-P_z^* h_phi^{n+1/2} + m h_z^{n+1}]
-            const R er2 = erh2 + er2c * (m * hzn2 - pzsHP2);
-
-            // row p-2 is final
-            const int q = p - 2;
-            const bool st = own_k && q >= ra && q < rb;
-            const uint32_t so = st ? ((uint32_t)q * (uint32_t)A.sz + (uint32_t)k) * RB : OOB;
-            bstore<R>(sHP, so, hph2);
-            bstore<R>(sHR, so, HRh2);
-            bstore<R>(sEZ, so, EZh2);
-            bstore<R>(sEP, so, ep2);
-            bstore<R>(sER, so, er2);
-            bstore<R>(sHZ, so, hzn2);
-
-            // advance the pipeline by one row
-            HZn3 = hzn2;
-            EPh2 = eph1;
-            HRh2 = hrh1;
-            ER2 = ER1;
-            EZh2 = ezh1;
-            HPn2 = hpn1;
-            HZ2 = HZ1;
-            C2 = C1;
-            EZ1 = cur.ez;
-            ER1 = cur.er;
-            EP1 = cur.ep;
-            HP1 = cur.hp;
-            HR1 = cur.hr;
-            HZ1 = cur.hz;
-            C1 = cur.c;
         }
     }
 }
@@ -330,15 +400,16 @@ __global__ __launch_bounds__(kRedThreads) void k_rz_finish(const double* partial
     if (threadIdx.x == 0) *out = s;
 }
 
-// Wakes in V/C: W_par = acc / (Q eps0) on both lines; W_perp by the trapezoidal
-// s-integral of (line jw+1 - line jw) / dr from the first sample.
+// Wakes in V/C: W_par = (even + odd step sums) / (Q eps0) on both lines;
+// W_perp by the trapezoidal s-integral of (line jw+1 - line jw) / dr from the
+// first sample.
 __global__ void k_rz_wakes(const double* acc, int nw, double scale, double dr, double ds, double* wpar,
                            double* wperp)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double prev = 0.0, run = 0.0;
     for (int j = 0; j < nw; ++j) {
-        const double a0 = acc[j] * scale, a1 = acc[nw + j] * scale;
+        const double a0 = (acc[j] + acc[2 * nw + j]) * scale, a1 = (acc[nw + j] + acc[3 * nw + j]) * scale;
         wpar[j] = a0;
         wpar[nw + j] = a1;
         const double d = (a1 - a0) / dr;
@@ -377,7 +448,7 @@ RZLayout rz_layout(const tete_rz_desc* d)
     L.coef = o;    o = up(o + 6 * rb * (size_t)(d->nr + 1 + 2 * kPad));
     L.raw = o;     o = up(o + sizeof(Raw) * (size_t)(d->nr + 1));
     L.lamw = o;    o = up(o + sizeof(double) * TETE_MAX_BUNCH_CELLS);
-    L.acc = o;     o = up(o + sizeof(double) * 2 * TETE_MAX_WAKE);
+    L.acc = o;     o = up(o + sizeof(double) * 4 * TETE_MAX_WAKE);
     L.partial = o; o = up(o + sizeof(double) * kRedBlocks);
     L.scal = o;    o = up(o + sizeof(double) * 8);
     L.wout = o;    o = up(o + sizeof(double) * 3 * TETE_MAX_WAKE);
@@ -412,9 +483,11 @@ struct tete_rz {
     int64_t n;
     int has_bunch;
     tete_rz_bunch b;
-    int chunk_rows, prefetch;
+    int kernel, chunk_rows, prefetch;   // TETE_KERNEL_AUTO / FUSED (one step) / FUSED2 (two)
+    int order;                          // workgroup order (0: default)
     int timing;
     hipEvent_t* ev;
+    unsigned char* ev_nst;              // steps of each timed launch
     int64_t ev_cap, ev_used;
 };
 
@@ -462,20 +535,38 @@ void rz_coef(const tete_rz_desc* d, const std::vector<Raw>& raw, std::vector<Coe
     }
 }
 
-int rz_nzt(const tete_rz_desc* d) { return (d->nz + 1 + kOwn - 1) / kOwn; }
-
-// Rows per r-chunk: enough chunks for about 16 waves per compute unit (4096
-// waves), chunks of at least 16 rows.
-int rz_rows(const tete_rz* g)
+// z-strips of a launch taking ns steps: each owns 64 - 2 ns consecutive k
+int rz_nzt(const tete_rz_desc* d, int ns)
 {
-    if (g->chunk_rows > 0) return g->chunk_rows;
-    const int nzt = rz_nzt(&g->d), rows = g->d.nr + 1;
-    const int want = std::max(1, (4096 + nzt - 1) / nzt);
-    return std::max(16, (rows + want - 1) / want);
+    const int own = kLanes - 2 * ns;
+    return (d->nz + 1 + own - 1) / own;
 }
 
+// Rows per r-chunk: 16 by default.  Short chunks give many workgroups (about
+// 19 rounds of 256 on the 1000 x 18183 deflector-like grid), so the last
+// round's tail is small; their halo rows are re-read mostly from L2.  On that
+// grid 16 rows measured within 3 % of the best of 16 .. 256 for both kernels
+// and precisions, while automatic chunks of 72 rows were 8 % slower.
+int rz_rows(const tete_rz* g, int ns)
+{
+    (void)ns;
+    return g->chunk_rows > 0 ? g->chunk_rows : 16;
+}
+
+template <typename R, int NS>
+void rz_kernel(int pf, dim3 grid, dim3 block, hipStream_t s, const RZArgs<R>& A)
+{
+    switch (pf) {
+        case 1: k_rz<R, 1, NS><<<grid, block, 0, s>>>(A); break;
+        case 3: k_rz<R, 3, NS><<<grid, block, 0, s>>>(A); break;
+        case 4: k_rz<R, 4, NS><<<grid, block, 0, s>>>(A); break;
+        default: k_rz<R, 2, NS><<<grid, block, 0, s>>>(A); break;
+    }
+}
+
+// One launch taking ns (1 or 2) steps from y^n in set cur to the other set.
 template <typename R>
-hipError_t rz_launch(tete_rz* g, hipStream_t s)
+hipError_t rz_launch(tete_rz* g, int ns, hipStream_t s)
 {
     RZArgs<R> A;
     const int in = g->cur, out = 1 - g->cur;
@@ -489,9 +580,9 @@ hipError_t rz_launch(tete_rz* g, hipStream_t s)
     A.nz = g->d.nz;
     A.sz = g->d.nz + 1;
     A.m = (R)g->d.mode;
-    A.nzt = rz_nzt(&g->d);
+    A.nzt = rz_nzt(&g->d, ns);
     A.nzb = (A.nzt + kWaves - 1) / kWaves;
-    A.rows = rz_rows(g);
+    A.rows = rz_rows(g, ns);
     A.src = g->has_bunch;
     A.j0 = g->b.j0;
     A.M = g->b.half_cells;
@@ -502,13 +593,12 @@ hipError_t rz_launch(tete_rz* g, hipStream_t s)
     A.lamw = g->lamw;
     A.acc = g->acc;
     const int nrc = (g->d.nr + 1 + A.rows - 1) / A.rows;
+    A.nrc = nrc;
+    A.order = g->order > 0 ? g->order : 2;
     const dim3 grid((unsigned)(A.nzb * nrc)), block(kLanes * kWaves);
-    switch (g->prefetch > 0 ? g->prefetch : 2) {
-        case 1: k_rz<R, 1><<<grid, block, 0, s>>>(A); break;
-        case 3: k_rz<R, 3><<<grid, block, 0, s>>>(A); break;
-        case 4: k_rz<R, 4><<<grid, block, 0, s>>>(A); break;
-        default: k_rz<R, 2><<<grid, block, 0, s>>>(A); break;
-    }
+    const int pf = g->prefetch > 0 ? g->prefetch : 2;
+    if (ns == 2) rz_kernel<R, 2>(pf, grid, block, s, A);
+    else rz_kernel<R, 1>(pf, grid, block, s, A);
     return hipGetLastError();
 }
 
@@ -625,6 +715,7 @@ tete_status tete_rz_destroy(tete_rz* g)
         for (int64_t i = 0; i < 2 * g->ev_cap; ++i) (void)hipEventDestroy(g->ev[i]);
         free(g->ev);
     }
+    free(g->ev_nst);
     free(g);
     return TETE_OK;
 }
@@ -661,7 +752,7 @@ tete_status tete_rz_set_fields(tete_rz* g, const void* const f[6], int32_t dtype
         RZCHK(hipGetLastError());
     }
     RZCHK(rz_sanitize_any(g, g->cur));
-    RZCHK(hipMemsetAsync(g->acc, 0, sizeof(double) * 2 * TETE_MAX_WAKE, g->stream));
+    RZCHK(hipMemsetAsync(g->acc, 0, sizeof(double) * 4 * TETE_MAX_WAKE, g->stream));
     g->n = 0;
     return TETE_OK;
 }
@@ -715,7 +806,7 @@ tete_status tete_rz_set_bunch(tete_rz* g, const tete_rz_bunch* b)
         lam[mm + M] = w * b->charge_C * v / g->d.cdt;
     }
     RZCHK(hipMemcpyAsync(g->lamw, lam.data(), sizeof(double) * lam.size(), hipMemcpyHostToDevice, g->stream));
-    RZCHK(hipMemsetAsync(g->acc, 0, sizeof(double) * 2 * TETE_MAX_WAKE, g->stream));
+    RZCHK(hipMemsetAsync(g->acc, 0, sizeof(double) * 4 * TETE_MAX_WAKE, g->stream));
     RZCHK(hipStreamSynchronize(g->stream));
     g->b = *b;
     g->has_bunch = 1;
@@ -727,16 +818,20 @@ tete_status tete_rz_step(tete_rz* g, int64_t nsteps)
     if (!g || nsteps < 0) return TETE_ERR_ARG;
     Guard dg(g->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
-    for (int64_t s = 0; s < nsteps; ++s) {
+    const bool two = g->kernel != TETE_KERNEL_FUSED;
+    for (int64_t s = 0; s < nsteps;) {
+        const int ns = two && nsteps - s >= 2 ? 2 : 1;
         const bool rec = g->timing && g->ev_used < g->ev_cap;
         if (rec) RZCHK(hipEventRecord(g->ev[2 * g->ev_used], g->stream));
-        RZCHK(g->fp32 ? rz_launch<float>(g, g->stream) : rz_launch<double>(g, g->stream));
+        RZCHK(g->fp32 ? rz_launch<float>(g, ns, g->stream) : rz_launch<double>(g, ns, g->stream));
         if (rec) {
             RZCHK(hipEventRecord(g->ev[2 * g->ev_used + 1], g->stream));
+            g->ev_nst[g->ev_used] = (unsigned char)ns;
             ++g->ev_used;
         }
         g->cur = 1 - g->cur;
-        ++g->n;
+        g->n += ns;
+        s += ns;
     }
     return TETE_OK;
 }
@@ -786,13 +881,16 @@ tete_status tete_rz_energy(tete_rz* g, double* W, int64_t* n)
     return isfinite(*W) ? TETE_OK : TETE_ERR_NONFINITE;
 }
 
-tete_status tete_rz_set_tuning(tete_rz* g, int32_t chunk_rows, int32_t prefetch)
+tete_status tete_rz_set_tuning(tete_rz* g, int32_t kernel, int32_t chunk_rows, int32_t prefetch, int32_t order)
 {
-    if (!g || chunk_rows < 0 || (chunk_rows > 0 && (chunk_rows < 8 || chunk_rows > 4096)) || prefetch < 0 ||
-        prefetch > 4)
+    if (!g || (kernel != TETE_KERNEL_AUTO && kernel != TETE_KERNEL_FUSED && kernel != TETE_KERNEL_FUSED2) ||
+        chunk_rows < 0 || (chunk_rows > 0 && (chunk_rows < 8 || chunk_rows > 4096)) || prefetch < 0 ||
+        prefetch > 4 || order < 0 || order > 2)
         return TETE_ERR_ARG;
+    g->kernel = kernel;
     g->chunk_rows = chunk_rows;
     g->prefetch = prefetch;
+    g->order = order;
     return TETE_OK;
 }
 
@@ -807,16 +905,27 @@ tete_status tete_rz_set_timing(tete_rz* g, int64_t max_launches)
         free(g->ev);
         g->ev = nullptr;
     }
+    free(g->ev_nst);
+    g->ev_nst = nullptr;
     g->ev_cap = g->ev_used = 0;
     g->timing = 0;
     if (max_launches == 0) return TETE_OK;
     g->ev = (hipEvent_t*)calloc((size_t)(2 * max_launches), sizeof(hipEvent_t));
-    if (!g->ev) return TETE_ERR_NOMEM;
+    g->ev_nst = (unsigned char*)calloc((size_t)max_launches, 1);
+    if (!g->ev || !g->ev_nst) {
+        free(g->ev);
+        free(g->ev_nst);
+        g->ev = nullptr;
+        g->ev_nst = nullptr;
+        return TETE_ERR_NOMEM;
+    }
     for (int64_t i = 0; i < 2 * max_launches; ++i) {
         if (hipEventCreate(&g->ev[i]) != hipSuccess) {
             for (int64_t t = 0; t < i; ++t) (void)hipEventDestroy(g->ev[t]);
             free(g->ev);
+            free(g->ev_nst);
             g->ev = nullptr;
+            g->ev_nst = nullptr;
             return TETE_ERR_DEVICE;
         }
     }
@@ -825,20 +934,23 @@ tete_status tete_rz_set_timing(tete_rz* g, int64_t max_launches)
     return TETE_OK;
 }
 
-tete_status tete_rz_timing(tete_rz* g, double* ms, int64_t* launches)
+tete_status tete_rz_timing(tete_rz* g, double* ms, int64_t* launches, int64_t* steps)
 {
-    if (!g || !ms || !launches) return TETE_ERR_ARG;
+    if (!g || !ms || !launches || !steps) return TETE_ERR_ARG;
     Guard dg(g->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
     RZCHK(hipStreamSynchronize(g->stream));
     double sum = 0.0;
+    int64_t ns = 0;
     for (int64_t i = 0; i < g->ev_used; ++i) {
         float t = 0.0f;
         RZCHK(hipEventElapsedTime(&t, g->ev[2 * i], g->ev[2 * i + 1]));
         sum += t;
+        ns += g->ev_nst[i];
     }
     *ms = sum;
     *launches = g->ev_used;
+    *steps = ns;
     return TETE_OK;
 }
 

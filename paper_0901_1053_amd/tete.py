@@ -125,9 +125,9 @@ def load(path: str = LIB_PATH):
         "tete_rz_steps_done": (st, [vp, C.POINTER(C.c_int64)]),
         "tete_rz_wake": (st, [vp, vp, vp, C.c_int32]),
         "tete_rz_energy": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
-        "tete_rz_set_tuning": (st, [vp, C.c_int32, C.c_int32]),
+        "tete_rz_set_tuning": (st, [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
         "tete_rz_set_timing": (st, [vp, C.c_int64]),
-        "tete_rz_timing": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "tete_rz_timing": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -487,15 +487,18 @@ class RZGrid:
         _chk("tete_rz_energy", load().tete_rz_energy(self.h, C.byref(w), C.byref(n)))
         return w.value, n.value
 
-    def set_tuning(self, chunk_rows=0, prefetch=0):
-        _chk("tete_rz_set_tuning", load().tete_rz_set_tuning(self.h, chunk_rows, prefetch))
+    def set_tuning(self, chunk_rows=0, prefetch=0, kernel="auto", order=0):
+        """kernel: "auto" or "fused2" (two steps per launch), "fused" (one);
+        order 1: r-chunks of a z-column consecutive, 2: z-strips of a chunk."""
+        _chk("tete_rz_set_tuning", load().tete_rz_set_tuning(self.h, KERNELS[kernel], chunk_rows, prefetch, order))
 
     def set_timing(self, max_launches: int):
         _chk("tete_rz_set_timing", load().tete_rz_set_timing(self.h, int(max_launches)))
 
     def timing(self):
-        """(summed kernel ms, launches timed)."""
+        """(summed kernel ms, launches timed, steps they took)."""
         ms = C.c_double()
         n = C.c_int64()
-        _chk("tete_rz_timing", load().tete_rz_timing(self.h, C.byref(ms), C.byref(n)))
-        return ms.value, n.value
+        st = C.c_int64()
+        _chk("tete_rz_timing", load().tete_rz_timing(self.h, C.byref(ms), C.byref(n), C.byref(st)))
+        return ms.value, n.value, st.value

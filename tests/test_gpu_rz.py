@@ -40,11 +40,11 @@ def _oracle(shape, seed, mode, steps):
     return f, E0, Z.energy(g, m, f)
 
 
-def _gpu(shape, seed, mode, steps, precision="fp64", chunk_rows=0, prefetch=0):
+def _gpu(shape, seed, mode, steps, precision="fp64", chunk_rows=0, prefetch=0, kernel="auto"):
     nr, nz = shape
     G = tete.RZGrid(nr, nz, DR, DZ, CDT, mode, precision)
     G.set_pec_cells(inputs.rz_random_cells(nr, nz, seed, frac=0.1))
-    G.set_tuning(chunk_rows, prefetch)
+    G.set_tuning(chunk_rows, prefetch, kernel)
     G.set_fields(inputs.rz_random_fields(G.shape, seed))
     E0 = G.energy()[0]
     G.step(steps)
@@ -65,13 +65,45 @@ def test_rz_matches_oracle(shape, mode):
     assert abs(G32.energy()[0] - E1) <= 1e-5 * abs(E1)
 
 
-@pytest.mark.parametrize("chunk_rows,prefetch", [(8, 1), (16, 2), (33, 3), (4096, 4), (9, 4), (0, 1)])
-def test_rz_launch_shape_invariance(chunk_rows, prefetch):
+@pytest.mark.parametrize("kernel,chunk_rows,prefetch,order", [
+    ("fused", 8, 1, 0), ("fused", 16, 2, 1), ("fused", 33, 3, 2), ("fused", 4096, 4, 0), ("fused", 9, 4, 1),
+    ("fused", 0, 0, 0), ("fused2", 8, 1, 1), ("fused2", 13, 2, 2), ("fused2", 32, 3, 1), ("fused2", 4096, 4, 0),
+    ("auto", 0, 0, 0)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_rz_launch_shape_invariance(kernel, chunk_rows, prefetch, order, precision):
+    """Chunk length, prefetch depth, workgroup order and one or two steps per
+    launch change nothing, bitwise: the two-step launch does the same
+    arithmetic in the same order, its intermediate level kept in registers
+    (13 steps: an odd last step)."""
     shape = (70, 300)
-    base = _gpu(shape, 72, 2, 12)[0].get_fields()
-    got = _gpu(shape, 72, 2, 12, chunk_rows=chunk_rows, prefetch=prefetch)[0].get_fields()
+    base = _gpu(shape, 72, 2, 13, precision, kernel="fused")[0].get_fields(precision)
+    G = _gpu(shape, 72, 2, 0, precision)[0]
+    G.set_tuning(chunk_rows, prefetch, kernel, order)
+    G.step(13)
+    got = G.get_fields(precision)
     for k in Z.KEYS:
         assert np.array_equal(got[k], base[k]), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_rz_two_step_wake_bitwise(precision):
+    """With the bunch on, one and two steps per launch give the same wake lines,
+    transverse wake and fields, bitwise."""
+    case = inputs.small_rz_case(1)
+    jmin, nw = case.window()
+    res = []
+    for kernel in ("fused", "fused2"):
+        G = tete.RZGrid(case.nr, case.nz, case.dr, case.dz, case.cdt, case.mode, precision)
+        G.set_pec_cells(case.cells())
+        G.set_tuning(0, 0, kernel)
+        G.set_bunch(case.charge, case.sigma, case.j0, case.M, case.jw, jmin, nw)
+        G.step(case.steps())
+        res.append((G.wake(), G.get_fields(precision)))
+    (wp0, wt0), f0 = res[0]
+    (wp1, wt1), f1 = res[1]
+    assert np.array_equal(wp0, wp1) and np.array_equal(wt0, wt1)
+    for k in Z.KEYS:
+        assert np.array_equal(f0[k], f1[k]), k
 
 
 def test_rz_energy_conserved_long_run():
