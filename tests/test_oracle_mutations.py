@@ -185,3 +185,62 @@ def test_rz_pins_catch_planted_mistake(tmp_path, name):
         except (AssertionError, FloatingPointError, ValueError, np.linalg.LinAlgError):
             caught += 1
     assert caught >= 1, "no pin caught mutant %s" % name
+
+
+# ---- the implicit oracle (Python), same harness as the r-z one
+from tests import test_oracle_implicit as TIM
+
+IM_SRC = os.path.join(os.path.dirname(HERE), "oracle", "implicit_oracle.py")
+
+IM_MUTANTS = {
+    # transverse coupling of e_z to h_y with the wrong sign
+    "imp_t0_sign": ([('(EZ, HY, "pxt", -1.0, "ka")', '(EZ, HY, "pxt", +1.0, "ka")')],
+                    [lambda z: TIM.test_implicit_eigenvalues_follow_the_dispersion_relation(z),
+                     lambda z: TIM.test_implicit_energy_law(z)]),
+    # the explicit half of the transverse operator dropped (backward Euler in T_0)
+    "imp_no_mean_t0": ([("self.P0 = (I + self.a * self.T0).tocsr()", "self.P0 = I.tocsr()"),
+                        ("self.lu0 = spla.splu((I - self.a * self.T0).tocsc())",
+                         "self.lu0 = spla.splu((I - 2 * self.a * self.T0).tocsc())")],
+                       [lambda z: TIM.test_implicit_eigenvalues_follow_the_dispersion_relation(z)]),
+    # coupling -L^T with the wrong sign on e_x
+    "imp_lt_sign": ([('(EX, HY, "pzt", +1.0, "ka")', '(EX, HY, "pzt", -1.0, "ka")')],
+                    [lambda z: TIM.test_implicit_transversely_uniform_pulse(z),
+                     lambda z: TIM.test_implicit_energy_law(z)]),
+    # current with the sign printed in the scaled forms
+    "imp_current_sign": ([("rhs[2 * self.n:] -= dt", "rhs[2 * self.n:] += dt")],
+                         [lambda z: TIM.test_implicit_gauss_law(z)]),
+    # energy cross term with the wrong sign
+    "imp_energy_cross": ([("return s + a * float(lc)", "return s - a * float(lc)")],
+                         [lambda z: TIM.test_implicit_energy_law(z)]),
+    # charge without the time average of the transverse fluxes
+    "imp_charge_no_mean": ([("dx = 0.5 * (d(fo, EX) + d(fn, EX))", "dx = d(fn, EX)")],
+                           [lambda z: TIM.test_implicit_gauss_law(z)]),
+}
+
+
+def _load_im_mutant(tmp_path, name, edits):
+    src = open(IM_SRC).read()
+    for old, new in edits:
+        assert src.count(old) >= 1, (name, old)
+        src = src.replace(old, new, 1)
+    p = tmp_path / (name + ".py")
+    p.write_text(src)
+    spec = importlib.util.spec_from_file_location("im_mutant_" + name, str(p))
+    mod = importlib.util.module_from_spec(spec)
+    sys.modules[spec.name] = mod
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(IM_MUTANTS))
+def test_implicit_pins_catch_planted_mistake(tmp_path, name):
+    edits, pins = IM_MUTANTS[name]
+    mod = _load_im_mutant(tmp_path, name, edits)
+    caught = 0
+    for pin in pins:
+        try:
+            with np.errstate(all="ignore"):
+                pin(mod)
+        except (AssertionError, FloatingPointError, ValueError, np.linalg.LinAlgError, RuntimeError):
+            caught += 1
+    assert caught >= 1, "no pin caught mutant %s" % name
