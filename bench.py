@@ -187,6 +187,33 @@ def yee_section(G, case, precision, steps=20):
                       "run_time_vs_yee_at_dx_sqrt2_dz": round((10 / 6) / 2 ** 0.5, 3)}}
 
 
+def implicit_section(case, precision, explicit_ms_per_step, steps=4):
+    """The implicit TE/TM scheme (16) on the large workload: kernel time per step
+    (HIP events around the two half steps on the grid's stream), the Chebyshev
+    iterations of each plane solve, and the time per step against the explicit
+    two-step kernel's."""
+    import math
+    from paper_0901_1053_amd import tete
+    G = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.cdt, precision=precision, implicit=True)
+    G.set_pec_cells(case.cell_mask())
+    G.set_bunch(case.Q, case.sigma, case.i0, case.j0, case.M, case.jmin, case.nw)
+    G.step(1)
+    G.set_timing(steps)
+    G.step(steps)
+    ms_u, ms_v, n = G.timing()
+    G.set_timing(0)
+    G.close()
+    a = 0.5 * case.cdt
+    lmax = 1.0 + a * a * (4.0 / case.dx ** 2 + 4.0 / case.dy ** 2)
+    rho = (math.sqrt(lmax) - 1.0) / (math.sqrt(lmax) + 1.0)
+    iters = max(1, math.ceil(math.log((1e-8 if precision == "fp32" else 1e-17) / 2.0) / math.log(rho)))
+    ms = (ms_u + ms_v) / n
+    return {"workload": case.name, "precision": precision, "ms_per_step": round(ms, 3),
+            "ms_per_half_step": {"u": round(ms_u / n, 3), "v": round(ms_v / n, 3)},
+            "chebyshev_iterations_per_plane_solve": iters, "spectral_bound": round(lmax, 4),
+            "vs_explicit_two_step": round(ms / explicit_ms_per_step, 2) if explicit_ms_per_step else None}
+
+
 def rz_section(steps=100, warmup=5):
     """The rotationally symmetric scheme (24) on the deflector-like r-z workload
     at harmonic m = 1: kernel time per step in FP32 and FP64 (HIP events on the
@@ -257,6 +284,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-yee", action="store_true", help="skip the comparison with Yee's scheme")
     ap.add_argument("--no-rz", action="store_true", help="skip the rotationally symmetric workload")
+    ap.add_argument("--no-implicit", action="store_true", help="skip the implicit scheme (16) comparison")
     ap.add_argument("--batched-count", type=int, default=64)
     ap.add_argument("--serve-rates", default="1,20,200", help="comma-separated request rates (req/s)")
     ap.add_argument("--serve-requests", type=int, default=12)
@@ -364,6 +392,10 @@ def main():
         print("# yee comparison done", file=sys.stderr, flush=True)
     del G
     torch.cuda.empty_cache()
+    if not args.no_implicit:
+        out["implicit_context"] = implicit_section(case, args.precision, ms_step)
+        torch.cuda.empty_cache()
+        print("# implicit comparison done", file=sys.stderr, flush=True)
 
     if not args.no_single_wake:
         sw = inputs.single_wake_case()

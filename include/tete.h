@@ -66,13 +66,26 @@ enum { TETE_FP64 = 0, TETE_FP32 = 1 };
 /* desc.flags */
 enum {
     TETE_F_MATERIALS = 1u << 0, /* reserve per-entry material arrays (tete_set_materials) */
-    TETE_F_YEE = 1u << 1        /* step with Yee's E/M scheme (7) instead of (23): a
+    TETE_F_YEE = 1u << 1,       /* step with Yee's E/M scheme (7) instead of (23): a
                                  * baseline for comparison.  State (e^{n-1/2}, h^n);
                                  * stability bound (8); vacuum with staircase PEC only
                                  * (not with TETE_F_MATERIALS); no bunch (its current
                                  * needs cdt = dz, which (8) excludes), no energy,
                                  * energy series or charges (TETE_ERR_STATE); probes
                                  * record e_z^{n+1/2}. */
+    TETE_F_IMPLICIT = 1u << 2   /* step with the implicit TE/TM scheme (16) of Sec. 4.1
+                                 * instead of (23): a comparator.  Each half step solves
+                                 * (I - alpha T_i) x = rhs; per z-plane this is one
+                                 * positive definite system for e_z (h_z), solved by a
+                                 * fixed number of Chebyshev iterations on the spectral
+                                 * bounds [1, 1 + alpha^2 (4/dx^2 + 4/dy^2)] (to 1e-17 in
+                                 * FP64, 1e-8 in FP32 relative to the first iterate's
+                                 * error).  Stable for cdt <= dz with any transverse
+                                 * mesh; vacuum with staircase PEC only (not with
+                                 * TETE_F_MATERIALS or TETE_F_YEE); bunch, wake, probes,
+                                 * energy (Q = B - alpha A of (16): no alpha^2 terms)
+                                 * and charges (the time-averaged charge, no alpha^2
+                                 * term) as for (23); not in batches. */
 };
 
 /* Capacities of the small per-grid tables held in the workspace. */
@@ -95,7 +108,7 @@ typedef struct {
 
 /* Stability and size check of a descriptor (host only, no device access).
  * Returns TETE_OK, TETE_ERR_ARG or TETE_ERR_UNSTABLE (bound (25), Sec. 4.4;
- * with TETE_F_YEE bound (8), Sec. 3). */
+ * with TETE_F_YEE bound (8), Sec. 3; with TETE_F_IMPLICIT cdt <= dz, (22)). */
 tete_status tete_check_desc(const tete_grid_desc* desc);
 
 /* Bytes of device workspace a grid with this descriptor needs (0 if the
@@ -232,7 +245,8 @@ tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h);
  * turns a forced FUSED or FUSED2 back into AUTO.  tete_get_tuning reports the kernel
  * that tete_step will use (FUSED2, FUSED or SPLIT). */
 enum { TETE_KERNEL_AUTO = 0, TETE_KERNEL_FUSED = 1, TETE_KERNEL_SPLIT = 2, TETE_KERNEL_FUSED2 = 3,
-       TETE_KERNEL_YEE = 4 /* reported for TETE_F_YEE grids, whose kernel ignores kernel, rows, depth */ };
+       TETE_KERNEL_YEE = 4 /* reported for TETE_F_YEE grids, whose kernel ignores kernel, rows, depth */,
+       TETE_KERNEL_IMPLICIT = 5 /* reported for TETE_F_IMPLICIT grids */ };
 typedef struct {
     int32_t kernel;
     int32_t rows;

@@ -21,7 +21,7 @@ constexpr size_t kAlign = 256;
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t lam, wacc, partial, scal, pidx, eser, pser, code, field[12], mat[6], total;
+    size_t lam, wacc, partial, scal, pidx, eser, pser, code, field[12], mat[6], imp[4], total;
 };
 
 int64_t series_cap(const tete_grid_desc* d) { return d->max_series > 0 ? d->max_series : 4096; }
@@ -43,6 +43,10 @@ bool make_layout(const tete_grid_desc* d, Layout* L)
     for (int c = 0; c < 6; ++c) {
         if (d->flags & TETE_F_MATERIALS) { L->mat[c] = o; o = up(o + rb * (size_t)np); }
         else L->mat[c] = 0;
+    }
+    for (int c = 0; c < 4; ++c) {          // plane-solve work arrays of the implicit scheme
+        if (d->flags & TETE_F_IMPLICIT) { L->imp[c] = o; o = up(o + rb * (size_t)np); }
+        else L->imp[c] = 0;
     }
     L->total = o;
     return true;
@@ -75,6 +79,7 @@ struct tete_grid {
     Geo geo;
     int fp32;
     int yee;           // Yee's scheme (7) instead of (23)
+    int implicit;      // the implicit scheme (16) instead of (23)
     void* f[2][6];
     int cur;           // f[cur] holds y^n
     uint8_t* code;
@@ -140,11 +145,26 @@ Src source(tete_grid* g, int64_t n)
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
+// weight of the alpha^2 terms in the energy and the charges: none for the
+// implicit scheme (16), whose transverse operators are time-centred
+double rweight(const tete_grid* g) { return g->implicit ? 0.0 : 1.0; }
+
+template <typename R>
+ImpWork<R> imp_work(tete_grid* g)
+{
+    ImpWork<R> w;
+    w.b = (R*)(g->ws + g->L.imp[0]);
+    w.r = (R*)(g->ws + g->L.imp[1]);
+    w.d[0] = (R*)(g->ws + g->L.imp[2]);
+    w.d[1] = (R*)(g->ws + g->L.imp[3]);
+    return w;
+}
+
 // The fused kernel covers vacuum cells with staircase PEC codes; per-entry
 // materials take the two-kernel path.
 bool use_fused(const tete_grid* g)
 {
-    if (g->yee || g->mat_set || !fused_fits(g->geo, g->fp32 ? 4 : 8)) return false;
+    if (g->yee || g->implicit || g->mat_set || !fused_fits(g->geo, g->fp32 ? 4 : 8)) return false;
     return g->tune.kernel != TETE_KERNEL_SPLIT;
 }
 
@@ -172,7 +192,7 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
     const bool two = use_fused2(g);
     for (int64_t s = 0; s < nsteps; ++s) {
         if (g->diag_every > 0 && g->n % g->diag_every == 0) {
-            HIPCHK(launch_energy<R>(fields<R>(g, g->cur), M, g->geo, g->alpha, g->partial, g->eser + g->ecount,
+            HIPCHK(launch_energy<R>(fields<R>(g, g->cur), M, g->geo, g->alpha, rweight(g), g->partial, g->eser + g->ecount,
                                     g->stream));
             g->ecount++;
         }
@@ -195,7 +215,10 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             ++s;
             continue;
         }
-        if (g->yee)
+        if (g->implicit)
+            HIPCHK(launch_step_implicit<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, g->d.dx,
+                                           g->d.dy, (R)g->alpha, source(g, g->n), imp_work<R>(g), g->stream, ev));
+        else if (g->yee)
             HIPCHK(launch_step_yee<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                       g->tune.xchunk, g->tune.order, g->stream, ev));
         else if (use_fused(g))
@@ -251,14 +274,20 @@ tete_status tete_check_desc(const tete_grid_desc* d)
     if (np >= ((int64_t)1 << 31) - 1) return TETE_ERR_ARG;
     if (!finite_pos(d->dx) || !finite_pos(d->dy) || !finite_pos(d->dz) || !finite_pos(d->cdt)) return TETE_ERR_ARG;
     if (d->precision != TETE_FP64 && d->precision != TETE_FP32) return TETE_ERR_ARG;
-    if (d->flags & ~(uint32_t)(TETE_F_MATERIALS | TETE_F_YEE)) return TETE_ERR_ARG;
+    if (d->flags & ~(uint32_t)(TETE_F_MATERIALS | TETE_F_YEE | TETE_F_IMPLICIT)) return TETE_ERR_ARG;
     if ((d->flags & TETE_F_YEE) && (d->flags & TETE_F_MATERIALS)) return TETE_ERR_ARG;
+    if ((d->flags & TETE_F_IMPLICIT) && (d->flags & (TETE_F_MATERIALS | TETE_F_YEE))) return TETE_ERR_ARG;
     if (d->max_series < 0 || d->max_series > (1 << 24)) return TETE_ERR_ARG;
     const double tol = 1.0 + 1e-12;
     if (d->flags & TETE_F_YEE) {
         // (8): dtau <= (dx^-2 + dy^-2 + dz^-2)^(-1/2)
         const double b8 = 1.0 / sqrt(1.0 / (d->dx * d->dx) + 1.0 / (d->dy * d->dy) + 1.0 / (d->dz * d->dz));
         if (d->cdt > b8 * tol) return TETE_ERR_UNSTABLE;
+        return TETE_OK;
+    }
+    if (d->flags & TETE_F_IMPLICIT) {
+        // (22): dtau <= dz; the transverse operators are implicit (no transverse bound)
+        if (d->cdt > d->dz * tol) return TETE_ERR_UNSTABLE;
         return TETE_OK;
     }
     // (25): dtau <= dz and dtau <= (dx^-2 + dy^-2)^(-1/2), equality allowed
@@ -302,6 +331,7 @@ tete_status tete_grid_create(const tete_grid_desc* d, void* dev_ws, size_t ws_by
     g->geo.np = (d->nx + 1) * g->geo.sp;
     g->fp32 = d->precision == TETE_FP32;
     g->yee = (d->flags & TETE_F_YEE) != 0;
+    g->implicit = (d->flags & TETE_F_IMPLICIT) != 0;
     if (g->yee && !yee_fits(g->geo, g->fp32 ? 4 : 8)) {   // planes too large for the Yee kernel's buffers
         free(g);
         return TETE_ERR_ARG;
@@ -368,7 +398,7 @@ tete_status tete_get_tuning(tete_grid* g, tete_tuning* t)
 {
     if (!g || !t) return TETE_ERR_ARG;
     *t = g->tune;
-    t->kernel = g->yee ? TETE_KERNEL_YEE
+    t->kernel = g->implicit ? TETE_KERNEL_IMPLICIT : g->yee ? TETE_KERNEL_YEE
               : use_fused2(g) ? TETE_KERNEL_FUSED2 : use_fused(g) ? TETE_KERNEL_FUSED : TETE_KERNEL_SPLIT;
     return TETE_OK;
 }
@@ -578,8 +608,8 @@ tete_status tete_energy(tete_grid* g, double* W, int64_t* n)
     if (g->yee) return TETE_ERR_STATE;
     DeviceGuard dg(g->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
-    if (g->fp32) HIPCHK(launch_energy<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->alpha, g->partial, g->scal, g->stream));
-    else HIPCHK(launch_energy<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->alpha, g->partial, g->scal, g->stream));
+    if (g->fp32) HIPCHK(launch_energy<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->alpha, rweight(g), g->partial, g->scal, g->stream));
+    else HIPCHK(launch_energy<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->alpha, rweight(g), g->partial, g->scal, g->stream));
     double v;
     HIPCHK(hipMemcpyAsync(&v, g->scal, sizeof(double), hipMemcpyDeviceToHost, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
@@ -622,10 +652,10 @@ tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h)
     Src s = source(g, g->n - 1);
     if (g->fp32)
         HIPCHK(launch_charges<float>(fields<float>(g, 1 - g->cur), fields<float>(g, g->cur), mats<float>(g), g->geo,
-                                     g->alpha, s, g->partial, g->scal + 2, g->stream));
+                                     g->alpha * rweight(g), s, g->partial, g->scal + 2, g->stream));
     else
         HIPCHK(launch_charges<double>(fields<double>(g, 1 - g->cur), fields<double>(g, g->cur), mats<double>(g),
-                                      g->geo, g->alpha, s, g->partial, g->scal + 2, g->stream));
+                                      g->geo, g->alpha * rweight(g), s, g->partial, g->scal + 2, g->stream));
     double v[2];
     HIPCHK(hipMemcpyAsync(v, g->scal + 2, sizeof(double) * 2, hipMemcpyDeviceToHost, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
@@ -885,7 +915,7 @@ tete_status tete_batch_set(tete_batch* b, int32_t slot, tete_grid* g)
     if (!b || slot < 0 || slot >= TETE_MAX_BATCH) return TETE_ERR_ARG;
     if (g) {
         if (g->fp32 != b->fp32 || g->device != b->device) return TETE_ERR_ARG;
-        if (g->yee || g->mat_set || !fused_fits(g->geo, g->fp32 ? 4 : 8)) return TETE_ERR_STATE;
+        if (g->yee || g->implicit || g->mat_set || !fused_fits(g->geo, g->fp32 ? 4 : 8)) return TETE_ERR_STATE;
         for (int s = 0; s < TETE_MAX_BATCH; ++s)
             if (s != slot && b->slot[s] == g) return TETE_ERR_ARG;
     }

@@ -149,9 +149,10 @@ hipError_t launch_batch_step2(BatchTable<R>* T, int grid, int flips, int steps, 
 template <typename R>
 hipError_t launch_batch_advance(BatchTable<R>* T, int steps, int flips, hipStream_t s);
 
-// energy of a state -> out[0] (FP64), using partial[RED_BLOCKS]
+// energy of a state -> out[0] (FP64), using partial[RED_BLOCKS]; rw weighs
+// the alpha^2 terms of Q (1: explicit scheme (23), 0: implicit scheme (16))
 template <typename R>
-hipError_t launch_energy(Fields<R> f, Mat<R> mat, Geo g, double alpha, double* partial, double* out,
+hipError_t launch_energy(Fields<R> f, Mat<R> mat, Geo g, double alpha, double rw, double* partial, double* out,
                          hipStream_t s);
 // charges: out[0] = max |q_e - node charge| (interior nodes), out[1] = max |q_h|
 template <typename R>
@@ -159,5 +160,20 @@ hipError_t launch_charges(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, dou
                           double* partial, double* out, hipStream_t s);
 template <typename R>
 hipError_t launch_probes(const R* ez, const int64_t* idx, int nprobe, double* out, hipStream_t s);
+
+// Work arrays of the implicit scheme's plane solves (np entries each)
+template <typename R>
+struct ImpWork {
+    R* b;        // right-hand side
+    R* r;        // residual
+    R* d[2];     // Chebyshev directions (ping-pong)
+};
+// One step of the implicit scheme (16) (tete_implicit.hip); ev[0..2] around
+// the two half steps if not NULL
+template <typename R>
+hipError_t launch_step_implicit(Fields<R> o, Fields<R> w, Mat<R> M, Geo g, double dx, double dy, R alpha, Src src,
+                                ImpWork<R> wk, hipStream_t s, hipEvent_t* ev);
+// Chebyshev iterations per plane solve and the spectral bound used
+int implicit_iters(const Geo& g, double dx, double dy, double alpha, int fp32, double* lmax);
 
 }  // namespace tete

@@ -367,8 +367,11 @@ __device__ __forceinline__ double ldd(const R* p, const Geo& g, int i, int j, in
 //   - a^2/2 [sum_hx mu_x (P_y e_z)^2 + sum_hy mu_y (P_x e_z)^2
 //            + sum_{ex,kappa>0} kappa_x (P_y^T h_z)^2 + sum_{ey,kappa>0} kappa_y (P_x^T h_z)^2]
 //   + a [sum_hx h_x P_z e_y - sum_hy h_y P_z e_x]
+// With rw = 0 the a^2 terms drop: the energy of the implicit scheme (16),
+// whose Q = B - alpha A holds no transverse operator.
 template <typename R>
-__global__ __launch_bounds__(RED_THREADS) void k_energy(Fields<R> f, Mat<R> M, Geo g, double a, double* partial)
+__global__ __launch_bounds__(RED_THREADS) void k_energy(Fields<R> f, Mat<R> M, Geo g, double a, double rw,
+                                                        double* partial)
 {
     const R *ex = f.c[0], *ey = f.c[1], *ez = f.c[2], *hx = f.c[3], *hy = f.c[4], *hz = f.c[5];
     double acc = 0.0;
@@ -409,7 +412,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_energy(Fields<R> f, Mat<R> M, G
             double mu = (double)muv(M, 2, idx), h = hz[idx];
             if (mu > 0.0) sq += h * h / mu;
         }
-        acc += 0.5 * sq - 0.5 * a * a * r + a * lc;
+        acc += 0.5 * sq - 0.5 * rw * a * a * r + a * lc;
     }
     double s = block_reduce<false>(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -603,9 +606,10 @@ hipError_t launch_step(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alph
 }
 
 template <typename R>
-hipError_t launch_energy(Fields<R> f, Mat<R> mat, Geo g, double alpha, double* partial, double* out, hipStream_t s)
+hipError_t launch_energy(Fields<R> f, Mat<R> mat, Geo g, double alpha, double rw, double* partial, double* out,
+                         hipStream_t s)
 {
-    k_energy<R><<<RED_BLOCKS, RED_THREADS, 0, s>>>(f, mat, g, alpha, partial);
+    k_energy<R><<<RED_BLOCKS, RED_THREADS, 0, s>>>(f, mat, g, alpha, rw, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_finish<false><<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, out);
@@ -640,7 +644,7 @@ hipError_t launch_probes(const R* ez, const int64_t* idx, int nprobe, double* ou
     template hipError_t launch_import_materials<R>(R* const[6], const void* const[6], int, Geo, hipStream_t);      \
     template hipError_t launch_zero_pec<R>(Fields<R>, Mat<R>, Geo, hipStream_t);                                   \
     template hipError_t launch_step<R>(Fields<R>, Fields<R>, Mat<R>, Geo, R, Src, hipStream_t, hipEvent_t*);                    \
-    template hipError_t launch_energy<R>(Fields<R>, Mat<R>, Geo, double, double*, double*, hipStream_t);           \
+    template hipError_t launch_energy<R>(Fields<R>, Mat<R>, Geo, double, double, double*, double*, hipStream_t);           \
     template hipError_t launch_charges<R>(Fields<R>, Fields<R>, Mat<R>, Geo, double, Src, double*, double*,        \
                                           hipStream_t);                                                            \
     template hipError_t launch_probes<R>(const R*, const int64_t*, int, double*, hipStream_t);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libtete.so")
 FP64, FP32 = 0, 1
 F_MATERIALS = 1
 F_YEE = 2
+F_IMPLICIT = 4
 MAX_BUNCH_CELLS = 8191
 MAX_WAKE = 65536
 MAX_PROBES = 16
@@ -45,7 +46,7 @@ class Tuning(C.Structure):
                 ("order", C.c_int32)]
 
 
-KERNELS = {"auto": 0, "fused": 1, "split": 2, "fused2": 3, "yee": 4}
+KERNELS = {"auto": 0, "fused": 1, "split": 2, "fused2": 3, "yee": 4, "implicit": 5}
 
 
 class Bunch(C.Structure):
@@ -143,9 +144,9 @@ def _chk(fn, code):
 
 
 def make_desc(nx, ny, nz, dx, dy, dz, cdt, precision="fp64", materials=False, max_series=0,
-              yee=False) -> GridDesc:
+              yee=False, implicit=False) -> GridDesc:
     prec = {"fp64": FP64, "fp32": FP32}[precision]
-    flags = (F_MATERIALS if materials else 0) | (F_YEE if yee else 0)
+    flags = (F_MATERIALS if materials else 0) | (F_YEE if yee else 0) | (F_IMPLICIT if implicit else 0)
     return GridDesc(nx, ny, nz, dx, dy, dz, cdt, prec, flags, max_series)
 
 
@@ -159,14 +160,15 @@ def workspace_bytes(desc: GridDesc) -> int:
 
 class Grid:
     """One explicit TE/TM grid (or, with yee=True, a grid stepped with Yee's
-    scheme (7) for comparison) living in a torch-owned device workspace."""
+    scheme (7), with implicit=True one stepped with the implicit TE/TM scheme
+    (16), for comparison) living in a torch-owned device workspace."""
 
     def __init__(self, nx, ny, nz, dx, dy, dz, cdt, precision="fp64", materials=False, max_series=0,
-                 device="cuda:0", stream=None, yee=False):
+                 device="cuda:0", stream=None, yee=False, implicit=False):
         import torch
         L = load()
         self.torch = torch
-        self.desc = make_desc(nx, ny, nz, dx, dy, dz, cdt, precision, materials, max_series, yee)
+        self.desc = make_desc(nx, ny, nz, dx, dy, dz, cdt, precision, materials, max_series, yee, implicit)
         _chk("tete_check_desc", L.tete_check_desc(C.byref(self.desc)))
         self.nbytes = workspace_bytes(self.desc)
         self.device = torch.device(device)

@@ -56,7 +56,7 @@ def test_descriptor_limits():
     d.precision = 7
     assert tete.check_desc(d) == "TETE_ERR_ARG"
     d = tete.make_desc(8, 8, 8, 2, 2, 1, 1)
-    d.flags = 4
+    d.flags = 8                                            # no such flag
     assert tete.check_desc(d) == "TETE_ERR_ARG"
     d = tete.make_desc(8, 8, 8, 2, 2, 1, 0.5, materials=True, yee=True)     # Yee is vacuum + PEC only
     assert tete.check_desc(d) == "TETE_ERR_ARG"
@@ -117,3 +117,24 @@ def test_rz_descriptor_limits_and_workspace():
     b = int(L.tete_rz_workspace_bytes(C.byref(d)))
     assert b >= 12 * 4 * np_ + np_
     assert int(L.tete_rz_workspace_bytes(C.byref(big))) == 0
+
+
+@pytest.mark.parametrize("dx,dz,cdt,want", [
+    (0.25e-3, 1e-3, 1e-3, "TETE_OK"),             # fine transverse mesh at dtau = dz: beyond (25), fine for (16)
+    (2e-3, 1e-3, 1e-3, "TETE_OK"),
+    (0.25e-3, 1e-3, 1.001e-3, "TETE_ERR_UNSTABLE"),  # dtau > dz
+])
+def test_implicit_stability_validation(dx, dz, cdt, want):
+    """Implicit grids are bounded by dtau <= dz only."""
+    assert tete.check_desc(tete.make_desc(24, 24, 48, dx, dx, dz, cdt, implicit=True)) == want
+    if dx < dz:
+        assert tete.check_desc(tete.make_desc(24, 24, 48, dx, dx, dz, cdt)) == "TETE_ERR_UNSTABLE"
+
+
+def test_implicit_flags_and_workspace():
+    assert tete.check_desc(tete.make_desc(8, 8, 8, 2, 2, 1, 1, implicit=True, materials=True)) == "TETE_ERR_ARG"
+    assert tete.check_desc(tete.make_desc(8, 8, 8, 2, 2, 1, 0.5, implicit=True, yee=True)) == "TETE_ERR_ARG"
+    np_ = 129 * 129 * 1025
+    b = tete.workspace_bytes(tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp32"))
+    bi = tete.workspace_bytes(tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp32", implicit=True))
+    assert bi - b == pytest.approx(4 * 4 * np_, rel=1e-3)       # four plane-solve arrays

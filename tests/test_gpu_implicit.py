@@ -1,0 +1,137 @@
+"""The implicit TE/TM scheme (16) on the GPU (TETE_F_IMPLICIT grids) against
+the implicit oracle (a sparse LU solve per half step): fields over ragged
+grids with obstacles, on a transverse mesh the explicit scheme's bound (25)
+allows and on one four times finer that it does not; the energy of (16); the
+time-averaged charge with a moving bunch; and the wake."""
+import numpy as np
+import pytest
+
+from oracle import implicit_oracle as IM
+from oracle import oracle as O
+from paper_0901_1053_amd import inputs, tete
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+EPS0 = 8.8541878128e-12
+SHAPES = [(13, 11, 37), (20, 17, 60), (2, 2, 2), (9, 20, 200)]
+MESHES = [(2.0e-3, 2.0e-3), (0.25e-3, 0.3e-3)]          # dx, dy with dz = 1 mm, dtau = dz
+
+
+def _oracle(shape, seed, mesh, steps):
+    nx, ny, nz = shape
+    g = O.Geom(nx, ny, nz, mesh[0], mesh[1], 1.0e-3, 1.0e-3)
+    m = O.vacuum_materials(g, inputs.random_cells(nx, ny, nz, seed, frac=0.1))
+    f = inputs.random_fields(g.shape, seed)
+    O.apply_pec(g, m, f)
+    S = IM.Implicit(g, m)
+    E0 = IM.energy(g, m, f)
+    for _ in range(steps):
+        S.step(f)
+    return f, E0, IM.energy(g, m, f)
+
+
+def _gpu(shape, seed, mesh, steps, precision="fp64"):
+    nx, ny, nz = shape
+    G = tete.Grid(nx, ny, nz, mesh[0], mesh[1], 1.0e-3, 1.0e-3, precision=precision, implicit=True)
+    G.set_pec_cells(inputs.random_cells(nx, ny, nz, seed, frac=0.1))
+    assert G.get_tuning()["kernel"] == "implicit"
+    G.set_fields(inputs.random_fields(G.shape, seed))
+    E0 = G.energy()[0]
+    G.step(steps)
+    return G, E0
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("mesh", MESHES)
+def test_implicit_matches_oracle(shape, mesh):
+    print("implicit parity", shape, mesh, flush=True)
+    ref, E0, E1 = _oracle(shape, 81, mesh, 12)
+    G, g0 = _gpu(shape, 81, mesh, 12)
+    assert P.field_rel_err(G.get_fields(), ref) <= 1e-12
+    assert abs(g0 - E0) <= 1e-12 * abs(E0)
+    assert abs(G.energy()[0] - E1) <= 1e-12 * abs(E1)
+    G32, _ = _gpu(shape, 81, mesh, 12, "fp32")
+    assert P.field_rel_err(G32.get_fields(), ref) <= 2e-5
+
+
+def test_implicit_energy_conserved_long_run():
+    """FP64 on the fine transverse mesh (beyond (25)): the energy of (16) stays
+    constant over 200 steps."""
+    G, E0 = _gpu((16, 16, 80), 82, MESHES[1], 0)
+    vals = [E0]
+    for _ in range(4):
+        G.step(50)
+        vals.append(G.energy()[0])
+    vals = np.array(vals)
+    assert np.max(np.abs(vals - vals[0])) <= 1e-12 * vals[0]
+
+
+def _wake_case():
+    nx, ny, nz = 12, 12, 90
+    dz = 1.0e-3
+    g = O.Geom(nx, ny, nz, 0.5e-3, 0.5e-3, dz, dz)               # transverse mesh beyond (25)
+    cells = inputs.random_cells(nx, ny, nz, 83, frac=0.0)
+    cells[:, :, 30:45] = 0
+    cells[:2, :, 30:45] = 1                                     # a slab on one side
+    b = dict(Q=1e-9, sigma=2.0e-3, i0=6, j0=6, M=12, jmin=-14, nw=60)
+    return g, cells, b
+
+
+def _oracle_wake(g, cells, b, steps):
+    """The bunch run of the explicit oracle around the implicit stepper: cell
+    charges crossing e_z edges (current = charge / dtau) and the wake quadrature
+    -1/2 (e_z^{n-1/2} + e_z^{n+1/2}) at n = k + M + j."""
+    m = O.vacuum_materials(g, cells)
+    S = IM.Implicit(g, m)
+    f = O.zeros(g)
+    lam = O.bunch_cells(b["Q"], b["sigma"], g.dz, b["M"])
+    acc = np.zeros(b["nw"])
+    i0, j0, M = b["i0"], b["j0"], b["M"]
+    for n in range(steps):
+        jz = np.zeros(g.shape)
+        for k in range(g.nz):
+            mm = k - n + M
+            if -M <= mm <= M:
+                jz[i0, j0, k] = lam[mm + M] / g.cdt
+        ezo = f["ez"][i0, j0, :].copy()
+        S.step(f, jz=jz)
+        for k in range(g.nz):
+            jj = n - k - M
+            if b["jmin"] <= jj < b["jmin"] + b["nw"]:
+                acc[jj - b["jmin"]] += -0.5 * (ezo[k] + f["ez"][i0, j0, k])
+    return acc / (b["Q"] * EPS0), f
+
+
+def test_implicit_wake_and_charges():
+    """Wake of a bunch through a slab on a transverse mesh beyond (25): FP64
+    within 1e-12 and FP32 within 1e-5 of the oracle (relative to the largest
+    |W|), FP64 fields within 5e-12; the time-averaged charge equals the bunch
+    charge at every free node (max residual / Q below 1e-13 in FP64)."""
+    g, cells, b = _wake_case()
+    steps = g.nz + 2 * b["M"] + b["jmin"] + b["nw"]
+    W, fo = _oracle_wake(g, cells, b, steps)
+    assert np.max(np.abs(W)) > 0
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        G = tete.Grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.cdt, precision=prec, implicit=True)
+        G.set_pec_cells(cells)
+        G.set_bunch(b["Q"], b["sigma"], b["i0"], b["j0"], b["M"], b["jmin"], b["nw"])
+        G.step(steps)
+        got = G.wake()
+        assert np.max(np.abs(got - W)) <= tol * np.max(np.abs(W)), prec
+        if prec == "fp64":
+            # the oracle solves each half step by LU and the GPU iterates: both
+            # round differently in each of the 2 x 160 solves, so the fields of this
+            # driven run are held to 5e-12 (the wake above to 1e-12)
+            assert P.field_rel_err(G.get_fields(), fo) <= 5e-12
+            G.step(3)                                         # the bunch is still in the grid
+            res_e, abs_h = G.charges()
+            assert res_e <= 1e-13 * b["Q"] and abs_h <= 1e-13 * b["Q"]
+
+
+def test_implicit_refused_in_batch():
+    G, _ = _gpu((8, 8, 40), 84, MESHES[0], 1, "fp32")
+    B = tete.Batch("fp32")
+    with pytest.raises(tete.TeteError) as e:
+        B.set(0, G)
+    assert e.value.status == "TETE_ERR_STATE"
