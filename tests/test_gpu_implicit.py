@@ -135,3 +135,38 @@ def test_implicit_refused_in_batch():
     with pytest.raises(tete.TeteError) as e:
         B.set(0, G)
     assert e.value.status == "TETE_ERR_STATE"
+
+
+def test_implicit_full_size_properties():
+    """At the benchmark's full size (512 x 512 x 2048, its geometry and launch):
+    from seeded random fields, the FP64 energy of (16) is constant over three
+    steps to 1e-12, and the FP32 fields stay within 1e-5 of the FP64 ones (both
+    runs iterate the plane solves to their precision)."""
+    import torch
+    case = inputs.large_case()
+    print("implicit full size", case.name, flush=True)
+    cells = case.cell_mask()
+    out = {}
+    for prec in ("fp64", "fp32"):
+        G = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.cdt, precision=prec, implicit=True)
+        G.set_pec_cells(cells)
+        f0 = inputs.random_fields_torch(G.shape, case.seed, "cuda", torch.float64)
+        G.set_fields(f0, dtype="fp64")
+        del f0
+        E0 = G.energy()[0]
+        G.step(3)
+        E1 = G.energy()[0]
+        if prec == "fp64":
+            assert abs(E1 - E0) <= 1e-12 * abs(E0)
+        else:
+            assert abs(E1 - E0) <= 1e-5 * abs(E0)
+        out[prec] = G.get_fields(dtype="fp64", numpy=False)
+        G.close()
+        del G
+        torch.cuda.empty_cache()
+    for k in tete.KEYS:
+        ref = out["fp64"][k]
+        d = torch.max(torch.abs(out["fp32"][k] - ref)).item()
+        assert d <= 1e-5 * max(torch.max(torch.abs(ref)).item(), 1.0), k
+    del out
+    torch.cuda.empty_cache()
