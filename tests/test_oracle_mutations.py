@@ -15,6 +15,7 @@ import pytest
 from tests import test_oracle_dense as TD
 from tests import test_oracle_dispersion as TP
 from tests import test_oracle_invariants as TI
+from tests import test_oracle_witness as TW
 from tests import test_oracle_yee as TY
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -242,5 +243,54 @@ def test_implicit_pins_catch_planted_mistake(tmp_path, name):
             with np.errstate(all="ignore"):
                 pin(mod)
         except (AssertionError, FloatingPointError, ValueError, np.linalg.LinAlgError, RuntimeError):
+            caught += 1
+    assert caught >= 1, "no pin caught mutant %s" % name
+
+
+WO_SRC = os.path.join(os.path.dirname(HERE), "oracle", "witness_oracle.py")
+
+WO_MUTANTS = {
+    # the quadrature one sample late
+    "wo_time_index": ([("js = n - k - bunch.M", "js = n + 1 - k - bunch.M")],
+                      [lambda w: TW.test_centre_line_is_the_bunch_line_wake(w),
+                       lambda w: TW.test_witness_causality(w)]),
+    # only the new level of e_z in the quadrature
+    "wo_no_average": ([("-0.5 * (old[l][ok] + new[ok])", "-1.0 * new[ok]")],
+                      [lambda w: TW.test_centre_line_is_the_bunch_line_wake(w)]),
+    # the -x and +x neighbours swapped
+    "wo_swapped_x": ([("OFFSETS = ((0, 0), (-1, 0), (1, 0),", "OFFSETS = ((0, 0), (1, 0), (-1, 0),")],
+                     [lambda w: TW.test_transverse_wake_matches_lorentz_force(w)]),
+    # a neighbour line two cells out
+    "wo_far_y": ([("(0, -1), (0, 1))", "(0, -2), (0, 1))")],
+                 [lambda w: TW.test_mirror_symmetry_of_off_axis_wakes(w),
+                  lambda w: TW.test_transverse_wake_matches_lorentz_force(w)]),
+    # one-cell difference taken as the centred one
+    "wo_half_width": ([("(W[2] - W[1]) / (2.0 * dx)", "(W[2] - W[1]) / dx")],
+                      [lambda w: TW.test_transverse_wake_matches_lorentz_force(w)]),
+    # rectangle rule instead of the trapezoid, one sample late
+    "wo_rectangle": ([("out[1:] = np.cumsum(0.5 * (D[1:] + D[:-1])) * ds", "out[1:] = np.cumsum(D[:-1]) * ds")],
+                     [lambda w: TW.test_transverse_wake_matches_lorentz_force(w)]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(WO_MUTANTS))
+def test_witness_pins_catch_planted_mistake(tmp_path, name):
+    edits, pins = WO_MUTANTS[name]
+    src = open(WO_SRC).read()
+    for old, new in edits:
+        assert src.count(old) >= 1, (name, old)
+        src = src.replace(old, new, 1)
+    p = tmp_path / (name + ".py")
+    p.write_text(src)
+    spec = importlib.util.spec_from_file_location("wo_mutant_" + name, str(p))
+    mod = importlib.util.module_from_spec(spec)
+    sys.modules[spec.name] = mod
+    spec.loader.exec_module(mod)
+    caught = 0
+    for pin in pins:
+        try:
+            with np.errstate(all="ignore"):
+                pin(mod)
+        except (AssertionError, FloatingPointError, ValueError):
             caught += 1
     assert caught >= 1, "no pin caught mutant %s" % name
