@@ -187,6 +187,35 @@ def yee_section(G, case, precision, steps=20):
                       "run_time_vs_yee_at_dx_sqrt2_dz": round((10 / 6) / 2 ** 0.5, 3)}}
 
 
+def witness_section(G, case, two_step_ms, offset=32, steps=20):
+    """Off-axis and transverse wakes on the large workload: a witness node
+    `offset` cells from the bunch line in x.  Each two-step launch also keeps
+    e_z^{n+1/2} of the five witness lines, and a small kernel over the lines
+    follows it; time per step from HIP events on the grid's stream around whole
+    launches, the step kernel's own time from the grid's timing, and the ratio
+    to the two-step kernel without a witness."""
+    import torch
+    G.set_witness(case.i0 + offset, case.j0)
+    G.step(2)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(G.stream)
+    G.step(steps)
+    e1.record(G.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    G.set_timing(steps)
+    G.step(steps)
+    ms_k, _, n = G.timing()
+    G.set_timing(0)
+    G.clear_witness()
+    return {"workload": case.name, "witness_offset_cells": [offset, 0], "lines": 5,
+            "ms_per_step": round(ms, 4), "step_kernel_ms": round(ms_k / n, 4),
+            "line_kernel_and_gap_ms": round(ms - ms_k / n, 4),
+            "vs_two_step_without_witness": round(ms / two_step_ms, 3)}
+
+
 def implicit_section(case, precision, explicit_ms_per_step, steps=4):
     """The implicit TE/TM scheme (16) on the large workload: kernel time per step
     (HIP events around the two half steps on the grid's stream), the Chebyshev
@@ -285,6 +314,7 @@ def main():
     ap.add_argument("--no-yee", action="store_true", help="skip the comparison with Yee's scheme")
     ap.add_argument("--no-rz", action="store_true", help="skip the rotationally symmetric workload")
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit scheme (16) comparison")
+    ap.add_argument("--no-witness", action="store_true", help="skip the off-axis witness timing")
     ap.add_argument("--batched-count", type=int, default=64)
     ap.add_argument("--serve-rates", default="1,20,200", help="comma-separated request rates (req/s)")
     ap.add_argument("--serve-requests", type=int, default=12)
@@ -390,6 +420,9 @@ def main():
     if not args.no_yee:
         out["yee_context"] = yee_section(G, case, args.precision)
         print("# yee comparison done", file=sys.stderr, flush=True)
+    if not args.no_witness:
+        out["witness_context"] = witness_section(G, case, ms_step)
+        print("# witness timing done", file=sys.stderr, flush=True)
     del G
     torch.cuda.empty_cache()
     if not args.no_implicit:

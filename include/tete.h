@@ -93,6 +93,7 @@ enum {
     TETE_MAX_BUNCH_CELLS = 8191, /* 2M+1 cells of the truncated bunch */
     TETE_MAX_WAKE = 65536,       /* wake samples */
     TETE_MAX_PROBES = 16,        /* e_z probe points */
+    TETE_WITNESS_LINES = 5,      /* e_z lines of a witness: its node and four neighbours */
     TETE_MAX_BATCH = 256         /* instances of one batch */
 };
 
@@ -197,6 +198,37 @@ tete_status tete_steps_done(tete_grid* g, int64_t* n);
  * (HOST array W of at least nw doubles).  Sample j is complete once step
  * nz - 1 + half_cells + j has run.  Synchronises the stream. */
 tete_status tete_wake(tete_grid* g, double* W, int32_t nw);
+
+/* Witness lines: off-axis and transverse wakes (Sec. 5 with the Panofsky-
+ * Wenzel theorem).  The longitudinal wake of tete_wake is also sampled, with
+ * the same quadrature, samples s_j and normalisation, on the e_z node lines
+ * through (iw, jw), (iw-1, jw), (iw+1, jw), (iw, jw-1) and (iw, jw+1), for
+ * 1 <= iw <= nx-1, 1 <= jw <= ny-1; the bunch line (i0, j0) may be another.
+ * Requires a bunch (TETE_ERR_STATE otherwise); resets the witness
+ * accumulators, as do tete_set_bunch and tete_set_fields.  A two-step launch
+ * also keeps e_z^{n+1/2} of the five lines (in the workspace; the FP32 32-row
+ * shape then runs as 16 rows), and a small kernel over the lines adds both
+ * steps' terms after it; a single step is followed by the same kernel for
+ * one step.  The results do not depend on the kernel.  A grid with a
+ * witness cannot join a batch (TETE_ERR_STATE).  Errors: TETE_ERR_ARG
+ * (range). */
+tete_status tete_set_witness(tete_grid* g, int32_t iw, int32_t jw);
+
+/* Stop sampling the witness lines. */
+tete_status tete_clear_witness(tete_grid* g);
+
+/* Witness wakes for nw samples (1 <= nw <= the bunch's nw), HOST arrays:
+ * W[l * nw + j] = W_par(s_j) on line l in the order of tete_set_witness
+ * (witness node first), in V/C.  Wx, Wy (either may be NULL; nw doubles
+ * each): the transverse wake at the witness node, W_perp(s_j) = integral
+ * from s_jmin to s_j of grad_perp W_par ds, the gradient by centred
+ * differences over 2 dx (2 dy) and the integral by the trapezoid rule, zero
+ * at the first sample (choose jmin ahead of the bunch, jmin <= -half_cells,
+ * so that the integral starts before any wake), in V/C; W_perp is the
+ * integral of (E + v x B)_perp along the witness path over Q.  Sample j is
+ * complete once step nz - 1 + half_cells + j has run.  Synchronises the
+ * stream.  TETE_ERR_STATE without a bunch or witness. */
+tete_status tete_witness_wake(tete_grid* g, double* W, double* Wx, double* Wy, int32_t nw);
 
 /* Discrete energy W^{n,e} = 1/2 <Q^e y^n, y^n> (Sec. 4.4) of the current
  * state, FP64, internal units (joules = W / eps0 with charge in coulombs);

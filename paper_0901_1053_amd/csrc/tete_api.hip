@@ -21,7 +21,7 @@ constexpr size_t kAlign = 256;
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t lam, wacc, partial, scal, pidx, eser, pser, code, field[12], mat[6], imp[4], total;
+    size_t lam, wacc, wit, wmid, partial, scal, pidx, eser, pser, code, field[12], mat[6], imp[4], total;
 };
 
 int64_t series_cap(const tete_grid_desc* d) { return d->max_series > 0 ? d->max_series : 4096; }
@@ -33,6 +33,8 @@ bool make_layout(const tete_grid_desc* d, Layout* L)
     size_t o = 0;
     L->lam = o;     o = up(o + sizeof(double) * TETE_MAX_BUNCH_CELLS);
     L->wacc = o;    o = up(o + sizeof(double) * TETE_MAX_WAKE);
+    L->wit = o;     o = up(o + sizeof(double) * TETE_WITNESS_LINES * TETE_MAX_WAKE);
+    L->wmid = o;    o = up(o + rb * TETE_WITNESS_LINES * (size_t)d->nz);
     L->partial = o; o = up(o + sizeof(double) * 2 * RED_BLOCKS);
     L->scal = o;    o = up(o + sizeof(double) * 64);
     L->pidx = o;    o = up(o + sizeof(int64_t) * TETE_MAX_PROBES);
@@ -86,6 +88,10 @@ struct tete_grid {
     void* mat[6];
     int mat_set;
     double *lam, *wacc, *partial, *scal, *eser, *pser;
+    double* wit;       // witness accumulators, TETE_WITNESS_LINES x TETE_MAX_WAKE
+    void* wmid;        // e_z^{n+1/2} of the witness lines in a two-step launch (TETE_WITNESS_LINES x nz)
+    int witness;       // witness lines armed (tete_set_witness)
+    int32_t iw, jw;
     int64_t* pidx;
     int64_t n;         // steps since create / set_fields
     int has_bunch;
@@ -143,6 +149,30 @@ Src source(tete_grid* g, int64_t n)
     return s;
 }
 
+// Witness node and its neighbours -x, +x, -y, +y (the order of tete_witness_wake)
+constexpr int kWdi[TETE_WITNESS_LINES] = {0, -1, 1, 0, 0};
+constexpr int kWdj[TETE_WITNESS_LINES] = {0, 0, 0, -1, 1};
+
+// Array offsets of (i, j, 0) of the witness node line and its four neighbours,
+// in the order of tete_witness_wake
+Witness witness_lines(const tete_grid* g)
+{
+    Witness w;
+    for (int l = 0; l < TETE_WITNESS_LINES; ++l)
+        w.base[l] = ((int64_t)(g->iw + kWdi[l]) * g->geo.sp + (int64_t)(g->jw + kWdj[l]) * g->geo.sz);
+    return w;
+}
+
+template <typename R>
+WitMid<R> witness_mid(const tete_grid* g)
+{
+    WitMid<R> w;
+    w.mid = (R*)g->wmid;
+    w.iw = g->iw;
+    w.jw = g->jw;
+    return w;
+}
+
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
 // weight of the alpha^2 terms in the energy and the charges: none for the
@@ -197,6 +227,7 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             g->ecount++;
         }
         // two steps at once unless the state after the first is observed
+        const bool wit = g->witness && g->has_bunch;
         const bool pair = two && s + 1 < nsteps && g->nprobe == 0 &&
                           !(g->diag_every > 0 && (g->n + 1) % g->diag_every == 0);
         hipEvent_t* ev = nullptr;
@@ -207,9 +238,15 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             g->ev_steps++;
         }
         if (pair) {
+            WitMid<R> wm;
+            if (wit) wm = witness_mid<R>(g);
             HIPCHK(launch_step_fused2<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
-                                         source(g, g->n), fused2_rows(g), g->tune.xchunk, g->tune.order, g->stream,
-                                         ev));
+                                         source(g, g->n), wit ? &wm : nullptr, fused2_rows(g), g->tune.xchunk,
+                                         g->tune.order, g->stream, ev));
+            if (wit)   // e_z^{n-1/2} in the old set, e_z^{n+1/2} in wm.mid, e_z^{n+3/2} in the new set
+                HIPCHK(launch_witness2<R>((const R*)g->f[g->cur][2], wm.mid, (const R*)g->f[1 - g->cur][2],
+                                          witness_lines(g), g->geo, g->n, g->b.half_cells, g->b.jmin, g->b.nw,
+                                          g->wit, g->stream));
             g->cur = 1 - g->cur;
             g->n += 2;
             ++s;
@@ -228,6 +265,9 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
         else
             HIPCHK(launch_step<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                   source(g, g->n), g->stream, ev));
+        if (wit)   // the step leaves e_z^{n-1/2} in the old set and e_z^{n+1/2} in the new one
+            HIPCHK(launch_witness<R>((const R*)g->f[g->cur][2], (const R*)g->f[1 - g->cur][2], witness_lines(g),
+                                     g->geo, g->n, g->b.half_cells, g->b.jmin, g->b.nw, g->wit, g->stream));
         g->cur = 1 - g->cur;
         g->n++;
         if (g->nprobe > 0) {
@@ -245,6 +285,7 @@ tete_status reset_series(tete_grid* g)
     g->ecount = 0;
     g->pcount = 0;
     HIPCHK(launch_fill_f64(g->wacc, TETE_MAX_WAKE, 0.0, g->stream));
+    HIPCHK(launch_fill_f64(g->wit, (int64_t)TETE_WITNESS_LINES * TETE_MAX_WAKE, 0.0, g->stream));
     return TETE_OK;
 }
 
@@ -343,6 +384,8 @@ tete_status tete_grid_create(const tete_grid_desc* d, void* dev_ws, size_t ws_by
     for (int c = 0; c < 6; ++c) g->mat[c] = (d->flags & TETE_F_MATERIALS) ? g->ws + L.mat[c] : nullptr;
     g->lam = (double*)(g->ws + L.lam);
     g->wacc = (double*)(g->ws + L.wacc);
+    g->wit = (double*)(g->ws + L.wit);
+    g->wmid = g->ws + L.wmid;
     g->partial = (double*)(g->ws + L.partial);
     g->scal = (double*)(g->ws + L.scal);
     g->pidx = (int64_t*)(g->ws + L.pidx);
@@ -527,6 +570,7 @@ tete_status tete_set_bunch(tete_grid* g, const tete_bunch* b)
     if (!dg.ok) return TETE_ERR_DEVICE;
     HIPCHK(launch_lambda(g->lam, b->charge_C, b->sigma_z, g->d.dz, b->half_cells, g->stream));
     HIPCHK(launch_fill_f64(g->wacc, TETE_MAX_WAKE, 0.0, g->stream));
+    HIPCHK(launch_fill_f64(g->wit, (int64_t)TETE_WITNESS_LINES * TETE_MAX_WAKE, 0.0, g->stream));
     g->b = *b;
     g->has_bunch = 1;
     return TETE_OK;
@@ -599,6 +643,61 @@ tete_status tete_wake(tete_grid* g, double* W, int32_t nw)
     HIPCHK(hipStreamSynchronize(g->stream));
     const double s = 1.0 / (g->b.charge_C * kEps0);
     for (int j = 0; j < nw; ++j) W[j] *= s;
+    return TETE_OK;
+}
+
+tete_status tete_set_witness(tete_grid* g, int32_t iw, int32_t jw)
+{
+    if (!g) return TETE_ERR_ARG;
+    if (!g->has_bunch) return TETE_ERR_STATE;
+    if (iw < 1 || iw > g->d.nx - 1 || jw < 1 || jw > g->d.ny - 1) return TETE_ERR_ARG;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    HIPCHK(launch_fill_f64(g->wit, (int64_t)TETE_WITNESS_LINES * TETE_MAX_WAKE, 0.0, g->stream));
+    g->iw = iw;
+    g->jw = jw;
+    g->witness = 1;
+    return TETE_OK;
+}
+
+tete_status tete_clear_witness(tete_grid* g)
+{
+    if (!g) return TETE_ERR_ARG;
+    g->witness = 0;
+    return TETE_OK;
+}
+
+tete_status tete_witness_wake(tete_grid* g, double* W, double* Wx, double* Wy, int32_t nw)
+{
+    if (!g || !W) return TETE_ERR_ARG;
+    if (!g->has_bunch || !g->witness) return TETE_ERR_STATE;
+    if (nw < 1 || nw > g->b.nw) return TETE_ERR_ARG;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    for (int l = 0; l < TETE_WITNESS_LINES; ++l)
+        HIPCHK(hipMemcpyAsync(W + (size_t)l * nw, g->wit + (size_t)l * TETE_MAX_WAKE, sizeof(double) * nw,
+                              hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    const double q = 1.0 / (g->b.charge_C * kEps0);
+    for (size_t e = 0; e < (size_t)TETE_WITNESS_LINES * nw; ++e) W[e] *= q;
+    // Panofsky-Wenzel: dW_perp/ds = grad_perp W_par, centred differences across
+    // the witness node, trapezoid rule in s from the first sample
+    const double ds = g->d.dz;
+    const double* Wm[2] = {W + 1 * (size_t)nw, W + 3 * (size_t)nw};
+    const double* Wp[2] = {W + 2 * (size_t)nw, W + 4 * (size_t)nw};
+    const double h2[2] = {2.0 * g->d.dx, 2.0 * g->d.dy};
+    double* out[2] = {Wx, Wy};
+    for (int c = 0; c < 2; ++c) {
+        if (!out[c]) continue;
+        double prev = (Wp[c][0] - Wm[c][0]) / h2[c], sum = 0.0;
+        out[c][0] = 0.0;
+        for (int j = 1; j < nw; ++j) {
+            const double d = (Wp[c][j] - Wm[c][j]) / h2[c];
+            sum += 0.5 * (d + prev) * ds;
+            out[c][j] = sum;
+            prev = d;
+        }
+    }
     return TETE_OK;
 }
 
@@ -915,7 +1014,8 @@ tete_status tete_batch_set(tete_batch* b, int32_t slot, tete_grid* g)
     if (!b || slot < 0 || slot >= TETE_MAX_BATCH) return TETE_ERR_ARG;
     if (g) {
         if (g->fp32 != b->fp32 || g->device != b->device) return TETE_ERR_ARG;
-        if (g->yee || g->implicit || g->mat_set || !fused_fits(g->geo, g->fp32 ? 4 : 8)) return TETE_ERR_STATE;
+        if (g->yee || g->implicit || g->mat_set || g->witness || !fused_fits(g->geo, g->fp32 ? 4 : 8))
+            return TETE_ERR_STATE;
         for (int s = 0; s < TETE_MAX_BATCH; ++s)
             if (s != slot && b->slot[s] == g) return TETE_ERR_ARG;
     }

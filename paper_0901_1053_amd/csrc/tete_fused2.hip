@@ -172,9 +172,11 @@ inline int lanes2(int real_bytes, int rows) { return real_bytes == 8 || rows == 
 
 // Two steps of one tile (ty, tz) and x-chunk cx.  Every thread of the
 // workgroup must call it (it contains barriers).
-template <typename R, int TYH, int NB, int LW>
+// WIT: also keep stage A's e_z^{n+1/2} on the witness lines of wm (a
+// separate instance; the kernel without witness lines is unchanged).
+template <typename R, int TYH, int NB, int LW, bool WIT = false>
 __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, const int tz, const int cx,
-                                            Lds2<R, TYH, NB, LW>& L)
+                                            Lds2<R, TYH, NB, LW>& L, const WitMid<R>& wm = WitMid<R>{})
 {
     constexpr int PD = 1;         // planes prefetched: a second one does not fit the register budget
     constexpr int TY = TYH - 6;   // rows owned
@@ -360,6 +362,15 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
         const Out<R> oB = stage_plane(SB, In<R>{oA.ex14, bEY, bEZ, bHX, bHY, bHZ}, nB, fB, injB);
 
         if (srcA) ezA = oA.ezold1;
+        if constexpr (WIT) {
+            // e_z^{n+1/2} of edge k at plane p-1, final on owned entries
+            const int di = p - 1 - wm.iw, dj = j - wm.jw;
+            const bool on = (dj == 0 && di >= -1 && di <= 1) || ((dj == 1 || dj == -1) && di == 0);
+            if (on && owned && xown(p - 1) && k < g.nz) {
+                const int l = dj == 0 ? (di == 0 ? 0 : di < 0 ? 1 : 2) : (dj < 0 ? 3 : 4);
+                wm.mid[l * g.nz + k] = oA.ezh1;
+            }
+        }
         // wave-uniform (one row per wave: srcB itself)
         if (srcBw) {
             const R ezA_km = lane_prev(ezA), ezB_km = lane_prev(oB.ezold1);
@@ -411,6 +422,17 @@ __global__ __launch_bounds__(TYH * LW) void k_fused2(FArgs<R> A)
     int ty, tz, cx;
     if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) return;   // whole group
     fused2_tile<R, S::rows, S::nb, S::lw>(A, ty, tz, cx, L);
+}
+
+// The two-step kernel that also keeps e_z^{n+1/2} of the witness lines.
+template <typename R, int TYH, int LW>
+__global__ __launch_bounds__(TYH * LW) void k_fused2_wit(FArgs<R> A, WitMid<R> wm)
+{
+    typedef Shape2<R, TYH, LW> S;
+    __shared__ Lds2<R, S::rows, S::nb, S::lw> L;
+    int ty, tz, cx;
+    if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) return;   // whole group
+    fused2_tile<R, S::rows, S::nb, S::lw, true>(A, ty, tz, cx, L, wm);
 }
 
 // Two steps of every active instance of a batch, by a persistent grid, as the
@@ -507,16 +529,23 @@ bool fused2_fits(Geo g, int real_bytes)
 }
 
 template <typename R>
-hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha, Src src, int rows, int xchunk,
-                              int order, hipStream_t s, hipEvent_t* ev)
+hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha, Src src, const WitMid<R>* wm,
+                              int rows, int xchunk, int order, hipStream_t s, hipEvent_t* ev)
 {
     FArgs<R> A = fused_args<R>(o, nf, M, g, alpha, src);
+    if (wm) rows = 0;   // the instance that keeps witness lines has the default shape only
     if (!fused2_setup<R>(A, rows, xchunk, order)) return hipErrorInvalidValue;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
     bool done = false;
+    if (wm) {
+        if (wm->iw < 1 || wm->iw > g.nx - 1 || wm->jw < 1 || wm->jw > g.ny - 1) return hipErrorInvalidValue;
+        k_fused2_wit<R, Default2<R>::rows, Default2<R>::lw>
+            <<<A.nblk, Default2<R>::rows * Default2<R>::lw, 0, s>>>(A, *wm);
+        done = true;
+    }
     if constexpr (sizeof(R) == 4) {
-        if (rows == 32) {
+        if (!done && rows == 32) {
             k_fused2<R, 32, 32><<<A.nblk, 32 * 32, 0, s>>>(A);
             done = true;
         }
@@ -531,8 +560,8 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
 #define TETE_FUSED2_INST(R)                                                                                    \
     template hipError_t launch_batch_step2<R>(BatchTable<R>*, int, int, int, hipStream_t);                     \
     template bool fused2_setup<R>(FArgs<R>&, int, int, int);                                                   \
-    template hipError_t launch_step_fused2<R>(Fields<R>, Fields<R>, Mat<R>, Geo, R, Src, int, int, int,         \
-                                              hipStream_t, hipEvent_t*);
+    template hipError_t launch_step_fused2<R>(Fields<R>, Fields<R>, Mat<R>, Geo, R, Src, const WitMid<R>*, int, \
+                                              int, int, hipStream_t, hipEvent_t*);
 TETE_FUSED2_INST(float)
 TETE_FUSED2_INST(double)
 

@@ -44,6 +44,20 @@ struct Src {
 
 enum { RED_BLOCKS = 2048, RED_THREADS = 256 };
 
+// Witness lines (tete_set_witness): array offset of (i, j, 0) of each e_z
+// node line
+struct Witness {
+    int64_t base[TETE_WITNESS_LINES];
+};
+// e_z^{n+1/2} of the witness lines, kept by the two-step kernel for the line
+// kernel that runs after it: mid[l * nz + k], lines l in the order (iw, jw),
+// (iw-1, jw), (iw+1, jw), (iw, jw-1), (iw, jw+1)
+template <typename R>
+struct WitMid {
+    R* mid;
+    int iw, jw;
+};
+
 // Arguments of one grid's fused step: old and new fields, PEC codes, vacuum
 // coefficients, source, and the tiling (tete_fused.hip).
 template <typename R>
@@ -128,9 +142,10 @@ bool fused2_fits(Geo g, int real_bytes);
 // rows: 0 (default), 16, or 32 (FP32 only: 32 rows of 32 lanes).
 template <typename R>
 bool fused2_setup(FArgs<R>& A, int rows, int xchunk, int order);
+// wm (or nullptr): the witness lines whose e_z^{n+1/2} the launch keeps
 template <typename R>
-hipError_t launch_step_fused2(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src, int rows,
-                              int xchunk, int order, hipStream_t s, hipEvent_t* ev);
+hipError_t launch_step_fused2(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src,
+                              const WitMid<R>* wm, int rows, int xchunk, int order, hipStream_t s, hipEvent_t* ev);
 // One step of Yee's scheme (7) (tete_yee.hip): state (e^{n-1/2}, h^n),
 // dtau = 2 alpha; xchunk and order as for the fused step.
 bool yee_fits(Geo g, int real_bytes);
@@ -160,6 +175,16 @@ hipError_t launch_charges(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, dou
                           double* partial, double* out, hipStream_t s);
 template <typename R>
 hipError_t launch_probes(const R* ez, const int64_t* idx, int nprobe, double* out, hipStream_t s);
+// wake quadrature of one step n on the witness lines: acc[l * TETE_MAX_WAKE +
+// j - jmin] += -1/2 (e_z^{n-1/2} + e_z^{n+1/2}) of edge k, j = n - k - M
+template <typename R>
+hipError_t launch_witness(const R* ez_old, const R* ez_new, Witness w, Geo g, int64_t n, int M, int jmin, int nw,
+                          double* acc, hipStream_t s);
+// the same for steps n and n+1 of one two-step launch, e_z^{n+1/2} from the
+// lines' mid buffer (WitMid)
+template <typename R>
+hipError_t launch_witness2(const R* ez_old, const R* ez_mid, const R* ez_new, Witness w, Geo g, int64_t n, int M,
+                           int jmin, int nw, double* acc, hipStream_t s);
 
 // Work arrays of the implicit scheme's plane solves (np entries each)
 template <typename R>

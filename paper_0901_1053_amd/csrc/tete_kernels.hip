@@ -512,6 +512,39 @@ __global__ void k_probes(const R* ez, const int64_t* idx, int n, double* out)
     if (t < n) out[t] = (double)ez[idx[t]];
 }
 
+// One thread per (edge k, line blockIdx.y).  Within one step the edges of a
+// line feed distinct samples, so no two threads add to one accumulator.
+template <typename R>
+__global__ void k_witness(const R* ez_old, const R* ez_new, Witness w, int nz, int64_t n, int M, int jmin, int nw,
+                          double* acc)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nz) return;
+    const int64_t js = n - k - M;
+    if (js < jmin || js >= (int64_t)jmin + nw) return;
+    const int l = blockIdx.y;
+    const int64_t o = w.base[l] + k;
+    acc[(int64_t)l * TETE_MAX_WAKE + (js - jmin)] += -0.5 * ((double)ez_old[o] + (double)ez_new[o]);
+}
+
+// Two steps n, n+1 of one two-step launch, one thread per (sample, line):
+// sample j takes edge k = n - j - M in step n and edge k+1 in step n+1, added
+// in that order, as two single steps would add them.
+template <typename R>
+__global__ void k_witness2(const R* ez_old, const R* ez_mid, const R* ez_new, Witness w, int nz, int64_t n, int M,
+                           int jmin, int nw, double* acc)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nw) return;
+    const int l = blockIdx.y;
+    const int64_t k = n - ((int64_t)jmin + t) - M;
+    const R* mid = ez_mid + (int64_t)l * nz;
+    double a = acc[(int64_t)l * TETE_MAX_WAKE + t];
+    if (k >= 0 && k < nz) a += -0.5 * ((double)ez_old[w.base[l] + k] + (double)mid[k]);
+    if (k + 1 >= 0 && k + 1 < nz) a += -0.5 * ((double)mid[k + 1] + (double)ez_new[w.base[l] + k + 1]);
+    acc[(int64_t)l * TETE_MAX_WAKE + t] = a;
+}
+
 inline int nblocks(int64_t n, int tb) { return (int)((n + tb - 1) / tb); }
 
 }  // namespace
@@ -638,6 +671,30 @@ hipError_t launch_probes(const R* ez, const int64_t* idx, int nprobe, double* ou
     return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_witness2(const R* ez_old, const R* ez_mid, const R* ez_new, Witness w, Geo g, int64_t n, int M,
+                           int jmin, int nw, double* acc, hipStream_t s)
+{
+    if (nw < 1 || nw > TETE_MAX_WAKE) return hipErrorInvalidValue;
+    for (int l = 0; l < TETE_WITNESS_LINES; ++l)   // every line inside the array
+        if (w.base[l] < 0 || w.base[l] + g.nz > (int64_t)g.np) return hipErrorInvalidValue;
+    k_witness2<R><<<dim3(nblocks(nw, TB), TETE_WITNESS_LINES), TB, 0, s>>>(ez_old, ez_mid, ez_new, w, g.nz, n, M,
+                                                                          jmin, nw, acc);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_witness(const R* ez_old, const R* ez_new, Witness w, Geo g, int64_t n, int M, int jmin, int nw,
+                          double* acc, hipStream_t s)
+{
+    if (nw < 1 || nw > TETE_MAX_WAKE) return hipErrorInvalidValue;
+    for (int l = 0; l < TETE_WITNESS_LINES; ++l)   // every line inside the array
+        if (w.base[l] < 0 || w.base[l] + g.nz > (int64_t)g.np) return hipErrorInvalidValue;
+    k_witness<R><<<dim3(nblocks(g.nz, TB), TETE_WITNESS_LINES), TB, 0, s>>>(ez_old, ez_new, w, g.nz, n, M, jmin, nw,
+                                                                            acc);
+    return hipGetLastError();
+}
+
 #define TETE_INST(R)                                                                                              \
     template hipError_t launch_import<R>(Fields<R>, const void* const[6], int, Mat<R>, Geo, hipStream_t);          \
     template hipError_t launch_export<R>(void* const[6], int, Fields<R>, Geo, hipStream_t);                        \
@@ -647,7 +704,11 @@ hipError_t launch_probes(const R* ez, const int64_t* idx, int nprobe, double* ou
     template hipError_t launch_energy<R>(Fields<R>, Mat<R>, Geo, double, double, double*, double*, hipStream_t);           \
     template hipError_t launch_charges<R>(Fields<R>, Fields<R>, Mat<R>, Geo, double, Src, double*, double*,        \
                                           hipStream_t);                                                            \
-    template hipError_t launch_probes<R>(const R*, const int64_t*, int, double*, hipStream_t);
+    template hipError_t launch_probes<R>(const R*, const int64_t*, int, double*, hipStream_t);                     \
+    template hipError_t launch_witness<R>(const R*, const R*, Witness, Geo, int64_t, int, int, int, double*,        \
+                                          hipStream_t);                                                            \
+    template hipError_t launch_witness2<R>(const R*, const R*, const R*, Witness, Geo, int64_t, int, int, int,      \
+                                           double*, hipStream_t);
 
 TETE_INST(double)
 TETE_INST(float)

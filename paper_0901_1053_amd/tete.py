@@ -98,6 +98,9 @@ def load(path: str = LIB_PATH):
         "tete_step": (st, [vp, C.c_int64]),
         "tete_steps_done": (st, [vp, C.POINTER(C.c_int64)]),
         "tete_wake": (st, [vp, vp, C.c_int32]),
+        "tete_set_witness": (st, [vp, C.c_int32, C.c_int32]),
+        "tete_clear_witness": (st, [vp]),
+        "tete_witness_wake": (st, [vp, vp, vp, vp, C.c_int32]),
         "tete_energy": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "tete_energy_series": (st, [vp, vp, C.c_int64, C.POINTER(C.c_int64)]),
         "tete_probes": (st, [vp, vp, C.c_int64, C.POINTER(C.c_int64)]),
@@ -283,6 +286,23 @@ class Grid:
 
     def wake_s(self) -> np.ndarray:
         return (self.bunch.jmin + np.arange(self.bunch.nw)) * self.dz
+
+    def set_witness(self, iw: int, jw: int):
+        """Sample the wake on the node lines (iw, jw), (iw -+ 1, jw), (iw, jw -+ 1)."""
+        _chk("tete_set_witness", load().tete_set_witness(self.h, int(iw), int(jw)))
+
+    def clear_witness(self):
+        _chk("tete_clear_witness", load().tete_clear_witness(self.h))
+
+    def witness_wake(self):
+        """(W (5, nw): W_par on the witness node and its neighbours -x, +x, -y,
+        +y; Wx, Wy (nw): the Panofsky-Wenzel transverse wake at the node), V/C."""
+        nw = self.bunch.nw
+        W = np.zeros((5, nw))
+        wx = np.zeros(nw)
+        wy = np.zeros(nw)
+        _chk("tete_witness_wake", load().tete_witness_wake(self.h, W.ctypes.data, wx.ctypes.data, wy.ctypes.data, nw))
+        return W, wx, wy
 
     def energy(self):
         w = C.c_double()

@@ -138,3 +138,11 @@ def test_implicit_flags_and_workspace():
     b = tete.workspace_bytes(tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp32"))
     bi = tete.workspace_bytes(tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp32", implicit=True))
     assert bi - b == pytest.approx(4 * 4 * np_, rel=1e-3)       # four plane-solve arrays
+
+
+def test_witness_entry_points_check_handles():
+    """No GPU needed: the witness calls reject a null grid."""
+    L = tete.load()
+    assert tete.STATUS[L.tete_set_witness(None, 1, 1)] == "TETE_ERR_ARG"
+    assert tete.STATUS[L.tete_clear_witness(None)] == "TETE_ERR_ARG"
+    assert tete.STATUS[L.tete_witness_wake(None, None, None, None, 1)] == "TETE_ERR_ARG"
