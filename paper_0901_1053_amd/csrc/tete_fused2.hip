@@ -363,12 +363,15 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
 
         if (srcA) ezA = oA.ezold1;
         if constexpr (WIT) {
-            // e_z^{n+1/2} of edge k at plane p-1, final on owned entries
-            const int di = p - 1 - wm.iw, dj = j - wm.jw;
+            // e_z^{n+1/2} of edge k at plane p-1, final on owned entries.  With
+            // 64 lanes a wave is one row, so the line test is scalar and adds
+            // no vector registers to the loop.
+            const int jr = LW == 64 ? __builtin_amdgcn_readfirstlane(j) : j;
+            const int di = p - 1 - wm.iw, dj = jr - wm.jw;
             const bool on = (dj == 0 && di >= -1 && di <= 1) || ((dj == 1 || dj == -1) && di == 0);
-            if (on && owned && xown(p - 1) && k < g.nz) {
+            if (on && xown(p - 1)) {
                 const int l = dj == 0 ? (di == 0 ? 0 : di < 0 ? 1 : 2) : (dj < 0 ? 3 : 4);
-                wm.mid[l * g.nz + k] = oA.ezh1;
+                if (owned && k < g.nz) wm.mid[l * g.nz + k] = oA.ezh1;
             }
         }
         // wave-uniform (one row per wave: srcB itself)
