@@ -24,7 +24,8 @@
 // Register budget.  Two stages of carried state fill the 128 VGPRs a
 // 1024-thread workgroup allows, so the coefficients are pre-multiplied by
 // their factor a or 2a, PEC selects are two bit operations, the delay lines
-// live in LDS and one plane is prefetched (a second one spills).
+// live in LDS and one plane is prefetched (a second one spills 23 registers).
+// The FP64 shape (512 threads, 256 VGPRs per wave) prefetches two.
 //
 // Wake.  The update of sample s at step n+1 from edge k and the update of the
 // same sample at step n from edge k-1 coincide.  The lane of node k applies
@@ -178,7 +179,9 @@ template <typename R, int TYH, int NB, int LW, bool WIT = false>
 __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, const int tz, const int cx,
                                             Lds2<R, TYH, NB, LW>& L, const WitMid<R>& wm = WitMid<R>{})
 {
-    constexpr int PD = 1;         // planes prefetched: a second one does not fit the register budget
+    // planes prefetched: FP64 (256 VGPRs per wave) fits two; a second one
+    // does not fit the 128 VGPRs of the FP32 shape
+    constexpr int PD = sizeof(R) == 8 ? 2 : 1;
     constexpr int TY = TYH - 6;   // rows owned
     constexpr int KT2 = LW - 4;   // entries owned per row
     // Lane shifts act on the whole wave; with two rows per wave (LW = 32) the
