@@ -210,8 +210,9 @@ tete_status tete_wake(tete_grid* g, double* W, int32_t nw);
  * shape then runs as 16 rows), and a small kernel over the lines adds both
  * steps' terms after it; a single step is followed by the same kernel for
  * one step.  The results do not depend on the kernel.  A grid with a
- * witness cannot join a batch (TETE_ERR_STATE).  Errors: TETE_ERR_ARG
- * (range). */
+ * witness cannot join a batch, and a batch with a member that has one does
+ * not step (TETE_ERR_STATE from tete_batch_set / tete_batch_step).  Errors:
+ * TETE_ERR_ARG (range). */
 tete_status tete_set_witness(tete_grid* g, int32_t iw, int32_t jw);
 
 /* Stop sampling the witness lines. */

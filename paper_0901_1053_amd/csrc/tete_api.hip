@@ -1043,6 +1043,8 @@ tete_status tete_batch_step(tete_batch* b, int64_t nsteps)
 {
     if (!b || nsteps < 0) return TETE_ERR_ARG;
     if (nsteps == 0) return TETE_OK;
+    for (int s = 0; s < TETE_MAX_BATCH; ++s)   // a witness set after joining: batched steps would skip it
+        if (b->slot[s] && b->slot[s]->witness) return TETE_ERR_STATE;
     DeviceGuard dg(b->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
     return b->fp32 ? batch_step<float>(b, nsteps) : batch_step<double>(b, nsteps);

@@ -43,13 +43,13 @@ def _oracle(shape, seed, src, wit):
     return W, wx / EPS0, wy / EPS0, r["src_acc"] / (Q * EPS0)
 
 
-def _gpu(shape, seed, src, wit, precision, kernel="auto", implicit=False, mesh=None):
+def _gpu(shape, seed, src, wit, precision, kernel="auto", implicit=False, mesh=None, xchunk=0):
     g, cells, sigma, M, jmin, nw, steps = _case(shape, seed)
     dx, dy = (g.dx, g.dy) if mesh is None else mesh
     G = tete.Grid(g.nx, g.ny, g.nz, dx, dy, g.dz, g.cdt, precision=precision, implicit=implicit)
     G.set_pec_cells(cells)
-    if kernel != "auto":
-        G.set_tuning(kernel=kernel)
+    if kernel != "auto" or xchunk:
+        G.set_tuning(kernel=kernel, xchunk=xchunk)
     G.set_bunch(Q, sigma, src[0], src[1], M, jmin, nw)
     if wit is not None:
         G.set_witness(*wit)
@@ -85,8 +85,11 @@ def test_witness_matches_oracle(ci, precision, kernel):
 def test_witness_on_the_bunch_line_is_the_wake():
     """A witness on the bunch line gives tete_wake bitwise; the witness lines do
     not depend on the kernel (two steps per launch keeping e_z^{n+1/2} of the
-    lines, single steps, and FP32's 32-row shape, which a witness runs as 16
-    rows), bitwise; and the bunch-line wake is that of a run without witness."""
+    lines, also with x-chunks of 3 planes so that the lines at iw-1, iw, iw+1
+    fall in different workgroups, single steps, and FP32's 32-row shape, which a
+    witness runs as 16 rows), bitwise; and the bunch-line wake is that of a run
+    without witness.  The j-rows of the lines (8..10) straddle the boundary of
+    the two-step kernel's first row tile (10 owned rows)."""
     shape, src, wit = CASES[1]
     for precision in ("fp64", "fp32"):
         G = _gpu(shape, 95, src, src, precision)
@@ -97,7 +100,7 @@ def test_witness_on_the_bunch_line_is_the_wake():
         G2 = _gpu(shape, 95, src, None, precision)
         assert np.array_equal(G2.wake(), w), precision
         ref = _gpu(shape, 95, src, wit, precision, "fused2").witness_wake()
-        kernels = ["fused", "auto"] + (["fused2_32"] if precision == "fp32" else [])
+        kernels = ["fused", "auto", "fused2_x3"] + (["fused2_32"] if precision == "fp32" else [])
         for kern in kernels:
             if kern == "fused2_32":
                 g, cells, sigma, M, jmin, nw, steps = _case(shape, 95)
@@ -108,6 +111,8 @@ def test_witness_on_the_bunch_line_is_the_wake():
                 G3.set_witness(*wit)
                 G3.step(steps)
                 got = G3.witness_wake()
+            elif kern == "fused2_x3":
+                got = _gpu(shape, 95, src, wit, precision, "fused2", xchunk=3).witness_wake()
             else:
                 got = _gpu(shape, 95, src, wit, precision, kern).witness_wake()
             for a, b in zip(got, ref):
@@ -179,6 +184,11 @@ def test_witness_state_rules():
     assert np.array_equal(W3, W1)                        # same start, same steps
     G.clear_witness()
     B.set(0, G)
+    G.set_witness(*wit)                                  # armed after joining: the batch refuses to step
+    with pytest.raises(tete.TeteError) as e:
+        B.step(2)
+    assert e.value.status == "TETE_ERR_STATE"
+    G.clear_witness()
     B.set(0, None)
 
 
