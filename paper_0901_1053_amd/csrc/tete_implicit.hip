@@ -164,15 +164,33 @@ __device__ __forceinline__ R apply_h(const R* x, const uint8_t* code, const IGeo
     return x0 + c.a * c.a * mz * r;
 }
 
-// Chebyshev start: r = b - A x, d = r / theta (zero off the unknowns)
+// An h_z row whose four surrounding e edges are all PEC (inside the metal) is
+// the identity and decoupled from every other unknown: its neighbours reach it
+// only through one of those edges, whose kappa is zero.  Its solution is b.
+template <typename R>
+__device__ __forceinline__ bool h_coupled(const uint8_t* code, const IGeo& g, const ICoef<R>& c, int i, int j, int k)
+{
+    return kap_x(code, g, c, i, j + 1, k) != (R)0 || kap_x(code, g, c, i, j, k) != (R)0 ||
+           kap_y(code, g, c, i + 1, j, k) != (R)0 || kap_y(code, g, c, i, j, k) != (R)0;
+}
+
+// Chebyshev start: r = b - A x, d = r / theta (zero off the unknowns); the
+// identity rows of the h_z system take x = b and are left out of the
+// iterations, with both direction buffers zero there (D1: the other one of
+// the ping-pong pair, which the iterations then never write on those rows)
 template <typename R, bool H>
-__global__ void k_cheb_init(const R* X, const R* B, R* Rr, R* D, const uint8_t* code, IGeo g, ICoef<R> c, R inv_theta)
+__global__ void k_cheb_init(R* X, const R* B, R* Rr, R* D, R* D1, const uint8_t* code, IGeo g, ICoef<R> c,
+                            R inv_theta)
 {
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < g.np; idx += gridDim.x * blockDim.x) {
         int i, j, k;
         dec(g, idx, i, j, k);
         const R s = H ? mu_z(g, c, i, j, k) : kap_z(code, g, c, i, j, k);
-        if (s == (R)0) {
+        if (s == (R)0 || (H && !h_coupled(code, g, c, i, j, k))) {
+            if (s != (R)0) {
+                X[idx] = B[idx];
+                D1[idx] = (R)0;
+            }
             Rr[idx] = (R)0;
             D[idx] = (R)0;
             continue;
@@ -194,6 +212,7 @@ __global__ void k_cheb_iter(R* X, R* Rr, const R* D, R* Dn, const uint8_t* code,
         dec(g, idx, i, j, k);
         const R s = H ? mu_z(g, c, i, j, k) : kap_z(code, g, c, i, j, k);
         if (s == (R)0) continue;
+        if (H && !h_coupled(code, g, c, i, j, k)) continue;   // identity row: x = b, d = 0 in both buffers
         const R d = D[idx];
         X[idx] += d;
         if (last) continue;
@@ -314,7 +333,7 @@ hipError_t cheb_solve(R* X, const R* B, const ImpWork<R>& wk, const uint8_t* cod
                       const Cheb& p, int iters, hipStream_t s)
 {
     const int nb = iblocks(g.np);
-    k_cheb_init<R, H><<<nb, TBI, 0, s>>>(X, B, wk.r, wk.d[0], code, g, c, (R)p.inv_theta);
+    k_cheb_init<R, H><<<nb, TBI, 0, s>>>(X, B, wk.r, wk.d[0], wk.d[1], code, g, c, (R)p.inv_theta);
     for (int t = 0; t < iters; ++t) {
         const bool last = t == iters - 1;
         const R c1 = last ? (R)0 : (R)p.c1[t], c2 = last ? (R)0 : (R)p.c2[t];
