@@ -174,10 +174,13 @@ __device__ __forceinline__ bool h_coupled(const uint8_t* code, const IGeo& g, co
            kap_y(code, g, c, i + 1, j, k) != (R)0 || kap_y(code, g, c, i, j, k) != (R)0;
 }
 
-// Chebyshev start: r = b - A x, d = r / theta (zero off the unknowns); the
-// identity rows of the h_z system take x = b and are left out of the
-// iterations, with both direction buffers zero there (D1: the other one of
-// the ping-pong pair, which the iterations then never write on those rows)
+// Chebyshev start: r = b - A x, d = r / theta; the identity rows of the h_z
+// system take x = b.  Rows left out of the iterations (PEC e_z edges, h_z
+// outside its range, identity rows) get a zero direction in both buffers of
+// the ping-pong pair (D and D1): the iterations never write them, the
+// neighbours' stencils read them (PEC e_z through a nonzero mu), and the two
+// buffers are shared by the e_z and h_z solves, so they would otherwise hold
+// the other system's last directions.
 template <typename R, bool H>
 __global__ void k_cheb_init(R* X, const R* B, R* Rr, R* D, R* D1, const uint8_t* code, IGeo g, ICoef<R> c,
                             R inv_theta)
@@ -187,12 +190,10 @@ __global__ void k_cheb_init(R* X, const R* B, R* Rr, R* D, R* D1, const uint8_t*
         dec(g, idx, i, j, k);
         const R s = H ? mu_z(g, c, i, j, k) : kap_z(code, g, c, i, j, k);
         if (s == (R)0 || (H && !h_coupled(code, g, c, i, j, k))) {
-            if (s != (R)0) {
-                X[idx] = B[idx];
-                D1[idx] = (R)0;
-            }
+            if (s != (R)0) X[idx] = B[idx];
             Rr[idx] = (R)0;
             D[idx] = (R)0;
+            D1[idx] = (R)0;
             continue;
         }
         const R ax = H ? apply_h(X, code, g, c, i, j, k, idx, s) : apply_e(X, code, g, c, i, j, k, idx, s);
