@@ -1,0 +1,74 @@
+"""A step depends only on the state it is given: a grid that has run other
+steps (another geometry, other fields, a bunch, a witness, probes) and is then
+given geometry B, fields F and a bunch matches, bitwise, a fresh grid given the
+same.  Every entry of the new field set must be written by each step and no
+work array may carry anything from an earlier run into a later one."""
+import numpy as np
+import pytest
+
+from paper_0901_1053_amd import inputs, tete
+
+pytestmark = pytest.mark.gpu
+
+NX, NY, NZ = 14, 12, 71
+DZ = 1.0e-3
+
+
+def _explicit(precision, kernel, history):
+    G = tete.Grid(NX, NY, NZ, 2 * DZ, 2 * DZ, DZ, DZ, precision=precision)
+    if kernel != "auto":
+        G.set_tuning(kernel)
+    if history:
+        G.set_pec_cells(inputs.random_cells(NX, NY, NZ, 71, frac=0.2))
+        G.set_fields(inputs.random_fields(G.shape, 71))
+        G.set_bunch(1e-9, 2e-3, 4, 8, 12, -14, 50)
+        G.set_witness(9, 3)
+        G.set_probes([5, 500, 5000])
+        G.step(9)
+        G.clear_witness()
+        G.set_probes([])
+    G.set_pec_cells(inputs.random_cells(NX, NY, NZ, 72, frac=0.08))
+    G.set_fields(inputs.random_fields(G.shape, 72))
+    G.set_bunch(1e-9, 2e-3, 7, 6, 12, -14, 50)
+    G.step(11)
+    return G.get_fields(), G.wake()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("kernel", ["auto", "fused", "split"])
+def test_explicit_step_independent_of_history(precision, kernel):
+    print("history", precision, kernel, flush=True)
+    f1, w1 = _explicit(precision, kernel, True)
+    f2, w2 = _explicit(precision, kernel, False)
+    for k in tete.KEYS:
+        assert np.array_equal(f1[k], f2[k]), k
+    assert np.array_equal(w1, w2)
+
+
+def _rz(precision, kernel, history):
+    case = inputs.small_rz_case(1)
+    G = tete.RZGrid(case.nr, case.nz, case.dr, case.dz, case.dz, mode=1, precision=precision)
+    if kernel != "auto":
+        G.set_tuning(kernel=kernel)
+    if history:
+        G.set_pec_cells(inputs.rz_random_cells(case.nr, case.nz, 73, frac=0.2))
+        G.set_fields(inputs.rz_random_fields(G.shape, 73))
+        G.set_bunch(1e-9, 3e-3, 3, 9, 5, -12, 40)
+        G.step(9)
+    G.set_pec_cells(inputs.rz_random_cells(case.nr, case.nz, 74, frac=0.05))
+    G.set_fields(inputs.rz_random_fields(G.shape, 74))
+    G.set_bunch(1e-9, 3e-3, 4, 9, 6, -12, 40)
+    G.step(11)
+    wpar, wperp = G.wake()
+    return G.get_fields(), wpar, wperp
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("kernel", ["auto", "fused"])
+def test_rz_step_independent_of_history(precision, kernel):
+    print("rz history", precision, kernel, flush=True)
+    f1, a1, b1 = _rz(precision, kernel, True)
+    f2, a2, b2 = _rz(precision, kernel, False)
+    for k in tete.RZ_KEYS:
+        assert np.array_equal(f1[k], f2[k]), k
+    assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
