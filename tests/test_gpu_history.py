@@ -72,3 +72,41 @@ def test_rz_step_independent_of_history(precision, kernel):
     for k in tete.RZ_KEYS:
         assert np.array_equal(f1[k], f2[k]), k
     assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_grids_do_not_share_state(precision):
+    """Two grids of different sizes stepped alternately on one device (each
+    with its own bunch and witness, one of them implicit) match, bitwise, the
+    same grids stepped alone: no state is shared between grids."""
+    def make(which):
+        if which == 0:
+            G = tete.Grid(NX, NY, NZ, 2 * DZ, 2 * DZ, DZ, DZ, precision=precision)
+            G.set_pec_cells(inputs.random_cells(NX, NY, NZ, 75, frac=0.08))
+            G.set_fields(inputs.random_fields(G.shape, 75))
+            G.set_bunch(1e-9, 2e-3, 7, 6, 12, -14, 50)
+            G.set_witness(5, 5)
+        else:
+            G = tete.Grid(9, 17, 45, 0.5e-3, 0.5e-3, DZ, DZ, precision=precision, implicit=True)
+            G.set_pec_cells(inputs.random_cells(9, 17, 45, 76, frac=0.08))
+            G.set_fields(inputs.random_fields(G.shape, 76))
+            G.set_bunch(1e-9, 2e-3, 4, 8, 12, -14, 50)
+            G.set_witness(4, 9)
+        return G
+
+    def result(G):
+        return G.get_fields(), G.wake(), G.witness_wake()[0]
+
+    alone = []
+    for w in (0, 1):
+        G = make(w)
+        G.step(12)
+        alone.append(result(G))
+    A, B = make(0), make(1)
+    for _ in range(4):
+        A.step(3)
+        B.step(3)
+    for got, ref in zip((result(A), result(B)), alone):
+        for k in tete.KEYS:
+            assert np.array_equal(got[0][k], ref[0][k]), k
+        assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
