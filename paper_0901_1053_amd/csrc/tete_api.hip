@@ -21,7 +21,8 @@ constexpr size_t kAlign = 256;
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t lam, wacc, wit, wmid, partial, scal, pidx, eser, pser, code, field[12], mat[6], imp[4], total;
+    size_t lam, wacc, wit, wmid, partial, scal, pidx, eser, pser, code, field[12], mat[6], imp[4], imp_le, imp_lh,
+        imp_cnt, total;
 };
 
 int64_t series_cap(const tete_grid_desc* d) { return d->max_series > 0 ? d->max_series : 4096; }
@@ -49,6 +50,12 @@ bool make_layout(const tete_grid_desc* d, Layout* L)
     for (int c = 0; c < 4; ++c) {          // plane-solve work arrays of the implicit scheme
         if (d->flags & TETE_F_IMPLICIT) { L->imp[c] = o; o = up(o + rb * (size_t)np); }
         else L->imp[c] = 0;
+    }
+    L->imp_le = L->imp_lh = L->imp_cnt = 0;
+    if (d->flags & TETE_F_IMPLICIT) {      // row lists of the plane systems and their chunk counts
+        L->imp_le = o;  o = up(o + sizeof(int) * (size_t)np);
+        L->imp_lh = o;  o = up(o + sizeof(int) * (size_t)np);
+        L->imp_cnt = o; o = up(o + sizeof(int) * 2 * (size_t)implicit_list_chunks(np));
     }
     L->total = o;
     return true;
@@ -82,6 +89,8 @@ struct tete_grid {
     int fp32;
     int yee;           // Yee's scheme (7) instead of (23)
     int implicit;      // the implicit scheme (16) instead of (23)
+    int imp_lists;     // row lists built for the current geometry
+    int imp_ne, imp_nh;
     void* f[2][6];
     int cur;           // f[cur] holds y^n
     uint8_t* code;
@@ -187,6 +196,10 @@ ImpWork<R> imp_work(tete_grid* g)
     w.r = (R*)(g->ws + g->L.imp[1]);
     w.d[0] = (R*)(g->ws + g->L.imp[2]);
     w.d[1] = (R*)(g->ws + g->L.imp[3]);
+    w.le = (const int*)(g->ws + g->L.imp_le);
+    w.lh = (const int*)(g->ws + g->L.imp_lh);
+    w.ne = g->imp_ne;
+    w.nh = g->imp_nh;
     return w;
 }
 
@@ -251,6 +264,11 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             g->n += 2;
             ++s;
             continue;
+        }
+        if (g->implicit && !g->imp_lists) {   // once per geometry
+            HIPCHK(implicit_build_lists<R>(M, g->geo, (int*)(g->ws + g->L.imp_cnt), (int*)(g->ws + g->L.imp_le),
+                                           (int*)(g->ws + g->L.imp_lh), &g->imp_ne, &g->imp_nh, g->stream));
+            g->imp_lists = 1;
         }
         if (g->implicit)
             HIPCHK(launch_step_implicit<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, g->d.dx,
@@ -500,6 +518,7 @@ tete_status tete_set_pec_cells(tete_grid* g, const uint8_t* cells)
     if (!dg.ok) return TETE_ERR_DEVICE;
     HIPCHK(launch_build_codes(g->code, cells, g->geo, g->stream));
     g->mat_set = 0;
+    g->imp_lists = 0;
     if (g->fp32) HIPCHK(launch_zero_pec<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->stream));
     else HIPCHK(launch_zero_pec<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->stream));
     return TETE_OK;

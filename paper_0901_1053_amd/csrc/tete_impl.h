@@ -191,8 +191,17 @@ template <typename R>
 struct ImpWork {
     R* b;        // right-hand side
     R* r;        // residual
-    R* d[2];     // Chebyshev directions (ping-pong)
+    R* d[2];     // Chebyshev directions (ping-pong), zero between solves
+    const int* le;   // ascending array indices of the free e_z edges (ne of them)
+    const int* lh;   // ascending array indices of the coupled h_z rows (nh)
+    int ne, nh;
 };
+// Row lists of the implicit scheme's plane systems for the current geometry:
+// cnt holds 2 ints per chunk (implicit_list_chunks), le and lh np ints each.
+// Synchronises the stream.
+int implicit_list_chunks(int64_t np);
+template <typename R>
+hipError_t implicit_build_lists(Mat<R> M, Geo g, int* cnt, int* le, int* lh, int* ne, int* nh, hipStream_t s);
 // One step of the implicit scheme (16) (tete_implicit.hip); ev[0..2] around
 // the two half steps if not NULL
 template <typename R>

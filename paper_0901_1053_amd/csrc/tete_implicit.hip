@@ -24,6 +24,7 @@ namespace tete {
 namespace {
 
 constexpr int TBI = 256;
+constexpr int kListChunk = 8192;   // entries counted and listed by one block
 
 struct IGeo {
     int nx, ny, nz, sz, sp, np;
@@ -174,28 +175,100 @@ __device__ __forceinline__ bool h_coupled(const uint8_t* code, const IGeo& g, co
            kap_y(code, g, c, i + 1, j, k) != (R)0 || kap_y(code, g, c, i, j, k) != (R)0;
 }
 
-// Chebyshev start: r = b - A x, d = r / theta; the identity rows of the h_z
-// system take x = b.  Rows left out of the iterations (PEC e_z edges, h_z
-// outside its range, identity rows) get a zero direction in both buffers of
-// the ping-pong pair (D and D1): the iterations never write them, the
-// neighbours' stencils read them (PEC e_z through a nonzero mu), and the two
-// buffers are shared by the e_z and h_z solves, so they would otherwise hold
-// the other system's last directions.
-template <typename R, bool H>
-__global__ void k_cheb_init(R* X, const R* B, R* Rr, R* D, R* D1, const uint8_t* code, IGeo g, ICoef<R> c,
-                            R inv_theta)
+// Row lists (built once per geometry, ascending): the free e_z edges and the
+// coupled h_z rows.  Chunk b of `chunk` entries is counted by block b, the
+// host turns the counts into offsets, and block b writes its chunk's rows
+// in order (wave ballots and a scan over the block's waves).
+template <typename R>
+__device__ __forceinline__ void row_flags(const uint8_t* code, const IGeo& g, const ICoef<R>& c, int idx, bool& fe,
+                                          bool& fh)
 {
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < g.np; idx += gridDim.x * blockDim.x) {
+    int i, j, k;
+    dec(g, idx, i, j, k);
+    fe = kap_z(code, g, c, i, j, k) != (R)0;
+    fh = mu_z(g, c, i, j, k) != (R)0 && h_coupled(code, g, c, i, j, k);
+}
+
+template <typename R>
+__global__ __launch_bounds__(TBI) void k_list_count(const uint8_t* code, IGeo g, ICoef<R> c, int chunk, int* cnt)
+{
+    __shared__ int se[TBI], sh[TBI];
+    const int lo = blockIdx.x * chunk, hi = min(lo + chunk, g.np);
+    int ne = 0, nh = 0;
+    for (int idx = lo + (int)threadIdx.x; idx < hi; idx += TBI) {
+        bool fe, fh;
+        row_flags(code, g, c, idx, fe, fh);
+        ne += fe;
+        nh += fh;
+    }
+    se[threadIdx.x] = ne;
+    sh[threadIdx.x] = nh;
+    __syncthreads();
+    for (int w = TBI / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            se[threadIdx.x] += se[threadIdx.x + w];
+            sh[threadIdx.x] += sh[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cnt[2 * blockIdx.x] = se[0];
+        cnt[2 * blockIdx.x + 1] = sh[0];
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(TBI) void k_list_write(const uint8_t* code, IGeo g, ICoef<R> c, int chunk,
+                                                    const int* off, int* le, int* lh)
+{
+    constexpr int NW = TBI / 64;
+    __shared__ int we[NW], wh[NW];
+    const int lo = blockIdx.x * chunk, hi = min(lo + chunk, g.np);
+    const int wave = threadIdx.x / 64;
+    const unsigned long long below = __lanemask_lt();
+    int oe = off[2 * blockIdx.x], oh = off[2 * blockIdx.x + 1];
+    for (int base = lo; base < hi; base += TBI) {       // same trip count for every thread
+        const int idx = base + (int)threadIdx.x;
+        bool fe = false, fh = false;
+        if (idx < hi) row_flags(code, g, c, idx, fe, fh);
+        const unsigned long long me = __ballot(fe), mh = __ballot(fh);
+        if ((threadIdx.x & 63) == 0) {
+            we[wave] = __popcll(me);
+            wh[wave] = __popcll(mh);
+        }
+        __syncthreads();
+        int pe = oe, ph = oh, te = 0, th = 0;
+        for (int w = 0; w < NW; ++w) {
+            if (w < wave) {
+                pe += we[w];
+                ph += wh[w];
+            }
+            te += we[w];
+            th += wh[w];
+        }
+        if (fe) le[pe + __popcll(me & below)] = idx;
+        if (fh) lh[ph + __popcll(mh & below)] = idx;
+        oe += te;
+        oh += th;
+        __syncthreads();                                 // the counts are rewritten next round
+    }
+}
+
+// Chebyshev start on the rows of the list: r = b - A x, d = r / theta.  Rows
+// outside the list (PEC e_z edges, h_z outside its range or inside the
+// metal) are not unknowns: their x is fixed (0, or h_z^n, which equals b on an
+// identity row) and their directions are zero in both buffers of the
+// ping-pong pair, which the e_z and h_z solves share: every solve zeroes its
+// own rows in both buffers in its last iteration.
+template <typename R, bool H>
+__global__ void k_cheb_init(const R* X, const R* B, R* Rr, R* D, const int* list, int n, const uint8_t* code, IGeo g,
+                            ICoef<R> c, R inv_theta)
+{
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        const int idx = list[t];
         int i, j, k;
         dec(g, idx, i, j, k);
         const R s = H ? mu_z(g, c, i, j, k) : kap_z(code, g, c, i, j, k);
-        if (s == (R)0 || (H && !h_coupled(code, g, c, i, j, k))) {
-            if (s != (R)0) X[idx] = B[idx];
-            Rr[idx] = (R)0;
-            D[idx] = (R)0;
-            D1[idx] = (R)0;
-            continue;
-        }
         const R ax = H ? apply_h(X, code, g, c, i, j, k, idx, s) : apply_e(X, code, g, c, i, j, k, idx, s);
         const R r = B[idx] - ax;
         Rr[idx] = r;
@@ -203,20 +276,24 @@ __global__ void k_cheb_init(R* X, const R* B, R* Rr, R* D, R* D1, const uint8_t*
     }
 }
 
-// One Chebyshev step: x += d; unless last: r -= A d, d' = c1 d + c2 r
+// One Chebyshev step: x += d; unless last: r -= A d, d' = c1 d + c2 r; in the
+// last step both direction buffers are cleared on the list's rows
 template <typename R, bool H>
-__global__ void k_cheb_iter(R* X, R* Rr, const R* D, R* Dn, const uint8_t* code, IGeo g, ICoef<R> c, R c1, R c2,
-                            int last)
+__global__ void k_cheb_iter(R* X, R* Rr, R* D, R* Dn, const int* list, int n, const uint8_t* code, IGeo g, ICoef<R> c,
+                            R c1, R c2, int last)
 {
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < g.np; idx += gridDim.x * blockDim.x) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        const int idx = list[t];
         int i, j, k;
         dec(g, idx, i, j, k);
         const R s = H ? mu_z(g, c, i, j, k) : kap_z(code, g, c, i, j, k);
-        if (s == (R)0) continue;
-        if (H && !h_coupled(code, g, c, i, j, k)) continue;   // identity row: x = b, d = 0 in both buffers
         const R d = D[idx];
         X[idx] += d;
-        if (last) continue;
+        if (last) {   // no thread reads the directions any more
+            D[idx] = (R)0;
+            Dn[idx] = (R)0;
+            continue;
+        }
         const R ad = H ? apply_h(D, code, g, c, i, j, k, idx, s) : apply_e(D, code, g, c, i, j, k, idx, s);
         const R r = Rr[idx] - ad;
         Rr[idx] = r;
@@ -333,12 +410,16 @@ template <typename R, bool H>
 hipError_t cheb_solve(R* X, const R* B, const ImpWork<R>& wk, const uint8_t* code, const IGeo& g, const ICoef<R>& c,
                       const Cheb& p, int iters, hipStream_t s)
 {
-    const int nb = iblocks(g.np);
-    k_cheb_init<R, H><<<nb, TBI, 0, s>>>(X, B, wk.r, wk.d[0], wk.d[1], code, g, c, (R)p.inv_theta);
+    const int* list = H ? wk.lh : wk.le;
+    const int n = H ? wk.nh : wk.ne;
+    if (n == 0) return hipSuccess;   // no unknowns: x stays as set
+    const int nb = iblocks(n);
+    k_cheb_init<R, H><<<nb, TBI, 0, s>>>(X, B, wk.r, wk.d[0], list, n, code, g, c, (R)p.inv_theta);
     for (int t = 0; t < iters; ++t) {
         const bool last = t == iters - 1;
         const R c1 = last ? (R)0 : (R)p.c1[t], c2 = last ? (R)0 : (R)p.c2[t];
-        k_cheb_iter<R, H><<<nb, TBI, 0, s>>>(X, wk.r, wk.d[t & 1], wk.d[(t + 1) & 1], code, g, c, c1, c2, last);
+        k_cheb_iter<R, H><<<nb, TBI, 0, s>>>(X, wk.r, wk.d[t & 1], wk.d[(t + 1) & 1], list, n, code, g, c, c1, c2,
+                                             last);
     }
     return hipGetLastError();
 }
@@ -357,6 +438,38 @@ int implicit_iters(const Geo& g, double dx, double dy, double alpha, int fp32, d
     int n = rho > 0.0 ? (int)ceil(log(tol / 2.0) / log(rho)) : 1;
     if (lmax_out) *lmax_out = lmax;
     return std::max(1, std::min(n, 10000));
+}
+
+int implicit_list_chunks(int64_t np) { return (int)((np + kListChunk - 1) / kListChunk); }
+
+template <typename R>
+hipError_t implicit_build_lists(Mat<R> M, Geo geo, int* cnt, int* le, int* lh, int* ne, int* nh, hipStream_t s)
+{
+    IGeo g{geo.nx, geo.ny, geo.nz, geo.sz, geo.sp, geo.np};
+    ICoef<R> c{M.k[0], M.k[1], M.k[2], M.m[0], M.m[1], M.m[2], (R)0, (R)0};
+    const int nch = implicit_list_chunks(geo.np);
+    hipError_t e;
+    k_list_count<R><<<nch, TBI, 0, s>>>(M.code, g, c, kListChunk, cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    std::vector<int> h(2 * (size_t)nch);
+    if ((e = hipMemcpyAsync(h.data(), cnt, sizeof(int) * h.size(), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    int64_t te = 0, th = 0;                      // exclusive scan of the chunk counts
+    for (int b = 0; b < nch; ++b) {
+        const int ce = h[2 * b], chh = h[2 * b + 1];
+        h[2 * b] = (int)te;
+        h[2 * b + 1] = (int)th;
+        te += ce;
+        th += chh;
+    }
+    if (te > geo.np || th > geo.np) return hipErrorInvalidValue;
+    if ((e = hipMemcpyAsync(cnt, h.data(), sizeof(int) * h.size(), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    k_list_write<R><<<nch, TBI, 0, s>>>(M.code, g, c, kListChunk, cnt, le, lh);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;   // h is released on return
+    *ne = (int)te;
+    *nh = (int)th;
+    return hipSuccess;
 }
 
 template <typename R>
@@ -384,6 +497,8 @@ hipError_t launch_step_implicit(Fields<R> o, Fields<R> w, Mat<R> M, Geo geo, dou
     return hipGetLastError();
 }
 
+template hipError_t implicit_build_lists<float>(Mat<float>, Geo, int*, int*, int*, int*, int*, hipStream_t);
+template hipError_t implicit_build_lists<double>(Mat<double>, Geo, int*, int*, int*, int*, int*, hipStream_t);
 template hipError_t launch_step_implicit<float>(Fields<float>, Fields<float>, Mat<float>, Geo, double, double, float,
                                                 Src, ImpWork<float>, hipStream_t, hipEvent_t*);
 template hipError_t launch_step_implicit<double>(Fields<double>, Fields<double>, Mat<double>, Geo, double, double,

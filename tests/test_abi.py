@@ -137,7 +137,8 @@ def test_implicit_flags_and_workspace():
     np_ = 129 * 129 * 1025
     b = tete.workspace_bytes(tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp32"))
     bi = tete.workspace_bytes(tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp32", implicit=True))
-    assert bi - b == pytest.approx(4 * 4 * np_, rel=1e-3)       # four plane-solve arrays
+    # four plane-solve arrays and two row lists (int32) of np entries each
+    assert bi - b == pytest.approx(4 * 4 * np_ + 2 * 4 * np_, rel=1e-3)
 
 
 def test_witness_entry_points_check_handles():
