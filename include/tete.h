@@ -80,7 +80,11 @@ enum {
                                  * fixed number of Chebyshev iterations on the spectral
                                  * bounds [1, 1 + alpha^2 (4/dx^2 + 4/dy^2)] (to 1e-17 in
                                  * FP64, 1e-8 in FP32 relative to the first iterate's
-                                 * error).  Stable for cdt <= dz with any transverse
+                                 * error), over lists of the systems' rows that the
+                                 * first tete_step after tete_set_pec_cells builds
+                                 * (that call synchronises the stream; the workspace
+                                 * holds two int32 lists of np entries).  Stable for
+                                 * cdt <= dz with any transverse
                                  * mesh; vacuum with staircase PEC only (not with
                                  * TETE_F_MATERIALS or TETE_F_YEE); bunch, wake, probes,
                                  * energy (Q = B - alpha A of (16): no alpha^2 terms)
