@@ -246,3 +246,42 @@ def test_witness_full_size_properties():
         assert np.max(np.abs(Wp[a] - Wm[b])) <= 1e-5 * big, (a, b)
     assert np.max(np.abs(xp + xm)) <= perp_tol
     assert np.max(np.abs(yp)) <= perp_tol and np.max(np.abs(ym)) <= perp_tol
+
+
+def test_witness_at_corners_matches_oracle():
+    """Witness nodes at the extreme allowed positions (1, 1) and (nx-1, ny-1),
+    whose neighbour lines lie on the box walls (e_z there is PEC, W = 0), FP64
+    against the oracle."""
+    shape, src, _ = CASES[0]
+    g = _case(shape, 98)[0]
+    for wit in ((1, 1), (g.nx - 1, g.ny - 1)):
+        W, wx, wy, _ = _oracle(shape, 98, src, wit)
+        gW, gx, gy = _gpu(shape, 98, src, wit, "fp64").witness_wake()
+        for l in range(5):
+            scale = max(np.max(np.abs(W[l])), 1e-300)
+            assert np.max(np.abs(gW[l] - W[l])) <= 1e-12 * max(scale, np.max(np.abs(W[0]))), (wit, l)
+        if wit == (1, 1):                                 # the -x line lies on the wall x = 0
+            assert np.all(W[1] == 0) and np.all(gW[1] == 0)
+        assert np.max(np.abs(gx - wx)) <= 1e-11 * np.max(np.abs(wx))
+        assert np.max(np.abs(gy - wy)) <= 1e-11 * np.max(np.abs(wy))
+
+
+def test_witness_largest_window():
+    """The largest wake window (TETE_MAX_WAKE samples) on all five lines: the
+    centre line on the bunch line equals tete_wake bitwise over the whole
+    window, through a two-step run with an odd step count."""
+    shape, src, _ = CASES[0]
+    g, cells, sigma, M, _, _, _ = _case(shape, 99)
+    nw = 65536                                            # TETE_MAX_WAKE
+    G = tete.Grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.cdt, precision="fp32")
+    G.set_pec_cells(cells)
+    G.set_bunch(Q, sigma, src[0], src[1], M, -M - 4, nw)
+    G.set_witness(*src)
+    G.step(151)
+    W, wx, wy = G.witness_wake()
+    w = G.wake()
+    assert W.shape == (5, nw) and np.any(w != 0)
+    assert np.array_equal(W[0], w)
+    assert np.all(np.isfinite(wx)) and np.all(np.isfinite(wy))
+    with pytest.raises(tete.TeteError):
+        G.set_bunch(Q, sigma, src[0], src[1], M, -M - 4, nw + 1)
