@@ -161,8 +161,9 @@ def _ms_per_step(G, steps):
 def yee_section(G, case, precision, steps=20):
     """The paper's cost comparison, measured: kernel time per step of the
     single-step and two-step TE/TM kernels (dtau = dz) and of Yee's scheme (7)
-    at its stability limit (8) on the same grid and geometry, and the time to
-    reach the same physical time tau (steps scale as 1 / dtau)."""
+    at its stability limit (8), also with one and two steps per launch, on the
+    same grid and geometry, and the time to reach the same physical time tau
+    (steps scale as 1 / dtau)."""
     from paper_0901_1053_amd import tete
     tuning = G.get_tuning()
     G.set_tuning("fused2")
@@ -174,15 +175,20 @@ def yee_section(G, case, precision, steps=20):
     dt_yee = (case.dx ** -2 + case.dy ** -2 + case.dz ** -2) ** -0.5
     Y = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, dt_yee, precision=precision, yee=True)
     Y.set_pec_cells(case.cell_mask())
+    Y.set_tuning("fused")
     ty = _ms_per_step(Y, steps)
+    Y.set_tuning("auto")
+    ty2 = _ms_per_step(Y, steps)
     Y.close()
     del Y
     r = dt_yee / case.cdt
     return {"workload": case.name, "precision": precision,
             "dtau_over_dz": {"te_tm": round(case.cdt / case.dz, 4), "yee_limit_8": round(dt_yee / case.dz, 4)},
-            "ms_per_step": {"te_tm_two_step": round(t2, 4), "te_tm_single_step": round(t1, 4), "yee": round(ty, 4)},
+            "ms_per_step": {"te_tm_two_step": round(t2, 4), "te_tm_single_step": round(t1, 4), "yee": round(ty, 4),
+                            "yee_two_step": round(ty2, 4)},
             "time_to_same_tau_vs_yee": {"te_tm_two_step": round(t2 * r / ty, 3),
-                                        "te_tm_single_step": round(t1 * r / ty, 3)},
+                                        "te_tm_single_step": round(t1 * r / ty, 3),
+                                        "te_tm_two_step_vs_yee_two_step": round(t2 * r / ty2, 3)},
             "paper": {"cost_per_step_vs_yee": round(10 / 6, 3),
                       "run_time_vs_yee_at_dx_sqrt2_dz": round((10 / 6) / 2 ** 0.5, 3)}}
 

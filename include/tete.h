@@ -282,7 +282,10 @@ tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h);
  * turns a forced FUSED or FUSED2 back into AUTO.  tete_get_tuning reports the kernel
  * that tete_step will use (FUSED2, FUSED or SPLIT). */
 enum { TETE_KERNEL_AUTO = 0, TETE_KERNEL_FUSED = 1, TETE_KERNEL_SPLIT = 2, TETE_KERNEL_FUSED2 = 3,
-       TETE_KERNEL_YEE = 4 /* reported for TETE_F_YEE grids, whose kernel ignores kernel, rows, depth */,
+       TETE_KERNEL_YEE = 4 /* reported for TETE_F_YEE grids: two steps per launch
+                            * (bitwise two single steps) unless kernel is
+                            * TETE_KERNEL_FUSED (single steps); rows and depth
+                            * are ignored */,
        TETE_KERNEL_IMPLICIT = 5 /* reported for TETE_F_IMPLICIT grids */ };
 typedef struct {
     int32_t kernel;

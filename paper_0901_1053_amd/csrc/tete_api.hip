@@ -233,6 +233,8 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
 {
     Mat<R> M = mats<R>(g);
     const bool two = use_fused2(g);
+    // Yee grids: two steps per launch unless the tuning asks for single steps
+    const bool two_yee = g->yee && g->tune.kernel != TETE_KERNEL_FUSED && yee2_fits(g->geo, g->fp32 ? 4 : 8);
     for (int64_t s = 0; s < nsteps; ++s) {
         if (g->diag_every > 0 && g->n % g->diag_every == 0) {
             HIPCHK(launch_energy<R>(fields<R>(g, g->cur), M, g->geo, g->alpha, rweight(g), g->partial, g->eser + g->ecount,
@@ -241,7 +243,7 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
         }
         // two steps at once unless the state after the first is observed
         const bool wit = g->witness && g->has_bunch;
-        const bool pair = two && s + 1 < nsteps && g->nprobe == 0 &&
+        const bool pair = (two || two_yee) && s + 1 < nsteps && g->nprobe == 0 &&
                           !(g->diag_every > 0 && (g->n + 1) % g->diag_every == 0);
         hipEvent_t* ev = nullptr;
         if (g->timing) {
@@ -249,6 +251,14 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             ev = g->ev + 3 * g->ev_steps;
             g->ev_nst[g->ev_steps] = pair ? 2 : 1;
             g->ev_steps++;
+        }
+        if (pair && g->yee) {
+            HIPCHK(launch_step_yee2<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
+                                       g->tune.xchunk, g->tune.order, g->stream, ev));
+            g->cur = 1 - g->cur;
+            g->n += 2;
+            ++s;
+            continue;
         }
         if (pair) {
             WitMid<R> wm;

@@ -152,6 +152,12 @@ bool yee_fits(Geo g, int real_bytes);
 template <typename R>
 hipError_t launch_step_yee(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, int xchunk, int order,
                            hipStream_t s, hipEvent_t* ev);
+// Two steps of Yee's scheme per launch, temporally blocked (bitwise two
+// single steps)
+bool yee2_fits(Geo g, int real_bytes);
+template <typename R>
+hipError_t launch_step_yee2(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, int xchunk, int order,
+                            hipStream_t s, hipEvent_t* ev);
 // One step of every instance of a batch (persistent grid of `grid`
 // workgroups), the launch after `flips` earlier launches and `steps` earlier
 // steps of the current block

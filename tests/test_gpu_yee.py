@@ -81,3 +81,28 @@ def test_yee_refuses_te_tm_only_calls():
     with pytest.raises(tete.TeteError) as e:
         B.set(0, G)
     assert e.value.status == "TETE_ERR_STATE"
+
+
+def _yee_pair(shape, seed, precision, steps, kernel, xchunk=0, order=0):
+    nx, ny, nz = shape
+    G = tete.Grid(nx, ny, nz, DX, DY, DZ, CDT, precision=precision, yee=True)
+    G.set_pec_cells(inputs.random_cells(nx, ny, nz, seed, frac=0.1))
+    G.set_tuning(kernel, 0, xchunk, 0, order)
+    G.set_fields(inputs.random_fields(G.shape, seed))
+    G.step(steps)
+    return G.get_fields()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_yee_two_step_kernel_equals_single_steps(precision, shape):
+    """Two Yee steps per launch (the default) give bitwise the fields of single
+    steps, for even and odd step counts (the last one single), x-chunks of one
+    to three planes and every tile order."""
+    print("yee two-step", precision, shape, flush=True)
+    for steps in (6, 7):
+        ref = _yee_pair(shape, 61, precision, steps, "fused")
+        for xchunk, order in ((0, 0), (1, 0), (2, 3), (3, 4), (0, 1), (0, 2), (0, 5), (0, 6)):
+            got = _yee_pair(shape, 61, precision, steps, "auto", xchunk, order)
+            for k in tete.KEYS:
+                assert np.array_equal(got[k], ref[k]), (steps, xchunk, order, k)
