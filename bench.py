@@ -77,7 +77,10 @@ def _tuned(cases, precision):
         key = size_class(c.nx, c.ny, c.nz, precision)
         if key not in shapes:
             sh = tuner.tune(c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, c.cdt, precision)
-            shapes[key] = {"xchunk": sh.xchunk, "order": sh.order, "ms_per_step": round(sh.ms, 4)}
+            # the class rounds each dimension up to a power of two; the time is
+            # that of the single-step kernel on the class's first grid
+            shapes[key] = {"xchunk": sh.xchunk, "order": sh.order, "ms_per_step": round(sh.ms, 4),
+                           "measured_on": "%dx%dx%d" % (c.nx, c.ny, c.nz)}
     return tuner, shapes
 
 
