@@ -106,3 +106,32 @@ def test_yee_two_step_kernel_equals_single_steps(precision, shape):
             got = _yee_pair(shape, 61, precision, steps, "auto", xchunk, order)
             for k in tete.KEYS:
                 assert np.array_equal(got[k], ref[k]), (steps, xchunk, order, k)
+
+
+def test_yee_two_step_full_size():
+    """At the benchmark's full size (512 x 512 x 2048 tapered collimator, FP32,
+    Yee's limit (8)): five steps from seeded random fields with two steps per
+    launch (the last one single) equal five single steps bitwise, compared
+    on the device."""
+    import torch
+    case = inputs.large_case()
+    print("yee full size", case.name, flush=True)
+    dt = (case.dx ** -2 + case.dy ** -2 + case.dz ** -2) ** -0.5
+    cells = case.cell_mask()
+    out = []
+    for kernel in ("auto", "fused"):
+        G = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, dt, precision="fp32", yee=True)
+        G.set_pec_cells(cells)
+        G.set_tuning(kernel)
+        f0 = inputs.random_fields_torch(G.shape, case.seed, "cuda", torch.float32)
+        G.set_fields(f0, dtype="fp32")
+        del f0
+        G.step(5)
+        out.append(G.get_fields(dtype="fp32", numpy=False))
+        G.close()
+        del G
+        torch.cuda.empty_cache()
+    for k in tete.KEYS:
+        assert torch.equal(out[0][k], out[1][k]), k
+    del out
+    torch.cuda.empty_cache()
