@@ -225,6 +225,45 @@ def witness_section(G, case, two_step_ms, offset=32, steps=20):
             "vs_two_step_without_witness": round(ms / two_step_ms, 3)}
 
 
+def materials_section(case, precision, explicit_ms_per_step, steps=6):
+    """Per-entry materials (tete_set_materials) on the large workload, every
+    kappa and mu 0.9 of its vacuum value (arrays made on the device): kernel
+    time per step of the fused single step's materials instance and of the
+    two-kernel step, against the vacuum two-step kernel.  The materials step
+    reads six coefficient arrays besides the fields: 73 B per entry in FP32
+    (97 + 48 in FP64) against 49 (97)."""
+    import torch
+    from paper_0901_1053_amd import tete
+    td = torch.float32 if precision == "fp32" else torch.float64
+    G = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.cdt, precision=precision,
+                  materials=True)
+    v = {"ex": case.dx / (case.dy * case.dz), "ey": case.dy / (case.dx * case.dz),
+         "ez": case.dz / (case.dx * case.dy)}
+    v.update({"hx": v["ex"], "hy": v["ey"], "hz": v["ez"]})
+    mat = {k: torch.full(G.shape, 0.9 * v[k], device="cuda", dtype=td) for k in tete.KEYS}
+    G.set_materials(mat, dtype=precision)
+    del mat
+    torch.cuda.empty_cache()
+    out = {}
+    for kernel in ("fused", "split"):
+        G.set_tuning(kernel)
+        G.step(2)
+        G.set_timing(steps)
+        G.step(steps)
+        a, b, n = G.timing()
+        G.set_timing(0)
+        out[kernel] = (a + b) / n
+    G.close()
+    del G
+    torch.cuda.empty_cache()
+    b = 4 if precision == "fp32" else 8
+    nbytes = (18 * b + 1) * (case.nx + 1) * (case.ny + 1) * (case.nz + 1)
+    return {"workload": case.name, "precision": precision, "materials": "0.9 x vacuum kappa and mu, per entry",
+            "ms_per_step": {"fused_materials": round(out["fused"], 3), "two_kernel": round(out["split"], 3)},
+            "fused_materials_gbps_algorithmic": round(nbytes / (out["fused"] / 1e3) / 1e9, 1),
+            "vs_vacuum_two_step": round(out["fused"] / explicit_ms_per_step, 2) if explicit_ms_per_step else None}
+
+
 def implicit_section(case, precision, explicit_ms_per_step, steps=4):
     """The implicit TE/TM scheme (16) on the large workload: kernel time per step
     (HIP events around the two half steps on the grid's stream), the Chebyshev
@@ -324,6 +363,7 @@ def main():
     ap.add_argument("--no-rz", action="store_true", help="skip the rotationally symmetric workload")
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit scheme (16) comparison")
     ap.add_argument("--no-witness", action="store_true", help="skip the off-axis witness timing")
+    ap.add_argument("--no-materials", action="store_true", help="skip the per-entry materials timing")
     ap.add_argument("--batched-count", type=int, default=64)
     ap.add_argument("--serve-rates", default="1,20,200", help="comma-separated request rates (req/s)")
     ap.add_argument("--serve-requests", type=int, default=12)
@@ -438,6 +478,10 @@ def main():
         out["implicit_context"] = implicit_section(case, args.precision, ms_step)
         torch.cuda.empty_cache()
         print("# implicit comparison done", file=sys.stderr, flush=True)
+    if not args.no_materials:
+        out["materials_context"] = materials_section(case, args.precision, ms_step)
+        torch.cuda.empty_cache()
+        print("# materials timing done", file=sys.stderr, flush=True)
 
     if not args.no_single_wake:
         sw = inputs.single_wake_case()

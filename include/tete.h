@@ -258,10 +258,12 @@ tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h);
 /* Kernel choice and launch shape (for tuning; results do not depend on it
  * beyond rounding order, and the fused kernels give identical results).
  * kernel:
- *   TETE_KERNEL_AUTO   the two-step kernel, or the two-kernel step with
+ *   TETE_KERNEL_AUTO   the two-step kernel, or the fused single step with
  *                      per-entry materials;
- *   TETE_KERNEL_FUSED  the fused single-kernel step (TETE_ERR_STATE with
- *                      per-entry materials);
+ *   TETE_KERNEL_FUSED  the fused single-kernel step (with per-entry
+ *                      materials: its materials instance, default rows and
+ *                      one prefetched plane, the coefficients read with the
+ *                      fields and carried to the sub-updates' planes);
  *   TETE_KERNEL_FUSED2 two steps per launch, temporally blocked
  *                      (TETE_ERR_STATE with per-entry materials).  tete_step
  *                      pairs consecutive steps except where an energy sample

@@ -203,11 +203,11 @@ ImpWork<R> imp_work(tete_grid* g)
     return w;
 }
 
-// The fused kernel covers vacuum cells with staircase PEC codes; per-entry
-// materials take the two-kernel path.
+// The fused kernel covers vacuum cells with staircase PEC codes and, in its
+// materials instance, per-entry materials.
 bool use_fused(const tete_grid* g)
 {
-    if (g->yee || g->implicit || g->mat_set || !fused_fits(g->geo, g->fp32 ? 4 : 8)) return false;
+    if (g->yee || g->implicit || !fused_fits(g->geo, g->fp32 ? 4 : 8)) return false;
     return g->tune.kernel != TETE_KERNEL_SPLIT;
 }
 
@@ -225,7 +225,7 @@ int fused2_rows(const tete_grid* g)
 bool use_fused2(const tete_grid* g)
 {
     const bool want = g->tune.kernel == TETE_KERNEL_FUSED2 || g->tune.kernel == TETE_KERNEL_AUTO;
-    return want && use_fused(g) && fused2_fits(g->geo, g->fp32 ? 4 : 8);
+    return want && !g->mat_set && use_fused(g) && fused2_fits(g->geo, g->fp32 ? 4 : 8);
 }
 
 template <typename R>
@@ -459,7 +459,7 @@ tete_status tete_set_tuning(tete_grid* g, const tete_tuning* t)
     if (t->xchunk < 0) return TETE_ERR_ARG;
     if (t->depth < 0 || t->depth > 3) return TETE_ERR_ARG;
     if (t->order < 0 || t->order > 6) return TETE_ERR_ARG;
-    if ((t->kernel == TETE_KERNEL_FUSED || t->kernel == TETE_KERNEL_FUSED2) && g->mat_set) return TETE_ERR_STATE;
+    if (t->kernel == TETE_KERNEL_FUSED2 && g->mat_set) return TETE_ERR_STATE;
     g->tune = *t;
     if (g->tune.depth == 0) g->tune.depth = 2;
     return TETE_OK;

@@ -42,11 +42,22 @@ struct Lds {
     R sHZN[2][TYH + 2][64];
 };
 
+// Per-entry materials (kappa_x, kappa_y, kappa_z, mu_x, mu_y, mu_z arrays,
+// zero on PEC edges and outside each component's range) for the MAT instance.
+template <typename R>
+struct MatA {
+    const R* m[6];
+};
+
 // One tile (ty, tz) and x-chunk cx of one step of the grid described by A.
-// Every thread of the workgroup must call it (it contains barriers).
-template <typename R, int TYH, int PD>
+// Every thread of the workgroup must call it (it contains barriers).  MAT:
+// the coefficients come from the per-entry arrays of MA, loaded with the
+// fields of each plane and carried to the lags where the sub-updates use them
+// (kappa_z to p-1, mu_x to p-2, mu_y to p-2, kappa_y to p-3, mu_z to p-3,
+// kappa_x to p-4), instead of the vacuum scalars and the PEC codes.
+template <typename R, int TYH, int PD, bool MAT = false>
 __device__ __forceinline__ void fused_tile(const FArgs<R>& A, const int ty, const int tz, const int cx,
-                                           Lds<R, TYH>& L)
+                                           Lds<R, TYH>& L, const MatA<R>& MA = MatA<R>{})
 {
     constexpr int TY = TYH - 4;
     auto& sEZ = L.sEZ;
@@ -120,6 +131,12 @@ __device__ __forceinline__ void fused_tile(const FArgs<R>& A, const int ty, cons
                sHX = mk(A.hx1 + st0, nstb), sHY = mk(A.hy1 + st0, nstb), sHZ1 = mk(A.hz1 + st0, nstb);
     const uint32_t in_ld = (uint32_t)roff * RB;
     const uint32_t cfix = node ? 0u : 7u;              // outside the grid: PEC
+    // material arrays over the same planes as the fields (MAT only)
+    __amdgpu_buffer_rsrc_t rM[6];
+    if constexpr (MAT) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) rM[c] = mk(MA.m[c] + ld0, nload * plane_bytes);
+    }
 
     auto load_plane = [&](int i, R& vex, R& vey, R& vez, R& vhx, R& vhy, R& vhz, uint32_t& vc) {
         const uint32_t po = (uint32_t)(i - pb);
@@ -141,16 +158,33 @@ __device__ __forceinline__ void fused_tile(const FArgs<R>& A, const int ty, cons
     struct PR {
         R ex, ey, ez, hx, hy, hz;
         uint32_t c;
+        R m[MAT ? 6 : 1];
     };
+    auto load_mat = [&](int i, PR& d) {
+        if constexpr (MAT) {
+            const uint32_t off = node ? in_ld + (uint32_t)(i - pb) * plane_bytes : OOB;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) d.m[c] = bload<R>(rM[c], off);
+        }
+    };
+    // carried coefficients of the MAT instance (index: planes behind p)
+    R KXc[5] = {}, KYc[4] = {}, KZc[2] = {}, MXc[3] = {}, MYc[3] = {}, MZc[4] = {};
     PR buf[PD + 1];
 #pragma unroll
-    for (int d = 0; d < PD; ++d)
+    for (int d = 0; d < PD; ++d) {
         load_plane(xs - 2 + d, buf[d].ex, buf[d].ey, buf[d].ez, buf[d].hx, buf[d].hy, buf[d].hz, buf[d].c);
+        load_mat(xs - 2 + d, buf[d]);
+    }
 
     const int pend = xe + 3;
     auto body = [&](const int p, const PR& cur, PR& nxt) {
         load_plane(p + PD, nxt.ex, nxt.ey, nxt.ez, nxt.hx, nxt.hy, nxt.hz, nxt.c);
+        load_mat(p + PD, nxt);
         const R EX0 = cur.ex, EY0 = cur.ey, EZ0 = cur.ez, HX0 = cur.hx, HY0 = cur.hy, HZ0 = cur.hz;
+        if constexpr (MAT) {
+            KXc[0] = cur.m[0]; KYc[0] = cur.m[1]; KZc[0] = cur.m[2];
+            MXc[0] = cur.m[3]; MYc[0] = cur.m[4]; MZc[0] = cur.m[5];
+        }
         // outside the grid, or a plane without old data: PEC on all edges
         const uint32_t c0 = ((cur.c >> (((uint32_t)(roff + p * g.sp) & 3u) * 8u)) & 7u) | cfix |
                             ((p >= pb && p <= xload_end) ? 0u : 7u);
@@ -177,16 +211,22 @@ __device__ __forceinline__ void fused_tile(const FArgs<R>& A, const int ty, cons
         const int q0 = p, q1 = p - 1, q2 = p - 2, q3 = p - 3, q4 = p - 4;
         auto xin = [&](int q) { return (unsigned)q <= (unsigned)g.nx; };
         auto xlt = [&](int q) { return q >= 0 && q < g.nx; };
-        const R mx0 = (hx_jk && xin(q0)) ? A.mx : R(0);
-        const R mx2 = (hx_jk && xin(q2)) ? A.mx : R(0);
-        const R my1 = (hy_k && xlt(q1)) ? A.my : R(0);
-        const R my2 = (hy_k && xlt(q2)) ? A.my : R(0);
-        const R mz3 = (hz_j && xlt(q3)) ? A.mz : R(0);
-        const R kz1 = (cm1 & 4u) ? R(0) : A.kz;
-        const R ky2 = (cm2 & 2u) ? R(0) : A.ky;
-        const R kx2 = (cm2 & 1u) ? R(0) : A.kx;
-        const R ky3 = (cm3 & 2u) ? R(0) : A.ky;
-        const R kx4 = (cm4 & 1u) ? R(0) : A.kx;
+        R mx0, mx2, my1, my2, mz3, kz1, ky2, kx2, ky3, kx4;
+        if constexpr (MAT) {
+            mx0 = MXc[0]; mx2 = MXc[2]; my1 = MYc[1]; my2 = MYc[2]; mz3 = MZc[3];
+            kz1 = KZc[1]; ky2 = KYc[2]; kx2 = KXc[2]; ky3 = KYc[3]; kx4 = KXc[4];
+        } else {
+            mx0 = (hx_jk && xin(q0)) ? A.mx : R(0);
+            mx2 = (hx_jk && xin(q2)) ? A.mx : R(0);
+            my1 = (hy_k && xlt(q1)) ? A.my : R(0);
+            my2 = (hy_k && xlt(q2)) ? A.my : R(0);
+            mz3 = (hz_j && xlt(q3)) ? A.mz : R(0);
+            kz1 = (cm1 & 4u) ? R(0) : A.kz;
+            ky2 = (cm2 & 2u) ? R(0) : A.ky;
+            kx2 = (cm2 & 1u) ? R(0) : A.kx;
+            ky3 = (cm3 & 2u) ? R(0) : A.ky;
+            kx4 = (cm4 & 1u) ? R(0) : A.kx;
+        }
 
         // S1 at q0: h_x^n = h_x^{n-1/2} + a mu_x [P_z e_y^n - P_y e_z^{n-1/2}]
         const R pzEY0 = lane_next(EY0) - EY0;
@@ -244,6 +284,15 @@ __device__ __forceinline__ void fused_tile(const FArgs<R>& A, const int ty, cons
         EZm1 = EZ0; HYm1 = HY0;
         HZm3 = HZm2; HZm2 = HZm1; HZm1 = HZ0;
         cm4 = cm3; cm3 = cm2; cm2 = cm1; cm1 = c0;
+        if constexpr (MAT) {
+#pragma unroll
+            for (int d = 4; d > 0; --d) KXc[d] = KXc[d - 1];
+#pragma unroll
+            for (int d = 3; d > 0; --d) { KYc[d] = KYc[d - 1]; MZc[d] = MZc[d - 1]; }
+#pragma unroll
+            for (int d = 2; d > 0; --d) { MXc[d] = MXc[d - 1]; MYc[d] = MYc[d - 1]; }
+            KZc[1] = KZc[0];
+        }
         hxn_m2 = hxn_m1; hxn_m1 = hxn0;
         hyn_m2 = hyn_m1;
         ezh_m2 = ezh_m1;
@@ -272,6 +321,16 @@ __global__ __launch_bounds__(64 * TYH) void k_fused(FArgs<R> A)
     int ty, tz, cx;
     if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) return;   // whole group
     fused_tile<R, TYH, PD>(A, ty, tz, cx, L);
+}
+
+// The same step with per-entry materials.
+template <typename R, int TYH, int PD>
+__global__ __launch_bounds__(64 * TYH) void k_fused_mat(FArgs<R> A, MatA<R> MA)
+{
+    __shared__ Lds<R, TYH> L;
+    int ty, tz, cx;
+    if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) return;   // whole group
+    fused_tile<R, TYH, PD, true>(A, ty, tz, cx, L, MA);
 }
 
 // One step of every active instance of a batch, by a persistent grid: work
@@ -422,11 +481,21 @@ hipError_t launch_step_fused(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha
                              int depth, int order, hipStream_t s, hipEvent_t* ev)
 {
     FArgs<R> A = fused_args<R>(o, nf, M, g, alpha, src);
-    if (rows == 0) rows = fused_default_rows(sizeof(R));
+    const bool mat = M.arr[0] != nullptr;   // per-entry materials: one shape, one plane prefetched
+    if (rows == 0 || mat) rows = fused_default_rows(sizeof(R));
     if (!fused_setup<R>(A, rows, xchunk, order)) return hipErrorInvalidValue;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
-    if (rows == 12) {
+    if (mat) {
+        MatA<R> MA;
+        for (int c = 0; c < 6; ++c) {
+            if (!M.arr[c]) return hipErrorInvalidValue;
+            MA.m[c] = M.arr[c];
+        }
+        constexpr int TYH = sizeof(R) == 8 ? 12 : 16;
+        k_fused_mat<R, TYH, 1><<<A.nblk, 64 * TYH, 0, s>>>(A, MA);
+        e = hipGetLastError();
+    } else if (rows == 12) {
         if (depth == 1) e = launch_fused_t<R, 12, 1>(A, s);
         else if (depth == 3) e = launch_fused_t<R, 12, 3>(A, s);
         else e = launch_fused_t<R, 12, 2>(A, s);

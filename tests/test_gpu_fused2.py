@@ -117,7 +117,11 @@ def test_materials_fall_back():
     assert G.get_tuning()["kernel"] == "fused2"
     rng = np.random.default_rng(0)
     G.set_materials({k: rng.uniform(0.5, 1.0, G.shape) for k in tete.KEYS})
+    assert G.get_tuning()["kernel"] == "fused"        # the single step's materials instance
+    G.set_tuning("split")
     assert G.get_tuning()["kernel"] == "split"
+    with pytest.raises(tete.TeteError):
+        G.set_tuning("fused2")
 
 
 @pytest.mark.parametrize("shape", [(13, 11, 37), (40, 29, 130), (2, 2, 2), (9, 20, 1000)])

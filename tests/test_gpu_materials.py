@@ -1,0 +1,92 @@
+"""Per-entry materials (tete_set_materials) on the fused single step's
+materials instance: fields against the oracle and against the two-kernel step
+on ragged grids with random kappa, mu and PEC edges, invariance under the
+launch shape, and a bunch wake through the materials."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_0901_1053_amd import inputs, tete
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(9, 10, 21), (17, 13, 70), (2, 2, 2), (30, 7, 131)]
+
+
+def _materials(g, seed):
+    rng = np.random.default_rng(seed)
+    m = O.vacuum_materials(g, inputs.random_cells(g.nx, g.ny, g.nz, seed, frac=0.1))
+    for k in O.KEYS:
+        m[k] = np.where(m[k] > 0, m[k] * rng.uniform(0.5, 1.0, size=m[k].shape), 0.0)
+    return m
+
+
+def _geom(shape):
+    nx, ny, nz = shape
+    return O.Geom(nx, ny, nz, 2.0e-3, 2.0e-3, 1.0e-3, 0.8e-3)
+
+
+def _gpu(shape, seed, precision, steps, kernel="auto", xchunk=0, order=0):
+    g = _geom(shape)
+    G = tete.Grid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.cdt, precision=precision, materials=True)
+    G.set_materials(_materials(g, seed))
+    if kernel != "auto" or xchunk or order:
+        G.set_tuning(kernel, 0, xchunk, 0, order)
+    G.set_fields(inputs.random_fields(G.shape, seed + 1))
+    G.step(steps)
+    return G
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fused_materials_matches_oracle(precision, shape):
+    """20 steps: FP64 within 1e-12 and FP32 within 2e-5 of the oracle, for the
+    fused materials instance and for the two-kernel step; energy as well."""
+    print("materials", precision, shape, flush=True)
+    g = _geom(shape)
+    m = _materials(g, 31)
+    f = inputs.random_fields(g.shape, 32)
+    O.apply_pec(g, m, f)
+    O.run(g, m, f, 20)
+    E = O.energy(g, m, f)
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    for kernel in ("fused", "split"):
+        G = _gpu(shape, 31, precision, 20, kernel)
+        assert G.get_tuning()["kernel"] == kernel
+        assert P.field_rel_err(G.get_fields(), f) <= tol, kernel
+        assert abs(G.energy()[0] - E) <= (1e-12 if precision == "fp64" else 1e-5) * abs(E), kernel
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_materials_launch_shape_invariance(precision):
+    """The materials instance gives bitwise the same fields for x-chunks of one
+    to three planes and every tile order."""
+    shape = (17, 13, 70)
+    ref = _gpu(shape, 33, precision, 9, "fused").get_fields()
+    for xchunk, order in ((1, 0), (2, 3), (3, 4), (0, 1), (0, 2), (0, 5), (0, 6)):
+        got = _gpu(shape, 33, precision, 9, "fused", xchunk, order).get_fields()
+        for k in tete.KEYS:
+            assert np.array_equal(got[k], ref[k]), (xchunk, order, k)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_materials_wake(precision):
+    """A bunch through random materials (cdt = dz): the wake within 1e-12
+    (FP64) / 1e-5 (FP32) of the oracle, the paper's delta norm."""
+    nx, ny, nz = 12, 12, 60
+    g = O.Geom(nx, ny, nz, 2.0e-3, 2.0e-3, 1.0e-3, 1.0e-3)
+    m = _materials(g, 34)
+    for k in ("ex", "ey", "ez", "hx", "hy", "hz"):       # the bunch line stays vacuum
+        m[k][6, 6, :] = np.where(m[k][6, 6, :] > 0, O.vacuum_materials(g)[k][6, 6, :], 0.0)
+    M = 12
+    b = O.Bunch(Q=1e-9, sigma=2e-3, i0=6, j0=6, M=M, jmin=-M - 4, nw=60)
+    steps = nz + M + b.jmin + b.nw
+    r = O.run(g, m, O.zeros(g), steps, bunch=b)
+    W = r["acc"] / (b.Q * P.EPS0)
+    G = tete.Grid(nx, ny, nz, g.dx, g.dy, g.dz, g.cdt, precision=precision, materials=True)
+    G.set_materials(m)
+    assert G.get_tuning()["kernel"] == "fused"
+    G.set_bunch(b.Q, b.sigma, b.i0, b.j0, M, b.jmin, b.nw)
+    G.step(steps)
+    assert P.delta_norm(G.wake(), W) <= (1e-12 if precision == "fp64" else 1e-5)
