@@ -1,10 +1,15 @@
-"""Launch-shape autotuner for the fused step.
+"""Launch-shape autotuner for the fused steps.
 
-For a grid size class it times the fused kernel over candidate launch shapes
-(x-planes per workgroup, tile order, and for single-grid stepping also rows per
+For a grid size class it times one kernel (the fused single step, or the
+two-step kernel that FP32 batches run) over candidate launch shapes (x-planes
+per workgroup, tile order, and for single-grid stepping also rows per
 workgroup and prefetch depth) with the library's live HIP-event timing, and
-caches the fastest shape per class in a JSON file.  Tuning changes only the
-launch shape, never the results (every shape gives bitwise the same fields).
+caches the fastest shape per class and kernel in a JSON file.  With batch = N
+each shape is timed on N copies of the grid stepped as one batch, the context
+batch members run in (there the instances already fill the GPU, and shorter
+x-chunks only add halo planes).  Tuning changes
+only the launch shape, never the results (every shape gives bitwise the same
+fields).
 """
 from __future__ import annotations
 
@@ -36,7 +41,11 @@ class Shape:
 
 class Tuner:
     def __init__(self, cache_path: str | None = DEFAULT_CACHE, xchunks=(0, 16, 32, 64, 128), orders=(1, 2),
-                 rows=(0,), depths=(0,), steps=6, warmup=2):
+                 rows=(0,), depths=(0,), steps=6, warmup=2, kernel="fused", batch=0):
+        if kernel not in ("fused", "fused2"):
+            raise ValueError("the tuner times the fused single step or the two-step kernel")
+        self.kernel = kernel
+        self.batch = batch
         self.cache_path = cache_path
         self.xchunks, self.orders, self.rows, self.depths = xchunks, orders, rows, depths
         self.steps, self.warmup = steps, warmup
@@ -66,8 +75,10 @@ class Tuner:
 
     def measure(self, nx, ny, nz, dx, dy, dz, cdt, precision, shape: Shape) -> float:
         from . import tete
+        if self.batch > 0:
+            return self._measure_batch(nx, ny, nz, dx, dy, dz, cdt, precision, shape)
         G = tete.Grid(nx, ny, nz, dx, dy, dz, cdt, precision=precision)
-        G.set_tuning("fused", shape.rows, shape.xchunk, shape.depth, shape.order)
+        G.set_tuning(self.kernel, shape.rows, shape.xchunk, shape.depth, shape.order)
         G.step(self.warmup)
         G.set_timing(self.steps)
         G.step(self.steps)
@@ -75,8 +86,41 @@ class Tuner:
         G.close()
         return ms / max(n, 1)
 
+    def _measure_batch(self, nx, ny, nz, dx, dy, dz, cdt, precision, shape: Shape) -> float:
+        """ms per step and instance of `batch` copies stepped as one batch
+        (HIP events on the batch's stream, after which its steps are ordered)."""
+        import torch
+
+        from . import tete
+        B = tete.Batch(precision)
+        B.set_launch(graph_steps=max(1, self.steps))
+        grids = []
+        for s in range(self.batch):
+            G = tete.Grid(nx, ny, nz, dx, dy, dz, cdt, precision=precision)
+            G.set_tuning(self.kernel, shape.rows, shape.xchunk, shape.depth, shape.order)
+            B.set(s, G)
+            grids.append(G)
+        B.step(self.steps)                      # warm-up (and the graph's capture)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(B.stream)
+        B.step(self.steps)
+        e1.record(B.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / (self.steps * self.batch)
+        for s in range(self.batch):
+            B.set(s, None)
+        B.close()
+        for G in grids:
+            G.close()
+        return ms
+
+    def _key(self, nx, ny, nz, precision):
+        return size_class(nx, ny, nz, precision) + "/" + self.kernel + ("/batch%d" % self.batch if self.batch else "")
+
     def tune(self, nx, ny, nz, dx, dy, dz, cdt, precision="fp32", force=False) -> Shape:
-        key = size_class(nx, ny, nz, precision)
+        key = self._key(nx, ny, nz, precision)
         if not force and key in self.cache:
             return Shape(**self.cache[key])
         best = None
@@ -89,5 +133,5 @@ class Tuner:
         return best
 
     def lookup(self, nx, ny, nz, precision) -> Shape | None:
-        v = self.cache.get(size_class(nx, ny, nz, precision))
+        v = self.cache.get(self._key(nx, ny, nz, precision))
         return Shape(**v) if v else None

@@ -134,7 +134,7 @@ class GpuExecutor:
         if self.tuner is not None:
             sh = self.tuner.lookup(c.nx, c.ny, c.nz, self.precision)
             if sh is not None:
-                G.set_tuning("fused", 0, sh.xchunk, 0, sh.order)
+                G.set_tuning(self.tuner.kernel, 0, sh.xchunk, 0, sh.order)   # the kernel it was timed on
         self.grids[slot] = G
         if self.batch is not None:
             self.batch.set(slot, G)

@@ -31,7 +31,9 @@ def _solo(case, precision):
 
 def test_served_equals_alone_and_fp64(tmp_path):
     cases = _cases(10)
-    tuner = Tuner(cache_path=str(tmp_path / "tune.json"), xchunks=(0, 32), orders=(1, 2), steps=2, warmup=1)
+    # the two-step kernel's shapes, which FP32 batch members then run with
+    tuner = Tuner(cache_path=str(tmp_path / "tune.json"), xchunks=(0, 32), orders=(1, 2), steps=2, warmup=1,
+                  kernel="fused2", batch=2)
     for c in cases[:2]:
         tuner.tune(c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, c.cdt, "fp32")
     assert (tmp_path / "tune.json").exists()
