@@ -83,3 +83,35 @@ def test_single_wake_full_run_properties(precision):
     if precision == "fp64":
         res_e, res_h = G.charges()
         assert res_e <= 1e-12 * case.Q and res_h <= 1e-12 * case.Q
+
+
+def test_large_wake_full_run_properties():
+    """The benchmark's workload in its launch configuration (512 x 512 x 2048
+    tapered collimator, FP32 fields, two steps per launch), run until the bunch
+    has left the grid with a wake window around the bunch: nothing ahead of the
+    head (bitwise zero), and the wake energy identity (field energy left behind
+    = sum_m lam_m Q W(s = -m dz)) within 1e-5, the FP32 tolerance on energy and
+    wake (measured: 2e-7 after 2243 steps)."""
+    case = inputs.large_case()
+    M = case.M
+    jmin = -M - 8
+    jmax = M + 8
+    nw = jmax - jmin + 1
+    steps = case.nz + M + jmax + 1
+    print("large full run, steps", steps, flush=True)
+    G = P.gpu_grid(case, "fp32")
+    assert G.get_tuning()["kernel"] == "fused2"
+    G.set_bunch(case.Q, case.sigma, case.i0, case.j0, M, jmin, nw)
+    G.step(steps)
+    W = G.wake()
+    e, _ = G.energy()
+    G.close()
+    j = jmin + np.arange(nw)
+    assert np.all(W[j < -M] == 0.0)
+    assert np.any(W[j >= -M] != 0.0)
+    from oracle import oracle as O
+    lam = O.bunch_cells(case.Q, case.sigma, case.dz, M)
+    acc = W * case.Q * P.EPS0
+    tot = sum(lam[m + M] * acc[-m - jmin] for m in range(-M, M + 1))
+    print("energy %.6e identity %.6e rel %.3e" % (e, tot, abs(e - tot) / e), flush=True)
+    assert e > 0 and abs(e - tot) <= 1e-5 * e
