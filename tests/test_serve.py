@@ -147,3 +147,17 @@ def test_cell_limit_bounds_work_in_flight():
     order = [e[2] for e in ex.log if e[0] == "admit"]
     assert order == sorted(order)
     assert st.max_active < len(cases)
+
+
+def test_tuner_keys_and_kernels(tmp_path):
+    """The tuner times the fused single step or the two-step kernel; its cache
+    keeps shapes apart by kernel and by batch context."""
+    from paper_0901_1053_amd.autotune import Tuner
+    with pytest.raises(ValueError):
+        Tuner(cache_path=None, kernel="split")
+    a = Tuner(cache_path=None)
+    b = Tuner(cache_path=None, kernel="fused2")
+    c = Tuner(cache_path=None, kernel="fused2", batch=8)
+    keys = {t._key(96, 96, 768, "fp32") for t in (a, b, c)}
+    assert len(keys) == 3
+    assert all(k.startswith("fp32:128x128x1024/") for k in keys)
