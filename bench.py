@@ -266,6 +266,38 @@ def materials_section(case, precision, explicit_ms_per_step, steps=6):
             "vs_vacuum_two_step": round(out["fused"] / explicit_ms_per_step, 2) if explicit_ms_per_step else None}
 
 
+def skip_section(case, precision, explicit_ms_per_step, steps=8, xchunks=(0, 128, 64, 32)):
+    """The two-step kernel leaving out tiles that lie wholly in PEC
+    (skip_static) on the large workload, for the library's x-chunk and a few
+    shorter ones (more tiles lie wholly in the metal block around the pipe,
+    each chunk re-reads seven halo planes): kernel time per step, tiles left
+    out, and the ratio to the full two-step step.  Fields and wake are those
+    of the full step (the skip tests); the headline counts every tile."""
+    import torch
+    from paper_0901_1053_amd import tete
+    G = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.cdt, precision=precision,
+                  skip_static=True)
+    G.set_pec_cells(case.cell_mask())
+    G.set_bunch(case.Q, case.sigma, case.i0, case.j0, case.M, case.jmin, case.nw)
+    rows = []
+    for xc in xchunks:
+        G.set_tuning("fused2", 0, xc)
+        G.step(4)
+        G.set_timing(steps)
+        G.step(steps)
+        a, b, n = G.timing()
+        G.set_timing(0)
+        ms = (a + b) / n
+        sk, tot = G.static_tiles()
+        rows.append({"xchunk": xc or "auto", "tiles": tot, "static_tiles": sk,
+                     "ms_per_step": round(ms, 3),
+                     "speedup_vs_full_step": round(explicit_ms_per_step / ms, 2) if explicit_ms_per_step else None})
+    G.close()
+    del G
+    torch.cuda.empty_cache()
+    return {"workload": case.name, "precision": precision, "runs": rows}
+
+
 def implicit_section(case, precision, explicit_ms_per_step, steps=4):
     """The implicit TE/TM scheme (16) on the large workload: kernel time per step
     (HIP events around the two half steps on the grid's stream), the Chebyshev
@@ -366,6 +398,7 @@ def main():
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit scheme (16) comparison")
     ap.add_argument("--no-witness", action="store_true", help="skip the off-axis witness timing")
     ap.add_argument("--no-materials", action="store_true", help="skip the per-entry materials timing")
+    ap.add_argument("--no-skip", action="store_true", help="skip the static-tile skip timing")
     ap.add_argument("--batched-count", type=int, default=64)
     ap.add_argument("--serve-rates", default="1,20,200", help="comma-separated request rates (req/s)")
     ap.add_argument("--serve-requests", type=int, default=12)
@@ -484,6 +517,10 @@ def main():
         out["materials_context"] = materials_section(case, args.precision, ms_step)
         torch.cuda.empty_cache()
         print("# materials timing done", file=sys.stderr, flush=True)
+    if not args.no_skip:
+        out["skip_static_context"] = skip_section(case, args.precision, ms_step)
+        torch.cuda.empty_cache()
+        print("# static-tile skip timing done", file=sys.stderr, flush=True)
 
     if not args.no_single_wake:
         sw = inputs.single_wake_case()

@@ -73,6 +73,16 @@ enum {
                                  * needs cdt = dz, which (8) excludes), no energy,
                                  * energy series or charges (TETE_ERR_STATE); probes
                                  * record e_z^{n+1/2}. */
+    TETE_F_SKIP_STATIC = 1u << 3, /* the two-step kernel leaves out tiles that lie wholly in
+                                 * PEC: every entry such a tile reads has its three e
+                                 * edges PEC, so e stays zero and h constant there and a
+                                 * step changes none of its entries.  Fields and wakes
+                                 * equal those of a grid without the flag.  Tiles are left out
+                                 * only once both ping-pong sets agree (from the second
+                                 * launch after tete_set_fields or tete_set_pec_cells),
+                                 * not while a witness is set, and not in single steps.
+                                 * Vacuum with staircase PEC only (not with
+                                 * TETE_F_MATERIALS, TETE_F_YEE, TETE_F_IMPLICIT). */
     TETE_F_IMPLICIT = 1u << 2   /* step with the implicit TE/TM scheme (16) of Sec. 4.1
                                  * instead of (23): a comparator.  Each half step solves
                                  * (I - alpha T_i) x = rhs; per z-plane this is one
@@ -234,6 +244,11 @@ tete_status tete_clear_witness(tete_grid* g);
  * complete once step nz - 1 + half_cells + j has run.  Synchronises the
  * stream.  TETE_ERR_STATE without a bunch or witness. */
 tete_status tete_witness_wake(tete_grid* g, double* W, double* Wx, double* Wy, int32_t nw);
+
+/* Static tiles of a TETE_F_SKIP_STATIC grid for its current geometry and
+ * two-step tiling: *skipped of *total tiles lie wholly in PEC.  Builds the
+ * table if needed; synchronises the stream.  TETE_ERR_STATE without the flag. */
+tete_status tete_static_tiles(tete_grid* g, int64_t* skipped, int64_t* total);
 
 /* Discrete energy W^{n,e} = 1/2 <Q^e y^n, y^n> (Sec. 4.4) of the current
  * state, FP64, internal units (joules = W / eps0 with charge in coulombs);

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "tete_impl.h"
 
@@ -22,7 +23,7 @@ size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t lam, wacc, wit, wmid, partial, scal, pidx, eser, pser, code, field[12], mat[6], imp[4], imp_le, imp_lh,
-        imp_cnt, total;
+        imp_cnt, skip, total;
 };
 
 int64_t series_cap(const tete_grid_desc* d) { return d->max_series > 0 ? d->max_series : 4096; }
@@ -56,6 +57,11 @@ bool make_layout(const tete_grid_desc* d, Layout* L)
         L->imp_le = o;  o = up(o + sizeof(int) * (size_t)np);
         L->imp_lh = o;  o = up(o + sizeof(int) * (size_t)np);
         L->imp_cnt = o; o = up(o + sizeof(int) * 2 * (size_t)implicit_list_chunks(np));
+    }
+    L->skip = 0;
+    if (d->flags & TETE_F_SKIP_STATIC) {   // static-tile table of the two-step kernel
+        Geo g = {d->nx, d->ny, d->nz, d->nz + 1, (d->ny + 1) * (d->nz + 1), (int)np};
+        L->skip = o; o = up(o + (size_t)fused2_tile_cap(g));
     }
     L->total = o;
     return true;
@@ -96,6 +102,15 @@ struct tete_grid {
     uint8_t* code;
     void* mat[6];
     int mat_set;
+    // static-tile skip (TETE_F_SKIP_STATIC): the table for the tiling
+    // (skip_rows, skip_xc), skip_rows = -1 while none is built for the
+    // current codes; skip_live is set once a launch has written the other
+    // field set since the fields or codes were last set, so that both sets
+    // agree on every static tile
+    int skip;
+    uint8_t* skip_tab;
+    int skip_rows, skip_xc;
+    int skip_live;
     double *lam, *wacc, *partial, *scal, *eser, *pser;
     double* wit;       // witness accumulators, TETE_WITNESS_LINES x TETE_MAX_WAKE
     void* wmid;        // e_z^{n+1/2} of the witness lines in a two-step launch (TETE_WITNESS_LINES x nz)
@@ -228,6 +243,20 @@ bool use_fused2(const tete_grid* g)
     return want && !g->mat_set && use_fused(g) && fused2_fits(g->geo, g->fp32 ? 4 : 8);
 }
 
+// Builds the static-tile table for the current tiling of the two-step
+// kernel unless it is already there.
+template <typename R>
+tete_status static_table(tete_grid* g)
+{
+    const int rows = fused2_rows(g), xc = g->tune.xchunk;
+    if (g->skip_rows == rows && g->skip_xc == xc) return TETE_OK;
+    int64_t nt = 0;
+    HIPCHK(fused2_static_tiles<R>(g->code, g->geo, rows, xc, g->skip_tab, fused2_tile_cap(g->geo), &nt, g->stream));
+    g->skip_rows = rows;
+    g->skip_xc = xc;
+    return TETE_OK;
+}
+
 template <typename R>
 tete_status do_steps(tete_grid* g, int64_t nsteps)
 {
@@ -263,9 +292,15 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
         if (pair) {
             WitMid<R> wm;
             if (wit) wm = witness_mid<R>(g);
+            const uint8_t* skip = nullptr;
+            if (g->skip && !wit && g->skip_live) {
+                if (static_table<R>(g) != TETE_OK) return TETE_ERR_DEVICE;
+                skip = g->skip_tab;
+            }
             HIPCHK(launch_step_fused2<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                          source(g, g->n), wit ? &wm : nullptr, fused2_rows(g), g->tune.xchunk,
-                                         g->tune.order, g->stream, ev));
+                                         g->tune.order, g->stream, ev, skip));
+            g->skip_live = 1;
             if (wit)   // e_z^{n-1/2} in the old set, e_z^{n+1/2} in wm.mid, e_z^{n+3/2} in the new set
                 HIPCHK(launch_witness2<R>((const R*)g->f[g->cur][2], wm.mid, (const R*)g->f[1 - g->cur][2],
                                           witness_lines(g), g->geo, g->n, g->b.half_cells, g->b.jmin, g->b.nw,
@@ -298,6 +333,7 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
                                      g->geo, g->n, g->b.half_cells, g->b.jmin, g->b.nw, g->wit, g->stream));
         g->cur = 1 - g->cur;
         g->n++;
+        g->skip_live = 1;
         if (g->nprobe > 0) {
             HIPCHK(launch_probes<R>((const R*)g->f[g->cur][2], g->pidx, g->nprobe, g->pser + g->pcount * g->nprobe,
                                     g->stream));
@@ -343,7 +379,10 @@ tete_status tete_check_desc(const tete_grid_desc* d)
     if (np >= ((int64_t)1 << 31) - 1) return TETE_ERR_ARG;
     if (!finite_pos(d->dx) || !finite_pos(d->dy) || !finite_pos(d->dz) || !finite_pos(d->cdt)) return TETE_ERR_ARG;
     if (d->precision != TETE_FP64 && d->precision != TETE_FP32) return TETE_ERR_ARG;
-    if (d->flags & ~(uint32_t)(TETE_F_MATERIALS | TETE_F_YEE | TETE_F_IMPLICIT)) return TETE_ERR_ARG;
+    if (d->flags & ~(uint32_t)(TETE_F_MATERIALS | TETE_F_YEE | TETE_F_IMPLICIT | TETE_F_SKIP_STATIC))
+        return TETE_ERR_ARG;
+    if ((d->flags & TETE_F_SKIP_STATIC) && (d->flags & (TETE_F_MATERIALS | TETE_F_YEE | TETE_F_IMPLICIT)))
+        return TETE_ERR_ARG;
     if ((d->flags & TETE_F_YEE) && (d->flags & TETE_F_MATERIALS)) return TETE_ERR_ARG;
     if ((d->flags & TETE_F_IMPLICIT) && (d->flags & (TETE_F_MATERIALS | TETE_F_YEE))) return TETE_ERR_ARG;
     if (d->max_series < 0 || d->max_series > (1 << 24)) return TETE_ERR_ARG;
@@ -409,6 +448,11 @@ tete_status tete_grid_create(const tete_grid_desc* d, void* dev_ws, size_t ws_by
         for (int c = 0; c < 6; ++c) g->f[s][c] = g->ws + L.field[6 * s + c];
     g->cur = 0;
     g->code = (uint8_t*)(g->ws + L.code);
+    g->skip = (d->flags & TETE_F_SKIP_STATIC) != 0;
+    g->skip_tab = g->skip ? (uint8_t*)(g->ws + L.skip) : nullptr;
+    g->skip_rows = -1;
+    g->skip_xc = 0;
+    g->skip_live = 0;
     for (int c = 0; c < 6; ++c) g->mat[c] = (d->flags & TETE_F_MATERIALS) ? g->ws + L.mat[c] : nullptr;
     g->lam = (double*)(g->ws + L.lam);
     g->wacc = (double*)(g->ws + L.wacc);
@@ -529,6 +573,8 @@ tete_status tete_set_pec_cells(tete_grid* g, const uint8_t* cells)
     HIPCHK(launch_build_codes(g->code, cells, g->geo, g->stream));
     g->mat_set = 0;
     g->imp_lists = 0;
+    g->skip_rows = -1;
+    g->skip_live = 0;
     if (g->fp32) HIPCHK(launch_zero_pec<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->stream));
     else HIPCHK(launch_zero_pec<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->stream));
     return TETE_OK;
@@ -571,7 +617,29 @@ tete_status tete_set_fields(tete_grid* g, const void* const f[6], int32_t dtype)
     if (!dg.ok) return TETE_ERR_DEVICE;
     if (g->fp32) HIPCHK(launch_import<float>(fields<float>(g, g->cur), f, dtype == TETE_FP32, mats<float>(g), g->geo, g->stream));
     else HIPCHK(launch_import<double>(fields<double>(g, g->cur), f, dtype == TETE_FP32, mats<double>(g), g->geo, g->stream));
+    g->skip_live = 0;
     return reset_series(g);
+}
+
+tete_status tete_static_tiles(tete_grid* g, int64_t* skipped, int64_t* total)
+{
+    if (!g || !skipped || !total) return TETE_ERR_ARG;
+    if (!g->skip) return TETE_ERR_STATE;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    tete_status st = g->fp32 ? static_table<float>(g) : static_table<double>(g);
+    if (st != TETE_OK) return st;
+    int64_t nt = 0;
+    HIPCHK(g->fp32 ? fused2_tile_count<float>(g->geo, g->skip_rows, g->skip_xc, &nt)
+                   : fused2_tile_count<double>(g->geo, g->skip_rows, g->skip_xc, &nt));
+    std::vector<uint8_t> t((size_t)nt);
+    HIPCHK(hipStreamSynchronize(g->stream));
+    if (nt > 0) HIPCHK(hipMemcpy(t.data(), g->skip_tab, (size_t)nt, hipMemcpyDeviceToHost));
+    int64_t c = 0;
+    for (uint8_t v : t) c += v;
+    *skipped = c;
+    *total = nt;
+    return TETE_OK;
 }
 
 tete_status tete_get_fields(tete_grid* g, void* const f[6], int32_t dtype)

@@ -420,14 +420,48 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
     }
 }
 
+// skip (or null): one byte per tile (cx, ty, tz), set where the tile is
+// static (fused2_static_tiles): the whole workgroup returns at once.
 template <typename R, int TYH, int LW>
-__global__ __launch_bounds__(TYH * LW) void k_fused2(FArgs<R> A)
+__global__ __launch_bounds__(TYH * LW) void k_fused2(FArgs<R> A, const uint8_t* skip)
 {
     typedef Shape2<R, TYH, LW> S;
     __shared__ Lds2<R, S::rows, S::nb, S::lw> L;
     int ty, tz, cx;
     if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) return;   // whole group
+    if (skip && skip[((int64_t)cx * A.nyt + ty) * A.nzt + tz]) return;
     fused2_tile<R, S::rows, S::nb, S::lw>(A, ty, tz, cx, L);
+}
+
+// A tile of the two-step kernel is static when every entry it loads (its rows
+// and lanes with their halos, over planes max(0, xs-4) .. min(xe+3, nx)) has
+// all three e edges PEC or absent (code 7), entries outside the grid counting
+// as PEC: then e stays zero and h constant there, and both steps leave every
+// entry the tile owns bitwise unchanged.  One workgroup per tile.
+__global__ __launch_bounds__(256) void k_static2(const uint8_t* code, Geo g, int TYH, int LW, int TY, int KT2,
+                                                 int xchunk, int nyt, int nzt, uint8_t* out)
+{
+    __shared__ int active;
+    const int t = blockIdx.x;
+    const int tz = t % nzt, ty = (t / nzt) % nyt, cx = t / (nzt * nyt);
+    if (threadIdx.x == 0) active = 0;
+    __syncthreads();
+    const int xs = cx * xchunk, xe = min(xs + xchunk, g.nx + 1);
+    const int pb = max(0, xs - 4), pe = min(xe + 3, g.nx);
+    const int rows = TYH, lanes = LW;
+    const int64_t per_plane = (int64_t)rows * lanes;
+    const int64_t n = (int64_t)(pe - pb + 1) * per_plane;
+    bool found = false;
+    for (int64_t e = threadIdx.x; e < n && !found; e += blockDim.x) {
+        const int q = pb + (int)(e / per_plane);
+        const int r = (int)(e % per_plane);
+        const int j = ty * TY - 3 + r / lanes, k = tz * KT2 - 2 + r % lanes;
+        if (j < 0 || j > g.ny || k < 0 || k > g.nz) continue;
+        if ((code[(int64_t)q * g.sp + (int64_t)j * g.sz + k] & 7u) != 7u) found = true;
+    }
+    if (found) atomicOr(&active, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) out[t] = active ? 0 : 1;
 }
 
 // The two-step kernel that also keeps e_z^{n+1/2} of the witness lines.
@@ -534,9 +568,43 @@ bool fused2_fits(Geo g, int real_bytes)
     return (int64_t)g.sp * real_bytes * 9 < (int64_t(1) << 31);
 }
 
+int64_t fused2_tile_cap(Geo g)
+{
+    // the smallest owned shape: 10 rows (16-row tiles) by 28 entries (32 lanes)
+    // over tiles of single planes
+    return (int64_t)(g.nx + 1) * ((g.ny + 1 + 9) / 10) * ((g.nz + 1 + 27) / 28);
+}
+
+template <typename R>
+hipError_t fused2_tile_count(Geo g, int rows, int xchunk, int64_t* ntiles)
+{
+    FArgs<R> A = fused_args<R>(Fields<R>{}, Fields<R>{}, Mat<R>{}, g, R(0), Src{});
+    if (!fused2_setup<R>(A, rows, xchunk, 1)) return hipErrorInvalidValue;
+    *ntiles = (int64_t)A.nyt * A.nzt * A.nxc;
+    return hipSuccess;
+}
+
+template <typename R>
+hipError_t fused2_static_tiles(const uint8_t* code, Geo g, int rows, int xchunk, uint8_t* out, int64_t cap,
+                               int64_t* ntiles, hipStream_t s)
+{
+    Fields<R> none = {};
+    Mat<R> M = {};
+    M.code = code;
+    FArgs<R> A = fused_args<R>(none, none, M, g, R(0), Src{});
+    if (!fused2_setup<R>(A, rows, xchunk, 1)) return hipErrorInvalidValue;
+    const int64_t nt = (int64_t)A.nyt * A.nzt * A.nxc;
+    if (nt > cap || nt > 0x7fffffff) return hipErrorInvalidValue;
+    const int r = rows == 0 ? Default2<R>::rows : rows;
+    const int lw = lanes2(sizeof(R), r);
+    k_static2<<<(int)nt, 256, 0, s>>>(code, g, r, lw, r - 6, lw - 4, A.xchunk, A.nyt, A.nzt, out);
+    *ntiles = nt;
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha, Src src, const WitMid<R>* wm,
-                              int rows, int xchunk, int order, hipStream_t s, hipEvent_t* ev)
+                              int rows, int xchunk, int order, hipStream_t s, hipEvent_t* ev, const uint8_t* skip)
 {
     FArgs<R> A = fused_args<R>(o, nf, M, g, alpha, src);
     if (wm) rows = 0;   // the instance that keeps witness lines has the default shape only
@@ -552,11 +620,12 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
     }
     if constexpr (sizeof(R) == 4) {
         if (!done && rows == 32) {
-            k_fused2<R, 32, 32><<<A.nblk, 32 * 32, 0, s>>>(A);
+            k_fused2<R, 32, 32><<<A.nblk, 32 * 32, 0, s>>>(A, skip);
             done = true;
         }
     }
-    if (!done) k_fused2<R, Default2<R>::rows, Default2<R>::lw><<<A.nblk, Default2<R>::rows * Default2<R>::lw, 0, s>>>(A);
+    if (!done)
+        k_fused2<R, Default2<R>::rows, Default2<R>::lw><<<A.nblk, Default2<R>::rows * Default2<R>::lw, 0, s>>>(A, skip);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
@@ -567,7 +636,10 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
     template hipError_t launch_batch_step2<R>(BatchTable<R>*, int, int, int, hipStream_t);                     \
     template bool fused2_setup<R>(FArgs<R>&, int, int, int);                                                   \
     template hipError_t launch_step_fused2<R>(Fields<R>, Fields<R>, Mat<R>, Geo, R, Src, const WitMid<R>*, int, \
-                                              int, int, hipStream_t, hipEvent_t*);
+                                              int, int, hipStream_t, hipEvent_t*, const uint8_t*);           \
+    template hipError_t fused2_static_tiles<R>(const uint8_t*, Geo, int, int, uint8_t*, int64_t, int64_t*,     \
+                                               hipStream_t);                                                   \
+    template hipError_t fused2_tile_count<R>(Geo, int, int, int64_t*);
 TETE_FUSED2_INST(float)
 TETE_FUSED2_INST(double)
 

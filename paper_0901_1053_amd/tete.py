@@ -19,6 +19,7 @@ FP64, FP32 = 0, 1
 F_MATERIALS = 1
 F_YEE = 2
 F_IMPLICIT = 4
+F_SKIP_STATIC = 8
 MAX_BUNCH_CELLS = 8191
 MAX_WAKE = 65536
 MAX_PROBES = 16
@@ -101,6 +102,7 @@ def load(path: str = LIB_PATH):
         "tete_set_witness": (st, [vp, C.c_int32, C.c_int32]),
         "tete_clear_witness": (st, [vp]),
         "tete_witness_wake": (st, [vp, vp, vp, vp, C.c_int32]),
+        "tete_static_tiles": (st, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
         "tete_energy": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "tete_energy_series": (st, [vp, vp, C.c_int64, C.POINTER(C.c_int64)]),
         "tete_probes": (st, [vp, vp, C.c_int64, C.POINTER(C.c_int64)]),
@@ -147,9 +149,10 @@ def _chk(fn, code):
 
 
 def make_desc(nx, ny, nz, dx, dy, dz, cdt, precision="fp64", materials=False, max_series=0,
-              yee=False, implicit=False) -> GridDesc:
+              yee=False, implicit=False, skip_static=False) -> GridDesc:
     prec = {"fp64": FP64, "fp32": FP32}[precision]
-    flags = (F_MATERIALS if materials else 0) | (F_YEE if yee else 0) | (F_IMPLICIT if implicit else 0)
+    flags = (F_MATERIALS if materials else 0) | (F_YEE if yee else 0) | (F_IMPLICIT if implicit else 0) | \
+        (F_SKIP_STATIC if skip_static else 0)
     return GridDesc(nx, ny, nz, dx, dy, dz, cdt, prec, flags, max_series)
 
 
@@ -164,14 +167,17 @@ def workspace_bytes(desc: GridDesc) -> int:
 class Grid:
     """One explicit TE/TM grid (or, with yee=True, a grid stepped with Yee's
     scheme (7), with implicit=True one stepped with the implicit TE/TM scheme
-    (16), for comparison) living in a torch-owned device workspace."""
+    (16), for comparison) living in a torch-owned device workspace.
+    skip_static=True lets the two-step kernel leave out tiles that lie wholly
+    in PEC (the results are unchanged)."""
 
     def __init__(self, nx, ny, nz, dx, dy, dz, cdt, precision="fp64", materials=False, max_series=0,
-                 device="cuda:0", stream=None, yee=False, implicit=False):
+                 device="cuda:0", stream=None, yee=False, implicit=False, skip_static=False):
         import torch
         L = load()
         self.torch = torch
-        self.desc = make_desc(nx, ny, nz, dx, dy, dz, cdt, precision, materials, max_series, yee, implicit)
+        self.desc = make_desc(nx, ny, nz, dx, dy, dz, cdt, precision, materials, max_series, yee, implicit,
+                              skip_static)
         _chk("tete_check_desc", L.tete_check_desc(C.byref(self.desc)))
         self.nbytes = workspace_bytes(self.desc)
         self.device = torch.device(device)
@@ -303,6 +309,13 @@ class Grid:
         wy = np.zeros(nw)
         _chk("tete_witness_wake", load().tete_witness_wake(self.h, W.ctypes.data, wx.ctypes.data, wy.ctypes.data, nw))
         return W, wx, wy
+
+    def static_tiles(self):
+        """(tiles left out, tiles) of the two-step kernel's current tiling
+        (skip_static grids)."""
+        a, b = C.c_int64(), C.c_int64()
+        _chk("tete_static_tiles", load().tete_static_tiles(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def energy(self):
         w = C.c_double()

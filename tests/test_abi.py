@@ -56,8 +56,11 @@ def test_descriptor_limits():
     d.precision = 7
     assert tete.check_desc(d) == "TETE_ERR_ARG"
     d = tete.make_desc(8, 8, 8, 2, 2, 1, 1)
-    d.flags = 8                                            # no such flag
+    d.flags = 16                                           # no such flag
     assert tete.check_desc(d) == "TETE_ERR_ARG"
+    for kw in ({"materials": True}, {"yee": True}, {"implicit": True}):   # the skip is for vacuum + PEC
+        assert tete.check_desc(tete.make_desc(8, 8, 8, 2, 2, 1, 0.5, skip_static=True, **kw)) == "TETE_ERR_ARG"
+    assert tete.check_desc(tete.make_desc(8, 8, 8, 2, 2, 1, 1, skip_static=True)) == "TETE_OK"
     d = tete.make_desc(8, 8, 8, 2, 2, 1, 0.5, materials=True, yee=True)     # Yee is vacuum + PEC only
     assert tete.check_desc(d) == "TETE_ERR_ARG"
 
@@ -84,6 +87,11 @@ def test_workspace_bytes():
     dm = tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp64", materials=True)
     assert tete.workspace_bytes(dm) >= b64 + 6 * 8 * np_
     assert tete.workspace_bytes(tete.make_desc(1, 1, 1, 2, 2, 1, 1)) == 0
+    # the static-tile table: one byte per tile of the finest tiling (single
+    # planes, 10 rows by 28 entries)
+    ds = tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp64", skip_static=True)
+    cap = 129 * -(-129 // 10) * -(-1025 // 28)
+    assert cap <= tete.workspace_bytes(ds) - b64 <= cap + 256
 
 
 @pytest.mark.parametrize("mode,dr,dz,cdt,want", [

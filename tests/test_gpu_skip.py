@@ -1,0 +1,185 @@
+"""Static-tile skip (TETE_F_SKIP_STATIC): a grid that leaves out the two-step
+kernel's tiles lying wholly in PEC gives the same fields, wake and witness
+wakes as a grid that steps every tile, over odd step counts, new fields and
+geometry mid-run, changed tilings and both precisions; the table's count of
+static tiles matches one derived on the CPU from the oracle's PEC edges."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_0901_1053_amd import inputs, tete
+
+pytestmark = pytest.mark.gpu
+
+DZ = 1.0e-3
+
+
+JC = 14   # the pipe's axis and the bunch: node (nx // 2, JC)
+
+
+def _pipe_cells(nx, ny, nz, r_cells, seed=0):
+    """Metal block with a round pipe along z (radius r_cells about node
+    (nx // 2, JC)) and a few random metal cells: the tiles away from the
+    pipe are wholly metal, the pipe's are not."""
+    i = np.arange(nx)[:, None] + 0.5 - nx // 2
+    j = np.arange(ny)[None, :] + 0.5 - JC
+    metal = (i * i + j * j) > r_cells * r_cells
+    cells = np.repeat(metal[:, :, None], nz, axis=2)
+    extra = inputs.random_cells(nx, ny, nz, seed, frac=0.03)
+    return (cells | extra.astype(bool)).astype(np.uint8)
+
+
+def _grid(shape, precision, skip, cells, fields_seed, xchunk=0, rows=0):
+    nx, ny, nz = shape
+    G = tete.Grid(nx, ny, nz, 2 * DZ, 2 * DZ, DZ, DZ, precision=precision, skip_static=skip)
+    if xchunk or rows:
+        G.set_tuning("fused2", rows, xchunk)
+    G.set_pec_cells(cells)
+    G.set_fields(inputs.random_fields(G.shape, fields_seed))
+    G.set_bunch(1e-9, 2e-3, nx // 2, JC, 10, -14, 40)
+    return G
+
+
+def _same(a, b):
+    fa, fb = a.get_fields(), b.get_fields()
+    for k in tete.KEYS:
+        assert np.array_equal(fa[k], fb[k]), k
+    assert np.array_equal(a.wake(), b.wake())
+
+
+SHAPE = (40, 61, 150)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("xchunk,rows", [(0, 0), (8, 0), (5, 16), (11, 32)])
+def test_skip_matches_full(precision, xchunk, rows):
+    """15 steps (seven two-step launches and one single step) with a bunch:
+    the same fields and wake as the grid without the skip."""
+    if rows == 32 and precision == "fp64":
+        pytest.skip("32-row tiles are FP32 only")
+    print("skip", precision, xchunk, rows, flush=True)
+    cells = _pipe_cells(*SHAPE, 6, seed=81)
+    A = _grid(SHAPE, precision, True, cells, 82, xchunk, rows)
+    B = _grid(SHAPE, precision, False, cells, 82, xchunk, rows)
+    A.step(15)
+    B.step(15)
+    assert A.get_tuning()["kernel"] in ("fused2", "auto")
+    skipped, total = A.static_tiles()
+    assert 0 < skipped < total
+    _same(A, B)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_skip_history(precision):
+    """Other geometry, fields and steps first, then new geometry and fields,
+    a change of x-chunk mid-run and new fields again: the same as a grid
+    without the skip given the same calls."""
+    print("skip history", precision, flush=True)
+    c1 = _pipe_cells(*SHAPE, 4, seed=83)
+    c2 = _pipe_cells(*SHAPE, 7, seed=84)
+    grids = []
+    for skip in (True, False):
+        G = _grid(SHAPE, precision, skip, c1, 85, xchunk=6)
+        G.step(6)
+        G.set_pec_cells(c2)
+        G.set_fields(inputs.random_fields(G.shape, 86))
+        G.step(5)
+        G.set_tuning("fused2", 0, 13)
+        G.step(6)
+        G.set_fields(inputs.random_fields(G.shape, 87))
+        G.step(4)
+        grids.append(G)
+    _same(*grids)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_skip_with_witness(precision):
+    """With a witness set the kernel steps every tile: the witness wakes
+    and fields match the grid without the skip."""
+    print("skip witness", precision, flush=True)
+    cells = _pipe_cells(*SHAPE, 6, seed=88)
+    A = _grid(SHAPE, precision, True, cells, 89)
+    B = _grid(SHAPE, precision, False, cells, 89)
+    for G in (A, B):
+        G.set_witness(SHAPE[0] // 2 + 2, JC)
+        G.step(12)
+    _same(A, B)
+    for a, b in zip(A.witness_wake(), B.witness_wake()):
+        assert np.array_equal(a, b)
+
+
+def _expected_static(shape, cells, precision, rows, xchunk):
+    """Tiles whose loaded window (rows and lanes with halos, planes
+    max(0, xs-4) .. min(xe+3, nx)) holds only entries whose three e edges
+    are PEC or absent, from the oracle's materials (kappa 0 on such edges)."""
+    nx, ny, nz = shape
+    g = O.Geom(nx, ny, nz, 2 * DZ, 2 * DZ, DZ, DZ)
+    m = O.vacuum_materials(g, cells)
+    s = (m["ex"] == 0) & (m["ey"] == 0) & (m["ez"] == 0)
+    r = rows or 16
+    lw = 32 if precision == "fp64" or r == 32 else 64
+    TY, KT = r - 6, lw - 4
+    nyt, nzt, nxc = -(-(ny + 1) // TY), -(-(nz + 1) // KT), -(-(nx + 1) // xchunk)
+    count = 0
+    for cx in range(nxc):
+        xs, xe = cx * xchunk, min(cx * xchunk + xchunk, nx + 1)
+        pl = s[max(0, xs - 4):min(xe + 3, nx) + 1].all(axis=0)
+        for ty in range(nyt):
+            j0, j1 = max(0, ty * TY - 3), min(ny, ty * TY - 3 + r - 1)
+            for tz in range(nzt):
+                k0, k1 = max(0, tz * KT - 2), min(nz, tz * KT - 2 + lw - 1)
+                count += bool(pl[j0:j1 + 1, k0:k1 + 1].all())
+    return count, nxc * nyt * nzt
+
+
+@pytest.mark.parametrize("precision,rows,xchunk", [("fp32", 0, 7), ("fp32", 32, 4), ("fp64", 0, 9)])
+def test_static_tile_count(precision, rows, xchunk):
+    print("static count", precision, rows, xchunk, flush=True)
+    cells = _pipe_cells(*SHAPE, 6, seed=90)
+    G = _grid(SHAPE, precision, True, cells, 91, xchunk, rows)
+    got = G.static_tiles()
+    assert got == _expected_static(SHAPE, cells, precision, rows, xchunk)
+    # all metal: every tile; vacuum: none
+    G.set_pec_cells(np.ones(SHAPE, np.uint8))
+    n = G.static_tiles()
+    assert n[0] == n[1] > 0
+    G.set_pec_cells(np.zeros(SHAPE, np.uint8))
+    assert G.static_tiles()[0] == 0
+
+
+def test_skip_flag_rules():
+    """The flag is refused with materials, Yee's scheme and the implicit
+    scheme; static_tiles needs the flag."""
+    for kw in ({"materials": True}, {"yee": True}, {"implicit": True}):
+        with pytest.raises(tete.TeteError):
+            tete.Grid(8, 8, 8, 2 * DZ, 2 * DZ, DZ, DZ, skip_static=True, **kw)
+    G = tete.Grid(8, 8, 8, 2 * DZ, 2 * DZ, DZ, DZ)
+    with pytest.raises(tete.TeteError):
+        G.static_tiles()
+
+
+def test_skip_large_case_samples():
+    """The large tapered collimator (512 x 512 x 2048, FP32) for 8 steps with
+    and without the skip, compared on the device (max |difference| over every
+    component must be 0)."""
+    import torch
+    print("skip large", flush=True)
+    case = inputs.large_case()
+    res = []
+    for skip in (True, False):
+        G = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.cdt, precision="fp32",
+                      skip_static=skip)
+        G.set_pec_cells(case.cell_mask())
+        G.set_bunch(case.Q, case.sigma, case.i0, case.j0, case.M, case.jmin, case.nw)
+        G.step(8)
+        if skip:
+            sk, tot = G.static_tiles()
+            print("static tiles", sk, tot, flush=True)
+            assert sk > tot // 2
+        res.append((G.get_fields(dtype="fp32", numpy=False), G.wake()))
+        del G
+        torch.cuda.synchronize()
+    (fa, wa), (fb, wb) = res
+    for k in tete.KEYS:
+        assert torch.equal(fa[k], fb[k]), k
+    assert np.array_equal(wa, wb)
