@@ -81,6 +81,8 @@ enum {
                                  * only once both ping-pong sets agree (from the second
                                  * launch after tete_set_fields or tete_set_pec_cells),
                                  * not while a witness is set, and not in single steps.
+                                 * The two-step launches take only the other tiles; with
+                                 * tuning x-chunk 0 such grids use chunks of 32 planes.
                                  * Vacuum with staircase PEC only (not with
                                  * TETE_F_MATERIALS, TETE_F_YEE, TETE_F_IMPLICIT). */
     TETE_F_IMPLICIT = 1u << 2   /* step with the implicit TE/TM scheme (16) of Sec. 4.1

@@ -23,7 +23,7 @@ size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t lam, wacc, wit, wmid, partial, scal, pidx, eser, pser, code, field[12], mat[6], imp[4], imp_le, imp_lh,
-        imp_cnt, skip, total;
+        imp_cnt, skip, skip_act, total;
 };
 
 int64_t series_cap(const tete_grid_desc* d) { return d->max_series > 0 ? d->max_series : 4096; }
@@ -58,10 +58,11 @@ bool make_layout(const tete_grid_desc* d, Layout* L)
         L->imp_lh = o;  o = up(o + sizeof(int) * (size_t)np);
         L->imp_cnt = o; o = up(o + sizeof(int) * 2 * (size_t)implicit_list_chunks(np));
     }
-    L->skip = 0;
-    if (d->flags & TETE_F_SKIP_STATIC) {   // static-tile table of the two-step kernel
+    L->skip = L->skip_act = 0;
+    if (d->flags & TETE_F_SKIP_STATIC) {   // static-tile table and active-tile list of the two-step kernel
         Geo g = {d->nx, d->ny, d->nz, d->nz + 1, (d->ny + 1) * (d->nz + 1), (int)np};
-        L->skip = o; o = up(o + (size_t)fused2_tile_cap(g));
+        L->skip = o;     o = up(o + (size_t)fused2_tile_cap(g));
+        L->skip_act = o; o = up(o + sizeof(int) * (size_t)fused2_tile_cap(g));
     }
     L->total = o;
     return true;
@@ -102,14 +103,16 @@ struct tete_grid {
     uint8_t* code;
     void* mat[6];
     int mat_set;
-    // static-tile skip (TETE_F_SKIP_STATIC): the table for the tiling
-    // (skip_rows, skip_xc), skip_rows = -1 while none is built for the
-    // current codes; skip_live is set once a launch has written the other
-    // field set since the fields or codes were last set, so that both sets
-    // agree on every static tile
+    // static-tile skip (TETE_F_SKIP_STATIC): the table and the list of the
+    // skip_nact active tiles for the tiling (skip_rows, skip_xc, skip_order),
+    // skip_rows = -1 while none is built for the current codes; skip_live is
+    // set once a launch has written the other field set since the fields or
+    // codes were last set, so that both sets agree on every static tile
     int skip;
     uint8_t* skip_tab;
-    int skip_rows, skip_xc;
+    int* skip_act;
+    int skip_rows, skip_xc, skip_order, skip_nact;
+    int64_t skip_nt;
     int skip_live;
     double *lam, *wacc, *partial, *scal, *eser, *pser;
     double* wit;       // witness accumulators, TETE_WITNESS_LINES x TETE_MAX_WAKE
@@ -237,6 +240,14 @@ int fused2_rows(const tete_grid* g)
     return r == 16 || (r == 32 && g->fp32) ? r : 0;
 }
 
+// X-chunk of the two-step kernel: the tuning's, else for grids that skip
+// static tiles chunks of 32 planes (short chunks find more tiles wholly in
+// the metal, at seven halo planes per chunk), else the library's choice (0).
+int fused2_xchunk(const tete_grid* g)
+{
+    return g->tune.xchunk != 0 ? g->tune.xchunk : g->skip ? 32 : 0;
+}
+
 bool use_fused2(const tete_grid* g)
 {
     const bool want = g->tune.kernel == TETE_KERNEL_FUSED2 || g->tune.kernel == TETE_KERNEL_AUTO;
@@ -248,12 +259,13 @@ bool use_fused2(const tete_grid* g)
 template <typename R>
 tete_status static_table(tete_grid* g)
 {
-    const int rows = fused2_rows(g), xc = g->tune.xchunk;
-    if (g->skip_rows == rows && g->skip_xc == xc) return TETE_OK;
-    int64_t nt = 0;
-    HIPCHK(fused2_static_tiles<R>(g->code, g->geo, rows, xc, g->skip_tab, fused2_tile_cap(g->geo), &nt, g->stream));
+    const int rows = fused2_rows(g), xc = fused2_xchunk(g), order = g->tune.order;
+    if (g->skip_rows == rows && g->skip_xc == xc && g->skip_order == order) return TETE_OK;
+    HIPCHK(fused2_static_tiles<R>(g->code, g->geo, rows, xc, order, g->skip_tab, g->skip_act, fused2_tile_cap(g->geo),
+                                  &g->skip_nt, &g->skip_nact, g->stream));
     g->skip_rows = rows;
     g->skip_xc = xc;
+    g->skip_order = order;
     return TETE_OK;
 }
 
@@ -292,14 +304,14 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
         if (pair) {
             WitMid<R> wm;
             if (wit) wm = witness_mid<R>(g);
-            const uint8_t* skip = nullptr;
+            const int* act = nullptr;
             if (g->skip && !wit && g->skip_live) {
                 if (static_table<R>(g) != TETE_OK) return TETE_ERR_DEVICE;
-                skip = g->skip_tab;
+                act = g->skip_act;
             }
             HIPCHK(launch_step_fused2<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
-                                         source(g, g->n), wit ? &wm : nullptr, fused2_rows(g), g->tune.xchunk,
-                                         g->tune.order, g->stream, ev, skip));
+                                         source(g, g->n), wit ? &wm : nullptr, fused2_rows(g), fused2_xchunk(g),
+                                         g->tune.order, g->stream, ev, act, g->skip_nact));
             g->skip_live = 1;
             if (wit)   // e_z^{n-1/2} in the old set, e_z^{n+1/2} in wm.mid, e_z^{n+3/2} in the new set
                 HIPCHK(launch_witness2<R>((const R*)g->f[g->cur][2], wm.mid, (const R*)g->f[1 - g->cur][2],
@@ -450,8 +462,10 @@ tete_status tete_grid_create(const tete_grid_desc* d, void* dev_ws, size_t ws_by
     g->code = (uint8_t*)(g->ws + L.code);
     g->skip = (d->flags & TETE_F_SKIP_STATIC) != 0;
     g->skip_tab = g->skip ? (uint8_t*)(g->ws + L.skip) : nullptr;
+    g->skip_act = g->skip ? (int*)(g->ws + L.skip_act) : nullptr;
     g->skip_rows = -1;
-    g->skip_xc = 0;
+    g->skip_xc = g->skip_order = g->skip_nact = 0;
+    g->skip_nt = 0;
     g->skip_live = 0;
     for (int c = 0; c < 6; ++c) g->mat[c] = (d->flags & TETE_F_MATERIALS) ? g->ws + L.mat[c] : nullptr;
     g->lam = (double*)(g->ws + L.lam);
@@ -629,16 +643,8 @@ tete_status tete_static_tiles(tete_grid* g, int64_t* skipped, int64_t* total)
     if (!dg.ok) return TETE_ERR_DEVICE;
     tete_status st = g->fp32 ? static_table<float>(g) : static_table<double>(g);
     if (st != TETE_OK) return st;
-    int64_t nt = 0;
-    HIPCHK(g->fp32 ? fused2_tile_count<float>(g->geo, g->skip_rows, g->skip_xc, &nt)
-                   : fused2_tile_count<double>(g->geo, g->skip_rows, g->skip_xc, &nt));
-    std::vector<uint8_t> t((size_t)nt);
-    HIPCHK(hipStreamSynchronize(g->stream));
-    if (nt > 0) HIPCHK(hipMemcpy(t.data(), g->skip_tab, (size_t)nt, hipMemcpyDeviceToHost));
-    int64_t c = 0;
-    for (uint8_t v : t) c += v;
-    *skipped = c;
-    *total = nt;
+    *skipped = g->skip_nt - g->skip_nact;
+    *total = g->skip_nt;
     return TETE_OK;
 }
 

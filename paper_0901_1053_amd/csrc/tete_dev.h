@@ -103,7 +103,7 @@ inline int default_order(int nyt, int nzt, int nxc)
     const bool fill = nzt >= block_z(4) && nyt >= block_y(4);
     return fill && (int64_t)nyt * nzt * nxc >= 8 * 256 ? 4 : 2;
 }
-__device__ __forceinline__ bool tile_of(int lb, int order, int nyt, int nzt, int& ty, int& tz, int& cx)
+__host__ __device__ __forceinline__ bool tile_of(int lb, int order, int nyt, int nzt, int& ty, int& tz, int& cx)
 {
     if (order == 2) {
         tz = lb % nzt;

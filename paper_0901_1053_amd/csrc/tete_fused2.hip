@@ -38,6 +38,7 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <vector>
 
 #include "tete_dev.h"
 
@@ -420,16 +421,24 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
     }
 }
 
-// skip (or null): one byte per tile (cx, ty, tz), set where the tile is
-// static (fused2_static_tiles): the whole workgroup returns at once.
+// act (or null): the tiles that are not static, (cx nyt + ty) nzt + tz in
+// the launch's tile order (fused2_static_tiles), one workgroup each.  The
+// XCD remap over the list spreads them evenly over the XCDs, while the
+// static tiles, which lie together in the metal, are not launched at all.
 template <typename R, int TYH, int LW>
-__global__ __launch_bounds__(TYH * LW) void k_fused2(FArgs<R> A, const uint8_t* skip)
+__global__ __launch_bounds__(TYH * LW) void k_fused2(FArgs<R> A, const int* act)
 {
     typedef Shape2<R, TYH, LW> S;
     __shared__ Lds2<R, S::rows, S::nb, S::lw> L;
     int ty, tz, cx;
-    if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) return;   // whole group
-    if (skip && skip[((int64_t)cx * A.nyt + ty) * A.nzt + tz]) return;
+    if (act) {
+        const int t = act[xcd_remap(blockIdx.x, gridDim.x)];
+        tz = t % A.nzt;
+        ty = (t / A.nzt) % A.nyt;
+        cx = t / (A.nzt * A.nyt);
+    } else if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) {
+        return;   // whole group
+    }
     fused2_tile<R, S::rows, S::nb, S::lw>(A, ty, tz, cx, L);
 }
 
@@ -576,38 +585,55 @@ int64_t fused2_tile_cap(Geo g)
 }
 
 template <typename R>
-hipError_t fused2_tile_count(Geo g, int rows, int xchunk, int64_t* ntiles)
-{
-    FArgs<R> A = fused_args<R>(Fields<R>{}, Fields<R>{}, Mat<R>{}, g, R(0), Src{});
-    if (!fused2_setup<R>(A, rows, xchunk, 1)) return hipErrorInvalidValue;
-    *ntiles = (int64_t)A.nyt * A.nzt * A.nxc;
-    return hipSuccess;
-}
-
-template <typename R>
-hipError_t fused2_static_tiles(const uint8_t* code, Geo g, int rows, int xchunk, uint8_t* out, int64_t cap,
-                               int64_t* ntiles, hipStream_t s)
+hipError_t fused2_static_tiles(const uint8_t* code, Geo g, int rows, int xchunk, int order, uint8_t* tab, int* act,
+                               int64_t cap, int64_t* ntiles, int* nact, hipStream_t s)
 {
     Fields<R> none = {};
     Mat<R> M = {};
     M.code = code;
     FArgs<R> A = fused_args<R>(none, none, M, g, R(0), Src{});
-    if (!fused2_setup<R>(A, rows, xchunk, 1)) return hipErrorInvalidValue;
+    if (!fused2_setup<R>(A, rows, xchunk, order)) return hipErrorInvalidValue;
     const int64_t nt = (int64_t)A.nyt * A.nzt * A.nxc;
     if (nt > cap || nt > 0x7fffffff) return hipErrorInvalidValue;
     const int r = rows == 0 ? Default2<R>::rows : rows;
     const int lw = lanes2(sizeof(R), r);
-    k_static2<<<(int)nt, 256, 0, s>>>(code, g, r, lw, r - 6, lw - 4, A.xchunk, A.nyt, A.nzt, out);
+    k_static2<<<(int)nt, 256, 0, s>>>(code, g, r, lw, r - 6, lw - 4, A.xchunk, A.nyt, A.nzt, tab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    std::vector<uint8_t> h((size_t)nt);
+    if ((e = hipMemcpyAsync(h.data(), tab, (size_t)nt, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    // the active tiles in the order the full launch takes them
+    std::vector<int> list;
+    list.reserve((size_t)nt);
+    for (int lb = 0; lb < A.nblk; ++lb) {
+        int ty, tz, cx;
+        if (!tile_of(lb, A.order, A.nyt, A.nzt, ty, tz, cx)) continue;
+        const int t = (cx * A.nyt + ty) * A.nzt + tz;
+        if (!h[(size_t)t]) list.push_back(t);
+    }
+    if (!list.empty()) {
+        if ((e = hipMemcpyAsync(act, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;   // list is a host temporary
+    }
     *ntiles = nt;
-    return hipGetLastError();
+    *nact = (int)list.size();
+    return hipSuccess;
 }
 
 template <typename R>
 hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha, Src src, const WitMid<R>* wm,
-                              int rows, int xchunk, int order, hipStream_t s, hipEvent_t* ev, const uint8_t* skip)
+                              int rows, int xchunk, int order, hipStream_t s, hipEvent_t* ev, const int* act,
+                              int nact)
 {
     FArgs<R> A = fused_args<R>(o, nf, M, g, alpha, src);
     if (wm) rows = 0;   // the instance that keeps witness lines has the default shape only
+    if (wm) act = nullptr;
+    // with a list of active tiles, one workgroup per entry (none: every tile is
+    // static and the new set already holds the result)
+    const int grid = act ? nact : 0;
     if (!fused2_setup<R>(A, rows, xchunk, order)) return hipErrorInvalidValue;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
@@ -620,12 +646,14 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
     }
     if constexpr (sizeof(R) == 4) {
         if (!done && rows == 32) {
-            k_fused2<R, 32, 32><<<A.nblk, 32 * 32, 0, s>>>(A, skip);
+            if (!act) k_fused2<R, 32, 32><<<A.nblk, 32 * 32, 0, s>>>(A, nullptr);
+            else if (grid > 0) k_fused2<R, 32, 32><<<grid, 32 * 32, 0, s>>>(A, act);
             done = true;
         }
     }
-    if (!done)
-        k_fused2<R, Default2<R>::rows, Default2<R>::lw><<<A.nblk, Default2<R>::rows * Default2<R>::lw, 0, s>>>(A, skip);
+    constexpr int T2 = Default2<R>::rows * Default2<R>::lw;
+    if (!done && !act) k_fused2<R, Default2<R>::rows, Default2<R>::lw><<<A.nblk, T2, 0, s>>>(A, nullptr);
+    else if (!done && grid > 0) k_fused2<R, Default2<R>::rows, Default2<R>::lw><<<grid, T2, 0, s>>>(A, act);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
@@ -636,10 +664,9 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
     template hipError_t launch_batch_step2<R>(BatchTable<R>*, int, int, int, hipStream_t);                     \
     template bool fused2_setup<R>(FArgs<R>&, int, int, int);                                                   \
     template hipError_t launch_step_fused2<R>(Fields<R>, Fields<R>, Mat<R>, Geo, R, Src, const WitMid<R>*, int, \
-                                              int, int, hipStream_t, hipEvent_t*, const uint8_t*);           \
-    template hipError_t fused2_static_tiles<R>(const uint8_t*, Geo, int, int, uint8_t*, int64_t, int64_t*,     \
-                                               hipStream_t);                                                   \
-    template hipError_t fused2_tile_count<R>(Geo, int, int, int64_t*);
+                                              int, int, hipStream_t, hipEvent_t*, const int*, int);          \
+    template hipError_t fused2_static_tiles<R>(const uint8_t*, Geo, int, int, int, uint8_t*, int*, int64_t,    \
+                                               int64_t*, int*, hipStream_t);
 TETE_FUSED2_INST(float)
 TETE_FUSED2_INST(double)
 

@@ -143,22 +143,22 @@ bool fused2_fits(Geo g, int real_bytes);
 template <typename R>
 bool fused2_setup(FArgs<R>& A, int rows, int xchunk, int order);
 // wm (or nullptr): the witness lines whose e_z^{n+1/2} the launch keeps;
-// skip (or nullptr): the static-tile table of fused2_static_tiles for the same
-// rows and xchunk, whose tiles the launch leaves out
+// act (or nullptr): the nact active tiles of fused2_static_tiles for the same
+// rows, xchunk and order; the launch takes only these (none if nact is 0)
 template <typename R>
 hipError_t launch_step_fused2(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src,
                               const WitMid<R>* wm, int rows, int xchunk, int order, hipStream_t s, hipEvent_t* ev,
-                              const uint8_t* skip);
-// One byte per tile of the two-step kernel's tiling (rows, xchunk): 1 where
-// every entry the tile loads has its three e edges PEC, so that a step leaves
-// the tile's entries unchanged.  *ntiles = tiles (at most cap).
-template <typename R>
-hipError_t fused2_tile_count(Geo g, int rows, int xchunk, int64_t* ntiles);
+                              const int* act, int nact);
+// One byte per tile of the two-step kernel's tiling (rows, xchunk) in tab: 1
+// where every entry the tile loads has its three e edges PEC, so that a step
+// leaves the tile's entries unchanged; and in act the *nact other tiles in the
+// launch order of the tile order `order`.  *ntiles = tiles (at most cap; act
+// holds cap ints).  Synchronises the stream.
 // Bytes a static-tile table needs at most, over every tiling.
 int64_t fused2_tile_cap(Geo g);
 template <typename R>
-hipError_t fused2_static_tiles(const uint8_t* code, Geo g, int rows, int xchunk, uint8_t* out, int64_t cap,
-                               int64_t* ntiles, hipStream_t s);
+hipError_t fused2_static_tiles(const uint8_t* code, Geo g, int rows, int xchunk, int order, uint8_t* tab, int* act,
+                               int64_t cap, int64_t* ntiles, int* nact, hipStream_t s);
 // One step of Yee's scheme (7) (tete_yee.hip): state (e^{n-1/2}, h^n),
 // dtau = 2 alpha; xchunk and order as for the fused step.
 bool yee_fits(Geo g, int real_bytes);

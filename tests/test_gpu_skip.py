@@ -29,11 +29,11 @@ def _pipe_cells(nx, ny, nz, r_cells, seed=0):
     return (cells | extra.astype(bool)).astype(np.uint8)
 
 
-def _grid(shape, precision, skip, cells, fields_seed, xchunk=0, rows=0):
+def _grid(shape, precision, skip, cells, fields_seed, xchunk=0, rows=0, order=0):
     nx, ny, nz = shape
     G = tete.Grid(nx, ny, nz, 2 * DZ, 2 * DZ, DZ, DZ, precision=precision, skip_static=skip)
-    if xchunk or rows:
-        G.set_tuning("fused2", rows, xchunk)
+    if xchunk or rows or order:
+        G.set_tuning("fused2", rows, xchunk, 0, order)
     G.set_pec_cells(cells)
     G.set_fields(inputs.random_fields(G.shape, fields_seed))
     G.set_bunch(1e-9, 2e-3, nx // 2, JC, 10, -14, 40)
@@ -51,16 +51,18 @@ SHAPE = (40, 61, 150)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-@pytest.mark.parametrize("xchunk,rows", [(0, 0), (8, 0), (5, 16), (11, 32)])
-def test_skip_matches_full(precision, xchunk, rows):
+@pytest.mark.parametrize("xchunk,rows,order", [(0, 0, 0), (8, 0, 0), (5, 16, 2), (11, 32, 1), (7, 0, 4),
+                                               (3, 0, 6)])
+def test_skip_matches_full(precision, xchunk, rows, order):
     """15 steps (seven two-step launches and one single step) with a bunch:
-    the same fields and wake as the grid without the skip."""
+    the same fields and wake as the grid without the skip, over tilings and
+    tile orders."""
     if rows == 32 and precision == "fp64":
         pytest.skip("32-row tiles are FP32 only")
-    print("skip", precision, xchunk, rows, flush=True)
+    print("skip", precision, xchunk, rows, order, flush=True)
     cells = _pipe_cells(*SHAPE, 6, seed=81)
-    A = _grid(SHAPE, precision, True, cells, 82, xchunk, rows)
-    B = _grid(SHAPE, precision, False, cells, 82, xchunk, rows)
+    A = _grid(SHAPE, precision, True, cells, 82, xchunk, rows, order)
+    B = _grid(SHAPE, precision, False, cells, 82, xchunk, rows, order)
     A.step(15)
     B.step(15)
     assert A.get_tuning()["kernel"] in ("fused2", "auto")
@@ -183,3 +185,18 @@ def test_skip_large_case_samples():
     for k in tete.KEYS:
         assert torch.equal(fa[k], fb[k]), k
     assert np.array_equal(wa, wb)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_skip_all_static(precision):
+    """Every cell metal: once both sets agree no workgroup is launched, and
+    the fields (random h, zero e) stay those of the grid without the skip."""
+    print("skip all static", precision, flush=True)
+    cells = np.ones(SHAPE, np.uint8)
+    A = _grid(SHAPE, precision, True, cells, 92, xchunk=9)
+    B = _grid(SHAPE, precision, False, cells, 92, xchunk=9)
+    A.step(10)
+    B.step(10)
+    n = A.static_tiles()
+    assert n[0] == n[1] > 0
+    _same(A, B)
