@@ -266,7 +266,7 @@ def materials_section(case, precision, explicit_ms_per_step, steps=6):
             "vs_vacuum_two_step": round(out["fused"] / explicit_ms_per_step, 2) if explicit_ms_per_step else None}
 
 
-def skip_section(case, precision, explicit_ms_per_step, steps=8, xchunks=(0, 257, 128, 64, 16)):
+def skip_section(case, precision, explicit_ms_per_step, witness_ms=None, steps=8, xchunks=(0, 257, 128, 64, 16)):
     """The two-step kernel leaving out tiles that lie wholly in PEC
     (skip_static) on the large workload, for the default x-chunk of such grids
     (32 planes), the full step's (257) and a few others (short chunks find
@@ -293,10 +293,17 @@ def skip_section(case, precision, explicit_ms_per_step, steps=8, xchunks=(0, 257
         rows.append({"xchunk": xc or "default (32)", "tiles": tot, "static_tiles": sk,
                      "ms_per_step": round(ms, 3),
                      "speedup_vs_full_step": round(explicit_ms_per_step / ms, 2) if explicit_ms_per_step else None})
+    # the same grid with the witness node of the witness timing (32 cells off
+    # the bunch line in x), default x-chunk: whole launches with the line kernel
+    G.set_tuning("fused2", 0, 0)
+    wit = witness_section(G, case, explicit_ms_per_step, steps=steps)
     G.close()
     del G
     torch.cuda.empty_cache()
-    return {"workload": case.name, "precision": precision, "runs": rows}
+    return {"workload": case.name, "precision": precision, "runs": rows,
+            "witness": {"offset_cells": wit["witness_offset_cells"], "ms_per_step": wit["ms_per_step"],
+                        "speedup_vs_full_step_with_witness":
+                            round(witness_ms / wit["ms_per_step"], 2) if witness_ms else None}}
 
 
 def implicit_section(case, precision, explicit_ms_per_step, steps=4):
@@ -519,7 +526,8 @@ def main():
         torch.cuda.empty_cache()
         print("# materials timing done", file=sys.stderr, flush=True)
     if not args.no_skip:
-        out["skip_static_context"] = skip_section(case, args.precision, ms_step)
+        out["skip_static_context"] = skip_section(case, args.precision, ms_step,
+                                                  out.get("witness_context", {}).get("ms_per_step"))
         torch.cuda.empty_cache()
         print("# static-tile skip timing done", file=sys.stderr, flush=True)
 

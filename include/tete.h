@@ -80,7 +80,7 @@ enum {
                                  * equal those of a grid without the flag.  Tiles are left out
                                  * only once both ping-pong sets agree (from the second
                                  * launch after tete_set_fields or tete_set_pec_cells),
-                                 * not while a witness is set, and not in single steps.
+                                 * and not in single steps.
                                  * The two-step launches take only the other tiles; with
                                  * tuning x-chunk 0 such grids use chunks of 32 planes.
                                  * Vacuum with staircase PEC only (not with

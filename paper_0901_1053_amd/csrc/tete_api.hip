@@ -257,9 +257,10 @@ bool use_fused2(const tete_grid* g)
 // Builds the static-tile table for the current tiling of the two-step
 // kernel unless it is already there.
 template <typename R>
-tete_status static_table(tete_grid* g)
+tete_status static_table(tete_grid* g, bool wit)
 {
-    const int rows = fused2_rows(g), xc = fused2_xchunk(g), order = g->tune.order;
+    // the instance that keeps witness lines has the default rows only
+    const int rows = wit ? 0 : fused2_rows(g), xc = fused2_xchunk(g), order = g->tune.order;
     if (g->skip_rows == rows && g->skip_xc == xc && g->skip_order == order) return TETE_OK;
     HIPCHK(fused2_static_tiles<R>(g->code, g->geo, rows, xc, order, g->skip_tab, g->skip_act, fused2_tile_cap(g->geo),
                                   &g->skip_nt, &g->skip_nact, g->stream));
@@ -305,9 +306,12 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             WitMid<R> wm;
             if (wit) wm = witness_mid<R>(g);
             const int* act = nullptr;
-            if (g->skip && !wit && g->skip_live) {
-                if (static_table<R>(g) != TETE_OK) return TETE_ERR_DEVICE;
+            if (g->skip && g->skip_live) {
+                if (static_table<R>(g, wit) != TETE_OK) return TETE_ERR_DEVICE;
                 act = g->skip_act;
+                // static tiles store no witness values: their e_z is zero
+                if (wit) HIPCHK(launch_zero_bytes(g->wmid, (g->fp32 ? 4 : 8) * (size_t)TETE_WITNESS_LINES * g->d.nz,
+                                                  g->stream));
             }
             HIPCHK(launch_step_fused2<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                          source(g, g->n), wit ? &wm : nullptr, fused2_rows(g), fused2_xchunk(g),
@@ -641,7 +645,8 @@ tete_status tete_static_tiles(tete_grid* g, int64_t* skipped, int64_t* total)
     if (!g->skip) return TETE_ERR_STATE;
     DeviceGuard dg(g->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
-    tete_status st = g->fp32 ? static_table<float>(g) : static_table<double>(g);
+    const bool wit = g->witness && g->has_bunch;
+    tete_status st = g->fp32 ? static_table<float>(g, wit) : static_table<double>(g, wit);
     if (st != TETE_OK) return st;
     *skipped = g->skip_nt - g->skip_nact;
     *total = g->skip_nt;

@@ -421,24 +421,32 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
     }
 }
 
-// act (or null): the tiles that are not static, (cx nyt + ty) nzt + tz in
-// the launch's tile order (fused2_static_tiles), one workgroup each.  The
-// XCD remap over the list spreads them evenly over the XCDs, while the
-// static tiles, which lie together in the metal, are not launched at all.
+// Tile of workgroup blockIdx.x.  act (or null): the tiles that are not
+// static, (cx nyt + ty) nzt + tz in the launch's tile order
+// (fused2_static_tiles), one workgroup each; the XCD remap over the list
+// spreads them evenly over the XCDs, while the static tiles, which lie
+// together in the metal, are not launched at all.  False for the padding
+// workgroups of a full launch.
+template <typename R>
+__device__ __forceinline__ bool fused2_tile_of(const FArgs<R>& A, const int* act, int& ty, int& tz, int& cx)
+{
+    if (act) {
+        const int t = act[xcd_remap(blockIdx.x, gridDim.x)];
+        tz = t % A.nzt;
+        ty = (t / A.nzt) % A.nyt;
+        cx = t / (A.nzt * A.nyt);
+        return true;
+    }
+    return tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx);
+}
+
 template <typename R, int TYH, int LW>
 __global__ __launch_bounds__(TYH * LW) void k_fused2(FArgs<R> A, const int* act)
 {
     typedef Shape2<R, TYH, LW> S;
     __shared__ Lds2<R, S::rows, S::nb, S::lw> L;
     int ty, tz, cx;
-    if (act) {
-        const int t = act[xcd_remap(blockIdx.x, gridDim.x)];
-        tz = t % A.nzt;
-        ty = (t / A.nzt) % A.nyt;
-        cx = t / (A.nzt * A.nyt);
-    } else if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) {
-        return;   // whole group
-    }
+    if (!fused2_tile_of(A, act, ty, tz, cx)) return;   // whole group
     fused2_tile<R, S::rows, S::nb, S::lw>(A, ty, tz, cx, L);
 }
 
@@ -473,14 +481,16 @@ __global__ __launch_bounds__(256) void k_static2(const uint8_t* code, Geo g, int
     if (threadIdx.x == 0) out[t] = active ? 0 : 1;
 }
 
-// The two-step kernel that also keeps e_z^{n+1/2} of the witness lines.
+// The two-step kernel that also keeps e_z^{n+1/2} of the witness lines
+// (static tiles, when left out, store nothing there: the caller clears the
+// lines, whose e_z is zero in such tiles).
 template <typename R, int TYH, int LW>
-__global__ __launch_bounds__(TYH * LW) void k_fused2_wit(FArgs<R> A, WitMid<R> wm)
+__global__ __launch_bounds__(TYH * LW) void k_fused2_wit(FArgs<R> A, WitMid<R> wm, const int* act)
 {
     typedef Shape2<R, TYH, LW> S;
     __shared__ Lds2<R, S::rows, S::nb, S::lw> L;
     int ty, tz, cx;
-    if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) return;   // whole group
+    if (!fused2_tile_of(A, act, ty, tz, cx)) return;   // whole group
     fused2_tile<R, S::rows, S::nb, S::lw, true>(A, ty, tz, cx, L, wm);
 }
 
@@ -630,7 +640,6 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
 {
     FArgs<R> A = fused_args<R>(o, nf, M, g, alpha, src);
     if (wm) rows = 0;   // the instance that keeps witness lines has the default shape only
-    if (wm) act = nullptr;
     // with a list of active tiles, one workgroup per entry (none: every tile is
     // static and the new set already holds the result)
     const int grid = act ? nact : 0;
@@ -640,8 +649,9 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
     bool done = false;
     if (wm) {
         if (wm->iw < 1 || wm->iw > g.nx - 1 || wm->jw < 1 || wm->jw > g.ny - 1) return hipErrorInvalidValue;
-        k_fused2_wit<R, Default2<R>::rows, Default2<R>::lw>
-            <<<A.nblk, Default2<R>::rows * Default2<R>::lw, 0, s>>>(A, *wm);
+        constexpr int TW = Default2<R>::rows * Default2<R>::lw;
+        if (!act) k_fused2_wit<R, Default2<R>::rows, Default2<R>::lw><<<A.nblk, TW, 0, s>>>(A, *wm, nullptr);
+        else if (grid > 0) k_fused2_wit<R, Default2<R>::rows, Default2<R>::lw><<<grid, TW, 0, s>>>(A, *wm, act);
         done = true;
     }
     if constexpr (sizeof(R) == 4) {

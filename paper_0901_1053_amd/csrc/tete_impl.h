@@ -144,7 +144,8 @@ template <typename R>
 bool fused2_setup(FArgs<R>& A, int rows, int xchunk, int order);
 // wm (or nullptr): the witness lines whose e_z^{n+1/2} the launch keeps;
 // act (or nullptr): the nact active tiles of fused2_static_tiles for the same
-// rows, xchunk and order; the launch takes only these (none if nact is 0)
+// rows (0 with wm), xchunk and order; the launch takes only these (none if
+// nact is 0), and with wm stores witness values only in them
 template <typename R>
 hipError_t launch_step_fused2(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src,
                               const WitMid<R>* wm, int rows, int xchunk, int order, hipStream_t s, hipEvent_t* ev,

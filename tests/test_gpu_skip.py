@@ -96,18 +96,23 @@ def test_skip_history(precision):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_skip_with_witness(precision):
-    """With a witness set the kernel steps every tile: the witness wakes
-    and fields match the grid without the skip."""
+    """Witness lines with the skip, first in the pipe, then moved into the
+    metal block, where they lie in static tiles that store no witness values
+    (the lines must not keep the earlier lines' values): fields and witness
+    wakes match the grid without the skip."""
     print("skip witness", precision, flush=True)
     cells = _pipe_cells(*SHAPE, 6, seed=88)
-    A = _grid(SHAPE, precision, True, cells, 89)
-    B = _grid(SHAPE, precision, False, cells, 89)
-    for G in (A, B):
-        G.set_witness(SHAPE[0] // 2 + 2, JC)
-        G.step(12)
-    _same(A, B)
-    for a, b in zip(A.witness_wake(), B.witness_wake()):
-        assert np.array_equal(a, b)
+    A = _grid(SHAPE, precision, True, cells, 89, xchunk=5)
+    B = _grid(SHAPE, precision, False, cells, 89, xchunk=5)
+    for iw, steps in ((SHAPE[0] // 2 + 2, 12), (SHAPE[0] // 2 + 16, 10)):
+        for G in (A, B):
+            G.set_witness(iw, JC)
+            G.step(steps)
+        _same(A, B)
+        for a, b in zip(A.witness_wake(), B.witness_wake()):
+            assert np.array_equal(a, b), iw
+    assert A.static_tiles()[0] > 0
+    assert np.abs(B.witness_wake()[0]).max() == 0.0   # the second lines lie in the metal
 
 
 def _expected_static(shape, cells, precision, rows, xchunk):
