@@ -83,7 +83,10 @@ enum {
                                  * and not in single steps.
                                  * The two-step launches take only the other tiles; with
                                  * tuning x-chunk 0 such grids use chunks of 32 planes.
-                                 * Vacuum with staircase PEC only (not with
+                                 * The tile list is built, and the stream synchronised,
+                                 * at the first such launch after the codes or the
+                                 * tiling (rows, x-chunk, order; witness set or not)
+                                 * change.  Vacuum with staircase PEC only (not with
                                  * TETE_F_MATERIALS, TETE_F_YEE, TETE_F_IMPLICIT). */
     TETE_F_IMPLICIT = 1u << 2   /* step with the implicit TE/TM scheme (16) of Sec. 4.1
                                  * instead of (23): a comparator.  Each half step solves
