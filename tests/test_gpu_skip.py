@@ -205,3 +205,26 @@ def test_skip_all_static(precision):
     n = A.static_tiles()
     assert n[0] == n[1] > 0
     _same(A, B)
+
+
+def test_skip_large_full_run():
+    """The large tapered collimator run until the bunch has left the grid
+    (2243 steps, FP32, wake window around the bunch) with and without the
+    skip: the same wake and field energy, bitwise."""
+    from tests import parity as P
+    case = inputs.large_case()
+    M = case.M
+    jmin, jmax = -M - 8, M + 8
+    nw = jmax - jmin + 1
+    steps = case.nz + M + jmax + 1
+    out = []
+    for skip in (True, False):
+        print("skip large full run", skip, steps, flush=True)
+        G = P.gpu_grid(case, "fp32", skip_static=skip)
+        G.set_bunch(case.Q, case.sigma, case.i0, case.j0, M, jmin, nw)
+        G.step(steps)
+        out.append((G.wake(), G.energy()[0]))
+        G.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+    assert np.any(out[0][0] != 0.0)
