@@ -228,3 +228,23 @@ def test_skip_large_full_run():
     assert np.array_equal(out[0][0], out[1][0])
     assert out[0][1] == out[1][1]
     assert np.any(out[0][0] != 0.0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_skip_grid_in_batch(precision):
+    """A skip grid stepped alone, then in a batch (which steps every tile),
+    then alone again matches a grid without the skip given the same calls."""
+    print("skip batch", precision, flush=True)
+    cells = _pipe_cells(*SHAPE, 6, seed=93)
+    grids = []
+    for skip in (True, False):
+        G = _grid(SHAPE, precision, skip, cells, 94, xchunk=6)
+        G.step(6)
+        B = tete.Batch(precision)
+        B.set(0, G)
+        B.step(7)
+        B.close()
+        G.step(8)
+        grids.append(G)
+    assert grids[0].steps_done() == 21
+    _same(*grids)
