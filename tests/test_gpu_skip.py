@@ -248,3 +248,27 @@ def test_skip_grid_in_batch(precision):
         grids.append(G)
     assert grids[0].steps_done() == 21
     _same(*grids)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_skip_matches_oracle(precision):
+    """The skip grid against the oracle directly: 15 steps with a bunch on
+    the mostly-metal grid, fields within 1e-12 (FP64) / 2e-5 (FP32) and the
+    wake within the paper's delta norm 1e-12 / 1e-5."""
+    from tests import parity as P
+    print("skip oracle", precision, flush=True)
+    nx, ny, nz = SHAPE
+    cells = _pipe_cells(*SHAPE, 6, seed=95)
+    g = O.Geom(nx, ny, nz, 2 * DZ, 2 * DZ, DZ, DZ)
+    m = O.vacuum_materials(g, cells)
+    f = inputs.random_fields(g.shape, 96)
+    O.apply_pec(g, m, f)
+    b = O.Bunch(Q=1e-9, sigma=2e-3, i0=nx // 2, j0=JC, M=10, jmin=-14, nw=40)
+    r = O.run(g, m, f, 15, bunch=b)
+    W = r["acc"] / (b.Q * P.EPS0)
+    G = _grid(SHAPE, precision, True, cells, 96)
+    G.step(15)
+    assert G.static_tiles()[0] > 0
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    assert P.field_rel_err(G.get_fields(), f) <= tol
+    assert P.delta_norm(G.wake(), W) <= (1e-12 if precision == "fp64" else 1e-5)
