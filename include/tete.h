@@ -86,8 +86,12 @@ enum {
                                  * The tile list is built, and the stream synchronised,
                                  * at the first such launch after the codes or the
                                  * tiling (rows, x-chunk, order; witness set or not)
-                                 * change.  Vacuum with staircase PEC only (not with
-                                 * TETE_F_MATERIALS, TETE_F_YEE, TETE_F_IMPLICIT). */
+                                 * change.  With TETE_F_MATERIALS, once materials are
+                                 * set, the fused single step leaves out the tiles
+                                 * whose kappa is zero on every e edge they load, by
+                                 * the same rules (the list is rebuilt after
+                                 * tete_set_materials).  Not with TETE_F_YEE or
+                                 * TETE_F_IMPLICIT. */
     TETE_F_IMPLICIT = 1u << 2   /* step with the implicit TE/TM scheme (16) of Sec. 4.1
                                  * instead of (23): a comparator.  Each half step solves
                                  * (I - alpha T_i) x = rhs; per z-plane this is one

@@ -28,6 +28,9 @@ struct Layout {
 
 int64_t series_cap(const tete_grid_desc* d) { return d->max_series > 0 ? d->max_series : 4096; }
 
+// Tiles of the finest tiling of the two-step kernel and of the materials step.
+int64_t skip_cap(Geo g) { return std::max(fused2_tile_cap(g), fused_tile_cap(g)); }
+
 bool make_layout(const tete_grid_desc* d, Layout* L)
 {
     const int64_t np = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
@@ -59,10 +62,11 @@ bool make_layout(const tete_grid_desc* d, Layout* L)
         L->imp_cnt = o; o = up(o + sizeof(int) * 2 * (size_t)implicit_list_chunks(np));
     }
     L->skip = L->skip_act = 0;
-    if (d->flags & TETE_F_SKIP_STATIC) {   // static-tile table and active-tile list of the two-step kernel
+    if (d->flags & TETE_F_SKIP_STATIC) {   // static-tile table and active-tile list
         Geo g = {d->nx, d->ny, d->nz, d->nz + 1, (d->ny + 1) * (d->nz + 1), (int)np};
-        L->skip = o;     o = up(o + (size_t)fused2_tile_cap(g));
-        L->skip_act = o; o = up(o + sizeof(int) * (size_t)fused2_tile_cap(g));
+        const int64_t cap = skip_cap(g);
+        L->skip = o;     o = up(o + (size_t)cap);
+        L->skip_act = o; o = up(o + sizeof(int) * (size_t)cap);
     }
     L->total = o;
     return true;
@@ -111,7 +115,7 @@ struct tete_grid {
     int skip;
     uint8_t* skip_tab;
     int* skip_act;
-    int skip_rows, skip_xc, skip_order, skip_nact;
+    int skip_kind, skip_rows, skip_xc, skip_order, skip_nact;   // kind 0: two-step, 1: materials
     int64_t skip_nt;
     int skip_live;
     double *lam, *wacc, *partial, *scal, *eser, *pser;
@@ -259,11 +263,24 @@ bool use_fused2(const tete_grid* g)
 template <typename R>
 tete_status static_table(tete_grid* g, bool wit)
 {
+    if (g->mat_set) {   // the materials step's tiling; kappa marks the PEC edges
+        const int xc = g->tune.xchunk, order = g->tune.order;
+        if (g->skip_kind == 1 && g->skip_rows == 0 && g->skip_xc == xc && g->skip_order == order) return TETE_OK;
+        const R* kap[3] = {(const R*)g->mat[0], (const R*)g->mat[1], (const R*)g->mat[2]};
+        HIPCHK(fused_mat_static_tiles<R>(kap, g->geo, xc, order, g->skip_tab, g->skip_act, skip_cap(g->geo),
+                                         &g->skip_nt, &g->skip_nact, g->stream));
+        g->skip_kind = 1;
+        g->skip_rows = 0;
+        g->skip_xc = xc;
+        g->skip_order = order;
+        return TETE_OK;
+    }
     // the instance that keeps witness lines has the default rows only
     const int rows = wit ? 0 : fused2_rows(g), xc = fused2_xchunk(g), order = g->tune.order;
-    if (g->skip_rows == rows && g->skip_xc == xc && g->skip_order == order) return TETE_OK;
-    HIPCHK(fused2_static_tiles<R>(g->code, g->geo, rows, xc, order, g->skip_tab, g->skip_act, fused2_tile_cap(g->geo),
+    if (g->skip_kind == 0 && g->skip_rows == rows && g->skip_xc == xc && g->skip_order == order) return TETE_OK;
+    HIPCHK(fused2_static_tiles<R>(g->code, g->geo, rows, xc, order, g->skip_tab, g->skip_act, skip_cap(g->geo),
                                   &g->skip_nt, &g->skip_nact, g->stream));
+    g->skip_kind = 0;
     g->skip_rows = rows;
     g->skip_xc = xc;
     g->skip_order = order;
@@ -337,10 +354,16 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
         else if (g->yee)
             HIPCHK(launch_step_yee<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                       g->tune.xchunk, g->tune.order, g->stream, ev));
-        else if (use_fused(g))
+        else if (use_fused(g)) {
+            const int* act = nullptr;   // static tiles: materials step only
+            if (g->skip && g->mat_set && g->skip_live) {
+                if (static_table<R>(g, false) != TETE_OK) return TETE_ERR_DEVICE;
+                act = g->skip_act;
+            }
             HIPCHK(launch_step_fused<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                         source(g, g->n), g->tune.rows == 32 ? 0 : g->tune.rows, g->tune.xchunk,
-                                        g->tune.depth, g->tune.order, g->stream, ev));
+                                        g->tune.depth, g->tune.order, g->stream, ev, act, g->skip_nact));
+        }
         else
             HIPCHK(launch_step<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                   source(g, g->n), g->stream, ev));
@@ -397,8 +420,7 @@ tete_status tete_check_desc(const tete_grid_desc* d)
     if (d->precision != TETE_FP64 && d->precision != TETE_FP32) return TETE_ERR_ARG;
     if (d->flags & ~(uint32_t)(TETE_F_MATERIALS | TETE_F_YEE | TETE_F_IMPLICIT | TETE_F_SKIP_STATIC))
         return TETE_ERR_ARG;
-    if ((d->flags & TETE_F_SKIP_STATIC) && (d->flags & (TETE_F_MATERIALS | TETE_F_YEE | TETE_F_IMPLICIT)))
-        return TETE_ERR_ARG;
+    if ((d->flags & TETE_F_SKIP_STATIC) && (d->flags & (TETE_F_YEE | TETE_F_IMPLICIT))) return TETE_ERR_ARG;
     if ((d->flags & TETE_F_YEE) && (d->flags & TETE_F_MATERIALS)) return TETE_ERR_ARG;
     if ((d->flags & TETE_F_IMPLICIT) && (d->flags & (TETE_F_MATERIALS | TETE_F_YEE))) return TETE_ERR_ARG;
     if (d->max_series < 0 || d->max_series > (1 << 24)) return TETE_ERR_ARG;
@@ -468,7 +490,7 @@ tete_status tete_grid_create(const tete_grid_desc* d, void* dev_ws, size_t ws_by
     g->skip_tab = g->skip ? (uint8_t*)(g->ws + L.skip) : nullptr;
     g->skip_act = g->skip ? (int*)(g->ws + L.skip_act) : nullptr;
     g->skip_rows = -1;
-    g->skip_xc = g->skip_order = g->skip_nact = 0;
+    g->skip_kind = g->skip_xc = g->skip_order = g->skip_nact = 0;
     g->skip_nt = 0;
     g->skip_live = 0;
     for (int c = 0; c < 6; ++c) g->mat[c] = (d->flags & TETE_F_MATERIALS) ? g->ws + L.mat[c] : nullptr;
@@ -614,12 +636,16 @@ tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3], const
         for (int c = 0; c < 6; ++c) dst[c] = (float*)g->mat[c];
         HIPCHK(launch_import_materials<float>(dst, src, dtype == TETE_FP32, g->geo, g->stream));
         g->mat_set = 1;
+        g->skip_rows = -1;
+        g->skip_live = 0;
         HIPCHK(launch_zero_pec<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->stream));
     } else {
         double* dst[6];
         for (int c = 0; c < 6; ++c) dst[c] = (double*)g->mat[c];
         HIPCHK(launch_import_materials<double>(dst, src, dtype == TETE_FP32, g->geo, g->stream));
         g->mat_set = 1;
+        g->skip_rows = -1;
+        g->skip_live = 0;
         HIPCHK(launch_zero_pec<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->stream));
     }
     return TETE_OK;

@@ -23,6 +23,7 @@
 // that are never stored; only the tile's own entries are written.
 
 #include <algorithm>
+#include <vector>
 
 #include "tete_dev.h"
 
@@ -323,14 +324,55 @@ __global__ __launch_bounds__(64 * TYH) void k_fused(FArgs<R> A)
     fused_tile<R, TYH, PD>(A, ty, tz, cx, L);
 }
 
-// The same step with per-entry materials.
+// The same step with per-entry materials.  act (or null): the tiles that are
+// not static, (cx nyt + ty) nzt + tz in the launch's tile order
+// (fused_mat_static_tiles), one workgroup each, remapped over the XCDs.
 template <typename R, int TYH, int PD>
-__global__ __launch_bounds__(64 * TYH) void k_fused_mat(FArgs<R> A, MatA<R> MA)
+__global__ __launch_bounds__(64 * TYH) void k_fused_mat(FArgs<R> A, MatA<R> MA, const int* act)
 {
     __shared__ Lds<R, TYH> L;
     int ty, tz, cx;
-    if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) return;   // whole group
+    if (act) {
+        const int t = act[xcd_remap(blockIdx.x, gridDim.x)];
+        tz = t % A.nzt;
+        ty = (t / A.nzt) % A.nyt;
+        cx = t / (A.nzt * A.nyt);
+    } else if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) {
+        return;   // whole group
+    }
     fused_tile<R, TYH, PD, true>(A, ty, tz, cx, L, MA);
+}
+
+// A tile of the materials step is static when every entry it loads (rows
+// ty TY - 2 .., TYH of them, lanes tz KT - 1 .., 64 of them, planes
+// max(0, xs-2) .. min(xe+1, nx)) has kappa zero on its three e edges (PEC, or
+// outside the component's range): e stays zero and h constant there, and the
+// step leaves every entry the tile owns unchanged.  One workgroup per tile.
+template <typename R>
+__global__ __launch_bounds__(256) void k_static_mat(const R* kx, const R* ky, const R* kz, Geo g, int TYH, int TY,
+                                                    int xchunk, int nyt, int nzt, uint8_t* out)
+{
+    __shared__ int active;
+    const int t = blockIdx.x;
+    const int tz = t % nzt, ty = (t / nzt) % nyt, cx = t / (nzt * nyt);
+    if (threadIdx.x == 0) active = 0;
+    __syncthreads();
+    const int xs = cx * xchunk, xe = min(xs + xchunk, g.nx + 1);
+    const int pb = max(0, xs - 2), pe = min(xe + 1, g.nx);
+    const int64_t per_plane = (int64_t)TYH * 64;
+    const int64_t n = (int64_t)(pe - pb + 1) * per_plane;
+    bool found = false;
+    for (int64_t e = threadIdx.x; e < n && !found; e += blockDim.x) {
+        const int q = pb + (int)(e / per_plane);
+        const int r = (int)(e % per_plane);
+        const int j = ty * TY - 2 + r / 64, k = tz * KT - 1 + r % 64;
+        if (j < 0 || j > g.ny || k < 0 || k > g.nz) continue;
+        const int64_t i = (int64_t)q * g.sp + (int64_t)j * g.sz + k;
+        if (kx[i] != R(0) || ky[i] != R(0) || kz[i] != R(0)) found = true;
+    }
+    if (found) atomicOr(&active, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) out[t] = active ? 0 : 1;
 }
 
 // One step of every active instance of a batch, by a persistent grid: work
@@ -476,9 +518,51 @@ bool fused_fits(Geo g, int real_bytes)
     return (int64_t)g.sp * real_bytes * 5 < (int64_t(1) << 31);
 }
 
+int64_t fused_tile_cap(Geo g)
+{
+    // the smallest owned shape: 8 rows (12-row tiles) by 62 entries over tiles
+    // of single planes
+    return (int64_t)(g.nx + 1) * ((g.ny + 1 + 7) / 8) * ((g.nz + 1 + KT - 1) / KT);
+}
+
+template <typename R>
+hipError_t fused_mat_static_tiles(const R* const kap[3], Geo g, int xchunk, int order, uint8_t* tab, int* act,
+                                  int64_t cap, int64_t* ntiles, int* nact, hipStream_t s)
+{
+    FArgs<R> A = fused_args<R>(Fields<R>{}, Fields<R>{}, Mat<R>{}, g, R(0), Src{});
+    const int rows = fused_default_rows(sizeof(R));   // the materials instance's shape
+    if (!fused_setup<R>(A, rows, xchunk, order)) return hipErrorInvalidValue;
+    const int64_t nt = (int64_t)A.nyt * A.nzt * A.nxc;
+    if (nt > cap || nt > 0x7fffffff) return hipErrorInvalidValue;
+    k_static_mat<R><<<(int)nt, 256, 0, s>>>(kap[0], kap[1], kap[2], g, rows, rows - 4, A.xchunk, A.nyt, A.nzt, tab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    std::vector<uint8_t> h((size_t)nt);
+    if ((e = hipMemcpyAsync(h.data(), tab, (size_t)nt, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    // the active tiles in the order the full launch takes them
+    std::vector<int> list;
+    list.reserve((size_t)nt);
+    for (int lb = 0; lb < A.nblk; ++lb) {
+        int ty, tz, cx;
+        if (!tile_of(lb, A.order, A.nyt, A.nzt, ty, tz, cx)) continue;
+        const int t = (cx * A.nyt + ty) * A.nzt + tz;
+        if (!h[(size_t)t]) list.push_back(t);
+    }
+    if (!list.empty()) {
+        if ((e = hipMemcpyAsync(act, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;   // list is a host temporary
+    }
+    *ntiles = nt;
+    *nact = (int)list.size();
+    return hipSuccess;
+}
+
 template <typename R>
 hipError_t launch_step_fused(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha, Src src, int rows, int xchunk,
-                             int depth, int order, hipStream_t s, hipEvent_t* ev)
+                             int depth, int order, hipStream_t s, hipEvent_t* ev, const int* act, int nact)
 {
     FArgs<R> A = fused_args<R>(o, nf, M, g, alpha, src);
     const bool mat = M.arr[0] != nullptr;   // per-entry materials: one shape, one plane prefetched
@@ -493,7 +577,10 @@ hipError_t launch_step_fused(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha
             MA.m[c] = M.arr[c];
         }
         constexpr int TYH = sizeof(R) == 8 ? 12 : 16;
-        k_fused_mat<R, TYH, 1><<<A.nblk, 64 * TYH, 0, s>>>(A, MA);
+        // with a list of active tiles, one workgroup per entry (none: every
+        // tile is static and the new set already holds the result)
+        if (!act) k_fused_mat<R, TYH, 1><<<A.nblk, 64 * TYH, 0, s>>>(A, MA, nullptr);
+        else if (nact > 0) k_fused_mat<R, TYH, 1><<<nact, 64 * TYH, 0, s>>>(A, MA, act);
         e = hipGetLastError();
     } else if (rows == 12) {
         if (depth == 1) e = launch_fused_t<R, 12, 1>(A, s);
@@ -519,8 +606,12 @@ TETE_FUSED_INST(float)
 TETE_FUSED_INST(double)
 
 template hipError_t launch_step_fused<float>(Fields<float>, Fields<float>, Mat<float>, Geo, float, Src, int, int,
-                                             int, int, hipStream_t, hipEvent_t*);
+                                             int, int, hipStream_t, hipEvent_t*, const int*, int);
 template hipError_t launch_step_fused<double>(Fields<double>, Fields<double>, Mat<double>, Geo, double, Src, int,
-                                              int, int, int, hipStream_t, hipEvent_t*);
+                                              int, int, int, hipStream_t, hipEvent_t*, const int*, int);
+template hipError_t fused_mat_static_tiles<float>(const float* const[3], Geo, int, int, uint8_t*, int*, int64_t,
+                                                  int64_t*, int*, hipStream_t);
+template hipError_t fused_mat_static_tiles<double>(const double* const[3], Geo, int, int, uint8_t*, int*, int64_t,
+                                                   int64_t*, int*, hipStream_t);
 
 }  // namespace tete

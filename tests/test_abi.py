@@ -58,9 +58,10 @@ def test_descriptor_limits():
     d = tete.make_desc(8, 8, 8, 2, 2, 1, 1)
     d.flags = 16                                           # no such flag
     assert tete.check_desc(d) == "TETE_ERR_ARG"
-    for kw in ({"materials": True}, {"yee": True}, {"implicit": True}):   # the skip is for vacuum + PEC
+    for kw in ({"yee": True}, {"implicit": True}):   # the skip is for the explicit TE/TM kernels
         assert tete.check_desc(tete.make_desc(8, 8, 8, 2, 2, 1, 0.5, skip_static=True, **kw)) == "TETE_ERR_ARG"
     assert tete.check_desc(tete.make_desc(8, 8, 8, 2, 2, 1, 1, skip_static=True)) == "TETE_OK"
+    assert tete.check_desc(tete.make_desc(8, 8, 8, 2, 2, 1, 1, materials=True, skip_static=True)) == "TETE_OK"
     d = tete.make_desc(8, 8, 8, 2, 2, 1, 0.5, materials=True, yee=True)     # Yee is vacuum + PEC only
     assert tete.check_desc(d) == "TETE_ERR_ARG"
 

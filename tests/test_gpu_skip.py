@@ -155,9 +155,9 @@ def test_static_tile_count(precision, rows, xchunk):
 
 
 def test_skip_flag_rules():
-    """The flag is refused with materials, Yee's scheme and the implicit
-    scheme; static_tiles needs the flag."""
-    for kw in ({"materials": True}, {"yee": True}, {"implicit": True}):
+    """The flag is refused with Yee's scheme and the implicit scheme;
+    static_tiles needs the flag."""
+    for kw in ({"yee": True}, {"implicit": True}):
         with pytest.raises(tete.TeteError):
             tete.Grid(8, 8, 8, 2 * DZ, 2 * DZ, DZ, DZ, skip_static=True, **kw)
     G = tete.Grid(8, 8, 8, 2 * DZ, 2 * DZ, DZ, DZ)
@@ -272,3 +272,50 @@ def test_skip_matches_oracle(precision):
     tol = 1e-12 if precision == "fp64" else 2e-5
     assert P.field_rel_err(G.get_fields(), f) <= tol
     assert P.delta_norm(G.wake(), W) <= (1e-12 if precision == "fp64" else 1e-5)
+
+
+def _skip_materials(precision, skip, cells, seed):
+    nx, ny, nz = SHAPE
+    g = O.Geom(nx, ny, nz, 2 * DZ, 2 * DZ, DZ, DZ)
+    rng = np.random.default_rng(seed)
+    m = O.vacuum_materials(g, cells)
+    for k in O.KEYS:
+        m[k] = np.where(m[k] > 0, m[k] * rng.uniform(0.5, 1.0, size=m[k].shape), 0.0)
+    G = tete.Grid(nx, ny, nz, g.dx, g.dy, g.dz, g.cdt, precision=precision, materials=True, skip_static=skip)
+    G.set_materials(m)
+    G.set_fields(inputs.random_fields(G.shape, seed + 1))
+    G.set_bunch(1e-9, 2e-3, nx // 2, JC, 10, -14, 40)
+    return G, g, m
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_skip_materials(precision):
+    """Per-entry materials (the fused single step): tiles whose kappa is zero
+    on every e edge they load are left out.  15 steps with a bunch give the
+    fields and wake of the grid without the skip, and fields within 1e-12
+    (FP64) / 2e-5 (FP32) of the oracle; new materials mid-run as well."""
+    print("skip materials", precision, flush=True)
+    cells = _pipe_cells(*SHAPE, 6, seed=97)
+    A, g, m = _skip_materials(precision, True, cells, 98)
+    B, _, _ = _skip_materials(precision, False, cells, 98)
+    assert A.get_tuning()["kernel"] == "fused"
+    A.step(15)
+    B.step(15)
+    sk, tot = A.static_tiles()
+    assert 0 < sk < tot
+    _same(A, B)
+    f = inputs.random_fields(g.shape, 99)
+    O.apply_pec(g, m, f)
+    r = O.run(g, m, f, 15, bunch=O.Bunch(Q=1e-9, sigma=2e-3, i0=SHAPE[0] // 2, j0=JC, M=10, jmin=-14, nw=40))
+    C, _, _ = _skip_materials(precision, True, cells, 98)
+    C.set_fields(inputs.random_fields(C.shape, 99))
+    C.step(15)
+    from tests import parity as P
+    assert P.field_rel_err(C.get_fields(), f) <= (1e-12 if precision == "fp64" else 2e-5)
+    # new materials (another geometry) mid-run
+    c2 = _pipe_cells(*SHAPE, 4, seed=100)
+    for G in (A, B):
+        G2, _, m2 = _skip_materials(precision, False, c2, 101)
+        G.set_materials(m2)
+        G.step(6)
+    _same(A, B)
