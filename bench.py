@@ -306,6 +306,59 @@ def skip_section(case, precision, explicit_ms_per_step, witness_ms=None, steps=8
                             round(witness_ms / wit["ms_per_step"], 2) if witness_ms else None}}
 
 
+def materials_skip_section(case, precision, steps=6):
+    """Per-entry materials that carry the workload's geometry: kappa and mu
+    0.9 of their vacuum values, kappa zero on the staircase PEC edges (an e
+    edge touching a metal cell, cells outside the box counting as metal).
+    Kernel time per step of the fused materials step over every tile and over
+    the active tiles only (skip_static); the fields are the same."""
+    import numpy as np
+    import torch
+    from paper_0901_1053_amd import tete
+    td = torch.float32 if precision == "fp32" else torch.float64
+    nx, ny, nz = case.nx, case.ny, case.nz
+    p = torch.ones((nx + 2, ny + 2, nz + 2), dtype=torch.bool, device="cuda")
+    p[1:-1, 1:-1, 1:-1] = torch.from_numpy(np.ascontiguousarray(case.cell_mask())).to("cuda").bool()
+    X, Y, Z = nx + 1, ny + 1, nz + 1
+    pec = {"ex": p[1:, 0:Y, 0:Z] | p[1:, 1:, 0:Z] | p[1:, 0:Y, 1:] | p[1:, 1:, 1:],
+           "ey": p[0:X, 1:Y + 1, 0:Z] | p[1:, 1:Y + 1, 0:Z] | p[0:X, 1:Y + 1, 1:] | p[1:, 1:Y + 1, 1:],
+           "ez": p[0:X, 0:Y, 1:Z + 1] | p[1:, 0:Y, 1:Z + 1] | p[0:X, 1:, 1:Z + 1] | p[1:, 1:, 1:Z + 1]}
+    del p
+    v = {"ex": case.dx / (case.dy * case.dz), "ey": case.dy / (case.dx * case.dz),
+         "ez": case.dz / (case.dx * case.dy)}
+    v.update({"hx": v["ex"], "hy": v["ey"], "hz": v["ez"]})
+    mat = {}
+    for k in tete.KEYS:
+        a = torch.full((X, Y, Z), 0.9 * v[k], device="cuda", dtype=td)
+        if k in pec:
+            a.masked_fill_(pec[k], 0.0)
+        mat[k] = a
+    del pec
+    out = {}
+    for skip in (False, True):
+        G = tete.Grid(nx, ny, nz, case.dx, case.dy, case.dz, case.cdt, precision=precision, materials=True,
+                      skip_static=skip)
+        G.set_materials(mat, dtype=precision)
+        G.step(2)
+        G.set_timing(steps)
+        G.step(steps)
+        a, b, n = G.timing()
+        G.set_timing(0)
+        out[skip] = (a + b) / n
+        if skip:
+            out["tiles"] = G.static_tiles()
+        G.close()
+        del G
+        torch.cuda.empty_cache()
+    del mat
+    torch.cuda.empty_cache()
+    return {"workload": case.name, "precision": precision,
+            "materials": "0.9 x vacuum kappa and mu, kappa 0 on the staircase PEC edges",
+            "ms_per_step": {"all_tiles": round(out[False], 3), "active_tiles": round(out[True], 3)},
+            "static_tiles": out["tiles"][0], "tiles": out["tiles"][1],
+            "speedup": round(out[False] / out[True], 2)}
+
+
 def implicit_section(case, precision, explicit_ms_per_step, steps=4):
     """The implicit TE/TM scheme (16) on the large workload: kernel time per step
     (HIP events around the two half steps on the grid's stream), the Chebyshev
@@ -528,6 +581,8 @@ def main():
     if not args.no_skip:
         out["skip_static_context"] = skip_section(case, args.precision, ms_step,
                                                   out.get("witness_context", {}).get("ms_per_step"))
+        if not args.no_materials:
+            out["skip_static_context"]["materials"] = materials_skip_section(case, args.precision)
         torch.cuda.empty_cache()
         print("# static-tile skip timing done", file=sys.stderr, flush=True)
 
