@@ -73,16 +73,18 @@ enum {
                                  * needs cdt = dz, which (8) excludes), no energy,
                                  * energy series or charges (TETE_ERR_STATE); probes
                                  * record e_z^{n+1/2}. */
-    TETE_F_SKIP_STATIC = 1u << 3, /* the two-step kernel leaves out tiles that lie wholly in
+    TETE_F_SKIP_STATIC = 1u << 3, /* the fused kernels leave out tiles that lie wholly in
                                  * PEC: every entry such a tile reads has its three e
                                  * edges PEC, so e stays zero and h constant there and a
                                  * step changes none of its entries.  Fields and wakes
                                  * equal those of a grid without the flag.  Tiles are left out
                                  * only once both ping-pong sets agree (from the second
-                                 * launch after tete_set_fields or tete_set_pec_cells),
-                                 * and not in single steps.
-                                 * The two-step launches take only the other tiles; with
-                                 * tuning x-chunk 0 such grids use chunks of 32 planes.
+                                 * launch after tete_set_fields or tete_set_pec_cells).
+                                 * Two-step and fused single-step launches take only
+                                 * the other tiles (the two-kernel step of
+                                 * TETE_KERNEL_SPLIT and batches take all); with tuning
+                                 * x-chunk 0 the two-step launches use chunks of 32
+                                 * planes.
                                  * The tile list is built, and the stream synchronised,
                                  * at the first such launch after the codes or the
                                  * tiling (rows, x-chunk, order; witness set or not)
@@ -90,8 +92,9 @@ enum {
                                  * set, the fused single step leaves out the tiles
                                  * whose kappa is zero on every e edge they load, by
                                  * the same rules (the list is rebuilt after
-                                 * tete_set_materials).  Not with TETE_F_YEE or
-                                 * TETE_F_IMPLICIT. */
+                                 * tete_set_materials).  tete_static_tiles reports
+                                 * the tiling of the next step.  Not with TETE_F_YEE
+                                 * or TETE_F_IMPLICIT. */
     TETE_F_IMPLICIT = 1u << 2   /* step with the implicit TE/TM scheme (16) of Sec. 4.1
                                  * instead of (23): a comparator.  Each half step solves
                                  * (I - alpha T_i) x = rhs; per z-plane this is one

@@ -115,7 +115,7 @@ struct tete_grid {
     int skip;
     uint8_t* skip_tab;
     int* skip_act;
-    int skip_kind, skip_rows, skip_xc, skip_order, skip_nact;   // kind 0: two-step, 1: materials
+    int skip_kind, skip_rows, skip_xc, skip_order, skip_nact;   // kind 0: two-step, 1: single step
     int64_t skip_nt;
     int skip_live;
     double *lam, *wacc, *partial, *scal, *eser, *pser;
@@ -261,16 +261,17 @@ bool use_fused2(const tete_grid* g)
 // Builds the static-tile table for the current tiling of the two-step
 // kernel unless it is already there.
 template <typename R>
-tete_status static_table(tete_grid* g, bool wit)
+tete_status static_table(tete_grid* g, bool wit, bool single)
 {
-    if (g->mat_set) {   // the materials step's tiling; kappa marks the PEC edges
+    if (single) {   // the fused single step's tiling; kappa marks the PEC edges of materials
+        const int rows = g->mat_set || g->tune.rows == 32 ? 0 : g->tune.rows;
         const int xc = g->tune.xchunk, order = g->tune.order;
-        if (g->skip_kind == 1 && g->skip_rows == 0 && g->skip_xc == xc && g->skip_order == order) return TETE_OK;
+        if (g->skip_kind == 1 && g->skip_rows == rows && g->skip_xc == xc && g->skip_order == order) return TETE_OK;
         const R* kap[3] = {(const R*)g->mat[0], (const R*)g->mat[1], (const R*)g->mat[2]};
-        HIPCHK(fused_mat_static_tiles<R>(kap, g->geo, xc, order, g->skip_tab, g->skip_act, skip_cap(g->geo),
-                                         &g->skip_nt, &g->skip_nact, g->stream));
+        HIPCHK(fused_static_tiles<R>(g->mat_set ? kap : nullptr, g->code, g->geo, rows, xc, order, g->skip_tab,
+                                     g->skip_act, skip_cap(g->geo), &g->skip_nt, &g->skip_nact, g->stream));
         g->skip_kind = 1;
-        g->skip_rows = 0;
+        g->skip_rows = rows;
         g->skip_xc = xc;
         g->skip_order = order;
         return TETE_OK;
@@ -324,7 +325,7 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             if (wit) wm = witness_mid<R>(g);
             const int* act = nullptr;
             if (g->skip && g->skip_live) {
-                if (static_table<R>(g, wit) != TETE_OK) return TETE_ERR_DEVICE;
+                if (static_table<R>(g, wit, false) != TETE_OK) return TETE_ERR_DEVICE;
                 act = g->skip_act;
                 // static tiles store no witness values: their e_z is zero
                 if (wit) HIPCHK(launch_zero_bytes(g->wmid, (g->fp32 ? 4 : 8) * (size_t)TETE_WITNESS_LINES * g->d.nz,
@@ -355,9 +356,9 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             HIPCHK(launch_step_yee<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                       g->tune.xchunk, g->tune.order, g->stream, ev));
         else if (use_fused(g)) {
-            const int* act = nullptr;   // static tiles: materials step only
-            if (g->skip && g->mat_set && g->skip_live) {
-                if (static_table<R>(g, false) != TETE_OK) return TETE_ERR_DEVICE;
+            const int* act = nullptr;
+            if (g->skip && g->skip_live) {
+                if (static_table<R>(g, false, true) != TETE_OK) return TETE_ERR_DEVICE;
                 act = g->skip_act;
             }
             HIPCHK(launch_step_fused<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
@@ -672,7 +673,9 @@ tete_status tete_static_tiles(tete_grid* g, int64_t* skipped, int64_t* total)
     DeviceGuard dg(g->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
     const bool wit = g->witness && g->has_bunch;
-    tete_status st = g->fp32 ? static_table<float>(g, wit) : static_table<double>(g, wit);
+    // the tiling the next step takes: two steps at once, else the single step
+    const bool single = !use_fused2(g);
+    tete_status st = g->fp32 ? static_table<float>(g, wit, single) : static_table<double>(g, wit, single);
     if (st != TETE_OK) return st;
     *skipped = g->skip_nt - g->skip_nact;
     *total = g->skip_nt;

@@ -316,17 +316,24 @@ __device__ __forceinline__ void fused_tile(const FArgs<R>& A, const int ty, cons
 
 // One step of one grid: one workgroup per (tile, x-chunk).
 template <typename R, int TYH, int PD>
-__global__ __launch_bounds__(64 * TYH) void k_fused(FArgs<R> A)
+__global__ __launch_bounds__(64 * TYH) void k_fused(FArgs<R> A, const int* act)
 {
     __shared__ Lds<R, TYH> L;
     int ty, tz, cx;
-    if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) return;   // whole group
+    if (act) {   // the active tiles only, as in the materials instance below
+        const int t = act[xcd_remap(blockIdx.x, gridDim.x)];
+        tz = t % A.nzt;
+        ty = (t / A.nzt) % A.nyt;
+        cx = t / (A.nzt * A.nyt);
+    } else if (!tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx)) {
+        return;   // whole group
+    }
     fused_tile<R, TYH, PD>(A, ty, tz, cx, L);
 }
 
 // The same step with per-entry materials.  act (or null): the tiles that are
 // not static, (cx nyt + ty) nzt + tz in the launch's tile order
-// (fused_mat_static_tiles), one workgroup each, remapped over the XCDs.
+// (fused_static_tiles), one workgroup each, remapped over the XCDs.
 template <typename R, int TYH, int PD>
 __global__ __launch_bounds__(64 * TYH) void k_fused_mat(FArgs<R> A, MatA<R> MA, const int* act)
 {
@@ -348,9 +355,11 @@ __global__ __launch_bounds__(64 * TYH) void k_fused_mat(FArgs<R> A, MatA<R> MA, 
 // max(0, xs-2) .. min(xe+1, nx)) has kappa zero on its three e edges (PEC, or
 // outside the component's range): e stays zero and h constant there, and the
 // step leaves every entry the tile owns unchanged.  One workgroup per tile.
+// kx null: the vacuum step, static where the PEC code of every entry is 7
+// (three e edges PEC or absent), so that e stays zero and h constant.
 template <typename R>
-__global__ __launch_bounds__(256) void k_static_mat(const R* kx, const R* ky, const R* kz, Geo g, int TYH, int TY,
-                                                    int xchunk, int nyt, int nzt, uint8_t* out)
+__global__ __launch_bounds__(256) void k_static_mat(const R* kx, const R* ky, const R* kz, const uint8_t* code, Geo g,
+                                                    int TYH, int TY, int xchunk, int nyt, int nzt, uint8_t* out)
 {
     __shared__ int active;
     const int t = blockIdx.x;
@@ -368,7 +377,7 @@ __global__ __launch_bounds__(256) void k_static_mat(const R* kx, const R* ky, co
         const int j = ty * TY - 2 + r / 64, k = tz * KT - 1 + r % 64;
         if (j < 0 || j > g.ny || k < 0 || k > g.nz) continue;
         const int64_t i = (int64_t)q * g.sp + (int64_t)j * g.sz + k;
-        if (kx[i] != R(0) || ky[i] != R(0) || kz[i] != R(0)) found = true;
+        if (kx ? (kx[i] != R(0) || ky[i] != R(0) || kz[i] != R(0)) : (code[i] & 7u) != 7u) found = true;
     }
     if (found) atomicOr(&active, 1);
     __syncthreads();
@@ -434,9 +443,10 @@ __global__ void k_batch_advance(BatchTable<R>* T, int steps, int flips)
 }
 
 template <typename R, int TYH, int PD>
-hipError_t launch_fused_t(const FArgs<R>& A, hipStream_t s)
+hipError_t launch_fused_t(const FArgs<R>& A, const int* act, int nact, hipStream_t s)
 {
-    k_fused<R, TYH, PD><<<A.nblk, 64 * TYH, 0, s>>>(A);
+    if (!act) k_fused<R, TYH, PD><<<A.nblk, 64 * TYH, 0, s>>>(A, nullptr);
+    else if (nact > 0) k_fused<R, TYH, PD><<<nact, 64 * TYH, 0, s>>>(A, act);
     return hipGetLastError();
 }
 
@@ -526,15 +536,17 @@ int64_t fused_tile_cap(Geo g)
 }
 
 template <typename R>
-hipError_t fused_mat_static_tiles(const R* const kap[3], Geo g, int xchunk, int order, uint8_t* tab, int* act,
-                                  int64_t cap, int64_t* ntiles, int* nact, hipStream_t s)
+hipError_t fused_static_tiles(const R* const kap[3], const uint8_t* code, Geo g, int rows, int xchunk, int order,
+                              uint8_t* tab, int* act, int64_t cap, int64_t* ntiles, int* nact, hipStream_t s)
 {
     FArgs<R> A = fused_args<R>(Fields<R>{}, Fields<R>{}, Mat<R>{}, g, R(0), Src{});
-    const int rows = fused_default_rows(sizeof(R));   // the materials instance's shape
+    if (kap || rows == 0) rows = fused_default_rows(sizeof(R));   // the materials instance: default shape
     if (!fused_setup<R>(A, rows, xchunk, order)) return hipErrorInvalidValue;
     const int64_t nt = (int64_t)A.nyt * A.nzt * A.nxc;
     if (nt > cap || nt > 0x7fffffff) return hipErrorInvalidValue;
-    k_static_mat<R><<<(int)nt, 256, 0, s>>>(kap[0], kap[1], kap[2], g, rows, rows - 4, A.xchunk, A.nyt, A.nzt, tab);
+    if (!kap && !code) return hipErrorInvalidValue;
+    k_static_mat<R><<<(int)nt, 256, 0, s>>>(kap ? kap[0] : nullptr, kap ? kap[1] : nullptr, kap ? kap[2] : nullptr,
+                                            code, g, rows, rows - 4, A.xchunk, A.nyt, A.nzt, tab);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     std::vector<uint8_t> h((size_t)nt);
@@ -583,13 +595,13 @@ hipError_t launch_step_fused(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha
         else if (nact > 0) k_fused_mat<R, TYH, 1><<<nact, 64 * TYH, 0, s>>>(A, MA, act);
         e = hipGetLastError();
     } else if (rows == 12) {
-        if (depth == 1) e = launch_fused_t<R, 12, 1>(A, s);
-        else if (depth == 3) e = launch_fused_t<R, 12, 3>(A, s);
-        else e = launch_fused_t<R, 12, 2>(A, s);
+        if (depth == 1) e = launch_fused_t<R, 12, 1>(A, act, nact, s);
+        else if (depth == 3) e = launch_fused_t<R, 12, 3>(A, act, nact, s);
+        else e = launch_fused_t<R, 12, 2>(A, act, nact, s);
     } else {
-        if (depth == 1) e = launch_fused_t<R, 16, 1>(A, s);
-        else if (depth == 3) e = launch_fused_t<R, 16, 3>(A, s);
-        else e = launch_fused_t<R, 16, 2>(A, s);
+        if (depth == 1) e = launch_fused_t<R, 16, 1>(A, act, nact, s);
+        else if (depth == 3) e = launch_fused_t<R, 16, 3>(A, act, nact, s);
+        else e = launch_fused_t<R, 16, 2>(A, act, nact, s);
     }
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
@@ -609,9 +621,9 @@ template hipError_t launch_step_fused<float>(Fields<float>, Fields<float>, Mat<f
                                              int, int, hipStream_t, hipEvent_t*, const int*, int);
 template hipError_t launch_step_fused<double>(Fields<double>, Fields<double>, Mat<double>, Geo, double, Src, int,
                                               int, int, int, hipStream_t, hipEvent_t*, const int*, int);
-template hipError_t fused_mat_static_tiles<float>(const float* const[3], Geo, int, int, uint8_t*, int*, int64_t,
-                                                  int64_t*, int*, hipStream_t);
-template hipError_t fused_mat_static_tiles<double>(const double* const[3], Geo, int, int, uint8_t*, int*, int64_t,
-                                                   int64_t*, int*, hipStream_t);
+template hipError_t fused_static_tiles<float>(const float* const[3], const uint8_t*, Geo, int, int, int, uint8_t*,
+                                              int*, int64_t, int64_t*, int*, hipStream_t);
+template hipError_t fused_static_tiles<double>(const double* const[3], const uint8_t*, Geo, int, int, int, uint8_t*,
+                                               int*, int64_t, int64_t*, int*, hipStream_t);
 
 }  // namespace tete

@@ -125,8 +125,8 @@ hipError_t launch_step(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alph
 // Whether a grid's planes are small enough for the fused kernel's buffer
 // addressing (five planes below 2^31 bytes).
 bool fused_fits(Geo g, int real_bytes);
-// act (or nullptr), per-entry materials only: the nact active tiles of
-// fused_mat_static_tiles for the same xchunk and order
+// act (or nullptr): the nact active tiles of fused_static_tiles for the same
+// rows, xchunk and order
 template <typename R>
 hipError_t launch_step_fused(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src, int rows,
                              int xchunk, int depth, int order, hipStream_t s, hipEvent_t* ev, const int* act,
@@ -134,12 +134,13 @@ hipError_t launch_step_fused(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, 
 // Bytes a static-tile table of the materials step needs at most.
 int64_t fused_tile_cap(Geo g);
 // The static-tile table (tab) and the active tiles (act, *nact of them) of the
-// materials step for the tiling (xchunk, order): static where kappa (kap:
-// kappa_x, kappa_y, kappa_z) is zero on every e edge the tile loads.
-// Synchronises the stream.
+// single step for the tiling (rows, xchunk, order): with kap (kappa_x,
+// kappa_y, kappa_z; the materials instance, default rows) static where kappa
+// is zero on every e edge the tile loads, else where every loaded PEC code is
+// 7.  Synchronises the stream.
 template <typename R>
-hipError_t fused_mat_static_tiles(const R* const kap[3], Geo g, int xchunk, int order, uint8_t* tab, int* act,
-                                  int64_t cap, int64_t* ntiles, int* nact, hipStream_t s);
+hipError_t fused_static_tiles(const R* const kap[3], const uint8_t* code, Geo g, int rows, int xchunk, int order,
+                              uint8_t* tab, int* act, int64_t cap, int64_t* ntiles, int* nact, hipStream_t s);
 
 template <typename R>
 FArgs<R> fused_args(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src);

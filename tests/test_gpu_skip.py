@@ -319,3 +319,33 @@ def test_skip_materials(precision):
         G.set_materials(m2)
         G.step(6)
     _same(A, B)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("rows,depth", [(0, 0), (12, 1), (16, 3)])
+def test_skip_single_steps(precision, rows, depth):
+    """The fused single step over the active tiles: with the single-step
+    kernel chosen, and with probes (every step a single step) and energy
+    diagnostics, fields, wake, probe series and energy series equal those of
+    the grid without the skip."""
+    print("skip single", precision, rows, depth, flush=True)
+    cells = _pipe_cells(*SHAPE, 6, seed=102)
+    nx, ny, nz = SHAPE
+    probes = [(nx // 2) * (ny + 1) * (nz + 1) + JC * (nz + 1) + k for k in (5, 40, 90)]
+    grids = []
+    for skip in (True, False):
+        G = tete.Grid(nx, ny, nz, 2 * DZ, 2 * DZ, DZ, DZ, precision=precision, skip_static=skip, max_series=64)
+        G.set_tuning("fused", rows, 7, depth)
+        G.set_pec_cells(cells)
+        G.set_fields(inputs.random_fields(G.shape, 103))
+        G.set_bunch(1e-9, 2e-3, nx // 2, JC, 10, -14, 40)
+        G.step(9)
+        G.set_tuning("auto")
+        G.set_probes(probes)
+        G.set_diagnostics(3)
+        G.step(8)
+        grids.append(G)
+    assert grids[0].static_tiles()[0] > 0
+    _same(*grids)
+    assert np.array_equal(grids[0].probes(3), grids[1].probes(3))
+    assert np.array_equal(grids[0].energy_series(), grids[1].energy_series())
