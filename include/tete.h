@@ -257,9 +257,10 @@ tete_status tete_clear_witness(tete_grid* g);
  * stream.  TETE_ERR_STATE without a bunch or witness. */
 tete_status tete_witness_wake(tete_grid* g, double* W, double* Wx, double* Wy, int32_t nw);
 
-/* Static tiles of a TETE_F_SKIP_STATIC grid for its current geometry and
- * two-step tiling: *skipped of *total tiles lie wholly in PEC.  Builds the
- * table if needed; synchronises the stream.  TETE_ERR_STATE without the flag. */
+/* Static tiles of a TETE_F_SKIP_STATIC grid for its current geometry (or
+ * materials) and the tiling its next step takes (two-step, else fused single
+ * step): *skipped of *total tiles lie wholly in PEC.  Builds the table if
+ * needed; synchronises the stream.  TETE_ERR_STATE without the flag. */
 tete_status tete_static_tiles(tete_grid* g, int64_t* skipped, int64_t* total);
 
 /* Discrete energy W^{n,e} = 1/2 <Q^e y^n, y^n> (Sec. 4.4) of the current
