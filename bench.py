@@ -11,7 +11,10 @@ measured with HIP events on the grid's stream.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 
-Prints one JSON line.
+Prints one JSON line.  The headline steps every tile; the context sections
+(Yee's scheme, witness lines, the implicit scheme, per-entry materials, tiles
+wholly in PEC left out, the r-z scheme, batches, serving) are measured on
+their own grids after it and do not enter `value`.
 """
 from __future__ import annotations
 
