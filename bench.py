@@ -13,8 +13,8 @@ measured with HIP events on the grid's stream.
 
 Prints one JSON line.  The headline steps every tile; the context sections
 (Yee's scheme, witness lines, the implicit scheme, per-entry materials, tiles
-wholly in PEC left out, the r-z scheme, batches, serving) are measured on
-their own grids after it and do not enter `value`.
+wholly in PEC left out, the r-z scheme, batches, serving) are measured
+after it and do not enter `value`.
 """
 from __future__ import annotations
 
