@@ -168,8 +168,9 @@ class Grid:
     """One explicit TE/TM grid (or, with yee=True, a grid stepped with Yee's
     scheme (7), with implicit=True one stepped with the implicit TE/TM scheme
     (16), for comparison) living in a torch-owned device workspace.
-    skip_static=True lets the two-step kernel leave out tiles that lie wholly
-    in PEC (the results are unchanged)."""
+    skip_static=True lets the fused kernels (two-step, single-step and the
+    materials step) leave out tiles that lie wholly in PEC (the results are
+    unchanged)."""
 
     def __init__(self, nx, ny, nz, dx, dy, dz, cdt, precision="fp64", materials=False, max_series=0,
                  device="cuda:0", stream=None, yee=False, implicit=False, skip_static=False):
@@ -311,7 +312,7 @@ class Grid:
         return W, wx, wy
 
     def static_tiles(self):
-        """(tiles left out, tiles) of the two-step kernel's current tiling
+        """(tiles left out, tiles) of the tiling the next step takes
         (skip_static grids)."""
         a, b = C.c_int64(), C.c_int64()
         _chk("tete_static_tiles", load().tete_static_tiles(self.h, C.byref(a), C.byref(b)))
