@@ -51,42 +51,154 @@ def measured_traffic(kernel_name, workload, precision):
 METRIC = "Gcell-updates/s + HBM GB/s; batched wake solves/s with p50/p99 latency"
 
 
-def cpu_baseline(case, nz_slab=32, steps=4):
-    """The FP64 oracle (plain C, one thread) on a z-slab of the same workload."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(case, gpu_fp64, nz_slab=32, steps_one=4, steps_all=16):
+    """The FP64 oracle (plain C; OpenMP shares the planes of each sub-update,
+    bitwise the single-thread result) on a z-slab of the same workload, with
+    one thread and with every thread the process may use, beside the GPU's
+    FP64 rate on the full workload (equal precision)."""
     from oracle import oracle as O
     g = O.Geom(case.nx, case.ny, nz_slab, case.dx, case.dy, case.dz, case.cdt)
     k0 = case.nz // 2 - nz_slab // 2
     cells = case.cell_mask()[:, :, k0:k0 + nz_slab]
     m = O.vacuum_materials(g, cells)
-    f = O.zeros(g)
     b = O.Bunch(Q=case.Q, sigma=case.sigma, i0=case.i0, j0=case.j0, M=case.M, jmin=-4, nw=8)
-    t0 = time.perf_counter()
-    O.run(g, m, f, steps, n0=nz_slab // 2 + case.M - steps // 2, bunch=b)
-    dt = time.perf_counter() - t0
-    return {"value": case.nx * case.ny * nz_slab * steps / dt / 1e9, "unit": "Gcell-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "%dx%dx%d z-slab (cells %d..%d) of the %s workload with its geometry and bunch, %d steps, "
-                      "FP64, single thread, %.1f s" % (case.nx, case.ny, nz_slab, k0, k0 + nz_slab - 1, case.name,
-                                                       steps, dt)}
+    threads_all = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads_all = min(threads_all, int(os.environ.get("OMP_NUM_THREADS", threads_all) or threads_all))
+    rates = {}
+    total = 0.0
+    for th, steps in ((1, steps_one), (threads_all, steps_all)):
+        O.set_threads(th)
+        f = O.zeros(g)
+        t0 = time.perf_counter()
+        O.run(g, m, f, steps, n0=nz_slab // 2 + case.M - steps // 2, bunch=b)
+        dt = time.perf_counter() - t0
+        total += dt
+        rates[th] = case.nx * case.ny * nz_slab * steps / dt / 1e9
+    O.set_threads(threads_all)
+    out = {"value": rates[threads_all], "unit": "Gcell-updates/s", "cores": threads_all, "kind": "oracle",
+           "single_thread_value": rates[1], "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+           "sample": "%dx%dx%d z-slab (cells %d..%d) of the %s workload with its geometry and bunch, FP64: "
+                     "%d steps on 1 thread, %d steps on %d threads, %.1f s in all"
+                     % (case.nx, case.ny, nz_slab, k0, k0 + nz_slab - 1, case.name, steps_one, steps_all,
+                        threads_all, total)}
+    if gpu_fp64:
+        out["gpu_fp64_gcell_updates_per_s"] = gpu_fp64
+        out["gpu_fp64_over_cpu_all_threads"] = round(gpu_fp64 / rates[threads_all], 1)
+    return out
+
+
+def gpu_fp64_rate(case, steps=10):
+    """FP64 fields on the same workload (the oracle's precision): Gcell-updates/s
+    of the library's default kernel, HIP events on the grid's stream."""
+    import torch
+    from paper_0901_1053_amd import tete
+    G = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.cdt, precision="fp64")
+    G.set_pec_cells(case.cell_mask())
+    G.set_bunch(case.Q, case.sigma, case.i0, case.j0, case.M, case.jmin, case.nw)
+    G.step(2)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(G.stream)
+    G.step(steps)
+    e1.record(G.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    G.close()
+    del G
+    torch.cuda.empty_cache()
+    return round(case.cells * steps / (ms / 1e3) / 1e9, 2)
+
+
+def copy_ceiling(entries, precision, reps=5):
+    """HBM rate of tete_stream_probe: the step's arrays (six read with the code
+    byte, six written) streamed once with coalesced 16-byte accesses, over as
+    many entries as the workload's grid; bytes per launch / mean launch time
+    (HIP events on the current stream)."""
+    import torch
+    from paper_0901_1053_amd import tete
+    td = torch.float32 if precision == "fp32" else torch.float64
+    b = 4 if precision == "fp32" else 8
+    src = [torch.ones(entries, dtype=td, device="cuda") for _ in range(6)]
+    dst = [torch.empty(entries, dtype=td, device="cuda") for _ in range(6)]
+    code = torch.zeros(entries, dtype=torch.uint8, device="cuda")
+    tete.stream_probe(src, dst, code)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        tete.stream_probe(src, dst, code)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(dst[5], src[5]))
+    del src, dst, code
+    torch.cuda.empty_cache()
+    nbytes = (12 * b + 1) * entries
+    return {"kernel": "k_stream (tete_stream_probe)", "bytes_per_launch": nbytes, "ms_per_launch": round(ms, 4),
+            "gbps": round(nbytes / (ms / 1e3) / 1e9, 1), "copied_correctly": ok}
 
 
 def _tuned(cases, precision):
-    """Autotune the fused launch shape for each size class present (cache in /tmp)."""
+    """Autotune the launch shape for each size class present (cache in /tmp):
+    x-planes per workgroup and tile order, each timed in a batch of eight
+    copies (the context batch members run in; the persistent batch launch
+    has one workgroup shape, 16 rows of 64 lanes, so rows are not searched
+    there).  Reports each class's best shape and its gain over the default
+    (x-chunk 0, order 2)."""
     from paper_0901_1053_amd.autotune import Tuner, size_class
     # FP32 batches run the two-step kernel: tune that one, in a batch of eight
-    tuner = Tuner(cache_path=os.path.join("/tmp", "tete_bench_autotune.json"), xchunks=(0, 32, 128), orders=(2,),
-                  steps=8, warmup=1, kernel="fused2" if precision == "fp32" else "fused", batch=8)
+    tuner = Tuner(cache_path=os.path.join("/tmp", "tete_bench_autotune.json"), xchunks=(0, 16, 32, 64, 128),
+                  orders=(2, 1, 4), steps=8, warmup=1, kernel="fused2" if precision == "fp32" else "fused", batch=8)
     shapes = {}
     for c in cases:
         key = size_class(c.nx, c.ny, c.nz, precision)
         if key not in shapes:
             sh = tuner.tune(c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, c.cdt, precision)
+            dflt = tuner.timed.get((0, 2, 0, 0))
             # the class rounds each dimension up to a power of two; the time is
             # that of the tuned kernel on the class's first grid
             shapes[key] = {"kernel": tuner.kernel, "xchunk": sh.xchunk, "order": sh.order,
-                           "ms_per_step_per_instance": round(sh.ms, 4), "timed_on": "batch of %d x %dx%dx%d"
-                           % (tuner.batch, c.nx, c.ny, c.nz)}
+                           "ms_per_step_per_instance": round(sh.ms, 4),
+                           "default_ms_per_step_per_instance": round(dflt, 4) if dflt else None,
+                           "gain_over_default": round(dflt / sh.ms, 3) if dflt else None,
+                           "candidates": len(tuner.timed),
+                           "timed_on": "batch of %d x %dx%dx%d" % (tuner.batch, c.nx, c.ny, c.nz)}
     return tuner, shapes
+
+
+def single_grid_tuning(G, steps=6):
+    """Launch shapes of the two-step kernel on the headline grid (rows 16 or
+    32, tile order, x-chunk), kernel time per step from the grid's own timing;
+    the grid's shape is restored afterwards.  The headline uses the library's
+    default shape."""
+    saved = G.get_tuning()
+    rows_ = []
+    for rows in (16, 32):
+        for order in (2, 4):
+            for xc in (0, 128):
+                G.set_tuning("fused2", rows, xc, 0, order)
+                G.step(2)
+                G.set_timing(steps)
+                G.step(steps)
+                ms, _, n = G.timing()
+                G.set_timing(0)
+                rows_.append({"rows": rows, "order": order, "xchunk": xc, "ms_per_step": round(ms / n, 4)})
+    G.set_tuning(saved["kernel"], saved["rows"], saved["xchunk"], saved["depth"], saved["order"])
+    best = min(rows_, key=lambda r: r["ms_per_step"])
+    return {"candidates": rows_, "best": best}
 
 
 def batched_section(count):
@@ -429,8 +541,13 @@ def rz_section(steps=100, warmup=5):
                                   "achieved": round(achieved, 1),
                                   "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                                   "frac": round(achieved / PEAK_HBM_GBPS, 4), "bytes_per_launch": kbytes,
+                                  "basis": "algorithmic bytes of %d single steps per launch; the two-step launch "
+                                           "reads and writes the state once, so frac can exceed 1: it is not a "
+                                           "bandwidth fraction, traffic_frac is" % per,
                                   "ms_per_launch": round(kms / n, 4), "traffic": traffic,
-                                  "traffic_gbps": round(traffic / (kms / n / 1e3) / 1e9, 1) if traffic else None},
+                                  "traffic_gbps": round(traffic / (kms / n / 1e3) / 1e9, 1) if traffic else None,
+                                  "traffic_frac": round(traffic / (kms / n / 1e3) / 1e9 / PEAK_HBM_GBPS, 4)
+                                  if traffic else None},
                      "solve_s_estimate": round(ms / steps * case.steps() / 1e3, 2)}
         G.close()
         del G
@@ -463,9 +580,10 @@ def main():
     ap.add_argument("--no-witness", action="store_true", help="skip the off-axis witness timing")
     ap.add_argument("--no-materials", action="store_true", help="skip the per-entry materials timing")
     ap.add_argument("--no-skip", action="store_true", help="skip the static-tile skip timing")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape table of the headline grid")
     ap.add_argument("--batched-count", type=int, default=64)
-    ap.add_argument("--serve-rates", default="1,20,200", help="comma-separated request rates (req/s)")
-    ap.add_argument("--serve-requests", type=int, default=12)
+    ap.add_argument("--serve-rates", default="1,10,50,200", help="comma-separated request rates (req/s)")
+    ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-max-cells", type=float, default=2 ** 28,
                     help="serving: grid cells in flight at most (0: no limit)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
@@ -535,6 +653,9 @@ def main():
         kbytes = (8 * b + 1) * entries         # each half reads five arrays + code, writes three
     achieved = kbytes / (kern[dom] / 1e3) / 1e9
     traffic = measured_traffic("k_" + dom, case.name, args.precision)
+    traffic_gbps = traffic / (kern[dom] / 1e3) / 1e9 if traffic else None
+    ceiling = copy_ceiling(entries, args.precision)
+    print("# copy ceiling %.1f GB/s" % ceiling["gbps"], file=sys.stderr, flush=True)
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -556,15 +677,26 @@ def main():
         "hbm_gbps_algorithmic": round(step_bytes / (ms_step / 1e3) / 1e9, 1),
         "roofline": {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(achieved, 1),
                      "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "basis": "algorithmic bytes: 12 b + 1 = %d B per grid entry per time step, %d step(s) per "
+                              "launch; a launch of the two-step kernel reads and writes the state once, so it "
+                              "moves about half of these bytes and frac can exceed what its DRAM traffic does"
+                              % (12 * b + 1, kbytes // step_bytes),
                      "traffic": traffic,
-                     "traffic_gbps": round(traffic / (kern[dom] / 1e3) / 1e9, 1) if traffic else None,
+                     "traffic_gbps": round(traffic_gbps, 1) if traffic else None,
+                     "traffic_frac": round(traffic_gbps / PEAK_HBM_GBPS, 4) if traffic else None,
+                     "copy_ceiling_gbps": ceiling["gbps"],
+                     "traffic_vs_copy_ceiling": round(traffic_gbps / ceiling["gbps"], 4) if traffic else None,
                      "bytes_per_launch": kbytes, "ms_per_launch": round(kern[dom], 4),
                      "kernels_ms_per_launch": {k: round(v, 4) for k, v in kern.items()}},
+        "copy_ceiling": ceiling,
         "paper_context": {"updates_per_step": {"explicit_te_tm": 10, "yee": 6},
                           "cost_per_step_vs_yee": round(10 / 6, 3),
                           "run_time_vs_yee_at_dx_sqrt2_dz": round((10 / 6) / 2 ** 0.5, 3),
                           "hardware": "not stated in the paper", "timings": "none reported"},
     }
+    if not args.no_tune:
+        out["single_grid_tuning"] = single_grid_tuning(G)
+        print("# single-grid tuning done", file=sys.stderr, flush=True)
     if not args.no_yee:
         out["yee_context"] = yee_section(G, case, args.precision)
         print("# yee comparison done", file=sys.stderr, flush=True)
@@ -626,7 +758,8 @@ def main():
         print("# serve done", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case)
+        fp64 = gpu_fp64_rate(case) if args.precision == "fp32" else round(value, 2)
+        out["cpu_baseline"] = cpu_baseline(case, fp64)
     print(json.dumps(out), flush=True)
 
 

@@ -32,6 +32,14 @@
  * stream; small result arguments are HOST pointers.  A call that returns an
  * error leaves the grid state unchanged unless stated otherwise.
  *
+ * Error state: a read-out (tete_wake, tete_witness_wake, tete_energy,
+ * tete_energy_series, tete_probes, tete_charges) that finds NaN or Inf puts
+ * the grid into the sticky TETE_ERR_NONFINITE state.  The read-out still
+ * fills its outputs; meanwhile tete_step does nothing and returns
+ * TETE_ERR_NONFINITE, every read-out returns it, and the grid cannot join or
+ * step in a batch.  tete_set_fields (a new initial state) clears it;
+ * tete_grid_status reports it.
+ *
  * Ordering: calls are ordered on the grid's stream.  tete_step only enqueues
  * work; tete_wake, tete_energy, tete_energy_series, tete_probes and
  * tete_charges synchronise the stream before they return.  One grid may be
@@ -52,11 +60,13 @@ typedef struct tete_grid tete_grid; /* opaque handle */
 typedef enum {
     TETE_OK = 0,
     TETE_ERR_ARG = -1,       /* invalid argument (size, index, pointer, alignment) */
-    TETE_ERR_UNSTABLE = -2,  /* cdt violates the stability bound (25) */
+    TETE_ERR_UNSTABLE = -2,  /* cdt violates the stability bound (25), or materials
+                              * fail the sufficient Q^e >= 0 test (Sec. 4.4) */
     TETE_ERR_NOMEM = -3,     /* workspace smaller than tete_workspace_bytes */
     TETE_ERR_DEVICE = -4,    /* a HIP call or kernel launch failed */
     TETE_ERR_STATE = -5,     /* call not valid in the grid's current state */
-    TETE_ERR_NONFINITE = -6  /* a diagnostic found NaN or Inf in the fields */
+    TETE_ERR_NONFINITE = -6  /* a read-out found NaN or Inf (fields diverged); the grid
+                              * stays in this state until tete_set_fields */
 } tete_status;
 
 /* Arithmetic type of the field arrays.  FP32 keeps the wake accumulation,
@@ -165,8 +175,26 @@ tete_status tete_set_pec_cells(tete_grid* g, const uint8_t* cell_is_pec);
 /* General diagonal materials (Sec. 2, eq. (4)): DEVICE arrays of np entries
  * of type dtype (TETE_FP64/TETE_FP32): inv_eps[0..2] = M_eps^-1 on e_x,e_y,e_z
  * edges (0 = PEC edge), inv_mu[0..2] = M_mu^-1 on h_x,h_y,h_z.  Requires a grid
- * created with TETE_F_MATERIALS, else TETE_ERR_STATE.  Values must be finite
- * and >= 0.  Zeroes e where inv_eps = 0.  Replaces the staircase vacuum. */
+ * created with TETE_F_MATERIALS, else TETE_ERR_STATE.  Values in each
+ * component's index range must be finite and >= 0 (TETE_ERR_ARG otherwise;
+ * entries outside it are ignored).  Zeroes e where inv_eps = 0.  Replaces the
+ * staircase vacuum.
+ * Stability (Sec. 4.4: the scheme is stable when Q^e is positive definite):
+ * before importing, the library checks a sufficient condition on the GPU.  In
+ * the scaled variables h / sqrt(mu), e / sqrt(kappa), Q^e falls into three
+ * independent blocks -- e_z alone (I - alpha^2 R_0), h_z alone
+ * (I - alpha^2 R_1) and (h_x, h_y, e_x, e_y) coupled by alpha L -- and each is
+ * positive semi-definite when every Gershgorin row sum of its subtracted and
+ * off-diagonal parts is at most 1, alpha = cdt/2:
+ *   e_z row:  alpha^2 sum over its 4 h facets of mu (kappa_z + sqrt(kappa_z kappa_z'))
+ *   h_z row:  alpha^2 sum over its 4 e edges of kappa (mu_z + sqrt(mu_z mu_z'))
+ *   h_x row:  alpha sqrt(mu_x) (sqrt(kappa_y(k)) + sqrt(kappa_y(k+1))), h_y likewise
+ *             with kappa_x; e_y row: alpha sqrt(kappa_y) (sqrt(mu_x(k-1)) +
+ *             sqrt(mu_x(k))), e_x likewise with mu_y,
+ * primes denoting the neighbour across the facet or edge.  With vacuum
+ * coefficients this is the bound (25).  If the largest sum exceeds 1 (to
+ * 1e-12) the call returns TETE_ERR_UNSTABLE and changes nothing.  The test
+ * is sufficient, not necessary.  Synchronises the stream. */
 tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3],
                                const void* const inv_mu[3], int32_t dtype);
 
@@ -219,6 +247,10 @@ tete_status tete_step(tete_grid* g, int64_t nsteps);
 /* Number of completed steps (host counter, no synchronisation). */
 tete_status tete_steps_done(tete_grid* g, int64_t* n);
 
+/* The grid's sticky error state (see "Error state" above): TETE_OK or
+ * TETE_ERR_NONFINITE.  Host only, no synchronisation. */
+tete_status tete_grid_status(tete_grid* g);
+
 /* Longitudinal wake potential (Sec. 5) W(s_j) = -(1/Q) int E_z dz at
  * t = (z + s)/c on the bunch line, in V/C, for the nw samples of the bunch
  * (HOST array W of at least nw doubles).  Sample j is complete once step
@@ -258,9 +290,11 @@ tete_status tete_clear_witness(tete_grid* g);
 tete_status tete_witness_wake(tete_grid* g, double* W, double* Wx, double* Wy, int32_t nw);
 
 /* Static tiles of a TETE_F_SKIP_STATIC grid for its current geometry (or
- * materials) and the tiling its next step takes (two-step, else fused single
- * step): *skipped of *total tiles lie wholly in PEC.  Builds the table if
- * needed; synchronises the stream.  TETE_ERR_STATE without the flag. */
+ * materials): *skipped of *total tiles lie wholly in PEC, for the tiling of
+ * the two-step kernel where tete_step pairs steps, else (no two-step kernel,
+ * probes set, or an energy sample before every step) for the fused single
+ * step's.  The two kinds keep separate tables.  Builds the table if needed;
+ * synchronises the stream.  TETE_ERR_STATE without the flag. */
 tete_status tete_static_tiles(tete_grid* g, int64_t* skipped, int64_t* total);
 
 /* Discrete energy W^{n,e} = 1/2 <Q^e y^n, y^n> (Sec. 4.4) of the current
@@ -521,6 +555,20 @@ tete_status tete_rz_set_tuning(tete_rz* g, int32_t kernel, int32_t chunk_rows, i
  * the launches recorded and the steps they took.  Synchronises. */
 tete_status tete_rz_set_timing(tete_rz* g, int64_t max_launches);
 tete_status tete_rz_timing(tete_rz* g, double* ms, int64_t* launches, int64_t* steps);
+
+/* ------------------------------------------------------------------------
+ * Measurement aid: the HBM ceiling of the step's access pattern.  One launch
+ * reads six arrays of n entries of dtype and n code bytes and writes six
+ * arrays: out[c][i] = in[c][i] (0 where bit 7 of code[i] is set, which the
+ * library's PEC codes never have), every access a coalesced 16-byte load or
+ * store.  The fused kernels move the same arrays (per launch: six fields
+ * and the codes read, six fields written), so this kernel's rate bounds
+ * theirs from above on the hardware.  DEVICE arrays, in/out 16-byte and code
+ * 4-byte aligned; in and out must not overlap.  Asynchronous on hip_stream.
+ * Errors: TETE_ERR_ARG, TETE_ERR_DEVICE.
+ * ---------------------------------------------------------------------- */
+tete_status tete_stream_probe(void* const in[6], void* const out[6], const uint8_t* code, int64_t n,
+                              int32_t dtype, void* hip_stream);
 
 /* Human-readable status name. */
 const char* tete_status_str(tete_status s);

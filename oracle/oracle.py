@@ -25,10 +25,12 @@ KEYS = ("ex", "ey", "ez", "hx", "hy", "hz")
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C11, no FMA contraction)."""
+    """Compile the oracle with gcc (plain C11, no FMA contraction; OpenMP shares
+    the planes of each sub-update among threads, which leaves every result
+    bitwise that of one thread)."""
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fPIC",
+        subprocess.check_call(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
                                "-shared", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
@@ -68,8 +70,21 @@ def lib():
         L.orc_run.argtypes = [C.POINTER(_Geom), P6, P6, C.c_int, C.c_int, C.POINTER(_Bunch),
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
         L.orc_run.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_get_threads.argtypes = []
+        L.orc_get_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads used by the sub-updates of a step (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
 
 
 @dataclass

@@ -99,6 +99,28 @@ static double at(const orc_geom* g, double* const f[6], int c, int i, int j, int
             for (int k = 0; k <= (g)->nz; ++k)         \
                 if (in_range((g), (c), i, j, k))
 
+/* LOOP with its planes shared among OpenMP threads.  Used only by the
+ * sub-updates, each of which writes one component from values of the other
+ * components alone: every entry gets the same operands and the same operations
+ * whatever the thread count, so results are bitwise those of one thread.  Sums
+ * (energy, charges, wake) stay serial. */
+#define PLOOP(g, c)                                    \
+    _Pragma("omp parallel for schedule(static)")       \
+    for (int i = 0; i <= (g)->nx; ++i)                 \
+        for (int j = 0; j <= (g)->ny; ++j)             \
+            for (int k = 0; k <= (g)->nz; ++k)         \
+                if (in_range((g), (c), i, j, k))
+
+/* Threads used by the sub-updates (OpenMP; 1 without it). */
+#ifdef _OPENMP
+#include <omp.h>
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
+#else
+void orc_set_threads(int n) { (void)n; }
+int orc_get_threads(void) { return 1; }
+#endif
+
 /* ---------------------------------------------------------------------------
  * Materials (Sec. 2): diagonal M_eps^-1 = kappa on edges, M_mu^-1 = mu on
  * facets, vacuum values for uniform cells in units c = eps0 = mu0 = 1:
@@ -163,7 +185,7 @@ void orc_apply_pec(const orc_geom* g, double* const m[6], double* f[6])
 /* S1 / S4: h_x += alpha mu_x [P_z e_y - P_y e_z] */
 static void upd_hx(const orc_geom* g, double* const m[6], double* f[6], double a)
 {
-    LOOP(g, HX) {
+    PLOOP(g, HX) {
         double pz_ey = at(g, f, EY, i, j, k + 1) - at(g, f, EY, i, j, k);
         double py_ez = at(g, f, EZ, i, j + 1, k) - at(g, f, EZ, i, j, k);
         f[HX][idx(g, i, j, k)] += a * m[HX][idx(g, i, j, k)] * (pz_ey - py_ez);
@@ -173,7 +195,7 @@ static void upd_hx(const orc_geom* g, double* const m[6], double* f[6], double a
 /* S2 / S5: h_y += alpha mu_y [-P_z e_x + P_x e_z] */
 static void upd_hy(const orc_geom* g, double* const m[6], double* f[6], double a)
 {
-    LOOP(g, HY) {
+    PLOOP(g, HY) {
         double pz_ex = at(g, f, EX, i, j, k + 1) - at(g, f, EX, i, j, k);
         double px_ez = at(g, f, EZ, i + 1, j, k) - at(g, f, EZ, i, j, k);
         f[HY][idx(g, i, j, k)] += a * m[HY][idx(g, i, j, k)] * (-pz_ex + px_ez);
@@ -183,7 +205,7 @@ static void upd_hy(const orc_geom* g, double* const m[6], double* f[6], double a
 /* S3: e_z += 2 alpha kappa_z [P_y^T h_x - P_x^T h_y - j_z] */
 static void upd_ez(const orc_geom* g, double* const m[6], double* f[6], double a2, const double* jz)
 {
-    LOOP(g, EZ) {
+    PLOOP(g, EZ) {
         double pyt_hx = at(g, f, HX, i, j - 1, k) - at(g, f, HX, i, j, k);
         double pxt_hy = at(g, f, HY, i - 1, j, k) - at(g, f, HY, i, j, k);
         double src = jz ? jz[idx(g, i, j, k)] : 0.0;
@@ -194,7 +216,7 @@ static void upd_ez(const orc_geom* g, double* const m[6], double* f[6], double a
 /* S6 / S9: e_x += alpha kappa_x [P_z^T h_y - P_y^T h_z - j_x] */
 static void upd_ex(const orc_geom* g, double* const m[6], double* f[6], double a, const double* jx)
 {
-    LOOP(g, EX) {
+    PLOOP(g, EX) {
         double pzt_hy = at(g, f, HY, i, j, k - 1) - at(g, f, HY, i, j, k);
         double pyt_hz = at(g, f, HZ, i, j - 1, k) - at(g, f, HZ, i, j, k);
         double src = jx ? jx[idx(g, i, j, k)] : 0.0;
@@ -205,7 +227,7 @@ static void upd_ex(const orc_geom* g, double* const m[6], double* f[6], double a
 /* S7 / S10: e_y += alpha kappa_y [-P_z^T h_x + P_x^T h_z - j_y] */
 static void upd_ey(const orc_geom* g, double* const m[6], double* f[6], double a, const double* jy)
 {
-    LOOP(g, EY) {
+    PLOOP(g, EY) {
         double pzt_hx = at(g, f, HX, i, j, k - 1) - at(g, f, HX, i, j, k);
         double pxt_hz = at(g, f, HZ, i - 1, j, k) - at(g, f, HZ, i, j, k);
         double src = jy ? jy[idx(g, i, j, k)] : 0.0;
@@ -216,7 +238,7 @@ static void upd_ey(const orc_geom* g, double* const m[6], double* f[6], double a
 /* S8: h_z += 2 alpha mu_z [P_y e_x - P_x e_y] */
 static void upd_hz(const orc_geom* g, double* const m[6], double* f[6], double a2)
 {
-    LOOP(g, HZ) {
+    PLOOP(g, HZ) {
         double py_ex = at(g, f, EX, i, j + 1, k) - at(g, f, EX, i, j, k);
         double px_ey = at(g, f, EY, i + 1, j, k) - at(g, f, EY, i, j, k);
         f[HZ][idx(g, i, j, k)] += a2 * m[HZ][idx(g, i, j, k)] * (py_ex - px_ey);

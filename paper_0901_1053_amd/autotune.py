@@ -38,6 +38,13 @@ class Shape:
     def as_dict(self):
         return {"xchunk": self.xchunk, "order": self.order, "rows": self.rows, "depth": self.depth, "ms": self.ms}
 
+    @classmethod
+    def from_dict(cls, d):
+        return cls(**{k: d[k] for k in ("xchunk", "order", "rows", "depth", "ms") if k in d})
+
+    def key(self):
+        return (self.xchunk, self.order, self.rows, self.depth)
+
 
 class Tuner:
     def __init__(self, cache_path: str | None = DEFAULT_CACHE, xchunks=(0, 16, 32, 64, 128), orders=(1, 2),
@@ -49,6 +56,9 @@ class Tuner:
         self.cache_path = cache_path
         self.xchunks, self.orders, self.rows, self.depths = xchunks, orders, rows, depths
         self.steps, self.warmup = steps, warmup
+        # ms per step of every candidate timed for the last class tuned (or
+        # read from the cache), keyed by (xchunk, order, rows, depth)
+        self.timed = {}
         self.cache = {}
         if cache_path and os.path.exists(cache_path):
             try:
@@ -122,16 +132,22 @@ class Tuner:
     def tune(self, nx, ny, nz, dx, dy, dz, cdt, precision="fp32", force=False) -> Shape:
         key = self._key(nx, ny, nz, precision)
         if not force and key in self.cache:
-            return Shape(**self.cache[key])
+            ent = self.cache[key]
+            self.timed = {tuple(t[:4]): t[4] for t in ent.get("timed", [])}
+            return Shape.from_dict(ent)
         best = None
+        self.timed = {}
         for cand in self.candidates():
             cand.ms = self.measure(nx, ny, nz, dx, dy, dz, cdt, precision, cand)
+            self.timed[cand.key()] = cand.ms
             if best is None or cand.ms < best.ms:
                 best = cand
-        self.cache[key] = best.as_dict()
+        ent = best.as_dict()
+        ent["timed"] = [list(k) + [v] for k, v in self.timed.items()]
+        self.cache[key] = ent
         self.save()
         return best
 
     def lookup(self, nx, ny, nz, precision) -> Shape | None:
         v = self.cache.get(self._key(nx, ny, nz, precision))
-        return Shape(**v) if v else None
+        return Shape.from_dict(v) if v else None

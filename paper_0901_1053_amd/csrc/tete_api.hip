@@ -23,7 +23,7 @@ size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t lam, wacc, wit, wmid, partial, scal, pidx, eser, pser, code, field[12], mat[6], imp[4], imp_le, imp_lh,
-        imp_cnt, skip, skip_act, total;
+        imp_cnt, skip[2], skip_act[2], total;
 };
 
 int64_t series_cap(const tete_grid_desc* d) { return d->max_series > 0 ? d->max_series : 4096; }
@@ -61,12 +61,14 @@ bool make_layout(const tete_grid_desc* d, Layout* L)
         L->imp_lh = o;  o = up(o + sizeof(int) * (size_t)np);
         L->imp_cnt = o; o = up(o + sizeof(int) * 2 * (size_t)implicit_list_chunks(np));
     }
-    L->skip = L->skip_act = 0;
-    if (d->flags & TETE_F_SKIP_STATIC) {   // static-tile table and active-tile list
+    L->skip[0] = L->skip[1] = L->skip_act[0] = L->skip_act[1] = 0;
+    if (d->flags & TETE_F_SKIP_STATIC) {   // static-tile table and active-tile list of each tiling kind
         Geo g = {d->nx, d->ny, d->nz, d->nz + 1, (d->ny + 1) * (d->nz + 1), (int)np};
         const int64_t cap = skip_cap(g);
-        L->skip = o;     o = up(o + (size_t)cap);
-        L->skip_act = o; o = up(o + sizeof(int) * (size_t)cap);
+        for (int kind = 0; kind < 2; ++kind) {
+            L->skip[kind] = o;     o = up(o + (size_t)cap);
+            L->skip_act[kind] = o; o = up(o + sizeof(int) * (size_t)cap);
+        }
     }
     L->total = o;
     return true;
@@ -107,17 +109,22 @@ struct tete_grid {
     uint8_t* code;
     void* mat[6];
     int mat_set;
-    // static-tile skip (TETE_F_SKIP_STATIC): the table and the list of the
-    // skip_nact active tiles for the tiling (skip_rows, skip_xc, skip_order),
-    // skip_rows = -1 while none is built for the current codes; skip_live is
-    // set once a launch has written the other field set since the fields or
-    // codes were last set, so that both sets agree on every static tile
+    // static-tile skip (TETE_F_SKIP_STATIC): per tiling kind (0: two-step
+    // kernel, 1: fused single step) the table and the list of the
+    // skip_nact[kind] active tiles for the tiling (skip_rows, skip_xc,
+    // skip_order)[kind], skip_rows[kind] = -1 while none is built for the
+    // current codes or materials; skip_live is set once a launch has written
+    // the other field set since the fields or codes were last set, so that
+    // both sets agree on every static tile
     int skip;
-    uint8_t* skip_tab;
-    int* skip_act;
-    int skip_kind, skip_rows, skip_xc, skip_order, skip_nact;   // kind 0: two-step, 1: single step
-    int64_t skip_nt;
+    uint8_t* skip_tab[2];
+    int* skip_act[2];
+    int skip_rows[2], skip_xc[2], skip_order[2], skip_nact[2];
+    int64_t skip_nt[2];
     int skip_live;
+    // sticky error state: TETE_ERR_NONFINITE once a read-out found NaN or
+    // Inf, until tete_set_fields; tete_step refuses to run meanwhile
+    tete_status err;
     double *lam, *wacc, *partial, *scal, *eser, *pser;
     double* wit;       // witness accumulators, TETE_WITNESS_LINES x TETE_MAX_WAKE
     void* wmid;        // e_z^{n+1/2} of the witness lines in a two-step launch (TETE_WITNESS_LINES x nz)
@@ -206,6 +213,18 @@ WitMid<R> witness_mid(const tete_grid* g)
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
+// Read-out values of a grid: a NaN or Inf puts the grid into the sticky
+// TETE_ERR_NONFINITE state (cleared by tete_set_fields).
+tete_status check_finite(tete_grid* g, const double* v, int64_t n)
+{
+    for (int64_t e = 0; e < n; ++e)
+        if (!isfinite(v[e])) {
+            g->err = TETE_ERR_NONFINITE;
+            break;
+        }
+    return g->err;
+}
+
 // weight of the alpha^2 terms in the energy and the charges: none for the
 // implicit scheme (16), whose transverse operators are time-centred
 double rweight(const tete_grid* g) { return g->implicit ? 0.0 : 1.0; }
@@ -260,32 +279,42 @@ bool use_fused2(const tete_grid* g)
 
 // Builds the static-tile table for the current tiling of the two-step
 // kernel unless it is already there.
+// Builds the static-tile table and active list of one tiling kind (0: the
+// two-step kernel, 1: the fused single step) for the current tiling unless it
+// is already there.  Each kind keeps its own, so alternating two-step and
+// single launches do not rebuild them.
 template <typename R>
 tete_status static_table(tete_grid* g, bool wit, bool single)
 {
+    const int kind = single ? 1 : 0;
+    int rows, xc, order = g->tune.order;
     if (single) {   // the fused single step's tiling; kappa marks the PEC edges of materials
-        const int rows = g->mat_set || g->tune.rows == 32 ? 0 : g->tune.rows;
-        const int xc = g->tune.xchunk, order = g->tune.order;
-        if (g->skip_kind == 1 && g->skip_rows == rows && g->skip_xc == xc && g->skip_order == order) return TETE_OK;
-        const R* kap[3] = {(const R*)g->mat[0], (const R*)g->mat[1], (const R*)g->mat[2]};
-        HIPCHK(fused_static_tiles<R>(g->mat_set ? kap : nullptr, g->code, g->geo, rows, xc, order, g->skip_tab,
-                                     g->skip_act, skip_cap(g->geo), &g->skip_nt, &g->skip_nact, g->stream));
-        g->skip_kind = 1;
-        g->skip_rows = rows;
-        g->skip_xc = xc;
-        g->skip_order = order;
-        return TETE_OK;
+        rows = g->mat_set || g->tune.rows == 32 ? 0 : g->tune.rows;
+        xc = g->tune.xchunk;
+    } else {        // the instance that keeps witness lines has the default rows only
+        rows = wit ? 0 : fused2_rows(g);
+        xc = fused2_xchunk(g);
     }
-    // the instance that keeps witness lines has the default rows only
-    const int rows = wit ? 0 : fused2_rows(g), xc = fused2_xchunk(g), order = g->tune.order;
-    if (g->skip_kind == 0 && g->skip_rows == rows && g->skip_xc == xc && g->skip_order == order) return TETE_OK;
-    HIPCHK(fused2_static_tiles<R>(g->code, g->geo, rows, xc, order, g->skip_tab, g->skip_act, skip_cap(g->geo),
-                                  &g->skip_nt, &g->skip_nact, g->stream));
-    g->skip_kind = 0;
-    g->skip_rows = rows;
-    g->skip_xc = xc;
-    g->skip_order = order;
+    if (g->skip_rows[kind] == rows && g->skip_xc[kind] == xc && g->skip_order[kind] == order) return TETE_OK;
+    if (single) {
+        const R* kap[3] = {(const R*)g->mat[0], (const R*)g->mat[1], (const R*)g->mat[2]};
+        HIPCHK(fused_static_tiles<R>(g->mat_set ? kap : nullptr, g->code, g->geo, rows, xc, order, g->skip_tab[1],
+                                     g->skip_act[1], skip_cap(g->geo), &g->skip_nt[1], &g->skip_nact[1], g->stream));
+    } else {
+        HIPCHK(fused2_static_tiles<R>(g->code, g->geo, rows, xc, order, g->skip_tab[0], g->skip_act[0],
+                                      skip_cap(g->geo), &g->skip_nt[0], &g->skip_nact[0], g->stream));
+    }
+    g->skip_rows[kind] = rows;
+    g->skip_xc[kind] = xc;
+    g->skip_order[kind] = order;
     return TETE_OK;
+}
+
+// The static-tile tables no longer match the codes or materials.
+void skip_invalidate(tete_grid* g)
+{
+    g->skip_rows[0] = g->skip_rows[1] = -1;
+    g->skip_live = 0;
 }
 
 template <typename R>
@@ -326,14 +355,14 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             const int* act = nullptr;
             if (g->skip && g->skip_live) {
                 if (static_table<R>(g, wit, false) != TETE_OK) return TETE_ERR_DEVICE;
-                act = g->skip_act;
+                act = g->skip_act[0];
                 // static tiles store no witness values: their e_z is zero
                 if (wit) HIPCHK(launch_zero_bytes(g->wmid, (g->fp32 ? 4 : 8) * (size_t)TETE_WITNESS_LINES * g->d.nz,
                                                   g->stream));
             }
             HIPCHK(launch_step_fused2<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                          source(g, g->n), wit ? &wm : nullptr, fused2_rows(g), fused2_xchunk(g),
-                                         g->tune.order, g->stream, ev, act, g->skip_nact));
+                                         g->tune.order, g->stream, ev, act, g->skip_nact[0]));
             g->skip_live = 1;
             if (wit)   // e_z^{n-1/2} in the old set, e_z^{n+1/2} in wm.mid, e_z^{n+3/2} in the new set
                 HIPCHK(launch_witness2<R>((const R*)g->f[g->cur][2], wm.mid, (const R*)g->f[1 - g->cur][2],
@@ -359,11 +388,11 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             const int* act = nullptr;
             if (g->skip && g->skip_live) {
                 if (static_table<R>(g, false, true) != TETE_OK) return TETE_ERR_DEVICE;
-                act = g->skip_act;
+                act = g->skip_act[1];
             }
             HIPCHK(launch_step_fused<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                         source(g, g->n), g->tune.rows == 32 ? 0 : g->tune.rows, g->tune.xchunk,
-                                        g->tune.depth, g->tune.order, g->stream, ev, act, g->skip_nact));
+                                        g->tune.depth, g->tune.order, g->stream, ev, act, g->skip_nact[1]));
         }
         else
             HIPCHK(launch_step<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
@@ -488,12 +517,14 @@ tete_status tete_grid_create(const tete_grid_desc* d, void* dev_ws, size_t ws_by
     g->cur = 0;
     g->code = (uint8_t*)(g->ws + L.code);
     g->skip = (d->flags & TETE_F_SKIP_STATIC) != 0;
-    g->skip_tab = g->skip ? (uint8_t*)(g->ws + L.skip) : nullptr;
-    g->skip_act = g->skip ? (int*)(g->ws + L.skip_act) : nullptr;
-    g->skip_rows = -1;
-    g->skip_kind = g->skip_xc = g->skip_order = g->skip_nact = 0;
-    g->skip_nt = 0;
-    g->skip_live = 0;
+    for (int kind = 0; kind < 2; ++kind) {
+        g->skip_tab[kind] = g->skip ? (uint8_t*)(g->ws + L.skip[kind]) : nullptr;
+        g->skip_act[kind] = g->skip ? (int*)(g->ws + L.skip_act[kind]) : nullptr;
+        g->skip_xc[kind] = g->skip_order[kind] = g->skip_nact[kind] = 0;
+        g->skip_nt[kind] = 0;
+    }
+    skip_invalidate(g);
+    g->err = TETE_OK;
     for (int c = 0; c < 6; ++c) g->mat[c] = (d->flags & TETE_F_MATERIALS) ? g->ws + L.mat[c] : nullptr;
     g->lam = (double*)(g->ws + L.lam);
     g->wacc = (double*)(g->ws + L.wacc);
@@ -614,8 +645,7 @@ tete_status tete_set_pec_cells(tete_grid* g, const uint8_t* cells)
     HIPCHK(launch_build_codes(g->code, cells, g->geo, g->stream));
     g->mat_set = 0;
     g->imp_lists = 0;
-    g->skip_rows = -1;
-    g->skip_live = 0;
+    skip_invalidate(g);
     if (g->fp32) HIPCHK(launch_zero_pec<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->stream));
     else HIPCHK(launch_zero_pec<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->stream));
     return TETE_OK;
@@ -631,22 +661,30 @@ tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3], const
     DeviceGuard dg(g->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
     const void* src[6] = {inv_eps[0], inv_eps[1], inv_eps[2], inv_mu[0], inv_mu[1], inv_mu[2]};
+    {
+        // Q^e >= 0 (Sec. 4.4) by the Gershgorin row sums of its three blocks,
+        // before anything is imported: an unstable set leaves the grid as it was
+        double bound;
+        HIPCHK(launch_mat_bound(src, dtype == TETE_FP32, g->geo, g->alpha, g->partial, g->scal + 4, g->stream));
+        HIPCHK(hipMemcpyAsync(&bound, g->scal + 4, sizeof(double), hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipStreamSynchronize(g->stream));
+        if (!(bound == bound)) return TETE_ERR_ARG;           // a negative or non-finite value
+        if (bound > 1.0 + 1e-12) return TETE_ERR_UNSTABLE;
+    }
     if (g->tune.kernel == TETE_KERNEL_FUSED || g->tune.kernel == TETE_KERNEL_FUSED2) g->tune.kernel = TETE_KERNEL_AUTO;
     if (g->fp32) {
         float* dst[6];
         for (int c = 0; c < 6; ++c) dst[c] = (float*)g->mat[c];
         HIPCHK(launch_import_materials<float>(dst, src, dtype == TETE_FP32, g->geo, g->stream));
         g->mat_set = 1;
-        g->skip_rows = -1;
-        g->skip_live = 0;
+        skip_invalidate(g);
         HIPCHK(launch_zero_pec<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->stream));
     } else {
         double* dst[6];
         for (int c = 0; c < 6; ++c) dst[c] = (double*)g->mat[c];
         HIPCHK(launch_import_materials<double>(dst, src, dtype == TETE_FP32, g->geo, g->stream));
         g->mat_set = 1;
-        g->skip_rows = -1;
-        g->skip_live = 0;
+        skip_invalidate(g);
         HIPCHK(launch_zero_pec<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->stream));
     }
     return TETE_OK;
@@ -663,6 +701,7 @@ tete_status tete_set_fields(tete_grid* g, const void* const f[6], int32_t dtype)
     if (g->fp32) HIPCHK(launch_import<float>(fields<float>(g, g->cur), f, dtype == TETE_FP32, mats<float>(g), g->geo, g->stream));
     else HIPCHK(launch_import<double>(fields<double>(g, g->cur), f, dtype == TETE_FP32, mats<double>(g), g->geo, g->stream));
     g->skip_live = 0;
+    g->err = TETE_OK;
     return reset_series(g);
 }
 
@@ -673,12 +712,15 @@ tete_status tete_static_tiles(tete_grid* g, int64_t* skipped, int64_t* total)
     DeviceGuard dg(g->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
     const bool wit = g->witness && g->has_bunch;
-    // the tiling the next step takes: two steps at once, else the single step
-    const bool single = !use_fused2(g);
+    // the tiling of paired steps (the two-step kernel), or of the single step
+    // where tete_step pairs no steps: no two-step kernel, probes set, or an
+    // energy sample before every step
+    const bool single = !use_fused2(g) || g->nprobe > 0 || g->diag_every == 1;
     tete_status st = g->fp32 ? static_table<float>(g, wit, single) : static_table<double>(g, wit, single);
     if (st != TETE_OK) return st;
-    *skipped = g->skip_nt - g->skip_nact;
-    *total = g->skip_nt;
+    const int kind = single ? 1 : 0;
+    *skipped = g->skip_nt[kind] - g->skip_nact[kind];
+    *total = g->skip_nt[kind];
     return TETE_OK;
 }
 
@@ -747,6 +789,7 @@ tete_status tete_set_probes(tete_grid* g, const int64_t* idx, int32_t np_)
 tete_status tete_step(tete_grid* g, int64_t nsteps)
 {
     if (!g || nsteps < 0) return TETE_ERR_ARG;
+    if (g->err != TETE_OK) return g->err;
     if (nsteps == 0) return TETE_OK;
     // capacity of the series for the steps requested
     int64_t need_e = 0;
@@ -760,6 +803,25 @@ tete_status tete_step(tete_grid* g, int64_t nsteps)
     DeviceGuard dg(g->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
     return g->fp32 ? do_steps<float>(g, nsteps) : do_steps<double>(g, nsteps);
+}
+
+tete_status tete_grid_status(tete_grid* g)
+{
+    if (!g) return TETE_ERR_ARG;
+    return g->err;
+}
+
+tete_status tete_stream_probe(void* const in[6], void* const out[6], const uint8_t* code, int64_t n, int32_t dtype,
+                              void* hip_stream)
+{
+    if (!in || !out || !code || n < 0) return TETE_ERR_ARG;
+    if (dtype != TETE_FP64 && dtype != TETE_FP32) return TETE_ERR_ARG;
+    for (int c = 0; c < 6; ++c) {
+        if (!in[c] || !out[c] || ((uintptr_t)in[c] % 16) != 0 || ((uintptr_t)out[c] % 16) != 0) return TETE_ERR_ARG;
+    }
+    if (((uintptr_t)code % 4) != 0) return TETE_ERR_ARG;
+    HIPCHK(launch_stream(in, out, code, n, dtype == TETE_FP32, (hipStream_t)hip_stream));
+    return TETE_OK;
 }
 
 tete_status tete_steps_done(tete_grid* g, int64_t* n)
@@ -780,7 +842,7 @@ tete_status tete_wake(tete_grid* g, double* W, int32_t nw)
     HIPCHK(hipStreamSynchronize(g->stream));
     const double s = 1.0 / (g->b.charge_C * kEps0);
     for (int j = 0; j < nw; ++j) W[j] *= s;
-    return TETE_OK;
+    return check_finite(g, W, nw);
 }
 
 tete_status tete_set_witness(tete_grid* g, int32_t iw, int32_t jw)
@@ -817,6 +879,7 @@ tete_status tete_witness_wake(tete_grid* g, double* W, double* Wx, double* Wy, i
     HIPCHK(hipStreamSynchronize(g->stream));
     const double q = 1.0 / (g->b.charge_C * kEps0);
     for (size_t e = 0; e < (size_t)TETE_WITNESS_LINES * nw; ++e) W[e] *= q;
+    if (check_finite(g, W, (int64_t)TETE_WITNESS_LINES * nw) != TETE_OK) return g->err;
     // Panofsky-Wenzel: dW_perp/ds = grad_perp W_par, centred differences across
     // the witness node, trapezoid rule in s from the first sample
     const double ds = g->d.dz;
@@ -851,7 +914,7 @@ tete_status tete_energy(tete_grid* g, double* W, int64_t* n)
     HIPCHK(hipStreamSynchronize(g->stream));
     *W = v;
     if (n) *n = g->n;
-    return isfinite(v) ? TETE_OK : TETE_ERR_NONFINITE;
+    return check_finite(g, &v, 1);
 }
 
 tete_status tete_energy_series(tete_grid* g, double* out, int64_t max, int64_t* count)
@@ -864,7 +927,7 @@ tete_status tete_energy_series(tete_grid* g, double* out, int64_t max, int64_t* 
     if (c > 0) HIPCHK(hipMemcpyAsync(out, g->eser, sizeof(double) * c, hipMemcpyDeviceToHost, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
     *count = g->ecount;
-    return TETE_OK;
+    return check_finite(g, out, c);
 }
 
 tete_status tete_probes(tete_grid* g, double* out, int64_t max, int64_t* count)
@@ -876,7 +939,7 @@ tete_status tete_probes(tete_grid* g, double* out, int64_t max, int64_t* count)
     if (c > 0) HIPCHK(hipMemcpyAsync(out, g->pser, sizeof(double) * c, hipMemcpyDeviceToHost, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
     *count = g->pcount;
-    return TETE_OK;
+    return check_finite(g, out, c);
 }
 
 tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h)
@@ -897,7 +960,7 @@ tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h)
     HIPCHK(hipStreamSynchronize(g->stream));
     *max_res_e = v[0];
     *max_abs_h = v[1];
-    return (isfinite(v[0]) && isfinite(v[1])) ? TETE_OK : TETE_ERR_NONFINITE;
+    return check_finite(g, v, 2);
 }
 
 }  // extern "C"
@@ -1153,6 +1216,7 @@ tete_status tete_batch_set(tete_batch* b, int32_t slot, tete_grid* g)
         if (g->fp32 != b->fp32 || g->device != b->device) return TETE_ERR_ARG;
         if (g->yee || g->implicit || g->mat_set || g->witness || !fused_fits(g->geo, g->fp32 ? 4 : 8))
             return TETE_ERR_STATE;
+        if (g->err != TETE_OK) return g->err;
         for (int s = 0; s < TETE_MAX_BATCH; ++s)
             if (s != slot && b->slot[s] == g) return TETE_ERR_ARG;
     }
@@ -1180,8 +1244,10 @@ tete_status tete_batch_step(tete_batch* b, int64_t nsteps)
 {
     if (!b || nsteps < 0) return TETE_ERR_ARG;
     if (nsteps == 0) return TETE_OK;
-    for (int s = 0; s < TETE_MAX_BATCH; ++s)   // a witness set after joining: batched steps would skip it
+    for (int s = 0; s < TETE_MAX_BATCH; ++s) {   // a witness set after joining: batched steps would skip it
         if (b->slot[s] && b->slot[s]->witness) return TETE_ERR_STATE;
+        if (b->slot[s] && b->slot[s]->err != TETE_OK) return b->slot[s]->err;
+    }
     DeviceGuard dg(b->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
     return b->fp32 ? batch_step<float>(b, nsteps) : batch_step<double>(b, nsteps);

@@ -202,6 +202,17 @@ hipError_t launch_batch_advance(BatchTable<R>* T, int steps, int flips, hipStrea
 template <typename R>
 hipError_t launch_energy(Fields<R> f, Mat<R> mat, Geo g, double alpha, double rw, double* partial, double* out,
                          hipStream_t s);
+// Largest Gershgorin row sum of the three blocks of Q^e (Sec. 4.4) for
+// general materials src[6] (kappa_x,y,z, mu_x,y,z; FP32 if src_fp32) ->
+// out[0]: Q^e >= 0 if it is at most 1; NaN if a value in a component's range
+// is negative or not finite.  Uses partial[RED_BLOCKS].
+hipError_t launch_mat_bound(const void* const src[6], int src_fp32, Geo g, double alpha, double* partial,
+                            double* out, hipStream_t s);
+// Streaming ceiling of the step's access pattern: out_c = in_c for six arrays
+// of n entries (FP32 or FP64, 16-byte aligned), the code byte of each entry
+// read as well.
+hipError_t launch_stream(void* const in[6], void* const out[6], const uint8_t* code, int64_t n, int fp32,
+                         hipStream_t s);
 // charges: out[0] = max |q_e - node charge| (interior nodes), out[1] = max |q_h|
 template <typename R>
 hipError_t launch_charges(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, double alpha, Src src,

@@ -545,6 +545,142 @@ __global__ void k_witness2(const R* ez_old, const R* ez_mid, const R* ez_new, Wi
     acc[(int64_t)l * TETE_MAX_WAKE + t] = a;
 }
 
+// ---------------------------------------------------------------------------
+// Stability of general diagonal materials (Sec. 4.4: the scheme is stable when
+// Q^e is positive definite).  In the scaled variables a = h / sqrt(mu),
+// b = e / sqrt(kappa) the form 2 W^{n,e} = |u|^2 + |v|^2 - alpha^2 (<R_0 u, u>
+// + <R_1 v, v>) + 2 alpha <L v, u> falls into three independent blocks:
+//   e_z alone:  I - alpha^2 R_0, with R_0 the transverse mu-weighted
+//               difference operator on the kappa_z-scaled e_z;
+//   h_z alone:  I - alpha^2 R_1, the same with kappa_x, kappa_y on h_z;
+//   (h_x, h_y, e_x, e_y):  [[I, alpha L], [alpha L^T, I]], L = the
+//               z-differences between h_x and e_y, h_y and e_x.
+// Each block is positive semi-definite when, in every row, the diagonal part
+// subtracted from the identity plus the off-diagonal magnitudes is at most 1
+// (Gershgorin).  This kernel forms those row sums for the rows of every
+// entry and reduces their maximum; with vacuum coefficients it is
+// max(cdt^2 (dx^-2 + dy^-2), cdt / dz) at interior rows, the bound (25).
+// Entries outside a component's index range are not read; a negative or
+// non-finite value in range makes the result NaN.
+// ---------------------------------------------------------------------------
+template <typename S>
+struct MatSrc {
+    const S* c[6];   // kappa_x, kappa_y, kappa_z, mu_x, mu_y, mu_z
+};
+
+template <typename S>
+__device__ __forceinline__ double msrc(const MatSrc<S>& m, int c, const Geo& g, int i, int j, int k)
+{
+    if (!in_nodes(g, i, j, k) || !comp_ok(c, g, i, j, k)) return 0.0;
+    return (double)m.c[c][lin(g, i, j, k)];
+}
+
+template <typename S>
+__global__ __launch_bounds__(RED_THREADS) void k_mat_bound(MatSrc<S> m, Geo g, double a, double* partial)
+{
+    double worst = 0.0;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < g.np; idx += gridDim.x * blockDim.x) {
+        int i, j, k;
+        decomp(idx, g, i, j, k);
+        bool bad = false;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            if (!comp_ok(c, g, i, j, k)) continue;
+            const double v = (double)m.c[c][idx];
+            if (!(v >= 0.0) || v > DBL_MAX) bad = true;
+        }
+        if (bad) {
+            worst = NAN;
+            continue;
+        }
+        double s = 0.0;
+        // e_z row: alpha^2 sum over its four h facets of mu (kappa_z + sqrt(kappa_z kappa_z'))
+        const double kz = msrc(m, 2, g, i, j, k);
+        if (kz > 0.0) {
+            const double r = msrc(m, 3, g, i, j, k) * (kz + sqrt(kz * msrc(m, 2, g, i, j + 1, k)))
+                           + msrc(m, 3, g, i, j - 1, k) * (kz + sqrt(kz * msrc(m, 2, g, i, j - 1, k)))
+                           + msrc(m, 4, g, i, j, k) * (kz + sqrt(kz * msrc(m, 2, g, i + 1, j, k)))
+                           + msrc(m, 4, g, i - 1, j, k) * (kz + sqrt(kz * msrc(m, 2, g, i - 1, j, k)));
+            s = fmax(s, a * a * r);
+        }
+        // h_z row: alpha^2 sum over its four e edges of kappa (mu_z + sqrt(mu_z mu_z'))
+        const double mz = msrc(m, 5, g, i, j, k);
+        if (mz > 0.0) {
+            const double r = msrc(m, 0, g, i, j, k) * (mz + sqrt(mz * msrc(m, 5, g, i, j - 1, k)))
+                           + msrc(m, 0, g, i, j + 1, k) * (mz + sqrt(mz * msrc(m, 5, g, i, j + 1, k)))
+                           + msrc(m, 1, g, i, j, k) * (mz + sqrt(mz * msrc(m, 5, g, i - 1, j, k)))
+                           + msrc(m, 1, g, i + 1, j, k) * (mz + sqrt(mz * msrc(m, 5, g, i + 1, j, k)));
+            s = fmax(s, a * a * r);
+        }
+        // rows of the L block: h_x with e_y at k, k+1; h_y with e_x at k, k+1;
+        // e_y with h_x at k-1, k; e_x with h_y at k-1, k
+        const double mx = msrc(m, 3, g, i, j, k), my = msrc(m, 4, g, i, j, k);
+        const double kx = msrc(m, 0, g, i, j, k), ky = msrc(m, 1, g, i, j, k);
+        s = fmax(s, a * sqrt(mx) * (sqrt(ky) + sqrt(msrc(m, 1, g, i, j, k + 1))));
+        s = fmax(s, a * sqrt(my) * (sqrt(kx) + sqrt(msrc(m, 0, g, i, j, k + 1))));
+        s = fmax(s, a * sqrt(ky) * (sqrt(mx) + sqrt(msrc(m, 3, g, i, j, k - 1))));
+        s = fmax(s, a * sqrt(kx) * (sqrt(my) + sqrt(msrc(m, 4, g, i, j, k - 1))));
+        worst = nan_max(worst, s);
+    }
+    const double r = block_reduce<true>(worst);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Streaming ceiling of the step's access pattern: six arrays and the PEC code
+// byte read, six arrays written, every access a coalesced 16-byte load or
+// store (four consecutive entries per thread).  out_c[i] = in_c[i], or 0
+// where bit 7 of code[i] is set (never for the library's codes, but the code
+// must be read).  n is a multiple of 4 handled by whole threads; the host
+// copies the remainder with a second launch of this kernel at offset.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Six {
+    R* c[6];
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_stream(Six<R> in, Six<R> out, const uint8_t* code, int64_t n4)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n4) return;
+    const uint32_t cw = ((const uint32_t*)code)[t];
+    if constexpr (sizeof(R) == 4) {
+        const uint32_t keep[4] = {(cw & 0x80u) ? 0u : ~0u, (cw & 0x8000u) ? 0u : ~0u, (cw & 0x800000u) ? 0u : ~0u,
+                                  (cw & 0x80000000u) ? 0u : ~0u};
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            uint4 v = ((const uint4*)in.c[c])[t];
+            v.x &= keep[0];
+            v.y &= keep[1];
+            v.z &= keep[2];
+            v.w &= keep[3];
+            ((uint4*)out.c[c])[t] = v;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            uint4 v0 = ((const uint4*)in.c[c])[2 * t], v1 = ((const uint4*)in.c[c])[2 * t + 1];
+            if (cw & 0x80u) v0.x = v0.y = 0u;
+            if (cw & 0x8000u) v0.z = v0.w = 0u;
+            if (cw & 0x800000u) v1.x = v1.y = 0u;
+            if (cw & 0x80000000u) v1.z = v1.w = 0u;
+            ((uint4*)out.c[c])[2 * t] = v0;
+            ((uint4*)out.c[c])[2 * t + 1] = v1;
+        }
+    }
+}
+
+template <typename R>
+__global__ void k_stream_tail(Six<R> in, Six<R> out, const uint8_t* code, int64_t from, int64_t n)
+{
+    const int64_t i = from + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool z = (code[i] & 0x80u) != 0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) out.c[c][i] = z ? R(0) : in.c[c][i];
+}
+
 inline int nblocks(int64_t n, int tb) { return (int)((n + tb - 1) / tb); }
 
 }  // namespace
@@ -636,6 +772,45 @@ hipError_t launch_step(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alph
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     return hipSuccess;
+}
+
+hipError_t launch_mat_bound(const void* const src[6], int src_fp32, Geo g, double alpha, double* partial,
+                            double* out, hipStream_t s)
+{
+    if (src_fp32) {
+        MatSrc<float> m;
+        for (int c = 0; c < 6; ++c) m.c[c] = (const float*)src[c];
+        k_mat_bound<float><<<RED_BLOCKS, RED_THREADS, 0, s>>>(m, g, alpha, partial);
+    } else {
+        MatSrc<double> m;
+        for (int c = 0; c < 6; ++c) m.c[c] = (const double*)src[c];
+        k_mat_bound<double><<<RED_BLOCKS, RED_THREADS, 0, s>>>(m, g, alpha, partial);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_finish<true><<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream(void* const in[6], void* const out[6], const uint8_t* code, int64_t n, int fp32,
+                         hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t n4 = n / 4;
+    auto run = [&](auto tag) -> hipError_t {
+        typedef decltype(tag) R;
+        Six<R> a, b;
+        for (int c = 0; c < 6; ++c) {
+            a.c[c] = (R*)in[c];
+            b.c[c] = (R*)out[c];
+        }
+        if (n4 > 0) k_stream<R><<<(unsigned)((n4 + 255) / 256), 256, 0, s>>>(a, b, code, n4);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (4 * n4 < n) k_stream_tail<R><<<1, 256, 0, s>>>(a, b, code, 4 * n4, n);
+        return hipGetLastError();
+    };
+    return fp32 ? run(float(0)) : run(double(0));
 }
 
 template <typename R>

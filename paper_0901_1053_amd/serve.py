@@ -140,11 +140,19 @@ class GpuExecutor:
             self.batch.set(slot, G)
 
     def step(self, k):
+        """Step every admitted request by k and wait until the block is done:
+        at most one block is in flight, so a request that arrives meanwhile
+        is admitted before the next block, not at the next completion."""
         if self.batch is not None:
             self.batch.step(k)
+            stream = self.batch.stream
         else:
             for G in self.grids.values():
                 G.step(k)
+            stream = self.torch.cuda.current_stream(self.device)
+        ev = self.torch.cuda.Event()
+        ev.record(stream)
+        ev.synchronize()
 
     def finish(self, slot):
         G = self.grids.pop(slot)

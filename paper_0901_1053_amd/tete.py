@@ -98,6 +98,8 @@ def load(path: str = LIB_PATH):
         "tete_set_probes": (st, [vp, vp, C.c_int32]),
         "tete_step": (st, [vp, C.c_int64]),
         "tete_steps_done": (st, [vp, C.POINTER(C.c_int64)]),
+        "tete_grid_status": (st, [vp]),
+        "tete_stream_probe": (st, [P6, P6, vp, C.c_int64, C.c_int32, vp]),
         "tete_wake": (st, [vp, vp, C.c_int32]),
         "tete_set_witness": (st, [vp, C.c_int32, C.c_int32]),
         "tete_clear_witness": (st, [vp]),
@@ -283,6 +285,10 @@ class Grid:
         _chk("tete_steps_done", load().tete_steps_done(self.h, C.byref(v)))
         return v.value
 
+    def status(self) -> str:
+        """The grid's sticky error state: "TETE_OK" or "TETE_ERR_NONFINITE"."""
+        return STATUS[load().tete_grid_status(self.h)]
+
     # -- results --------------------------------------------------------
     def wake(self) -> np.ndarray:
         """W(s_j) in V/C for j = jmin .. jmin+nw-1."""
@@ -411,6 +417,23 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def stream_probe(src: list, dst: list, code, stream=None):
+    """tete_stream_probe: dst[c] = src[c] for six device tensors of one dtype
+    (float32 or float64, same length n), reading the uint8 device tensor code
+    (n entries) as well; asynchronous on `stream` (default: the current one)."""
+    import torch
+    n = src[0].numel()
+    assert len(src) == 6 and len(dst) == 6 and code.numel() == n and code.dtype == torch.uint8
+    for a in list(src) + list(dst):
+        assert a.numel() == n and a.dtype == src[0].dtype and a.is_contiguous()
+    dt = {torch.float32: FP32, torch.float64: FP64}[src[0].dtype]
+    s = stream if stream is not None else torch.cuda.current_stream(src[0].device)
+    _chk("tete_stream_probe", load().tete_stream_probe(P6(*[a.data_ptr() for a in src]),
+                                                       P6(*[a.data_ptr() for a in dst]),
+                                                       C.c_void_p(code.data_ptr()), n, dt,
+                                                       C.c_void_p(s.cuda_stream)))
 
 
 def make_rz_desc(nr, nz, dr, dz, cdt, mode=0, precision="fp64") -> RZDesc:

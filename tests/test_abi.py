@@ -88,11 +88,12 @@ def test_workspace_bytes():
     dm = tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp64", materials=True)
     assert tete.workspace_bytes(dm) >= b64 + 6 * 8 * np_
     assert tete.workspace_bytes(tete.make_desc(1, 1, 1, 2, 2, 1, 1)) == 0
-    # the static-tile table and the active-tile list: one byte and one int32
-    # per tile of the finest tiling (single planes, 10 rows by 28 entries)
+    # the static-tile table and the active-tile list of each tiling kind (the
+    # two-step kernel's and the single step's): one byte and one int32 per
+    # tile of the finest tiling (single planes, 10 rows by 28 entries)
     ds = tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp64", skip_static=True)
     cap = 129 * -(-129 // 10) * -(-1025 // 28)
-    assert 5 * cap <= tete.workspace_bytes(ds) - b64 <= 5 * cap + 512
+    assert 10 * cap <= tete.workspace_bytes(ds) - b64 <= 10 * cap + 1024
 
 
 @pytest.mark.parametrize("mode,dr,dz,cdt,want", [
@@ -156,3 +157,6 @@ def test_witness_entry_points_check_handles():
     assert tete.STATUS[L.tete_set_witness(None, 1, 1)] == "TETE_ERR_ARG"
     assert tete.STATUS[L.tete_clear_witness(None)] == "TETE_ERR_ARG"
     assert tete.STATUS[L.tete_witness_wake(None, None, None, None, 1)] == "TETE_ERR_ARG"
+    assert tete.STATUS[L.tete_grid_status(None)] == "TETE_ERR_ARG"
+    null6 = tete.P6(*([None] * 6))
+    assert tete.STATUS[L.tete_stream_probe(null6, null6, None, 16, tete.FP32, None)] == "TETE_ERR_ARG"

@@ -59,3 +59,25 @@ def test_one_at_a_time_baseline_fp64():
     assert st.completed == 3 and st.max_active == 1
     for r in reqs:
         assert np.array_equal(r.wake, _solo(r.case, "fp64"))
+
+
+def test_arrival_during_a_long_solve_is_admitted_before_it_completes():
+    """A request that arrives while a long solve is on the device is admitted
+    at the next block boundary (the executor keeps one block in flight), so it
+    runs beside the long solve and finishes first; its wake is the one it
+    gets alone."""
+    big = inputs.scaled_wake_case(192, 1024, seed=3)
+    small = inputs.scaled_wake_case(24, 64, seed=4, sigma_dz=2.0)
+    reqs = [serve.Request(0, big, 0.0), serve.Request(1, small, 0.2)]
+    ex = serve.GpuExecutor("fp32", batch=True, graph_steps=8)
+    st = serve.Server(ex, max_slots=4, block_steps=64).run(reqs)
+    ex.close()
+    b, s = reqs
+    print("big admitted %.3f done %.3f; small arrival %.3f admitted %.3f done %.3f"
+          % (b.admitted, b.done, s.arrival, s.admitted, s.done), flush=True)
+    assert st.completed == 2 and st.max_active == 2
+    assert b.admitted <= s.arrival < b.done            # the long solve is running when it arrives
+    assert s.arrival <= s.admitted < b.done             # admitted before the long solve completes
+    assert s.done < b.done
+    assert np.array_equal(s.wake, _solo(small, "fp32"))
+    assert np.array_equal(b.wake, _solo(big, "fp32"))
