@@ -180,22 +180,25 @@ def _tuned(cases, precision):
 
 
 def single_grid_tuning(G, steps=6):
-    """Launch shapes of the two-step kernel on the headline grid (rows 16 or
-    32, tile order, x-chunk), kernel time per step from the grid's own timing;
+    """Launch shapes of the two-step kernel on the headline grid (rows and
+    planes loaded ahead, tile order, x-chunk; depth 0 is the shape's default),
+    kernel time per step from the grid's own timing;
     the grid's shape is restored afterwards.  The headline uses the library's
     default shape."""
     saved = G.get_tuning()
     rows_ = []
-    for rows in (16, 32):
+    shapes = [(16, 0), (16, 2), (24, 1), (24, 0), (24, 3), (32, 0)] if G.precision == "fp32" else [(16, 0)]
+    for rows, depth in shapes:
         for order in (2, 4):
             for xc in (0, 128):
-                G.set_tuning("fused2", rows, xc, 0, order)
+                G.set_tuning("fused2", rows, xc, depth, order)
                 G.step(2)
                 G.set_timing(steps)
                 G.step(steps)
                 ms, _, n = G.timing()
                 G.set_timing(0)
-                rows_.append({"rows": rows, "order": order, "xchunk": xc, "ms_per_step": round(ms / n, 4)})
+                rows_.append({"rows": rows, "depth": depth, "order": order, "xchunk": xc,
+                              "ms_per_step": round(ms / n, 4)})
     G.set_tuning(saved["kernel"], saved["rows"], saved["xchunk"], saved["depth"], saved["order"])
     best = min(rows_, key=lambda r: r["ms_per_step"])
     return {"candidates": rows_, "best": best}

@@ -277,46 +277,62 @@ void orc_step(const orc_geom* g, double* const m[6], double* f[6],
  *   <R_1 v, v>         = sum_{ex, kappa>0} kappa_x (P_y^T h_z)^2 + sum_{ey, kappa>0} kappa_y (P_x^T h_z)^2
  *   <L v, u>           = sum_hx h_x P_z e_y - sum_hy h_y P_z e_x
  */
+/* Compensated running sum (Neumaier's variant of Kahan summation): a grid's
+ * energy adds up ~1e8 terms, and a plain running sum of that many loses about
+ * 1e-12 of the total, the size of the parity tolerance; the compensation
+ * keeps the rounding error of the sum near one unit of the result. */
+typedef struct { double s, c; } orc_sum;
+
+static void add(orc_sum* a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+static double total(const orc_sum* a) { return a->s + a->c; }
+
 double orc_energy(const orc_geom* g, double* const m[6], double* f[6])
 {
     const double a = 0.5 * g->cdt;
-    double sq = 0.0, r0 = 0.0, r1 = 0.0, lc = 0.0;
+    orc_sum sq = {0, 0}, r0 = {0, 0}, r1 = {0, 0}, lc = {0, 0};
     for (int c = EX; c <= EZ; ++c)
         LOOP(g, c) {
             double kap = m[c][idx(g, i, j, k)];
-            if (kap > 0.0) { double e = f[c][idx(g, i, j, k)]; sq += e * e / kap; }
+            if (kap > 0.0) { double e = f[c][idx(g, i, j, k)]; add(&sq, e * e / kap); }
         }
     for (int c = HX; c <= HZ; ++c)
         LOOP(g, c) {
             double mu = m[c][idx(g, i, j, k)];
             double h = f[c][idx(g, i, j, k)];
-            if (mu > 0.0) sq += h * h / mu;
+            if (mu > 0.0) add(&sq, h * h / mu);
         }
     LOOP(g, HX) {
         double d = at(g, f, EZ, i, j + 1, k) - at(g, f, EZ, i, j, k);
-        r0 += m[HX][idx(g, i, j, k)] * d * d;
-        lc += f[HX][idx(g, i, j, k)] * (at(g, f, EY, i, j, k + 1) - at(g, f, EY, i, j, k));
+        add(&r0, m[HX][idx(g, i, j, k)] * d * d);
+        add(&lc, f[HX][idx(g, i, j, k)] * (at(g, f, EY, i, j, k + 1) - at(g, f, EY, i, j, k)));
     }
     LOOP(g, HY) {
         double d = at(g, f, EZ, i + 1, j, k) - at(g, f, EZ, i, j, k);
-        r0 += m[HY][idx(g, i, j, k)] * d * d;
-        lc -= f[HY][idx(g, i, j, k)] * (at(g, f, EX, i, j, k + 1) - at(g, f, EX, i, j, k));
+        add(&r0, m[HY][idx(g, i, j, k)] * d * d);
+        add(&lc, -f[HY][idx(g, i, j, k)] * (at(g, f, EX, i, j, k + 1) - at(g, f, EX, i, j, k)));
     }
     LOOP(g, EX) {
         double kap = m[EX][idx(g, i, j, k)];
         if (kap > 0.0) {
             double d = at(g, f, HZ, i, j - 1, k) - at(g, f, HZ, i, j, k);
-            r1 += kap * d * d;
+            add(&r1, kap * d * d);
         }
     }
     LOOP(g, EY) {
         double kap = m[EY][idx(g, i, j, k)];
         if (kap > 0.0) {
             double d = at(g, f, HZ, i - 1, j, k) - at(g, f, HZ, i, j, k);
-            r1 += kap * d * d;
+            add(&r1, kap * d * d);
         }
     }
-    return 0.5 * sq - 0.5 * a * a * (r0 + r1) + a * lc;
+    return 0.5 * total(&sq) - 0.5 * a * a * (total(&r0) + total(&r1)) + a * total(&lc);
 }
 
 /*

@@ -255,12 +255,12 @@ bool use_fused(const tete_grid* g)
 // The two-step kernel (automatic choice, or asked for) when the grid
 // qualifies; do_steps still takes single steps where a diagnostic needs the
 // state in between.
-// Rows of the two-step kernel: the tuning's rows when it asks for 16 or 32
-// (32: FP32 only), else the default.
+// Rows of the two-step kernel: the tuning's rows when it asks for 16, 24 or
+// 32 (24, 32: FP32 only), else the default.
 int fused2_rows(const tete_grid* g)
 {
     const int r = g->tune.rows;
-    return r == 16 || (r == 32 && g->fp32) ? r : 0;
+    return r == 16 || ((r == 24 || r == 32) && g->fp32) ? r : 0;
 }
 
 // X-chunk of the two-step kernel: the tuning's, else for grids that skip
@@ -289,7 +289,7 @@ tete_status static_table(tete_grid* g, bool wit, bool single)
     const int kind = single ? 1 : 0;
     int rows, xc, order = g->tune.order;
     if (single) {   // the fused single step's tiling; kappa marks the PEC edges of materials
-        rows = g->mat_set || g->tune.rows == 32 ? 0 : g->tune.rows;
+        rows = g->mat_set || g->tune.rows == 24 || g->tune.rows == 32 ? 0 : g->tune.rows;
         xc = g->tune.xchunk;
     } else {        // the instance that keeps witness lines has the default rows only
         rows = wit ? 0 : fused2_rows(g);
@@ -361,7 +361,8 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
                                                   g->stream));
             }
             HIPCHK(launch_step_fused2<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
-                                         source(g, g->n), wit ? &wm : nullptr, fused2_rows(g), fused2_xchunk(g),
+                                         source(g, g->n), wit ? &wm : nullptr, fused2_rows(g), g->tune.depth,
+                                         fused2_xchunk(g),
                                          g->tune.order, g->stream, ev, act, g->skip_nact[0]));
             g->skip_live = 1;
             if (wit)   // e_z^{n-1/2} in the old set, e_z^{n+1/2} in wm.mid, e_z^{n+3/2} in the new set
@@ -391,7 +392,8 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
                 act = g->skip_act[1];
             }
             HIPCHK(launch_step_fused<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
-                                        source(g, g->n), g->tune.rows == 32 ? 0 : g->tune.rows, g->tune.xchunk,
+                                        source(g, g->n), g->tune.rows == 24 || g->tune.rows == 32 ? 0 : g->tune.rows,
+                                        g->tune.xchunk,
                                         g->tune.depth, g->tune.order, g->stream, ev, act, g->skip_nact[1]));
         }
         else
@@ -544,7 +546,7 @@ tete_status tete_grid_create(const tete_grid_desc* d, void* dev_ws, size_t ws_by
     g->tune.kernel = TETE_KERNEL_AUTO;
     g->tune.rows = 0;
     g->tune.xchunk = 0;
-    g->tune.depth = 2;
+    g->tune.depth = 0;
     g->tune.order = 0;
 
     // zero the whole workspace, then mark the box walls
@@ -571,13 +573,12 @@ tete_status tete_set_tuning(tete_grid* g, const tete_tuning* t)
 {
     if (!g || !t) return TETE_ERR_ARG;
     if (t->kernel < TETE_KERNEL_AUTO || t->kernel > TETE_KERNEL_FUSED2) return TETE_ERR_ARG;
-    if (t->rows != 0 && t->rows != 12 && t->rows != 16 && t->rows != 32) return TETE_ERR_ARG;
+    if (t->rows != 0 && t->rows != 12 && t->rows != 16 && t->rows != 24 && t->rows != 32) return TETE_ERR_ARG;
     if (t->xchunk < 0) return TETE_ERR_ARG;
     if (t->depth < 0 || t->depth > 3) return TETE_ERR_ARG;
     if (t->order < 0 || t->order > 6) return TETE_ERR_ARG;
     if (t->kernel == TETE_KERNEL_FUSED2 && g->mat_set) return TETE_ERR_STATE;
     g->tune = *t;
-    if (g->tune.depth == 0) g->tune.depth = 2;
     return TETE_OK;
 }
 

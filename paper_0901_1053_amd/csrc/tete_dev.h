@@ -12,17 +12,19 @@
 namespace tete {
 namespace {
 
+// Raw buffer load of one field value at byte offset off (vector) + soff
+// (scalar); a lane whose off is past the buffer's size reads 0.
 template <typename R>
-__device__ __forceinline__ R bload(__amdgpu_buffer_rsrc_t r, uint32_t off);
+__device__ __forceinline__ R bload(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff = 0);
 template <>
-__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, 0));
 }
 template <>
-__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff)
 {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
 }
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 template <typename R>
@@ -39,9 +41,10 @@ __device__ __forceinline__ void bstore<double>(__amdgpu_buffer_rsrc_t r, uint32_
 }
 
 // Neighbours along k are the neighbouring lanes of the wave: DPP whole-wave
-// shifts by one lane (lane 0 / lane 63 receive 0; both are halo lanes).
-__device__ __forceinline__ int dpp_prev(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
-__device__ __forceinline__ int dpp_next(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+// shifts by one lane (lane 0 / lane 63 receive 0; both are halo lanes).  The
+// bound control writes the 0, so no register has to be cleared first.
+__device__ __forceinline__ int dpp_prev(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_next(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true); }
 __device__ __forceinline__ float lane_prev(float v) { return __builtin_bit_cast(float, dpp_prev(__builtin_bit_cast(int, v))); }
 __device__ __forceinline__ float lane_next(float v) { return __builtin_bit_cast(float, dpp_next(__builtin_bit_cast(int, v))); }
 typedef int i32x2 __attribute__((ext_vector_type(2)));

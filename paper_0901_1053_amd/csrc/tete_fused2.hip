@@ -165,24 +165,26 @@ template <typename R, int TYH, int LW>
 struct Shape2 {
     static constexpr int rows = TYH, nb = 2, lw = LW, threads = TYH * LW;
 };
-// default rows and lanes per row of the two-step kernel, and the other
-// shape (FP32: 32 rows of 32 lanes, owning 26 x 28, selected by rows = 32)
+// default rows, lanes per row and planes prefetched of the two-step kernel,
+// and the other FP32 shapes: 24 rows of 32 lanes (768 threads, owning
+// 18 x 28; 168 VGPRs per wave hold two prefetched planes) and 32 rows of 32
+// lanes (owning 26 x 28), selected by rows = 24 or 32
 template <typename R> struct Default2;
-template <> struct Default2<float> { static constexpr int rows = 16, lw = 64; };
-template <> struct Default2<double> { static constexpr int rows = 16, lw = 32; };
-inline int lanes2(int real_bytes, int rows) { return real_bytes == 8 || rows == 32 ? 32 : 64; }
+template <> struct Default2<float> { static constexpr int rows = 16, lw = 64, pd = 1; };
+template <> struct Default2<double> { static constexpr int rows = 16, lw = 32, pd = 2; };
+inline int lanes2(int real_bytes, int rows) { return real_bytes == 8 || rows == 24 || rows == 32 ? 32 : 64; }
 
 // Two steps of one tile (ty, tz) and x-chunk cx.  Every thread of the
 // workgroup must call it (it contains barriers).
 // WIT: also keep stage A's e_z^{n+1/2} on the witness lines of wm (a
 // separate instance; the kernel without witness lines is unchanged).
-template <typename R, int TYH, int NB, int LW, bool WIT = false>
+// PD: planes of old data loaded ahead (their loads in flight while a plane
+// is processed): two fit the 256 VGPRs of the FP64 shape and the 168 of the
+// FP32 24-row shape; the 128 of the 1024-thread FP32 shapes hold one.
+template <typename R, int TYH, int NB, int LW, int PD, bool WIT = false>
 __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, const int tz, const int cx,
                                             Lds2<R, TYH, NB, LW>& L, const WitMid<R>& wm = WitMid<R>{})
 {
-    // planes prefetched: FP64 (256 VGPRs per wave) fits two; a second one
-    // does not fit the 128 VGPRs of the FP32 shape
-    constexpr int PD = sizeof(R) == 8 ? 2 : 1;
     constexpr int TY = TYH - 6;   // rows owned
     constexpr int KT2 = LW - 4;   // entries owned per row
     // Lane shifts act on the whole wave; with two rows per wave (LW = 32) the
@@ -199,7 +201,8 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
     const bool owned = node && jl >= 3 && jl < 3 + TY && kl >= 2 && kl < 2 + KT2;
     const int roff = k + j * g.sz;
 
-    // index-range masks of the h components (x part applied per plane)
+    // index-range masks of the h components in j and k (the x part needs
+    // none, see coef below)
     const bool hx_jk = node && j < g.ny && k < g.nz;
     const bool hy_k = node && k < g.nz;
     const bool hz_j = node && j < g.ny;
@@ -209,7 +212,10 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
     const int xload_end = min(xe + 3, g.nx);    // last plane whose old data is needed
 
     const R a2 = A.a + A.a;
-    const bool src_row = A.src.on && j == A.src.j0;
+    // with 64 lanes a wave is one row: the row test is then scalar, and so are
+    // the source-plane tests built on it
+    const int jrow = LW == 64 ? __builtin_amdgcn_readfirstlane(j) : j;
+    const bool src_row = A.src.on && jrow == A.src.j0;
     // the source row lies in this wave (uniform over the wave: lane shifts
     // below run with every lane active)
     const int wj0 = ty * TY - 3 + (int)(threadIdx.x / 64) * (64 / LW);
@@ -244,9 +250,9 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
     char* const gHX = (char*)(A.hx1 + st0);
     char* const gHY = (char*)(A.hy1 + st0);
     char* const gHZ = (char*)(A.hz1 + st0);
+    const uint32_t in_ld = (uint32_t)roff * RB;
     auto gstore = [](char* base, uint32_t off, R v) { *(R*)(base + off) = v; };
     auto xown = [&](int q) { return q >= xs && q < xe; };
-    const uint32_t in_ld = (uint32_t)roff * RB;
     const uint32_t cfix = node ? 0u : 7u;              // outside the grid: PEC
 
     struct PR {
@@ -274,10 +280,9 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
     R ezA = 0;                   // e_z^{n-1/2} of edge k on the source plane
 
     // coefficient factors: a mu and 2a mu zero outside the index range of the
-    // h component in j and k (x is applied per plane), a kappa and 2a kappa
+    // h component in j and k, a kappa and 2a kappa
     const R amx = hx_jk ? A.a * A.mx : R(0), amy = hy_k ? A.a * A.my : R(0), a2mz = hz_j ? a2 * A.mz : R(0);
     const R akx = A.a * A.kx, aky = A.a * A.ky, a2kz = a2 * A.kz;
-    auto xlt = [&](int q) { return q >= 0 && q < g.nx; };
     // v, or 0 where bit b of the code history is set (a PEC edge)
     auto sel = [](uint32_t hist, int b, R v) {
         const uint32_t m = (uint32_t)(((int32_t)(hist << (31 - b))) >> 31);
@@ -289,16 +294,20 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
         }
     };
     // coefficients of a stage whose input plane is q; hist holds the codes of
-    // planes q-1 .. q-4 in bits 0-15.  h_x outside the grid's planes needs no
-    // mask: it reaches only e on the same plane, which such planes hold at 0
-    // (their edges are PEC).
+    // planes q-1 .. q-4 in bits 0-15.  The h components need no mask along x:
+    // on the planes outside their range (i = nx for h_y and h_z, and planes
+    // before the grid or past it, which have no old data) every e their
+    // update reads lies on a wall or outside the grid, where e is 0, so the
+    // update adds exactly 0 and they keep the 0 they hold; the e they feed
+    // are wall or outside edges too (kappa 0).
     auto coef = [&](int q, uint32_t hist) {
+        (void)q;
         Co<R> f;
         f.mx0 = amx;
         f.mx2 = amx;
-        f.my1 = xlt(q - 1) ? amy : R(0);
-        f.my2 = xlt(q - 2) ? amy : R(0);
-        f.mz3 = xlt(q - 3) ? a2mz : R(0);
+        f.my1 = amy;
+        f.my2 = amy;
+        f.mz3 = a2mz;
         f.kz1 = sel(hist, 2, a2kz);
         f.ky2 = sel(hist, 5, aky);
         f.kx2 = sel(hist, 4, akx);
@@ -440,14 +449,14 @@ __device__ __forceinline__ bool fused2_tile_of(const FArgs<R>& A, const int* act
     return tile_of(xcd_remap(blockIdx.x, A.nblk), A.order, A.nyt, A.nzt, ty, tz, cx);
 }
 
-template <typename R, int TYH, int LW>
+template <typename R, int TYH, int LW, int PD>
 __global__ __launch_bounds__(TYH * LW) void k_fused2(FArgs<R> A, const int* act)
 {
     typedef Shape2<R, TYH, LW> S;
     __shared__ Lds2<R, S::rows, S::nb, S::lw> L;
     int ty, tz, cx;
     if (!fused2_tile_of(A, act, ty, tz, cx)) return;   // whole group
-    fused2_tile<R, S::rows, S::nb, S::lw>(A, ty, tz, cx, L);
+    fused2_tile<R, S::rows, S::nb, S::lw, PD>(A, ty, tz, cx, L);
 }
 
 // A tile of the two-step kernel is static when every entry it loads (its rows
@@ -491,7 +500,7 @@ __global__ __launch_bounds__(TYH * LW) void k_fused2_wit(FArgs<R> A, WitMid<R> w
     __shared__ Lds2<R, S::rows, S::nb, S::lw> L;
     int ty, tz, cx;
     if (!fused2_tile_of(A, act, ty, tz, cx)) return;   // whole group
-    fused2_tile<R, S::rows, S::nb, S::lw, true>(A, ty, tz, cx, L, wm);
+    fused2_tile<R, S::rows, S::nb, S::lw, Default2<R>::pd, true>(A, ty, tz, cx, L, wm);
 }
 
 // Two steps of every active instance of a batch, by a persistent grid, as the
@@ -536,7 +545,7 @@ __global__ __launch_bounds__(Default2<R>::rows * Default2<R>::lw) void k_fused2_
         A.src.n = T->step[inst] + steps;
         int ty, tz, cx;
         if (tile_of(w - T->offset2[inst], A.order, A.nyt, A.nzt, ty, tz, cx))
-            fused2_tile<R, S::rows, S::nb, S::lw>(A, ty, tz, cx, L);
+            fused2_tile<R, S::rows, S::nb, S::lw, Default2<R>::pd>(A, ty, tz, cx, L);
         __syncthreads();   // the LDS is reused by the next item
     }
 }
@@ -554,7 +563,7 @@ template <typename R>
 bool fused2_setup(FArgs<R>& A, int rows, int xchunk, int order)
 {
     if (rows == 0) rows = Default2<R>::rows;
-    if (rows != 16 && !(rows == 32 && sizeof(R) == 4)) return false;
+    if (rows != 16 && !((rows == 24 || rows == 32) && sizeof(R) == 4)) return false;
     const int TY = rows - 6, KT2 = lanes2(sizeof(R), rows) - 4;
     A.nyt = (A.g.ny + 1 + TY - 1) / TY;
     A.nzt = (A.g.nz + 1 + KT2 - 1) / KT2;
@@ -633,10 +642,19 @@ hipError_t fused2_static_tiles(const uint8_t* code, Geo g, int rows, int xchunk,
     return hipSuccess;
 }
 
+// One launch of k_fused2 with the given shape over the full tiling or the
+// active list.
+template <typename R, int TYH, int LW, int PD>
+void run_fused2(const FArgs<R>& A, const int* act, int nact, hipStream_t s)
+{
+    if (!act) k_fused2<R, TYH, LW, PD><<<A.nblk, TYH * LW, 0, s>>>(A, nullptr);
+    else if (nact > 0) k_fused2<R, TYH, LW, PD><<<nact, TYH * LW, 0, s>>>(A, act);
+}
+
 template <typename R>
 hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha, Src src, const WitMid<R>* wm,
-                              int rows, int xchunk, int order, hipStream_t s, hipEvent_t* ev, const int* act,
-                              int nact)
+                              int rows, int depth, int xchunk, int order, hipStream_t s, hipEvent_t* ev,
+                              const int* act, int nact)
 {
     FArgs<R> A = fused_args<R>(o, nf, M, g, alpha, src);
     if (wm) rows = 0;   // the instance that keeps witness lines has the default shape only
@@ -655,15 +673,23 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
         done = true;
     }
     if constexpr (sizeof(R) == 4) {
+        // FP32 shapes: rows 16 (64 lanes, one plane ahead, or two with depth 2),
+        // 24 (32 lanes, two planes ahead, or depth 1 or 3), 32 (32 lanes, one
+        // plane ahead)
         if (!done && rows == 32) {
-            if (!act) k_fused2<R, 32, 32><<<A.nblk, 32 * 32, 0, s>>>(A, nullptr);
-            else if (grid > 0) k_fused2<R, 32, 32><<<grid, 32 * 32, 0, s>>>(A, act);
+            run_fused2<R, 32, 32, 1>(A, act, grid, s);
+            done = true;
+        } else if (!done && rows == 24) {
+            if (depth == 1) run_fused2<R, 24, 32, 1>(A, act, grid, s);
+            else if (depth == 3) run_fused2<R, 24, 32, 3>(A, act, grid, s);
+            else run_fused2<R, 24, 32, 2>(A, act, grid, s);
+            done = true;
+        } else if (!done && depth == 2) {
+            run_fused2<R, 16, 64, 2>(A, act, grid, s);
             done = true;
         }
     }
-    constexpr int T2 = Default2<R>::rows * Default2<R>::lw;
-    if (!done && !act) k_fused2<R, Default2<R>::rows, Default2<R>::lw><<<A.nblk, T2, 0, s>>>(A, nullptr);
-    else if (!done && grid > 0) k_fused2<R, Default2<R>::rows, Default2<R>::lw><<<grid, T2, 0, s>>>(A, act);
+    if (!done) run_fused2<R, Default2<R>::rows, Default2<R>::lw, Default2<R>::pd>(A, act, grid, s);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
@@ -674,7 +700,7 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
     template hipError_t launch_batch_step2<R>(BatchTable<R>*, int, int, int, hipStream_t);                     \
     template bool fused2_setup<R>(FArgs<R>&, int, int, int);                                                   \
     template hipError_t launch_step_fused2<R>(Fields<R>, Fields<R>, Mat<R>, Geo, R, Src, const WitMid<R>*, int, \
-                                              int, int, hipStream_t, hipEvent_t*, const int*, int);          \
+                                              int, int, int, hipStream_t, hipEvent_t*, const int*, int);     \
     template hipError_t fused2_static_tiles<R>(const uint8_t*, Geo, int, int, int, uint8_t*, int*, int64_t,    \
                                                int64_t*, int*, hipStream_t);
 TETE_FUSED2_INST(float)

@@ -152,7 +152,7 @@ int fused_default_rows(int real_bytes);
 // Two steps in one launch (tete_fused2.hip): the fused step temporally
 // blocked; xchunk and order as for the single step.
 bool fused2_fits(Geo g, int real_bytes);
-// rows: 0 (default), 16, or 32 (FP32 only: 32 rows of 32 lanes).
+// rows: 0 (default), 16, or 24 or 32 (FP32 only: rows of 32 lanes).
 template <typename R>
 bool fused2_setup(FArgs<R>& A, int rows, int xchunk, int order);
 // wm (or nullptr): the witness lines whose e_z^{n+1/2} the launch keeps;
@@ -161,8 +161,8 @@ bool fused2_setup(FArgs<R>& A, int rows, int xchunk, int order);
 // nact is 0), and with wm stores witness values only in them
 template <typename R>
 hipError_t launch_step_fused2(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src,
-                              const WitMid<R>* wm, int rows, int xchunk, int order, hipStream_t s, hipEvent_t* ev,
-                              const int* act, int nact);
+                              const WitMid<R>* wm, int rows, int depth, int xchunk, int order, hipStream_t s,
+                              hipEvent_t* ev, const int* act, int nact);
 // One byte per tile of the two-step kernel's tiling (rows, xchunk) in tab: 1
 // where every entry the tile loads has its three e edges PEC, so that a step
 // leaves the tile's entries unchanged; and in act the *nact other tiles in the

@@ -80,6 +80,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError("libtete.so is not built (%s); run python -m paper_0901_1053_amd.build" % path)
+    # torch first: the library then binds to the HIP runtime torch already
+    # loaded, so the process holds one runtime and torch's device memory and
+    # streams are valid in the library's calls
+    import torch  # noqa: F401
     L = C.CDLL(path)
     st = C.c_int
     vp = C.c_void_p

@@ -149,12 +149,16 @@ def test_fp64_wake_identical_and_oracle(nt, nz, xchunk):
     assert P.delta_norm(a.wake(), ref["W"]) <= 1e-12
 
 
+@pytest.mark.parametrize("rows,depth", [(32, 0), (24, 0), (24, 1), (24, 3), (16, 2)])
 @pytest.mark.parametrize("xchunk", [0, 3])
-def test_fp32_32_row_shape(xchunk):
-    """The 32-row, 32-lane FP32 shape gives the single-step results bitwise."""
+def test_fp32_other_shapes(rows, depth, xchunk):
+    """The other FP32 shapes of the two-step kernel (rows of 32 lanes: 32 rows,
+    24 rows with one, two or three planes loaded ahead; 16 rows of 64 lanes with
+    two) give the single-step results bitwise, fields and wake."""
+    print("fp32 shape", rows, depth, xchunk, flush=True)
     shape = (20, 70, 300)
     G = _grid(shape, 51, "fused2")
-    G.set_tuning("fused2", 32, xchunk, 0, 0)
+    G.set_tuning("fused2", rows, xchunk, depth, 0)
     G.step(13)
     _same(G.get_fields(), _fields(shape, 51, "fused", 13))
     case = inputs.scaled_wake_case(32, 200, seed=77, sigma_dz=3.0)
@@ -162,7 +166,7 @@ def test_fp32_32_row_shape(xchunk):
     jmin, nw = -M - 3, 2 * M + 40
     steps = case.nz + M + jmin + nw
     a = P.gpu_grid(case, "fp32")
-    a.set_tuning("fused2", 32, xchunk, 0, 0)
+    a.set_tuning("fused2", rows, xchunk, depth, 0)
     a.set_bunch(case.Q, case.sigma, case.i0, case.j0, M, jmin, nw)
     a.step(steps)
     b = _wake_run(case, "fused", steps, jmin, nw)

@@ -14,6 +14,7 @@ import pytest
 
 from tests import test_oracle_dense as TD
 from tests import test_oracle_dispersion as TP
+from tests import test_oracle_energy_sum as TE
 from tests import test_oracle_invariants as TI
 from tests import test_oracle_witness as TW
 from tests import test_oracle_yee as TY
@@ -39,13 +40,17 @@ MUTANTS = {
                      "double pyt_hz = at(g, f, HZ, i, j, k) - at(g, f, HZ, i, j + 1, k);",
                      [lambda o: TD.test_ten_updates_equal_dense_scheme(o, 0)]),
     # cross term of W^{n,e} with the wrong sign
-    "energy_cross_sign": ("return 0.5 * sq - 0.5 * a * a * (r0 + r1) + a * lc;",
-                          "return 0.5 * sq - 0.5 * a * a * (r0 + r1) - a * lc;",
+    "energy_cross_sign": ("return 0.5 * total(&sq) - 0.5 * a * a * (total(&r0) + total(&r1)) + a * total(&lc);",
+                          "return 0.5 * total(&sq) - 0.5 * a * a * (total(&r0) + total(&r1)) - a * total(&lc);",
                           [lambda o: TD.test_energy_is_half_yQy(o, 0)]),
     # energy R-term with + alpha^2 (the sign the paper prints)
-    "energy_r_sign": ("return 0.5 * sq - 0.5 * a * a * (r0 + r1) + a * lc;",
-                      "return 0.5 * sq + 0.5 * a * a * (r0 + r1) + a * lc;",
+    "energy_r_sign": ("return 0.5 * total(&sq) - 0.5 * a * a * (total(&r0) + total(&r1)) + a * total(&lc);",
+                      "return 0.5 * total(&sq) + 0.5 * a * a * (total(&r0) + total(&r1)) + a * total(&lc);",
                       [lambda o: TD.test_energy_is_half_yQy(o, 0)]),
+    # energy summed without the compensation (a plain running sum)
+    "energy_plain_sum": ("static double total(const orc_sum* a) { return a->s + a->c; }",
+                         "static double total(const orc_sum* a) { return a->s; }",
+                         [lambda o: TE.test_energy_sum_is_exactly_rounded_to_a_few_ulp(o)]),
     # charge with (I + alpha^2 r_0)
     "charge_r_sign": ("return e0 / kap - a * a * r;", "return e0 / kap + a * a * r;",
                       [lambda o: TI.test_gauss_law_moving_bunch(o)]),
