@@ -345,26 +345,56 @@ def witness_section(G, case, two_step_ms, offset=32, steps=20):
             "vs_two_step_without_witness": round(ms / two_step_ms, 3)}
 
 
-def materials_section(case, precision, explicit_ms_per_step, steps=6):
-    """Per-entry materials (tete_set_materials) on the large workload, every
-    kappa and mu 0.9 of its vacuum value (arrays made on the device): kernel
-    time per step of the fused single step's materials instance and of the
-    two-kernel step, against the vacuum two-step kernel.  The materials step
-    reads six coefficient arrays besides the fields: 73 B per entry in FP32
-    (97 + 48 in FP64) against 49 (97)."""
+def _pec_materials(case, precision, scale=0.9):
+    """Per-entry materials carrying the workload's geometry, made on the
+    device: kappa and mu `scale` of their vacuum values, kappa zero on the
+    staircase PEC edges (an e edge touching a metal cell, cells outside the box
+    counting as metal)."""
+    import numpy as np
     import torch
     from paper_0901_1053_amd import tete
     td = torch.float32 if precision == "fp32" else torch.float64
-    G = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.cdt, precision=precision,
-                  materials=True)
+    nx, ny, nz = case.nx, case.ny, case.nz
+    p = torch.ones((nx + 2, ny + 2, nz + 2), dtype=torch.bool, device="cuda")
+    p[1:-1, 1:-1, 1:-1] = torch.from_numpy(np.ascontiguousarray(case.cell_mask())).to("cuda").bool()
+    X, Y, Z = nx + 1, ny + 1, nz + 1
+    pec = {"ex": p[1:, 0:Y, 0:Z] | p[1:, 1:, 0:Z] | p[1:, 0:Y, 1:] | p[1:, 1:, 1:],
+           "ey": p[0:X, 1:Y + 1, 0:Z] | p[1:, 1:Y + 1, 0:Z] | p[0:X, 1:Y + 1, 1:] | p[1:, 1:Y + 1, 1:],
+           "ez": p[0:X, 0:Y, 1:Z + 1] | p[1:, 0:Y, 1:Z + 1] | p[0:X, 1:, 1:Z + 1] | p[1:, 1:, 1:Z + 1]}
+    del p
     v = {"ex": case.dx / (case.dy * case.dz), "ey": case.dy / (case.dx * case.dz),
          "ez": case.dz / (case.dx * case.dy)}
     v.update({"hx": v["ex"], "hy": v["ey"], "hz": v["ez"]})
-    mat = {k: torch.full(G.shape, 0.9 * v[k], device="cuda", dtype=td) for k in tete.KEYS}
+    mat = {}
+    for k in tete.KEYS:
+        a = torch.full((X, Y, Z), scale * v[k], device="cuda", dtype=td)
+        if k in pec:
+            a.masked_fill_(pec[k], 0.0)
+        mat[k] = a
+    del pec
+    return mat, [scale * v[k] for k in tete.KEYS]
+
+
+def materials_section(case, precision, explicit_ms_per_step, steps=6):
+    """Per-entry materials on the large workload: kappa and mu 0.9 of their
+    vacuum values, kappa zero on the staircase PEC edges.  Kernel time per
+    step of (1) the per-entry arrays (tete_set_materials) with the fused
+    materials step, single steps reading six coefficient arrays besides the
+    fields (73 B per entry in FP32, 145 in FP64), and with the two-kernel step;
+    (2) the same values as one material class (tete_set_material_classes):
+    paired steps run the two-step kernel's class instance, reading one class
+    byte per entry and the class table from LDS (one read and one write of
+    the state per two steps).  The fields of (1) and (2) are the same (tests)."""
+    import torch
+    from paper_0901_1053_amd import tete
+    mat, table = _pec_materials(case, precision)
+    out = {}
+    G = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.cdt, precision=precision,
+                  materials=True)
+    G.set_pec_cells(case.cell_mask())
     G.set_materials(mat, dtype=precision)
     del mat
     torch.cuda.empty_cache()
-    out = {}
     for kernel in ("fused", "split"):
         G.set_tuning(kernel)
         G.step(2)
@@ -376,12 +406,33 @@ def materials_section(case, precision, explicit_ms_per_step, steps=6):
     G.close()
     del G
     torch.cuda.empty_cache()
+    C = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.cdt, precision=precision,
+                  materials=True)
+    C.set_pec_cells(case.cell_mask())
+    C.set_material_classes(torch.zeros(C.shape, dtype=torch.uint8, device="cuda"), [table])
+    kernel = C.get_tuning()["kernel"]
+    C.step(2)
+    C.set_timing(2 * steps)
+    C.step(2 * steps)
+    a, _, n = C.timing()
+    C.set_timing(0)
+    out["classes"] = a / n
+    C.close()
+    del C
+    torch.cuda.empty_cache()
     b = 4 if precision == "fp32" else 8
-    nbytes = (18 * b + 1) * (case.nx + 1) * (case.ny + 1) * (case.nz + 1)
-    return {"workload": case.name, "precision": precision, "materials": "0.9 x vacuum kappa and mu, per entry",
-            "ms_per_step": {"fused_materials": round(out["fused"], 3), "two_kernel": round(out["split"], 3)},
+    entries = (case.nx + 1) * (case.ny + 1) * (case.nz + 1)
+    nbytes = (18 * b + 1) * entries
+    return {"workload": case.name, "precision": precision,
+            "materials": "0.9 x vacuum kappa and mu per entry, kappa 0 on the staircase PEC edges",
+            "ms_per_step": {"fused_materials": round(out["fused"], 3), "two_kernel": round(out["split"], 3),
+                            "classes_two_step": round(out["classes"], 3)},
+            "classes_kernel": kernel,
             "fused_materials_gbps_algorithmic": round(nbytes / (out["fused"] / 1e3) / 1e9, 1),
-            "vs_vacuum_two_step": round(out["fused"] / explicit_ms_per_step, 2) if explicit_ms_per_step else None}
+            "classes_vs_fused_materials": round(out["fused"] / out["classes"], 2),
+            "vs_vacuum_two_step": round(out["fused"] / explicit_ms_per_step, 2) if explicit_ms_per_step else None,
+            "classes_vs_vacuum_two_step": round(out["classes"] / explicit_ms_per_step, 2)
+            if explicit_ms_per_step else None}
 
 
 def skip_section(case, precision, explicit_ms_per_step, witness_ms=None, steps=8, xchunks=(0, 257, 128, 64, 16)):
@@ -425,33 +476,14 @@ def skip_section(case, precision, explicit_ms_per_step, witness_ms=None, steps=8
 
 
 def materials_skip_section(case, precision, steps=6):
-    """Per-entry materials that carry the workload's geometry: kappa and mu
-    0.9 of their vacuum values, kappa zero on the staircase PEC edges (an e
-    edge touching a metal cell, cells outside the box counting as metal).
+    """Per-entry materials that carry the workload's geometry (kappa and mu
+    0.9 of their vacuum values, kappa zero on the staircase PEC edges).
     Kernel time per step of the fused materials step over every tile and over
     the active tiles only (skip_static); the fields are the same."""
-    import numpy as np
     import torch
     from paper_0901_1053_amd import tete
-    td = torch.float32 if precision == "fp32" else torch.float64
     nx, ny, nz = case.nx, case.ny, case.nz
-    p = torch.ones((nx + 2, ny + 2, nz + 2), dtype=torch.bool, device="cuda")
-    p[1:-1, 1:-1, 1:-1] = torch.from_numpy(np.ascontiguousarray(case.cell_mask())).to("cuda").bool()
-    X, Y, Z = nx + 1, ny + 1, nz + 1
-    pec = {"ex": p[1:, 0:Y, 0:Z] | p[1:, 1:, 0:Z] | p[1:, 0:Y, 1:] | p[1:, 1:, 1:],
-           "ey": p[0:X, 1:Y + 1, 0:Z] | p[1:, 1:Y + 1, 0:Z] | p[0:X, 1:Y + 1, 1:] | p[1:, 1:Y + 1, 1:],
-           "ez": p[0:X, 0:Y, 1:Z + 1] | p[1:, 0:Y, 1:Z + 1] | p[0:X, 1:, 1:Z + 1] | p[1:, 1:, 1:Z + 1]}
-    del p
-    v = {"ex": case.dx / (case.dy * case.dz), "ey": case.dy / (case.dx * case.dz),
-         "ez": case.dz / (case.dx * case.dy)}
-    v.update({"hx": v["ex"], "hy": v["ey"], "hz": v["ez"]})
-    mat = {}
-    for k in tete.KEYS:
-        a = torch.full((X, Y, Z), 0.9 * v[k], device="cuda", dtype=td)
-        if k in pec:
-            a.masked_fill_(pec[k], 0.0)
-        mat[k] = a
-    del pec
+    mat, _ = _pec_materials(case, precision)
     out = {}
     for skip in (False, True):
         G = tete.Grid(nx, ny, nz, case.dx, case.dy, case.dz, case.cdt, precision=precision, materials=True,

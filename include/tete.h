@@ -130,7 +130,8 @@ enum {
     TETE_MAX_WAKE = 65536,       /* wake samples */
     TETE_MAX_PROBES = 16,        /* e_z probe points */
     TETE_WITNESS_LINES = 5,      /* e_z lines of a witness: its node and four neighbours */
-    TETE_MAX_BATCH = 256         /* instances of one batch */
+    TETE_MAX_BATCH = 256,        /* instances of one batch */
+    TETE_MAX_CLASSES = 256       /* material classes (tete_set_material_classes) */
 };
 
 typedef struct {
@@ -197,6 +198,27 @@ tete_status tete_set_pec_cells(tete_grid* g, const uint8_t* cell_is_pec);
  * is sufficient, not necessary.  Synchronises the stream. */
 tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3],
                                const void* const inv_mu[3], int32_t dtype);
+
+/* Materials by class: an exact compact form of the general diagonal
+ * M_eps^-1, M_mu^-1 of eq. (4) (Sec. 2) for media with at most
+ * TETE_MAX_CLASSES distinct coefficient tuples.  cls: DEVICE array of np
+ * bytes, the class of each entry; table: HOST array of ncls x 6 doubles,
+ * (kappa_x, kappa_y, kappa_z, mu_x, mu_y, mu_z) of class c at table[6c ..
+ * 6c+5], finite and >= 0, 1 <= ncls <= TETE_MAX_CLASSES.  Entry e then has
+ * the coefficients of class cls[e], except that kappa is 0 on the PEC edges
+ * of the current geometry (tete_set_pec_cells: staircase cells and the box
+ * walls; call that first, it drops the materials) and entries outside a
+ * component's range hold no object.  Requires TETE_F_MATERIALS
+ * (TETE_ERR_STATE).  Class bytes >= ncls are TETE_ERR_ARG; the stability
+ * test of tete_set_materials applies (TETE_ERR_UNSTABLE), and on any error
+ * nothing changes.  The classes are expanded into the per-entry arrays
+ * (single steps, diagnostics), and steps paired by tete_step run the
+ * two-step kernel's class instance (FP32 24 rows of 32 lanes; FP64 16 rows
+ * of 32 lanes; the tuning's rows and depth do not apply): it reads one class
+ * byte per entry and the class table from LDS instead of the six arrays, with
+ * the same results as single materials steps.  With witness lines every step
+ * is a single step.  Zeroes e on PEC edges.  Synchronises the stream. */
+tete_status tete_set_material_classes(tete_grid* g, const uint8_t* cls, const double* table, int32_t ncls);
 
 /* Initial field y^0 = (u^{-1/2}, v^0) (time levels of eq. (17)): h_x, h_y, e_z
  * at tau = -cdt/2 and e_x, e_y, h_z at tau = 0.  f[6] are DEVICE arrays of np
@@ -327,7 +349,8 @@ tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h);
  *                      one prefetched plane, the coefficients read with the
  *                      fields and carried to the sub-updates' planes);
  *   TETE_KERNEL_FUSED2 two steps per launch, temporally blocked
- *                      (TETE_ERR_STATE with per-entry materials).  tete_step
+ *                      (TETE_ERR_STATE with per-entry materials set by
+ *                      tete_set_materials; materials by class use it).  tete_step
  *                      pairs consecutive steps except where an energy sample
  *                      or probes need the state in between; those steps, and
  *                      an odd last one, run as fused single steps;

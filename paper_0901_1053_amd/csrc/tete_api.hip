@@ -23,7 +23,7 @@ size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t lam, wacc, wit, wmid, partial, scal, pidx, eser, pser, code, field[12], mat[6], imp[4], imp_le, imp_lh,
-        imp_cnt, skip[2], skip_act[2], total;
+        imp_cnt, skip[2], skip_act[2], cls, ctab, craw, total;
 };
 
 int64_t series_cap(const tete_grid_desc* d) { return d->max_series > 0 ? d->max_series : 4096; }
@@ -50,6 +50,12 @@ bool make_layout(const tete_grid_desc* d, Layout* L)
     for (int c = 0; c < 6; ++c) {
         if (d->flags & TETE_F_MATERIALS) { L->mat[c] = o; o = up(o + rb * (size_t)np); }
         else L->mat[c] = 0;
+    }
+    L->cls = L->ctab = L->craw = 0;
+    if (d->flags & TETE_F_MATERIALS) {     // materials by class: class bytes, step table, table as given
+        L->cls = o;  o = up(o + (size_t)np);
+        L->ctab = o; o = up(o + rb * TETE_MAX_CLASSES * CLS_STRIDE);
+        L->craw = o; o = up(o + sizeof(double) * TETE_MAX_CLASSES * 6);
     }
     for (int c = 0; c < 4; ++c) {          // plane-solve work arrays of the implicit scheme
         if (d->flags & TETE_F_IMPLICIT) { L->imp[c] = o; o = up(o + rb * (size_t)np); }
@@ -109,6 +115,13 @@ struct tete_grid {
     uint8_t* code;
     void* mat[6];
     int mat_set;
+    // materials by class (tete_set_material_classes): the class bytes, the
+    // step kernels' table and the table as given; mat_cls is set while the
+    // material arrays hold the classes' expansion
+    int mat_cls;
+    uint8_t* cls;
+    void* ctab;
+    double* craw;
     // static-tile skip (TETE_F_SKIP_STATIC): per tiling kind (0: two-step
     // kernel, 1: fused single step) the table and the list of the
     // skip_nact[kind] active tiles for the tiling (skip_rows, skip_xc,
@@ -169,6 +182,8 @@ Mat<R> mats(tete_grid* g)
     M.code = g->code;
     for (int c = 0; c < 6; ++c) M.arr[c] = g->mat_set ? (const R*)g->mat[c] : nullptr;
     for (int c = 0; c < 3; ++c) { M.k[c] = (R)g->kv[c]; M.m[c] = (R)g->mv[c]; }
+    M.cls = g->mat_cls ? g->cls : nullptr;
+    M.ctab = g->mat_cls ? (const R*)g->ctab : nullptr;
     return M;
 }
 
@@ -255,10 +270,12 @@ bool use_fused(const tete_grid* g)
 // The two-step kernel (automatic choice, or asked for) when the grid
 // qualifies; do_steps still takes single steps where a diagnostic needs the
 // state in between.
-// Rows of the two-step kernel: the tuning's rows when it asks for 16, 24 or
-// 32 (24, 32: FP32 only), else the default.
+// Rows of the two-step kernel: the class instance's for materials by class
+// (FP32 24, FP64 the default), else the tuning's rows when it asks for 16, 24
+// or 32 (24, 32: FP32 only), else the default.
 int fused2_rows(const tete_grid* g)
 {
+    if (g->mat_cls) return g->fp32 ? 24 : 0;
     const int r = g->tune.rows;
     return r == 16 || ((r == 24 || r == 32) && g->fp32) ? r : 0;
 }
@@ -271,10 +288,13 @@ int fused2_xchunk(const tete_grid* g)
     return g->tune.xchunk != 0 ? g->tune.xchunk : g->skip ? 32 : 0;
 }
 
+// Per-entry materials step as single steps, except materials by class, which
+// the two-step kernel's class instance takes (without witness lines).
 bool use_fused2(const tete_grid* g)
 {
     const bool want = g->tune.kernel == TETE_KERNEL_FUSED2 || g->tune.kernel == TETE_KERNEL_AUTO;
-    return want && !g->mat_set && use_fused(g) && fused2_fits(g->geo, g->fp32 ? 4 : 8);
+    const bool mat_ok = !g->mat_set || (g->mat_cls && !(g->witness && g->has_bunch));
+    return want && mat_ok && use_fused(g) && fused2_fits(g->geo, g->fp32 ? 4 : 8);
 }
 
 // Builds the static-tile table for the current tiling of the two-step
@@ -528,6 +548,10 @@ tete_status tete_grid_create(const tete_grid_desc* d, void* dev_ws, size_t ws_by
     skip_invalidate(g);
     g->err = TETE_OK;
     for (int c = 0; c < 6; ++c) g->mat[c] = (d->flags & TETE_F_MATERIALS) ? g->ws + L.mat[c] : nullptr;
+    g->mat_cls = 0;
+    g->cls = (d->flags & TETE_F_MATERIALS) ? (uint8_t*)(g->ws + L.cls) : nullptr;
+    g->ctab = (d->flags & TETE_F_MATERIALS) ? (void*)(g->ws + L.ctab) : nullptr;
+    g->craw = (d->flags & TETE_F_MATERIALS) ? (double*)(g->ws + L.craw) : nullptr;
     g->lam = (double*)(g->ws + L.lam);
     g->wacc = (double*)(g->ws + L.wacc);
     g->wit = (double*)(g->ws + L.wit);
@@ -577,7 +601,7 @@ tete_status tete_set_tuning(tete_grid* g, const tete_tuning* t)
     if (t->xchunk < 0) return TETE_ERR_ARG;
     if (t->depth < 0 || t->depth > 3) return TETE_ERR_ARG;
     if (t->order < 0 || t->order > 6) return TETE_ERR_ARG;
-    if (t->kernel == TETE_KERNEL_FUSED2 && g->mat_set) return TETE_ERR_STATE;
+    if (t->kernel == TETE_KERNEL_FUSED2 && g->mat_set && !g->mat_cls) return TETE_ERR_STATE;
     g->tune = *t;
     return TETE_OK;
 }
@@ -645,6 +669,7 @@ tete_status tete_set_pec_cells(tete_grid* g, const uint8_t* cells)
     if (!dg.ok) return TETE_ERR_DEVICE;
     HIPCHK(launch_build_codes(g->code, cells, g->geo, g->stream));
     g->mat_set = 0;
+    g->mat_cls = 0;
     g->imp_lists = 0;
     skip_invalidate(g);
     if (g->fp32) HIPCHK(launch_zero_pec<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->stream));
@@ -678,6 +703,7 @@ tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3], const
         for (int c = 0; c < 6; ++c) dst[c] = (float*)g->mat[c];
         HIPCHK(launch_import_materials<float>(dst, src, dtype == TETE_FP32, g->geo, g->stream));
         g->mat_set = 1;
+        g->mat_cls = 0;
         skip_invalidate(g);
         HIPCHK(launch_zero_pec<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->stream));
     } else {
@@ -685,9 +711,56 @@ tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3], const
         for (int c = 0; c < 6; ++c) dst[c] = (double*)g->mat[c];
         HIPCHK(launch_import_materials<double>(dst, src, dtype == TETE_FP32, g->geo, g->stream));
         g->mat_set = 1;
+        g->mat_cls = 0;
         skip_invalidate(g);
         HIPCHK(launch_zero_pec<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->stream));
     }
+    return TETE_OK;
+}
+
+tete_status tete_set_material_classes(tete_grid* g, const uint8_t* cls, const double* table, int32_t ncls)
+{
+    if (!g || !cls || !table || ncls < 1 || ncls > TETE_MAX_CLASSES) return TETE_ERR_ARG;
+    for (int64_t e = 0; e < 6 * (int64_t)ncls; ++e)
+        if (!(table[e] >= 0.0) || !isfinite(table[e])) return TETE_ERR_ARG;
+    if (!(g->d.flags & TETE_F_MATERIALS)) return TETE_ERR_STATE;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    // the table as given, padded with zero classes, into the staging area
+    // (used only here and by the expansion below)
+    std::vector<double> t((size_t)6 * TETE_MAX_CLASSES, 0.0);
+    std::copy(table, table + 6 * (int64_t)ncls, t.begin());
+    HIPCHK(hipMemcpyAsync(g->craw, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice, g->stream));
+    {
+        // Q^e >= 0 (Sec. 4.4) for the per-entry values the classes give, and
+        // every class byte below ncls, before anything changes
+        double bound;
+        HIPCHK(launch_mat_bound_cls(g->code, cls, g->craw, ncls, g->geo, g->alpha, g->partial, g->scal + 4,
+                                    g->stream));
+        HIPCHK(hipMemcpyAsync(&bound, g->scal + 4, sizeof(double), hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipStreamSynchronize(g->stream));
+        if (!(bound == bound)) return TETE_ERR_ARG;
+        if (bound > 1.0 + 1e-12) return TETE_ERR_UNSTABLE;
+    }
+    HIPCHK(hipMemcpyAsync(g->cls, cls, (size_t)g->geo.np, hipMemcpyDeviceToDevice, g->stream));
+    if (g->tune.kernel == TETE_KERNEL_FUSED) g->tune.kernel = TETE_KERNEL_AUTO;
+    if (g->fp32) {
+        float* dst[6];
+        for (int c = 0; c < 6; ++c) dst[c] = (float*)g->mat[c];
+        HIPCHK(launch_expand_classes<float>(dst, (float*)g->ctab, g->code, g->cls, g->craw, (float)g->alpha, g->geo,
+                                            g->stream));
+    } else {
+        double* dst[6];
+        for (int c = 0; c < 6; ++c) dst[c] = (double*)g->mat[c];
+        HIPCHK(launch_expand_classes<double>(dst, (double*)g->ctab, g->code, g->cls, g->craw, g->alpha, g->geo,
+                                             g->stream));
+    }
+    g->mat_set = 1;
+    g->mat_cls = 1;
+    skip_invalidate(g);
+    if (g->fp32) HIPCHK(launch_zero_pec<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->stream));
+    else HIPCHK(launch_zero_pec<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));   // the staging vector is a host temporary
     return TETE_OK;
 }
 

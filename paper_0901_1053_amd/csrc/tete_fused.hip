@@ -490,6 +490,8 @@ FArgs<R> fused_args(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha, Src src
     A.ex = o.c[0]; A.ey = o.c[1]; A.ez = o.c[2]; A.hx = o.c[3]; A.hy = o.c[4]; A.hz = o.c[5];
     A.ex1 = nf.c[0]; A.ey1 = nf.c[1]; A.ez1 = nf.c[2]; A.hx1 = nf.c[3]; A.hy1 = nf.c[4]; A.hz1 = nf.c[5];
     A.code = M.code;
+    A.cls = M.cls;
+    A.ctab = M.ctab;
     A.g = g;
     A.a = alpha;
     A.kx = M.k[0]; A.ky = M.k[1]; A.kz = M.k[2];

@@ -148,11 +148,13 @@ __device__ __forceinline__ Out<R> stage_plane(Stage<R>& S, const In<R>& c, const
 // or single (NB = 1, a second barrier per plane); and stage B's delay lines
 // for e_z, h_x and h_y, two planes deep, one slot per thread
 // ([quantity][plane parity][thread]), kept here to free registers.
-template <typename R, int TYH, int NB, int LW>
+// With materials by class (TAB) the class table is staged here too.
+template <typename R, int TYH, int NB, int LW, bool TAB = false>
 struct Lds2 {
     R a[6][NB][TYH + 2][LW];
     R b[6][NB][TYH + 2][LW];
     R d[3][2][LW * TYH];
+    R tab[TAB ? TETE_MAX_CLASSES * CLS_STRIDE : 1];
 };
 
 // Launch shape of the two-step kernel per field type: rows of LW lanes
@@ -181,9 +183,15 @@ inline int lanes2(int real_bytes, int rows) { return real_bytes == 8 || rows == 
 // PD: planes of old data loaded ahead (their loads in flight while a plane
 // is processed): two fit the 256 VGPRs of the FP64 shape and the 168 of the
 // FP32 24-row shape; the 128 of the 1024-thread FP32 shapes hold one.
-template <typename R, int TYH, int NB, int LW, int PD, bool WIT = false>
-__device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, const int tz, const int cx,
-                                            Lds2<R, TYH, NB, LW>& L, const WitMid<R>& wm = WitMid<R>{})
+// CLS: materials by class.  Each plane's class bytes are loaded with its
+// fields and kept, a byte per plane, for the nine planes the two stages'
+// sub-updates reach back; each coefficient is then read from the class table
+// in LDS (already multiplied by a or 2a, the product the materials step forms
+// from its arrays, so the results are those of single materials steps), the
+// kappa of PEC edges zeroed by the codes as in vacuum.
+template <typename R, int TYH, int NB, int LW, int PD, bool WIT = false, bool CLS = false, class LDS>
+__device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, const int tz, const int cx, LDS& L,
+                                            const WitMid<R>& wm = WitMid<R>{})
 {
     constexpr int TY = TYH - 6;   // rows owned
     constexpr int KT2 = LW - 4;   // entries owned per row
@@ -239,6 +247,13 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
                rEZ = mk(A.ez + ld0, nload * plane_bytes), rHX = mk(A.hx + ld0, nload * plane_bytes),
                rHY = mk(A.hy + ld0, nload * plane_bytes), rHZ = mk(A.hz + ld0, nload * plane_bytes);
     const auto rC = mk(A.code, (uint32_t)std::min<int64_t>((int64_t)g.np + 4, 0x7fffffff));
+    __amdgpu_buffer_rsrc_t rK = rC;
+    if constexpr (CLS) {
+        rK = mk(A.cls, (uint32_t)std::min<int64_t>((int64_t)g.np + 4, 0x7fffffff));
+        // the class table into LDS; the barrier of the first j-exchange
+        // orders these writes before any read
+        for (int t = threadIdx.x; t < TETE_MAX_CLASSES * CLS_STRIDE; t += TYH * LW) L.tab[t] = A.ctab[t];
+    }
     // Stores are plain global stores: the chunk's first plane as a scalar base
     // plus a 32-bit byte offset, predicated on the plane lying in the chunk
     // (uniform) and the entry being owned; this keeps six buffer resources
@@ -258,6 +273,7 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
     struct PR {
         R ex, ey, ez, hx, hy, hz;
         uint32_t c;
+        uint32_t k[CLS ? 1 : 0];
     };
     auto load_plane = [&](int i, PR& d) {
         const uint32_t po = (uint32_t)(i - pb);
@@ -270,9 +286,13 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
         d.hz = bload<R>(rHZ, off);
         const uint32_t offc = node ? ((uint32_t)(roff + i * g.sp) & ~3u) : OOB;
         d.c = __builtin_amdgcn_raw_buffer_load_b32(rC, offc, 0, 0);   // byte extracted when used
+        if constexpr (CLS) d.k[0] = __builtin_amdgcn_raw_buffer_load_b32(rK, offc, 0, 0);
     };
 
     Stage<R> SA = {}, SB = {};
+    // class bytes of planes p .. p-3 (kh0, byte i = plane p-i), p-4 .. p-7 (kh1)
+    // and p-8 (kh2) (CLS only)
+    uint32_t kh0 = 0, kh1 = 0, kh2 = 0;
     const int tid = threadIdx.x;
     for (int q = 0; q < 3; ++q) L.d[q][0][tid] = L.d[q][1][tid] = R(0);   // stage B's delay lines
     R d_ey4 = 0;                 // e_y^{n+1} of plane p-4
@@ -315,6 +335,24 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
         f.kx4 = sel(hist, 12, akx);
         return f;
     };
+    // coefficients from the class table, for a stage whose input plane holds
+    // class l0 and planes q-1 .. q-4 classes l1 .. l4 (CLS)
+    auto tab = [&](uint32_t cls, int e) { return L.tab[cls * CLS_STRIDE + e]; };
+    auto coefc = [&](uint32_t l0, uint32_t l1, uint32_t l2, uint32_t l3, uint32_t l4, uint32_t hist) {
+        Co<R> f;
+        f.mx0 = hx_jk ? tab(l0, CLS_AMX) : R(0);
+        f.mx2 = hx_jk ? tab(l2, CLS_AMX) : R(0);
+        f.my1 = hy_k ? tab(l1, CLS_AMY) : R(0);
+        f.my2 = hy_k ? tab(l2, CLS_AMY) : R(0);
+        f.mz3 = hz_j ? tab(l3, CLS_A2MZ) : R(0);
+        f.kz1 = sel(hist, 2, tab(l1, CLS_A2KZ));
+        f.ky2 = sel(hist, 5, tab(l2, CLS_AKY));
+        f.kx2 = sel(hist, 4, tab(l2, CLS_AKX));
+        f.ky3 = sel(hist, 9, tab(l3, CLS_AKY));
+        f.kx4 = sel(hist, 12, tab(l4, CLS_AKX));
+        return f;
+    };
+    auto cbyte = [](uint32_t h, int b) { return (h >> (8 * b)) & 0xffu; };
     // bunch current of step n on edge k (zero where no cell crosses it),
     // rounded on its own before it is subtracted
     auto inject = [&](int64_t n, R kz) {
@@ -331,8 +369,13 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
     auto body = [&](const int p, const PR& cur, PR& nxt) {
         load_plane(p + PD, nxt);
         // outside the grid, or a plane without old data: PEC on all edges
-        const uint32_t c0 = ((cur.c >> (((uint32_t)(roff + p * g.sp) & 3u) * 8u)) & 7u) | cfix |
-                            ((p >= pb && p <= xload_end) ? 0u : 7u);
+        const uint32_t bsh = ((uint32_t)(roff + p * g.sp) & 3u) * 8u;
+        const uint32_t c0 = ((cur.c >> bsh) & 7u) | cfix | ((p >= pb && p <= xload_end) ? 0u : 7u);
+        if constexpr (CLS) {
+            kh2 = kh1 >> 24;
+            kh1 = (kh1 << 8) | (kh0 >> 24);
+            kh0 = (kh0 << 8) | ((cur.k[0] >> bsh) & 0xffu);
+        }
 
         // stage B's input plane p-4, except e_x (stage A's S9 of this
         // iteration); the delay-line slot of this parity holds plane p-4 and
@@ -363,13 +406,25 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
                           L.b[3][x][jl][kl],     L.b[4][x][jl + 2][kl], L.b[5][x][jl][kl]};
         if (NB == 1) __syncthreads();    // all reads done before the next plane's writes
 
-        const Co<R> fA = coef(p, ch), fB = coef(p - 4, ch >> 16);
+        Co<R> fA, fB;
+        if constexpr (CLS) {
+            fA = coefc(cbyte(kh0, 0), cbyte(kh0, 1), cbyte(kh0, 2), cbyte(kh0, 3), cbyte(kh1, 0), ch);
+            fB = coefc(cbyte(kh1, 0), cbyte(kh1, 1), cbyte(kh1, 2), cbyte(kh1, 3), cbyte(kh2, 0), ch >> 16);
+        } else {
+            fA = coef(p, ch);
+            fB = coef(p - 4, ch >> 16);
+        }
         // S3 of stage A is at plane p-1 (step n), of stage B at plane p-5 (step n+1)
         const bool srcA = src_row && p - 1 == A.src.i0;
         const bool srcB = src_row && p - 5 == A.src.i0;
         const bool srcBw = LW == 64 ? srcB : src_wave && p - 5 == A.src.i0;   // wave-uniform
-        const R injA = (srcA && src_k) ? inject(A.src.n, sel(ch, 2, A.kz)) : R(0);
-        const R injB = (srcB && src_k) ? inject(A.src.n + 1, sel(ch, 18, A.kz)) : R(0);
+        R kzA = A.kz, kzB = A.kz;
+        if constexpr (CLS) {
+            kzA = tab(cbyte(kh0, 1), CLS_KZ);
+            kzB = tab(cbyte(kh1, 1), CLS_KZ);
+        }
+        const R injA = (srcA && src_k) ? inject(A.src.n, sel(ch, 2, kzA)) : R(0);
+        const R injB = (srcB && src_k) ? inject(A.src.n + 1, sel(ch, 18, kzB)) : R(0);
 
         const Out<R> oA = stage_plane(SA, In<R>{cur.ex, cur.ey, cur.ez, cur.hx, cur.hy, cur.hz}, nA, fA, injA);
         const Out<R> oB = stage_plane(SB, In<R>{oA.ex14, bEY, bEZ, bHX, bHY, bHZ}, nB, fB, injB);
@@ -457,6 +512,17 @@ __global__ __launch_bounds__(TYH * LW) void k_fused2(FArgs<R> A, const int* act)
     int ty, tz, cx;
     if (!fused2_tile_of(A, act, ty, tz, cx)) return;   // whole group
     fused2_tile<R, S::rows, S::nb, S::lw, PD>(A, ty, tz, cx, L);
+}
+
+// The two-step kernel with materials by class.
+template <typename R, int TYH, int LW, int PD>
+__global__ __launch_bounds__(TYH * LW) void k_fused2_cls(FArgs<R> A, const int* act)
+{
+    typedef Shape2<R, TYH, LW> S;
+    __shared__ Lds2<R, S::rows, S::nb, S::lw, true> L;
+    int ty, tz, cx;
+    if (!fused2_tile_of(A, act, ty, tz, cx)) return;   // whole group
+    fused2_tile<R, S::rows, S::nb, S::lw, PD, false, true>(A, ty, tz, cx, L);
 }
 
 // A tile of the two-step kernel is static when every entry it loads (its rows
@@ -658,6 +724,10 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
 {
     FArgs<R> A = fused_args<R>(o, nf, M, g, alpha, src);
     if (wm) rows = 0;   // the instance that keeps witness lines has the default shape only
+    if (A.cls) {        // materials by class: the class instance's one shape, no witness lines
+        if (wm) return hipErrorInvalidValue;
+        rows = sizeof(R) == 4 ? 24 : 16;
+    }
     // with a list of active tiles, one workgroup per entry (none: every tile is
     // static and the new set already holds the result)
     const int grid = act ? nact : 0;
@@ -670,6 +740,15 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
         constexpr int TW = Default2<R>::rows * Default2<R>::lw;
         if (!act) k_fused2_wit<R, Default2<R>::rows, Default2<R>::lw><<<A.nblk, TW, 0, s>>>(A, *wm, nullptr);
         else if (grid > 0) k_fused2_wit<R, Default2<R>::rows, Default2<R>::lw><<<grid, TW, 0, s>>>(A, *wm, act);
+        done = true;
+    }
+    if (!done && A.cls) {
+        // materials by class: one shape per field type (FP32: 24 rows of 32
+        // lanes, two planes ahead, 167 VGPRs; FP64: 16 rows of 32 lanes, one
+        // plane ahead), whatever the tuning asks
+        constexpr int CR = sizeof(R) == 4 ? 24 : 16, CP = sizeof(R) == 4 ? 2 : 1;
+        if (!act) k_fused2_cls<R, CR, 32, CP><<<A.nblk, CR * 32, 0, s>>>(A, nullptr);
+        else if (grid > 0) k_fused2_cls<R, CR, 32, CP><<<grid, CR * 32, 0, s>>>(A, act);
         done = true;
     }
     if constexpr (sizeof(R) == 4) {

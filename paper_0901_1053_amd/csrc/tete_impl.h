@@ -24,13 +24,23 @@ struct Fields {
     R* c[6];     // ex, ey, ez, hx, hy, hz
 };
 
-// Material description: vacuum scalars with PEC codes, or per-entry arrays.
+// Material description: vacuum scalars with PEC codes, or per-entry arrays;
+// with materials by class also the class bytes and the class table that the
+// two-step kernel reads instead of the arrays (the arrays hold the same
+// values, expanded).
 template <typename R>
 struct Mat {
     const uint8_t* code;   // bit0: e_x PEC/absent, bit1: e_y, bit2: e_z
     const R* arr[6];       // kappa_x,y,z, mu_x,y,z per entry (nullptr: vacuum)
     R k[3], m[3];          // vacuum kappa_x,y,z and mu_x,y,z
+    const uint8_t* cls;    // class per entry (nullptr: no classes)
+    const R* ctab;         // class table, TETE_MAX_CLASSES x CLS_STRIDE
 };
+
+// Class table entries (per class, CLS_STRIDE values of the field type): the
+// coefficients of the sub-updates multiplied by their factor, as the step
+// kernels form them, and kappa_z alone for the bunch current.
+enum { CLS_AMX = 0, CLS_AMY = 1, CLS_A2MZ = 2, CLS_A2KZ = 3, CLS_AKY = 4, CLS_AKX = 5, CLS_KZ = 6, CLS_STRIDE = 8 };
 
 // Rigid-bunch source and wake accumulator for one step.
 struct Src {
@@ -65,6 +75,11 @@ struct FArgs {
     const R* ex; const R* ey; const R* ez; const R* hx; const R* hy; const R* hz;
     R* ex1; R* ey1; R* ez1; R* hx1; R* hy1; R* hz1;
     const uint8_t* code;
+    // materials by class (or null): one class byte per entry and the class
+    // table, TETE_MAX_CLASSES x CLS_STRIDE values (CLS_* order, already
+    // multiplied by their factor a or 2a)
+    const uint8_t* cls;
+    const R* ctab;
     Geo g;
     R a, kx, ky, kz, mx, my, mz;
     Src src;
@@ -202,6 +217,18 @@ hipError_t launch_batch_advance(BatchTable<R>* T, int steps, int flips, hipStrea
 template <typename R>
 hipError_t launch_energy(Fields<R> f, Mat<R> mat, Geo g, double alpha, double rw, double* partial, double* out,
                          hipStream_t s);
+// Materials by class: table (TETE_MAX_CLASSES x 6 doubles, kappa_x,y,z,
+// mu_x,y,z per class) and class bytes cls -> the six per-entry arrays dst (PEC
+// codes zero kappa, entries outside a component's range 0) and the class
+// table of the step kernels ctab (TETE_MAX_CLASSES x CLS_STRIDE, multiplied
+// by alpha or 2 alpha in R).
+template <typename R>
+hipError_t launch_expand_classes(R* const dst[6], R* ctab, const uint8_t* code, const uint8_t* cls,
+                                 const double* table, R alpha, Geo g, hipStream_t s);
+// The Gershgorin bound below for materials by class (kappa from the table,
+// zero on PEC codes); NaN also for a class byte >= ncls.
+hipError_t launch_mat_bound_cls(const uint8_t* code, const uint8_t* cls, const double* table, int ncls, Geo g,
+                                double alpha, double* partial, double* out, hipStream_t s);
 // Largest Gershgorin row sum of the three blocks of Q^e (Sec. 4.4) for
 // general materials src[6] (kappa_x,y,z, mu_x,y,z; FP32 if src_fp32) ->
 // out[0]: Q^e >= 0 if it is at most 1; NaN if a value in a component's range

@@ -563,67 +563,128 @@ __global__ void k_witness2(const R* ez_old, const R* ez_mid, const R* ez_new, Wi
 // Entries outside a component's index range are not read; a negative or
 // non-finite value in range makes the result NaN.
 // ---------------------------------------------------------------------------
+// Per-entry material arrays (kappa_x, kappa_y, kappa_z, mu_x, mu_y, mu_z).
 template <typename S>
 struct MatSrc {
-    const S* c[6];   // kappa_x, kappa_y, kappa_z, mu_x, mu_y, mu_z
+    const S* c[6];
+    __device__ double v(int comp, const Geo& g, int i, int j, int k) const
+    {
+        if (!in_nodes(g, i, j, k) || !comp_ok(comp, g, i, j, k)) return 0.0;
+        return (double)c[comp][lin(g, i, j, k)];
+    }
+    __device__ bool bad(const Geo& g, int idx, int i, int j, int k) const
+    {
+        bool b = false;
+#pragma unroll
+        for (int comp = 0; comp < 6; ++comp) {
+            if (!comp_ok(comp, g, i, j, k)) continue;
+            const double x = (double)c[comp][idx];
+            if (!(x >= 0.0) || x > DBL_MAX) b = true;
+        }
+        return b;
+    }
 };
 
-template <typename S>
-__device__ __forceinline__ double msrc(const MatSrc<S>& m, int c, const Geo& g, int i, int j, int k)
-{
-    if (!in_nodes(g, i, j, k) || !comp_ok(c, g, i, j, k)) return 0.0;
-    return (double)m.c[c][lin(g, i, j, k)];
-}
+// Materials by class: the table's values of the entry's class, kappa zero
+// where the PEC code marks the edge (the table itself is checked on the host).
+struct ClsSrc {
+    const uint8_t* code;
+    const uint8_t* cls;
+    const double* tab;   // TETE_MAX_CLASSES x 6
+    int ncls;
+    __device__ double v(int comp, const Geo& g, int i, int j, int k) const
+    {
+        if (!in_nodes(g, i, j, k) || !comp_ok(comp, g, i, j, k)) return 0.0;
+        const int id = lin(g, i, j, k);
+        if (comp < 3 && ((code[id] >> comp) & 1u)) return 0.0;
+        return tab[6 * (int)cls[id] + comp];
+    }
+    __device__ bool bad(const Geo&, int idx, int, int, int) const { return (int)cls[idx] >= ncls; }
+};
 
-template <typename S>
-__global__ __launch_bounds__(RED_THREADS) void k_mat_bound(MatSrc<S> m, Geo g, double a, double* partial)
+template <typename SRC>
+__global__ __launch_bounds__(RED_THREADS) void k_mat_bound(SRC m, Geo g, double a, double* partial)
 {
     double worst = 0.0;
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < g.np; idx += gridDim.x * blockDim.x) {
         int i, j, k;
         decomp(idx, g, i, j, k);
-        bool bad = false;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            if (!comp_ok(c, g, i, j, k)) continue;
-            const double v = (double)m.c[c][idx];
-            if (!(v >= 0.0) || v > DBL_MAX) bad = true;
-        }
-        if (bad) {
+        if (m.bad(g, idx, i, j, k)) {
             worst = NAN;
             continue;
         }
         double s = 0.0;
         // e_z row: alpha^2 sum over its four h facets of mu (kappa_z + sqrt(kappa_z kappa_z'))
-        const double kz = msrc(m, 2, g, i, j, k);
+        const double kz = m.v(2, g, i, j, k);
         if (kz > 0.0) {
-            const double r = msrc(m, 3, g, i, j, k) * (kz + sqrt(kz * msrc(m, 2, g, i, j + 1, k)))
-                           + msrc(m, 3, g, i, j - 1, k) * (kz + sqrt(kz * msrc(m, 2, g, i, j - 1, k)))
-                           + msrc(m, 4, g, i, j, k) * (kz + sqrt(kz * msrc(m, 2, g, i + 1, j, k)))
-                           + msrc(m, 4, g, i - 1, j, k) * (kz + sqrt(kz * msrc(m, 2, g, i - 1, j, k)));
+            const double r = m.v(3, g, i, j, k) * (kz + sqrt(kz * m.v(2, g, i, j + 1, k)))
+                           + m.v(3, g, i, j - 1, k) * (kz + sqrt(kz * m.v(2, g, i, j - 1, k)))
+                           + m.v(4, g, i, j, k) * (kz + sqrt(kz * m.v(2, g, i + 1, j, k)))
+                           + m.v(4, g, i - 1, j, k) * (kz + sqrt(kz * m.v(2, g, i - 1, j, k)));
             s = fmax(s, a * a * r);
         }
         // h_z row: alpha^2 sum over its four e edges of kappa (mu_z + sqrt(mu_z mu_z'))
-        const double mz = msrc(m, 5, g, i, j, k);
+        const double mz = m.v(5, g, i, j, k);
         if (mz > 0.0) {
-            const double r = msrc(m, 0, g, i, j, k) * (mz + sqrt(mz * msrc(m, 5, g, i, j - 1, k)))
-                           + msrc(m, 0, g, i, j + 1, k) * (mz + sqrt(mz * msrc(m, 5, g, i, j + 1, k)))
-                           + msrc(m, 1, g, i, j, k) * (mz + sqrt(mz * msrc(m, 5, g, i - 1, j, k)))
-                           + msrc(m, 1, g, i + 1, j, k) * (mz + sqrt(mz * msrc(m, 5, g, i + 1, j, k)));
+            const double r = m.v(0, g, i, j, k) * (mz + sqrt(mz * m.v(5, g, i, j - 1, k)))
+                           + m.v(0, g, i, j + 1, k) * (mz + sqrt(mz * m.v(5, g, i, j + 1, k)))
+                           + m.v(1, g, i, j, k) * (mz + sqrt(mz * m.v(5, g, i - 1, j, k)))
+                           + m.v(1, g, i + 1, j, k) * (mz + sqrt(mz * m.v(5, g, i + 1, j, k)));
             s = fmax(s, a * a * r);
         }
         // rows of the L block: h_x with e_y at k, k+1; h_y with e_x at k, k+1;
         // e_y with h_x at k-1, k; e_x with h_y at k-1, k
-        const double mx = msrc(m, 3, g, i, j, k), my = msrc(m, 4, g, i, j, k);
-        const double kx = msrc(m, 0, g, i, j, k), ky = msrc(m, 1, g, i, j, k);
-        s = fmax(s, a * sqrt(mx) * (sqrt(ky) + sqrt(msrc(m, 1, g, i, j, k + 1))));
-        s = fmax(s, a * sqrt(my) * (sqrt(kx) + sqrt(msrc(m, 0, g, i, j, k + 1))));
-        s = fmax(s, a * sqrt(ky) * (sqrt(mx) + sqrt(msrc(m, 3, g, i, j, k - 1))));
-        s = fmax(s, a * sqrt(kx) * (sqrt(my) + sqrt(msrc(m, 4, g, i, j, k - 1))));
+        const double mx = m.v(3, g, i, j, k), my = m.v(4, g, i, j, k);
+        const double kx = m.v(0, g, i, j, k), ky = m.v(1, g, i, j, k);
+        s = fmax(s, a * sqrt(mx) * (sqrt(ky) + sqrt(m.v(1, g, i, j, k + 1))));
+        s = fmax(s, a * sqrt(my) * (sqrt(kx) + sqrt(m.v(0, g, i, j, k + 1))));
+        s = fmax(s, a * sqrt(ky) * (sqrt(mx) + sqrt(m.v(3, g, i, j, k - 1))));
+        s = fmax(s, a * sqrt(kx) * (sqrt(my) + sqrt(m.v(4, g, i, j, k - 1))));
         worst = nan_max(worst, s);
     }
     const double r = block_reduce<true>(worst);
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// Materials by class -> the six per-entry arrays (kappa zero on PEC codes,
+// every component zero outside its range).
+template <typename R>
+__global__ void k_expand_classes(R* d0, R* d1, R* d2, R* d3, R* d4, R* d5, const uint8_t* code,
+                                 const uint8_t* cls, const double* tab, Geo g)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= g.np) return;
+    int i, j, k;
+    decomp(idx, g, i, j, k);
+    R* dst[6] = {d0, d1, d2, d3, d4, d5};
+    const int c0 = 6 * (int)cls[idx];
+    const uint32_t pec = code[idx];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const bool zero = !comp_ok(c, g, i, j, k) || (c < 3 && ((pec >> c) & 1u));
+        dst[c][idx] = zero ? R(0) : (R)tab[c0 + c];
+    }
+}
+
+// The step kernels' class table: per class the coefficients multiplied by
+// their factor in the field type, as the materials step forms them from its
+// arrays (a mu, 2a kappa_z, ...; a = alpha rounded to R, 2a = a + a).
+template <typename R>
+__global__ void k_class_table(R* ctab, const double* tab, R a)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= TETE_MAX_CLASSES) return;
+    const R a2 = a + a;
+    const double* t = tab + 6 * c;
+    R* o = ctab + CLS_STRIDE * c;
+    o[CLS_AMX] = a * (R)t[3];
+    o[CLS_AMY] = a * (R)t[4];
+    o[CLS_A2MZ] = a2 * (R)t[5];
+    o[CLS_A2KZ] = a2 * (R)t[2];
+    o[CLS_AKY] = a * (R)t[1];
+    o[CLS_AKX] = a * (R)t[0];
+    o[CLS_KZ] = (R)t[2];
+    o[7] = R(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -780,15 +841,38 @@ hipError_t launch_mat_bound(const void* const src[6], int src_fp32, Geo g, doubl
     if (src_fp32) {
         MatSrc<float> m;
         for (int c = 0; c < 6; ++c) m.c[c] = (const float*)src[c];
-        k_mat_bound<float><<<RED_BLOCKS, RED_THREADS, 0, s>>>(m, g, alpha, partial);
+        k_mat_bound<MatSrc<float>><<<RED_BLOCKS, RED_THREADS, 0, s>>>(m, g, alpha, partial);
     } else {
         MatSrc<double> m;
         for (int c = 0; c < 6; ++c) m.c[c] = (const double*)src[c];
-        k_mat_bound<double><<<RED_BLOCKS, RED_THREADS, 0, s>>>(m, g, alpha, partial);
+        k_mat_bound<MatSrc<double>><<<RED_BLOCKS, RED_THREADS, 0, s>>>(m, g, alpha, partial);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_finish<true><<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mat_bound_cls(const uint8_t* code, const uint8_t* cls, const double* table, int ncls, Geo g,
+                                double alpha, double* partial, double* out, hipStream_t s)
+{
+    ClsSrc m{code, cls, table, ncls};
+    k_mat_bound<ClsSrc><<<RED_BLOCKS, RED_THREADS, 0, s>>>(m, g, alpha, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_finish<true><<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, out);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_expand_classes(R* const dst[6], R* ctab, const uint8_t* code, const uint8_t* cls,
+                                 const double* table, R alpha, Geo g, hipStream_t s)
+{
+    k_expand_classes<R><<<nblocks(g.np, TB), TB, 0, s>>>(dst[0], dst[1], dst[2], dst[3], dst[4], dst[5], code, cls,
+                                                         table, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_class_table<R><<<1, TETE_MAX_CLASSES, 0, s>>>(ctab, table, alpha);
     return hipGetLastError();
 }
 
@@ -874,6 +958,8 @@ hipError_t launch_witness(const R* ez_old, const R* ez_new, Witness w, Geo g, in
     template hipError_t launch_import<R>(Fields<R>, const void* const[6], int, Mat<R>, Geo, hipStream_t);          \
     template hipError_t launch_export<R>(void* const[6], int, Fields<R>, Geo, hipStream_t);                        \
     template hipError_t launch_import_materials<R>(R* const[6], const void* const[6], int, Geo, hipStream_t);      \
+    template hipError_t launch_expand_classes<R>(R* const[6], R*, const uint8_t*, const uint8_t*, const double*, R, \
+                                                 Geo, hipStream_t);                                              \
     template hipError_t launch_zero_pec<R>(Fields<R>, Mat<R>, Geo, hipStream_t);                                   \
     template hipError_t launch_step<R>(Fields<R>, Fields<R>, Mat<R>, Geo, R, Src, hipStream_t, hipEvent_t*);                    \
     template hipError_t launch_energy<R>(Fields<R>, Mat<R>, Geo, double, double, double*, double*, hipStream_t);           \

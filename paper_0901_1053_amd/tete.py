@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
         "tete_grid_destroy": (st, [vp]),
         "tete_set_pec_cells": (st, [vp, vp]),
         "tete_set_materials": (st, [vp, P3, P3, C.c_int32]),
+        "tete_set_material_classes": (st, [vp, vp, vp, C.c_int32]),
         "tete_set_fields": (st, [vp, P6, C.c_int32]),
         "tete_get_fields": (st, [vp, P6, C.c_int32]),
         "tete_set_bunch": (st, [vp, C.POINTER(Bunch)]),
@@ -243,6 +244,17 @@ class Grid:
         pm = P3(*[a.data_ptr() for a in arrs[3:]])
         _chk("tete_set_materials", load().tete_set_materials(self.h, pe, pm, FP64 if dtype == "fp64" else FP32))
         self.stream.synchronize()
+
+    def set_material_classes(self, cls, table):
+        """Materials by class: cls (nx+1, ny+1, nz+1) uint8 class per entry,
+        table (ncls, 6) doubles kappa_x, kappa_y, kappa_z, mu_x, mu_y, mu_z."""
+        t = self.torch
+        d = self._dev(cls, t.uint8)
+        assert d.numel() == self.np
+        tab = np.ascontiguousarray(np.asarray(table, dtype=np.float64))
+        assert tab.ndim == 2 and tab.shape[1] == 6
+        _chk("tete_set_material_classes", load().tete_set_material_classes(self.h, C.c_void_p(d.data_ptr()),
+                                                                           tab.ctypes.data, tab.shape[0]))
 
     def set_fields(self, f: dict, dtype="fp64"):
         t = self.torch
