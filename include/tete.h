@@ -324,6 +324,22 @@ tete_status tete_static_tiles(tete_grid* g, int64_t* skipped, int64_t* total);
  * *n = steps done.  Synchronises.  TETE_ERR_NONFINITE if the sum is not finite. */
 tete_status tete_energy(tete_grid* g, double* W, int64_t* n);
 
+/* tete_energy for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same value by the same kernels, with the reduction's partial sums and
+ * result in a file-scope device array of the library instead of the grid's
+ * workspace.  That array holds RED_BLOCKS = 2048 partial sums and the result
+ * (16,448 bytes; each GPU the library runs on keeps its own copy until the
+ * process ends); the reduction uses 2048 partial sums for every grid, so
+ * every grid tete_check_desc accepts fits and no size is rejected.  The call
+ * allocates nothing (no hipMalloc, hipFree or other allocating routine); its
+ * address is looked up once per device, on the first call there.  Every
+ * partial sum and the result are written before they are read, so nothing
+ * needs clearing; calls that overlap on one GPU (other host threads, other
+ * streams) share the array and race.  Synchronises the grid's stream.
+ * Errors as tete_energy. */
+tete_status tete_energy_noalloc(tete_grid* g, double* W, int64_t* n);
+
 /* Copy the energies recorded during tete_step (see tete_set_diagnostics):
  * out[0..count-1] in step order, *count = entries recorded (<= max).  Synchronises. */
 tete_status tete_energy_series(tete_grid* g, double* out, int64_t max, int64_t* count);

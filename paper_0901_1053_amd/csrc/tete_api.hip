@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "tete_impl.h"
@@ -441,6 +442,38 @@ tete_status reset_series(tete_grid* g)
     g->pcount = 0;
     HIPCHK(launch_fill_f64(g->wacc, TETE_MAX_WAKE, 0.0, g->stream));
     HIPCHK(launch_fill_f64(g->wit, (int64_t)TETE_WITNESS_LINES * TETE_MAX_WAKE, 0.0, g->stream));
+    return TETE_OK;
+}
+
+}  // namespace
+
+// Reduction scratch of tete_energy_noalloc: the partial sums of the energy
+// reduction and its result, in a file-scope device array (each GPU holds its
+// own copy until the process ends).  In host code the name stands for a
+// host-side shadow, never a device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr int kScratchDoubles = RED_BLOCKS + 8;
+static_assert(RED_BLOCKS + 1 <= kScratchDoubles, "the energy reduction's partials and result fit the scratch");
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices];   // device address of scratch, per device
+
+// Device address of the scratch array on device dev (which must be current),
+// looked up once per device.
+tete_status scratch_on(int dev, double** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return TETE_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TETE_ERR_DEVICE;
+        g_scratch_dev[dev] = (double*)p;
+    }
+    *out = g_scratch_dev[dev];
     return TETE_OK;
 }
 
@@ -985,6 +1018,29 @@ tete_status tete_energy(tete_grid* g, double* W, int64_t* n)
     else HIPCHK(launch_energy<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->alpha, rweight(g), g->partial, g->scal, g->stream));
     double v;
     HIPCHK(hipMemcpyAsync(&v, g->scal, sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    *W = v;
+    if (n) *n = g->n;
+    return check_finite(g, &v, 1);
+}
+
+tete_status tete_energy_noalloc(tete_grid* g, double* W, int64_t* n)
+{
+    if (!g || !W) return TETE_ERR_ARG;
+    if (g->yee) return TETE_ERR_STATE;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    double* sc;
+    tete_status st = scratch_on(g->device, &sc);
+    if (st != TETE_OK) return st;
+    // the same kernels as tete_energy; every partial sum and the result are
+    // written before they are read, so nothing is cleared first
+    double* partial = sc;
+    double* result = sc + RED_BLOCKS;
+    if (g->fp32) HIPCHK(launch_energy<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->alpha, rweight(g), partial, result, g->stream));
+    else HIPCHK(launch_energy<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->alpha, rweight(g), partial, result, g->stream));
+    double v;
+    HIPCHK(hipMemcpyAsync(&v, result, sizeof(double), hipMemcpyDeviceToHost, g->stream));
     HIPCHK(hipStreamSynchronize(g->stream));
     *W = v;
     if (n) *n = g->n;

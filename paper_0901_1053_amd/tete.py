@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH):
         "tete_witness_wake": (st, [vp, vp, vp, vp, C.c_int32]),
         "tete_static_tiles": (st, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
         "tete_energy": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "tete_energy_noalloc": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "tete_energy_series": (st, [vp, vp, C.c_int64, C.POINTER(C.c_int64)]),
         "tete_probes": (st, [vp, vp, C.c_int64, C.POINTER(C.c_int64)]),
         "tete_charges": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -344,6 +345,14 @@ class Grid:
         w = C.c_double()
         n = C.c_int64()
         _chk("tete_energy", load().tete_energy(self.h, C.byref(w), C.byref(n)))
+        return w.value, n.value
+
+    def energy_noalloc(self):
+        """tete_energy_noalloc: the energy with the library's static device
+        scratch instead of the workspace (no allocation)."""
+        w = C.c_double()
+        n = C.c_int64()
+        _chk("tete_energy_noalloc", load().tete_energy_noalloc(self.h, C.byref(w), C.byref(n)))
         return w.value, n.value
 
     def energy_series(self, max_n=1 << 20) -> np.ndarray:
