@@ -34,18 +34,19 @@ def traffic_file(kernel_name, precision):
 
 def measured_traffic(kernel_name, workload, precision):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current source of the kernel; else None."""
+    were taken on the current sources of the kernel (every file it is built
+    from, by SHA-256); else None."""
     import hashlib
     try:
         with open(traffic_file(kernel_name, precision)) as fh:
             t = json.load(fh)
-        with open(os.path.join(ROOT, t["source"]), "rb") as fh:
-            sha = hashlib.sha256(fh.read()).hexdigest()
-    except (OSError, ValueError, KeyError):
+        for path, want in t["sources"].items():
+            with open(os.path.join(ROOT, path), "rb") as fh:
+                if hashlib.sha256(fh.read()).hexdigest() != want:
+                    return None
+    except (OSError, ValueError, KeyError, AttributeError):
         return None
-    if sha != t["source_sha256"] or t["workload"] != workload or t["precision"] != precision:
-        return None
-    if not (kernel_name.startswith("k_fused") or kernel_name == "k_rz"):
+    if t["workload"] != workload or t["precision"] != precision:
         return None
     return t["read_bytes_per_launch"] + t["write_bytes_per_launch"]
 METRIC = "Gcell-updates/s + HBM GB/s; batched wake solves/s with p50/p99 latency"
@@ -622,7 +623,8 @@ def main():
     ap.add_argument("--serve-max-cells", type=float, default=2 ** 28,
                     help="serving: grid cells in flight at most (0: no limit)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
-                    help="only run a plain device copy of this many GiB, 5 times (HBM counter calibration)")
+                    help="only run tete_stream_probe over six arrays of this many GiB each, 5 times (HBM "
+                         "counter calibration: reads 6 x GIB + the code bytes, writes 6 x GIB per launch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (requested --gpus %d)" % args.gpus,
@@ -634,13 +636,16 @@ def main():
 
     if args.calibrate_copy > 0:
         n = int(args.calibrate_copy * 2 ** 30) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
+        src = [torch.ones(n, dtype=torch.float32, device="cuda") for _ in range(6)]
+        dst = [torch.empty_like(src[0]) for _ in range(6)]
+        code = torch.zeros(n, dtype=torch.uint8, device="cuda")
         torch.cuda.synchronize()
         for _ in range(5):
-            dst.copy_(src)
+            tete.stream_probe(src, dst, code)
         torch.cuda.synchronize()
-        print(json.dumps({"calibration": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n}))
+        assert torch.equal(dst[3], src[3])
+        print(json.dumps({"calibration": "k_stream", "bytes_read_per_launch": 6 * 4 * n + n,
+                          "bytes_written_per_launch": 6 * 4 * n}))
         return
 
     case = inputs.large_case()
