@@ -537,6 +537,59 @@ def implicit_section(case, precision, explicit_ms_per_step, steps=4):
             "vs_explicit_two_step": round(ms / explicit_ms_per_step, 2) if explicit_ms_per_step else None}
 
 
+def open_pipes_section(sw, w_closed):
+    """The single-wake workload between open pipes (tete_set_open_pipes): the
+    bunch starts with its own field one plane before the collimator, and the
+    wake quadrature ends where no reflection from the exit wall reaches any
+    sample.  Set-up (the cross-section's potential by conjugate gradients and
+    the state) and solve times, and the difference from the closed box's wake,
+    which includes the entrance and exit wall transitions."""
+    import numpy as np
+    kst = int(round(sw.geometry["z0"] / sw.dz))          # first plane of the collimator
+    jmax = sw.jmin + sw.nw - 1
+    n0 = kst - 1
+    kend = sw.nz - (sw.M + jmax + 3) // 2
+    steps = kend + sw.M + jmax - n0
+    res = {"start_step": n0, "kend": kend, "steps": steps,
+           "exact_samples": "j < %d (entrance cut) and j <= %d (exit); beyond the first, at the level of the "
+                            "truncated bunch's alternating charge sum" % (n0 - sw.M - 1, 2 * (sw.nz - kend) - sw.M - 2)}
+    W = {}
+    for prec in ("fp64", "fp32"):
+        S = tete.Grid(sw.nx, sw.ny, sw.nz, sw.dx, sw.dy, sw.dz, sw.cdt, precision=prec)
+        S.set_pec_cells(sw.cell_mask())
+        S.set_bunch(sw.Q, sw.sigma, sw.i0, sw.j0, sw.M, sw.jmin, sw.nw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it = S.set_open_pipes(n0, kend)
+        t1 = time.perf_counter()
+        S.step(steps)
+        W[prec] = S.wake()
+        t2 = time.perf_counter()
+        res[prec] = {"setup_ms": round((t1 - t0) * 1e3, 2), "cg_iterations": it, "solve_s": round(t2 - t1, 4),
+                     "gcell_updates_per_s": round(sw.cells * steps / (t2 - t1) / 1e9, 2)}
+        del S
+        torch.cuda.empty_cache()
+    rng = float(np.max(w_closed) - np.min(w_closed))
+    res["fp32_delta_vs_fp64_gpu"] = float(np.max(np.abs(W["fp32"] - W["fp64"])) / (np.max(W["fp64"]) - np.min(W["fp64"])))
+    res["closed_box_minus_open_over_closed_range"] = float(np.max(np.abs(w_closed - W["fp64"])) / rng)
+    lam = _lambda_over_q(sw)
+    res["loss_factor_V_per_C"] = {"open": float(np.sum(W["fp64"] * lam)), "closed": float(np.sum(w_closed * lam))}
+    return res
+
+
+def _lambda_over_q(sw):
+    """Fraction of the bunch charge in the cell at each wake sample (sample j
+    at s = j dz behind the centre), for the loss factor k = sum W(s_j) lambda_j."""
+    import numpy as np
+    from math import erfc, sqrt
+    j = sw.jmin + np.arange(sw.nw)
+    out = np.zeros(sw.nw)
+    for t, jj in enumerate(j):
+        a, b = (jj - 0.5) * sw.dz / sw.sigma, (jj + 0.5) * sw.dz / sw.sigma
+        out[t] = 0.5 * (erfc(a / sqrt(2)) - erfc(b / sqrt(2))) if abs(jj) <= sw.M else 0.0
+    return out
+
+
 def rz_section(steps=100, warmup=5):
     """The rotationally symmetric scheme (24) on the deflector-like r-z workload
     at harmonic m = 1: kernel time per step in FP32 and FP64 (HIP events on the
@@ -617,6 +670,7 @@ def main():
     ap.add_argument("--no-materials", action="store_true", help="skip the per-entry materials timing")
     ap.add_argument("--no-skip", action="store_true", help="skip the static-tile skip timing")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape table of the headline grid")
+    ap.add_argument("--no-pipes", action="store_true", help="skip the open-pipe single wake")
     ap.add_argument("--batched-count", type=int, default=64)
     ap.add_argument("--serve-rates", default="1,10,50,200", help="comma-separated request rates (req/s)")
     ap.add_argument("--serve-requests", type=int, default=48)
@@ -784,6 +838,9 @@ def main():
         res["steps"] = sw.steps
         out["single_wake"] = res
         print("# single wake done", file=sys.stderr, flush=True)
+        if not args.no_pipes:
+            out["open_pipes"] = open_pipes_section(sw, w64)
+            print("# open pipes done", file=sys.stderr, flush=True)
 
     if not args.no_rz:
         out["rz"] = rz_section()

@@ -276,8 +276,52 @@ tete_status tete_grid_status(tete_grid* g);
 /* Longitudinal wake potential (Sec. 5) W(s_j) = -(1/Q) int E_z dz at
  * t = (z + s)/c on the bunch line, in V/C, for the nw samples of the bunch
  * (HOST array W of at least nw doubles).  Sample j is complete once step
- * nz - 1 + half_cells + j has run.  Synchronises the stream. */
+ * kend - 1 + half_cells + j has run (kend = nz, or the end an open-pipe run
+ * set).  Synchronises the stream. */
 tete_status tete_wake(tete_grid* g, double* W, int32_t nw);
+
+/* Open entrance and exit pipes.  The structure of Sec. 5 lies between
+ * infinitely long ingoing and outgoing pipes; the paper gives no method for
+ * them, and this call emulates both on the closed grid of scheme (23):
+ *
+ * Entrance.  The state y^n0, n0 = start_step, becomes the field that the
+ * bunch of tete_set_bunch carries through a uniform pipe, and the step
+ * counter becomes n0, so that the bunch centre sits on edge n0 - half_cells,
+ * inside the grid, with its field in place; the entrance wall sees no
+ * transition.  With p = k - n:
+ *   e_x = -(P_x phi) F(p), e_y = -(P_y phi) F(p) (plane k, time n),
+ *   h_x = (dx/dy)(P_y phi) F(p+1), h_y = -(dy/dx)(P_x phi) F(p+1)
+ *   (plane k + 1/2, time n - 1/2), e_z = h_z = 0,
+ * where phi solves the cross-section's 5-point problem
+ *   (dy/dx)(2 phi - phi(i+1,j) - phi(i-1,j)) + (dx/dy)(2 phi - phi(i,j+1) - phi(i,j-1))
+ *   = 1 at (i0, j0), 0 at the other nodes whose e_z edge is not PEC,
+ * phi = 0 on the PEC nodes (conjugate gradients in FP64 to a residual of
+ * 1e-16), and (F(p) + F(p+1))/2 = lam_{p+M}/dtau is the bunch current
+ * (cell p + M crosses edge k in step n), F(p) = 0 for p > 0.  The scheme
+ * carries this state one cell per step while the pipe stays uniform: e_z and
+ * h_z stay 0 to rounding.  Below the bunch F continues as a checkerboard of
+ * the truncated bunch's alternating charge sum (a free wave without charge);
+ * the entrance wall cuts it, which samples j >= n0 - half_cells - 1 feel at
+ * the level of the last bunch cell's charge.
+ *
+ * Exit.  The wake quadrature (tete_wake, tete_witness_wake) ends before edge
+ * kend (0: nz).  A field reflected by the exit wall reaches edge k no earlier
+ * than step 2 nz - k, and sample j meets edge k in step k + half_cells + j,
+ * so samples j <= 2 (nz - kend) - half_cells - 2 never meet a reflection.
+ *
+ * Requires: a bunch; an explicit TE/TM grid without TETE_F_MATERIALS (the
+ * pipe is vacuum with PEC walls); cell planes 0 .. n0 uniform in z (the codes
+ * of every node line repeat plane 0's, e_x and e_y from plane 1), the bunch
+ * node not on PEC; 0 <= n0 < nz, 0 <= kend <= nz.  The other field set and
+ * the witness accumulators serve as scratch; the wake and witness
+ * accumulators, series and sticky error are reset, as by tete_set_fields.
+ * tete_set_fields, tete_set_bunch, tete_clear_bunch and tete_set_pec_cells
+ * end the open-pipe run (the quadrature takes all edges again).
+ * *iterations (may be NULL) receives the conjugate-gradient iterations.
+ * Synchronises the stream.  Errors: TETE_ERR_ARG (ranges, a non-uniform
+ * entrance pipe, the bunch node on PEC), TETE_ERR_STATE (no bunch, a Yee,
+ * implicit or materials grid, or no convergence). */
+tete_status tete_set_open_pipes(tete_grid* g, int64_t start_step, int32_t kend, int32_t* iterations);
 
 /* Witness lines: off-axis and transverse wakes (Sec. 5 with the Panofsky-
  * Wenzel theorem).  The longitudinal wake of tete_wake is also sampled, with
@@ -307,8 +351,9 @@ tete_status tete_clear_witness(tete_grid* g);
  * at the first sample (choose jmin ahead of the bunch, jmin <= -half_cells,
  * so that the integral starts before any wake), in V/C; W_perp is the
  * integral of (E + v x B)_perp along the witness path over Q.  Sample j is
- * complete once step nz - 1 + half_cells + j has run.  Synchronises the
- * stream.  TETE_ERR_STATE without a bunch or witness. */
+ * complete once step kend - 1 + half_cells + j has run (kend as for
+ * tete_wake).  Synchronises the stream.  TETE_ERR_STATE without a bunch or
+ * witness. */
 tete_status tete_witness_wake(tete_grid* g, double* W, double* Wx, double* Wy, int32_t nw);
 
 /* Static tiles of a TETE_F_SKIP_STATIC grid for its current geometry (or

@@ -43,7 +43,7 @@ class _Geom(C.Structure):
 
 class _Bunch(C.Structure):
     _fields_ = [("active", C.c_int), ("i0", C.c_int), ("j0", C.c_int), ("M", C.c_int),
-                ("lam", C.POINTER(C.c_double)), ("jmin", C.c_int), ("nw", C.c_int)]
+                ("lam", C.POINTER(C.c_double)), ("jmin", C.c_int), ("nw", C.c_int), ("kend", C.c_int)]
 
 
 _lib = None
@@ -193,6 +193,7 @@ class Bunch:
     M: int
     jmin: int
     nw: int
+    kend: int = 0          # wake quadrature over edges k < kend (0: all edges)
 
 
 def run(g: Geom, m: dict, f: dict, nsteps: int, n0: int = 0, bunch: Bunch | None = None,
@@ -208,7 +209,7 @@ def run(g: Geom, m: dict, f: dict, nsteps: int, n0: int = 0, bunch: Bunch | None
         lam = bunch_cells(bunch.Q, bunch.sigma, g.dz, bunch.M)
         if acc is None:
             acc = np.zeros(bunch.nw)
-        cb = _Bunch(1, bunch.i0, bunch.j0, bunch.M, _ptr(lam), bunch.jmin, bunch.nw)
+        cb = _Bunch(1, bunch.i0, bunch.j0, bunch.M, _ptr(lam), bunch.jmin, bunch.nw, bunch.kend)
     en = np.zeros(nsteps) if want_energy else None
     pidx = None
     pout = None

@@ -458,6 +458,10 @@ void orc_bunch_cells(double Q, double sigma, double dz, int M, double* lam)
  * averaged:  acc[j - jmin] += -1/2 (e_z^{n-1/2} + e_z^{n+1/2})(i0,j0,k) with
  * n = k + M + j.  The caller divides by Q (and by eps0 for V/C).
  *
+ * Only edges k < kend enter the quadrature (kend <= 0: every edge): the wake
+ * integral of a run with open pipes ends there, so that no field reflected
+ * by the exit wall reaches it (reading of the infinite pipes of Sec. 5).
+ *
  * Per step n in [n0, n0+nsteps): energy[n-n0] = W^{n,e} of y^n (if energy),
  * probe_out[(n-n0)*nprobe + p] = f[EZ][probe_idx[p]] after the step (e_z^{n+1/2}).
  */
@@ -466,6 +470,7 @@ typedef struct {
     int i0, j0, M;
     const double* lam;   /* 2M+1 cell charges */
     int jmin, nw;        /* wake samples s_j, j = jmin .. jmin+nw-1 */
+    int kend;            /* quadrature over edges k < kend; <= 0: all nz edges */
 } orc_bunch;
 
 int orc_run(const orc_geom* g, double* const m[6], double* f[6], int n0, int nsteps,
@@ -493,7 +498,8 @@ int orc_run(const orc_geom* g, double* const m[6], double* f[6], int n0, int nst
         }
         orc_step(g, m, f, NULL, NULL, jz);
         if (jz && acc) {
-            for (int k = 0; k < g->nz; ++k) {
+            const int kend = b->kend > 0 && b->kend < g->nz ? b->kend : g->nz;
+            for (int k = 0; k < kend; ++k) {
                 int jj = n - k - b->M;
                 if (jj >= b->jmin && jj < b->jmin + b->nw)
                     acc[jj - b->jmin] += -0.5 * (ezo[k] + f[EZ][idx(g, b->i0, b->j0, k)]);

@@ -49,6 +49,8 @@ def run(g: O.Geom, m: dict, f: dict, nsteps: int, bunch: O.Bunch, lines, n0: int
         O.run(g, m, f, 1, n0=n, bunch=bunch, acc=src_acc)
         js = n - k - bunch.M
         ok = (js >= bunch.jmin) & (js < bunch.jmin + bunch.nw)
+        if 0 < bunch.kend < g.nz:
+            ok &= k < bunch.kend
         for l, (i, j) in enumerate(lines):
             new = f["ez"][i, j, : g.nz]
             # distinct edges of one step feed distinct samples

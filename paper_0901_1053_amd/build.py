@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtete.so")
-SOURCES = ["tete_api.hip", "tete_kernels.hip", "tete_fused.hip", "tete_fused2.hip", "tete_yee.hip", "tete_rz.hip", "tete_implicit.hip"]
+SOURCES = ["tete_api.hip", "tete_kernels.hip", "tete_fused.hip", "tete_fused2.hip", "tete_yee.hip", "tete_rz.hip", "tete_implicit.hip", "tete_pipe.hip"]
 ARCH = "gfx950"
 
 

@@ -145,9 +145,10 @@ struct tete_grid {
     int witness;       // witness lines armed (tete_set_witness)
     int32_t iw, jw;
     int64_t* pidx;
-    int64_t n;         // steps since create / set_fields
+    int64_t n;         // step index of y^n: 0 after create / set_fields, the start step of an open-pipe run
     int has_bunch;
     tete_bunch b;
+    int32_t kend;      // open-pipe run: the wake quadrature ends before edge kend (0: all nz edges)
     int diag_every;
     int64_t ecount, pcount, cap;
     int nprobe;
@@ -188,6 +189,10 @@ Mat<R> mats(tete_grid* g)
     return M;
 }
 
+// Edges k < wake_end(g) enter the wake quadrature: all nz, or those before
+// the end that an open-pipe run set.
+int wake_end(const tete_grid* g) { return g->kend > 0 ? g->kend : g->d.nz; }
+
 Src source(tete_grid* g, int64_t n)
 {
     Src s;
@@ -200,6 +205,7 @@ Src source(tete_grid* g, int64_t n)
     s.wacc = g->wacc;
     s.jmin = g->b.jmin;
     s.nw = g->b.nw;
+    s.kend = wake_end(g);
     return s;
 }
 
@@ -389,7 +395,7 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             if (wit)   // e_z^{n-1/2} in the old set, e_z^{n+1/2} in wm.mid, e_z^{n+3/2} in the new set
                 HIPCHK(launch_witness2<R>((const R*)g->f[g->cur][2], wm.mid, (const R*)g->f[1 - g->cur][2],
                                           witness_lines(g), g->geo, g->n, g->b.half_cells, g->b.jmin, g->b.nw,
-                                          g->wit, g->stream));
+                                          wake_end(g), g->wit, g->stream));
             g->cur = 1 - g->cur;
             g->n += 2;
             ++s;
@@ -422,7 +428,8 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
                                   source(g, g->n), g->stream, ev));
         if (wit)   // the step leaves e_z^{n-1/2} in the old set and e_z^{n+1/2} in the new one
             HIPCHK(launch_witness<R>((const R*)g->f[g->cur][2], (const R*)g->f[1 - g->cur][2], witness_lines(g),
-                                     g->geo, g->n, g->b.half_cells, g->b.jmin, g->b.nw, g->wit, g->stream));
+                                     g->geo, g->n, g->b.half_cells, g->b.jmin, g->b.nw, wake_end(g), g->wit,
+                                     g->stream));
         g->cur = 1 - g->cur;
         g->n++;
         g->skip_live = 1;
@@ -704,6 +711,7 @@ tete_status tete_set_pec_cells(tete_grid* g, const uint8_t* cells)
     g->mat_set = 0;
     g->mat_cls = 0;
     g->imp_lists = 0;
+    g->kend = 0;
     skip_invalidate(g);
     if (g->fp32) HIPCHK(launch_zero_pec<float>(fields<float>(g, g->cur), mats<float>(g), g->geo, g->stream));
     else HIPCHK(launch_zero_pec<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->stream));
@@ -809,6 +817,7 @@ tete_status tete_set_fields(tete_grid* g, const void* const f[6], int32_t dtype)
     else HIPCHK(launch_import<double>(fields<double>(g, g->cur), f, dtype == TETE_FP32, mats<double>(g), g->geo, g->stream));
     g->skip_live = 0;
     g->err = TETE_OK;
+    g->kend = 0;
     return reset_series(g);
 }
 
@@ -859,6 +868,90 @@ tete_status tete_set_bunch(tete_grid* g, const tete_bunch* b)
     HIPCHK(launch_fill_f64(g->wit, (int64_t)TETE_WITNESS_LINES * TETE_MAX_WAKE, 0.0, g->stream));
     g->b = *b;
     g->has_bunch = 1;
+    g->kend = 0;
+    return TETE_OK;
+}
+
+namespace {
+
+// Zero the six arrays of field set o (after their use as scratch they must
+// hold zeros again: entries outside a component's range are read as 0).
+tete_status zero_set(tete_grid* g, int o)
+{
+    const size_t bytes = (size_t)(g->fp32 ? 4 : 8) * (size_t)g->geo.np;
+    for (int c = 0; c < 6; ++c) HIPCHK(launch_zero_bytes(g->f[o][c], bytes, g->stream));
+    return TETE_OK;
+}
+
+}  // namespace
+
+tete_status tete_set_open_pipes(tete_grid* g, int64_t start_step, int32_t kend, int32_t* iterations)
+{
+    if (!g) return TETE_ERR_ARG;
+    if (!g->has_bunch || g->yee || g->implicit || (g->d.flags & TETE_F_MATERIALS)) return TETE_ERR_STATE;
+    const int nz = g->d.nz;
+    if (start_step < 0 || start_step >= nz || kend < 0 || kend > nz) return TETE_ERR_ARG;
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    const int64_t n2 = (int64_t)(g->d.nx + 1) * (g->d.ny + 1);
+    // scratch: the other field set, whose arrays (np entries, np >= 2 n2) each
+    // hold n2 doubles; the next step rewrites it, and it is zeroed below
+    if ((size_t)(g->fp32 ? 4 : 8) * (size_t)g->geo.np < sizeof(double) * (size_t)n2 + 256) return TETE_ERR_ARG;
+    const int o = 1 - g->cur;
+    double* a[6];
+    for (int c = 0; c < 6; ++c) a[c] = (double*)g->f[o][c];
+    const CgPlane P = {g->d.nx, g->d.ny, n2, g->d.dy / g->d.dx, g->d.dx / g->d.dy};
+    const CgWork W = {a[0], a[1], a[2], a[3], a[4], g->partial, g->scal + 8};
+    int* bad = (int*)a[5];
+    const int64_t src = (int64_t)g->b.i0 * (g->d.ny + 1) + g->b.j0;
+    HIPCHK(launch_zero_bytes(bad, 256, g->stream));
+    HIPCHK(launch_pipe_check(W.w, g->code, g->geo, P, (int)start_step + 1, bad, g->stream));
+    int hbad = 0;
+    double wsrc = 0.0;
+    HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipMemcpyAsync(&wsrc, W.w + src, sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    if (hbad || wsrc == 0.0) {
+        // a non-uniform entrance pipe, or the bunch line on PEC
+        tete_status st = zero_set(g, o);
+        HIPCHK(hipStreamSynchronize(g->stream));
+        return st == TETE_OK ? TETE_ERR_ARG : st;
+    }
+    // |r|^2 <= 1e-32 |b|^2 (b = delta): the residual at the rounding level
+    HIPCHK(launch_cg_init(W, P, src, 1e-32, g->stream));
+    const int cap = 20 * (g->d.nx + g->d.ny) + 1000, chunk = 32;
+    double hs[8] = {0};
+    int done = 0;
+    for (int it = 0; it < cap && !done; it += chunk) {
+        HIPCHK(launch_cg_iterations(W, P, chunk, g->stream));
+        HIPCHK(hipMemcpyAsync(hs, W.sc, sizeof(hs), hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipStreamSynchronize(g->stream));
+        done = hs[3] != 0.0;
+        if (!(hs[0] == hs[0])) break;                // NaN: cannot converge
+    }
+    if (!done) {
+        tete_status st = zero_set(g, o);
+        HIPCHK(hipStreamSynchronize(g->stream));
+        return st == TETE_OK ? TETE_ERR_STATE : st;
+    }
+    // the profile table in the witness accumulators (reset below)
+    HIPCHK(launch_pipe_profile(g->wit, g->lam, g->b.half_cells, g->d.cdt, g->stream));
+    if (g->fp32)
+        HIPCHK(launch_pipe_field<float>(fields<float>(g, g->cur), g->code, W.x, g->wit, g->b.half_cells, start_step,
+                                        g->d.dx / g->d.dy, g->d.dy / g->d.dx, g->geo, g->stream));
+    else
+        HIPCHK(launch_pipe_field<double>(fields<double>(g, g->cur), g->code, W.x, g->wit, g->b.half_cells, start_step,
+                                         g->d.dx / g->d.dy, g->d.dy / g->d.dx, g->geo, g->stream));
+    tete_status st = zero_set(g, o);
+    if (st != TETE_OK) return st;
+    g->skip_live = 0;
+    g->err = TETE_OK;
+    st = reset_series(g);
+    if (st != TETE_OK) return st;
+    g->n = start_step;
+    g->kend = kend;
+    HIPCHK(hipStreamSynchronize(g->stream));
+    if (iterations) *iterations = (int32_t)hs[5];
     return TETE_OK;
 }
 
@@ -866,6 +959,7 @@ tete_status tete_clear_bunch(tete_grid* g)
 {
     if (!g) return TETE_ERR_ARG;
     g->has_bunch = 0;
+    g->kend = 0;
     return TETE_OK;
 }
 

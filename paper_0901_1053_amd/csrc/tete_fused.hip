@@ -245,7 +245,7 @@ __device__ __forceinline__ void fused_tile(const FArgs<R>& A, const int ty, cons
 #pragma clang fp contract(off)
                 ezh_m1 -= (R)((double)kz1 * A.src.lam[m + A.src.M]);
             }
-            if (owned && q1 >= xs && q1 < xe) {
+            if (owned && q1 >= xs && q1 < xe && k < A.src.kend) {
                 const int64_t js = A.src.n - k - A.src.M;      // wake sample of edge k
                 if (js >= A.src.jmin && js < (int64_t)A.src.jmin + A.src.nw)
                     A.src.wacc[js - A.src.jmin] += -0.5 * ((double)EZm1 + (double)ezh_m1);

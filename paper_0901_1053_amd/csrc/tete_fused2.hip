@@ -449,8 +449,8 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
                 const int64_t js = A.src.n + 1 - k - A.src.M;   // edge k at step n+1, edge k-1 at step n
                 if (js >= A.src.jmin && js < (int64_t)A.src.jmin + A.src.nw) {
                     double w = A.src.wacc[js - A.src.jmin];
-                    if (k >= 1) w += -0.5 * ((double)ezA_km + (double)ezB_km);
-                    if (src_k) w += -0.5 * ((double)oB.ezold1 + (double)oB.ezh1);
+                    if (k >= 1 && k - 1 < A.src.kend) w += -0.5 * ((double)ezA_km + (double)ezB_km);
+                    if (src_k && k < A.src.kend) w += -0.5 * ((double)oB.ezold1 + (double)oB.ezh1);
                     A.src.wacc[js - A.src.jmin] = w;
                 }
             }

@@ -50,6 +50,7 @@ struct Src {
     const double* lam;   // 2M+1 cell charges
     double* wacc;        // wake accumulator (FP64)
     int jmin, nw;
+    int kend;            // the wake quadrature takes edges k < kend (nz, or the end of an open-pipe run)
 };
 
 enum { RED_BLOCKS = 2048, RED_THREADS = 256 };
@@ -247,15 +248,15 @@ hipError_t launch_charges(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, dou
 template <typename R>
 hipError_t launch_probes(const R* ez, const int64_t* idx, int nprobe, double* out, hipStream_t s);
 // wake quadrature of one step n on the witness lines: acc[l * TETE_MAX_WAKE +
-// j - jmin] += -1/2 (e_z^{n-1/2} + e_z^{n+1/2}) of edge k, j = n - k - M
+// j - jmin] += -1/2 (e_z^{n-1/2} + e_z^{n+1/2}) of edge k < kend, j = n - k - M
 template <typename R>
 hipError_t launch_witness(const R* ez_old, const R* ez_new, Witness w, Geo g, int64_t n, int M, int jmin, int nw,
-                          double* acc, hipStream_t s);
+                          int kend, double* acc, hipStream_t s);
 // the same for steps n and n+1 of one two-step launch, e_z^{n+1/2} from the
 // lines' mid buffer (WitMid)
 template <typename R>
 hipError_t launch_witness2(const R* ez_old, const R* ez_mid, const R* ez_new, Witness w, Geo g, int64_t n, int M,
-                           int jmin, int nw, double* acc, hipStream_t s);
+                           int jmin, int nw, int kend, double* acc, hipStream_t s);
 
 // Work arrays of the implicit scheme's plane solves (np entries each)
 template <typename R>
@@ -280,5 +281,34 @@ hipError_t launch_step_implicit(Fields<R> o, Fields<R> w, Mat<R> M, Geo g, doubl
                                 ImpWork<R> wk, hipStream_t s, hipEvent_t* ev);
 // Chebyshev iterations per plane solve and the spectral bound used
 int implicit_iters(const Geo& g, double dx, double dy, double alpha, int fp32, double* lmax);
+
+// ---- open pipes (tete_pipe.hip) ------------------------------------------
+// Node plane of the entrance cross-section: (nx+1)(ny+1) nodes, node (i, j)
+// at j + (ny+1) i; wx = dy/dx, wy = dx/dy weigh the x and y neighbours of the
+// cross-section's Laplacian.
+struct CgPlane {
+    int nx, ny;
+    int64_t n;
+    double wx, wy;
+};
+// Conjugate-gradient work arrays (n doubles each), the free-node weights w,
+// RED_BLOCKS partial sums and the iteration's scalars sc (8 doubles).
+struct CgWork {
+    double *x, *r, *p, *q, *w, *partial, *sc;
+};
+// free-node weights from the e_z codes of plane 0, and *bad = 1 unless cell
+// planes 0 .. kst-1 are uniform (*bad must hold 0 before)
+hipError_t launch_pipe_check(double* w, const uint8_t* code, Geo g, CgPlane P, int kst, int* bad, hipStream_t s);
+// x = 0, r = p = delta at node src; tol bounds |r|^2 for convergence
+hipError_t launch_cg_init(CgWork W, CgPlane P, int64_t src, double tol, hipStream_t s);
+// iters iterations (a converged iteration leaves x unchanged); sc[0] = |r|^2,
+// sc[3] = 1 once converged, sc[5] = the iterations taken
+hipError_t launch_cg_iterations(CgWork W, CgPlane P, int iters, hipStream_t s);
+// profile table F[p + 2M + 1], p = -2M-1 .. 1, of the bunch current lam
+hipError_t launch_pipe_profile(double* F, const double* lam, int M, double dtau, hipStream_t s);
+// the state y^{n0} of the bunch's field in the pipe into f
+template <typename R>
+hipError_t launch_pipe_field(Fields<R> f, const uint8_t* code, const double* phi, const double* F, int M, int64_t n0,
+                             double rxy, double ryx, Geo g, hipStream_t s);
 
 }  // namespace tete

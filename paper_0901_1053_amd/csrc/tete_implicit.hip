@@ -314,7 +314,7 @@ __global__ void k_imp_back_u(Fields<R> o, Fields<R> w, const uint8_t* code, IGeo
         const R e0 = ez[idx];
         if (mx != (R)0) w.c[3][idx] -= c.a * mx * (val(ez, g, i, j + 1, k) - e0);
         if (my != (R)0) w.c[4][idx] += c.a * my * (val(ez, g, i + 1, j, k) - e0);
-        if (src.on && i == src.i0 && j == src.j0 && k < g.nz) {
+        if (src.on && i == src.i0 && j == src.j0 && k < src.kend) {
             const int64_t js = src.n - k - src.M;            // wake sample of edge k
             if (js >= src.jmin && js < (int64_t)src.jmin + src.nw)
                 src.wacc[js - src.jmin] += -0.5 * ((double)o.c[2][idx] + (double)e0);

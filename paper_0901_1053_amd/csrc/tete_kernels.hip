@@ -270,7 +270,7 @@ __global__ __launch_bounds__(TB) void k_tm(Fields<R> o, Fields<R> nf, Mat<R> M, 
     nf.c[4][idx] = hyv;
 
     // wake: W(s_j) sample of edge k is taken in step n = k + M + j
-    if (src.on && i == src.i0 && j == src.j0 && k < g.nz) {
+    if (src.on && i == src.i0 && j == src.j0 && k < src.kend) {
         int64_t js = src.n - k - src.M;
         if (js >= src.jmin && js < (int64_t)src.jmin + src.nw)
             src.wacc[js - src.jmin] += -0.5 * ((double)ez[idx] + (double)e0);
@@ -515,11 +515,11 @@ __global__ void k_probes(const R* ez, const int64_t* idx, int n, double* out)
 // One thread per (edge k, line blockIdx.y).  Within one step the edges of a
 // line feed distinct samples, so no two threads add to one accumulator.
 template <typename R>
-__global__ void k_witness(const R* ez_old, const R* ez_new, Witness w, int nz, int64_t n, int M, int jmin, int nw,
+__global__ void k_witness(const R* ez_old, const R* ez_new, Witness w, int kend, int64_t n, int M, int jmin, int nw,
                           double* acc)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nz) return;
+    if (k >= kend) return;
     const int64_t js = n - k - M;
     if (js < jmin || js >= (int64_t)jmin + nw) return;
     const int l = blockIdx.y;
@@ -531,8 +531,8 @@ __global__ void k_witness(const R* ez_old, const R* ez_new, Witness w, int nz, i
 // sample j takes edge k = n - j - M in step n and edge k+1 in step n+1, added
 // in that order, as two single steps would add them.
 template <typename R>
-__global__ void k_witness2(const R* ez_old, const R* ez_mid, const R* ez_new, Witness w, int nz, int64_t n, int M,
-                           int jmin, int nw, double* acc)
+__global__ void k_witness2(const R* ez_old, const R* ez_mid, const R* ez_new, Witness w, int nz, int kend, int64_t n,
+                           int M, int jmin, int nw, double* acc)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nw) return;
@@ -540,8 +540,8 @@ __global__ void k_witness2(const R* ez_old, const R* ez_mid, const R* ez_new, Wi
     const int64_t k = n - ((int64_t)jmin + t) - M;
     const R* mid = ez_mid + (int64_t)l * nz;
     double a = acc[(int64_t)l * TETE_MAX_WAKE + t];
-    if (k >= 0 && k < nz) a += -0.5 * ((double)ez_old[w.base[l] + k] + (double)mid[k]);
-    if (k + 1 >= 0 && k + 1 < nz) a += -0.5 * ((double)mid[k + 1] + (double)ez_new[w.base[l] + k + 1]);
+    if (k >= 0 && k < kend) a += -0.5 * ((double)ez_old[w.base[l] + k] + (double)mid[k]);
+    if (k + 1 >= 0 && k + 1 < kend) a += -0.5 * ((double)mid[k + 1] + (double)ez_new[w.base[l] + k + 1]);
     acc[(int64_t)l * TETE_MAX_WAKE + t] = a;
 }
 
@@ -932,24 +932,24 @@ hipError_t launch_probes(const R* ez, const int64_t* idx, int nprobe, double* ou
 
 template <typename R>
 hipError_t launch_witness2(const R* ez_old, const R* ez_mid, const R* ez_new, Witness w, Geo g, int64_t n, int M,
-                           int jmin, int nw, double* acc, hipStream_t s)
+                           int jmin, int nw, int kend, double* acc, hipStream_t s)
 {
-    if (nw < 1 || nw > TETE_MAX_WAKE) return hipErrorInvalidValue;
+    if (nw < 1 || nw > TETE_MAX_WAKE || kend < 0 || kend > g.nz) return hipErrorInvalidValue;
     for (int l = 0; l < TETE_WITNESS_LINES; ++l)   // every line inside the array
         if (w.base[l] < 0 || w.base[l] + g.nz > (int64_t)g.np) return hipErrorInvalidValue;
-    k_witness2<R><<<dim3(nblocks(nw, TB), TETE_WITNESS_LINES), TB, 0, s>>>(ez_old, ez_mid, ez_new, w, g.nz, n, M,
-                                                                          jmin, nw, acc);
+    k_witness2<R><<<dim3(nblocks(nw, TB), TETE_WITNESS_LINES), TB, 0, s>>>(ez_old, ez_mid, ez_new, w, g.nz, kend, n,
+                                                                          M, jmin, nw, acc);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_witness(const R* ez_old, const R* ez_new, Witness w, Geo g, int64_t n, int M, int jmin, int nw,
-                          double* acc, hipStream_t s)
+                          int kend, double* acc, hipStream_t s)
 {
-    if (nw < 1 || nw > TETE_MAX_WAKE) return hipErrorInvalidValue;
+    if (nw < 1 || nw > TETE_MAX_WAKE || kend < 0 || kend > g.nz) return hipErrorInvalidValue;
     for (int l = 0; l < TETE_WITNESS_LINES; ++l)   // every line inside the array
         if (w.base[l] < 0 || w.base[l] + g.nz > (int64_t)g.np) return hipErrorInvalidValue;
-    k_witness<R><<<dim3(nblocks(g.nz, TB), TETE_WITNESS_LINES), TB, 0, s>>>(ez_old, ez_new, w, g.nz, n, M, jmin, nw,
+    k_witness<R><<<dim3(nblocks(g.nz, TB), TETE_WITNESS_LINES), TB, 0, s>>>(ez_old, ez_new, w, kend, n, M, jmin, nw,
                                                                             acc);
     return hipGetLastError();
 }
@@ -966,9 +966,9 @@ hipError_t launch_witness(const R* ez_old, const R* ez_new, Witness w, Geo g, in
     template hipError_t launch_charges<R>(Fields<R>, Fields<R>, Mat<R>, Geo, double, Src, double*, double*,        \
                                           hipStream_t);                                                            \
     template hipError_t launch_probes<R>(const R*, const int64_t*, int, double*, hipStream_t);                     \
-    template hipError_t launch_witness<R>(const R*, const R*, Witness, Geo, int64_t, int, int, int, double*,        \
+    template hipError_t launch_witness<R>(const R*, const R*, Witness, Geo, int64_t, int, int, int, int, double*,   \
                                           hipStream_t);                                                            \
-    template hipError_t launch_witness2<R>(const R*, const R*, const R*, Witness, Geo, int64_t, int, int, int,      \
+    template hipError_t launch_witness2<R>(const R*, const R*, const R*, Witness, Geo, int64_t, int, int, int, int, \
                                            double*, hipStream_t);
 
 TETE_INST(double)

@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH):
         "tete_get_fields": (st, [vp, P6, C.c_int32]),
         "tete_set_bunch": (st, [vp, C.POINTER(Bunch)]),
         "tete_clear_bunch": (st, [vp]),
+        "tete_set_open_pipes": (st, [vp, C.c_int64, C.c_int32, C.POINTER(C.c_int32)]),
         "tete_set_diagnostics": (st, [vp, C.c_int32]),
         "tete_set_probes": (st, [vp, vp, C.c_int32]),
         "tete_step": (st, [vp, C.c_int64]),
@@ -285,6 +286,16 @@ class Grid:
     def clear_bunch(self):
         _chk("tete_clear_bunch", load().tete_clear_bunch(self.h))
         self.bunch = None
+
+    def set_open_pipes(self, start_step: int, kend: int = 0) -> int:
+        """Open entrance and exit pipes (tete_set_open_pipes): the bunch's
+        field in the uniform entrance pipe as the state of step start_step,
+        and the wake quadrature ending before edge kend (0: all edges).
+        Returns the conjugate-gradient iterations of the cross-section's
+        potential."""
+        it = C.c_int32(0)
+        _chk("tete_set_open_pipes", load().tete_set_open_pipes(self.h, int(start_step), int(kend), C.byref(it)))
+        return it.value
 
     def set_diagnostics(self, every: int):
         _chk("tete_set_diagnostics", load().tete_set_diagnostics(self.h, every))

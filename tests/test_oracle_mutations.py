@@ -299,3 +299,51 @@ def test_witness_pins_catch_planted_mistake(tmp_path, name):
         except (AssertionError, FloatingPointError, ValueError):
             caught += 1
     assert caught >= 1, "no pin caught mutant %s" % name
+
+
+# ---- the open-pipe oracle (Python), same harness
+from tests import test_oracle_pipe as TPI
+
+PI_SRC = os.path.join(os.path.dirname(HERE), "oracle", "pipe_oracle.py")
+
+PI_MUTANTS = {
+    # h taken at the same time level as e (no half-step stagger)
+    "pipe_h_stagger": ([("Fh = profile(lam, M, g.cdt, k + 1 - n0)", "Fh = profile(lam, M, g.cdt, k - n0)")],
+                       [lambda p: TPI.test_self_field_moves_one_cell_per_step(p, 5, 7, 1.0)]),
+    # the x and y weights of the cross-section's operator swapped
+    "pipe_weights_swapped": ([("wx, wy = g.dy / g.dx, g.dx / g.dy", "wx, wy = g.dx / g.dy, g.dy / g.dx")],
+                             [lambda p: TPI.test_potential_matches_discrete_sine_series(p)]),
+    # the profile's mean tied to half the current
+    "pipe_profile_half": ([("F[q] = 2.0 * cur - F[q + 1]", "F[q] = cur - F[q + 1]")],
+                          [lambda p: TPI.test_self_field_node_charges_are_the_bunch(p)]),
+    # h_y with the wrong sign
+    "pipe_hy_sign": ([('f["hy"][:-1, :, :-1] = ((g.dy / g.dx) * Ex)', 'f["hy"][:-1, :, :-1] = (-(g.dy / g.dx) * Ex)')],
+                     [lambda p: TPI.test_self_field_moves_one_cell_per_step(p, 5, 7, 1.0)]),
+    # the bunch cells one cell late in the profile
+    "pipe_cell_offset": ([("cur = lam[q + 2 * M] / dtau if q >= -2 * M else 0.0",
+                           "cur = lam[q + 2 * M - 1] / dtau if q >= -2 * M + 1 else 0.0")],
+                         [lambda p: TPI.test_self_field_node_charges_are_the_bunch(p)]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PI_MUTANTS))
+def test_pipe_pins_catch_planted_mistake(tmp_path, name):
+    edits, pins = PI_MUTANTS[name]
+    src = open(PI_SRC).read()
+    for old, new in edits:
+        assert src.count(old) >= 1, (name, old)
+        src = src.replace(old, new, 1)
+    p = tmp_path / (name + ".py")
+    p.write_text(src)
+    spec = importlib.util.spec_from_file_location("pi_mutant_" + name, str(p))
+    mod = importlib.util.module_from_spec(spec)
+    sys.modules[spec.name] = mod
+    spec.loader.exec_module(mod)
+    caught = 0
+    for pin in pins:
+        try:
+            with np.errstate(all="ignore"):
+                pin(mod)
+        except (AssertionError, FloatingPointError, ValueError):
+            caught += 1
+    assert caught >= 1, "no pin caught mutant %s" % name
