@@ -545,6 +545,8 @@ def open_pipes_section(sw, w_closed):
     the state) and solve times, and the difference from the closed box's wake,
     which includes the entrance and exit wall transitions."""
     import numpy as np
+    import torch
+    from paper_0901_1053_amd import tete
     kst = int(round(sw.geometry["z0"] / sw.dz))          # first plane of the collimator
     jmax = sw.jmin + sw.nw - 1
     n0 = kst - 1
@@ -572,22 +574,8 @@ def open_pipes_section(sw, w_closed):
     rng = float(np.max(w_closed) - np.min(w_closed))
     res["fp32_delta_vs_fp64_gpu"] = float(np.max(np.abs(W["fp32"] - W["fp64"])) / (np.max(W["fp64"]) - np.min(W["fp64"])))
     res["closed_box_minus_open_over_closed_range"] = float(np.max(np.abs(w_closed - W["fp64"])) / rng)
-    lam = _lambda_over_q(sw)
-    res["loss_factor_V_per_C"] = {"open": float(np.sum(W["fp64"] * lam)), "closed": float(np.sum(w_closed * lam))}
+    res["W_range_V_per_C"] = {"open": float(np.ptp(W["fp64"])), "closed": rng}
     return res
-
-
-def _lambda_over_q(sw):
-    """Fraction of the bunch charge in the cell at each wake sample (sample j
-    at s = j dz behind the centre), for the loss factor k = sum W(s_j) lambda_j."""
-    import numpy as np
-    from math import erfc, sqrt
-    j = sw.jmin + np.arange(sw.nw)
-    out = np.zeros(sw.nw)
-    for t, jj in enumerate(j):
-        a, b = (jj - 0.5) * sw.dz / sw.sigma, (jj + 0.5) * sw.dz / sw.sigma
-        out[t] = 0.5 * (erfc(a / sqrt(2)) - erfc(b / sqrt(2))) if abs(jj) <= sw.M else 0.0
-    return out
 
 
 def rz_section(steps=100, warmup=5):
