@@ -195,7 +195,16 @@ tete_status tete_set_pec_cells(tete_grid* g, const uint8_t* cell_is_pec);
  * primes denoting the neighbour across the facet or edge.  With vacuum
  * coefficients this is the bound (25).  If the largest sum exceeds 1 (to
  * 1e-12) the call returns TETE_ERR_UNSTABLE and changes nothing.  The test
- * is sufficient, not necessary.  Synchronises the stream. */
+ * is sufficient, not necessary.
+ * Classes found in the arrays: after importing, the library collects the
+ * distinct tuples (kappa_x, kappa_y, kappa_z, mu_x, mu_y, mu_z) of the entries
+ * (in the grid's precision; 0 outside a component's range) with a hash table
+ * on the GPU.  If there are at most TETE_MAX_CLASSES and kappa is 0 on every
+ * edge the PEC codes mark (the box walls and tete_set_pec_cells), the grid
+ * runs as after tete_set_material_classes with those tuples: paired steps
+ * take the two-step kernel's class instance, with the same results as the
+ * materials step over the arrays.  Otherwise every step is the materials
+ * step.  Synchronises the stream. */
 tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3],
                                const void* const inv_mu[3], int32_t dtype);
 

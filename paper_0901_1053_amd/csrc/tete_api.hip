@@ -718,6 +718,63 @@ tete_status tete_set_pec_cells(tete_grid* g, const uint8_t* cells)
     return TETE_OK;
 }
 
+extern "C++" {
+namespace {
+
+// Materials by class recognised in imported per-entry arrays: if the arrays
+// hold at most TETE_MAX_CLASSES distinct coefficient tuples and kappa is 0 on
+// every edge the PEC codes mark, the grid gets their class bytes and table,
+// so that paired steps run the two-step kernel's class instance; the arrays
+// stay as they are (the class expansion would give them bitwise).  Otherwise
+// nothing changes.  Work space: the reduction partials (hash keys, tuples,
+// slot classes) and scalars (flags).
+template <typename R>
+tete_status find_classes(tete_grid* g)
+{
+    unsigned long long* keys = (unsigned long long*)g->partial;
+    double* vals = g->partial + CLS_SLOTS;
+    int* slot_class = (int*)(g->partial + 7 * CLS_SLOTS);
+    static_assert(7 * CLS_SLOTS + CLS_SLOTS / 2 <= 2 * RED_BLOCKS, "the class search fits the partials");
+    int* flags = (int*)(g->scal + 16);
+    R* arr[6];
+    for (int c = 0; c < 6; ++c) arr[c] = (R*)g->mat[c];
+    HIPCHK(launch_zero_bytes(keys, sizeof(unsigned long long) * CLS_SLOTS, g->stream));
+    HIPCHK(launch_zero_bytes(flags, 4 * sizeof(int), g->stream));
+    HIPCHK(launch_classify<R>(arr, g->code, g->geo, keys, vals, nullptr, nullptr, flags, 0, g->stream));
+    std::vector<unsigned long long> hk(CLS_SLOTS);
+    int hf[4];
+    HIPCHK(hipMemcpyAsync(hk.data(), keys, sizeof(unsigned long long) * CLS_SLOTS, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    if (hf[0] || hf[1]) return TETE_OK;
+    // classes numbered in the order of their keys (the same numbering every run)
+    std::vector<std::pair<unsigned long long, int>> used;
+    for (int t = 0; t < CLS_SLOTS; ++t)
+        if (hk[t]) used.emplace_back(hk[t], t);
+    if (used.empty() || used.size() > (size_t)TETE_MAX_CLASSES) return TETE_OK;
+    std::sort(used.begin(), used.end());
+    std::vector<int> sc(CLS_SLOTS, -1);
+    for (size_t c = 0; c < used.size(); ++c) sc[used[c].second] = (int)c;
+    HIPCHK(hipMemcpyAsync(slot_class, sc.data(), sizeof(int) * CLS_SLOTS, hipMemcpyHostToDevice, g->stream));
+    HIPCHK(launch_classify<R>(arr, g->code, g->geo, keys, vals, slot_class, g->cls, flags, 1, g->stream));
+    std::vector<double> hv((size_t)6 * CLS_SLOTS);
+    HIPCHK(hipMemcpyAsync(hv.data(), vals, sizeof(double) * hv.size(), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));   // sc and hv are host temporaries
+    if (hf[2]) return TETE_OK;                 // two tuples shared a key: keep the arrays alone
+    std::vector<double> t((size_t)6 * TETE_MAX_CLASSES, 0.0);
+    for (size_t c = 0; c < used.size(); ++c)
+        for (int e = 0; e < 6; ++e) t[6 * c + e] = hv[(size_t)6 * used[c].second + e];
+    HIPCHK(hipMemcpyAsync(g->craw, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice, g->stream));
+    HIPCHK(launch_class_table<R>((R*)g->ctab, g->craw, (R)g->alpha, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));   // t is a host temporary
+    g->mat_cls = 1;
+    return TETE_OK;
+}
+
+}  // namespace
+}  // extern "C++"
+
 tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3], const void* const inv_mu[3], int32_t dtype)
 {
     if (!g || !inv_eps || !inv_mu) return TETE_ERR_ARG;
@@ -756,7 +813,7 @@ tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3], const
         skip_invalidate(g);
         HIPCHK(launch_zero_pec<double>(fields<double>(g, g->cur), mats<double>(g), g->geo, g->stream));
     }
-    return TETE_OK;
+    return g->fp32 ? find_classes<float>(g) : find_classes<double>(g);
 }
 
 tete_status tete_set_material_classes(tete_grid* g, const uint8_t* cls, const double* table, int32_t ncls)

@@ -41,6 +41,9 @@ struct Mat {
 // coefficients of the sub-updates multiplied by their factor, as the step
 // kernels form them, and kappa_z alone for the bunch current.
 enum { CLS_AMX = 0, CLS_AMY = 1, CLS_A2MZ = 2, CLS_A2KZ = 3, CLS_AKY = 4, CLS_AKX = 5, CLS_KZ = 6, CLS_STRIDE = 8 };
+// Slots of the hash table that recognises classes in per-entry arrays
+// (a power of two, twice the classes a grid may have)
+enum { CLS_SLOTS = 2 * TETE_MAX_CLASSES };
 
 // Rigid-bunch source and wake accumulator for one step.
 struct Src {
@@ -228,6 +231,17 @@ hipError_t launch_expand_classes(R* const dst[6], R* ctab, const uint8_t* code, 
                                  const double* table, R alpha, Geo g, hipStream_t s);
 // The Gershgorin bound below for materials by class (kappa from the table,
 // zero on PEC codes); NaN also for a class byte >= ncls.
+// classes in the per-entry arrays arr (tete_set_materials): pass 0 fills the
+// hash table keys / vals (CLS_SLOTS each; keys and flags zero before), pass 1
+// writes the class byte of every entry from slot_class (the class of each
+// slot, -1 for none); flags[0..2]: overflow, kappa on a PEC-coded edge, a
+// tuple unlike its slot's
+template <typename R>
+hipError_t launch_classify(R* const arr[6], const uint8_t* code, Geo g, unsigned long long* keys, double* vals,
+                           const int* slot_class, uint8_t* cls, int* flags, int pass, hipStream_t s);
+// the step kernels' class table from the table of doubles (TETE_MAX_CLASSES x 6)
+template <typename R>
+hipError_t launch_class_table(R* ctab, const double* table, R alpha, hipStream_t s);
 hipError_t launch_mat_bound_cls(const uint8_t* code, const uint8_t* cls, const double* table, int ncls, Geo g,
                                 double alpha, double* partial, double* out, hipStream_t s);
 // Largest Gershgorin row sum of the three blocks of Q^e (Sec. 4.4) for

@@ -666,6 +666,114 @@ __global__ void k_expand_classes(R* d0, R* d1, R* d2, R* d3, R* d4, R* d5, const
     }
 }
 
+template <typename R>
+struct Six {
+    R* c[6];
+};
+
+// Classes recognised in per-entry arrays (tete_set_materials): entries with
+// the same six coefficients share a class.  A table of CLS_SLOTS slots keyed
+// by a 64-bit hash of the tuple's bits (open addressing, linear probing)
+// collects the distinct tuples; a second pass finds each entry's slot,
+// checks its tuple against the slot's bitwise (two tuples with one hash
+// fail this check) and writes its class byte.  Entries outside a
+// component's range hold 0 there, as imported.  flags[0]: the table
+// overflowed; flags[1]: an e edge that the PEC codes mark carries a nonzero
+// kappa (the class kernel takes kappa 0 there from the codes); flags[2]: a
+// tuple differs from its slot's.
+__device__ __forceinline__ uint64_t mix64(uint64_t x)
+{
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    x ^= x >> 31;
+    return x;
+}
+
+template <typename R>
+__device__ __forceinline__ uint64_t bits_of(R v)
+{
+    if constexpr (sizeof(R) == 4) return (uint64_t)__builtin_bit_cast(uint32_t, v);
+    else return __builtin_bit_cast(uint64_t, v);
+}
+
+template <typename R>
+__device__ __forceinline__ uint64_t tuple_key(const R (&v)[6])
+{
+    uint64_t h = 0x9e3779b97f4a7c15ull;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) h = mix64(h ^ (bits_of(v[c]) + (uint64_t)(c + 1) * 0x632be59bd9b4e019ull));
+    return h | 1ull;                      // 0 marks an empty slot
+}
+
+template <typename R>
+__global__ void k_classify_insert(Six<const R> m, const uint8_t* code, Geo g, unsigned long long* keys,
+                                  double* vals, int* flags)
+{
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < g.np;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        R v[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = m.c[c][idx];
+        const uint32_t pec = code[idx];
+        if ((((pec & 1u) && v[0] != R(0)) || ((pec & 2u) && v[1] != R(0)) || ((pec & 4u) && v[2] != R(0))))
+            flags[1] = 1;
+        const unsigned long long key = tuple_key(v);
+        int slot = (int)((key >> 32) & (CLS_SLOTS - 1));
+        bool placed = false;
+        for (int t = 0; t < CLS_SLOTS && !placed; ++t) {
+            // read first: after the first insertion every entry of the class
+            // finds its key without an atomic
+            unsigned long long cur = keys[slot];
+            if (cur == 0ull) {
+                cur = atomicCAS(&keys[slot], 0ull, key);
+                if (cur == 0ull) {                     // this entry inserted the tuple
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) vals[6 * slot + c] = (double)v[c];
+                    placed = true;
+                    break;
+                }
+            }
+            if (cur == key) placed = true;
+            else slot = (slot + 1) & (CLS_SLOTS - 1);
+        }
+        if (!placed) flags[0] = 1;
+    }
+}
+
+template <typename R>
+__global__ void k_classify_assign(Six<const R> m, Geo g, const unsigned long long* keys, const double* vals,
+                                  const int* slot_class, uint8_t* cls, int* flags)
+{
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < g.np;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        R v[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = m.c[c][idx];
+        const unsigned long long key = tuple_key(v);
+        int slot = (int)((key >> 32) & (CLS_SLOTS - 1));
+        int found = -1;
+        for (int t = 0; t < CLS_SLOTS; ++t) {
+            const unsigned long long cur = keys[slot];
+            if (cur == key) { found = slot; break; }
+            if (cur == 0ull) break;
+            slot = (slot + 1) & (CLS_SLOTS - 1);
+        }
+        bool same = found >= 0 && slot_class[found] >= 0;
+        if (same) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) same = same && bits_of((R)vals[6 * found + c]) == bits_of(v[c]);
+        }
+        if (!same) {
+            flags[2] = 1;
+            cls[idx] = 0;
+        } else {
+            cls[idx] = (uint8_t)slot_class[found];
+        }
+    }
+}
+
 // The step kernels' class table: per class the coefficients multiplied by
 // their factor in the field type, as the materials step forms them from its
 // arrays (a mu, 2a kappa_z, ...; a = alpha rounded to R, 2a = a + a).
@@ -695,10 +803,6 @@ __global__ void k_class_table(R* ctab, const double* tab, R a)
 // must be read).  n is a multiple of 4 handled by whole threads; the host
 // copies the remainder with a second launch of this kernel at offset.
 // ---------------------------------------------------------------------------
-template <typename R>
-struct Six {
-    R* c[6];
-};
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_stream(Six<R> in, Six<R> out, const uint8_t* code, int64_t n4)
@@ -876,6 +980,25 @@ hipError_t launch_expand_classes(R* const dst[6], R* ctab, const uint8_t* code, 
     return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_classify(R* const arr[6], const uint8_t* code, Geo g, unsigned long long* keys, double* vals,
+                           const int* slot_class, uint8_t* cls, int* flags, int pass, hipStream_t s)
+{
+    Six<const R> m;
+    for (int c = 0; c < 6; ++c) m.c[c] = arr[c];
+    const int nb = (int)std::min<int64_t>(nblocks(g.np, TB), 16384);
+    if (pass == 0) k_classify_insert<R><<<nb, TB, 0, s>>>(m, code, g, keys, vals, flags);
+    else k_classify_assign<R><<<nb, TB, 0, s>>>(m, g, keys, vals, slot_class, cls, flags);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_class_table(R* ctab, const double* table, R alpha, hipStream_t s)
+{
+    k_class_table<R><<<1, TETE_MAX_CLASSES, 0, s>>>(ctab, table, alpha);
+    return hipGetLastError();
+}
+
 hipError_t launch_stream(void* const in[6], void* const out[6], const uint8_t* code, int64_t n, int fp32,
                          hipStream_t s)
 {
@@ -960,6 +1083,9 @@ hipError_t launch_witness(const R* ez_old, const R* ez_new, Witness w, Geo g, in
     template hipError_t launch_import_materials<R>(R* const[6], const void* const[6], int, Geo, hipStream_t);      \
     template hipError_t launch_expand_classes<R>(R* const[6], R*, const uint8_t*, const uint8_t*, const double*, R, \
                                                  Geo, hipStream_t);                                              \
+    template hipError_t launch_classify<R>(R* const[6], const uint8_t*, Geo, unsigned long long*, double*,         \
+                                           const int*, uint8_t*, int*, int, hipStream_t);                         \
+    template hipError_t launch_class_table<R>(R*, const double*, R, hipStream_t);                                  \
     template hipError_t launch_zero_pec<R>(Fields<R>, Mat<R>, Geo, hipStream_t);                                   \
     template hipError_t launch_step<R>(Fields<R>, Fields<R>, Mat<R>, Geo, R, Src, hipStream_t, hipEvent_t*);                    \
     template hipError_t launch_energy<R>(Fields<R>, Mat<R>, Geo, double, double, double*, double*, hipStream_t);           \

@@ -73,6 +73,8 @@ def test_classes_two_step_equals_single_materials_steps(orc, precision):
     out = []
     for use_cls in (True, False):
         G = _grid(g, cells, precision, cls if use_cls else None, table, None if use_cls else mat)
+        if not use_cls:
+            G.set_tuning("fused")      # the arrays hold few tuples: force the materials step
         G.set_fields(inputs.random_fields(g.shape, 44))
         G.set_bunch(1e-9, 3e-3, g.nx // 2, g.ny // 2, 18, -20, 120)
         assert G.get_tuning()["kernel"] == ("fused2" if use_cls else "fused")
