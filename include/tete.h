@@ -617,6 +617,26 @@ tete_status tete_rz_set_bunch(tete_rz* g, const tete_rz_bunch* b);
  * Errors: TETE_ERR_ARG (nsteps < 0), TETE_ERR_DEVICE. */
 tete_status tete_rz_step(tete_rz* g, int64_t nsteps);
 
+/* Open entrance and exit pipes for the r-z grid (the construction of
+ * tete_set_open_pipes for scheme (24)).  The state of step start_step
+ * becomes the ring bunch's own field in the uniform entrance pipe:
+ *   e_phi = -m Phi_j F(p), e_r = -(Phi_{j+1} - Phi_j) F(p),
+ *   h_phi = (r_{j+1/2}/dr)(Phi_{j+1} - Phi_j) F(p+1), h_r = (dr/r_j) e_phi-shape F(p+1),
+ *   e_z = h_z = 0, p = k - n,
+ * where Phi solves the radial problem
+ *   [r_{j-1/2}(Phi_j - Phi_{j-1}) - r_{j+1/2}(Phi_{j+1} - Phi_j)]/dr + m^2 (dr/r_j) Phi_j = delta_{j, j0}
+ * on the nodes whose e_z edge is free (r_{-1/2} = 0; Phi = 0 on the wall,
+ * on PEC nodes and, for m >= 1, on the axis; a tridiagonal solve in FP64)
+ * and F carries the ring current as in 3-D.  The wake quadrature (both
+ * lines) ends before edge kend (0: nz).  Requires a bunch (TETE_ERR_STATE);
+ * cell planes 0 .. start_step uniform in z and the ring's node free, 0 <=
+ * start_step < nz, 0 <= kend <= nz (TETE_ERR_ARG otherwise).  The other field
+ * set and the wake read-out area serve as scratch; the step counter becomes
+ * start_step and the wake accumulators are reset.  tete_rz_set_fields,
+ * tete_rz_set_bunch and tete_rz_set_pec_cells end the open-pipe run.
+ * Synchronises the stream. */
+tete_status tete_rz_set_open_pipes(tete_rz* g, int64_t start_step, int32_t kend);
+
 /* Number of completed steps (host counter). */
 tete_status tete_rz_steps_done(tete_rz* g, int64_t* n);
 

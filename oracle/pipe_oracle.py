@@ -188,3 +188,100 @@ def run(g: O.Geom, m: dict, bunch: O.Bunch, n0: int, nsteps: int, want_energy: b
     out["field"] = f
     out["phi"] = phi
     return out
+
+
+# ---------------------------------------------------------------------------
+# The rotationally symmetric scheme (24) at azimuthal mode m (Sec. 4.3), on the
+# r-z grid of ``oracle/rz_oracle``.  The same construction: with e_z = h_z = 0
+# the pairs (e_r, h_phi) and (e_phi, h_r) see the one-dimensional leapfrog at
+# Courant number one along z (alpha^2 mu_phi kappa_r = alpha^2 kappa_phi mu_r =
+# 1/4 at dtau = dz), S8 keeps h_z = 0 when P_r e_phi = m e_r, which the radial
+# gradient form e_r = -P_r Phi, e_phi = -m Phi gives, and S3 keeps e_z = 0 when
+# P_r^* h_phi - m h_r at step n equals the ring current.  With h tied to e as
+# in 3-D (h = -2 alpha mu e for the pair (e_r, h_phi), +2 alpha mu_r e for
+# (e_phi, h_r)), the last condition is the radial problem
+#   (L_m Phi)(j) = [r_{j-1/2} (Phi_j - Phi_{j-1}) - r_{j+1/2} (Phi_{j+1} - Phi_j)] / dr
+#                  + m^2 (dr / r_j) Phi_j = w_m delta_{j, j0}
+# on the nodes whose e_z edge has kappa_z > 0 (r_{-1/2} = 0; on the axis for
+# m = 0 the disk facet gives the row (Phi_0 - Phi_1) / 2), Phi = 0 on the
+# others (the wall, the axis for m >= 1, PEC nodes), w_m the harmonic weight
+# of the ring charge.  Then, with F the profile of the 3-D case:
+#   e_phi = -m Phi_j F(p),  e_r = -(Phi_{j+1} - Phi_j) F(p),
+#   h_phi = (r_{j+1/2} / dr)(Phi_{j+1} - Phi_j) F(p+1),  h_r = -(dr / r_j) m Phi_j F(p+1).
+# ---------------------------------------------------------------------------
+def rz_uniform_entrance(m: dict, kst: int) -> bool:
+    """True if the r-z materials repeat along z over cell planes 0 .. kst-1
+    (e_phi, e_r from plane 1, e_z and the h from plane 0)."""
+    for key, lo in (("ephi", 1), ("er", 1), ("ez", 0), ("hphi", 0), ("hr", 0), ("hz", 1)):
+        a = m[key][:, lo:kst]
+        if not np.array_equal(a, np.repeat(a[:, :1], a.shape[1], axis=1)):
+            return False
+    return True
+
+
+def rz_potential(g, m: dict, j0: int) -> np.ndarray:
+    """Phi of the radial problem above by a sparse direct solve of L_m written
+    out row by row."""
+    import scipy.sparse as sp
+    from oracle import rz_oracle as Z
+    nr = g.nr
+    free = m["ez"][:, 0] > 0.0
+    if not free[j0]:
+        raise ValueError("the ring lies on a node without e_z")
+    ids = -np.ones(nr + 1, dtype=np.int64)
+    ids[free] = np.arange(int(free.sum()))
+    rows, cols, vals = [], [], []
+    for j in range(nr + 1):
+        if not free[j]:
+            continue
+        rm = (j - 0.5) * g.dr if j > 0 else 0.0
+        rp = (j + 0.5) * g.dr
+        diag = (rm + rp) / g.dr + (g.m * g.m * g.dr / (j * g.dr) if j > 0 else 0.0)
+        rows.append(ids[j]); cols.append(ids[j]); vals.append(diag)
+        for jj, w in ((j - 1, rm / g.dr), (j + 1, rp / g.dr)):
+            if 0 <= jj <= nr and free[jj] and w != 0.0:
+                rows.append(ids[j]); cols.append(ids[jj]); vals.append(-w)
+    n = int(free.sum())
+    A = sp.csc_matrix((vals, (rows, cols)), shape=(n, n))
+    rhs = np.zeros(n)
+    rhs[ids[j0]] = Z.mode_weight(g.m)
+    phi = np.zeros(nr + 1)
+    phi[free] = spl.spsolve(A, rhs)
+    return phi
+
+
+def rz_self_field(g, m: dict, phi: np.ndarray, lam: np.ndarray, M: int, n0: int) -> dict:
+    """The r-z state y^{n0} above, with e on PEC edges and entries outside
+    their range zeroed."""
+    from oracle import rz_oracle as Z
+    f = Z.zeros(g)
+    k = np.arange(g.nz + 1)
+    Fe = profile(lam, M, g.cdt, k - n0)
+    Fh = profile(lam, M, g.cdt, k + 1 - n0)
+    j = np.arange(g.nr + 1, dtype=float)
+    Ep = -g.m * phi                                   # e_phi shape at node j
+    Er = np.zeros(g.nr + 1)
+    Er[:-1] = -(phi[1:] - phi[:-1])                   # e_r shape at j + 1/2
+    f["ephi"] = Ep[:, None] * Fe[None, :]
+    f["er"] = Er[:, None] * Fe[None, :]
+    f["hphi"] = (((j + 0.5) * g.dr / g.dr) * (-Er))[:, None] * Fh[None, :]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        hr = np.where(j > 0, (g.dr / (j * g.dr)) * Ep, 0.0)
+    f["hr"] = hr[:, None] * Fh[None, :]
+    Z.apply_pec(g, m, f)
+    return f
+
+
+def rz_run(g, m: dict, bunch, n0: int, nsteps: int, want_energy: bool = False) -> dict:
+    """Open-pipe r-z wake run: the self-field at step n0, then nsteps steps of
+    ``rz_oracle.run`` with the quadrature ending at bunch.kend."""
+    from oracle import rz_oracle as Z
+    if not rz_uniform_entrance(m, n0 + 1):
+        raise ValueError("cell planes 0 .. n0 are not a uniform pipe")
+    phi = rz_potential(g, m, bunch.j0)
+    lam = Z.bunch_cells(bunch.Q, bunch.sigma, g.dz, bunch.M)
+    f = rz_self_field(g, m, phi, lam, bunch.M, n0)
+    out = Z.run(g, m, f, nsteps, n0=n0, bunch=bunch, want_energy=want_energy)
+    out["field"] = f
+    out["phi"] = phi
+    return out

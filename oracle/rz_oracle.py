@@ -278,6 +278,7 @@ class RZBunch:
     jw: int
     jmin: int
     nw: int
+    kend: int = 0          # wake quadrature over edges k < kend (0: all edges)
 
 
 def run(g: RZGeom, m: dict, f: dict, nsteps: int, n0: int = 0, bunch: RZBunch | None = None,
@@ -286,7 +287,8 @@ def run(g: RZGeom, m: dict, f: dict, nsteps: int, n0: int = 0, bunch: RZBunch | 
     k - n + M crosses the dual facet of e_z edge (j0, k) in step n (current
     = charge / dtau, times the mode weight), and each wake line L in (jw, jw+1)
     accumulates acc[L - jw, j - jmin] += -1/2 (e_z^{n-1/2} + e_z^{n+1/2})(L, k)
-    with n = k + M + j, the quadrature of the 3-D wake.  W_par^m(s_j) = acc / Q."""
+    with n = k + M + j, the quadrature of the 3-D wake, over edges k < kend
+    (all edges for kend 0).  W_par^m(s_j) = acc / Q."""
     out = {"energy": [], "acc": acc}
     if bunch is not None:
         lam = bunch_cells(bunch.Q, bunch.sigma, g.dz, bunch.M)
@@ -309,7 +311,8 @@ def run(g: RZGeom, m: dict, f: dict, nsteps: int, n0: int = 0, bunch: RZBunch | 
             ezo = f["ez"][list(lines), :].copy()
         step(g, m, f, jz)
         if bunch is not None:
-            for k in range(g.nz):
+            kend = bunch.kend if 0 < bunch.kend < g.nz else g.nz
+            for k in range(kend):
                 jj = n - k - bunch.M
                 if bunch.jmin <= jj < bunch.jmin + bunch.nw:
                     for li, L in enumerate(lines):

@@ -60,6 +60,7 @@ struct RZArgs {
     int nzt, nzb, rows;     // z-strips, workgroups along z, rows per chunk
     int nrc, order;         // r-chunks, workgroup order (1: chunks fastest, 2: strips fastest)
     int src, j0, M, jw, jmin, nw;
+    int kend;               // the wake quadrature takes edges k < kend
     int64_t n;              // step being taken
     const double* lamw;     // 2M+1: harmonic weight * cell charge / dtau
     double* acc;            // [step parity][line jw, jw+1][nw] wake accumulators
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(kLanes * kWaves) void k_rz(RZArgs<R> A)
                     ezh1 -= (R)((double)cz1 * A.lamw[mm + A.M]);
                 }
             }
-            if (A.src && (j1 == A.jw || j1 == A.jw + 1) && j1 >= ra && j1 < rb && own_k && k < A.nz) {
+            if (A.src && (j1 == A.jw || j1 == A.jw + 1) && j1 >= ra && j1 < rb && own_k && k < A.kend) {
                 const int64_t js = n - k - A.M;                  // wake sample of edge k
                 // even and odd steps accumulate into separate arrays: in a two-step
                 // launch lane k's step n and lane k+1's step n+1 meet at one sample
@@ -421,6 +422,87 @@ __global__ void k_rz_wakes(const double* acc, int nw, double scale, double dr, d
 
 size_t up(size_t v) { return (v + 255) / 256 * 256; }
 
+// Open pipes (the infinite pipes of the structure of Sec. 5) on the r-z grid:
+// the ring bunch's own field in a uniform entrance pipe as the starting state.
+// With e_z = h_z = 0 the pairs (e_r, h_phi) and (e_phi, h_r) see the 1-D
+// leapfrog at Courant number one along z; S8 keeps h_z = 0 for the radial
+// gradient form e_r = -P_r Phi, e_phi = -m Phi; S3 keeps e_z = 0 when the
+// radial problem
+//   [r_{j-1/2}(Phi_j - Phi_{j-1}) - r_{j+1/2}(Phi_{j+1} - Phi_j)] / dr + m^2 (dr / r_j) Phi_j = delta_{j, j0}
+// holds on the nodes whose e_z edge is free (r_{-1/2} = 0), Phi = 0 on the
+// others, and the profile F carries the ring current (the weighted cell
+// charges over dtau).  Then e_phi = -m Phi F(p), e_r = -(Phi_{j+1} - Phi_j) F(p),
+// h_phi = (r_{j+1/2}/dr)(Phi_{j+1} - Phi_j) F(p+1), h_r = (dr/r_j) e_phi-shape F(p+1).
+
+// bad = 1 unless every node line repeats, over planes 0 .. kst-1, the e_z bit
+// of plane 0 and the e_phi, e_r bits of plane 1 (plane 0 of those is the wall)
+__global__ void k_rz_pipe_check(const uint8_t* code, int nr, int nz, int kst, int* bad)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > nr) return;
+    const uint8_t* c = code + (int64_t)j * (nz + 1);
+    const int z0 = c[0] & C_EZ, t1 = c[1] & (C_EPHI | C_ER);
+    int diff = 0;
+    for (int k = 1; k < kst; ++k) diff |= ((c[k] & C_EZ) != z0) | ((c[k] & (C_EPHI | C_ER)) != t1);
+    if (diff) *bad = 1;
+}
+
+// Phi by the Thomas algorithm (one thread; the system is tridiagonal and
+// diagonally dominant).  A node is free when kappa_z > 0 and its plane-0 e_z
+// edge is not PEC; other rows are Phi = 0.  cw, dw: nr + 1 doubles of work.
+__global__ void k_rz_pipe_solve(const uint8_t* code, const Raw* raw, int nr, int nz, double dr, int m, int j0,
+                                double* phi, double* cw, double* dw)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    auto free_node = [&](int j) { return raw[j].kz > 0.0 && !(code[(int64_t)j * (nz + 1)] & C_EZ); };
+    double cp = 0.0, dp = 0.0;
+    for (int j = 0; j <= nr; ++j) {
+        double a = 0.0, b = 1.0, c = 0.0, d = 0.0;
+        if (free_node(j)) {
+            const double rm = j > 0 ? (j - 0.5) * dr : 0.0, rp = (j + 0.5) * dr;
+            b = (rm + rp) / dr + (j > 0 ? (double)m * m * dr / (j * dr) : 0.0);
+            if (j > 0 && rm != 0.0 && free_node(j - 1)) a = -(rm / dr);
+            if (j < nr && free_node(j + 1)) c = -(rp / dr);
+            d = j == j0 ? 1.0 : 0.0;
+        }
+        const double den = b - a * cp;
+        cw[j] = c / den;
+        dw[j] = (d - a * dp) / den;
+        cp = cw[j];
+        dp = dw[j];
+    }
+    phi[nr] = dw[nr];
+    for (int j = nr - 1; j >= 0; --j) phi[j] = dw[j] - cw[j] * phi[j + 1];
+}
+
+__device__ __forceinline__ double rz_prof(const double* F, int lo, int64_t p)
+{
+    if (p > 0) return 0.0;
+    if (p >= lo) return F[p - lo];
+    return ((lo - p) & 1) ? -F[0] : F[0];
+}
+
+// The state y^{n0} of the field above into the six arrays f (sanitized after)
+template <typename R>
+__global__ void k_rz_pipe_field(R* const* f, const double* phi, const double* F, int lo, int64_t n0, int nr, int nz,
+                                double dr, int m)
+{
+    const int64_t np = (int64_t)(nr + 1) * (nz + 1);
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < np;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(idx / (nz + 1)), k = (int)(idx % (nz + 1));
+        const double fe = rz_prof(F, lo, (int64_t)k - n0), fh = rz_prof(F, lo, (int64_t)k + 1 - n0);
+        const double Ep = -(double)m * phi[j];
+        const double Er = j < nr ? -(phi[j + 1] - phi[j]) : 0.0;
+        f[0][idx] = (R)(Ep * fe);
+        f[1][idx] = (R)(Er * fe);
+        f[2][idx] = R(0);
+        f[3][idx] = (R)((((j + 0.5) * dr / dr) * (-Er)) * fh);
+        f[4][idx] = j > 0 ? (R)(((dr / (j * dr)) * Ep) * fh) : R(0);
+        f[5][idx] = R(0);
+    }
+}
+
 struct RZLayout {
     size_t field[12], code, coef, raw, lamw, acc, partial, scal, wout, ptrs, total;
 };
@@ -483,6 +565,7 @@ struct tete_rz {
     int64_t n;
     int has_bunch;
     tete_rz_bunch b;
+    int32_t kend;        // open-pipe run: the wake quadrature ends before edge kend (0: all edges)
     int kernel, chunk_rows, prefetch;   // TETE_KERNEL_AUTO / FUSED (one step) / FUSED2 (two)
     int order;                          // workgroup order (0: default)
     int timing;
@@ -589,6 +672,7 @@ hipError_t rz_launch(tete_rz* g, int ns, hipStream_t s)
     A.jw = g->b.jw;
     A.jmin = g->b.jmin;
     A.nw = g->b.nw;
+    A.kend = g->kend > 0 ? g->kend : g->d.nz;
     A.n = g->n;
     A.lamw = g->lamw;
     A.acc = g->acc;
@@ -728,6 +812,7 @@ tete_status tete_rz_set_pec_cells(tete_rz* g, const uint8_t* cells)
     k_rz_code<<<512, 256, 0, g->stream>>>(cells, g->code, g->d.nr, g->d.nz);
     RZCHK(hipGetLastError());
     RZCHK(rz_sanitize_any(g, g->cur));
+    g->kend = 0;
     return TETE_OK;
 }
 
@@ -754,6 +839,7 @@ tete_status tete_rz_set_fields(tete_rz* g, const void* const f[6], int32_t dtype
     RZCHK(rz_sanitize_any(g, g->cur));
     RZCHK(hipMemsetAsync(g->acc, 0, sizeof(double) * 4 * TETE_MAX_WAKE, g->stream));
     g->n = 0;
+    g->kend = 0;
     return TETE_OK;
 }
 
@@ -810,6 +896,7 @@ tete_status tete_rz_set_bunch(tete_rz* g, const tete_rz_bunch* b)
     RZCHK(hipStreamSynchronize(g->stream));
     g->b = *b;
     g->has_bunch = 1;
+    g->kend = 0;
     return TETE_OK;
 }
 
@@ -833,6 +920,55 @@ tete_status tete_rz_step(tete_rz* g, int64_t nsteps)
         g->n += ns;
         s += ns;
     }
+    return TETE_OK;
+}
+
+tete_status tete_rz_set_open_pipes(tete_rz* g, int64_t start_step, int32_t kend)
+{
+    if (!g) return TETE_ERR_ARG;
+    if (!g->has_bunch) return TETE_ERR_STATE;
+    const int nr = g->d.nr, nz = g->d.nz;
+    if (start_step < 0 || start_step >= nz || kend < 0 || kend > nz) return TETE_ERR_ARG;
+    Guard dg(g->device);
+    if (!dg.ok) return TETE_ERR_DEVICE;
+    int* bad = (int*)(g->scal + 6);
+    RZCHK(launch_zero_bytes(bad, sizeof(int), g->stream));
+    k_rz_pipe_check<<<(nr + 256) / 256, 256, 0, g->stream>>>(g->code, nr, nz, (int)start_step + 1, bad);
+    RZCHK(hipGetLastError());
+    int hbad = 0;
+    uint8_t c0 = 0;
+    Raw r0;
+    const int j0 = g->b.j0;
+    RZCHK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, g->stream));
+    RZCHK(hipMemcpyAsync(&c0, g->code + (int64_t)j0 * (nz + 1), 1, hipMemcpyDeviceToHost, g->stream));
+    RZCHK(hipMemcpyAsync(&r0, g->raw + j0, sizeof(Raw), hipMemcpyDeviceToHost, g->stream));
+    RZCHK(hipStreamSynchronize(g->stream));
+    if (hbad || (c0 & C_EZ) || !(r0.kz > 0.0)) return TETE_ERR_ARG;
+    // scratch: three arrays of the other field set (each holds nr + 1 doubles)
+    const int o = 1 - g->cur;
+    double* phi = (double*)g->f[o][0];
+    double* cw = (double*)g->f[o][1];
+    double* dw = (double*)g->f[o][2];
+    k_rz_pipe_solve<<<1, 64, 0, g->stream>>>(g->code, g->raw, nr, nz, g->d.dr, g->d.mode, j0, phi, cw, dw);
+    RZCHK(hipGetLastError());
+    // the profile of the ring current (weighted cell charges over dtau) in the
+    // wake read-out area
+    const int M = g->b.half_cells;
+    RZCHK(launch_pipe_profile(g->wout, g->lamw, M, 1.0, g->stream));
+    if (g->fp32)
+        k_rz_pipe_field<float><<<512, 256, 0, g->stream>>>((float* const*)(g->dptr + 6 * g->cur), phi, g->wout,
+                                                           -2 * M - 1, start_step, nr, nz, g->d.dr, g->d.mode);
+    else
+        k_rz_pipe_field<double><<<512, 256, 0, g->stream>>>((double* const*)(g->dptr + 6 * g->cur), phi, g->wout,
+                                                            -2 * M - 1, start_step, nr, nz, g->d.dr, g->d.mode);
+    RZCHK(hipGetLastError());
+    RZCHK(rz_sanitize_any(g, g->cur));
+    const size_t bytes = (size_t)(g->fp32 ? 4 : 8) * (size_t)(nr + 1) * (size_t)(nz + 1);
+    for (int c = 0; c < 6; ++c) RZCHK(launch_zero_bytes(g->f[o][c], bytes, g->stream));
+    RZCHK(launch_zero_bytes(g->acc, sizeof(double) * 4 * TETE_MAX_WAKE, g->stream));
+    RZCHK(hipStreamSynchronize(g->stream));
+    g->n = start_step;
+    g->kend = kend;
     return TETE_OK;
 }
 

@@ -138,6 +138,7 @@ def load(path: str = LIB_PATH):
         "tete_rz_set_bunch": (st, [vp, C.POINTER(RZBunch)]),
         "tete_rz_step": (st, [vp, C.c_int64]),
         "tete_rz_steps_done": (st, [vp, C.POINTER(C.c_int64)]),
+        "tete_rz_set_open_pipes": (st, [vp, C.c_int64, C.c_int32]),
         "tete_rz_wake": (st, [vp, vp, vp, C.c_int32]),
         "tete_rz_energy": (st, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "tete_rz_set_tuning": (st, [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
@@ -559,6 +560,12 @@ class RZGrid:
 
     def step(self, n: int):
         _chk("tete_rz_step", load().tete_rz_step(self.h, int(n)))
+
+    def set_open_pipes(self, start_step: int, kend: int = 0) -> None:
+        """Open entrance and exit pipes (tete_rz_set_open_pipes): the ring
+        bunch's field in the uniform entrance pipe as the state of step
+        start_step, and the wake quadrature ending before edge kend."""
+        _chk("tete_rz_set_open_pipes", load().tete_rz_set_open_pipes(self.h, int(start_step), int(kend)))
 
     def steps_done(self) -> int:
         v = C.c_int64()

@@ -99,3 +99,48 @@ def test_single_wake_against_oracle(golden, precision):
     print("fields: bunch line %.3e  samples %.3e" % (dl, dv), flush=True)
     assert dl <= ftol and dv <= ftol
     G.close()
+
+
+OPEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                    "single_wake_open_pipes_step_collimator_128x128x1024.json")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_single_wake_between_open_pipes_against_oracle(precision):
+    """The same workload between open pipes (tete_set_open_pipes), against the
+    oracle's run of ``make_single_wake_open_golden.py``: the device solves for
+    the cross-section's potential itself.  W within the delta norm 1e-12
+    (FP64) / 1e-5 (FP32), the energies every 128 steps within 1e-12 / 1e-5 of
+    the largest, and e_z on the bunch line within 1e-12 / 1e-4 of the bunch's
+    own field (as above)."""
+    with open(OPEN) as fh:
+        gold = json.load(fh)
+    case = inputs.single_wake_case()
+    assert [case.nx, case.ny, case.nz] == gold["grid"] and (case.jmin, case.nw, case.M) == (
+        gold["jmin"], gold["nw"], gold["M"])
+    print("single wake, open pipes", precision, flush=True)
+    G = P.gpu_grid(case, precision)
+    G.set_bunch(case.Q, case.sigma, case.i0, case.j0, case.M, case.jmin, case.nw)
+    G.set_open_pipes(gold["start_step"], gold["kend"])
+    n = gold["start_step"]
+    energies = {n: G.energy()[0]}
+    end = n + gold["steps"]
+    while n < end:
+        k = min(128, end - n)
+        G.step(k)
+        n += k
+        energies[n] = G.energy()[0]
+    assert sorted(energies) == gold["energy_steps"]
+    W = G.wake()
+    delta = P.delta_norm(W, np.array(gold["W_V_per_C"]))
+    e = np.array([energies[s] for s in gold["energy_steps"]])
+    e_ref = np.array(gold["energy"])
+    de = float(np.max(np.abs(e - e_ref)) / np.max(np.abs(e_ref)))
+    f = G.get_fields(dtype=precision, numpy=False)
+    line = f["ez"][case.i0, case.j0, :case.nz].double().cpu().numpy()
+    dl = float(np.max(np.abs(line - np.array(gold["ez_bunch_line"]))) / _self_field_max(case))
+    print("delta W %.3e  energy %.3e  bunch line %.3e" % (delta, de, dl), flush=True)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert delta <= tol and de <= tol
+    assert dl <= (1e-12 if precision == "fp64" else 1e-4)
+    G.close()

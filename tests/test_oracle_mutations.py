@@ -323,6 +323,17 @@ PI_MUTANTS = {
     "pipe_cell_offset": ([("cur = lam[q + 2 * M] / dtau if q >= -2 * M else 0.0",
                            "cur = lam[q + 2 * M - 1] / dtau if q >= -2 * M + 1 else 0.0")],
                          [lambda p: TPI.test_self_field_node_charges_are_the_bunch(p)]),
+    # r-z: the azimuthal term of the radial problem left out
+    "rz_pipe_no_m2": ([("diag = (rm + rp) / g.dr + (g.m * g.m * g.dr / (j * g.dr) if j > 0 else 0.0)",
+                        "diag = (rm + rp) / g.dr")],
+                      [lambda p: TPI.test_rz_self_field_moves_one_cell_per_step(p, 1, 4)]),
+    # r-z: h_r with the wrong sign
+    "rz_pipe_hr_sign": ([("hr = np.where(j > 0, (g.dr / (j * g.dr)) * Ep, 0.0)",
+                          "hr = np.where(j > 0, -(g.dr / (j * g.dr)) * Ep, 0.0)")],
+                        [lambda p: TPI.test_rz_self_field_moves_one_cell_per_step(p, 1, 4)]),
+    # r-z: h_phi tied to e_r at the node radius instead of r_{j+1/2}
+    "rz_pipe_hphi_radius": ([("((j + 0.5) * g.dr / g.dr)", "((j + 0.0) * g.dr / g.dr)")],
+                            [lambda p: TPI.test_rz_self_field_moves_one_cell_per_step(p, 0, 0)]),
 }
 
 

@@ -192,3 +192,96 @@ def test_uniformity_and_node_checks(po):
     g2, cells2, m2 = _pipe_grid(10, 14, 60)
     with pytest.raises(ValueError):
         po.potential(g2, po.pec_nodes(m2), 1, 7)
+
+
+# ---- the rotationally symmetric scheme (24)
+from oracle import rz_oracle as Z   # noqa: E402
+
+
+def _rz_pipe(mode, nr=20, nz=90, radius=15, collimator=None):
+    dr = 1.2 * DZ if mode == 0 else DZ          # m = 0 is stable for dtau <= 0.9089 dr
+    g = Z.RZGeom(nr, nz, dr, DZ, DZ, mode)
+    cells = np.zeros((nr, nz), bool)
+    cells[radius:, :] = True
+    if collimator is not None:
+        k0, k1, r_in = collimator
+        cells[r_in:, k0:k1] = True
+    return g, Z.materials(g, cells)
+
+
+@pytest.mark.parametrize("mode,j0", [(0, 0), (1, 4), (2, 6)])
+def test_rz_self_field_moves_one_cell_per_step(po, mode, j0):
+    """r-z pipe of radius 15 dr, a ring bunch at mode m: after 30 steps the
+    fields ahead of the entrance wall's front equal the state built for the
+    later step, e_z and h_z stay 0 to rounding, the energy of (24) is
+    constant."""
+    g, m = _rz_pipe(mode)
+    M, n0, K = 15, 40, 30
+    b = Z.RZBunch(1e-9, 2.5 * DZ, j0, M, 5, -M, 20)
+    out = po.rz_run(g, m, b, n0, K, want_energy=True)
+    f = out["field"]
+    lam = Z.bunch_cells(b.Q, b.sigma, DZ, M)
+    ref = po.rz_self_field(g, m, out["phi"], lam, M, n0 + K)
+    sc = max(np.abs(ref[k]).max() for k in Z.KEYS)
+    front = K + 2
+    for k in Z.KEYS:
+        assert np.abs(f[k][:, front:] - ref[k][:, front:]).max() <= 1e-13 * sc, k
+    assert np.abs(f["ez"][:, front:]).max() <= 1e-14 * sc
+    assert np.abs(f["hz"]).max() <= 1e-14 * sc
+    e = np.array(out["energy"])
+    assert np.ptp(e) <= 1e-13 * e[0]
+
+
+@pytest.mark.parametrize("mode,j0", [(0, 0), (1, 4)])
+def test_rz_self_field_node_charges_are_the_ring(po, mode, j0):
+    """The r-z node charges of the first step: the ring's weighted cell
+    charge on its node line, nothing at the other free nodes."""
+    g, m = _rz_pipe(mode)
+    M, n0 = 10, 30
+    b = Z.RZBunch(1e-9, 2.0 * DZ, j0, M, 5, -M, 10)
+    phi = po.rz_potential(g, m, j0)
+    lam = Z.bunch_cells(b.Q, b.sigma, DZ, M)
+    fo = po.rz_self_field(g, m, phi, lam, M, n0)
+    fn = {k: v.copy() for k, v in fo.items()}
+    Z.run(g, m, fn, 1, n0=n0, bunch=b)
+    q = Z.charge(g, m, fo, fn)
+    want = np.zeros_like(q)
+    for k in range(g.nz + 1):
+        c = k - n0 - 1 + M
+        if -M <= c <= M:
+            want[j0, k] = Z.mode_weight(mode) * lam[c + M]
+    inner = np.zeros(q.shape, bool)
+    inner[:14, 3:-1] = True                      # nodes with free edges, clear of the wall's cut
+    inner &= m["ez"] > 0
+    assert np.abs(q - want)[inner].max() <= 1e-12 * b.Q
+    assert np.abs(want).max() > 0.1 * Z.mode_weight(mode) * b.Q
+
+
+def test_rz_uniform_pipe_wake_vanishes(po):
+    """Mode 1, uniform pipe: both wake lines are 1e-12 of the closed box's
+    for the samples the entrance cut cannot reach."""
+    g, m = _rz_pipe(1, nz=150)
+    M, n0 = 15, 60
+    nw = (n0 - M - 2) + M + 1
+    b = Z.RZBunch(1e-9, 2.5 * DZ, 4, M, 5, -M, nw)
+    W = po.rz_run(g, m, b, n0, 80)["acc"]
+    Wc = Z.run(g, m, Z.zeros(g), n0 + 80, bunch=Z.RZBunch(1e-9, 2.5 * DZ, 4, M, 5, -M, nw))["acc"]
+    assert np.abs(Wc).max() > 1e3 * np.abs(W).max()
+    assert np.abs(W).max() <= 1e-12 * np.abs(Wc).max()
+
+
+def test_rz_exit_truncation_is_causal(po):
+    """An iris between open pipes: a longer outgoing pipe leaves the wake
+    bitwise unchanged when the quadrature ends early enough."""
+    M, jmax = 10, 24
+    out = []
+    k0 = 45
+    kend = k0 + 14                               # 4 planes past the iris
+    for post in (4 + (M + jmax + 3) // 2, 13 + (M + jmax + 3) // 2):
+        g, m = _rz_pipe(1, nz=k0 + 10 + post, collimator=(k0, k0 + 10, 8))
+        assert g.nz - kend >= (M + jmax + 3) // 2
+        b = Z.RZBunch(1e-9, 2.0 * DZ, 4, M, 5, -M, jmax + M + 1, kend=kend)
+        steps = kend + M + jmax - (k0 - 2)
+        out.append(po.rz_run(g, m, b, k0 - 2, steps)["acc"])
+    assert np.array_equal(out[0], out[1])
+    assert np.abs(out[0]).max() > 0
