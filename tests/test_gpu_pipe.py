@@ -250,3 +250,33 @@ def test_open_pipe_rules():
     C.set_bunch(Q, 2.0 * DZ, 6, 8, M, -M, jmax + M + 1)
     C.step(g2.nz + M + jmax)
     assert np.array_equal(A.wake(), C.wake())
+
+
+def test_large_cross_section_potential():
+    """A 512 x 512 cross-section (round pipe of 200 cells radius, off-centre
+    bunch): the device's conjugate gradients converge, and e_x, e_y on the
+    bunch's planes match the oracle's direct solve within 1e-12 of the
+    largest (FP64)."""
+    nx = ny = 512
+    nz = 12
+    g = O.Geom(nx, ny, nz, 2 * DZ, 2 * DZ, DZ, DZ)
+    i = np.arange(nx)[:, None] + 0.5 - nx / 2
+    j = np.arange(ny)[None, :] + 0.5 - ny / 2
+    pec = (i * i + j * j) > 200.0 ** 2
+    cells = np.repeat(pec[:, :, None], nz, axis=2).astype(np.uint8)
+    m = O.vacuum_materials(g, cells)
+    src = (nx // 2 + 37, ny // 2 - 21)
+    M, n0 = 3, 8
+    phi = PO.potential(g, PO.pec_nodes(m), *src)
+    lam = O.bunch_cells(Q, 1.5 * DZ, DZ, M)
+    ref = PO.self_field(g, m, phi, lam, M, n0)
+    G = _grid(g, cells, "fp64")
+    G.set_bunch(Q, 1.5 * DZ, src[0], src[1], M, -M, 10)
+    it = G.set_open_pipes(n0)
+    print("512 x 512 cross-section: %d conjugate-gradient iterations" % it, flush=True)
+    assert 0 < it < 20 * (nx + ny) + 1000
+    f = G.get_fields()
+    for k in ("ex", "ey", "hx", "hy"):
+        sc = np.abs(ref[k]).max()
+        assert sc > 0
+        assert np.abs(f[k] - ref[k]).max() <= 1e-12 * sc, k
