@@ -34,7 +34,7 @@ int64_t skip_cap(Geo g) { return std::max(fused2_tile_cap(g), fused_tile_cap(g))
 
 bool make_layout(const tete_grid_desc* d, Layout* L)
 {
-    const int64_t np = padded_entries(d->nx, d->ny, d->nz);
+    const int64_t np = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
     const size_t rb = d->precision == TETE_FP32 ? 4 : 8;
     size_t o = 0;
     L->lam = o;     o = up(o + sizeof(double) * TETE_MAX_BUNCH_CELLS);
@@ -70,7 +70,7 @@ bool make_layout(const tete_grid_desc* d, Layout* L)
     }
     L->skip[0] = L->skip[1] = L->skip_act[0] = L->skip_act[1] = 0;
     if (d->flags & TETE_F_SKIP_STATIC) {   // static-tile table and active-tile list of each tiling kind
-        const Geo g = make_geo(d->nx, d->ny, d->nz);
+        Geo g = {d->nx, d->ny, d->nz, d->nz + 1, (d->ny + 1) * (d->nz + 1), (int)np};
         const int64_t cap = skip_cap(g);
         for (int kind = 0; kind < 2; ++kind) {
             L->skip[kind] = o;     o = up(o + (size_t)cap);
@@ -506,7 +506,8 @@ tete_status tete_check_desc(const tete_grid_desc* d)
 {
     if (!d) return TETE_ERR_ARG;
     if (d->nx < 2 || d->ny < 2 || d->nz < 2) return TETE_ERR_ARG;
-    if (padded_entries(d->nx, d->ny, d->nz) >= ((int64_t)1 << 31) - 1) return TETE_ERR_ARG;
+    const int64_t np = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
+    if (np >= ((int64_t)1 << 31) - 1) return TETE_ERR_ARG;
     if (!finite_pos(d->dx) || !finite_pos(d->dy) || !finite_pos(d->dz) || !finite_pos(d->cdt)) return TETE_ERR_ARG;
     if (d->precision != TETE_FP64 && d->precision != TETE_FP32) return TETE_ERR_ARG;
     if (d->flags & ~(uint32_t)(TETE_F_MATERIALS | TETE_F_YEE | TETE_F_IMPLICIT | TETE_F_SKIP_STATIC))
@@ -560,7 +561,12 @@ tete_status tete_grid_create(const tete_grid_desc* d, void* dev_ws, size_t ws_by
     if (hipGetDevice(&g->device) != hipSuccess) { free(g); return TETE_ERR_DEVICE; }
     g->ws = (char*)dev_ws;
     g->L = L;
-    g->geo = make_geo(d->nx, d->ny, d->nz);
+    g->geo.nx = d->nx;
+    g->geo.ny = d->ny;
+    g->geo.nz = d->nz;
+    g->geo.sz = d->nz + 1;
+    g->geo.sp = (d->ny + 1) * (d->nz + 1);
+    g->geo.np = (d->nx + 1) * g->geo.sp;
     g->fp32 = d->precision == TETE_FP32;
     g->yee = (d->flags & TETE_F_YEE) != 0;
     g->implicit = (d->flags & TETE_F_IMPLICIT) != 0;
@@ -783,8 +789,7 @@ tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3], const
         // Q^e >= 0 (Sec. 4.4) by the Gershgorin row sums of its three blocks,
         // before anything is imported: an unstable set leaves the grid as it was
         double bound;
-        HIPCHK(launch_mat_bound(src, dtype == TETE_FP32, caller_geo(g->geo), g->alpha, g->partial, g->scal + 4,
-                                g->stream));
+        HIPCHK(launch_mat_bound(src, dtype == TETE_FP32, g->geo, g->alpha, g->partial, g->scal + 4, g->stream));
         HIPCHK(hipMemcpyAsync(&bound, g->scal + 4, sizeof(double), hipMemcpyDeviceToHost, g->stream));
         HIPCHK(hipStreamSynchronize(g->stream));
         if (!(bound == bound)) return TETE_ERR_ARG;           // a negative or non-finite value
@@ -835,7 +840,7 @@ tete_status tete_set_material_classes(tete_grid* g, const uint8_t* cls, const do
         if (!(bound == bound)) return TETE_ERR_ARG;
         if (bound > 1.0 + 1e-12) return TETE_ERR_UNSTABLE;
     }
-    HIPCHK(launch_import_bytes(g->cls, cls, g->geo, g->stream));
+    HIPCHK(hipMemcpyAsync(g->cls, cls, (size_t)g->geo.np, hipMemcpyDeviceToDevice, g->stream));
     if (g->tune.kernel == TETE_KERNEL_FUSED) g->tune.kernel = TETE_KERNEL_AUTO;
     if (g->fp32) {
         float* dst[6];
@@ -1026,18 +1031,12 @@ tete_status tete_set_diagnostics(tete_grid* g, int32_t every)
 tete_status tete_set_probes(tete_grid* g, const int64_t* idx, int32_t np_)
 {
     if (!g || np_ < 0 || np_ > TETE_MAX_PROBES || (np_ > 0 && !idx)) return TETE_ERR_ARG;
-    // the caller's linear indices (rows of nz + 1) -> the grid's
-    const int64_t sz = g->d.nz + 1, sp = (int64_t)(g->d.ny + 1) * sz;
-    int64_t in[TETE_MAX_PROBES];
-    for (int p = 0; p < np_; ++p) {
-        if (idx[p] < 0 || idx[p] >= (g->d.nx + 1) * sp) return TETE_ERR_ARG;
-        const int64_t i = idx[p] / sp, j = (idx[p] % sp) / sz, k = idx[p] % sz;
-        in[p] = k + j * g->geo.sz + i * (int64_t)g->geo.sp;
-    }
+    for (int p = 0; p < np_; ++p)
+        if (idx[p] < 0 || idx[p] >= g->geo.np) return TETE_ERR_ARG;
     DeviceGuard dg(g->device);
     if (!dg.ok) return TETE_ERR_DEVICE;
     if (np_ > 0) {
-        HIPCHK(hipMemcpyAsync(g->pidx, in, sizeof(int64_t) * np_, hipMemcpyHostToDevice, g->stream));
+        HIPCHK(hipMemcpyAsync(g->pidx, idx, sizeof(int64_t) * np_, hipMemcpyHostToDevice, g->stream));
         HIPCHK(hipStreamSynchronize(g->stream));
     }
     g->nprobe = np_;

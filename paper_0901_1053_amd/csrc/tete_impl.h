@@ -9,47 +9,14 @@
 
 namespace tete {
 
-// Grid geometry as the kernels see it.  Arrays are (nx+1)(ny+1) rows of sz
-// entries, z fastest.  The row length sz is nz+1 rounded up to a multiple of
-// 32 entries, so that every row starts on a 128-byte line; the entries past
-// k = nz belong to no component and hold 0.  sp = (ny+1) sz is the plane
-// length.  Arrays the caller passes in or gets back have rows of nz+1.
+// Grid geometry as the kernels see it.  Arrays are (nx+1)(ny+1)(nz+1), z
+// fastest; sz = nz+1 is the row length, sp = (ny+1)(nz+1) the plane length.
 struct Geo {
     int nx, ny, nz;
-    int sz;      // row length: nz + 1 rounded up to a multiple of 32
-    int sp;      // (ny + 1) * sz
+    int sz;      // nz + 1
+    int sp;      // (ny + 1) * (nz + 1)
     int np;      // (nx + 1) * sp
 };
-
-enum { ROW_ALIGN = 32 };
-inline int row_pitch(int nz) { return (nz + 1 + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN; }
-// entries of a grid's arrays with padded rows
-inline int64_t padded_entries(int nx, int ny, int nz) { return (int64_t)(nx + 1) * (ny + 1) * row_pitch(nz); }
-inline Geo make_geo(int nx, int ny, int nz)
-{
-    Geo g;
-    g.nx = nx;
-    g.ny = ny;
-    g.nz = nz;
-    g.sz = row_pitch(nz);
-    g.sp = (ny + 1) * g.sz;
-    g.np = (int)((int64_t)(nx + 1) * g.sp);
-    return g;
-}
-// the same grid with the caller's rows of nz + 1 entries
-inline Geo caller_geo(const Geo& g)
-{
-    Geo c = g;
-    c.sz = g.nz + 1;
-    c.sp = (g.ny + 1) * c.sz;
-    c.np = (int)((int64_t)(g.nx + 1) * c.sp);
-    return c;
-}
-// linear index of entry (i, j, k) in a caller's array (rows of nz + 1)
-__host__ __device__ inline int64_t caller_index(const Geo& g, int i, int j, int k)
-{
-    return (int64_t)k + (int64_t)(g.nz + 1) * ((int64_t)j + (int64_t)(g.ny + 1) * i);
-}
 
 // Six field components of one time level.
 template <typename R>
@@ -277,14 +244,10 @@ template <typename R>
 hipError_t launch_class_table(R* ctab, const double* table, R alpha, hipStream_t s);
 hipError_t launch_mat_bound_cls(const uint8_t* code, const uint8_t* cls, const double* table, int ncls, Geo g,
                                 double alpha, double* partial, double* out, hipStream_t s);
-// class bytes in the caller's layout (cls of launch_mat_bound_cls too) ->
-// the grid's rows, padding entries class 0
-hipError_t launch_import_bytes(uint8_t* dst, const uint8_t* src, Geo g, hipStream_t s);
 // Largest Gershgorin row sum of the three blocks of Q^e (Sec. 4.4) for
-// general materials src[6] (kappa_x,y,z, mu_x,y,z; FP32 if src_fp32, laid out
-// as g says: the caller's arrays take caller_geo) -> out[0]: Q^e >= 0 if it
-// is at most 1; NaN if a value in a component's range is negative or not
-// finite.  Uses partial[RED_BLOCKS].
+// general materials src[6] (kappa_x,y,z, mu_x,y,z; FP32 if src_fp32) ->
+// out[0]: Q^e >= 0 if it is at most 1; NaN if a value in a component's range
+// is negative or not finite.  Uses partial[RED_BLOCKS].
 hipError_t launch_mat_bound(const void* const src[6], int src_fp32, Geo g, double alpha, double* partial,
                             double* out, hipStream_t s);
 // Streaming ceiling of the step's access pattern: out_c = in_c for six arrays

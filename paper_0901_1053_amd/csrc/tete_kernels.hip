@@ -47,7 +47,6 @@ __device__ __forceinline__ bool hz_ok(const Geo& g, int i, int j, int) { return 
 
 __device__ __forceinline__ bool comp_ok(int c, const Geo& g, int i, int j, int k)
 {
-    if (k > g.nz) return false;   // row padding
     switch (c) {
     case 0: return ex_ok(g, i, j, k);
     case 1: return ey_ok(g, i, j, k);
@@ -147,8 +146,6 @@ __device__ __forceinline__ bool e_pec(const Mat<R>& M, int c, int id)
     return kap(M, c, id) == R(0);
 }
 
-// The caller's arrays have rows of nz + 1 entries; the padding entries of
-// the grid's rows are written 0.
 template <typename R>
 __global__ void k_import(Fields<R> dst, const void* s0, const void* s1, const void* s2, const void* s3,
                          const void* s4, const void* s5, int src_fp32, Mat<R> M, Geo g)
@@ -157,14 +154,12 @@ __global__ void k_import(Fields<R> dst, const void* s0, const void* s1, const vo
     if (idx >= g.np) return;
     int i, j, k;
     decomp(idx, g, i, j, k);
-    const int64_t ci = k <= g.nz ? caller_index(g, i, j, k) : 0;
     const void* src[6] = {s0, s1, s2, s3, s4, s5};
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-        const bool keep = comp_ok(c, g, i, j, k) && (c >= 3 || !e_pec(M, c, idx));
-        R v = R(0);
-        if (keep) v = src_fp32 ? (R)((const float*)src[c])[ci] : (R)((const double*)src[c])[ci];
-        dst.c[c][idx] = v;
+        R v = src_fp32 ? (R)((const float*)src[c])[idx] : (R)((const double*)src[c])[idx];
+        bool keep = comp_ok(c, g, i, j, k) && (c >= 3 || !e_pec(M, c, idx));
+        dst.c[c][idx] = keep ? v : R(0);
     }
 }
 
@@ -174,17 +169,13 @@ __global__ void k_export(void* d0, void* d1, void* d2, void* d3, void* d4, void*
 {
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= g.np) return;
-    int i, j, k;
-    decomp(idx, g, i, j, k);
-    if (k > g.nz) return;
-    const int64_t ci = caller_index(g, i, j, k);
     void* dst[6] = {d0, d1, d2, d3, d4, d5};
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
         if (dst_fp32)
-            ((float*)dst[c])[ci] = (float)src.c[c][idx];
+            ((float*)dst[c])[idx] = (float)src.c[c][idx];
         else
-            ((double*)dst[c])[ci] = (double)src.c[c][idx];
+            ((double*)dst[c])[idx] = (double)src.c[c][idx];
     }
 }
 
@@ -197,25 +188,13 @@ __global__ void k_import_mat(R* d0, R* d1, R* d2, R* d3, R* d4, R* d5, const voi
     if (idx >= g.np) return;
     int i, j, k;
     decomp(idx, g, i, j, k);
-    const int64_t ci = k <= g.nz ? caller_index(g, i, j, k) : 0;
     R* dst[6] = {d0, d1, d2, d3, d4, d5};
     const void* src[6] = {s0, s1, s2, s3, s4, s5};
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-        R v = R(0);
-        if (comp_ok(c, g, i, j, k)) v = src_fp32 ? (R)((const float*)src[c])[ci] : (R)((const double*)src[c])[ci];
-        dst[c][idx] = v;
+        R v = src_fp32 ? (R)((const float*)src[c])[idx] : (R)((const double*)src[c])[idx];
+        dst[c][idx] = comp_ok(c, g, i, j, k) ? v : R(0);
     }
-}
-
-// Class bytes from the caller's layout; the padding entries take class 0.
-__global__ void k_import_bytes(uint8_t* dst, const uint8_t* src, Geo g)
-{
-    int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= g.np) return;
-    int i, j, k;
-    decomp(idx, g, i, j, k);
-    dst[idx] = k <= g.nz ? src[caller_index(g, i, j, k)] : (uint8_t)0;
 }
 
 template <typename R>
@@ -608,7 +587,6 @@ struct MatSrc {
 
 // Materials by class: the table's values of the entry's class, kappa zero
 // where the PEC code marks the edge (the table itself is checked on the host).
-// The class bytes are the caller's (rows of nz + 1), the codes the grid's.
 struct ClsSrc {
     const uint8_t* code;
     const uint8_t* cls;
@@ -619,12 +597,9 @@ struct ClsSrc {
         if (!in_nodes(g, i, j, k) || !comp_ok(comp, g, i, j, k)) return 0.0;
         const int id = lin(g, i, j, k);
         if (comp < 3 && ((code[id] >> comp) & 1u)) return 0.0;
-        return tab[6 * (int)cls[caller_index(g, i, j, k)] + comp];
+        return tab[6 * (int)cls[id] + comp];
     }
-    __device__ bool bad(const Geo& g, int, int i, int j, int k) const
-    {
-        return k <= g.nz && (int)cls[caller_index(g, i, j, k)] >= ncls;
-    }
+    __device__ bool bad(const Geo&, int idx, int, int, int) const { return (int)cls[idx] >= ncls; }
 };
 
 template <typename SRC>
@@ -938,12 +913,6 @@ hipError_t launch_import_materials(R* const dst[6], const void* const src[6], in
 {
     k_import_mat<R><<<nblocks(g.np, TB), TB, 0, s>>>(dst[0], dst[1], dst[2], dst[3], dst[4], dst[5], src[0], src[1],
                                                      src[2], src[3], src[4], src[5], src_fp32, g);
-    return hipGetLastError();
-}
-
-hipError_t launch_import_bytes(uint8_t* dst, const uint8_t* src, Geo g, hipStream_t s)
-{
-    k_import_bytes<<<nblocks(g.np, TB), TB, 0, s>>>(dst, src, g);
     return hipGetLastError();
 }
 

@@ -78,17 +78,10 @@ def test_yee_stability_validation(dx, dy, dz, cdt, want):
     assert tete.check_desc(tete.make_desc(24, 24, 48, dx, dy, dz, cdt, yee=True)) == want
 
 
-def _padded(nx, ny, nz):
-    """Entries of a grid array: rows of nz + 1 entries rounded up to a
-    multiple of 32 (a 128-byte line in FP32)."""
-    return (nx + 1) * (ny + 1) * (-(-(nz + 1) // 32) * 32)
-
-
 def test_workspace_bytes():
     d64 = tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp64")
     d32 = tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp32")
-    np_ = _padded(128, 128, 1024)
-    assert np_ == 129 * 129 * 1056
+    np_ = 129 * 129 * 1025
     b64, b32 = tete.workspace_bytes(d64), tete.workspace_bytes(d32)
     assert b64 >= 12 * 8 * np_ + np_ and b32 >= 12 * 4 * np_ + np_
     assert b64 - b32 == pytest.approx(12 * 4 * np_, rel=1e-3)
@@ -151,7 +144,7 @@ def test_implicit_stability_validation(dx, dz, cdt, want):
 def test_implicit_flags_and_workspace():
     assert tete.check_desc(tete.make_desc(8, 8, 8, 2, 2, 1, 1, implicit=True, materials=True)) == "TETE_ERR_ARG"
     assert tete.check_desc(tete.make_desc(8, 8, 8, 2, 2, 1, 0.5, implicit=True, yee=True)) == "TETE_ERR_ARG"
-    np_ = _padded(128, 128, 1024)
+    np_ = 129 * 129 * 1025
     b = tete.workspace_bytes(tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp32"))
     bi = tete.workspace_bytes(tete.make_desc(128, 128, 1024, 2, 2, 1, 1, "fp32", implicit=True))
     # four plane-solve arrays and two row lists (int32) of np entries each
