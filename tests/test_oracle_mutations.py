@@ -303,6 +303,7 @@ def test_witness_pins_catch_planted_mistake(tmp_path, name):
 
 # ---- the open-pipe oracle (Python), same harness
 from tests import test_oracle_pipe as TPI
+from tests import test_oracle_pipe_closed as TPC
 
 PI_SRC = os.path.join(os.path.dirname(HERE), "oracle", "pipe_oracle.py")
 
@@ -315,7 +316,8 @@ PI_MUTANTS = {
                              [lambda p: TPI.test_potential_matches_discrete_sine_series(p)]),
     # the profile's mean tied to half the current
     "pipe_profile_half": ([("F[q] = 2.0 * cur - F[q + 1]", "F[q] = cur - F[q + 1]")],
-                          [lambda p: TPI.test_self_field_node_charges_are_the_bunch(p)]),
+                          [lambda p: TPI.test_self_field_node_charges_are_the_bunch(p),
+                           lambda p: TPC.test_3d_step_out_open_pipes_equal_closed_box_limit(p)]),
     # h_y with the wrong sign
     "pipe_hy_sign": ([('f["hy"][:-1, :, :-1] = ((g.dy / g.dx) * Ex)', 'f["hy"][:-1, :, :-1] = (-(g.dy / g.dx) * Ex)')],
                      [lambda p: TPI.test_self_field_moves_one_cell_per_step(p, 5, 7, 1.0)]),
@@ -333,7 +335,8 @@ PI_MUTANTS = {
                         [lambda p: TPI.test_rz_self_field_moves_one_cell_per_step(p, 1, 4)]),
     # r-z: h_phi tied to e_r at the node radius instead of r_{j+1/2}
     "rz_pipe_hphi_radius": ([("((j + 0.5) * g.dr / g.dr)", "((j + 0.0) * g.dr / g.dr)")],
-                            [lambda p: TPI.test_rz_self_field_moves_one_cell_per_step(p, 0, 0)]),
+                            [lambda p: TPI.test_rz_self_field_moves_one_cell_per_step(p, 0, 0),
+                             lambda p: TPC.test_rz_step_out_open_pipes_equal_closed_box_limit(p)]),
 }
 
 
