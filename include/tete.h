@@ -135,7 +135,7 @@ enum {
 };
 
 typedef struct {
-    int32_t nx, ny, nz;   /* cells, each >= 2; (nx+1)(ny+1)(nz+1) < 2^31 */
+    int32_t nx, ny, nz;   /* cells, each >= 2; (nx+1)(ny+1)(nz+1) <= 2^31 - 2^24 */
     double dx, dy, dz;    /* cell sizes [m] */
     double cdt;           /* dtau = c dt [m]; must satisfy (25):
                              cdt <= dz and cdt <= (dx^-2 + dy^-2)^(-1/2) */

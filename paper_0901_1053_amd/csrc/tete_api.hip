@@ -507,7 +507,8 @@ tete_status tete_check_desc(const tete_grid_desc* d)
     if (!d) return TETE_ERR_ARG;
     if (d->nx < 2 || d->ny < 2 || d->nz < 2) return TETE_ERR_ARG;
     const int64_t np = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
-    if (np >= ((int64_t)1 << 31) - 1) return TETE_ERR_ARG;
+    // entries fit int indices with room for the grid-stride loops' last step
+    if (np > ((int64_t)1 << 31) - ((int64_t)1 << 24)) return TETE_ERR_ARG;
     if (!finite_pos(d->dx) || !finite_pos(d->dy) || !finite_pos(d->dz) || !finite_pos(d->cdt)) return TETE_ERR_ARG;
     if (d->precision != TETE_FP64 && d->precision != TETE_FP32) return TETE_ERR_ARG;
     if (d->flags & ~(uint32_t)(TETE_F_MATERIALS | TETE_F_YEE | TETE_F_IMPLICIT | TETE_F_SKIP_STATIC))

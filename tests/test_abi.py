@@ -52,6 +52,10 @@ def test_descriptor_limits():
     assert tete.check_desc(tete.make_desc(1, 4, 4, 2, 2, 1, 1)) == "TETE_ERR_ARG"
     assert tete.check_desc(tete.make_desc(2, 2, 2, 2, 2, 1, 1)) == "TETE_OK"
     assert tete.check_desc(tete.make_desc(2048, 1024, 1024, 2, 2, 1, 1)) == "TETE_ERR_ARG"   # >= 2^31 entries
+    # the largest grid: 1016 x 1024 x 2048 = 2^31 - 2^24 entries (int indices
+    # with room for a grid-stride loop's last step); one plane more is refused
+    assert tete.check_desc(tete.make_desc(1015, 1023, 2047, 2, 2, 1, 1)) == "TETE_OK"
+    assert tete.check_desc(tete.make_desc(1016, 1023, 2047, 2, 2, 1, 1)) == "TETE_ERR_ARG"
     d = tete.make_desc(8, 8, 8, 2, 2, 1, 1)
     d.precision = 7
     assert tete.check_desc(d) == "TETE_ERR_ARG"

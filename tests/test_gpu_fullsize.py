@@ -56,6 +56,55 @@ def test_full_size_sampled_parity(which, precision):
     torch.cuda.empty_cache()
 
 
+def test_maximum_size_sampled_parity():
+    """The largest grid the descriptor admits, 1015 x 1023 x 2047 cells
+    (2^31 - 2^24 entries; FP32, about 104 GB of workspace), with a tapered
+    round aperture: three steps (a two-step launch and a single step, over five
+    x-chunks) from random fields, sampled entries against the oracle's
+    sub-box recomputation within 1e-5 of the sub-box's largest value."""
+    import torch
+    nx, ny, nz = 1015, 1023, 2047
+    dx = dy = 2e-3
+    dz = cdt = 1e-3
+    assert (nx + 1) * (ny + 1) * (nz + 1) == 2 ** 31 - 2 ** 24
+    print("maximum-size grid", nx, ny, nz, flush=True)
+    i = (np.arange(nx) + 0.5 - nx / 2)[:, None]
+    j = (np.arange(ny) + 0.5 - ny / 2)[None, :]
+    dist = np.sqrt(i * i + j * j).astype(np.float32)
+    radius = np.linspace(60.0, 300.0, nz, dtype=np.float32)       # taper along z, in cells
+    cells = dist[:, :, None] > radius[None, None, :]
+    G = tete.Grid(nx, ny, nz, dx, dy, dz, cdt, precision="fp32")
+    G.set_pec_cells(cells)
+    f0 = inputs.random_fields_torch(G.shape, 4242, "cuda", torch.float32)
+    G.set_fields(f0, dtype="fp32")
+    steps = 3
+    G.step(steps)
+    fg = G.get_fields(dtype="fp32", numpy=False)
+    print("maximum-size steps done", flush=True)
+
+    def in_range(k, p):
+        a, b, c = p
+        return {"ex": a < nx, "ey": b < ny, "ez": c < nz, "hx": b < ny and c < nz,
+                "hy": a < nx and c < nz, "hz": a < nx and b < ny}[k]
+
+    pts = inputs.sample_points(G.shape, 4243, count=12) + [(nx // 2, ny // 2, nz // 2), (nx // 2 + 60, ny // 2, 5)]
+    for p in pts:
+        vals, sub = oracle_point(
+            p, G.shape, dx, dy, dz, cdt,
+            lambda lo, hi: {k: f0[k][lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1].double().cpu().numpy()
+                            for k in tete.KEYS},
+            lambda lo, hi: cells[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]], steps)
+        scale = max(np.max(np.abs(v)) for v in sub.values())
+        for k in tete.KEYS:
+            got = float(fg[k][p].item())
+            if in_range(k, p):
+                assert abs(got - vals[k]) <= 1e-5 * scale, (p, k, got, vals[k])
+            else:
+                assert got == 0.0, (p, k)
+    del fg, f0, G
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_single_wake_full_run_properties(precision):
     """Step collimator 128x128x1024, 1 nC, sigma = 1 mm, run until the bunch
