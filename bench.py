@@ -357,11 +357,13 @@ def witness_section(G, case, two_step_ms, offset=32, steps=20):
             "vs_two_step_without_witness": round(ms / two_step_ms, 3)}
 
 
-def _pec_materials(case, precision, scale=0.9):
+def _pec_materials(case, precision, scale=0.9, graded=False):
     """Per-entry materials carrying the workload's geometry, made on the
     device: kappa and mu `scale` of their vacuum values, kappa zero on the
     staircase PEC edges (an e edge touching a metal cell, cells outside the box
-    counting as metal)."""
+    counting as metal).  graded: each value also times 1 + 0.05 sin(0.013 k +
+    0.007 i + c), a medium graded along z and x with far more distinct tuples
+    than classes."""
     import numpy as np
     import torch
     from paper_0901_1053_amd import tete
@@ -378,8 +380,12 @@ def _pec_materials(case, precision, scale=0.9):
          "ez": case.dz / (case.dx * case.dy)}
     v.update({"hx": v["ex"], "hy": v["ey"], "hz": v["ez"]})
     mat = {}
-    for k in tete.KEYS:
+    for c, k in enumerate(tete.KEYS):
         a = torch.full((X, Y, Z), scale * v[k], device="cuda", dtype=td)
+        if graded:
+            kk = torch.arange(Z, device="cuda", dtype=torch.float64)[None, None, :]
+            ii = torch.arange(X, device="cuda", dtype=torch.float64)[:, None, None]
+            a *= (1.0 + 0.05 * torch.sin(0.013 * kk + 0.007 * ii + c)).to(td)
         if k in pec:
             a.masked_fill_(pec[k], 0.0)
         mat[k] = a
@@ -397,8 +403,11 @@ def materials_section(case, precision, explicit_ms_per_step, steps=6):
     paired steps run the two-step kernel's class instance, reading one class
     byte per entry and the class table from LDS (one read and one write of
     the state per two steps); (3) the arrays of (1) with the default tuning,
-    which finds their few tuples as classes and runs as (2).  The fields of
-    (1), (2) and (3) are the same (tests)."""
+    which finds their few tuples as classes and runs as (2); (4) a graded
+    medium with far more tuples than classes, by default (FP32: the two-step
+    kernel's arrays instance, six arrays read with the fields once per two
+    steps) and by the materials step.  The fields of (1), (2) and (3) are the
+    same, and those of (4) by either kernel (tests)."""
     import torch
     from paper_0901_1053_amd import tete
     mat, table = _pec_materials(case, precision)
@@ -443,6 +452,27 @@ def materials_section(case, precision, explicit_ms_per_step, steps=6):
     C.close()
     del C
     torch.cuda.empty_cache()
+    # (4) a graded medium (no classes): the arrays instance of the two-step
+    # kernel (FP32) against the materials step
+    mat, _ = _pec_materials(case, precision, graded=True)
+    D = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.cdt, precision=precision,
+                  materials=True)
+    D.set_pec_cells(case.cell_mask())
+    D.set_materials(mat, dtype=precision)
+    del mat
+    torch.cuda.empty_cache()
+    graded_kernel = D.get_tuning()["kernel"]
+    for kn in ("auto", "fused"):
+        D.set_tuning(kn)
+        D.step(2)
+        D.set_timing(2 * steps)
+        D.step(2 * steps)
+        a, b2, n = D.timing()
+        D.set_timing(0)
+        out["graded_" + kn] = (a + b2) / n
+    D.close()
+    del D
+    torch.cuda.empty_cache()
     b = 4 if precision == "fp32" else 8
     entries = (case.nx + 1) * (case.ny + 1) * (case.nz + 1)
     nbytes = (18 * b + 1) * entries
@@ -450,7 +480,11 @@ def materials_section(case, precision, explicit_ms_per_step, steps=6):
             "materials": "0.9 x vacuum kappa and mu per entry, kappa 0 on the staircase PEC edges",
             "ms_per_step": {"fused_materials": round(out["fused"], 3), "two_kernel": round(out["split"], 3),
                             "classes_two_step": round(out["classes"], 3),
-                            "arrays_default": round(out["auto"], 3)},
+                            "arrays_default": round(out["auto"], 3),
+                            "graded_arrays_default": round(out["graded_auto"], 3),
+                            "graded_arrays_materials_step": round(out["graded_fused"], 3)},
+            "graded_arrays": "each value also times 1 + 0.05 sin(0.013 k + 0.007 i + c): no classes; the default "
+                             "kernel is %s" % graded_kernel,
             "classes_kernel": kernel,
             "arrays_default_kernel": auto_kernel + (" (classes found in the arrays)" if auto_kernel == "fused2" else ""),
             "fused_materials_gbps_algorithmic": round(nbytes / (out["fused"] / 1e3) / 1e9, 1),

@@ -203,8 +203,12 @@ tete_status tete_set_pec_cells(tete_grid* g, const uint8_t* cell_is_pec);
  * edge the PEC codes mark (the box walls and tete_set_pec_cells), the grid
  * runs as after tete_set_material_classes with those tuples: paired steps
  * take the two-step kernel's class instance, with the same results as the
- * materials step over the arrays.  Otherwise every step is the materials
- * step.  Synchronises the stream. */
+ * materials step over the arrays.  Otherwise, with FP32 fields, paired steps
+ * take the two-step kernel's arrays instance (16 rows of 32 lanes, the six
+ * arrays read with the fields once per two steps; not with witness lines or
+ * TETE_F_SKIP_STATIC), with the same results as single materials steps; every
+ * other step (and every step with FP64 fields) is the materials step.
+ * Synchronises the stream. */
 tete_status tete_set_materials(tete_grid* g, const void* const inv_eps[3],
                                const void* const inv_mu[3], int32_t dtype);
 
@@ -413,14 +417,17 @@ tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h);
  * beyond rounding order, and the fused kernels give identical results).
  * kernel:
  *   TETE_KERNEL_AUTO   the two-step kernel, or the fused single step with
- *                      per-entry materials;
+ *                      per-entry materials it has no instance for (FP64
+ *                      arrays, arrays with witness lines or the static-tile
+ *                      skip);
  *   TETE_KERNEL_FUSED  the fused single-kernel step (with per-entry
  *                      materials: its materials instance, default rows and
  *                      one prefetched plane, the coefficients read with the
  *                      fields and carried to the sub-updates' planes);
  *   TETE_KERNEL_FUSED2 two steps per launch, temporally blocked
- *                      (TETE_ERR_STATE with per-entry materials set by
- *                      tete_set_materials; materials by class use it).  tete_step
+ *                      (TETE_ERR_STATE with FP64 per-entry arrays or arrays on a
+ *                      TETE_F_SKIP_STATIC grid; materials by class and FP32
+ *                      arrays use it).  tete_step
  *                      pairs consecutive steps except where an energy sample
  *                      or probes need the state in between; those steps, and
  *                      an odd last one, run as fused single steps;

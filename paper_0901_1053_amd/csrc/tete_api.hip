@@ -295,12 +295,18 @@ int fused2_xchunk(const tete_grid* g)
     return g->tune.xchunk != 0 ? g->tune.xchunk : g->skip ? 32 : 0;
 }
 
+// FP32 per-entry arrays: the two-step kernel's arrays instance, without
+// witness lines or a static-tile list.
+bool arrays_fused2(const tete_grid* g) { return g->fp32 && !g->skip; }
+
 // Per-entry materials step as single steps, except materials by class, which
-// the two-step kernel's class instance takes (without witness lines).
+// the two-step kernel's class instance takes, and FP32 arrays, which its
+// arrays instance takes (both without witness lines).
 bool use_fused2(const tete_grid* g)
 {
     const bool want = g->tune.kernel == TETE_KERNEL_FUSED2 || g->tune.kernel == TETE_KERNEL_AUTO;
-    const bool mat_ok = !g->mat_set || (g->mat_cls && !(g->witness && g->has_bunch));
+    const bool wit = g->witness && g->has_bunch;
+    const bool mat_ok = !g->mat_set || (g->mat_cls && !wit) || (!g->mat_cls && arrays_fused2(g) && !wit);
     return want && mat_ok && use_fused(g) && fused2_fits(g->geo, g->fp32 ? 4 : 8);
 }
 
@@ -642,7 +648,7 @@ tete_status tete_set_tuning(tete_grid* g, const tete_tuning* t)
     if (t->xchunk < 0) return TETE_ERR_ARG;
     if (t->depth < 0 || t->depth > 3) return TETE_ERR_ARG;
     if (t->order < 0 || t->order > 6) return TETE_ERR_ARG;
-    if (t->kernel == TETE_KERNEL_FUSED2 && g->mat_set && !g->mat_cls) return TETE_ERR_STATE;
+    if (t->kernel == TETE_KERNEL_FUSED2 && g->mat_set && !g->mat_cls && !arrays_fused2(g)) return TETE_ERR_STATE;
     g->tune = *t;
     return TETE_OK;
 }

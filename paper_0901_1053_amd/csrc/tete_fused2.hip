@@ -189,10 +189,24 @@ inline int lanes2(int real_bytes, int rows) { return real_bytes == 8 || rows == 
 // in LDS (already multiplied by a or 2a, the product the materials step forms
 // from its arrays, so the results are those of single materials steps), the
 // kappa of PEC edges zeroed by the codes as in vacuum.
-template <typename R, int TYH, int NB, int LW, int PD, bool WIT = false, bool CLS = false, class LDS>
+// ARR: per-entry materials, the six arrays kappa_x,y,z, mu_x,y,z of MA (zero
+// on PEC edges and outside each component's range, as the materials step
+// takes them).  Each plane's six values are loaded with its fields and
+// carried in registers for the planes the two stages reach back (kappa_x
+// eight planes, kappa_y and mu_z seven, mu_x and mu_y six, kappa_z five);
+// each coefficient is multiplied by a or 2a where it is used, the product the
+// materials step forms, so the results are those of single materials steps.
+// The PEC codes are not read.
+template <typename R>
+struct Arr6 {
+    const R* m[6];
+};
+template <typename R, int TYH, int NB, int LW, int PD, bool WIT = false, bool CLS = false, bool ARR = false,
+          class LDS>
 __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, const int tz, const int cx, LDS& L,
-                                            const WitMid<R>& wm = WitMid<R>{})
+                                            const WitMid<R>& wm = WitMid<R>{}, const Arr6<R>& MA = Arr6<R>{})
 {
+    static_assert(!(ARR && (CLS || WIT)), "one material source per instance");
     constexpr int TY = TYH - 6;   // rows owned
     constexpr int KT2 = LW - 4;   // entries owned per row
     // Lane shifts act on the whole wave; with two rows per wave (LW = 32) the
@@ -248,6 +262,11 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
                rHY = mk(A.hy + ld0, nload * plane_bytes), rHZ = mk(A.hz + ld0, nload * plane_bytes);
     const auto rC = mk(A.code, (uint32_t)std::min<int64_t>((int64_t)g.np + 4, 0x7fffffff));
     __amdgpu_buffer_rsrc_t rK = rC;
+    __amdgpu_buffer_rsrc_t rM[ARR ? 6 : 1];
+    if constexpr (ARR) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) rM[c] = mk(MA.m[c] + ld0, nload * plane_bytes);
+    }
     if constexpr (CLS) {
         rK = mk(A.cls, (uint32_t)std::min<int64_t>((int64_t)g.np + 4, 0x7fffffff));
         // the class table into LDS; the barrier of the first j-exchange
@@ -274,6 +293,7 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
         R ex, ey, ez, hx, hy, hz;
         uint32_t c;
         uint32_t k[CLS ? 1 : 0];
+        R m[ARR ? 6 : 0];
     };
     auto load_plane = [&](int i, PR& d) {
         const uint32_t po = (uint32_t)(i - pb);
@@ -284,15 +304,29 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
         d.hx = bload<R>(rHX, off);
         d.hy = bload<R>(rHY, off);
         d.hz = bload<R>(rHZ, off);
-        const uint32_t offc = node ? ((uint32_t)(roff + i * g.sp) & ~3u) : OOB;
-        d.c = __builtin_amdgcn_raw_buffer_load_b32(rC, offc, 0, 0);   // byte extracted when used
-        if constexpr (CLS) d.k[0] = __builtin_amdgcn_raw_buffer_load_b32(rK, offc, 0, 0);
+        if constexpr (ARR) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) d.m[c] = bload<R>(rM[c], off);
+            d.c = 0u;
+        } else {
+            const uint32_t offc = node ? ((uint32_t)(roff + i * g.sp) & ~3u) : OOB;
+            d.c = __builtin_amdgcn_raw_buffer_load_b32(rC, offc, 0, 0);   // byte extracted when used
+        }
+        if constexpr (CLS) {
+            const uint32_t offc = node ? ((uint32_t)(roff + i * g.sp) & ~3u) : OOB;
+            d.k[0] = __builtin_amdgcn_raw_buffer_load_b32(rK, offc, 0, 0);
+        }
     };
 
     Stage<R> SA = {}, SB = {};
     // class bytes of planes p .. p-3 (kh0, byte i = plane p-i), p-4 .. p-7 (kh1)
     // and p-8 (kh2) (CLS only)
     uint32_t kh0 = 0, kh1 = 0, kh2 = 0;
+    // coefficient histories of ARR, index = planes behind p (index 0 is the
+    // current plane's, set from its loads)
+    constexpr int HA = ARR ? 1 : 0;
+    R hKX[9 * HA + 1] = {}, hKY[8 * HA + 1] = {}, hKZ[6 * HA + 1] = {}, hMX[7 * HA + 1] = {}, hMY[7 * HA + 1] = {},
+      hMZ[8 * HA + 1] = {};
     const int tid = threadIdx.x;
     for (int q = 0; q < 3; ++q) L.d[q][0][tid] = L.d[q][1][tid] = R(0);   // stage B's delay lines
     R d_ey4 = 0;                 // e_y^{n+1} of plane p-4
@@ -353,6 +387,22 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
         return f;
     };
     auto cbyte = [](uint32_t h, int b) { return (h >> (8 * b)) & 0xffu; };
+    // coefficients from the histories for a stage whose input plane is lb
+    // planes behind p (ARR)
+    auto coefa = [&](const int lb) {
+        Co<R> f;
+        f.mx0 = A.a * hMX[lb];
+        f.mx2 = A.a * hMX[lb + 2];
+        f.my1 = A.a * hMY[lb + 1];
+        f.my2 = A.a * hMY[lb + 2];
+        f.mz3 = a2 * hMZ[lb + 3];
+        f.kz1 = a2 * hKZ[lb + 1];
+        f.ky2 = A.a * hKY[lb + 2];
+        f.kx2 = A.a * hKX[lb + 2];
+        f.ky3 = A.a * hKY[lb + 3];
+        f.kx4 = A.a * hKX[lb + 4];
+        return f;
+    };
     // bunch current of step n on edge k (zero where no cell crosses it),
     // rounded on its own before it is subtracted
     auto inject = [&](int64_t n, R kz) {
@@ -375,6 +425,10 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
             kh2 = kh1 >> 24;
             kh1 = (kh1 << 8) | (kh0 >> 24);
             kh0 = (kh0 << 8) | ((cur.k[0] >> bsh) & 0xffu);
+        }
+        if constexpr (ARR) {
+            hKX[0] = cur.m[0]; hKY[0] = cur.m[1]; hKZ[0] = cur.m[2];
+            hMX[0] = cur.m[3]; hMY[0] = cur.m[4]; hMZ[0] = cur.m[5];
         }
 
         // stage B's input plane p-4, except e_x (stage A's S9 of this
@@ -410,6 +464,9 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
         if constexpr (CLS) {
             fA = coefc(cbyte(kh0, 0), cbyte(kh0, 1), cbyte(kh0, 2), cbyte(kh0, 3), cbyte(kh1, 0), ch);
             fB = coefc(cbyte(kh1, 0), cbyte(kh1, 1), cbyte(kh1, 2), cbyte(kh1, 3), cbyte(kh2, 0), ch >> 16);
+        } else if constexpr (ARR) {
+            fA = coefa(0);
+            fB = coefa(4);
         } else {
             fA = coef(p, ch);
             fB = coef(p - 4, ch >> 16);
@@ -423,8 +480,14 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
             kzA = tab(cbyte(kh0, 1), CLS_KZ);
             kzB = tab(cbyte(kh1, 1), CLS_KZ);
         }
-        const R injA = (srcA && src_k) ? inject(A.src.n, sel(ch, 2, kzA)) : R(0);
-        const R injB = (srcB && src_k) ? inject(A.src.n + 1, sel(ch, 18, kzB)) : R(0);
+        R injA, injB;
+        if constexpr (ARR) {      // the arrays hold kappa_z = 0 on PEC edges
+            injA = (srcA && src_k) ? inject(A.src.n, hKZ[1]) : R(0);
+            injB = (srcB && src_k) ? inject(A.src.n + 1, hKZ[5]) : R(0);
+        } else {
+            injA = (srcA && src_k) ? inject(A.src.n, sel(ch, 2, kzA)) : R(0);
+            injB = (srcB && src_k) ? inject(A.src.n + 1, sel(ch, 18, kzB)) : R(0);
+        }
 
         const Out<R> oA = stage_plane(SA, In<R>{cur.ex, cur.ey, cur.ez, cur.hx, cur.hy, cur.hz}, nA, fA, injA);
         const Out<R> oB = stage_plane(SB, In<R>{oA.ex14, bEY, bEZ, bHX, bHY, bHZ}, nB, fB, injB);
@@ -476,6 +539,16 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
         L.d[2][s][tid] = oA.hyh2;
         d_ey4 = oA.ey13;
         ch = (ch << 4) | c0;
+        if constexpr (ARR) {      // histories one plane older
+#pragma unroll
+            for (int d = 8; d > 0; --d) hKX[d] = hKX[d - 1];
+#pragma unroll
+            for (int d = 7; d > 0; --d) { hKY[d] = hKY[d - 1]; hMZ[d] = hMZ[d - 1]; }
+#pragma unroll
+            for (int d = 6; d > 0; --d) { hMX[d] = hMX[d - 1]; hMY[d] = hMY[d - 1]; }
+#pragma unroll
+            for (int d = 5; d > 0; --d) hKZ[d] = hKZ[d - 1];
+        }
     };
 
     // trip count rounded up to a multiple of PD+1, as in the single-step kernel
@@ -512,6 +585,18 @@ __global__ __launch_bounds__(TYH * LW) void k_fused2(FArgs<R> A, const int* act)
     int ty, tz, cx;
     if (!fused2_tile_of(A, act, ty, tz, cx)) return;   // whole group
     fused2_tile<R, S::rows, S::nb, S::lw, PD>(A, ty, tz, cx, L);
+}
+
+// The two-step kernel with per-entry materials (FP32: 16 rows of 32 lanes,
+// 512 threads, two planes loaded ahead).
+template <typename R, int TYH, int LW, int PD>
+__global__ __launch_bounds__(TYH * LW) void k_fused2_arr(FArgs<R> A, Arr6<R> MA, const int* act)
+{
+    typedef Shape2<R, TYH, LW> S;
+    __shared__ Lds2<R, S::rows, S::nb, S::lw> L;
+    int ty, tz, cx;
+    if (!fused2_tile_of(A, act, ty, tz, cx)) return;   // whole group
+    fused2_tile<R, S::rows, S::nb, S::lw, PD, false, false, true>(A, ty, tz, cx, L, WitMid<R>{}, MA);
 }
 
 // The two-step kernel with materials by class.
@@ -626,11 +711,12 @@ hipError_t launch_batch_step2(BatchTable<R>* T, int grid, int flips, int steps, 
 }
 
 template <typename R>
-bool fused2_setup(FArgs<R>& A, int rows, int xchunk, int order)
+bool fused2_setup(FArgs<R>& A, int rows, int xchunk, int order, int lanes)
 {
     if (rows == 0) rows = Default2<R>::rows;
     if (rows != 16 && !((rows == 24 || rows == 32) && sizeof(R) == 4)) return false;
-    const int TY = rows - 6, KT2 = lanes2(sizeof(R), rows) - 4;
+    if (lanes != 0 && lanes != 32 && lanes != 64) return false;
+    const int TY = rows - 6, KT2 = (lanes ? lanes : lanes2(sizeof(R), rows)) - 4;
     A.nyt = (A.g.ny + 1 + TY - 1) / TY;
     A.nzt = (A.g.nz + 1 + KT2 - 1) / KT2;
     const int nplanes = A.g.nx + 1;
@@ -728,13 +814,32 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
         if (wm) return hipErrorInvalidValue;
         rows = sizeof(R) == 4 ? 24 : 16;
     }
+    // per-entry materials (FP32 only): one shape, 16 rows of 32 lanes; no
+    // witness lines, no static-tile list
+    const bool arr = !A.cls && M.arr[0] != nullptr;
+    int lanes = 0;
+    if (arr) {
+        if (sizeof(R) != 4 || wm || act) return hipErrorInvalidValue;
+        for (int c = 0; c < 6; ++c)
+            if (!M.arr[c]) return hipErrorInvalidValue;
+        rows = 16;
+        lanes = 32;
+    }
     // with a list of active tiles, one workgroup per entry (none: every tile is
     // static and the new set already holds the result)
     const int grid = act ? nact : 0;
-    if (!fused2_setup<R>(A, rows, xchunk, order)) return hipErrorInvalidValue;
+    if (!fused2_setup<R>(A, rows, xchunk, order, lanes)) return hipErrorInvalidValue;
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
     bool done = false;
+    if constexpr (sizeof(R) == 4) {
+        if (arr) {
+            Arr6<R> MA;
+            for (int c = 0; c < 6; ++c) MA.m[c] = M.arr[c];
+            k_fused2_arr<R, 16, 32, 2><<<A.nblk, 16 * 32, 0, s>>>(A, MA, nullptr);
+            done = true;
+        }
+    }
     if (wm) {
         if (wm->iw < 1 || wm->iw > g.nx - 1 || wm->jw < 1 || wm->jw > g.ny - 1) return hipErrorInvalidValue;
         constexpr int TW = Default2<R>::rows * Default2<R>::lw;
@@ -777,7 +882,7 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
 
 #define TETE_FUSED2_INST(R)                                                                                    \
     template hipError_t launch_batch_step2<R>(BatchTable<R>*, int, int, int, hipStream_t);                     \
-    template bool fused2_setup<R>(FArgs<R>&, int, int, int);                                                   \
+    template bool fused2_setup<R>(FArgs<R>&, int, int, int, int);                                              \
     template hipError_t launch_step_fused2<R>(Fields<R>, Fields<R>, Mat<R>, Geo, R, Src, const WitMid<R>*, int, \
                                               int, int, int, hipStream_t, hipEvent_t*, const int*, int);     \
     template hipError_t fused2_static_tiles<R>(const uint8_t*, Geo, int, int, int, uint8_t*, int*, int64_t,    \

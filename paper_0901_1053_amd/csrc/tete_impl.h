@@ -173,7 +173,7 @@ int fused_default_rows(int real_bytes);
 bool fused2_fits(Geo g, int real_bytes);
 // rows: 0 (default), 16, or 24 or 32 (FP32 only: rows of 32 lanes).
 template <typename R>
-bool fused2_setup(FArgs<R>& A, int rows, int xchunk, int order);
+bool fused2_setup(FArgs<R>& A, int rows, int xchunk, int order, int lanes = 0);
 // wm (or nullptr): the witness lines whose e_z^{n+1/2} the launch keeps;
 // act (or nullptr): the nact active tiles of fused2_static_tiles for the same
 // rows (0 with wm), xchunk and order; the launch takes only these (none if
