@@ -678,9 +678,11 @@ struct Six {
 // checks its tuple against the slot's bitwise (two tuples with one hash
 // fail this check) and writes its class byte.  Entries outside a
 // component's range hold 0 there, as imported.  flags[0]: the table
-// overflowed; flags[1]: an e edge that the PEC codes mark carries a nonzero
-// kappa (the class kernel takes kappa 0 there from the codes); flags[2]: a
-// tuple differs from its slot's.
+// overflowed or took more than TETE_MAX_CLASSES tuples (flags[3] counts
+// them); flags[1]: an e edge that the PEC codes mark carries a nonzero kappa
+// (the class kernel takes kappa 0 there from the codes); flags[2]: a tuple
+// differs from its slot's.  The insert pass stops early once flags[0] or
+// flags[1] is set: the arrays are then no classes whatever the rest holds.
 __device__ __forceinline__ uint64_t mix64(uint64_t x)
 {
     x ^= x >> 30;
@@ -713,6 +715,10 @@ __global__ void k_classify_insert(Six<const R> m, const uint8_t* code, Geo g, un
 {
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < g.np;
          idx += (int64_t)gridDim.x * blockDim.x) {
+        // the arrays are no classes once flags[0] or flags[1] is set: stop
+        // (a graded medium fills the table within its first entries, and every
+        // later new tuple would probe all its slots)
+        if (*(volatile const int*)&flags[0] | *(volatile const int*)&flags[1]) break;
         R v[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) v[c] = m.c[c][idx];
@@ -731,6 +737,8 @@ __global__ void k_classify_insert(Six<const R> m, const uint8_t* code, Geo g, un
                 if (cur == 0ull) {                     // this entry inserted the tuple
 #pragma unroll
                     for (int c = 0; c < 6; ++c) vals[6 * slot + c] = (double)v[c];
+                    // more tuples than classes: as good as an overflow
+                    if (atomicAdd(&flags[3], 1) >= TETE_MAX_CLASSES) flags[0] = 1;
                     placed = true;
                     break;
                 }
