@@ -111,17 +111,25 @@ def test_timing_counts_steps():
     assert n == 7 and ms > 0
 
 
-def test_materials_fall_back():
-    G = tete.Grid(8, 8, 40, 2.0e-3, 1.7e-3, 1.0e-3, 0.9e-3, precision="fp32", materials=True)
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_materials_kernel_choice(precision):
+    """Per-entry arrays with many tuples: FP32 pairs steps in the two-step
+    kernel's arrays instance; FP64 falls back to the single step's materials
+    instance and refuses a forced two-step kernel."""
+    G = tete.Grid(8, 8, 40, 2.0e-3, 1.7e-3, 1.0e-3, 0.9e-3, precision=precision, materials=True)
     G.set_tuning("fused2")
     assert G.get_tuning()["kernel"] == "fused2"
     rng = np.random.default_rng(0)
     G.set_materials({k: rng.uniform(0.5, 1.0, G.shape) for k in tete.KEYS})
-    assert G.get_tuning()["kernel"] == "fused"        # the single step's materials instance
+    assert G.get_tuning()["kernel"] == ("fused2" if precision == "fp32" else "fused")
     G.set_tuning("split")
     assert G.get_tuning()["kernel"] == "split"
-    with pytest.raises(tete.TeteError):
+    if precision == "fp32":
         G.set_tuning("fused2")
+        assert G.get_tuning()["kernel"] == "fused2"
+    else:
+        with pytest.raises(tete.TeteError):
+            G.set_tuning("fused2")
 
 
 @pytest.mark.parametrize("shape", [(13, 11, 37), (40, 29, 130), (2, 2, 2), (9, 20, 1000)])
