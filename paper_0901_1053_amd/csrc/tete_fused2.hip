@@ -324,9 +324,8 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
     uint32_t kh0 = 0, kh1 = 0, kh2 = 0;
     // coefficient histories of ARR, index = planes behind p (index 0 is the
     // current plane's, set from its loads)
-    constexpr int HA = ARR ? 1 : 0;
-    R hKX[9 * HA + 1] = {}, hKY[8 * HA + 1] = {}, hKZ[6 * HA + 1] = {}, hMX[7 * HA + 1] = {}, hMY[7 * HA + 1] = {},
-      hMZ[8 * HA + 1] = {};
+    R hKX[ARR ? 9 : 1] = {}, hKY[ARR ? 8 : 1] = {}, hKZ[ARR ? 6 : 1] = {}, hMX[ARR ? 7 : 1] = {},
+      hMY[ARR ? 7 : 1] = {}, hMZ[ARR ? 8 : 1] = {};
     const int tid = threadIdx.x;
     for (int q = 0; q < 3; ++q) L.d[q][0][tid] = L.d[q][1][tid] = R(0);   // stage B's delay lines
     R d_ey4 = 0;                 // e_y^{n+1} of plane p-4
