@@ -357,6 +357,34 @@ def witness_section(G, case, two_step_ms, offset=32, steps=20):
             "vs_two_step_without_witness": round(ms / two_step_ms, 3)}
 
 
+def diagnostics_section(G, case, two_step_ms, steps=16):
+    """An energy sample (Sec. 4.4) before every step on the large workload:
+    time per step from HIP events on the grid's stream, with the default
+    kernel (paired launches take both samples, of y^n and y^{n+1}, inside the
+    launch) and with single steps (the fused step, the energy kernel before
+    each).  The series agree to the rounding of their FP64 sums (tests)."""
+    import torch
+    saved = G.get_tuning()
+    res = {}
+    for name, kernel in (("paired_with_samples", "auto"), ("single_steps_and_energy_kernel", "fused")):
+        G.set_tuning(kernel)
+        G.set_diagnostics(1)
+        G.step(2)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(G.stream)
+        G.step(steps)
+        e1.record(G.stream)
+        torch.cuda.synchronize()
+        res[name] = round(e0.elapsed_time(e1) / steps, 4)
+        G.set_diagnostics(0)
+    G.set_tuning(saved["kernel"], saved["rows"], saved["xchunk"], saved["depth"], saved["order"])
+    return {"workload": case.name, "energy_every": 1, "ms_per_step": res,
+            "vs_two_step_without_samples": round(res["paired_with_samples"] / two_step_ms, 3),
+            "speedup_over_single_steps": round(res["single_steps_and_energy_kernel"] / res["paired_with_samples"], 2)}
+
+
 def _pec_materials(case, precision, scale=0.9, graded=False):
     """Per-entry materials carrying the workload's geometry, made on the
     device: kappa and mu `scale` of their vacuum values, kappa zero on the
@@ -717,6 +745,7 @@ def main():
     ap.add_argument("--no-skip", action="store_true", help="skip the static-tile skip timing")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape table of the headline grid")
     ap.add_argument("--no-pipes", action="store_true", help="skip the open-pipe single wake")
+    ap.add_argument("--no-diag", action="store_true", help="skip the energy-every-step timing")
     ap.add_argument("--batched-count", type=int, default=64)
     ap.add_argument("--serve-rates", default="1,10,50,200", help="comma-separated request rates (req/s)")
     ap.add_argument("--serve-requests", type=int, default=48)
@@ -843,6 +872,9 @@ def main():
     if not args.no_witness:
         out["witness_context"] = witness_section(G, case, ms_step)
         print("# witness timing done", file=sys.stderr, flush=True)
+    if not args.no_diag:
+        out["diagnostics_context"] = diagnostics_section(G, case, ms_step)
+        print("# diagnostics timing done", file=sys.stderr, flush=True)
     del G
     torch.cuda.empty_cache()
     if not args.no_implicit:

@@ -267,7 +267,13 @@ tete_status tete_set_bunch(tete_grid* g, const tete_bunch* b);
 tete_status tete_clear_bunch(tete_grid* g);
 
 /* Diagnostics recorded during tete_step: every > 0 records W^{n,e} of y^n
- * (Sec. 4.4) before each step n with n % every == 0; 0 disables. */
+ * (Sec. 4.4) before each step n with n % every == 0; 0 disables.  On vacuum
+ * grids without witness lines or TETE_F_SKIP_STATIC, a launch of the two-step
+ * kernel takes the samples of its input y^n and of y^{n+1} itself (FP64 sums
+ * of the same terms in another order: equal to the energy kernel's to
+ * rounding), so samples do not break the pairing of steps; otherwise a sample
+ * is a separate pass over the state and a sample at n+1 leaves step n
+ * single. */
 tete_status tete_set_diagnostics(tete_grid* g, int32_t every);
 
 /* e_z probes recorded after every step (e_z^{n+1/2}); idx are HOST array

@@ -23,11 +23,15 @@ constexpr size_t kAlign = 256;
 size_t up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t lam, wacc, wit, wmid, partial, scal, pidx, eser, pser, code, field[12], mat[6], imp[4], imp_le, imp_lh,
+    size_t lam, wacc, wit, wmid, partial, epart, scal, pidx, eser, pser, code, field[12], mat[6], imp[4], imp_le, imp_lh,
         imp_cnt, skip[2], skip_act[2], cls, ctab, craw, total;
 };
 
 int64_t series_cap(const tete_grid_desc* d) { return d->max_series > 0 ? d->max_series : 4096; }
+
+// Workgroups whose energy partial sums a two-step launch can keep (energy
+// samples taken inside two-step launches; larger launches sample apart).
+enum { EN_PARTS = 65536 };
 
 // Tiles of the finest tiling of the two-step kernel and of the materials step.
 int64_t skip_cap(Geo g) { return std::max(fused2_tile_cap(g), fused_tile_cap(g)); }
@@ -42,6 +46,7 @@ bool make_layout(const tete_grid_desc* d, Layout* L)
     L->wit = o;     o = up(o + sizeof(double) * TETE_WITNESS_LINES * TETE_MAX_WAKE);
     L->wmid = o;    o = up(o + rb * TETE_WITNESS_LINES * (size_t)d->nz);
     L->partial = o; o = up(o + sizeof(double) * 2 * RED_BLOCKS);
+    L->epart = o;   o = up(o + sizeof(double) * 2 * EN_PARTS);
     L->scal = o;    o = up(o + sizeof(double) * 64);
     L->pidx = o;    o = up(o + sizeof(int64_t) * TETE_MAX_PROBES);
     L->eser = o;    o = up(o + sizeof(double) * (size_t)series_cap(d));
@@ -139,7 +144,7 @@ struct tete_grid {
     // sticky error state: TETE_ERR_NONFINITE once a read-out found NaN or
     // Inf, until tete_set_fields; tete_step refuses to run meanwhile
     tete_status err;
-    double *lam, *wacc, *partial, *scal, *eser, *pser;
+    double *lam, *wacc, *partial, *epart, *scal, *eser, *pser;
     double* wit;       // witness accumulators, TETE_WITNESS_LINES x TETE_MAX_WAKE
     void* wmid;        // e_z^{n+1/2} of the witness lines in a two-step launch (TETE_WITNESS_LINES x nz)
     int witness;       // witness lines armed (tete_set_witness)
@@ -357,16 +362,25 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
     const bool two = use_fused2(g);
     // Yee grids: two steps per launch unless the tuning asks for single steps
     const bool two_yee = g->yee && g->tune.kernel != TETE_KERNEL_FUSED && yee2_fits(g->geo, g->fp32 ? 4 : 8);
+    // energy samples inside two-step launches: vacuum grids without witness
+    // lines or static-tile lists, launches of at most EN_PARTS workgroups
+    int64_t en_blocks = 0;
+    const bool en_fuse = two && g->diag_every > 0 && !g->mat_set && !(g->witness && g->has_bunch) && !g->skip &&
+                         (en_blocks = fused2_blocks<R>(g->geo, fused2_xchunk(g), g->tune.order)) > 0 &&
+                         en_blocks <= EN_PARTS;
     for (int64_t s = 0; s < nsteps; ++s) {
-        if (g->diag_every > 0 && g->n % g->diag_every == 0) {
+        const bool at_n = g->diag_every > 0 && g->n % g->diag_every == 0;
+        const bool at_n1 = g->diag_every > 0 && (g->n + 1) % g->diag_every == 0;
+        // two steps at once unless the state after the first is observed
+        // (an energy sample of it is taken inside the launch where it can be)
+        const bool wit = g->witness && g->has_bunch;
+        const bool pair = (two || two_yee) && s + 1 < nsteps && g->nprobe == 0 && (!at_n1 || en_fuse);
+        const bool en_pair = pair && en_fuse && (at_n || at_n1);
+        if (at_n && !en_pair) {
             HIPCHK(launch_energy<R>(fields<R>(g, g->cur), M, g->geo, g->alpha, rweight(g), g->partial, g->eser + g->ecount,
                                     g->stream));
             g->ecount++;
         }
-        // two steps at once unless the state after the first is observed
-        const bool wit = g->witness && g->has_bunch;
-        const bool pair = (two || two_yee) && s + 1 < nsteps && g->nprobe == 0 &&
-                          !(g->diag_every > 0 && (g->n + 1) % g->diag_every == 0);
         hipEvent_t* ev = nullptr;
         if (g->timing) {
             if (g->ev_steps >= g->ev_cap) return TETE_ERR_STATE;
@@ -393,10 +407,12 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
                 if (wit) HIPCHK(launch_zero_bytes(g->wmid, (g->fp32 ? 4 : 8) * (size_t)TETE_WITNESS_LINES * g->d.nz,
                                                   g->stream));
             }
+            EnergyPair en = {(at_n ? 1 : 0) | (at_n1 ? 2 : 0), g->alpha, g->epart, EN_PARTS, g->eser + g->ecount};
             HIPCHK(launch_step_fused2<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                          source(g, g->n), wit ? &wm : nullptr, fused2_rows(g), g->tune.depth,
-                                         fused2_xchunk(g),
-                                         g->tune.order, g->stream, ev, act, g->skip_nact[0]));
+                                         fused2_xchunk(g), g->tune.order, g->stream, ev, act, g->skip_nact[0],
+                                         en_pair ? &en : nullptr));
+            if (en_pair) g->ecount += (at_n ? 1 : 0) + (at_n1 ? 1 : 0);
             g->skip_live = 1;
             if (wit)   // e_z^{n-1/2} in the old set, e_z^{n+1/2} in wm.mid, e_z^{n+3/2} in the new set
                 HIPCHK(launch_witness2<R>((const R*)g->f[g->cur][2], wm.mid, (const R*)g->f[1 - g->cur][2],
@@ -604,6 +620,7 @@ tete_status tete_grid_create(const tete_grid_desc* d, void* dev_ws, size_t ws_by
     g->wit = (double*)(g->ws + L.wit);
     g->wmid = g->ws + L.wmid;
     g->partial = (double*)(g->ws + L.partial);
+    g->epart = (double*)(g->ws + L.epart);
     g->scal = (double*)(g->ws + L.scal);
     g->pidx = (int64_t*)(g->ws + L.pidx);
     g->eser = (double*)(g->ws + L.eser);

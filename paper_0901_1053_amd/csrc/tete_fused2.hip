@@ -201,12 +201,27 @@ template <typename R>
 struct Arr6 {
     const R* m[6];
 };
+// EN: the energy W^{n,e} of Sec. 4.4 of the launch's input state y^n (from
+// stage A's input, eo.want bit 0) and of y^{n+1} (from stage B's input, bit
+// 1), summed in FP64 over the entries the tile owns and written as the
+// workgroup's two partial sums eo.part[2 b], eo.part[2 b + 1].  Each term of
+// an entry is taken where the stage holds its operands: e_z and h_x (with
+// e_z at j+1 and e_y at k+1) at the input plane, h_y (e_z at i+1, e_x at k+1)
+// one plane behind, e_x, e_y and h_z (h_z at j-1 and at i-1) two behind; the
+// terms are those of the energy kernel, in another summation order.
+struct EnOut {
+    double* part;
+    int want;
+    double a;
+};
 template <typename R, int TYH, int NB, int LW, int PD, bool WIT = false, bool CLS = false, bool ARR = false,
-          class LDS>
+          class LDS, bool EN = false>
 __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, const int tz, const int cx, LDS& L,
-                                            const WitMid<R>& wm = WitMid<R>{}, const Arr6<R>& MA = Arr6<R>{})
+                                            const WitMid<R>& wm = WitMid<R>{}, const Arr6<R>& MA = Arr6<R>{},
+                                            const EnOut& eo = EnOut{})
 {
     static_assert(!(ARR && (CLS || WIT)), "one material source per instance");
+    static_assert(!(EN && (ARR || CLS || WIT)), "energy with vacuum coefficients only");
     constexpr int TY = TYH - 6;   // rows owned
     constexpr int KT2 = LW - 4;   // entries owned per row
     // Lane shifts act on the whole wave; with two rows per wave (LW = 32) the
@@ -414,6 +429,56 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
 #pragma unroll
     for (int d = 0; d < PD; ++d) load_plane(xs - 4 + d, buf[d]);
 
+    // energy partial sums of y^n and y^{n+1} (EN)
+    double accA = 0.0, accB = 0.0;
+    // the vacuum coefficients folded into the terms' factors: 1/(2 kappa) and
+    // 1/(2 mu) for the squares, a^2 kappa / 2 and a^2 mu / 2 for the
+    // differences (a product per term instead of a division; the terms then
+    // differ from the energy kernel's by rounding)
+    const double ea = eo.a, ha2 = 0.5 * ea * ea;
+    const double skx = 0.5 / (double)A.kx, sky = 0.5 / (double)A.ky, skz = 0.5 / (double)A.kz;
+    const double smx = 0.5 / (double)A.mx, smy = 0.5 / (double)A.my, smz = 0.5 / (double)A.mz;
+    const double dkx = ha2 * (double)A.kx, dky = ha2 * (double)A.ky, dmx = ha2 * (double)A.mx,
+                 dmy = ha2 * (double)A.my;
+    // one stage's energy terms: input c at plane q with PEC code cq, carried
+    // state S (before the stage rotates it), j-neighbours nb, codes of planes
+    // q-1 .. q-4 in hist
+    auto en_terms = [&](const In<R>& c, const Stage<R>& S, const Nb<R>& nb, const uint32_t cq, const uint32_t hist,
+                        const int q) {
+        const R eyk = lane_next(c.ey), exk = lane_next(S.EXm1);   // e_y(k+1) at q, e_x(k+1) at q-1
+        double e = 0.0;
+        if (!owned) return e;
+        if (xown(q)) {
+            if (!(cq & 4u)) {                                   // e_z
+                const double v = (double)c.ez;
+                e += v * v * skz;
+            }
+            if (hx_jk) {                                        // h_x
+                const double h = (double)c.hx, d = (double)nb.ez0_jp - (double)c.ez;
+                e += h * h * smx - dmx * (d * d) + ea * (h * ((double)eyk - (double)c.ey));
+            }
+        }
+        if (xown(q - 1) && hy_k && q - 1 < g.nx) {                 // h_y
+            const double h = (double)S.HYm1, d = (double)c.ez - (double)S.EZm1;
+            e += h * h * smy - dmy * (d * d) - ea * (h * ((double)exk - (double)S.EXm1));
+        }
+        if (xown(q - 2)) {
+            if (!((hist >> 4) & 1u)) {                            // e_x
+                const double v = (double)S.EXm2, d = (double)nb.hz2_jm - (double)S.HZm2;
+                e += v * v * skx - dkx * (d * d);
+            }
+            if (!((hist >> 5) & 1u)) {                            // e_y
+                const double v = (double)S.EYm2, d = (double)S.HZm3 - (double)S.HZm2;
+                e += v * v * sky - dky * (d * d);
+            }
+            if (hz_j && q - 2 < g.nx) {                           // h_z
+                const double h = (double)S.HZm2;
+                e += h * h * smz;
+            }
+        }
+        return e;
+    };
+
     const int pend = xe + 7;
     auto body = [&](const int p, const PR& cur, PR& nxt) {
         load_plane(p + PD, nxt);
@@ -488,7 +553,15 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
             injB = (srcB && src_k) ? inject(A.src.n + 1, sel(ch, 18, kzB)) : R(0);
         }
 
+        if constexpr (EN) {      // y^n: stage A's input, before the stage rotates its state
+            if (eo.want & 1)
+                accA += en_terms(In<R>{cur.ex, cur.ey, cur.ez, cur.hx, cur.hy, cur.hz}, SA, nA, c0, ch, p);
+        }
         const Out<R> oA = stage_plane(SA, In<R>{cur.ex, cur.ey, cur.ez, cur.hx, cur.hy, cur.hz}, nA, fA, injA);
+        if constexpr (EN) {      // y^{n+1}: stage B's input at plane p-4 (its e_x is stage A's S9 above)
+            if (eo.want & 2)
+                accB += en_terms(In<R>{oA.ex14, bEY, bEZ, bHX, bHY, bHZ}, SB, nB, (ch >> 12) & 7u, ch >> 16, p - 4);
+        }
         const Out<R> oB = stage_plane(SB, In<R>{oA.ex14, bEY, bEZ, bHX, bHY, bHZ}, nB, fB, injB);
 
         if (srcA) ezA = oA.ezold1;
@@ -555,6 +628,29 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
 #pragma unroll
         for (int u = 0; u <= PD; ++u) body(p + u, buf[u], buf[(u + PD) % (PD + 1)]);
     }
+    if constexpr (EN) {
+        // the workgroup's two sums: waves by shuffles, then the waves in order
+        constexpr int NW = TYH * LW / 64;
+        __shared__ double ered[2][NW];
+        for (int off = 32; off > 0; off >>= 1) {
+            accA += __shfl_down(accA, off, 64);
+            accB += __shfl_down(accB, off, 64);
+        }
+        if ((tid & 63) == 0) {
+            ered[0][tid >> 6] = accA;
+            ered[1][tid >> 6] = accB;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double sa = 0.0, sb = 0.0;
+            for (int w = 0; w < NW; ++w) {
+                sa += ered[0][w];
+                sb += ered[1][w];
+            }
+            eo.part[2 * blockIdx.x] = sa;
+            eo.part[2 * blockIdx.x + 1] = sb;
+        }
+    }
 }
 
 // Tile of workgroup blockIdx.x.  act (or null): the tiles that are not
@@ -584,6 +680,25 @@ __global__ __launch_bounds__(TYH * LW) void k_fused2(FArgs<R> A, const int* act)
     int ty, tz, cx;
     if (!fused2_tile_of(A, act, ty, tz, cx)) return;   // whole group
     fused2_tile<R, S::rows, S::nb, S::lw, PD>(A, ty, tz, cx, L);
+}
+
+// The two-step kernel that also sums the energy of its input and of the
+// state between its two steps (16 rows of 32 lanes, vacuum coefficients, the
+// full tiling: one pair of partial sums per workgroup, zero for the padding
+// workgroups of the blocked tile orders).
+template <typename R, int TYH, int LW, int PD>
+__global__ __launch_bounds__(TYH * LW) void k_fused2_en(FArgs<R> A, EnOut eo)
+{
+    typedef Shape2<R, TYH, LW> S;
+    typedef Lds2<R, S::rows, S::nb, S::lw> LT;
+    __shared__ LT L;
+    int ty, tz, cx;
+    if (!fused2_tile_of(A, nullptr, ty, tz, cx)) {      // whole group
+        if (threadIdx.x == 0) eo.part[2 * blockIdx.x] = eo.part[2 * blockIdx.x + 1] = 0.0;
+        return;
+    }
+    fused2_tile<R, S::rows, S::nb, S::lw, PD, false, false, false, LT, true>(A, ty, tz, cx, L, WitMid<R>{},
+                                                                               Arr6<R>{}, eo);
 }
 
 // The two-step kernel with per-entry materials (FP32: 16 rows of 32 lanes,
@@ -803,10 +918,40 @@ void run_fused2(const FArgs<R>& A, const int* act, int nact, hipStream_t s)
 }
 
 template <typename R>
+int64_t fused2_blocks(Geo g, int xchunk, int order)
+{
+    Fields<R> none = {};
+    Mat<R> M = {};
+    FArgs<R> A = fused_args<R>(none, none, M, g, R(0), Src{});
+    if (!fused2_setup<R>(A, 16, xchunk, order, 32)) return -1;
+    return A.nblk;
+}
+
+template <typename R>
 hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alpha, Src src, const WitMid<R>* wm,
                               int rows, int depth, int xchunk, int order, hipStream_t s, hipEvent_t* ev,
-                              const int* act, int nact)
+                              const int* act, int nact, const EnergyPair* en)
 {
+    if (en && en->want) {
+        // energy samples: the default shape over the full tiling, vacuum
+        FArgs<R> A = fused_args<R>(o, nf, M, g, alpha, src);
+        // 16 rows of 32 lanes: 512 threads, whose VGPRs hold the sums'
+        // operands (FP32 two planes ahead, FP64 one)
+        if (wm || act || A.cls || M.arr[0] || !fused2_setup<R>(A, 16, xchunk, order, 32)) return hipErrorInvalidValue;
+        if (A.nblk > en->cap) return hipErrorInvalidValue;
+        hipError_t e;
+        if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+        constexpr int EPD = sizeof(R) == 4 ? 2 : 1;   // FP64: one plane ahead fits the VGPRs
+        k_fused2_en<R, 16, 32, EPD><<<A.nblk, 16 * 32, 0, s>>>(A, EnOut{en->part, en->want, en->alpha});
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+        int slot = 0;
+        for (int b = 0; b < 2; ++b)
+            if (en->want & (1 << b))
+                if ((e = launch_sum(en->part + b, A.nblk, 2, en->out + slot++, s)) != hipSuccess) return e;
+        if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+        return hipSuccess;
+    }
     FArgs<R> A = fused_args<R>(o, nf, M, g, alpha, src);
     if (wm) rows = 0;   // the instance that keeps witness lines has the default shape only
     if (A.cls) {        // materials by class: the class instance's one shape, no witness lines
@@ -883,7 +1028,9 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
     template hipError_t launch_batch_step2<R>(BatchTable<R>*, int, int, int, hipStream_t);                     \
     template bool fused2_setup<R>(FArgs<R>&, int, int, int, int);                                              \
     template hipError_t launch_step_fused2<R>(Fields<R>, Fields<R>, Mat<R>, Geo, R, Src, const WitMid<R>*, int, \
-                                              int, int, int, hipStream_t, hipEvent_t*, const int*, int);     \
+                                              int, int, int, hipStream_t, hipEvent_t*, const int*, int,      \
+                                              const EnergyPair*);                                            \
+    template int64_t fused2_blocks<R>(Geo, int, int);                                                         \
     template hipError_t fused2_static_tiles<R>(const uint8_t*, Geo, int, int, int, uint8_t*, int*, int64_t,    \
                                                int64_t*, int*, hipStream_t);
 TETE_FUSED2_INST(float)

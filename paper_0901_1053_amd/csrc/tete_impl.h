@@ -174,14 +174,33 @@ bool fused2_fits(Geo g, int real_bytes);
 // rows: 0 (default), 16, or 24 or 32 (FP32 only: rows of 32 lanes).
 template <typename R>
 bool fused2_setup(FArgs<R>& A, int rows, int xchunk, int order, int lanes = 0);
+// Energy samples taken by a two-step launch: want bit 0 the energy of its
+// input y^n, bit 1 that of y^{n+1}; written to out[0], out[1] (only the ones
+// wanted, in that order); part: cap pairs of FP64 partial sums.
+struct EnergyPair {
+    int want;
+    double alpha;
+    double* part;
+    int64_t cap;
+    double* out;
+};
 // wm (or nullptr): the witness lines whose e_z^{n+1/2} the launch keeps;
 // act (or nullptr): the nact active tiles of fused2_static_tiles for the same
 // rows (0 with wm), xchunk and order; the launch takes only these (none if
-// nact is 0), and with wm stores witness values only in them
+// nact is 0), and with wm stores witness values only in them; en (or
+// nullptr, or want 0): energy samples, with vacuum coefficients only, in
+// their own shape (16 rows of 32 lanes; the rows and depth asked for do not
+// apply; hipErrorInvalidValue otherwise, or when the launch has more
+// workgroups than en->cap)
 template <typename R>
 hipError_t launch_step_fused2(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, R alpha, Src src,
                               const WitMid<R>* wm, int rows, int depth, int xchunk, int order, hipStream_t s,
-                              hipEvent_t* ev, const int* act, int nact);
+                              hipEvent_t* ev, const int* act, int nact, const EnergyPair* en = nullptr);
+// workgroups of a two-step launch that takes energy samples
+template <typename R>
+int64_t fused2_blocks(Geo g, int xchunk, int order);
+// out[0] = sum of part[t * stride], t < n, in a fixed order (FP64)
+hipError_t launch_sum(const double* part, int n, int stride, double* out, hipStream_t s);
 // One byte per tile of the two-step kernel's tiling (rows, xchunk) in tab: 1
 // where every entry the tile loads has its three e edges PEC, so that a step
 // leaves the tile's entries unchanged; and in act the *nact other tiles in the

@@ -1039,6 +1039,12 @@ hipError_t launch_energy(Fields<R> f, Mat<R> mat, Geo g, double alpha, double rw
     return hipGetLastError();
 }
 
+hipError_t launch_sum(const double* part, int n, int stride, double* out, hipStream_t s)
+{
+    k_finish<false><<<1, RED_THREADS, 0, s>>>(part, n, stride, out);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_charges(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, double alpha, Src src, double* partial,
                           double* out, hipStream_t s)

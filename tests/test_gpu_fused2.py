@@ -1,11 +1,12 @@
 """The two-step (temporally blocked) fused kernel: two steps per launch must give
 exactly the fields and wake of two single fused steps, for every launch shape
 (tile and chunk boundaries everywhere, the bunch line on and off tile edges),
-with diagnostics that force single steps in between, and within the FP32
-tolerance of the FP64 oracle."""
+with probes that force single steps in between and energy samples taken inside
+the paired launches, and within the FP32 tolerance of the FP64 oracle."""
 import numpy as np
 import pytest
 
+from oracle import oracle as O
 from paper_0901_1053_amd import inputs, tete
 from tests import parity as P
 
@@ -86,16 +87,22 @@ def test_wake_within_tolerance_of_oracle():
     assert P.delta_norm(W, ref["W"]) <= 1e-5
 
 
-def test_diagnostics_force_single_steps():
-    """An energy sample every 3 steps (odd, so pairs must break) and, in a
-    second run, probes every step: the series equal those of single steps."""
+def test_diagnostics_and_single_steps():
+    """An energy sample every 3 steps (odd: the paired launches take the
+    samples between their two steps) and, in a second run, probes every step
+    (single steps): fields, wake and probes equal those of single steps
+    bitwise, the energy series to the rounding of its FP64 sums (the paired
+    launch adds the same terms in another order)."""
     case = inputs.scaled_wake_case(24, 100, seed=4, sigma_dz=3.0)
     jmin, nw = -case.M, 2 * case.M + 20
     steps = 40
     a = _wake_run(case, "fused2", steps, jmin, nw, diag=3)
     b = _wake_run(case, "fused", steps, jmin, nw, diag=3)
-    assert np.array_equal(a.energy_series(), b.energy_series())
+    ea, eb = a.energy_series(), b.energy_series()
+    assert len(ea) == len(eb) == 14
+    assert np.max(np.abs(ea - eb)) <= 1e-13 * np.max(np.abs(eb))
     assert np.array_equal(a.wake(), b.wake())
+    _same(a.get_fields(), b.get_fields())
     idx = np.array([5, 1000, 20000], dtype=np.int64)
     a = _wake_run(case, "fused2", steps, jmin, nw, probes=idx)
     b = _wake_run(case, "fused", steps, jmin, nw, probes=idx)
@@ -180,3 +187,43 @@ def test_fp32_other_shapes(rows, depth, xchunk):
     b = _wake_run(case, "fused", steps, jmin, nw)
     assert np.array_equal(a.wake(), b.wake())
     _same(a.get_fields(), b.get_fields())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("diag", [1, 2, 3, 5])
+def test_energy_samples_in_paired_launches(precision, diag):
+    """Energy samples taken inside the two-step launches (of y^n from the
+    first stage's input, of y^{n+1} from the second's): every sample against
+    the oracle's energy within 1e-12 (FP64) / 1e-5 (FP32) of the largest, and
+    against the energy kernel between single steps to its FP64 rounding; the
+    fields bitwise those of single steps.  Random fields, obstacles and a
+    bunch on a ragged grid, every x-chunk boundary and an odd step count."""
+    print("energy in pairs", precision, diag, flush=True)
+    nx, ny, nz = 23, 17, 71
+    g = O.Geom(nx, ny, nz, 2.0e-3, 1.7e-3, 1.0e-3, 1.0e-3)         # c dt = dz: the bunch moves at c
+    cells = inputs.random_cells(nx, ny, nz, 91, frac=0.08)
+    m = O.vacuum_materials(g, cells)
+    f0 = inputs.random_fields((nx + 1, ny + 1, nz + 1), 92)
+    steps = 23
+    res = []
+    for kernel, xchunk in (("fused2", 0), ("fused2", 5), ("fused", 0)):
+        G = tete.Grid(nx, ny, nz, g.dx, g.dy, g.dz, g.cdt, precision=precision, max_series=64)
+        G.set_pec_cells(cells)
+        G.set_tuning(kernel, 0, xchunk, 0, 0)
+        G.set_fields(f0)
+        G.set_bunch(1e-9, 2e-3, 11, 8, 10, -12, 40)
+        G.set_diagnostics(diag)
+        G.step(steps)
+        res.append((G.energy_series(), G.get_fields()))
+        G.close()
+    ref = {k: v.copy() for k, v in f0.items()}
+    O.apply_pec(g, m, ref)
+    b = O.Bunch(Q=1e-9, sigma=2e-3, i0=11, j0=8, M=10, jmin=-12, nw=40)
+    e_ref = np.array(O.run(g, m, ref, steps, bunch=b, want_energy=True)["energy"])[::diag]
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    scale = np.max(np.abs(e_ref))
+    for e, f in res:
+        assert len(e) == len(e_ref)
+        assert np.max(np.abs(e - e_ref)) <= tol * scale
+        assert np.max(np.abs(e - res[2][0])) <= 1e-13 * scale
+        _same(f, res[2][1])
