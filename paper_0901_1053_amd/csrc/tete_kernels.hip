@@ -15,6 +15,7 @@
 
 #include <algorithm>
 
+#include "tete_dev.h"
 #include "tete_impl.h"
 
 namespace tete {
@@ -369,50 +370,115 @@ __device__ __forceinline__ double ldd(const R* p, const Geo& g, int i, int j, in
 //   + a [sum_hx h_x P_z e_y - sum_hy h_y P_z e_x]
 // With rw = 0 the a^2 terms drop: the energy of the implicit scheme (16),
 // whose Q = B - alpha A holds no transverse operator.
+//
+// Work decomposition: a work item is a tile of EN_ROWS rows (j, one wave each)
+// by 63 entries (k) and a chunk of xc planes, marched along x; workgroup b
+// takes items b, b + gridDim.x, ...  Each lane loads its entry's six values,
+// its PEC code and the two j-neighbours the terms need (h_z at j-1, e_z at
+// j+1), two planes ahead.  The k-neighbour (e_x, e_y at k+1) is the next lane
+// (lane 63 only supplies it), the x-neighbours are the planes before and
+// after in registers: every value is read from HBM about once and no index is
+// divided per entry.  In vacuum 1/kappa and 1/mu are formed once.  The sums
+// are per lane in plane order, then per workgroup and finished in a fixed
+// order, so the result does not depend on timing.
+constexpr int EN_ROWS = RED_THREADS / 64;
+constexpr int EN_KT = 63;
+
 template <typename R>
-__global__ __launch_bounds__(RED_THREADS) void k_energy(Fields<R> f, Mat<R> M, Geo g, double a, double rw,
-                                                        double* partial)
+struct EnPlane {
+    R ex, ey, ez, hx, hy, hz, hz_jm, ez_jp;
+    uint32_t c;
+};
+
+template <typename R>
+__global__ __launch_bounds__(RED_THREADS) void k_energy(Fields<R> f, Mat<R> M, Geo g, double a, double rw, int nyt,
+                                                        int nzt, int xc, int items, double* partial)
 {
     const R *ex = f.c[0], *ey = f.c[1], *ez = f.c[2], *hx = f.c[3], *hy = f.c[4], *hz = f.c[5];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // vacuum reciprocals (per-entry arrays divide per entry)
+    const double ik[3] = {1.0 / (double)M.k[0], 1.0 / (double)M.k[1], 1.0 / (double)M.k[2]};
+    const double im[3] = {1.0 / (double)M.m[0], 1.0 / (double)M.m[1], 1.0 / (double)M.m[2]};
+    const double ra2 = 0.5 * rw * a * a;
     double acc = 0.0;
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < g.np; idx += gridDim.x * blockDim.x) {
-        int i, j, k;
-        decomp(idx, g, i, j, k);
-        double sq = 0.0, r = 0.0, lc = 0.0;
-        double kx = (double)kap(M, 0, idx), ky = (double)kap(M, 1, idx), kz = (double)kap(M, 2, idx);
-        if (kx > 0.0) {
-            double e = ex[idx], d = ldd(hz, g, i, j - 1, k) - (double)hz[idx];
-            sq += e * e / kx;
-            r += kx * d * d;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        const int tz = it % nzt, q = it / nzt, ty = q % nyt, cx = q / nyt;
+        const int j = ty * EN_ROWS + w, k = tz * EN_KT + lane;
+        const bool node = j <= g.ny && k <= g.nz;
+        const bool own = node && lane < EN_KT;
+        const int roff = k + j * g.sz;
+        const int xs = cx * xc, xe = min(xs + xc, g.nx + 1);
+        auto load = [&](int i, EnPlane<R>& d) {
+            const bool ok = node && i >= 0 && i <= g.nx;
+            const int id = roff + i * g.sp;
+            d.ex = ok ? ex[id] : R(0);
+            d.ey = ok ? ey[id] : R(0);
+            d.ez = ok ? ez[id] : R(0);
+            d.hx = ok ? hx[id] : R(0);
+            d.hy = ok ? hy[id] : R(0);
+            d.hz = ok ? hz[id] : R(0);
+            d.hz_jm = ok && j >= 1 ? hz[id - g.sz] : R(0);
+            d.ez_jp = ok && j < g.ny ? ez[id + g.sz] : R(0);
+            d.c = ok && M.code ? (uint32_t)M.code[id] : 0u;
+        };
+        // kappa of e component c and mu of h component c at entry id
+        auto kapc = [&](int c, uint32_t code, int id) {
+            return M.arr[c] ? (double)M.arr[c][id] : (((code >> c) & 1u) ? 0.0 : (double)M.k[c]);
+        };
+        auto muc = [&](int c, int id) { return M.arr[3 + c] ? (double)M.arr[3 + c][id] : (double)M.m[c]; };
+        // v^2 / kappa (or / mu): the vacuum reciprocal, else a division
+        auto sqk = [&](double v, double kv, int c) { return M.arr[c] ? v * v / kv : v * v * ik[c]; };
+        auto sqm = [&](double v, double mv, int c) { return M.arr[3 + c] ? v * v / mv : v * v * im[c]; };
+
+        EnPlane<R> cur, nxt;
+        load(xs, cur);
+        load(xs + 1, nxt);
+        R hz_im = (node && xs >= 1) ? hz[roff + (xs - 1) * g.sp] : R(0);   // h_z at plane i-1
+        for (int i = xs; i < xe; ++i) {
+            EnPlane<R> n2;
+            load(i + 2, n2);
+            // k-neighbours from the next lane, with every lane active
+            const double eyk = (double)lane_next(cur.ey), exk = (double)lane_next(cur.ex);
+            if (own) {
+                const int id = roff + i * g.sp;
+                double sq = 0.0, r = 0.0, lc = 0.0;
+                const double kx = kapc(0, cur.c, id), ky = kapc(1, cur.c, id), kz = kapc(2, cur.c, id);
+                const double hzv = (double)cur.hz;
+                if (kx > 0.0) {
+                    const double d = (double)cur.hz_jm - hzv;
+                    sq += sqk((double)cur.ex, kx, 0);
+                    r += kx * d * d;
+                }
+                if (ky > 0.0) {
+                    const double d = (double)hz_im - hzv;
+                    sq += sqk((double)cur.ey, ky, 1);
+                    r += ky * d * d;
+                }
+                if (kz > 0.0) sq += sqk((double)cur.ez, kz, 2);
+                if (j < g.ny && k < g.nz) {                       // h_x
+                    const double mu = muc(0, id), h = (double)cur.hx;
+                    if (mu > 0.0) sq += sqm(h, mu, 0);
+                    const double d = (double)cur.ez_jp - (double)cur.ez;
+                    r += mu * d * d;
+                    lc += h * (eyk - (double)cur.ey);
+                }
+                if (i < g.nx && k < g.nz) {                       // h_y
+                    const double mu = muc(1, id), h = (double)cur.hy;
+                    if (mu > 0.0) sq += sqm(h, mu, 1);
+                    const double d = (double)nxt.ez - (double)cur.ez;
+                    r += mu * d * d;
+                    lc -= h * (exk - (double)cur.ex);
+                }
+                if (i < g.nx && j < g.ny) {                       // h_z
+                    const double mu = muc(2, id);
+                    if (mu > 0.0) sq += sqm(hzv, mu, 2);
+                }
+                acc += 0.5 * sq - ra2 * r + a * lc;
+            }
+            hz_im = cur.hz;
+            cur = nxt;
+            nxt = n2;
         }
-        if (ky > 0.0) {
-            double e = ey[idx], d = ldd(hz, g, i - 1, j, k) - (double)hz[idx];
-            sq += e * e / ky;
-            r += ky * d * d;
-        }
-        if (kz > 0.0) {
-            double e = ez[idx];
-            sq += e * e / kz;
-        }
-        if (hx_ok(g, i, j, k)) {
-            double mu = (double)muv(M, 0, idx), h = hx[idx];
-            if (mu > 0.0) sq += h * h / mu;
-            double d = ldd(ez, g, i, j + 1, k) - (double)ez[idx];
-            r += mu * d * d;
-            lc += h * (ldd(ey, g, i, j, k + 1) - (double)ey[idx]);
-        }
-        if (hy_ok(g, i, j, k)) {
-            double mu = (double)muv(M, 1, idx), h = hy[idx];
-            if (mu > 0.0) sq += h * h / mu;
-            double d = ldd(ez, g, i + 1, j, k) - (double)ez[idx];
-            r += mu * d * d;
-            lc -= h * (ldd(ex, g, i, j, k + 1) - (double)ex[idx]);
-        }
-        if (hz_ok(g, i, j, k)) {
-            double mu = (double)muv(M, 2, idx), h = hz[idx];
-            if (mu > 0.0) sq += h * h / mu;
-        }
-        acc += 0.5 * sq - 0.5 * rw * a * a * r + a * lc;
     }
     double s = block_reduce<false>(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -1032,10 +1098,19 @@ template <typename R>
 hipError_t launch_energy(Fields<R> f, Mat<R> mat, Geo g, double alpha, double rw, double* partial, double* out,
                          hipStream_t s)
 {
-    k_energy<R><<<RED_BLOCKS, RED_THREADS, 0, s>>>(f, mat, g, alpha, rw, partial);
+    // tiles of EN_ROWS x EN_KT entries; chunks of at least 32 planes, short
+    // enough that each workgroup takes about 16 work items
+    const int nyt = (g.ny + 1 + EN_ROWS - 1) / EN_ROWS, nzt = (g.nz + 1 + EN_KT - 1) / EN_KT;
+    const int64_t tiles = (int64_t)nyt * nzt, planes = g.nx + 1;
+    int64_t xc = (planes * tiles + 16 * RED_BLOCKS - 1) / (16 * RED_BLOCKS);
+    xc = std::min<int64_t>(std::max<int64_t>(xc, 32), planes);
+    const int64_t items = tiles * ((planes + xc - 1) / xc);
+    if (items > 0x7fffffff) return hipErrorInvalidValue;
+    const int grid = (int)std::min<int64_t>(items, RED_BLOCKS);
+    k_energy<R><<<grid, RED_THREADS, 0, s>>>(f, mat, g, alpha, rw, nyt, nzt, (int)xc, (int)items, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_finish<false><<<1, RED_THREADS, 0, s>>>(partial, RED_BLOCKS, 1, out);
+    k_finish<false><<<1, RED_THREADS, 0, s>>>(partial, grid, 1, out);
     return hipGetLastError();
 }
 
