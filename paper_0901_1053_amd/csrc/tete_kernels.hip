@@ -373,16 +373,18 @@ __device__ __forceinline__ double ldd(const R* p, const Geo& g, int i, int j, in
 //
 // Work decomposition: a work item is a tile of EN_ROWS rows (j, one wave each)
 // by 63 entries (k) and a chunk of xc planes, marched along x; workgroup b
-// takes items b, b + gridDim.x, ...  Each lane loads its entry's six values,
-// its PEC code and the two j-neighbours the terms need (h_z at j-1, e_z at
-// j+1), two planes ahead.  The k-neighbour (e_x, e_y at k+1) is the next lane
-// (lane 63 only supplies it), the x-neighbours are the planes before and
-// after in registers: every value is read from HBM about once and no index is
-// divided per entry.  In vacuum 1/kappa and 1/mu are formed once.  The sums
-// are per lane in plane order, then per workgroup and finished in a fixed
-// order, so the result does not depend on timing.
-constexpr int EN_ROWS = RED_THREADS / 64;
+// takes items b, b + gridDim.x, ...  Each lane loads its entry's six values
+// and its PEC code two planes ahead.  The k-neighbour (e_x, e_y at k+1) is the
+// next lane (lane 63 only supplies it), the j-neighbours (h_z at j-1, e_z at
+// j+1) come through LDS from the neighbouring waves (the tile's first and last
+// rows load theirs), and the x-neighbours are the planes before and after in
+// registers: every value is read from HBM about once and no index is divided
+// per entry.  In vacuum 1/kappa and 1/mu are formed once.  The sums are per
+// lane in plane order, then per workgroup and finished in a fixed order, so
+// the result does not depend on timing.
+constexpr int EN_ROWS = 8;
 constexpr int EN_KT = 63;
+constexpr int EN_THREADS = 64 * EN_ROWS;
 
 template <typename R>
 struct EnPlane {
@@ -391,9 +393,13 @@ struct EnPlane {
 };
 
 template <typename R>
-__global__ __launch_bounds__(RED_THREADS) void k_energy(Fields<R> f, Mat<R> M, Geo g, double a, double rw, int nyt,
-                                                        int nzt, int xc, int items, double* partial)
+__global__ __launch_bounds__(EN_THREADS) void k_energy(Fields<R> f, Mat<R> M, Geo g, double a, double rw, int nyt,
+                                                       int nzt, int xc, int items, double* partial)
 {
+    // h_z and e_z of the plane being summed, by plane parity (one barrier per
+    // plane: a buffer is rewritten two planes later, after the next barrier)
+    __shared__ R sHZ[2][EN_ROWS][64], sEZ[2][EN_ROWS][64];
+    __shared__ double red[EN_ROWS];
     const R *ex = f.c[0], *ey = f.c[1], *ez = f.c[2], *hx = f.c[3], *hy = f.c[4], *hz = f.c[5];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // vacuum reciprocals (per-entry arrays divide per entry)
@@ -408,18 +414,31 @@ __global__ __launch_bounds__(RED_THREADS) void k_energy(Fields<R> f, Mat<R> M, G
         const bool own = node && lane < EN_KT;
         const int roff = k + j * g.sz;
         const int xs = cx * xc, xe = min(xs + xc, g.nx + 1);
+        // Loads of a plane, issued by every lane from a valid address (entry 0
+        // outside the grid), so that no load sits in a branch and the waits
+        // count only the loads they need.  Values loaded outside the grid are
+        // never used: a term reads its own entry, the next lane's only when
+        // k < nz, the next plane's only when i < nx, and a j-neighbour only
+        // when it lies in the grid (h_z at j-1 is taken as 0 for j = 0).  The
+        // waves of the tile's inner rows load their own entry again instead of
+        // a j-neighbour (cache hits).
         auto load = [&](int i, EnPlane<R>& d) {
             const bool ok = node && i >= 0 && i <= g.nx;
-            const int id = roff + i * g.sp;
-            d.ex = ok ? ex[id] : R(0);
-            d.ey = ok ? ey[id] : R(0);
-            d.ez = ok ? ez[id] : R(0);
-            d.hx = ok ? hx[id] : R(0);
-            d.hy = ok ? hy[id] : R(0);
-            d.hz = ok ? hz[id] : R(0);
-            d.hz_jm = ok && j >= 1 ? hz[id - g.sz] : R(0);
-            d.ez_jp = ok && j < g.ny ? ez[id + g.sz] : R(0);
-            d.c = ok && M.code ? (uint32_t)M.code[id] : 0u;
+            const int id = ok ? roff + i * g.sp : 0;
+            d.ex = ex[id];
+            d.ey = ey[id];
+            d.ez = ez[id];
+            d.hx = hx[id];
+            d.hy = hy[id];
+            d.hz = hz[id];
+            int idm = ok && w == 0 && j >= 1 ? id - g.sz : id;
+            int idp = ok && w == EN_ROWS - 1 && j < g.ny ? id + g.sz : id;
+            // opaque to the compiler, so that it issues these loads instead of
+            // reusing the entry's own (which would make them conditional)
+            asm volatile("" : "+v"(idm), "+v"(idp));
+            d.hz_jm = hz[idm];
+            d.ez_jp = ez[idp];
+            d.c = M.code ? (uint32_t)M.code[id] : 0u;
         };
         // kappa of e component c and mu of h component c at entry id
         auto kapc = [&](int c, uint32_t code, int id) {
@@ -435,6 +454,12 @@ __global__ __launch_bounds__(RED_THREADS) void k_energy(Fields<R> f, Mat<R> M, G
         load(xs + 1, nxt);
         R hz_im = (node && xs >= 1) ? hz[roff + (xs - 1) * g.sp] : R(0);   // h_z at plane i-1
         for (int i = xs; i < xe; ++i) {
+            const int x = i & 1;
+            sHZ[x][w][lane] = cur.hz;
+            sEZ[x][w][lane] = cur.ez;
+            __syncthreads();
+            const R hz_jm = w > 0 ? sHZ[x][w - 1][lane] : (j >= 1 ? cur.hz_jm : R(0));
+            const R ez_jp = w < EN_ROWS - 1 ? sEZ[x][w + 1][lane] : cur.ez_jp;
             EnPlane<R> n2;
             load(i + 2, n2);
             // k-neighbours from the next lane, with every lane active
@@ -445,7 +470,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_energy(Fields<R> f, Mat<R> M, G
                 const double kx = kapc(0, cur.c, id), ky = kapc(1, cur.c, id), kz = kapc(2, cur.c, id);
                 const double hzv = (double)cur.hz;
                 if (kx > 0.0) {
-                    const double d = (double)cur.hz_jm - hzv;
+                    const double d = (double)hz_jm - hzv;
                     sq += sqk((double)cur.ex, kx, 0);
                     r += kx * d * d;
                 }
@@ -458,7 +483,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_energy(Fields<R> f, Mat<R> M, G
                 if (j < g.ny && k < g.nz) {                       // h_x
                     const double mu = muc(0, id), h = (double)cur.hx;
                     if (mu > 0.0) sq += sqm(h, mu, 0);
-                    const double d = (double)cur.ez_jp - (double)cur.ez;
+                    const double d = (double)ez_jp - (double)cur.ez;
                     r += mu * d * d;
                     lc += h * (eyk - (double)cur.ey);
                 }
@@ -480,8 +505,14 @@ __global__ __launch_bounds__(RED_THREADS) void k_energy(Fields<R> f, Mat<R> M, G
             nxt = n2;
         }
     }
-    double s = block_reduce<false>(acc);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    acc = wave_sum(acc);
+    if (lane == 0) red[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = red[0];
+        for (int t = 1; t < EN_ROWS; ++t) s += red[t];
+        partial[blockIdx.x] = s;
+    }
 }
 
 template <bool MAX>
@@ -1107,7 +1138,7 @@ hipError_t launch_energy(Fields<R> f, Mat<R> mat, Geo g, double alpha, double rw
     const int64_t items = tiles * ((planes + xc - 1) / xc);
     if (items > 0x7fffffff) return hipErrorInvalidValue;
     const int grid = (int)std::min<int64_t>(items, RED_BLOCKS);
-    k_energy<R><<<grid, RED_THREADS, 0, s>>>(f, mat, g, alpha, rw, nyt, nzt, (int)xc, (int)items, partial);
+    k_energy<R><<<grid, EN_THREADS, 0, s>>>(f, mat, g, alpha, rw, nyt, nzt, (int)xc, (int)items, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_finish<false><<<1, RED_THREADS, 0, s>>>(partial, grid, 1, out);
