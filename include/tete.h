@@ -277,7 +277,10 @@ tete_status tete_clear_bunch(tete_grid* g);
 tete_status tete_set_diagnostics(tete_grid* g, int32_t every);
 
 /* e_z probes recorded after every step (e_z^{n+1/2}); idx are HOST array
- * indices into the e_z array (0 <= idx < np), np_ <= TETE_MAX_PROBES. */
+ * indices into the e_z array (0 <= idx < np), np_ <= TETE_MAX_PROBES.  Probes
+ * leave steps paired: for the state a two-step launch passes through, the
+ * probes' e_z is evaluated from the launch's input (S1-S3 at each probe edge,
+ * the arithmetic of the step). */
 tete_status tete_set_probes(tete_grid* g, const int64_t* idx, int32_t np_);
 
 /* Enqueue nsteps steps of scheme (23) on the grid's stream (asynchronous).
@@ -378,9 +381,9 @@ tete_status tete_witness_wake(tete_grid* g, double* W, double* Wx, double* Wy, i
 /* Static tiles of a TETE_F_SKIP_STATIC grid for its current geometry (or
  * materials): *skipped of *total tiles lie wholly in PEC, for the tiling of
  * the two-step kernel where tete_step pairs steps, else (no two-step kernel,
- * probes set, or an energy sample before every step) for the fused single
- * step's.  The two kinds keep separate tables.  Builds the table if needed;
- * synchronises the stream.  TETE_ERR_STATE without the flag. */
+ * or an energy sample before every step) for the fused single step's.  The
+ * two kinds keep separate tables.  Builds the table if needed; synchronises
+ * the stream.  TETE_ERR_STATE without the flag. */
 tete_status tete_static_tiles(tete_grid* g, int64_t* skipped, int64_t* total);
 
 /* Discrete energy W^{n,e} = 1/2 <Q^e y^n, y^n> (Sec. 4.4) of the current
@@ -435,7 +438,7 @@ tete_status tete_charges(tete_grid* g, double* max_res_e, double* max_abs_h);
  *                      TETE_F_SKIP_STATIC grid; materials by class and FP32
  *                      arrays use it).  tete_step
  *                      pairs consecutive steps except where an energy sample
- *                      or probes need the state in between; those steps, and
+ *                      needs the state in between; those steps, and
  *                      an odd last one, run as fused single steps;
  *   TETE_KERNEL_SPLIT  the two-kernel step (one kernel per half step).
  * rows: rows per workgroup of the fused single step, 12 or 16 (0: 16 for

@@ -372,9 +372,10 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
         const bool at_n = g->diag_every > 0 && g->n % g->diag_every == 0;
         const bool at_n1 = g->diag_every > 0 && (g->n + 1) % g->diag_every == 0;
         // two steps at once unless the state after the first is observed
-        // (an energy sample of it is taken inside the launch where it can be)
+        // (an energy sample of it is taken inside the launch where it can be;
+        // the probes' values of it are recomputed from the launch's input)
         const bool wit = g->witness && g->has_bunch;
-        const bool pair = (two || two_yee) && s + 1 < nsteps && g->nprobe == 0 && (!at_n1 || en_fuse);
+        const bool pair = (two || two_yee) && s + 1 < nsteps && (g->nprobe == 0 || two) && (!at_n1 || en_fuse);
         const bool en_pair = pair && en_fuse && (at_n || at_n1);
         if (at_n && !en_pair) {
             HIPCHK(launch_energy<R>(fields<R>(g, g->cur), M, g->geo, g->alpha, rweight(g), g->partial, g->eser + g->ecount,
@@ -407,6 +408,9 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
                 if (wit) HIPCHK(launch_zero_bytes(g->wmid, (g->fp32 ? 4 : 8) * (size_t)TETE_WITNESS_LINES * g->d.nz,
                                                   g->stream));
             }
+            if (g->nprobe > 0)   // the probes after step n+1, from y^n before the launch replaces it
+                HIPCHK(launch_probes_next<R>(fields<R>(g, g->cur), M, g->geo, (R)g->alpha, source(g, g->n), g->pidx,
+                                             g->nprobe, g->pser + g->pcount * g->nprobe, g->stream));
             EnergyPair en = {(at_n ? 1 : 0) | (at_n1 ? 2 : 0), g->alpha, g->epart, EN_PARTS, g->eser + g->ecount};
             HIPCHK(launch_step_fused2<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                          source(g, g->n), wit ? &wm : nullptr, fused2_rows(g), g->tune.depth,
@@ -421,6 +425,11 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             g->cur = 1 - g->cur;
             g->n += 2;
             ++s;
+            if (g->nprobe > 0) {   // the probes after step n+2
+                HIPCHK(launch_probes<R>((const R*)g->f[g->cur][2], g->pidx, g->nprobe,
+                                        g->pser + (g->pcount + 1) * g->nprobe, g->stream));
+                g->pcount += 2;
+            }
             continue;
         }
         if (g->implicit && !g->imp_lists) {   // once per geometry
@@ -910,9 +919,9 @@ tete_status tete_static_tiles(tete_grid* g, int64_t* skipped, int64_t* total)
     if (!dg.ok) return TETE_ERR_DEVICE;
     const bool wit = g->witness && g->has_bunch;
     // the tiling of paired steps (the two-step kernel), or of the single step
-    // where tete_step pairs no steps: no two-step kernel, probes set, or an
-    // energy sample before every step
-    const bool single = !use_fused2(g) || g->nprobe > 0 || g->diag_every == 1;
+    // where tete_step pairs no steps: no two-step kernel, or an energy sample
+    // before every step (skip grids take samples apart from the launches)
+    const bool single = !use_fused2(g) || g->diag_every == 1;
     tete_status st = g->fp32 ? static_table<float>(g, wit, single) : static_table<double>(g, wit, single);
     if (st != TETE_OK) return st;
     const int kind = single ? 1 : 0;

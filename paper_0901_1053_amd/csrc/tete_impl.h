@@ -280,6 +280,11 @@ hipError_t launch_charges(Fields<R> oldf, Fields<R> newf, Mat<R> mat, Geo g, dou
                           double* partial, double* out, hipStream_t s);
 template <typename R>
 hipError_t launch_probes(const R* ez, const int64_t* idx, int nprobe, double* out, hipStream_t s);
+// e_z of the probes after one step from state o (the state a two-step launch
+// passes through without storing it), nprobe <= 64
+template <typename R>
+hipError_t launch_probes_next(Fields<R> o, Mat<R> mat, Geo g, R alpha, Src src, const int64_t* idx, int nprobe,
+                              double* out, hipStream_t s);
 // wake quadrature of one step n on the witness lines: acc[l * TETE_MAX_WAKE +
 // j - jmin] += -1/2 (e_z^{n-1/2} + e_z^{n+1/2}) of edge k < kend, j = n - k - M
 template <typename R>

@@ -609,6 +609,50 @@ __global__ void k_probes(const R* ez, const int64_t* idx, int n, double* out)
     if (t < n) out[t] = (double)ez[idx[t]];
 }
 
+// The probes' e_z after one step from state o, for a two-step launch that
+// never stores that state: one thread per probe evaluates S3 at its edge from
+// S1 and S2 at the four h edges around it, the formulas and the order of
+// operations of the TM half step (k_tm), bunch current included.
+template <typename R>
+__global__ void k_probes_next(Fields<R> o, Mat<R> M, Geo g, R a, Src src, const int64_t* idx, int n, double* out)
+{
+    const int t = threadIdx.x;
+    if (t >= n) return;
+    int i, j, k;
+    decomp((int)idx[t], g, i, j, k);
+    const R* ex = o.c[0];
+    const R* ey = o.c[1];
+    const R* ez = o.c[2];
+    const R* hx = o.c[3];
+    const R* hy = o.c[4];
+    const R a2 = a + a;
+    // S1 and S2 at (ii, jj, k)
+    auto hxn = [&](int ii, int jj) -> R {
+        if (!in_nodes(g, ii, jj, k) || !hx_ok(g, ii, jj, k)) return R(0);
+        int id = lin(g, ii, jj, k);
+        return hx[id] + a * muv(M, 0, id) * ((ld(ey, g, ii, jj, k + 1) - ey[id]) - (ld(ez, g, ii, jj + 1, k) - ez[id]));
+    };
+    auto hyn = [&](int ii, int jj) -> R {
+        if (!in_nodes(g, ii, jj, k) || !hy_ok(g, ii, jj, k)) return R(0);
+        int id = lin(g, ii, jj, k);
+        return hy[id] + a * muv(M, 1, id) * (-(ld(ex, g, ii, jj, k + 1) - ex[id]) + (ld(ez, g, ii + 1, jj, k) - ez[id]));
+    };
+    R v = R(0);
+    if (ez_ok(g, i, j, k)) {
+        const int id = lin(g, i, j, k);
+        const R kp = kap(M, 2, id);
+        v = ez[id] + a2 * kp * ((hxn(i, j - 1) - hxn(i, j)) - (hyn(i - 1, j) - hyn(i, j)));
+        if (src.on && i == src.i0 && j == src.j0) {
+            int64_t m = (int64_t)k - src.n + src.M;
+            if (m >= -src.M && m <= src.M) {
+#pragma clang fp contract(off)
+                v -= (R)((double)kp * src.lam[m + src.M]);
+            }
+        }
+    }
+    out[t] = (double)v;
+}
+
 // One thread per (edge k, line blockIdx.y).  Within one step the edges of a
 // line feed distinct samples, so no two threads add to one accumulator.
 template <typename R>
@@ -1174,6 +1218,16 @@ hipError_t launch_probes(const R* ez, const int64_t* idx, int nprobe, double* ou
 }
 
 template <typename R>
+hipError_t launch_probes_next(Fields<R> o, Mat<R> mat, Geo g, R alpha, Src src, const int64_t* idx, int nprobe,
+                              double* out, hipStream_t s)
+{
+    if (nprobe <= 0) return hipSuccess;
+    if (nprobe > 64) return hipErrorInvalidValue;
+    k_probes_next<R><<<1, 64, 0, s>>>(o, mat, g, alpha, src, idx, nprobe, out);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_witness2(const R* ez_old, const R* ez_mid, const R* ez_new, Witness w, Geo g, int64_t n, int M,
                            int jmin, int nw, int kend, double* acc, hipStream_t s)
 {
@@ -1212,6 +1266,8 @@ hipError_t launch_witness(const R* ez_old, const R* ez_new, Witness w, Geo g, in
     template hipError_t launch_charges<R>(Fields<R>, Fields<R>, Mat<R>, Geo, double, Src, double*, double*,        \
                                           hipStream_t);                                                            \
     template hipError_t launch_probes<R>(const R*, const int64_t*, int, double*, hipStream_t);                     \
+    template hipError_t launch_probes_next<R>(Fields<R>, Mat<R>, Geo, R, Src, const int64_t*, int, double*,        \
+                                              hipStream_t);                                                        \
     template hipError_t launch_witness<R>(const R*, const R*, Witness, Geo, int64_t, int, int, int, int, double*,   \
                                           hipStream_t);                                                            \
     template hipError_t launch_witness2<R>(const R*, const R*, const R*, Witness, Geo, int64_t, int, int, int, int, \

@@ -1,8 +1,9 @@
 """The two-step (temporally blocked) fused kernel: two steps per launch must give
 exactly the fields and wake of two single fused steps, for every launch shape
 (tile and chunk boundaries everywhere, the bunch line on and off tile edges),
-with probes that force single steps in between and energy samples taken inside
-the paired launches, and within the FP32 tolerance of the FP64 oracle."""
+with probes (their values between a pair's two steps evaluated from the pair's
+input) and energy samples taken inside the paired launches, and within the FP32
+tolerance of the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -90,9 +91,10 @@ def test_wake_within_tolerance_of_oracle():
 def test_diagnostics_and_single_steps():
     """An energy sample every 3 steps (odd: the paired launches take the
     samples between their two steps) and, in a second run, probes every step
-    (single steps): fields, wake and probes equal those of single steps
-    bitwise, the energy series to the rounding of its FP64 sums (the paired
-    launch adds the same terms in another order)."""
+    (the steps stay paired; a pair's first-step values come from its input):
+    fields, wake and probes equal those of single steps bitwise, the energy
+    series to the rounding of its FP64 sums (the paired launch adds the same
+    terms in another order)."""
     case = inputs.scaled_wake_case(24, 100, seed=4, sigma_dz=3.0)
     jmin, nw = -case.M, 2 * case.M + 20
     steps = 40
@@ -108,6 +110,42 @@ def test_diagnostics_and_single_steps():
     b = _wake_run(case, "fused", steps, jmin, nw, probes=idx)
     assert np.array_equal(a.probes(3), b.probes(3))
     _same(a.get_fields(), b.get_fields())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("materials", [False, True])
+def test_probes_in_paired_launches(precision, materials):
+    """Probes on the bunch line (its current enters their step), on a PEC
+    edge, on the last k (no e_z edge) and inside, over an odd number of steps:
+    the series of the paired run equals that of single steps bitwise, and so
+    do the fields.  With materials (0.9 x vacuum with PEC zeros, a few
+    distinct tuples: the two-step kernel's class instance)."""
+    print("probes in pairs", precision, materials, flush=True)
+    case = inputs.scaled_wake_case(24, 100, seed=5, sigma_dz=3.0)
+    g = P.oracle_geom(case)
+    cells = case.cell_mask()
+    sp, sz = (case.ny + 1) * (case.nz + 1), case.nz + 1
+    line = case.i0 * sp + case.j0 * sz
+    m = O.vacuum_materials(g, cells)
+    pec = [int(i) for i in np.flatnonzero(m["ez"] == 0) if (i % sz) < case.nz]
+    idx = np.array([line + 10, line + 50, line + 90, line + case.nz, pec[len(pec) // 2], 3 * sp + 5 * sz + 40],
+                   dtype=np.int64)
+    steps = 41
+    runs = []
+    for kernel in ("auto", "fused"):
+        G = P.gpu_grid(case, precision, cells=not materials, materials=materials, max_series=steps + 16)
+        if materials:
+            G.set_materials({k: 0.9 * v for k, v in m.items()})
+        G.set_tuning(kernel)
+        G.set_bunch(case.Q, case.sigma, case.i0, case.j0, case.M, -case.M, 2 * case.M + 20)
+        G.set_probes(idx)
+        G.step(steps)
+        runs.append(G)
+    pa, pb = runs[0].probes(len(idx)), runs[1].probes(len(idx))
+    assert pa.shape == (steps, len(idx))
+    assert np.abs(pb[:, :3]).max() > 0
+    assert np.array_equal(pa, pb)
+    _same(runs[0].get_fields(), runs[1].get_fields())
 
 
 def test_timing_counts_steps():

@@ -325,9 +325,12 @@ def test_skip_materials(precision):
 @pytest.mark.parametrize("rows,depth", [(0, 0), (12, 1), (16, 3)])
 def test_skip_single_steps(precision, rows, depth):
     """The fused single step over the active tiles: with the single-step
-    kernel chosen, and with probes (every step a single step) and energy
-    diagnostics, fields, wake, probe series and energy series equal those of
-    the grid without the skip."""
+    kernel chosen, then with probes and an energy sample every 3 steps (the
+    samples at odd steps leave single steps between the pairs): fields, wake
+    and probe series equal those of the grid without the skip, the energy
+    series to the rounding of its FP64 sums (the grid without the skip takes
+    its samples inside the paired launches, the skip grid with the energy
+    kernel)."""
     print("skip single", precision, rows, depth, flush=True)
     cells = _pipe_cells(*SHAPE, 6, seed=102)
     nx, ny, nz = SHAPE
@@ -348,4 +351,6 @@ def test_skip_single_steps(precision, rows, depth):
     assert grids[0].static_tiles()[0] > 0
     _same(*grids)
     assert np.array_equal(grids[0].probes(3), grids[1].probes(3))
-    assert np.array_equal(grids[0].energy_series(), grids[1].energy_series())
+    ea, eb = grids[0].energy_series(), grids[1].energy_series()
+    assert len(ea) == len(eb) > 0
+    assert np.max(np.abs(ea - eb)) <= 1e-13 * np.max(np.abs(eb))
