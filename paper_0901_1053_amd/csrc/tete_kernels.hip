@@ -396,8 +396,10 @@ template <typename R>
 __global__ __launch_bounds__(EN_THREADS) void k_energy(Fields<R> f, Mat<R> M, Geo g, double a, double rw, int nyt,
                                                        int nzt, int xc, int items, double* partial)
 {
-    // h_z and e_z of the plane being summed, by plane parity (one barrier per
-    // plane: a buffer is rewritten two planes later, after the next barrier)
+    // h_z and e_z of the plane being summed, in two buffers taken in turn by
+    // the planes the workgroup sums, across its work items (one barrier per
+    // plane: a buffer is rewritten two planes later, after the next barrier,
+    // which every wave reaches only once it has read the buffer)
     __shared__ R sHZ[2][EN_ROWS][64], sEZ[2][EN_ROWS][64];
     __shared__ double red[EN_ROWS];
     const R *ex = f.c[0], *ey = f.c[1], *ez = f.c[2], *hx = f.c[3], *hy = f.c[4], *hz = f.c[5];
@@ -407,6 +409,7 @@ __global__ __launch_bounds__(EN_THREADS) void k_energy(Fields<R> f, Mat<R> M, Ge
     const double im[3] = {1.0 / (double)M.m[0], 1.0 / (double)M.m[1], 1.0 / (double)M.m[2]};
     const double ra2 = 0.5 * rw * a * a;
     double acc = 0.0;
+    int turn = 0;   // planes summed so far by the workgroup
     for (int it = blockIdx.x; it < items; it += gridDim.x) {
         const int tz = it % nzt, q = it / nzt, ty = q % nyt, cx = q / nyt;
         const int j = ty * EN_ROWS + w, k = tz * EN_KT + lane;
@@ -454,7 +457,7 @@ __global__ __launch_bounds__(EN_THREADS) void k_energy(Fields<R> f, Mat<R> M, Ge
         load(xs + 1, nxt);
         R hz_im = (node && xs >= 1) ? hz[roff + (xs - 1) * g.sp] : R(0);   // h_z at plane i-1
         for (int i = xs; i < xe; ++i) {
-            const int x = i & 1;
+            const int x = turn++ & 1;
             sHZ[x][w][lane] = cur.hz;
             sEZ[x][w][lane] = cur.ez;
             __syncthreads();

@@ -50,3 +50,21 @@ def test_energy_matches_oracle(shape, materials, precision):
     assert abs(e - ref) <= tol * abs(ref), (e, ref)
     # the read-out that allocates nothing takes the same kernel
     assert G.energy_noalloc()[0] == e
+
+
+def test_energy_with_several_work_items_per_workgroup():
+    """A grid whose energy launch gives each workgroup several work items
+    (2560 items: 512 tiles by 5 x-chunks, the last one a single plane), so the
+    LDS buffers pass from one item to the next: the oracle's value to 1e-12,
+    and the same value on every read-out."""
+    shape = (128, 255, 1000)
+    print("energy read-out", shape, flush=True)
+    g, cells, m, f = _state(shape, 77, False)
+    ref = O.energy(g, m, f)
+    G = tete.Grid(*shape, g.dx, g.dy, g.dz, g.cdt, precision="fp64")
+    G.set_pec_cells(cells)
+    G.set_fields(f)
+    del f
+    e = [G.energy()[0] for _ in range(3)]
+    assert abs(e[0] - ref) <= 1e-12 * abs(ref), (e[0], ref)
+    assert e[1] == e[0] and e[2] == e[0]
