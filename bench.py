@@ -380,9 +380,19 @@ def diagnostics_section(G, case, two_step_ms, steps=16):
         res[name] = round(e0.elapsed_time(e1) / steps, 4)
         G.set_diagnostics(0)
     G.set_tuning(saved["kernel"], saved["rows"], saved["xchunk"], saved["depth"], saved["order"])
+    # a read-out on its own (tete_energy: the energy kernel, its fixed-order
+    # finish and the copy of the value to the host), wall clock per call
+    G.energy()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        G.energy()
+    readout = (time.perf_counter() - t0) / 5 * 1e3
+    b = 4 if G.precision == "fp32" else 8
     return {"workload": case.name, "energy_every": 1, "ms_per_step": res,
             "vs_two_step_without_samples": round(res["paired_with_samples"] / two_step_ms, 3),
-            "speedup_over_single_steps": round(res["single_steps_and_energy_kernel"] / res["paired_with_samples"], 2)}
+            "speedup_over_single_steps": round(res["single_steps_and_energy_kernel"] / res["paired_with_samples"], 2),
+            "energy_readout_ms": round(readout, 3),
+            "energy_readout_gbps_algorithmic": round((6 * b + 1) * G.np / (readout / 1e3) / 1e9, 1)}
 
 
 def _pec_materials(case, precision, scale=0.9, graded=False):
