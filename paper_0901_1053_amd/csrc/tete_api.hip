@@ -362,10 +362,13 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
     const bool two = use_fused2(g);
     // Yee grids: two steps per launch unless the tuning asks for single steps
     const bool two_yee = g->yee && g->tune.kernel != TETE_KERNEL_FUSED && yee2_fits(g->geo, g->fp32 ? 4 : 8);
-    // energy samples inside two-step launches: vacuum grids without witness
-    // lines or static-tile lists, launches of at most EN_PARTS workgroups
+    // energy samples inside two-step launches: vacuum grids and FP32
+    // materials by class, without witness lines or static-tile lists,
+    // launches of at most EN_PARTS workgroups
     int64_t en_blocks = 0;
-    const bool en_fuse = two && g->diag_every > 0 && !g->mat_set && !(g->witness && g->has_bunch) && !g->skip &&
+    const bool en_fuse = two && g->diag_every > 0 && (!g->mat_set || (g->mat_cls && g->fp32)) &&
+                         !(g->witness && g->has_bunch) &&
+                         !g->skip &&
                          (en_blocks = fused2_blocks<R>(g->geo, fused2_xchunk(g), g->tune.order)) > 0 &&
                          en_blocks <= EN_PARTS;
     for (int64_t s = 0; s < nsteps; ++s) {
@@ -411,7 +414,8 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
             if (g->nprobe > 0)   // the probes after step n+1, from y^n before the launch replaces it
                 HIPCHK(launch_probes_next<R>(fields<R>(g, g->cur), M, g->geo, (R)g->alpha, source(g, g->n), g->pidx,
                                              g->nprobe, g->pser + g->pcount * g->nprobe, g->stream));
-            EnergyPair en = {(at_n ? 1 : 0) | (at_n1 ? 2 : 0), g->alpha, g->epart, EN_PARTS, g->eser + g->ecount};
+            EnergyPair en = {(at_n ? 1 : 0) | (at_n1 ? 2 : 0), g->alpha, g->epart, EN_PARTS, g->eser + g->ecount,
+                             g->mat_cls ? g->craw : nullptr};
             HIPCHK(launch_step_fused2<R>(fields<R>(g, g->cur), fields<R>(g, 1 - g->cur), M, g->geo, (R)g->alpha,
                                          source(g, g->n), wit ? &wm : nullptr, fused2_rows(g), g->tune.depth,
                                          fused2_xchunk(g), g->tune.order, g->stream, ev, act, g->skip_nact[0],

@@ -208,12 +208,20 @@ struct Arr6 {
 // an entry is taken where the stage holds its operands: e_z and h_x (with
 // e_z at j+1 and e_y at k+1) at the input plane, h_y (e_z at i+1, e_x at k+1)
 // one plane behind, e_x, e_y and h_z (h_z at j-1 and at i-1) two behind; the
-// terms are those of the energy kernel, in another summation order.
+// terms are those of the energy kernel, in another summation order.  With
+// materials by class (CLS) each term's coefficients come from et, a table in
+// LDS of ET_N FP64 values per class built from the class materials craw
+// (kappa_x, kappa_y, kappa_z, mu_x, mu_y, mu_z per class, rounded to the
+// field type as the per-entry arrays hold them): 1/(2 kappa) and 1/(2 mu), 0
+// where kappa or mu is 0, and a^2 kappa / 2, a^2 mu / 2.
 struct EnOut {
     double* part;
     int want;
     double a;
+    const double* craw;
+    const double* et;
 };
+enum { ET_SKX, ET_SKY, ET_SKZ, ET_SMX, ET_SMY, ET_SMZ, ET_DKX, ET_DKY, ET_DMX, ET_DMY, ET_N };
 template <typename R, int TYH, int NB, int LW, int PD, bool WIT = false, bool CLS = false, bool ARR = false,
           class LDS, bool EN = false>
 __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, const int tz, const int cx, LDS& L,
@@ -221,7 +229,7 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
                                             const EnOut& eo = EnOut{})
 {
     static_assert(!(ARR && (CLS || WIT)), "one material source per instance");
-    static_assert(!(EN && (ARR || CLS || WIT)), "energy with vacuum coefficients only");
+    static_assert(!(EN && (ARR || WIT)), "energy with vacuum coefficients or materials by class only");
     constexpr int TY = TYH - 6;   // rows owned
     constexpr int KT2 = LW - 4;   // entries owned per row
     // Lane shifts act on the whole wave; with two rows per wave (LW = 32) the
@@ -436,18 +444,31 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
     // differences (a product per term instead of a division; the terms then
     // differ from the energy kernel's by rounding)
     const double ea = eo.a, ha2 = 0.5 * ea * ea;
-    const double skx = 0.5 / (double)A.kx, sky = 0.5 / (double)A.ky, skz = 0.5 / (double)A.kz;
-    const double smx = 0.5 / (double)A.mx, smy = 0.5 / (double)A.my, smz = 0.5 / (double)A.mz;
-    const double dkx = ha2 * (double)A.kx, dky = ha2 * (double)A.ky, dmx = ha2 * (double)A.mx,
-                 dmy = ha2 * (double)A.my;
+    const double skx0 = 0.5 / (double)A.kx, sky0 = 0.5 / (double)A.ky, skz0 = 0.5 / (double)A.kz;
+    const double smx0 = 0.5 / (double)A.mx, smy0 = 0.5 / (double)A.my, smz0 = 0.5 / (double)A.mz;
+    const double dkx0 = ha2 * (double)A.kx, dky0 = ha2 * (double)A.ky, dmx0 = ha2 * (double)A.mx,
+                 dmy0 = ha2 * (double)A.my;
     // one stage's energy terms: input c at plane q with PEC code cq, carried
     // state S (before the stage rotates it), j-neighbours nb, codes of planes
-    // q-1 .. q-4 in hist
+    // q-1 .. q-4 in hist; with CLS the classes of planes q, q-1, q-2 in the
+    // low bytes of kc
     auto en_terms = [&](const In<R>& c, const Stage<R>& S, const Nb<R>& nb, const uint32_t cq, const uint32_t hist,
-                        const int q) {
+                        const int q, const uint32_t kc) {
         const R eyk = lane_next(c.ey), exk = lane_next(S.EXm1);   // e_y(k+1) at q, e_x(k+1) at q-1
         double e = 0.0;
         if (!owned) return e;
+        double skx = skx0, sky = sky0, skz = skz0, smx = smx0, smy = smy0, smz = smz0;
+        double dkx = dkx0, dky = dky0, dmx = dmx0, dmy = dmy0;
+        if constexpr (CLS) {
+            const double* t0 = eo.et + ET_N * cbyte(kc, 0);
+            const double* t1 = eo.et + ET_N * cbyte(kc, 1);
+            const double* t2 = eo.et + ET_N * cbyte(kc, 2);
+            skz = t0[ET_SKZ]; smx = t0[ET_SMX]; dmx = t0[ET_DMX];
+            smy = t1[ET_SMY]; dmy = t1[ET_DMY];
+            skx = t2[ET_SKX]; sky = t2[ET_SKY]; smz = t2[ET_SMZ]; dkx = t2[ET_DKX]; dky = t2[ET_DKY];
+        } else {
+            (void)kc;
+        }
         if (xown(q)) {
             if (!(cq & 4u)) {                                   // e_z
                 const double v = (double)c.ez;
@@ -555,12 +576,13 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
 
         if constexpr (EN) {      // y^n: stage A's input, before the stage rotates its state
             if (eo.want & 1)
-                accA += en_terms(In<R>{cur.ex, cur.ey, cur.ez, cur.hx, cur.hy, cur.hz}, SA, nA, c0, ch, p);
+                accA += en_terms(In<R>{cur.ex, cur.ey, cur.ez, cur.hx, cur.hy, cur.hz}, SA, nA, c0, ch, p, kh0);
         }
         const Out<R> oA = stage_plane(SA, In<R>{cur.ex, cur.ey, cur.ez, cur.hx, cur.hy, cur.hz}, nA, fA, injA);
         if constexpr (EN) {      // y^{n+1}: stage B's input at plane p-4 (its e_x is stage A's S9 above)
             if (eo.want & 2)
-                accB += en_terms(In<R>{oA.ex14, bEY, bEZ, bHX, bHY, bHZ}, SB, nB, (ch >> 12) & 7u, ch >> 16, p - 4);
+                accB += en_terms(In<R>{oA.ex14, bEY, bEZ, bHX, bHY, bHZ}, SB, nB, (ch >> 12) & 7u, ch >> 16, p - 4,
+                                 kh1);
         }
         const Out<R> oB = stage_plane(SB, In<R>{oA.ex14, bEY, bEZ, bHX, bHY, bHZ}, nB, fB, injB);
 
@@ -699,6 +721,42 @@ __global__ __launch_bounds__(TYH * LW) void k_fused2_en(FArgs<R> A, EnOut eo)
     }
     fused2_tile<R, S::rows, S::nb, S::lw, PD, false, false, false, LT, true>(A, ty, tz, cx, L, WitMid<R>{},
                                                                                Arr6<R>{}, eo);
+}
+
+// The same with materials by class (FP32): the class table and the energy
+// coefficients per class (EnOut) staged in LDS.
+template <typename R, int TYH, int LW, int PD>
+__global__ __launch_bounds__(TYH * LW) void k_fused2_en_cls(FArgs<R> A, EnOut eo)
+{
+    typedef Shape2<R, TYH, LW> S;
+    typedef Lds2<R, S::rows, S::nb, S::lw, true> LT;
+    __shared__ LT L;
+    __shared__ double et[TETE_MAX_CLASSES * ET_N];
+    int ty, tz, cx;
+    if (!fused2_tile_of(A, nullptr, ty, tz, cx)) {      // whole group
+        if (threadIdx.x == 0) eo.part[2 * blockIdx.x] = eo.part[2 * blockIdx.x + 1] = 0.0;
+        return;
+    }
+    const double ha2 = 0.5 * eo.a * eo.a;
+    for (int t = threadIdx.x; t < TETE_MAX_CLASSES; t += TYH * LW) {
+        double v[6];
+        for (int c = 0; c < 6; ++c) v[c] = (double)(R)eo.craw[6 * t + c];
+        double* o = et + ET_N * t;
+        o[ET_SKX] = v[0] > 0.0 ? 0.5 / v[0] : 0.0;
+        o[ET_SKY] = v[1] > 0.0 ? 0.5 / v[1] : 0.0;
+        o[ET_SKZ] = v[2] > 0.0 ? 0.5 / v[2] : 0.0;
+        o[ET_SMX] = v[3] > 0.0 ? 0.5 / v[3] : 0.0;
+        o[ET_SMY] = v[4] > 0.0 ? 0.5 / v[4] : 0.0;
+        o[ET_SMZ] = v[5] > 0.0 ? 0.5 / v[5] : 0.0;
+        o[ET_DKX] = ha2 * v[0];
+        o[ET_DKY] = ha2 * v[1];
+        o[ET_DMX] = ha2 * v[3];
+        o[ET_DMY] = ha2 * v[4];
+    }
+    __syncthreads();
+    eo.et = et;
+    fused2_tile<R, S::rows, S::nb, S::lw, PD, false, true, false, LT, true>(A, ty, tz, cx, L, WitMid<R>{}, Arr6<R>{},
+                                                                              eo);
 }
 
 // The two-step kernel with per-entry materials (FP32: 16 rows of 32 lanes,
@@ -937,12 +995,22 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
         FArgs<R> A = fused_args<R>(o, nf, M, g, alpha, src);
         // 16 rows of 32 lanes: 512 threads, whose VGPRs hold the sums'
         // operands (FP32 two planes ahead, FP64 one)
-        if (wm || act || A.cls || M.arr[0] || !fused2_setup<R>(A, 16, xchunk, order, 32)) return hipErrorInvalidValue;
+        // (materials by class: their energy coefficients from en->craw)
+        if (wm || act || (M.arr[0] && !A.cls) || (A.cls && !en->craw) || !fused2_setup<R>(A, 16, xchunk, order, 32))
+            return hipErrorInvalidValue;
         if (A.nblk > en->cap) return hipErrorInvalidValue;
         hipError_t e;
         if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
         constexpr int EPD = sizeof(R) == 4 ? 2 : 1;   // FP64: one plane ahead fits the VGPRs
-        k_fused2_en<R, 16, 32, EPD><<<A.nblk, 16 * 32, 0, s>>>(A, EnOut{en->part, en->want, en->alpha});
+        const EnOut eo = {en->part, en->want, en->alpha, en->craw, nullptr};
+        if (A.cls) {
+            // FP32 only: in FP64 the class and energy tables would not fit the
+            // LDS beside the exchange planes
+            if constexpr (sizeof(R) == 4) k_fused2_en_cls<R, 16, 32, EPD><<<A.nblk, 16 * 32, 0, s>>>(A, eo);
+            else return hipErrorInvalidValue;
+        } else {
+            k_fused2_en<R, 16, 32, EPD><<<A.nblk, 16 * 32, 0, s>>>(A, eo);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
         int slot = 0;

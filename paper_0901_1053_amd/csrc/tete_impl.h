@@ -183,6 +183,7 @@ struct EnergyPair {
     double* part;
     int64_t cap;
     double* out;
+    const double* craw;   // materials by class: kappa_x .. mu_z per class (FP64), else nullptr
 };
 // wm (or nullptr): the witness lines whose e_z^{n+1/2} the launch keeps;
 // act (or nullptr): the nact active tiles of fused2_static_tiles for the same

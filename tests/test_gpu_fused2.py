@@ -265,3 +265,47 @@ def test_energy_samples_in_paired_launches(precision, diag):
         assert np.max(np.abs(e - e_ref)) <= tol * scale
         assert np.max(np.abs(e - res[2][0])) <= 1e-13 * scale
         _same(f, res[2][1])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("diag", [1, 3])
+def test_energy_samples_in_paired_launches_with_classes(precision, diag):
+    """Materials by class (0.9 and 0.75 of vacuum in the two halves along x,
+    PEC zeros: three classes recognised in the per-entry arrays) with energy
+    samples: in FP32 the paired launches take the samples with each entry's
+    class coefficients, in FP64 they are taken apart.  Every sample against
+    the oracle within 1e-12 (FP64) / 1e-5 (FP32) of the largest, against the
+    energy kernel between single steps to its FP64 rounding; the fields
+    bitwise those of single steps."""
+    print("energy in pairs, classes", precision, diag, flush=True)
+    nx, ny, nz = 23, 17, 71
+    g = O.Geom(nx, ny, nz, 2.0e-3, 1.7e-3, 1.0e-3, 1.0e-3)
+    cells = inputs.random_cells(nx, ny, nz, 93, frac=0.08)
+    m = O.vacuum_materials(g, cells)
+    f = np.where(np.arange(nx + 1) < nx // 2, 0.9, 0.75)[:, None, None]
+    m = {k: v * f for k, v in m.items()}
+    f0 = inputs.random_fields((nx + 1, ny + 1, nz + 1), 94)
+    steps = 23
+    res = []
+    for kernel, xchunk in (("fused2", 0), ("fused2", 5), ("fused", 0)):
+        G = tete.Grid(nx, ny, nz, g.dx, g.dy, g.dz, g.cdt, precision=precision, materials=True, max_series=64)
+        G.set_materials(m)
+        G.set_tuning(kernel, 0, xchunk, 0, 0)
+        assert G.get_tuning()["kernel"] == kernel
+        G.set_fields(f0)
+        G.set_bunch(1e-9, 2e-3, 11, 8, 10, -12, 40)
+        G.set_diagnostics(diag)
+        G.step(steps)
+        res.append((G.energy_series(), G.get_fields()))
+        G.close()
+    ref = {k: v.copy() for k, v in f0.items()}
+    O.apply_pec(g, m, ref)
+    b = O.Bunch(Q=1e-9, sigma=2e-3, i0=11, j0=8, M=10, jmin=-12, nw=40)
+    e_ref = np.array(O.run(g, m, ref, steps, bunch=b, want_energy=True)["energy"])[::diag]
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    scale = np.max(np.abs(e_ref))
+    for e, fl in res:
+        assert len(e) == len(e_ref)
+        assert np.max(np.abs(e - e_ref)) <= tol * scale
+        assert np.max(np.abs(e - res[2][0])) <= 1e-13 * scale
+        _same(fl, res[2][1])
