@@ -445,7 +445,9 @@ def materials_section(case, precision, explicit_ms_per_step, steps=6):
     medium with far more tuples than classes, by default (FP32: the two-step
     kernel's arrays instance, six arrays read with the fields once per two
     steps) and by the materials step.  The fields of (1), (2) and (3) are the
-    same, and those of (4) by either kernel (tests)."""
+    same, and those of (4) by either kernel (tests).  With (2) also the
+    time per step with an energy sample before every step, inside the paired
+    launches and with single steps."""
     import torch
     from paper_0901_1053_amd import tete
     mat, table = _pec_materials(case, precision)
@@ -487,6 +489,22 @@ def materials_section(case, precision, explicit_ms_per_step, steps=6):
     a, _, n = C.timing()
     C.set_timing(0)
     out["classes"] = a / n
+    # an energy sample before every step: taken inside the paired launches
+    # (FP32; FP64 class grids sample apart), against single steps with the
+    # energy kernel; HIP events around the steps on the grid's stream
+    for name, kn in (("classes_energy", "auto"), ("classes_energy_single", "fused")):
+        C.set_tuning(kn)
+        C.set_diagnostics(1)
+        C.step(2)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(C.stream)
+        C.step(steps)
+        e1.record(C.stream)
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / steps
+        C.set_diagnostics(0)
     C.close()
     del C
     torch.cuda.empty_cache()
@@ -518,6 +536,8 @@ def materials_section(case, precision, explicit_ms_per_step, steps=6):
             "materials": "0.9 x vacuum kappa and mu per entry, kappa 0 on the staircase PEC edges",
             "ms_per_step": {"fused_materials": round(out["fused"], 3), "two_kernel": round(out["split"], 3),
                             "classes_two_step": round(out["classes"], 3),
+                            "classes_energy_every_step": round(out["classes_energy"], 3),
+                            "classes_energy_every_step_single_steps": round(out["classes_energy_single"], 3),
                             "arrays_default": round(out["auto"], 3),
                             "graded_arrays_default": round(out["graded_auto"], 3),
                             "graded_arrays_materials_step": round(out["graded_fused"], 3)},
