@@ -386,13 +386,16 @@ constexpr int EN_ROWS = 8;
 constexpr int EN_KT = 63;
 constexpr int EN_THREADS = 64 * EN_ROWS;
 
-template <typename R>
+template <typename R, bool ARR>
 struct EnPlane {
     R ex, ey, ez, hx, hy, hz, hz_jm, ez_jp;
     uint32_t c;
+    R m[ARR ? 6 : 1];   // per-entry kappa_x .. mu_z (ARR)
 };
 
-template <typename R>
+// ARR: per-entry materials, loaded with the fields (M.arr[0..5] all set);
+// else vacuum coefficients and the PEC codes.
+template <typename R, bool ARR>
 __global__ __launch_bounds__(EN_THREADS) void k_energy(Fields<R> f, Mat<R> M, Geo g, double a, double rw, int nyt,
                                                        int nzt, int xc, int items, double* partial)
 {
@@ -425,7 +428,7 @@ __global__ __launch_bounds__(EN_THREADS) void k_energy(Fields<R> f, Mat<R> M, Ge
         // when it lies in the grid (h_z at j-1 is taken as 0 for j = 0).  The
         // waves of the tile's inner rows load their own entry again instead of
         // a j-neighbour (cache hits).
-        auto load = [&](int i, EnPlane<R>& d) {
+        auto load = [&](int i, EnPlane<R, ARR>& d) {
             const bool ok = node && i >= 0 && i <= g.nx;
             const int id = ok ? roff + i * g.sp : 0;
             d.ex = ex[id];
@@ -442,17 +445,31 @@ __global__ __launch_bounds__(EN_THREADS) void k_energy(Fields<R> f, Mat<R> M, Ge
             d.hz_jm = hz[idm];
             d.ez_jp = ez[idp];
             d.c = M.code ? (uint32_t)M.code[id] : 0u;
+            if constexpr (ARR) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) d.m[c] = M.arr[c][id];
+            }
         };
-        // kappa of e component c and mu of h component c at entry id
-        auto kapc = [&](int c, uint32_t code, int id) {
-            return M.arr[c] ? (double)M.arr[c][id] : (((code >> c) & 1u) ? 0.0 : (double)M.k[c]);
+        // kappa of e component c and mu of h component c of plane d
+        auto kapc = [&](int c, const EnPlane<R, ARR>& d) {
+            if constexpr (ARR) return (double)d.m[c];
+            else return ((d.c >> c) & 1u) ? 0.0 : (double)M.k[c];
         };
-        auto muc = [&](int c, int id) { return M.arr[3 + c] ? (double)M.arr[3 + c][id] : (double)M.m[c]; };
+        auto muc = [&](int c, const EnPlane<R, ARR>& d) {
+            if constexpr (ARR) return (double)d.m[3 + c];
+            else return (double)M.m[c];
+        };
         // v^2 / kappa (or / mu): the vacuum reciprocal, else a division
-        auto sqk = [&](double v, double kv, int c) { return M.arr[c] ? v * v / kv : v * v * ik[c]; };
-        auto sqm = [&](double v, double mv, int c) { return M.arr[3 + c] ? v * v / mv : v * v * im[c]; };
+        auto sqk = [&](double v, double kv, int c) {
+            if constexpr (ARR) return v * v / kv;
+            else return v * v * ik[c];
+        };
+        auto sqm = [&](double v, double mv, int c) {
+            if constexpr (ARR) return v * v / mv;
+            else return v * v * im[c];
+        };
 
-        EnPlane<R> cur, nxt;
+        EnPlane<R, ARR> cur, nxt;
         load(xs, cur);
         load(xs + 1, nxt);
         R hz_im = (node && xs >= 1) ? hz[roff + (xs - 1) * g.sp] : R(0);   // h_z at plane i-1
@@ -463,14 +480,13 @@ __global__ __launch_bounds__(EN_THREADS) void k_energy(Fields<R> f, Mat<R> M, Ge
             __syncthreads();
             const R hz_jm = w > 0 ? sHZ[x][w - 1][lane] : (j >= 1 ? cur.hz_jm : R(0));
             const R ez_jp = w < EN_ROWS - 1 ? sEZ[x][w + 1][lane] : cur.ez_jp;
-            EnPlane<R> n2;
+            EnPlane<R, ARR> n2;
             load(i + 2, n2);
             // k-neighbours from the next lane, with every lane active
             const double eyk = (double)lane_next(cur.ey), exk = (double)lane_next(cur.ex);
             if (own) {
-                const int id = roff + i * g.sp;
                 double sq = 0.0, r = 0.0, lc = 0.0;
-                const double kx = kapc(0, cur.c, id), ky = kapc(1, cur.c, id), kz = kapc(2, cur.c, id);
+                const double kx = kapc(0, cur), ky = kapc(1, cur), kz = kapc(2, cur);
                 const double hzv = (double)cur.hz;
                 if (kx > 0.0) {
                     const double d = (double)hz_jm - hzv;
@@ -484,21 +500,21 @@ __global__ __launch_bounds__(EN_THREADS) void k_energy(Fields<R> f, Mat<R> M, Ge
                 }
                 if (kz > 0.0) sq += sqk((double)cur.ez, kz, 2);
                 if (j < g.ny && k < g.nz) {                       // h_x
-                    const double mu = muc(0, id), h = (double)cur.hx;
+                    const double mu = muc(0, cur), h = (double)cur.hx;
                     if (mu > 0.0) sq += sqm(h, mu, 0);
                     const double d = (double)ez_jp - (double)cur.ez;
                     r += mu * d * d;
                     lc += h * (eyk - (double)cur.ey);
                 }
                 if (i < g.nx && k < g.nz) {                       // h_y
-                    const double mu = muc(1, id), h = (double)cur.hy;
+                    const double mu = muc(1, cur), h = (double)cur.hy;
                     if (mu > 0.0) sq += sqm(h, mu, 1);
                     const double d = (double)nxt.ez - (double)cur.ez;
                     r += mu * d * d;
                     lc -= h * (exk - (double)cur.ex);
                 }
                 if (i < g.nx && j < g.ny) {                       // h_z
-                    const double mu = muc(2, id);
+                    const double mu = muc(2, cur);
                     if (mu > 0.0) sq += sqm(hzv, mu, 2);
                 }
                 acc += 0.5 * sq - ra2 * r + a * lc;
@@ -1185,7 +1201,10 @@ hipError_t launch_energy(Fields<R> f, Mat<R> mat, Geo g, double alpha, double rw
     const int64_t items = tiles * ((planes + xc - 1) / xc);
     if (items > 0x7fffffff) return hipErrorInvalidValue;
     const int grid = (int)std::min<int64_t>(items, RED_BLOCKS);
-    k_energy<R><<<grid, EN_THREADS, 0, s>>>(f, mat, g, alpha, rw, nyt, nzt, (int)xc, (int)items, partial);
+    bool arr = true;
+    for (int c = 0; c < 6; ++c) arr = arr && mat.arr[c] != nullptr;
+    if (arr) k_energy<R, true><<<grid, EN_THREADS, 0, s>>>(f, mat, g, alpha, rw, nyt, nzt, (int)xc, (int)items, partial);
+    else k_energy<R, false><<<grid, EN_THREADS, 0, s>>>(f, mat, g, alpha, rw, nyt, nzt, (int)xc, (int)items, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_finish<false><<<1, RED_THREADS, 0, s>>>(partial, grid, 1, out);
