@@ -489,9 +489,9 @@ def materials_section(case, precision, explicit_ms_per_step, steps=6):
     a, _, n = C.timing()
     C.set_timing(0)
     out["classes"] = a / n
-    # an energy sample before every step: taken inside the paired launches
-    # (FP32; FP64 class grids sample apart), against single steps with the
-    # energy kernel; HIP events around the steps on the grid's stream
+    # an energy sample before every step: taken inside the paired launches,
+    # against single steps with the energy kernel; HIP events around the
+    # steps on the grid's stream
     for name, kn in (("classes_energy", "auto"), ("classes_energy_single", "fused")):
         C.set_tuning(kn)
         C.set_diagnostics(1)

@@ -723,13 +723,16 @@ __global__ __launch_bounds__(TYH * LW) void k_fused2_en(FArgs<R> A, EnOut eo)
                                                                                Arr6<R>{}, eo);
 }
 
-// The same with materials by class (FP32): the class table and the energy
-// coefficients per class (EnOut) staged in LDS.
+// The same with materials by class: the class table and the energy
+// coefficients per class (EnOut) staged in LDS.  FP64 exchanges the
+// j-neighbours through single buffers (a second barrier per plane) to leave
+// room for the two tables.
 template <typename R, int TYH, int LW, int PD>
 __global__ __launch_bounds__(TYH * LW) void k_fused2_en_cls(FArgs<R> A, EnOut eo)
 {
     typedef Shape2<R, TYH, LW> S;
-    typedef Lds2<R, S::rows, S::nb, S::lw, true> LT;
+    constexpr int NBC = sizeof(R) == 8 ? 1 : S::nb;
+    typedef Lds2<R, S::rows, NBC, S::lw, true> LT;
     __shared__ LT L;
     __shared__ double et[TETE_MAX_CLASSES * ET_N];
     int ty, tz, cx;
@@ -755,8 +758,8 @@ __global__ __launch_bounds__(TYH * LW) void k_fused2_en_cls(FArgs<R> A, EnOut eo
     }
     __syncthreads();
     eo.et = et;
-    fused2_tile<R, S::rows, S::nb, S::lw, PD, false, true, false, LT, true>(A, ty, tz, cx, L, WitMid<R>{}, Arr6<R>{},
-                                                                              eo);
+    fused2_tile<R, S::rows, NBC, S::lw, PD, false, true, false, LT, true>(A, ty, tz, cx, L, WitMid<R>{}, Arr6<R>{},
+                                                                            eo);
 }
 
 // The two-step kernel with per-entry materials (FP32: 16 rows of 32 lanes,
@@ -1004,10 +1007,7 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
         constexpr int EPD = sizeof(R) == 4 ? 2 : 1;   // FP64: one plane ahead fits the VGPRs
         const EnOut eo = {en->part, en->want, en->alpha, en->craw, nullptr};
         if (A.cls) {
-            // FP32 only: in FP64 the class and energy tables would not fit the
-            // LDS beside the exchange planes
-            if constexpr (sizeof(R) == 4) k_fused2_en_cls<R, 16, 32, EPD><<<A.nblk, 16 * 32, 0, s>>>(A, eo);
-            else return hipErrorInvalidValue;
+            k_fused2_en_cls<R, 16, 32, EPD><<<A.nblk, 16 * 32, 0, s>>>(A, eo);
         } else {
             k_fused2_en<R, 16, 32, EPD><<<A.nblk, 16 * 32, 0, s>>>(A, eo);
         }

@@ -272,8 +272,8 @@ def test_energy_samples_in_paired_launches(precision, diag):
 def test_energy_samples_in_paired_launches_with_classes(precision, diag):
     """Materials by class (0.9 and 0.75 of vacuum in the two halves along x,
     PEC zeros: three classes recognised in the per-entry arrays) with energy
-    samples: in FP32 the paired launches take the samples with each entry's
-    class coefficients, in FP64 they are taken apart.  Every sample against
+    samples, which the paired launches take with each entry's class
+    coefficients (FP64: single exchange buffers).  Every sample against
     the oracle within 1e-12 (FP64) / 1e-5 (FP32) of the largest, against the
     energy kernel between single steps to its FP64 rounding; the fields
     bitwise those of single steps."""
