@@ -165,3 +165,39 @@ def test_large_wake_full_run_properties():
     tot = sum(lam[m + M] * acc[-m - jmin] for m in range(-M, M + 1))
     print("energy %.6e identity %.6e rel %.3e" % (e, tot, abs(e - tot) / e), flush=True)
     assert e > 0 and abs(e - tot) <= 1e-5 * e
+
+
+def test_energy_paths_agree_at_full_size():
+    """The benchmark's 512 x 512 x 2048 grid (FP32 fields) with random fields
+    and an energy sample before every step: the samples a paired launch takes
+    inside (of y^0 and y^1) against the energy kernel's samples between
+    single steps, and the first against a read-out of y^0, all to the
+    rounding of their FP64 sums (1e-12 of the value); the two samples agree
+    to the FP32 tolerance, since nothing drives the fields."""
+    import torch
+    case = inputs.large_case()
+    print("case", case.name, "energy paths", flush=True)
+    cells = case.cell_mask()
+    f0 = inputs.random_fields_torch((case.nx + 1, case.ny + 1, case.nz + 1), case.seed + 7, "cuda", torch.float32)
+    series = {}
+    for kernel in ("auto", "fused"):
+        G = tete.Grid(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.cdt, precision="fp32")
+        G.set_pec_cells(cells)
+        G.set_tuning(kernel)
+        G.set_fields(f0, dtype="fp32")
+        e0 = G.energy()[0]
+        G.set_diagnostics(1)
+        G.step(2)
+        series[kernel] = (e0, G.energy_series())
+        G.close()
+        del G
+        torch.cuda.empty_cache()
+    (e0a, sa), (e0b, sb) = series["auto"], series["fused"]
+    assert len(sa) == len(sb) == 2
+    assert e0a == e0b
+    scale = abs(e0a)
+    assert abs(sa[0] - e0a) <= 1e-12 * scale
+    assert np.max(np.abs(sa - sb)) <= 1e-12 * scale
+    # no current: W^{n,e} is conserved (Sec. 4.4), here to the FP32 rounding
+    # of one step's fields
+    assert abs(sa[1] - sa[0]) <= 1e-5 * scale
