@@ -268,7 +268,7 @@ tete_status tete_clear_bunch(tete_grid* g);
 
 /* Diagnostics recorded during tete_step: every > 0 records W^{n,e} of y^n
  * (Sec. 4.4) before each step n with n % every == 0; 0 disables.  On vacuum
- * grids and grids with materials by class, without witness lines or
+ * grids (also with witness lines) and grids with materials by class, without
  * TETE_F_SKIP_STATIC, a launch of the two-step kernel takes the samples of its
  * input y^n and of y^{n+1} itself (FP64 sums
  * of the same terms in another order: equal to the energy kernel's to

@@ -362,13 +362,11 @@ tete_status do_steps(tete_grid* g, int64_t nsteps)
     const bool two = use_fused2(g);
     // Yee grids: two steps per launch unless the tuning asks for single steps
     const bool two_yee = g->yee && g->tune.kernel != TETE_KERNEL_FUSED && yee2_fits(g->geo, g->fp32 ? 4 : 8);
-    // energy samples inside two-step launches: vacuum grids and materials
-    // by class, without witness lines or static-tile lists, launches of at
-    // most EN_PARTS workgroups
+    // energy samples inside two-step launches: vacuum grids (with or without
+    // witness lines) and materials by class, without static-tile lists,
+    // launches of at most EN_PARTS workgroups
     int64_t en_blocks = 0;
-    const bool en_fuse = two && g->diag_every > 0 && (!g->mat_set || g->mat_cls) &&
-                         !(g->witness && g->has_bunch) &&
-                         !g->skip &&
+    const bool en_fuse = two && g->diag_every > 0 && (!g->mat_set || g->mat_cls) && !g->skip &&
                          (en_blocks = fused2_blocks<R>(g->geo, fused2_xchunk(g), g->tune.order)) > 0 &&
                          en_blocks <= EN_PARTS;
     for (int64_t s = 0; s < nsteps; ++s) {

@@ -229,7 +229,7 @@ __device__ __forceinline__ void fused2_tile(const FArgs<R>& A, const int ty, con
                                             const EnOut& eo = EnOut{})
 {
     static_assert(!(ARR && (CLS || WIT)), "one material source per instance");
-    static_assert(!(EN && (ARR || WIT)), "energy with vacuum coefficients or materials by class only");
+    static_assert(!(EN && ARR), "energy with vacuum coefficients or materials by class only");
     constexpr int TY = TYH - 6;   // rows owned
     constexpr int KT2 = LW - 4;   // entries owned per row
     // Lane shifts act on the whole wave; with two rows per wave (LW = 32) the
@@ -723,6 +723,21 @@ __global__ __launch_bounds__(TYH * LW) void k_fused2_en(FArgs<R> A, EnOut eo)
                                                                                Arr6<R>{}, eo);
 }
 
+// The same keeping stage A's e_z^{n+1/2} on the witness lines of wm (vacuum).
+template <typename R, int TYH, int LW, int PD>
+__global__ __launch_bounds__(TYH * LW) void k_fused2_en_wit(FArgs<R> A, EnOut eo, WitMid<R> wm)
+{
+    typedef Shape2<R, TYH, LW> S;
+    typedef Lds2<R, S::rows, S::nb, S::lw> LT;
+    __shared__ LT L;
+    int ty, tz, cx;
+    if (!fused2_tile_of(A, nullptr, ty, tz, cx)) {      // whole group
+        if (threadIdx.x == 0) eo.part[2 * blockIdx.x] = eo.part[2 * blockIdx.x + 1] = 0.0;
+        return;
+    }
+    fused2_tile<R, S::rows, S::nb, S::lw, PD, true, false, false, LT, true>(A, ty, tz, cx, L, wm, Arr6<R>{}, eo);
+}
+
 // The same with materials by class: the class table and the energy
 // coefficients per class (EnOut) staged in LDS.  FP64 exchanges the
 // j-neighbours through single buffers (a second barrier per plane) to leave
@@ -998,9 +1013,11 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
         FArgs<R> A = fused_args<R>(o, nf, M, g, alpha, src);
         // 16 rows of 32 lanes: 512 threads, whose VGPRs hold the sums'
         // operands (FP32 two planes ahead, FP64 one)
-        // (materials by class: their energy coefficients from en->craw)
-        if (wm || act || (M.arr[0] && !A.cls) || (A.cls && !en->craw) || !fused2_setup<R>(A, 16, xchunk, order, 32))
+        // (materials by class: their energy coefficients from en->craw; witness
+        // lines on vacuum grids only)
+        if (act || (M.arr[0] && !A.cls) || (A.cls && (!en->craw || wm)) || !fused2_setup<R>(A, 16, xchunk, order, 32))
             return hipErrorInvalidValue;
+        if (wm && (wm->iw < 1 || wm->iw > g.nx - 1 || wm->jw < 1 || wm->jw > g.ny - 1)) return hipErrorInvalidValue;
         if (A.nblk > en->cap) return hipErrorInvalidValue;
         hipError_t e;
         if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
@@ -1008,6 +1025,8 @@ hipError_t launch_step_fused2(Fields<R> o, Fields<R> nf, Mat<R> M, Geo g, R alph
         const EnOut eo = {en->part, en->want, en->alpha, en->craw, nullptr};
         if (A.cls) {
             k_fused2_en_cls<R, 16, 32, EPD><<<A.nblk, 16 * 32, 0, s>>>(A, eo);
+        } else if (wm) {
+            k_fused2_en_wit<R, 16, 32, EPD><<<A.nblk, 16 * 32, 0, s>>>(A, eo, *wm);
         } else {
             k_fused2_en<R, 16, 32, EPD><<<A.nblk, 16 * 32, 0, s>>>(A, eo);
         }

@@ -309,3 +309,35 @@ def test_energy_samples_in_paired_launches_with_classes(precision, diag):
         assert np.max(np.abs(e - e_ref)) <= tol * scale
         assert np.max(np.abs(e - res[2][0])) <= 1e-13 * scale
         _same(fl, res[2][1])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("diag", [1, 3])
+def test_energy_samples_with_witness_lines(precision, diag):
+    """Witness lines and an energy sample every `diag` steps: the paired
+    launches keep the lines' e_z^{n+1/2} and take the samples together; the
+    witness wakes, the wake and the fields equal those of single steps
+    bitwise, the energy series to the rounding of its FP64 sums."""
+    print("energy in pairs, witness", precision, diag, flush=True)
+    case = inputs.scaled_wake_case(24, 100, seed=6, sigma_dz=3.0)
+    jmin, nw = -case.M, 2 * case.M + 20
+    steps = 41
+    runs = []
+    for kernel in ("auto", "fused"):
+        G = P.gpu_grid(case, precision, max_series=steps + 16)
+        G.set_tuning(kernel)
+        G.set_bunch(case.Q, case.sigma, case.i0, case.j0, case.M, jmin, nw)
+        G.set_witness(case.i0 + 3, case.j0 - 2)
+        G.set_diagnostics(diag)
+        G.step(steps)
+        runs.append(G)
+    a, b = runs
+    ea, eb = a.energy_series(), b.energy_series()
+    assert len(ea) == len(eb) == (steps + diag - 1) // diag
+    assert np.max(np.abs(ea - eb)) <= 1e-13 * np.max(np.abs(eb))
+    assert np.array_equal(a.wake(), b.wake())
+    wa, wb = a.witness_wake(), b.witness_wake()
+    for x, y in zip(wa, wb):
+        assert np.array_equal(x, y)
+    assert np.abs(wb[0]).max() > 0
+    _same(a.get_fields(), b.get_fields())
