@@ -334,7 +334,8 @@ def witness_section(G, case, two_step_ms, offset=32, steps=20):
     e_z^{n+1/2} of the five witness lines, and a small kernel over the lines
     follows it; time per step from HIP events on the grid's stream around whole
     launches, the step kernel's own time from the grid's timing, and the ratio
-    to the two-step kernel without a witness."""
+    to the two-step kernel without a witness; then also with an energy sample
+    before every step."""
     import torch
     G.set_witness(case.i0 + offset, case.j0)
     G.step(2)
@@ -350,11 +351,23 @@ def witness_section(G, case, two_step_ms, offset=32, steps=20):
     G.step(steps)
     ms_k, _, n = G.timing()
     G.set_timing(0)
+    # with an energy sample before every step as well (taken inside the
+    # paired launches, which also keep the lines' values)
+    G.set_diagnostics(1)
+    G.step(2)
+    torch.cuda.synchronize()
+    e0.record(G.stream)
+    G.step(steps)
+    e1.record(G.stream)
+    torch.cuda.synchronize()
+    ms_e = e0.elapsed_time(e1) / steps
+    G.set_diagnostics(0)
     G.clear_witness()
     return {"workload": case.name, "witness_offset_cells": [offset, 0], "lines": 5,
             "ms_per_step": round(ms, 4), "step_kernel_ms": round(ms_k / n, 4),
             "line_kernel_and_gap_ms": round(ms - ms_k / n, 4),
-            "vs_two_step_without_witness": round(ms / two_step_ms, 3)}
+            "vs_two_step_without_witness": round(ms / two_step_ms, 3),
+            "ms_per_step_with_energy_every_step": round(ms_e, 4)}
 
 
 def diagnostics_section(G, case, two_step_ms, steps=16):
